@@ -1,0 +1,461 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage of Farrell & Pearson (arXiv:1603.04570) it relies
+on.  The references are independent of the oracle (tests/fe_reference.py):
+Kronecker closed forms, brute-force 5-point quadrature, the DCT-I eigenbasis,
+dense linear algebra, and analytic solutions of the linearised timestep.
+"""
+import numpy as np
+import pytest
+
+import fe_reference as fr
+from oracle.okref import MAT_A, MAT_K, MAT_M, MAT_ME, MAT_P, Oracle, local_jacobian, \
+    local_residual
+from paper_1603_04570_amd.inputs import noise_state, uniform01
+
+CFG1 = dict(eps=0.02, sigma=100.0, m=0.0, dt=1e-4)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ----------------------------------------------------------------------------
+# P1: M and K (Sec. 2, entries below eq. (newton); properties stated after it)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n", [(2, 4), (2, 8), (3, 2), (3, 4)])
+def test_mass_stiffness_closed_forms(dim, n):
+    o = Oracle(dim, n, **CFG1, mg_levels=1)
+    M = o.dense(MAT_M)
+    K = o.dense(MAT_K)
+    assert np.abs(M - fr.mass(dim, n)).max() <= 1e-15 * np.abs(M).max() * 10
+    assert np.abs(K - fr.stiffness(dim, n)).max() <= 1e-14 * np.abs(K).max()
+    one = np.ones(M.shape[0])
+    assert abs(one @ M @ one - 1.0) < 1e-14            # |Omega| = 1
+    assert np.abs(K @ one).max() < 1e-12 * np.abs(K).max()   # constants in null(K)
+    assert np.allclose(M, M.T, rtol=0, atol=0) and np.allclose(K, K.T, rtol=0, atol=0)
+    assert np.linalg.eigvalsh(M).min() > 0                 # M SPD
+    ek = np.linalg.eigvalsh(K)
+    assert np.sum(ek < 1e-10 * ek.max()) == 1              # one zero eigenvalue
+
+
+# ----------------------------------------------------------------------------
+# P2: M_E(u) and N(u) (Sec. 2, M_E entries int (3u^2-1) phi_i phi_j; eq. (okb))
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n", [(2, 4), (3, 2)])
+def test_me_constant_states(dim, n):
+    o = Oracle(dim, n, **CFG1, mg_levels=1)
+    M = o.dense(MAT_M)
+    nodes = M.shape[0]
+    for c in (0.0, 1.0, -1.0, 0.3):
+        u = np.full(nodes, c)
+        ME = o.dense(MAT_ME, u=u)
+        assert np.abs(ME - (3 * c * c - 1) * M).max() <= 1e-15 * np.abs(M).max() * 10
+        nv = o.nonlinear(u)
+        assert np.abs(nv - (c ** 3 - c) * M.sum(axis=1)).max() <= 1e-16 + 1e-14 * abs(c)
+    # M_E = -M at u = 0 and 2M at u = +-1 (exact)
+    assert np.abs(o.dense(MAT_ME, u=np.zeros(nodes)) + M).max() < 1e-17
+    assert np.abs(o.dense(MAT_ME, u=np.ones(nodes)) - 2 * M).max() < 1e-16
+
+
+@pytest.mark.parametrize("dim,n", [(2, 3), (2, 4), (3, 2)])
+def test_me_and_n_exact_quadrature(dim, n):
+    """3-point Gauss is exact for the degree-4 integrands: compare with a
+    brute-force 5-point rule on an arbitrary nodal field."""
+    o = Oracle(dim, n, **CFG1, mg_levels=1)
+    nodes = (n + 1) ** dim
+    u = 2.0 * uniform01(11, nodes) - 1.0
+    ME_ref, N_ref = fr.brute_element_integrals(dim, n, u, npts=5)
+    ME = o.dense(MAT_ME, u=u)
+    assert np.abs(ME - ME_ref).max() <= 1e-15 * np.abs(ME_ref).max() * 10
+    assert np.abs(o.nonlinear(u) - N_ref).max() <= 1e-15 * np.abs(N_ref).max() * 10
+    assert np.allclose(ME, ME.T, rtol=0, atol=1e-18)
+    assert np.abs(o.dense(MAT_ME, u=-u) - ME).max() == 0.0   # even in u
+    # u = x coordinate (a linear field)
+    x = fr.coords(dim, n)[:, 0].copy()
+    ME_ref, N_ref = fr.brute_element_integrals(dim, n, x, npts=5)
+    assert np.abs(o.dense(MAT_ME, u=x) - ME_ref).max() <= 1e-15 * np.abs(ME_ref).max() * 10
+
+
+# ----------------------------------------------------------------------------
+# P3: the generalised (K, M) spectrum is the DCT-I basis
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n", [(2, 8), (3, 4)])
+def test_dct_generalised_eigenpairs(dim, n):
+    o = Oracle(dim, n, **CFG1, mg_levels=1)
+    M = o.dense(MAT_M)
+    K = o.dense(MAT_K)
+    for ks in [(0,) * dim, (1,) + (0,) * (dim - 1), (n,) * dim, tuple(range(1, dim + 1))]:
+        v = fr.dct_mode(dim, n, ks)
+        lam = sum(fr.gen_eig_1d(n, k) for k in ks)
+        assert np.abs(K @ v - lam * (M @ v)).max() <= 1e-12 * max(1.0, lam) * np.abs(M @ v).max()
+
+
+def test_fast_diagonalisation_is_exact():
+    """P4: the DCT solver used below as an exact reference equals a dense solve."""
+    for dim, n in [(2, 8), (3, 4)]:
+        o = Oracle(dim, n, **CFG1, mg_levels=1)
+        A = o.dense(MAT_A, 0)
+        b = uniform01(5, A.shape[0]) - 0.5
+        alpha = 0.37
+        A2 = fr.mass(dim, n) + alpha * fr.stiffness(dim, n)
+        x = fr.fast_diag_solve(dim, n, alpha, b)
+        assert rel(x, np.linalg.solve(A2, b)) < 1e-12
+        del A
+
+
+# ----------------------------------------------------------------------------
+# P5: Chebyshev semi-iteration for A = (1+dt th sigma) M (Sec. 3)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [2, 3])
+def test_chebyshev_mass_interval_and_polynomial(dim):
+    n = 8 if dim == 2 else 4
+    o = Oracle(dim, n, **CFG1, mg_levels=1)
+    lo, hi = o.cheb_interval(0, mass=True)
+    assert lo == pytest.approx(2.0 ** -dim, rel=1e-15)
+    assert hi == pytest.approx(1.5 ** dim, rel=1e-15)
+    M = o.dense(MAT_M)
+    D = np.diag(M)
+    ev = np.linalg.eigvals(M / D[:, None]).real
+    assert ev.min() == pytest.approx(lo, rel=1e-12) and ev.max() == pytest.approx(hi, rel=1e-12)
+    # residual polynomial: x_K = (1 - T_K((th-l)/de)/T_K(th/de)) A^-1 b for an eigenvector
+    K = 10
+    th, de = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    for ks in [(1,) + (0,) * (dim - 1), (n,) * dim, (n // 2,) * dim, tuple([2] * dim)]:
+        v = fr.dct_mode(dim, n, ks)
+        lam = np.prod([(2 + np.cos(np.pi * k / n)) / 2 for k in ks])
+        x = o.cheb_mass(M @ v)
+        factor = 1.0 - fr.cheb_T(K, (th - lam) / de) / fr.cheb_T(K, th / de)
+        assert rel(x, factor * v) < 1e-13
+
+
+@pytest.mark.parametrize("dim,n", [(2, 16), (3, 8)])
+def test_smoother_intervals_match_spectrum(dim, n):
+    """The multigrid smoother interval: max eigenvalue of D^-1 A and the min
+    over the high-frequency DCT modes (some k_d >= N/2)."""
+    o = Oracle(dim, n, **CFG1, mg_levels=2)
+    for level in range(o.levels):
+        nl = n >> level
+        A = o.dense(MAT_A, level)
+        DA = A / np.diag(A)[:, None]
+        lo, hi = o.cheb_interval(level)
+        ev = np.linalg.eigvals(DA).real
+        assert hi == pytest.approx(ev.max(), rel=1e-12)
+        hf = []
+        for ks in np.ndindex(*([nl + 1] * dim)):
+            if max(ks) * 2 < nl:
+                continue
+            v = fr.dct_mode(dim, nl, ks)
+            w = DA @ v
+            i = np.argmax(np.abs(v))
+            hf.append(w[i] / v[i])
+        assert lo == pytest.approx(min(hf), rel=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# P6: multigrid for S^ = M + eps sqrt(c) K (Sec. 2 after eq. (schurinv))
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n", [(2, 32), (3, 8)])
+def test_mg_galerkin_and_transfer(dim, n):
+    o = Oracle(dim, n, **CFG1, mg_levels=0 if dim == 2 else 2)
+    for level in range(o.levels - 1):
+        A = o.scipy(MAT_A, level)
+        Ac = o.scipy(MAT_A, level + 1)
+        P = o.scipy(MAT_P, level)
+        nl = n >> level
+        Pref = fr.kron_list([fr.prolongation_1d(nl // 2)] * dim)
+        assert np.abs(P.toarray() - Pref).max() == 0.0
+        G = (P.T @ A @ P).toarray()
+        assert np.abs(G - Ac.toarray()).max() <= 1e-14 * np.abs(G).max()
+
+
+@pytest.mark.parametrize("dim,n", [(2, 32), (3, 16)])
+def test_mg_symmetric_and_converges_to_exact(dim, n):
+    o = Oracle(dim, n, **CFG1)
+    nodes = o.nodes
+    x = uniform01(21, nodes) - 0.5
+    y = uniform01(22, nodes) - 0.5
+    assert abs(x @ o.mg(y) - y @ o.mg(x)) <= 1e-12 * abs(x @ o.mg(y)) + 1e-15
+    alpha = 0.02 * np.sqrt(1e-4 / (1 + 1e-4 * 100))
+    xs = fr.fast_diag_solve(dim, n, alpha, y)
+    errs = [rel(o.mg(y, c), xs) for c in (1, 2, 4, 8, 30)]
+    assert errs[-1] < 1e-12
+    assert all(errs[i + 1] < errs[i] for i in range(3))
+
+
+def test_mg_contraction_flat_in_n():
+    """One V(2,2) cycle contracts the error by a bounded factor at every N, in a
+    mass-dominated (eps sqrt(c) lam_max ~ 20) and a stiffness-dominated (~2000)
+    regime."""
+    for eps, dt, sigma in [(0.02, 1e-4, 100.0), (0.05, 1e-2, 1.0)]:
+        rates = []
+        for n in (16, 32, 64, 128):
+            o = Oracle(2, n, eps, sigma, 0.0, dt)
+            b = uniform01(3, o.nodes) - 0.5
+            c = dt / (1 + dt * sigma)
+            xs = fr.fast_diag_solve(2, n, eps * np.sqrt(c), b)
+            e1, e3 = rel(o.mg(b, 1), xs), rel(o.mg(b, 3), xs)
+            rates.append((e3 / e1) ** 0.5)
+        assert max(rates) < 0.1, rates
+
+
+# ----------------------------------------------------------------------------
+# P7, P8, P9: block preconditioner, Schur algebra, spectrum (Sec. 2, 3)
+# ----------------------------------------------------------------------------
+def _blocks(o, u):
+    p = o.params
+    dth = p.dt * p.theta
+    M = o.dense(MAT_M)
+    K = o.dense(MAT_K)
+    ME = o.dense(MAT_ME, u=u)
+    A = (1 + dth * p.sigma) * M
+    B = dth * K
+    Cm = -p.eps ** 2 * K - ME
+    D = M
+    c = dth / (1 + dth * p.sigma)
+    return M, K, ME, A, B, Cm, D, c
+
+
+def test_exact_blocks_give_two_iterations():
+    """Sec. 2 after eq. (prec): with exact A^-1 and S^-1 GMRES converges in 2
+    iterations.  Large Chebyshev counts make A~ exact, one-level multigrid makes
+    S^^-1 exact, and many Richardson steps make the Schur solve exact."""
+    n = 8
+    o = Oracle(2, n, **CFG1, mg_levels=1, cheb_A_its=80, schur_richardson=60, gmres_rtol=1e-10)
+    u, _ = noise_state(2, n, 0.0, 1)
+    b = uniform01(9, 2 * o.nodes) - 0.5
+    x, its, st = o.fgmres(u, b)
+    assert st == 0 and its == 2
+    M, K, ME, A, B, Cm, D, c = _blocks(o, u)
+    J = np.block([[A, B], [Cm, D]])
+    assert rel(J @ x, b) < 1e-9
+
+
+def test_schur_formulas_and_apply():
+    n = 8
+    o = Oracle(2, n, **CFG1, mg_levels=1, cheb_A_its=80)
+    u, _ = noise_state(2, n, 0.1, 2)
+    M, K, ME, A, B, Cm, D, c = _blocks(o, u)
+    p = o.params
+    S = D - Cm @ np.linalg.solve(A, B)
+    Mi = np.linalg.inv(M)
+    # eq. (schur)
+    S2 = M + p.eps ** 2 * c * K @ Mi @ K + c * ME @ Mi @ K
+    assert rel(S, S2) < 1e-12
+    # eqs. (outer_approx) and (schurapprox)
+    Sh = M + p.eps * np.sqrt(c) * K
+    St = Sh @ Mi @ Sh
+    St2 = M + p.eps ** 2 * c * K @ Mi @ K + 2 * p.eps * np.sqrt(c) * K
+    assert rel(St, St2) < 1e-12
+    # the oracle's matrix-free S with Chebyshev A~^-1 (80 sweeps: exact)
+    x = uniform01(4, o.nodes) - 0.5
+    assert rel(o.schur_apply(u, x), S @ x) < 1e-12
+
+
+def test_schur_spectrum_lemmas():
+    """Lemma 1 (real eigenvalues) and Lemma 2 (bounds) for S~^-1 S, and the
+    closed form at constant u: (1 + eps^2 c l^2 + c b l)/(1 + eps sqrt(c) l)^2."""
+    n = 8
+    o = Oracle(2, n, **CFG1, mg_levels=1)
+    p = o.params
+    for u in [noise_state(2, n, 0.0, 1)[0], np.full(o.nodes, 0.3)]:
+        M, K, ME, A, B, Cm, D, c = _blocks(o, u)
+        S = D - Cm @ np.linalg.solve(A, B)
+        Sh = M + p.eps * np.sqrt(c) * K
+        St = Sh @ np.linalg.solve(M, Sh)
+        ev = np.linalg.eigvals(np.linalg.solve(St, S))
+        assert np.abs(ev.imag).max() < 1e-10
+        lme = np.linalg.eigvals(np.linalg.solve(M, ME)).real
+        lm, lp = min(lme.min(), 0.0), max(lme.max(), 0.0)
+        lo = 0.5 + np.sqrt(c) * lm / (2 * p.eps)
+        hi = 1.0 + np.sqrt(c) * lp / (2 * p.eps)
+        assert ev.real.min() >= lo - 1e-10 and ev.real.max() <= hi + 1e-10
+    beta = 3 * 0.3 ** 2 - 1
+    lam = np.array([fr.gen_eig_1d(n, kx) + fr.gen_eig_1d(n, ky)
+                    for ky in range(n + 1) for kx in range(n + 1)])
+    pred = (1 + p.eps ** 2 * c * lam ** 2 + c * beta * lam) / (1 + p.eps * np.sqrt(c) * lam) ** 2
+    assert np.abs(np.sort(ev.real) - np.sort(pred)).max() < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# P10: the linear solve against dense LU
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n", [(2, 16), (3, 8)])
+def test_fgmres_matches_dense_lu(dim, n):
+    o = Oracle(dim, n, **CFG1, gmres_rtol=1e-13, gmres_max_restarts=20)
+    u, _ = noise_state(dim, n, 0.0, 3)
+    M, K, ME, A, B, Cm, D, c = _blocks(o, u)
+    J = np.block([[A, B], [Cm, D]])
+    b = uniform01(8, 2 * o.nodes) - 0.5
+    x, its, st = o.fgmres(u, b)
+    assert st == 0
+    assert rel(x, np.linalg.solve(J, b)) < 1e-11
+    assert rel(o.jacobian_apply(u, x), J @ x) < 1e-14
+
+
+# ----------------------------------------------------------------------------
+# P11: one timestep of a single DCT mode (linearised analytic decay factor)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n,theta", [(2, 16, 1.0), (2, 16, 0.5), (3, 8, 1.0)])
+def test_single_mode_decay(dim, n, theta):
+    eps, sigma, dt = 0.05, 30.0, 2e-4
+    o = Oracle(dim, n, eps, sigma, 0.0, dt, theta, newton_atol=1e-22, gmres_rtol=1e-12)
+    ks = (2,) + (1,) * (dim - 1)
+    lam = sum(fr.gen_eig_1d(n, k) for k in ks)
+    beta = -1.0
+    amp = 1e-6
+    v = fr.dct_mode(dim, n, ks)
+    u0 = amp * v
+    w0 = (eps ** 2 * lam + beta) * u0      # consistent with (okb), linearised
+    g = lam * (eps ** 2 * lam + beta) + sigma
+    ratio = (1 - dt * (1 - theta) * g) / (1 + dt * theta * g)
+    if theta == 1.0:
+        u1, w1, info, st = o.timestep(u0, np.zeros_like(u0), 1)
+    else:
+        un, wn = u0.copy(), w0.copy()
+        u1, w1 = u0.copy(), w0.copy()
+        from oracle.okref import OracleInfo
+        import ctypes as C
+        info = OracleInfo()
+        st = o.lib.okref_newton_solve(o.h, u1.ctypes.data_as(C.POINTER(C.c_double)),
+                                      w1.ctypes.data_as(C.POINTER(C.c_double)),
+                                      un.ctypes.data_as(C.POINTER(C.c_double)),
+                                      wn.ctypes.data_as(C.POINTER(C.c_double)), C.byref(info))
+    assert st == 0
+    assert rel(u1, ratio * u0) < 1e-9
+    assert rel(w1, ratio * w0) < 1e-8
+
+
+# ----------------------------------------------------------------------------
+# P12: conservation of the mean, P13: the constant fixed point
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_mean_law(theta):
+    n, m = 16, 0.2
+    o = Oracle(2, n, **dict(CFG1, m=m, dt=2e-4), theta=theta, newton_atol=1e-14)
+    u, w = noise_state(2, n, m, 5, zero_mean=False)
+    u = u + 0.01
+    if theta < 1.0:
+        # a consistent w for the theta-scheme: solve (okb) M w = eps^2 K u + N(u)
+        M = o.dense(MAT_M)
+        K = o.dense(MAT_K)
+        w = np.linalg.solve(M, 0.02 ** 2 * K @ u + o.nonlinear(u))
+    Mv = o.dense(MAT_M).sum(axis=0)
+    e = [Mv @ u - m]
+    for _ in range(3):
+        u, w, info, st = o.timestep(u, w, 1)
+        assert st == 0
+        e.append(Mv @ u - m)
+    dts = 2e-4 * 100.0
+    fac = (1 - dts * (1 - theta)) / (1 + dts * theta)
+    for a, b in zip(e[:-1], e[1:]):
+        assert abs(b - fac * a) < 1e-12
+
+
+def test_fixed_point():
+    for dim, n in [(2, 16), (3, 8)]:
+        m = 0.3
+        o = Oracle(dim, n, **dict(CFG1, m=m))
+        u = np.full(o.nodes, m)
+        w = np.full(o.nodes, m ** 3 - m)
+        F, nrm = o.residual(u, w, u)
+        assert nrm < 1e-16
+        u1, w1, info, st = o.timestep(u, w, 1)
+        assert st == 0 and info.newton_its == 0
+        assert np.array_equal(u1, u) and np.array_equal(w1, w)
+
+
+# ----------------------------------------------------------------------------
+# P14: F versus J (eq. (newton) is the derivative of the discrete residual)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n", [(2, 8), (3, 4)])
+def test_jacobian_is_derivative_of_residual(dim, n):
+    o = Oracle(dim, n, **dict(CFG1, m=0.1))
+    u, _ = noise_state(dim, n, 0.1, 6)
+    w = 0.3 * (uniform01(7, o.nodes) - 0.5)
+    un = u + 0.01 * (uniform01(8, o.nodes) - 0.5)
+    v = uniform01(9, 2 * o.nodes) - 0.5
+    eta = 1e-4
+    nn = o.nodes
+    Fp, _ = o.residual(u + eta * v[:nn], w + eta * v[nn:], un)
+    Fm, _ = o.residual(u - eta * v[:nn], w - eta * v[nn:], un)
+    fd = (Fp - Fm) / (2 * eta)
+    assert rel(fd, o.jacobian_apply(u, v)) < 1e-8
+
+
+# ----------------------------------------------------------------------------
+# P15: iteration counts flat under refinement (Table 1's shape) and in eps (Table 2)
+# ----------------------------------------------------------------------------
+def test_iteration_counts_flat_under_refinement():
+    avgs = []
+    for n in (16, 32, 64, 128):
+        o = Oracle(2, n, **CFG1)
+        u, w = noise_state(2, n, 0.0, 1)
+        _, _, info, st = o.timestep(u, w, 1)
+        assert st == 0
+        avgs.append(info.fgmres_its_total / info.newton_its)
+    assert max(avgs) / min(avgs) <= 1.3, avgs
+
+
+def test_iteration_counts_flat_in_eps():
+    avgs = []
+    for eps in (0.04, 0.02, 0.01):
+        n = int(round(2 / eps))
+        n = 1 << int(np.ceil(np.log2(n)))
+        o = Oracle(2, n, eps, 100.0, 0.0, eps * eps)
+        u, w = noise_state(2, n, 0.0, 1)
+        _, _, info, st = o.timestep(u, w, 1)
+        assert st == 0
+        avgs.append(info.fgmres_its_total / info.newton_its)
+    assert max(avgs) / min(avgs) <= 1.35, avgs
+
+
+# ----------------------------------------------------------------------------
+# P16: whole Newton step against a dense brute-force Newton
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n", [(2, 8), (3, 4)])
+def test_timestep_matches_dense_newton(dim, n):
+    eps, sigma, m, dt = 0.05, 50.0, 0.1, 5e-4
+    o = Oracle(dim, n, eps, sigma, m, dt, newton_atol=1e-15, gmres_rtol=1e-13)
+    u0, w0 = noise_state(dim, n, m, 4, amp=0.2)
+    M = fr.mass(dim, n)
+    K = fr.stiffness(dim, n)
+
+    def F(u, w):
+        _, NV = fr.brute_element_integrals(dim, n, u, npts=5)
+        f1 = M @ (u - u0) + dt * K @ w + dt * sigma * M @ (u - m)
+        f2 = M @ w - eps ** 2 * K @ u - NV
+        return np.concatenate([f1, f2])
+
+    u, w = u0.copy(), w0.copy()
+    for _ in range(20):
+        f = F(u, w)
+        if np.linalg.norm(f) < 1e-16:
+            break
+        ME, _ = fr.brute_element_integrals(dim, n, u, npts=5)
+        J = np.block([[(1 + dt * sigma) * M, dt * K], [-eps ** 2 * K - ME, M]])
+        d = np.linalg.solve(J, -f)
+        u, w = u + d[:len(u)], w + d[len(u):]
+    u1, w1, info, st = o.timestep(u0, w0, 1)
+    assert st == 0
+    assert rel(u1, u) < 1e-12 and rel(w1, w) < 1e-11
+
+
+# ----------------------------------------------------------------------------
+# Local (matrix-free) rows used for sampled checks at full size
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,n,theta", [(2, 8, 1.0), (2, 8, 0.5), (3, 4, 1.0)])
+def test_local_rows_match_assembled(dim, n, theta):
+    o = Oracle(dim, n, **dict(CFG1, m=0.1), theta=theta)
+    u, _ = noise_state(dim, n, 0.1, 6)
+    w = 0.3 * (uniform01(7, o.nodes) - 0.5)
+    un = u + 0.01 * (uniform01(8, o.nodes) - 0.5)
+    wn = w + 0.01 * (uniform01(10, o.nodes) - 0.5)
+    F, _ = o.residual(u, w, un, wn)
+    nodes = np.arange(o.nodes)
+    f1, f2 = local_residual(o.params, u, w, un, wn, nodes)
+    assert np.abs(np.concatenate([f1, f2]) - F).max() <= 1e-15 * np.abs(F).max() * 10
+    x = uniform01(9, 2 * o.nodes) - 0.5
+    y = o.jacobian_apply(u, x)
+    y1, y2 = local_jacobian(o.params, u, x, nodes)
+    assert np.abs(np.concatenate([y1, y2]) - y).max() <= 1e-14 * np.abs(y).max()
