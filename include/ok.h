@@ -1,0 +1,201 @@
+/*
+ * ok.h -- C ABI of libok.so: the preconditioned Newton-Krylov timestep of the
+ * Ohta-Kawasaki equations on one MI355X (gfx950) GPU.
+ *
+ * Method: Farrell & Pearson, "A preconditioner for the Ohta-Kawasaki
+ * equation" (arXiv:1603.04570).
+ *   Sec. 1, eqs. (oka)-(okb) with Neumann conditions (okbcs): the PDE
+ *     u_t - lap w + sigma (u - m) = 0,   w + eps^2 lap u - u(u^2 - 1) = 0.
+ *   Sec. 2, eq. (newton): each Newton iteration of the theta-method solves
+ *     J [du; dw] = [f1; f2],  J = [(1+dt th sigma) M, dt th K; -eps^2 K - M_E(u), M].
+ *   Sec. 2, eq. (prec): block lower-triangular preconditioner
+ *     P^-1 = diag(A~^-1, S~^-1) [I, 0; -C A~^-1, I],
+ *   with, eqs. (outer_approx)/(schurinv), S~^-1 = S^^-1 M S^^-1 and
+ *     S^ = M + eps sqrt(c) K,  c = dt th / (1 + dt th sigma).
+ *   Sec. 3: A~^-1 by Chebyshev semi-iteration on the (scaled) mass matrix.
+ *   Sec. 4: GMRES as the outer solver; S^^-1 by multigrid V-cycles.
+ *
+ * Discretisation: Q1 (bilinear/trilinear) elements on the uniform grid of
+ * Omega = (0,1)^d, d in {2,3}, with N elements per direction; all integrals
+ * exact (3-point Gauss per direction).  The S^^-1 action is one geometric
+ * multigrid V(pre,post) cycle with Chebyshev-Jacobi smoothing, R = P^T and an
+ * exact coarse solve; A~^-1 is Chebyshev-Jacobi on M; the outer solver is
+ * flexible GMRES(m), right preconditioned, modified Gram-Schmidt.
+ *
+ * Data layout (every array argument): FP64, contiguous, device memory, node
+ * index i + (N+1)*(j + (N+1)*k) with x fastest; a field has n = (N+1)^d
+ * entries; a two-field vector is [u-block; w-block] (2n entries).  Arrays must
+ * be 8-byte aligned; 256-byte alignment is recommended.
+ *
+ * Memory ownership: the caller allocates all device memory -- the state
+ * vectors and one workspace blob of ok_workspace_bytes() bytes -- and keeps it
+ * alive until ok_destroy().  The library never allocates device memory; it
+ * owns only its host-side context and a few HIP events/graphs.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  Apply functions (ok_jacobian_apply, ok_precond_apply, ...) are
+ * asynchronous on that stream.  Functions that return host scalars or stats
+ * (ok_residual, ok_newton_step, ok_timestep, ok_fgmres) synchronise it.
+ * A context must not be used from two streams or threads at once.
+ *
+ * Errors: every entry point returns 0 on success or a negative ok_status.
+ * Nothing throws across the ABI.  ok_last_error() gives a message for the
+ * last failure on a context.  On a solver failure the state holds the last
+ * iterate and the info/stats structs are filled.
+ */
+#ifndef OK_H
+#define OK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum ok_status {
+  OK_SUCCESS = 0,
+  OK_E_INVALID = -1,       /* bad d, N, parameter range, null/misaligned pointer */
+  OK_E_WORKSPACE = -2,     /* workspace null, misaligned or smaller than required */
+  OK_E_HIP = -3,           /* a HIP runtime call or kernel launch failed */
+  OK_E_GMRES_MAXIT = -4,   /* FGMRES hit gmres_max_restarts without converging */
+  OK_E_NEWTON_MAXIT = -5,  /* Newton hit newton_max_it without converging */
+  OK_E_NONFINITE = -6      /* NaN/Inf in ||F|| or in the Krylov recurrence */
+};
+
+/* Preconditioner precision. */
+#define OK_FP64 0   /* everything in FP64 */
+#define OK_MIXED 1  /* Chebyshev (A~^-1), multigrid (S^^-1), mass action and the
+                       stored preconditioned vectors in FP32; FGMRES, J, the
+                       residual and the M_E(u) coupling stay FP64 */
+
+typedef struct ok_ctx ok_ctx;
+
+typedef struct {
+  int32_t dim;             /* d in {2,3}                                         */
+  int32_t n;               /* N elements per direction; N = Nc * 2^(levels-1),  */
+                           /* Nc >= 2 (default levels: halve down to N <= 8)     */
+  double eps;              /* interfacial thickness epsilon > 0 (Sec. 1)        */
+  double sigma;            /* nonlocal coefficient sigma >= 0 (Sec. 1)          */
+  double m;                /* mean value m of u, |m| < 1 (Sec. 1)               */
+  double dt;               /* timestep > 0                                       */
+  double theta;            /* theta-method parameter, 0 < theta <= 1 (Sec. 2)    */
+  int32_t precision;       /* OK_FP64 or OK_MIXED                                */
+  int32_t gmres_restart;   /* m of FGMRES(m), 1..64 (default 30)                 */
+  int32_t gmres_max_restarts; /* restarts allowed after the first cycle (10)     */
+  double gmres_rtol;       /* stop at ||r||_2 <= rtol ||b||_2 (1e-8)             */
+  double newton_atol;      /* stop at ||F||_2 <= atol (1e-10)                    */
+  int32_t newton_max_it;   /* (25)                                               */
+  int32_t cheb_A_its;      /* Chebyshev iterations for A~^-1, >= 1 (10)          */
+  int32_t schur_richardson;/* Richardson iterations on S with S~^-1, >= 1 (1)    */
+  int32_t mg_levels;       /* 0 = automatic                                      */
+  int32_t mg_pre, mg_post; /* Chebyshev smoothing iterations, >= 1 (2, 2)        */
+  int32_t mg_cycles;       /* V-cycles per S^^-1 application, >= 1 (1)           */
+} ok_params;
+
+typedef struct {
+  int32_t status;          /* result of this Newton iteration's linear solve    */
+  int32_t fgmres_its;      /* FGMRES iterations (all cycles)                     */
+  int32_t restarts;        /* FGMRES restarts taken                              */
+  double fnorm;            /* ||F(u,w)||_2 before the update                     */
+  double lin_res;          /* final FGMRES residual estimate / ||F||             */
+} ok_newton_info;
+
+#define OK_HIST 256
+typedef struct {
+  int32_t status;
+  int32_t steps_done;
+  int32_t newton_its;                  /* total over all steps                   */
+  int32_t fgmres_its_total;
+  int32_t newton_per_step[OK_HIST];    /* Newton iterations of each step         */
+  int32_t fgmres_its[OK_HIST];         /* FGMRES iterations of each Newton iter  */
+  double fnorm[OK_HIST];               /* ||F|| at each residual evaluation      */
+  int32_t fnorm_count;
+  double step_ms[OK_HIST];             /* wall time of each step (HIP events)    */
+} ok_stats;
+
+/* Fill *p with the defaults above (dim=3, n=128, eps=0.01, sigma=1000,
+ * m=0.1, dt=2e-5, theta=1, OK_FP64). */
+int ok_default_params(ok_params *p);
+
+/* Bytes of device workspace ok_assemble_mesh needs for these parameters
+ * (the whole per-problem HBM footprint apart from the caller's u, w). */
+int ok_workspace_bytes(const ok_params *p, size_t *bytes);
+
+/* Set up a problem (Sec. 2: the preconditioner needs no reassembly between
+ * Newton steps, so everything is built once here): derived constants c,
+ * eps sqrt(c), 1 + dt th sigma; the multigrid levels and closed-form
+ * Chebyshev intervals; the coarse-level exact solver; the carving of d_ws.
+ * d_ws: device pointer, 256-byte aligned, ws_bytes >= ok_workspace_bytes().
+ * On success *out owns a host context; free it with ok_destroy(). */
+int ok_assemble_mesh(const ok_params *p, void *d_ws, size_t ws_bytes, void *stream,
+                     ok_ctx **out);
+
+/* Newton residual of the theta-method (Sec. 2, the right-hand side of
+ * (newton) is f = -F):
+ *   F1 = M(u - un) + dt K (th w + (1-th) wn) + dt sigma M (th u + (1-th) un - m)
+ *   F2 = M w - eps^2 K u - N(u),  N_i = int (u^3 - u) phi_i.
+ * u, w, un: n each; wn: n (may be NULL when theta == 1); d_F: 2n output (may
+ * be NULL).  *h_norm (may be NULL) receives ||F||_2.  Synchronises. */
+int ok_residual(ok_ctx *ctx, const double *d_u, const double *d_w, const double *d_un,
+                const double *d_wn, double *d_F, double *h_norm, void *stream);
+
+/* y = J(u) x, eq. (newton): y1 = (1+dt th sigma) M x1 + dt th K x2,
+ * y2 = -eps^2 K x1 - M_E(u) x1 + M x2.  u: n; x, y: 2n (x != y).  Async. */
+int ok_jacobian_apply(ok_ctx *ctx, const double *d_u, const double *d_x, double *d_y,
+                      void *stream);
+
+/* z = P^-1 r, eq. (prec) with the matching Schur approximation (schurinv):
+ *   z1 = Chebyshev_M(r1) / (1 + dt th sigma)
+ *   y  = r2 + eps^2 K z1 + M_E(u) z1                (= r2 - C z1)
+ *   z2 = S^^-1 M S^^-1 y  (multigrid; Richardson on S if schur_richardson > 1)
+ * u: n; r, z: 2n (r != z).  Async. */
+int ok_precond_apply(ok_ctx *ctx, const double *d_u, const double *d_r, double *d_z,
+                     void *stream);
+
+/* Components of the preconditioner, exposed for testing:
+ * x = Chebyshev_M(r) (cheb_A_its iterations on M, no 1+dt th sigma scaling);
+ * x = MG(b) (`cycles` V-cycles on M + eps sqrt(c) K from x = 0).
+ * FP64 in/out of n entries regardless of precision.  Async. */
+int ok_cheb_mass(ok_ctx *ctx, const double *d_r, double *d_x, void *stream);
+int ok_mg_apply(ok_ctx *ctx, const double *d_b, double *d_x, int32_t cycles, void *stream);
+
+/* Solve J(u) x = b with FGMRES(m) from x = 0 (Sec. 2 and 4).  u: n; b, x: 2n.
+ * *its (may be NULL) receives the iteration count.  Synchronises. */
+int ok_fgmres(ok_ctx *ctx, const double *d_u, const double *d_b, double *d_x, int32_t *its,
+              void *stream);
+
+/* ONE Newton iteration in place: F(u,w), then J dx = -F by FGMRES, then
+ * (u,w) += dx.  un, wn: previous time level (wn may be NULL if theta == 1).
+ * info (may be NULL) is filled.  Synchronises. */
+int ok_newton_step(ok_ctx *ctx, double *d_u, double *d_w, const double *d_un,
+                   const double *d_wn, ok_newton_info *info, void *stream);
+
+/* nsteps timesteps in place: for each, (un,wn) <- (u,w) and Newton from
+ * (u,w) = (un,wn) until ||F||_2 <= newton_atol.  stats may be NULL.
+ * Synchronises. */
+int ok_timestep(ok_ctx *ctx, double *d_u, double *d_w, int32_t nsteps, ok_stats *stats,
+                void *stream);
+
+/* Per-kernel timing for roofline reporting: after ok_profile_enable(ctx, k)
+ * every launch of kernel class k is bracketed by HIP events on the stream it
+ * runs on; ok_profile_read returns the number of launches, their summed
+ * duration and the algorithmic bytes they moved (each vector read once and
+ * written once), then clears the counters.  Classes are listed below. */
+enum ok_kernel_class {
+  OK_K_NONE = 0, OK_K_CHEB_MASS = 1, OK_K_MG_SMOOTH = 2, OK_K_ELEMENT = 3,
+  OK_K_STENCIL_ANY = 4, OK_K_KRYLOV = 5
+};
+int ok_profile_enable(ok_ctx *ctx, int32_t kernel_class);
+int ok_profile_read(ok_ctx *ctx, int64_t *launches, double *total_ms, double *bytes);
+
+/* Destroy a context (frees host state only; the caller frees its memory). */
+int ok_destroy(ok_ctx *ctx);
+
+const char *ok_error_string(int status);
+const char *ok_last_error(const ok_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OK_H */

@@ -1,0 +1,346 @@
+// Element quadrature of the u-dependent terms on the finest Q1 grid:
+//   (M_E(u) x)_i = int (3u^2 - 1) x phi_i      (Sec. 2, entries of M_E)
+//   N(u)_i       = int (u^3 - u) phi_i          (weak form of u(u^2-1) in (okb))
+// with u, x the Q1 interpolants.  The integrands are of degree 4 per
+// direction, so the 3-point Gauss-Legendre rule per direction is exact.
+//
+// Layout of the work: a block of 8 wavefronts covers 7 node rows of the x-y
+// plane and streams along z one element layer at a time.  Wavefront w owns
+// element row ey = y0 - 1 + w; lane l owns elements ex = l + 64c.  Each lane
+// evaluates its element by sum factorisation (2^d corners -> 3^d Gauss points
+// -> integrand -> 2^d corner contributions).  Contributions are summed into
+// nodes deterministically: along x with cross-lane shuffles, along y through
+// LDS (wavefront w reads w-1), along z with a register carry.
+#include "ok_internal.h"
+
+#include <algorithm>
+
+namespace okd {
+
+namespace {
+
+constexpr int kRows = 7;              // node rows per block
+constexpr int kWaves = kRows + 1;     // one halo element row
+
+// Gauss points 1/2 -+ sqrt(15)/10 and 1/2 on [0,1], weights 5/18, 8/18, 5/18.
+constexpr double kG0 = 0.11270166537925831148;
+constexpr double kW0 = 5.0 / 18.0;
+constexpr double kW1 = 8.0 / 18.0;
+
+__device__ __forceinline__ double ld(const double* p) { return *p; }
+__device__ __forceinline__ double ld(const float* p) { return (double)*p; }
+
+// Values at the 3 Gauss points of the linear interpolant of (v0, v1).
+__device__ __forceinline__ void lerp3(double v0, double v1, double* o) {
+  double d = v1 - v0;
+  o[0] = v0 + kG0 * d;
+  o[1] = 0.5 * (v0 + v1);
+  o[2] = v1 - kG0 * d;
+}
+
+// Transpose of lerp3: contributions of 3 Gauss-point values to the 2 ends.
+__device__ __forceinline__ void proj3(const double* t, double& o0, double& o1) {
+  double m = 0.5 * t[1];
+  o0 = (1.0 - kG0) * t[0] + m + kG0 * t[2];
+  o1 = kG0 * t[0] + m + (1.0 - kG0) * t[2];
+}
+
+__device__ __forceinline__ double wq(int q) { return q == 1 ? kW1 : kW0; }
+
+__device__ __forceinline__ int remap(int b, int nb) {
+  int q = nb / 8, r = nb % 8;
+  int x = b % 8, t = b / 8;
+  return ((x < r) ? x * (q + 1) : r * (q + 1) + (x - r) * q) + t;
+}
+
+// One 3D element: corners v[az][ay][ax] of u and x; returns corner
+// contributions E[az][ay][ax] without the h^3 factor.
+template <int MODE>
+__device__ __forceinline__ void element3(const double (&u)[2][2][2], const double (&x)[2][2][2],
+                                         double (&E)[2][2][2]) {
+  double uq[3][3][3], xq[3][3][3];
+  {
+    double a[2][2][3], b[2][3][3];
+    for (int az = 0; az < 2; az++)
+      for (int ay = 0; ay < 2; ay++) lerp3(u[az][ay][0], u[az][ay][1], a[az][ay]);
+    for (int az = 0; az < 2; az++)
+      for (int qx = 0; qx < 3; qx++) {
+        double t[3];
+        lerp3(a[az][0][qx], a[az][1][qx], t);
+        for (int qy = 0; qy < 3; qy++) b[az][qy][qx] = t[qy];
+      }
+    for (int qy = 0; qy < 3; qy++)
+      for (int qx = 0; qx < 3; qx++) {
+        double t[3];
+        lerp3(b[0][qy][qx], b[1][qy][qx], t);
+        for (int qz = 0; qz < 3; qz++) uq[qz][qy][qx] = t[qz];
+      }
+  }
+  if (MODE == 0) {
+    double a[2][2][3], b[2][3][3];
+    for (int az = 0; az < 2; az++)
+      for (int ay = 0; ay < 2; ay++) lerp3(x[az][ay][0], x[az][ay][1], a[az][ay]);
+    for (int az = 0; az < 2; az++)
+      for (int qx = 0; qx < 3; qx++) {
+        double t[3];
+        lerp3(a[az][0][qx], a[az][1][qx], t);
+        for (int qy = 0; qy < 3; qy++) b[az][qy][qx] = t[qy];
+      }
+    for (int qy = 0; qy < 3; qy++)
+      for (int qx = 0; qx < 3; qx++) {
+        double t[3];
+        lerp3(b[0][qy][qx], b[1][qy][qx], t);
+        for (int qz = 0; qz < 3; qz++) xq[qz][qy][qx] = t[qz];
+      }
+  }
+  // integrand times the Gauss weights
+  for (int qz = 0; qz < 3; qz++)
+    for (int qy = 0; qy < 3; qy++)
+      for (int qx = 0; qx < 3; qx++) {
+        double w = wq(qx) * wq(qy) * wq(qz);
+        double v = uq[qz][qy][qx];
+        if (MODE == 0)
+          uq[qz][qy][qx] = w * (3.0 * v * v - 1.0) * xq[qz][qy][qx];
+        else
+          uq[qz][qy][qx] = w * (v * v * v - v);
+      }
+  // project back: z, then y, then x
+  double b[2][3][3];
+  for (int qy = 0; qy < 3; qy++)
+    for (int qx = 0; qx < 3; qx++) {
+      double t[3] = {uq[0][qy][qx], uq[1][qy][qx], uq[2][qy][qx]};
+      proj3(t, b[0][qy][qx], b[1][qy][qx]);
+    }
+  for (int az = 0; az < 2; az++) {
+    double a[2][3];
+    for (int qx = 0; qx < 3; qx++) {
+      double t[3] = {b[az][0][qx], b[az][1][qx], b[az][2][qx]};
+      proj3(t, a[0][qx], a[1][qx]);
+    }
+    for (int ay = 0; ay < 2; ay++) proj3(a[ay], E[az][ay][0], E[az][ay][1]);
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void element2(const double (&u)[2][2], const double (&x)[2][2],
+                                         double (&E)[2][2]) {
+  double uq[3][3], xq[3][3];
+  {
+    double a[2][3];
+    for (int ay = 0; ay < 2; ay++) lerp3(u[ay][0], u[ay][1], a[ay]);
+    for (int qx = 0; qx < 3; qx++) {
+      double t[3];
+      lerp3(a[0][qx], a[1][qx], t);
+      for (int qy = 0; qy < 3; qy++) uq[qy][qx] = t[qy];
+    }
+  }
+  if (MODE == 0) {
+    double a[2][3];
+    for (int ay = 0; ay < 2; ay++) lerp3(x[ay][0], x[ay][1], a[ay]);
+    for (int qx = 0; qx < 3; qx++) {
+      double t[3];
+      lerp3(a[0][qx], a[1][qx], t);
+      for (int qy = 0; qy < 3; qy++) xq[qy][qx] = t[qy];
+    }
+  }
+  for (int qy = 0; qy < 3; qy++)
+    for (int qx = 0; qx < 3; qx++) {
+      double w = wq(qx) * wq(qy);
+      double v = uq[qy][qx];
+      if (MODE == 0)
+        uq[qy][qx] = w * (3.0 * v * v - 1.0) * xq[qy][qx];
+      else
+        uq[qy][qx] = w * (v * v * v - v);
+    }
+  double a[2][3];
+  for (int qx = 0; qx < 3; qx++) {
+    double t[3] = {uq[0][qx], uq[1][qx], uq[2][qx]};
+    proj3(t, a[0][qx], a[1][qx]);
+  }
+  for (int ay = 0; ay < 2; ay++) proj3(a[ay], E[ay][0], E[ay][1]);
+}
+
+struct EShape {
+  int epl;       // elements per lane along x: ceil(N/64)
+  int rowtiles;  // ceil((N+1)/kRows)
+  int zc, nzc;   // planes per block, z-chunks
+};
+
+EShape element_shape(const Grid& g) {
+  EShape s;
+  s.epl = (g.N + 63) / 64;
+  s.rowtiles = (g.nn + kRows - 1) / kRows;
+  if (g.dim == 2) {
+    s.zc = 1;
+    s.nzc = 1;
+  } else {
+    int64_t zc = ((int64_t)g.nn * s.rowtiles + 599) / 600;
+    zc = std::max<int64_t>(4, std::min<int64_t>(zc, 32));
+    s.zc = (int)std::min<int64_t>(zc, g.nn);
+    s.nzc = (g.nn + s.zc - 1) / s.zc;
+  }
+  return s;
+}
+
+// EPLT > 0: elements per lane fixed at compile time (3D, keeps the z carry in
+// registers); EPLT == 0: taken from the shape (2D, no carry).
+template <int DIM, int MODE, int EPLT, class TX, class TO>
+__global__ void __launch_bounds__(64 * kWaves)
+    k_element(const double* __restrict__ u, const TX* __restrict__ x,
+              const double* __restrict__ add, TO* __restrict__ out, Grid g, EShape sh,
+              double alpha, double beta) {
+  constexpr int NZ = (DIM == 3) ? 2 : 1;  // corner layers per element
+  __shared__ double xch[2][kWaves][NZ][64];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int b = remap(blockIdx.x, gridDim.x);
+  const int rt = b % sh.rowtiles;
+  const int zch = b / sh.rowtiles;
+  const int N = g.N, nn = g.nn;
+  const int64_t plane = g.plane;
+  const int y0 = rt * kRows;
+  const int ey = y0 - 1 + w;          // element row of this wavefront
+  const bool row_ok = (ey >= 0 && ey < N);
+  const bool out_row = (w >= 1 && ey <= N);  // node row ey is output by this wavefront
+  const double hd = (DIM == 3) ? g.h * g.h * g.h : g.h * g.h;
+  const double sc = alpha * hd;
+
+  int z0 = 0, z1 = 1;
+  if (DIM == 3) {
+    z0 = zch * sh.zc;
+    z1 = min(z0 + sh.zc, nn);
+  }
+  const int epl = (EPLT > 0) ? EPLT : sh.epl;
+  double carry[EPLT + 1];
+#pragma unroll
+  for (int c = 0; c <= EPLT; c++) carry[c] = 0.0;
+
+  const int lz0 = (DIM == 3) ? z0 - 1 : 0;
+  const int lz1 = (DIM == 3) ? z1 - 1 : 0;
+  int buf = 0;
+  for (int ez = lz0; ez <= lz1; ez++) {
+    const bool layer_ok = (DIM == 2) || (ez >= 0 && ez < N);
+    double prevR[2][NZ];  // lane-63 right contributions of the previous slot
+    for (int a = 0; a < 2; a++)
+      for (int cz = 0; cz < NZ; cz++) prevR[a][cz] = 0.0;
+#pragma unroll
+    for (int c = 0; c <= epl; c++) {
+      const int i = lane + 64 * c;
+      double L[2][NZ], R[2][NZ];  // [ay][cz]: left (ax=0) and right (ax=1) corner parts
+      for (int a = 0; a < 2; a++)
+        for (int cz = 0; cz < NZ; cz++) L[a][cz] = R[a][cz] = 0.0;
+      if (c < epl && row_ok && layer_ok && i < N) {
+        if (DIM == 3) {
+          double uc[2][2][2], xc[2][2][2], E[2][2][2];
+          for (int az = 0; az < 2; az++)
+            for (int ay = 0; ay < 2; ay++) {
+              int64_t base = (int64_t)(ez + az) * plane + (int64_t)(ey + ay) * nn + i;
+              uc[az][ay][0] = u[base];
+              uc[az][ay][1] = u[base + 1];
+              if (MODE == 0) {
+                xc[az][ay][0] = ld(x + base);
+                xc[az][ay][1] = ld(x + base + 1);
+              } else {
+                xc[az][ay][0] = xc[az][ay][1] = 0.0;
+              }
+            }
+          element3<MODE>(uc, xc, E);
+          for (int ay = 0; ay < 2; ay++)
+            for (int az = 0; az < 2; az++) {
+              L[ay][az] = E[az][ay][0];
+              R[ay][az] = E[az][ay][1];
+            }
+        } else {
+          double uc[2][2], xc[2][2], E[2][2];
+          for (int ay = 0; ay < 2; ay++) {
+            int64_t base = (int64_t)(ey + ay) * nn + i;
+            uc[ay][0] = u[base];
+            uc[ay][1] = u[base + 1];
+            if (MODE == 0) {
+              xc[ay][0] = ld(x + base);
+              xc[ay][1] = ld(x + base + 1);
+            } else {
+              xc[ay][0] = xc[ay][1] = 0.0;
+            }
+          }
+          element2<MODE>(uc, xc, E);
+          for (int ay = 0; ay < 2; ay++) {
+            L[ay][0] = E[ay][0];
+            R[ay][0] = E[ay][1];
+          }
+        }
+      }
+      // x: node i gets L of element i and R of element i-1 (lane-1, or lane 63
+      // of the previous slot).
+      double X[2][NZ];
+      for (int a = 0; a < 2; a++)
+        for (int cz = 0; cz < NZ; cz++) {
+          double up = __shfl_up(R[a][cz], 1);
+          X[a][cz] = L[a][cz] + (lane >= 1 ? up : prevR[a][cz]);
+          prevR[a][cz] = __shfl(R[a][cz], 63);
+        }
+      // y: node row ey gets the ay=0 parts of row ey and the ay=1 parts of row ey-1.
+      for (int cz = 0; cz < NZ; cz++) xch[buf][w][cz][lane] = X[1][cz];
+      __syncthreads();
+      if (out_row) {
+        double tot[NZ];
+        for (int cz = 0; cz < NZ; cz++) tot[cz] = X[0][cz] + xch[buf][w - 1][cz][lane];
+        const bool node_ok = (i <= N);
+        if (DIM == 2) {
+          if (node_ok) {
+            int64_t idx = (int64_t)ey * nn + i;
+            double v = sc * tot[0];
+            if (add) v += beta * add[idx];
+            out[idx] = (TO)v;
+          }
+        } else {
+          if (ez >= z0 && node_ok) {
+            int64_t idx = (int64_t)ez * plane + (int64_t)ey * nn + i;
+            double v = sc * ((EPLT > 0 ? carry[c] : 0.0) + tot[0]);
+            if (add) v += beta * add[idx];
+            out[idx] = (TO)v;
+          }
+          if (EPLT > 0) carry[c] = tot[NZ - 1];
+        }
+      }
+      buf ^= 1;
+    }
+  }
+}
+
+}  // namespace
+
+template <class TX, class TO>
+hipError_t launch_element(const Grid& g, int mode, const double* u, const TX* x,
+                          const double* add, double alpha, double beta, TO* out, hipStream_t st) {
+  EShape sh = element_shape(g);
+  int blocks = sh.rowtiles * sh.nzc;
+  dim3 grid(blocks), block(64 * kWaves);
+#define OKD_EL(D, M, E)                                                                     \
+  hipLaunchKernelGGL((k_element<D, M, E, TX, TO>), grid, block, 0, st, u, x, add, out, g, sh, \
+                     alpha, beta)
+  if (g.dim == 2) {
+    if (mode == 0) OKD_EL(2, 0, 0); else OKD_EL(2, 1, 0);
+  } else {
+    int e = sh.epl;
+    if (e > 8) return hipErrorInvalidValue;
+    if (mode == 0) {
+      if (e == 1) OKD_EL(3, 0, 1); else if (e == 2) OKD_EL(3, 0, 2);
+      else if (e <= 4) { sh.epl = 4; OKD_EL(3, 0, 4); } else { sh.epl = 8; OKD_EL(3, 0, 8); }
+    } else {
+      if (e == 1) OKD_EL(3, 1, 1); else if (e == 2) OKD_EL(3, 1, 2);
+      else if (e <= 4) { sh.epl = 4; OKD_EL(3, 1, 4); } else { sh.epl = 8; OKD_EL(3, 1, 8); }
+    }
+  }
+#undef OKD_EL
+  return hipGetLastError();
+}
+
+template hipError_t launch_element<double, double>(const Grid&, int, const double*,
+                                                   const double*, const double*, double, double,
+                                                   double*, hipStream_t);
+template hipError_t launch_element<float, double>(const Grid&, int, const double*, const float*,
+                                                  const double*, double, double, double*,
+                                                  hipStream_t);
+
+}  // namespace okd

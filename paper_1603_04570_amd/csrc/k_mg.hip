@@ -1,0 +1,209 @@
+// Multigrid transfers between nested uniform Q1 grids and the exact
+// coarse-grid solve of M + alpha K.
+//
+// Prolongation P is Q1 interpolation from N/2 to N elements per direction:
+// a fine node copies the coarse node at an even index and averages the two
+// coarse neighbours at an odd index, direction by direction (tensor product
+// of the 1D weights 1 and 1/2).  Restriction is its transpose R = P^T, the
+// finite-element restriction that makes P^T A_h P equal the rediscretised
+// coarse operator.
+//
+// Coarse solve: on a uniform grid with Neumann ends the DCT-I vectors
+// v_k(j) = cos(k pi j / N) diagonalise M + alpha K in the sense
+// (M + alpha K) V = W V Lambda, with W the trapezoid weights and
+// Lambda_k = prod mu + alpha sum kap prod mu (mu = (h/3)(2 + cos), kap =
+// (2/h)(1 - cos)), and V^T W V = Gamma = diag(N/2, with N at k = 0, N).
+// Hence (M + alpha K)^-1 = V (Lambda Gamma)^-1 V^T; V is symmetric.
+#include "ok_internal.h"
+
+namespace okd {
+
+namespace {
+
+__device__ __forceinline__ double ld(const double* p) { return *p; }
+__device__ __forceinline__ double ld(const float* p) { return (double)*p; }
+
+template <int DIM, class T>
+__global__ void __launch_bounds__(256)
+    k_restrict(const T* __restrict__ r, T* __restrict__ bc, Grid f, Grid c) {
+  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= c.nodes) return;
+  int ci = (int)(I % c.nn);
+  int cj = (int)((I / c.nn) % c.nn);
+  int ck = (DIM == 3) ? (int)(I / c.plane) : 0;
+  double s = 0.0;
+  const int kz = (DIM == 3) ? 1 : 0;
+  for (int dk = -kz; dk <= kz; dk++) {
+    int fk = 2 * ck + dk;
+    if (fk < 0 || fk > f.N) continue;
+    double wk = dk ? 0.5 : 1.0;
+    for (int dj = -1; dj <= 1; dj++) {
+      int fj = 2 * cj + dj;
+      if (fj < 0 || fj > f.N) continue;
+      double wj = wk * (dj ? 0.5 : 1.0);
+      int64_t row = (int64_t)fk * f.plane + (int64_t)fj * f.nn;
+      for (int di = -1; di <= 1; di++) {
+        int fi = 2 * ci + di;
+        if (fi < 0 || fi > f.N) continue;
+        s += wj * (di ? 0.5 : 1.0) * ld(r + row + fi);
+      }
+    }
+  }
+  bc[I] = (T)s;
+}
+
+template <int DIM, class T>
+__global__ void __launch_bounds__(256)
+    k_prolong_add(const T* __restrict__ ec, T* __restrict__ x, Grid f, Grid c) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= f.nodes) return;
+  int fi = (int)(i % f.nn);
+  int fj = (int)((i / f.nn) % f.nn);
+  int fk = (DIM == 3) ? (int)(i / f.plane) : 0;
+  int lo[3] = {fi >> 1, fj >> 1, fk >> 1};
+  int hi[3] = {(fi + 1) >> 1, (fj + 1) >> 1, (fk + 1) >> 1};
+  double s = 0.0;
+  const int nz = (DIM == 3) ? 2 : 1;
+  for (int a = 0; a < nz; a++) {
+    int K = a ? hi[2] : lo[2];
+    if (a && hi[2] == lo[2]) continue;
+    double wk = (DIM == 3 && hi[2] != lo[2]) ? 0.5 : 1.0;
+    for (int bb = 0; bb < 2; bb++) {
+      int J = bb ? hi[1] : lo[1];
+      if (bb && hi[1] == lo[1]) continue;
+      double wj = wk * ((hi[1] != lo[1]) ? 0.5 : 1.0);
+      for (int cc = 0; cc < 2; cc++) {
+        int Ii = cc ? hi[0] : lo[0];
+        if (cc && hi[0] == lo[0]) continue;
+        double w = wj * ((hi[0] != lo[0]) ? 0.5 : 1.0);
+        s += w * ld(ec + (int64_t)K * c.plane + (int64_t)J * c.nn + Ii);
+      }
+    }
+  }
+  x[i] = (T)(ld(x + i) + s);
+}
+
+constexpr int kCoarseMax = 1024;   // nodes of the coarse grid
+constexpr int kCoarseLine = 64;    // nodes per direction
+
+// One block solves (M + alpha K) x = b exactly on a grid of at most 1024 nodes.
+template <int DIM, class T>
+__global__ void __launch_bounds__(1024)
+    k_coarse(const T* __restrict__ b, T* __restrict__ x, Grid g, double alpha) {
+  __shared__ double A[kCoarseMax], B[kCoarseMax];
+  __shared__ double V[kCoarseLine * kCoarseLine];
+  __shared__ double mu[kCoarseLine], kap[kCoarseLine], gam[kCoarseLine];
+  const int nn = g.nn, N = g.N;
+  const int n = (int)g.nodes;
+  const int t = threadIdx.x;
+  for (int q = t; q < nn * nn; q += blockDim.x) {
+    int j = q / nn, k = q % nn;
+    V[q] = cospi((double)(j * k % (2 * N)) / (double)N);
+  }
+  if (t < nn) {
+    double c = cospi((double)t / (double)N);
+    mu[t] = (g.h / 3.0) * (2.0 + c);
+    kap[t] = (2.0 / g.h) * (1.0 - c);
+    gam[t] = (t == 0 || t == N) ? (double)N : 0.5 * N;
+  }
+  for (int q = t; q < n; q += blockDim.x) A[q] = ld(b + q);
+  __syncthreads();
+  // forward transform along each axis: out[..k..] = sum_j V[j][k] in[..j..]
+  double* src = A;
+  double* dst = B;
+  for (int ax = 0; ax < DIM; ax++) {
+    int64_t stride = (ax == 0) ? 1 : (ax == 1 ? nn : (int64_t)nn * nn);
+    for (int q = t; q < n; q += blockDim.x) {
+      int k = (int)((q / stride) % nn);
+      int base = q - k * (int)stride;
+      double s = 0.0;
+      for (int j = 0; j < nn; j++) s += V[j * nn + k] * src[base + j * stride];
+      dst[q] = s;
+    }
+    __syncthreads();
+    double* tt = src;
+    src = dst;
+    dst = tt;
+  }
+  for (int q = t; q < n; q += blockDim.x) {
+    int k0 = q % nn, k1 = (q / nn) % nn, k2 = (DIM == 3) ? q / (nn * nn) : 0;
+    double lam, gg;
+    if (DIM == 3) {
+      double pm = mu[k0] * mu[k1] * mu[k2];
+      double sk = kap[k0] * mu[k1] * mu[k2] + mu[k0] * kap[k1] * mu[k2] + mu[k0] * mu[k1] * kap[k2];
+      lam = pm + alpha * sk;
+      gg = gam[k0] * gam[k1] * gam[k2];
+    } else {
+      double pm = mu[k0] * mu[k1];
+      double sk = kap[k0] * mu[k1] + mu[k0] * kap[k1];
+      lam = pm + alpha * sk;
+      gg = gam[k0] * gam[k1];
+    }
+    src[q] = src[q] / (lam * gg);
+  }
+  __syncthreads();
+  for (int ax = 0; ax < DIM; ax++) {
+    int64_t stride = (ax == 0) ? 1 : (ax == 1 ? nn : (int64_t)nn * nn);
+    for (int q = t; q < n; q += blockDim.x) {
+      int k = (int)((q / stride) % nn);
+      int base = q - k * (int)stride;
+      double s = 0.0;
+      for (int j = 0; j < nn; j++) s += V[k * nn + j] * src[base + j * stride];
+      dst[q] = s;
+    }
+    __syncthreads();
+    double* tt = src;
+    src = dst;
+    dst = tt;
+  }
+  for (int q = t; q < n; q += blockDim.x) x[q] = (T)src[q];
+}
+
+}  // namespace
+
+template <class T>
+hipError_t launch_restrict(const Grid& fine, const Grid& coarse, const T* r, T* bc,
+                           hipStream_t st) {
+  dim3 grid((unsigned)((coarse.nodes + 255) / 256)), block(256);
+  if (fine.dim == 2)
+    hipLaunchKernelGGL((k_restrict<2, T>), grid, block, 0, st, r, bc, fine, coarse);
+  else
+    hipLaunchKernelGGL((k_restrict<3, T>), grid, block, 0, st, r, bc, fine, coarse);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_prolong_add(const Grid& fine, const Grid& coarse, const T* ec, T* x,
+                              hipStream_t st) {
+  dim3 grid((unsigned)((fine.nodes + 255) / 256)), block(256);
+  if (fine.dim == 2)
+    hipLaunchKernelGGL((k_prolong_add<2, T>), grid, block, 0, st, ec, x, fine, coarse);
+  else
+    hipLaunchKernelGGL((k_prolong_add<3, T>), grid, block, 0, st, ec, x, fine, coarse);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_coarse_solve(const Grid& g, double alpha, const T* b, T* x, hipStream_t st) {
+  if (g.nodes > kCoarseMax || g.nn > kCoarseLine) return hipErrorInvalidValue;
+  if (g.dim == 2)
+    hipLaunchKernelGGL((k_coarse<2, T>), dim3(1), dim3(1024), 0, st, b, x, g, alpha);
+  else
+    hipLaunchKernelGGL((k_coarse<3, T>), dim3(1), dim3(1024), 0, st, b, x, g, alpha);
+  return hipGetLastError();
+}
+
+template hipError_t launch_restrict<double>(const Grid&, const Grid&, const double*, double*,
+                                            hipStream_t);
+template hipError_t launch_restrict<float>(const Grid&, const Grid&, const float*, float*,
+                                           hipStream_t);
+template hipError_t launch_prolong_add<double>(const Grid&, const Grid&, const double*, double*,
+                                               hipStream_t);
+template hipError_t launch_prolong_add<float>(const Grid&, const Grid&, const float*, float*,
+                                              hipStream_t);
+template hipError_t launch_coarse_solve<double>(const Grid&, double, const double*, double*,
+                                                hipStream_t);
+template hipError_t launch_coarse_solve<float>(const Grid&, double, const float*, float*,
+                                               hipStream_t);
+
+}  // namespace okd

@@ -1,0 +1,476 @@
+// Matrix-free Q1 node stencils of M and K on uniform grids, with the fused
+// epilogues used by Chebyshev-Jacobi iterations, multigrid residuals and
+// mass actions.
+//
+// The Q1 mass and stiffness matrices of (0,1)^d with Neumann ends are
+// Kronecker sums/products of the 1D matrices
+//   M1 = (h/6) tridiag(1, 4, 1)  (diagonal 2 at the two ends),
+//   K1 = (1/h) tridiag(-1, 2, -1) (diagonal 1 at the two ends),
+// M = M1 x M1 (x M1),  K = K1 x M1 (x M1) + M1 x K1 (x M1) (+ M1 x M1 x K1).
+// A block owns a contiguous chunk of nodes of an x-y plane and streams along
+// z: each plane chunk (with a one-row halo on each side) is staged in LDS, the
+// in-plane partial products P_M = (M1 x M1) s and P_K = (K1 x M1 + M1 x K1) s
+// are formed from LDS and kept in registers for three consecutive planes, and
+// the z-direction 1D stencil combines them.  Every node is read once from HBM
+// per plane pass; the halo rows come from L2 because neighbouring chunks run
+// on the same XCD (see block_remap).
+#include "ok_internal.h"
+
+#include <algorithm>
+
+namespace okd {
+
+Grid make_grid(int dim, int N) {
+  Grid g;
+  g.dim = dim;
+  g.N = N;
+  g.nn = N + 1;
+  g.plane = (int64_t)g.nn * g.nn;
+  g.nodes = (dim == 3) ? g.plane * g.nn : g.plane;
+  g.h = 1.0 / N;
+  return g;
+}
+
+StencilShape stencil_shape(const Grid& g) {
+  StencilShape s;
+  // Nodes per thread per plane: enough work per block on big planes, few
+  // idle threads on small ones.
+  s.items = g.plane >= 8192 ? 8 : (g.plane >= 2048 ? 4 : (g.plane >= 512 ? 2 : 1));
+  s.chunk = kThreads * s.items;
+  s.nchunks = (int)((g.plane + s.chunk - 1) / s.chunk);
+  if (g.dim == 2) {
+    s.zc = 1;
+    s.nzc = 1;
+  } else {
+    // Planes per block: aim at ~768 blocks, at least 4 planes per block.
+    int64_t zc = ((int64_t)g.nn * s.nchunks + 767) / 768;
+    zc = std::max<int64_t>(4, std::min<int64_t>(zc, 32));
+    s.zc = (int)std::min<int64_t>(zc, g.nn);
+    s.nzc = (g.nn + s.zc - 1) / s.zc;
+  }
+  s.blocks = s.nchunks * s.nzc;
+  return s;
+}
+
+Op make_op(const Grid& g, double cm, double ck) {
+  // Interior diagonal: M1 -> 2h/3, K1 -> 2/h.
+  double mi = 2.0 * g.h / 3.0, ki = 2.0 / g.h;
+  double dm = 1.0, dk = 0.0;
+  for (int d = 0; d < g.dim; d++) dm *= mi;
+  dk = g.dim * ki;
+  for (int d = 0; d < g.dim - 1; d++) dk *= mi;
+  Op o;
+  o.cm = cm;
+  o.ck = ck;
+  o.dinv_int = 1.0 / (cm * dm + ck * dk);
+  return o;
+}
+
+// Hardware places block b on XCD b % 8.  Renumber blocks so that each XCD
+// receives a contiguous range of logical blocks (neighbouring chunks), which
+// keeps the halo rows of a chunk in that XCD's L2.
+__device__ __forceinline__ int block_remap(int b, int nb) {
+  int q = nb / 8, r = nb % 8;
+  int x = b % 8, t = b / 8;
+  int base = (x < r) ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+  return base + t;
+}
+
+// 1D stencil patterns of node i on N elements (constants h/6, 1/h applied
+// later).  M pattern: [wl, 2(wl+wr), wr];  K pattern: [-wl, wl+wr, -wr].
+// SCALED multiplies the weight of each neighbour j by 2 when j is an end
+// node, i.e. applies the stencil to W^-1 s with W the trapezoid weights.
+template <bool SCALED>
+__device__ __forceinline__ void pattern(int i, int N, double& a0, double& a1, double& a2,
+                                        double& b0, double& b1, double& b2) {
+  double wl = (i > 0) ? 1.0 : 0.0, wr = (i < N) ? 1.0 : 0.0;
+  double sl = 1.0, sc = 1.0, sr = 1.0;
+  if (SCALED) {
+    sl = (i - 1 == 0) ? 2.0 : 1.0;
+    sc = (i == 0 || i == N) ? 2.0 : 1.0;
+    sr = (i + 1 == N) ? 2.0 : 1.0;
+  }
+  a0 = wl * sl;
+  a1 = 2.0 * (wl + wr) * sc;
+  a2 = wr * sr;
+  b0 = -wl * sl;
+  b1 = (wl + wr) * sc;
+  b2 = -wr * sr;
+}
+
+__device__ __forceinline__ double to_d(double v) { return v; }
+__device__ __forceinline__ double to_d(float v) { return (double)v; }
+
+// ---------------------------------------------------------------------------
+// The streaming kernel.  Epi is called once per owned node with
+// (index, #boundary coordinates, (M s)_i, (K s)_i, s_i).
+// ---------------------------------------------------------------------------
+template <int DIM, int P, bool SCALED, class TS, class Epi>
+__global__ void __launch_bounds__(kThreads)
+    k_stencil(const TS* __restrict__ s, Grid g, StencilShape sh, Epi epi) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x;
+  const int b = block_remap(blockIdx.x, gridDim.x);
+  const int chunk = b % sh.nchunks;
+  const int zch = b / sh.nchunks;
+  const int nn = g.nn, N = g.N;
+  const int64_t plane = g.plane;
+  const int halo = nn + 1;
+  const int ldsn = sh.chunk + 2 * halo;
+  const int64_t s0 = (int64_t)chunk * sh.chunk;
+
+  int ii[P], jj[P];
+  bool valid[P];
+#pragma unroll
+  for (int p = 0; p < P; p++) {
+    int64_t q = s0 + tid + kThreads * p;
+    valid[p] = q < plane;
+    int j = (int)(q / nn);
+    jj[p] = j;
+    ii[p] = (int)(q - (int64_t)j * nn);
+  }
+
+  const double h = g.h;
+  auto plane_partials = [&](double* pm, double* pk, double* cen) {
+#pragma unroll
+    for (int p = 0; p < P; p++) {
+      const int L = tid + kThreads * p + halo;
+      double ax0, ax1, ax2, bx0, bx1, bx2, ay0, ay1, ay2, by0, by1, by2;
+      pattern<SCALED>(ii[p], N, ax0, ax1, ax2, bx0, bx1, bx2);
+      pattern<SCALED>(jj[p], N, ay0, ay1, ay2, by0, by1, by2);
+      double mr[3], kr[3];
+#pragma unroll
+      for (int r = 0; r < 3; r++) {
+        const int base = L + (r - 1) * nn;
+        double va = lds[base - 1], vb = lds[base], vc = lds[base + 1];
+        mr[r] = ax0 * va + ax1 * vb + ax2 * vc;
+        kr[r] = bx0 * va + bx1 * vb + bx2 * vc;
+      }
+      pm[p] = ay0 * mr[0] + ay1 * mr[1] + ay2 * mr[2];
+      pk[p] = ay0 * kr[0] + ay1 * kr[1] + ay2 * kr[2] + by0 * mr[0] + by1 * mr[1] + by2 * mr[2];
+      cen[p] = lds[L];
+    }
+  };
+  auto fill = [&](int64_t zoff) {
+    for (int t = tid; t < ldsn; t += kThreads) {
+      int64_t gq = s0 - halo + t;
+      lds[t] = (gq >= 0 && gq < plane) ? to_d(s[zoff + gq]) : 0.0;
+    }
+  };
+
+  if (DIM == 2) {
+    fill(0);
+    __syncthreads();
+    double pm[P], pk[P], cen[P];
+    plane_partials(pm, pk, cen);
+    const double cmass = h * h / 36.0, cstiff = 1.0 / 6.0;
+#pragma unroll
+    for (int p = 0; p < P; p++) {
+      if (!valid[p]) continue;
+      int nb = (ii[p] == 0 || ii[p] == N) + (jj[p] == 0 || jj[p] == N);
+      int64_t idx = s0 + tid + kThreads * p;
+      epi(idx, nb, cmass * pm[p], cstiff * pk[p], cen[p]);
+    }
+    return;
+  }
+
+  // 3D: stream planes z0-1 .. z1, output planes z0 .. z1-1.
+  const int z0 = zch * sh.zc;
+  const int z1 = min(z0 + sh.zc, nn);
+  double pma[P], pmb[P], pka[P], pkb[P], cb[P];
+#pragma unroll
+  for (int p = 0; p < P; p++) pma[p] = pmb[p] = pka[p] = pkb[p] = cb[p] = 0.0;
+  const double cmass = h * h * h / 216.0, cstiff = h / 36.0;
+  for (int pz = z0 - 1; pz <= z1; pz++) {
+    double pmn[P], pkn[P], cn[P];
+    const bool inside = (pz >= 0 && pz <= N);
+    __syncthreads();
+    if (inside) fill((int64_t)pz * plane);
+    __syncthreads();
+    if (inside) {
+      plane_partials(pmn, pkn, cn);
+    } else {
+#pragma unroll
+      for (int p = 0; p < P; p++) pmn[p] = pkn[p] = cn[p] = 0.0;
+    }
+    const int o = pz - 1;  // output plane
+    if (o >= z0) {
+      double az0, az1, az2, bz0, bz1, bz2;
+      pattern<SCALED>(o, N, az0, az1, az2, bz0, bz1, bz2);
+      const int nbz = (o == 0 || o == N);
+#pragma unroll
+      for (int p = 0; p < P; p++) {
+        if (!valid[p]) continue;
+        double ms = cmass * (az0 * pma[p] + az1 * pmb[p] + az2 * pmn[p]);
+        double ks = cstiff * (az0 * pka[p] + az1 * pkb[p] + az2 * pkn[p] + bz0 * pma[p] +
+                              bz1 * pmb[p] + bz2 * pmn[p]);
+        int nb = (ii[p] == 0 || ii[p] == N) + (jj[p] == 0 || jj[p] == N) + nbz;
+        int64_t idx = (int64_t)o * plane + s0 + tid + kThreads * p;
+        epi(idx, nb, ms, ks, cb[p]);
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < P; p++) {
+      pma[p] = pmb[p];
+      pmb[p] = pmn[p];
+      pka[p] = pkb[p];
+      pkb[p] = pkn[p];
+      cb[p] = cn[p];
+    }
+  }
+}
+
+template <bool SCALED, class TS, class Epi>
+static hipError_t run_stencil(const Grid& g, const TS* s, const Epi& e, hipStream_t st) {
+  StencilShape sh = stencil_shape(g);
+  size_t lds = (size_t)(sh.chunk + 2 * (g.nn + 1)) * sizeof(double);
+  dim3 grid(sh.blocks), block(kThreads);
+#define OKD_LAUNCH(D, PP)                                                                   \
+  hipLaunchKernelGGL((k_stencil<D, PP, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e)
+  if (g.dim == 2) {
+    switch (sh.items) {
+      case 8: OKD_LAUNCH(2, 8); break;
+      case 4: OKD_LAUNCH(2, 4); break;
+      case 2: OKD_LAUNCH(2, 2); break;
+      default: OKD_LAUNCH(2, 1); break;
+    }
+  } else {
+    switch (sh.items) {
+      case 8: OKD_LAUNCH(3, 8); break;
+      case 4: OKD_LAUNCH(3, 4); break;
+      case 2: OKD_LAUNCH(3, 2); break;
+      default: OKD_LAUNCH(3, 1); break;
+    }
+  }
+#undef OKD_LAUNCH
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Epilogues
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double dinv_at(double dinv_int, int nb) {
+  return dinv_int * (double)(1 << nb);
+}
+
+// out = add + a*(M s) + b*(K s)
+template <class TA, class TO>
+struct EpiAxpy {
+  const TA* add;
+  double a, b;
+  TO* out;
+  __device__ void operator()(int64_t i, int, double ms, double ks, double) const {
+    double v = a * ms + b * ks;
+    if (add) v += to_d(add[i]);
+    out[i] = (TO)v;
+  }
+};
+
+// First Chebyshev iteration from x0 = 0; the stencil input is b and is
+// applied with SCALED patterns, so (cm M + ck K) W^-1 b is available and
+// A d0 = (dinv_int/theta) (cm M + ck K) W^-1 b.
+template <class T, class TX, bool LAST>
+struct EpiChebFirst {
+  Op A;
+  double inv_theta, c1, c2, out_scale;
+  TX* x;
+  T* r;
+  T* d;
+  __device__ void operator()(int64_t i, int nb, double ms, double ks, double bi) const {
+    double dv = dinv_at(A.dinv_int, nb);
+    double ad0 = A.dinv_int * inv_theta * (A.cm * ms + A.ck * ks);
+    double d0 = dv * bi * inv_theta;
+    double r1 = bi - ad0;
+    double d1 = c1 * d0 + c2 * dv * r1;
+    if (LAST) {
+      x[i] = (TX)(out_scale * (d0 + d1));
+    } else {
+      x[i] = (TX)d0;
+      r[i] = (T)r1;
+      d[i] = (T)d1;
+    }
+  }
+};
+
+// Iteration k: stencil input d_k.  x_{k+1} = x_k + d_k, r_{k+1} = r_k - A d_k,
+// d_{k+1} = c1 d_k + c2 D^-1 r_{k+1}.  LAST also adds the final step:
+// x_{k+2} = x_{k+1} + d_{k+1}, and writes only x.
+template <class T, class TX, bool LAST>
+struct EpiChebStep {
+  Op A;
+  double c1, c2, out_scale;
+  const TX* xin;
+  TX* x;
+  T* r;
+  T* dn;
+  __device__ void operator()(int64_t i, int nb, double ms, double ks, double dk) const {
+    double dv = dinv_at(A.dinv_int, nb);
+    double xv = to_d(xin[i]) + dk;
+    double rv = to_d(r[i]) - (A.cm * ms + A.ck * ks);
+    double d1 = c1 * dk + c2 * dv * rv;
+    if (LAST) {
+      x[i] = (TX)(out_scale * (xv + d1));
+    } else {
+      x[i] = (TX)xv;
+      r[i] = (T)rv;
+      dn[i] = (T)d1;
+    }
+  }
+};
+
+// Start from a given x (stencil input x): r0 = b - A x, d0 = D^-1 r0 / theta.
+template <class T>
+struct EpiChebStart {
+  Op A;
+  double inv_theta;
+  const T* b;
+  T* r;
+  T* d;
+  __device__ void operator()(int64_t i, int nb, double ms, double ks, double) const {
+    double r0 = to_d(b[i]) - (A.cm * ms + A.ck * ks);
+    r[i] = (T)r0;
+    d[i] = (T)(dinv_at(A.dinv_int, nb) * r0 * inv_theta);
+  }
+};
+
+// One Chebyshev iteration from x0 = 0: x = D^-1 b / theta (pointwise).
+template <class T, class TX>
+struct EpiChebOne {
+  Op A;
+  double inv_theta, out_scale;
+  TX* x;
+  __device__ void operator()(int64_t i, int nb, double, double, double bi) const {
+    x[i] = (TX)(out_scale * dinv_at(A.dinv_int, nb) * bi * inv_theta);
+  }
+};
+
+// r = b - A x
+template <class T>
+struct EpiResid {
+  Op A;
+  const T* b;
+  T* r;
+  __device__ void operator()(int64_t i, int, double ms, double ks, double) const {
+    r[i] = (T)(to_d(b[i]) - (A.cm * ms + A.ck * ks));
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <class TI, class TO>
+hipError_t launch_mass(const Grid& g, const TI* s, TO* out, double scale, hipStream_t st) {
+  EpiAxpy<TO, TO> e{nullptr, scale, 0.0, out};
+  return run_stencil<false>(g, s, e, st);
+}
+
+template <class TS, class TA, class TO>
+hipError_t launch_stencil_axpy(const Grid& g, const TS* s, const TA* add, double a, double b,
+                               TO* out, hipStream_t st) {
+  EpiAxpy<TA, TO> e{add, a, b, out};
+  return run_stencil<false>(g, s, e, st);
+}
+
+template <class T>
+__global__ void k_add_inplace(T* x, const T* d, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) x[i] = (T)(to_d(x[i]) + to_d(d[i]));
+}
+
+template <class TB, class T>
+hipError_t launch_cheb_one(const Grid& g, const Op& A, double inv_theta, double out_scale,
+                           const TB* b, T* x, hipStream_t st) {
+  EpiChebOne<T, T> e{A, inv_theta, out_scale, x};
+  return run_stencil<true>(g, b, e, st);
+}
+
+template <class TB, class T>
+hipError_t launch_cheb_first(const Grid& g, const Op& A, double inv_theta, double c1, double c2,
+                             double out_scale, bool last, const TB* b, T* x, T* r, T* d,
+                             hipStream_t st) {
+  if (last) {
+    EpiChebFirst<T, T, true> e{A, inv_theta, c1, c2, out_scale, x, r, d};
+    return run_stencil<true>(g, b, e, st);
+  }
+  EpiChebFirst<T, T, false> e{A, inv_theta, c1, c2, 1.0, x, r, d};
+  return run_stencil<true>(g, b, e, st);
+}
+
+template <class T>
+hipError_t launch_cheb_step(const Grid& g, const Op& A, double c1, double c2, double out_scale,
+                            bool last, T* x, T* r, const T* din, T* dout, hipStream_t st) {
+  if (last) {
+    EpiChebStep<T, T, true> e{A, c1, c2, out_scale, x, x, r, dout};
+    return run_stencil<false>(g, din, e, st);
+  }
+  EpiChebStep<T, T, false> e{A, c1, c2, 1.0, x, x, r, dout};
+  return run_stencil<false>(g, din, e, st);
+}
+
+template <class T>
+hipError_t launch_cheb_start(const Grid& g, const Op& A, double inv_theta, const T* b,
+                             const T* x, T* r, T* d, hipStream_t st) {
+  EpiChebStart<T> e{A, inv_theta, b, r, d};
+  return run_stencil<false>(g, x, e, st);
+}
+
+template <class T>
+hipError_t launch_add_inplace(T* x, const T* d, int64_t n, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_add_inplace<T>, dim3((unsigned)blocks), dim3(256), 0, st, x, d, n);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_resid(const Grid& g, const Op& A, const T* b, const T* x, T* r,
+                        hipStream_t st) {
+  EpiResid<T> e{A, b, r};
+  return run_stencil<false>(g, x, e, st);
+}
+
+// Explicit instantiations.
+template hipError_t launch_mass<double, double>(const Grid&, const double*, double*, double,
+                                                hipStream_t);
+template hipError_t launch_mass<float, float>(const Grid&, const float*, float*, double,
+                                              hipStream_t);
+template hipError_t launch_stencil_axpy<double, double, double>(const Grid&, const double*,
+                                                                const double*, double, double,
+                                                                double*, hipStream_t);
+template hipError_t launch_stencil_axpy<float, double, float>(const Grid&, const float*,
+                                                              const double*, double, double,
+                                                              float*, hipStream_t);
+template hipError_t launch_stencil_axpy<double, double, float>(const Grid&, const double*,
+                                                               const double*, double, double,
+                                                               float*, hipStream_t);
+template hipError_t launch_stencil_axpy<float, double, double>(const Grid&, const float*,
+                                                               const double*, double, double,
+                                                               double*, hipStream_t);
+template hipError_t launch_stencil_axpy<float, float, float>(const Grid&, const float*,
+                                                             const float*, double, double,
+                                                             float*, hipStream_t);
+#define OKD_CHEB_TB(TB, T)                                                                    \
+  template hipError_t launch_cheb_one<TB, T>(const Grid&, const Op&, double, double, const TB*,  \
+                                             T*, hipStream_t);                                   \
+  template hipError_t launch_cheb_first<TB, T>(const Grid&, const Op&, double, double, double,   \
+                                               double, bool, const TB*, T*, T*, T*, hipStream_t);
+OKD_CHEB_TB(double, double)
+OKD_CHEB_TB(float, float)
+OKD_CHEB_TB(double, float)
+#undef OKD_CHEB_TB
+#define OKD_CHEB_T(T)                                                                           \
+  template hipError_t launch_cheb_step<T>(const Grid&, const Op&, double, double, double, bool,  \
+                                          T*, T*, const T*, T*, hipStream_t);                    \
+  template hipError_t launch_cheb_start<T>(const Grid&, const Op&, double, const T*, const T*,   \
+                                           T*, T*, hipStream_t);                                 \
+  template hipError_t launch_add_inplace<T>(T*, const T*, int64_t, hipStream_t);
+OKD_CHEB_T(double)
+OKD_CHEB_T(float)
+#undef OKD_CHEB_T
+template hipError_t launch_resid<double>(const Grid&, const Op&, const double*, const double*,
+                                         double*, hipStream_t);
+template hipError_t launch_resid<float>(const Grid&, const Op&, const float*, const float*,
+                                        float*, hipStream_t);
+
+}  // namespace okd

@@ -1,0 +1,238 @@
+"""ctypes binding of libok.so (argument marshalling only).
+
+Every operation runs in the library's HIP kernels; PyTorch is used only to
+allocate device memory and to supply the current HIP stream.  The binding
+raises if the library has not been built -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(PKG, "libok.so")
+
+OK_FP64, OK_MIXED = 0, 1
+OK_K_NONE, OK_K_CHEB_MASS, OK_K_MG_SMOOTH, OK_K_ELEMENT, OK_K_STENCIL_ANY, OK_K_KRYLOV = range(6)
+HIST = 256
+
+STATUS = {0: "OK_SUCCESS", -1: "OK_E_INVALID", -2: "OK_E_WORKSPACE", -3: "OK_E_HIP",
+          -4: "OK_E_GMRES_MAXIT", -5: "OK_E_NEWTON_MAXIT", -6: "OK_E_NONFINITE"}
+
+
+class Params(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32),
+                ("eps", C.c_double), ("sigma", C.c_double), ("m", C.c_double),
+                ("dt", C.c_double), ("theta", C.c_double),
+                ("precision", C.c_int32),
+                ("gmres_restart", C.c_int32), ("gmres_max_restarts", C.c_int32),
+                ("gmres_rtol", C.c_double), ("newton_atol", C.c_double),
+                ("newton_max_it", C.c_int32), ("cheb_A_its", C.c_int32),
+                ("schur_richardson", C.c_int32), ("mg_levels", C.c_int32),
+                ("mg_pre", C.c_int32), ("mg_post", C.c_int32), ("mg_cycles", C.c_int32)]
+
+
+class NewtonInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("fgmres_its", C.c_int32), ("restarts", C.c_int32),
+                ("fnorm", C.c_double), ("lin_res", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("steps_done", C.c_int32), ("newton_its", C.c_int32),
+                ("fgmres_its_total", C.c_int32), ("newton_per_step", C.c_int32 * HIST),
+                ("fgmres_its", C.c_int32 * HIST), ("fnorm", C.c_double * HIST),
+                ("fnorm_count", C.c_int32), ("step_ms", C.c_double * HIST)]
+
+    def its(self):
+        return [self.fgmres_its[i] for i in range(min(self.newton_its, HIST))]
+
+    def per_step(self):
+        return [self.newton_per_step[i] for i in range(min(self.steps_done, HIST))]
+
+    def fnorms(self):
+        return [self.fnorm[i] for i in range(min(self.fnorm_count, HIST))]
+
+    def ms(self):
+        return [self.step_ms[i] for i in range(min(self.steps_done, HIST))]
+
+
+class OkError(RuntimeError):
+    def __init__(self, status, msg=""):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libok.so; raises if it is missing (build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise OSError(f"{LIBPATH} is not built; run __graft_entry__.build() first")
+    lib = C.CDLL(LIBPATH)
+    vp, i32, d = C.c_void_p, C.c_int32, C.c_double
+    P = C.POINTER
+    lib.ok_default_params.argtypes = [P(Params)]
+    lib.ok_workspace_bytes.argtypes = [P(Params), P(C.c_size_t)]
+    lib.ok_assemble_mesh.argtypes = [P(Params), vp, C.c_size_t, vp, P(vp)]
+    lib.ok_residual.argtypes = [vp, vp, vp, vp, vp, vp, P(d), vp]
+    lib.ok_jacobian_apply.argtypes = [vp, vp, vp, vp, vp]
+    lib.ok_precond_apply.argtypes = [vp, vp, vp, vp, vp]
+    lib.ok_cheb_mass.argtypes = [vp, vp, vp, vp]
+    lib.ok_mg_apply.argtypes = [vp, vp, vp, i32, vp]
+    lib.ok_fgmres.argtypes = [vp, vp, vp, vp, P(i32), vp]
+    lib.ok_newton_step.argtypes = [vp, vp, vp, vp, vp, P(NewtonInfo), vp]
+    lib.ok_timestep.argtypes = [vp, vp, vp, i32, P(Stats), vp]
+    lib.ok_profile_enable.argtypes = [vp, i32]
+    lib.ok_profile_read.argtypes = [vp, P(C.c_int64), P(d), P(d)]
+    lib.ok_destroy.argtypes = [vp]
+    lib.ok_error_string.argtypes = [C.c_int]
+    lib.ok_error_string.restype = C.c_char_p
+    lib.ok_last_error.argtypes = [vp]
+    lib.ok_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    load().ok_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def workspace_bytes(p: Params) -> int:
+    b = C.c_size_t()
+    st = load().ok_workspace_bytes(C.byref(p), C.byref(b))
+    if st:
+        raise OkError(st, "ok_workspace_bytes")
+    return b.value
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "need a contiguous cuda float64 tensor"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Problem:
+    """One assembled problem (ok_assemble_mesh) with its torch-owned workspace."""
+
+    def __init__(self, params: Params, device="cuda", stream=None):
+        import torch
+        self.lib = load()
+        self.params = params
+        self.device = torch.device(device)
+        self.stream = stream
+        self.ws_bytes = workspace_bytes(params)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self.ctx = C.c_void_p()
+        st = self.lib.ok_assemble_mesh(C.byref(params), C.c_void_p(base + off),
+                                       C.c_size_t(self.ws_bytes), _stream(stream),
+                                       C.byref(self.ctx))
+        if st:
+            raise OkError(st, "ok_assemble_mesh")
+        self.nodes = (params.n + 1) ** params.dim
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, st, what):
+        if st:
+            msg = self.lib.ok_last_error(self.ctx).decode()
+            raise OkError(st, f"{what}: {msg}")
+
+    def field(self, k=1):
+        import torch
+        return torch.zeros(k * self.nodes, dtype=torch.float64, device=self.device)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.ok_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- ABI calls -----------------------------------------------------------
+    def residual(self, u, w, un, wn=None, F=None):
+        nrm = C.c_double()
+        st = self.lib.ok_residual(self.ctx, _ptr(u), _ptr(w), _ptr(un), _ptr(wn), _ptr(F),
+                                  C.byref(nrm), _stream(self.stream))
+        self._check(st, "ok_residual")
+        return nrm.value
+
+    def jacobian_apply(self, u, x, y=None):
+        y = self.field(2) if y is None else y
+        self._check(self.lib.ok_jacobian_apply(self.ctx, _ptr(u), _ptr(x), _ptr(y),
+                                               _stream(self.stream)), "ok_jacobian_apply")
+        return y
+
+    def precond_apply(self, u, r, z=None):
+        z = self.field(2) if z is None else z
+        self._check(self.lib.ok_precond_apply(self.ctx, _ptr(u), _ptr(r), _ptr(z),
+                                              _stream(self.stream)), "ok_precond_apply")
+        return z
+
+    def cheb_mass(self, r, x=None):
+        x = self.field(1) if x is None else x
+        self._check(self.lib.ok_cheb_mass(self.ctx, _ptr(r), _ptr(x), _stream(self.stream)),
+                    "ok_cheb_mass")
+        return x
+
+    def mg_apply(self, b, x=None, cycles=1):
+        x = self.field(1) if x is None else x
+        self._check(self.lib.ok_mg_apply(self.ctx, _ptr(b), _ptr(x), cycles,
+                                         _stream(self.stream)), "ok_mg_apply")
+        return x
+
+    def fgmres(self, u, b, x=None):
+        x = self.field(2) if x is None else x
+        its = C.c_int32()
+        st = self.lib.ok_fgmres(self.ctx, _ptr(u), _ptr(b), _ptr(x), C.byref(its),
+                                _stream(self.stream))
+        return x, its.value, st
+
+    def newton_step(self, u, w, un, wn=None):
+        info = NewtonInfo()
+        st = self.lib.ok_newton_step(self.ctx, _ptr(u), _ptr(w), _ptr(un), _ptr(wn),
+                                     C.byref(info), _stream(self.stream))
+        return info, st
+
+    def timestep(self, u, w, nsteps=1, check=True):
+        stats = Stats()
+        st = self.lib.ok_timestep(self.ctx, _ptr(u), _ptr(w), nsteps, C.byref(stats),
+                                  _stream(self.stream))
+        if check:
+            self._check(st, "ok_timestep")
+        return stats
+
+    def profile_enable(self, kernel_class):
+        self._check(self.lib.ok_profile_enable(self.ctx, kernel_class), "ok_profile_enable")
+
+    def profile_read(self):
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        self._check(self.lib.ok_profile_read(self.ctx, C.byref(n), C.byref(ms), C.byref(by)),
+                    "ok_profile_read")
+        return n.value, ms.value, by.value
+
+
+def error_string(status: int) -> str:
+    return load().ok_error_string(status).decode()

@@ -1,0 +1,94 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point the
+header declares, and rejects bad arguments before touching the GPU."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ok.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ok_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1603_04570_amd import ok
+    if not os.path.exists(ok.LIBPATH):
+        from paper_1603_04570_amd.build import build
+        build()
+    return ok.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_1603_04570_amd import ok
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    out = subprocess.run(["nm", "-D", "--defined-only", ok.LIBPATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (ok_\w+)", out))
+    missing = [s for s in syms if s not in exported]
+    assert not missing, missing
+    for s in syms:
+        assert hasattr(lib, s)
+
+
+def test_default_params_and_workspace(lib):
+    from paper_1603_04570_amd import ok
+    p = ok.default_params()
+    assert (p.dim, p.n, p.gmres_restart, p.cheb_A_its, p.mg_pre, p.mg_post) == (3, 128, 30, 10, 2, 2)
+    assert p.eps == 0.01 and p.sigma == 1000.0 and p.dt == 2e-5 and p.theta == 1.0
+    b = ok.workspace_bytes(p)
+    n = 129 ** 3
+    # V (31 x 2n) and Z (30 x 2n) dominate: 61*2n doubles
+    assert 61 * 2 * n * 8 <= b <= 61 * 2 * n * 8 + 40 * n * 8
+    pm = ok.default_params(precision=ok.OK_MIXED)
+    assert ok.workspace_bytes(pm) < b
+
+
+@pytest.mark.parametrize("field,value", [("dim", 4), ("n", 1), ("eps", 0.0), ("dt", -1.0),
+                                         ("theta", 0.0), ("theta", 1.5), ("m", 1.0),
+                                         ("precision", 7), ("gmres_restart", 0),
+                                         ("gmres_restart", 65), ("cheb_A_its", 0),
+                                         ("mg_pre", 0), ("mg_levels", 9), ("n", 100)])
+def test_invalid_params_rejected(lib, field, value):
+    from paper_1603_04570_amd import ok
+    p = ok.default_params(**{field: value})
+    b = C.c_size_t()
+    assert lib.ok_workspace_bytes(C.byref(p), C.byref(b)) == -1
+    ctx = C.c_void_p()
+    assert lib.ok_assemble_mesh(C.byref(p), C.c_void_p(256), C.c_size_t(1 << 40), None,
+                                C.byref(ctx)) == -1
+    assert not ctx.value
+
+
+def test_workspace_errors(lib):
+    from paper_1603_04570_amd import ok
+    p = ok.default_params(dim=2, n=64)
+    need = ok.workspace_bytes(p)
+    ctx = C.c_void_p()
+    # null, misaligned, and one byte too small: rejected without any device access
+    assert lib.ok_assemble_mesh(C.byref(p), None, C.c_size_t(need), None, C.byref(ctx)) == -2
+    assert lib.ok_assemble_mesh(C.byref(p), C.c_void_p(4096 + 8), C.c_size_t(need), None,
+                                C.byref(ctx)) == -2
+    assert lib.ok_assemble_mesh(C.byref(p), C.c_void_p(4096), C.c_size_t(need - 1), None,
+                                C.byref(ctx)) == -2
+
+
+def test_error_strings(lib):
+    from paper_1603_04570_amd import ok
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert ok.error_string(s)
+    assert ok.error_string(-99) == "unknown status"
+
+
+def test_null_context_calls(lib):
+    assert lib.ok_destroy(None) == -1
+    assert lib.ok_jacobian_apply(None, None, None, None, None) == -1
+    assert lib.ok_timestep(None, None, None, 1, None, None) == -1

@@ -1,0 +1,159 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
+the same seeded inputs.
+
+Bars (elementwise, max |gpu - oracle| / max |oracle|):
+  stencil and element operators (J x, F):     1e-13   (a few FP64 roundings)
+  Chebyshev, multigrid, preconditioner:       1e-12   (tens of roundings)
+  FGMRES solve, Newton step, timestep:        1e-10   relative per field, with
+                                                      identical iteration counts
+"""
+import numpy as np
+import pytest
+
+from oracle.okref import Oracle
+from paper_1603_04570_amd.inputs import noise_state, uniform01
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relmax(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def relnorm(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+CFG1 = dict(eps=0.02, sigma=100.0, m=0.0, dt=1e-4)
+CFG2 = dict(eps=0.01, sigma=1000.0, m=0.1, dt=2e-5)
+
+# (dim, n): several plane chunks, ragged tails, and every multigrid depth
+SIZES = [(2, 8), (2, 16), (2, 64), (2, 128), (3, 8), (3, 16), (3, 32)]
+
+
+def make(dim, n, cfg, **kw):
+    from paper_1603_04570_amd import ok
+    o = Oracle(dim, n, **cfg, **kw)
+    p = ok.default_params(dim=dim, n=n, **cfg, **kw)
+    return o, ok.Problem(p)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("dim,n", SIZES)
+def test_jacobian_apply(dim, n):
+    say("jacobian", dim, n)
+    o, P = make(dim, n, CFG2)
+    u, _ = noise_state(dim, n, 0.1, 2)
+    x = uniform01(31, 2 * o.nodes) - 0.5
+    y = host(P.jacobian_apply(dev(u), dev(x)))
+    assert relmax(y, o.jacobian_apply(u, x)) < 1e-13
+
+
+@pytest.mark.parametrize("dim,n", SIZES)
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_residual(dim, n, theta):
+    say("residual", dim, n, theta)
+    o, P = make(dim, n, CFG2, theta=theta)
+    u, _ = noise_state(dim, n, 0.1, 2)
+    w = 0.3 * (uniform01(7, o.nodes) - 0.5)
+    un = u + 0.01 * (uniform01(8, o.nodes) - 0.5)
+    wn = w + 0.01 * (uniform01(9, o.nodes) - 0.5)
+    F_o, nrm_o = o.residual(u, w, un, wn)
+    F = P.field(2)
+    nrm = P.residual(dev(u), dev(w), dev(un), dev(wn), F)
+    assert relmax(host(F), F_o) < 1e-13
+    assert abs(nrm - nrm_o) <= 1e-13 * nrm_o
+
+
+@pytest.mark.parametrize("dim,n", SIZES)
+def test_chebyshev_mass(dim, n):
+    say("cheb", dim, n)
+    o, P = make(dim, n, CFG2)
+    r = uniform01(41, o.nodes) - 0.5
+    x = host(P.cheb_mass(dev(r)))
+    assert relmax(x, o.cheb_mass(r)) < 1e-12
+
+
+@pytest.mark.parametrize("dim,n", SIZES)
+@pytest.mark.parametrize("cycles", [1, 2])
+def test_multigrid(dim, n, cycles):
+    say("mg", dim, n, cycles)
+    o, P = make(dim, n, CFG2)
+    b = uniform01(51, o.nodes) - 0.5
+    x = host(P.mg_apply(dev(b), cycles=cycles))
+    assert relmax(x, o.mg(b, cycles)) < 1e-12
+
+
+@pytest.mark.parametrize("dim,n", SIZES)
+def test_preconditioner(dim, n):
+    say("precond", dim, n)
+    o, P = make(dim, n, CFG2)
+    u, _ = noise_state(dim, n, 0.1, 2)
+    r = uniform01(61, 2 * o.nodes) - 0.5
+    z = host(P.precond_apply(dev(u), dev(r)))
+    assert relmax(z, o.precond_apply(u, r)) < 1e-12
+
+
+@pytest.mark.parametrize("dim,n", [(2, 16), (2, 64), (3, 16)])
+def test_fgmres(dim, n):
+    say("fgmres", dim, n)
+    o, P = make(dim, n, CFG1)
+    u, _ = noise_state(dim, n, 0.0, 1)
+    b = uniform01(71, 2 * o.nodes) - 0.5
+    x_o, its_o, st_o = o.fgmres(u, b)
+    x, its, st = P.fgmres(dev(u), dev(b))
+    assert st == 0 and st_o == 0 and its == its_o
+    assert relnorm(host(x), x_o) < 1e-10
+
+
+def test_fgmres_restarts():
+    """A short restart length forces restarts; counts and solution still agree."""
+    dim, n = 2, 32
+    o, P = make(dim, n, CFG1, gmres_restart=3)
+    u, _ = noise_state(dim, n, 0.0, 1)
+    b = uniform01(72, 2 * o.nodes) - 0.5
+    x_o, its_o, st_o = o.fgmres(u, b)
+    x, its, st = P.fgmres(dev(u), dev(b))
+    assert st == st_o == 0 and its == its_o and its > 3
+    assert relnorm(host(x), x_o) < 1e-10
+
+
+@pytest.mark.parametrize("dim,n,cfg,seed", [(2, 64, CFG1, 1), (2, 32, CFG2, 3), (3, 16, CFG2, 2),
+                                            (3, 32, CFG2, 2)])
+def test_timestep(dim, n, cfg, seed):
+    say("timestep", dim, n)
+    o, P = make(dim, n, cfg)
+    u0, w0 = noise_state(dim, n, cfg["m"], seed)
+    u_o, w_o, info, st_o = o.timestep(u0, w0, 1)
+    u, w = dev(u0), dev(w0)
+    stats = P.timestep(u, w, 1)
+    assert st_o == 0 and stats.status == 0
+    assert stats.its() == info.its()
+    assert relnorm(host(u), u_o) < 1e-10
+    assert relnorm(host(w), w_o) < 1e-10
+
+
+def test_newton_step_matches():
+    dim, n = 2, 32
+    o, P = make(dim, n, CFG1)
+    u0, w0 = noise_state(dim, n, 0.0, 1)
+    u1, w1, fn_o, its_o, st_o = o.newton_step(u0, w0, u0)
+    u, w, un = dev(u0), dev(w0), dev(u0)
+    info, st = P.newton_step(u, w, un)
+    assert st == 0 and st_o == 0 and info.fgmres_its == its_o
+    assert abs(info.fnorm - fn_o) <= 1e-13 * fn_o
+    assert relnorm(host(u), u1) < 1e-10 and relnorm(host(w), w1) < 1e-10
