@@ -33,17 +33,25 @@ Grid make_grid(int dim, int N) {
 
 StencilShape stencil_shape(const Grid& g) {
   StencilShape s;
-  // Nodes per thread per plane: enough work per block on big planes, few
-  // idle threads on small ones.
-  s.items = g.plane >= 8192 ? 8 : (g.plane >= 2048 ? 4 : (g.plane >= 512 ? 2 : 1));
-  s.chunk = kThreads * s.items;
-  s.nchunks = (int)((g.plane + s.chunk - 1) / s.chunk);
   if (g.dim == 2) {
+    s.items = g.plane >= 8192 * 64 ? 8 : (g.plane >= 2048 * 64 ? 4 : (g.plane >= 512 * 16 ? 2 : 1));
+    s.chunk = kThreads * s.items;
+    s.nchunks = (int)((g.plane + s.chunk - 1) / s.chunk);
     s.zc = 1;
     s.nzc = 1;
   } else {
-    // Planes per block: aim at ~768 blocks, at least 4 planes per block.
-    int64_t zc = ((int64_t)g.nn * s.nchunks + 767) / 768;
+    // Largest per-thread item count that still gives ~1024 blocks with at
+    // least 8 planes per block; small grids fall back to 1 item, 4 planes.
+    const int target = 1024;
+    int items = 8;
+    for (; items > 1; items /= 2) {
+      int64_t nch = (g.plane + kThreads * items - 1) / (kThreads * items);
+      if (nch * ((g.nn + 7) / 8) >= target) break;
+    }
+    s.items = items;
+    s.chunk = kThreads * items;
+    s.nchunks = (int)((g.plane + s.chunk - 1) / s.chunk);
+    int64_t zc = ((int64_t)g.nn * s.nchunks) / target;
     zc = std::max<int64_t>(4, std::min<int64_t>(zc, 32));
     s.zc = (int)std::min<int64_t>(zc, g.nn);
     s.nzc = (g.nn + s.zc - 1) / s.zc;
@@ -102,13 +110,17 @@ __device__ __forceinline__ double to_d(double v) { return v; }
 __device__ __forceinline__ double to_d(float v) { return (double)v; }
 
 // ---------------------------------------------------------------------------
-// The streaming kernel.  Epi is called once per owned node with
-// (index, #boundary coordinates, (M s)_i, (K s)_i, s_i).
+// The streaming kernel.  For each owned node the epilogue first issues its
+// pointwise loads (Epi::load) and later receives
+// (index, #boundary coordinates, (M s)_i, (K s)_i, s_i, loaded values).
+// Plane pz+1 is prefetched into registers (F loads per thread, all issued
+// back to back) while plane pz is processed from LDS.
 // ---------------------------------------------------------------------------
-template <int DIM, int P, bool SCALED, class TS, class Epi>
+template <int DIM, int P, int F, bool SCALED, class TS, class Epi>
 __global__ void __launch_bounds__(kThreads)
     k_stencil(const TS* __restrict__ s, Grid g, StencilShape sh, Epi epi) {
   extern __shared__ double lds[];
+  using In = typename Epi::In;
   const int tid = threadIdx.x;
   const int b = block_remap(blockIdx.x, gridDim.x);
   const int chunk = b % sh.nchunks;
@@ -130,7 +142,22 @@ __global__ void __launch_bounds__(kThreads)
     ii[p] = (int)(q - (int64_t)j * nn);
   }
 
-  const double h = g.h;
+  double pre[F];
+  auto issue = [&](int64_t zoff) {
+#pragma unroll
+    for (int f = 0; f < F; f++) {
+      const int t = tid + kThreads * f;
+      const int64_t gq = s0 - halo + t;
+      pre[f] = (t < ldsn && gq >= 0 && gq < plane) ? to_d(s[zoff + gq]) : 0.0;
+    }
+  };
+  auto commit = [&]() {
+#pragma unroll
+    for (int f = 0; f < F; f++) {
+      const int t = tid + kThreads * f;
+      if (t < ldsn) lds[t] = pre[f];
+    }
+  };
   auto plane_partials = [&](double* pm, double* pk, double* cen) {
 #pragma unroll
     for (int p = 0; p < P; p++) {
@@ -151,15 +178,15 @@ __global__ void __launch_bounds__(kThreads)
       cen[p] = lds[L];
     }
   };
-  auto fill = [&](int64_t zoff) {
-    for (int t = tid; t < ldsn; t += kThreads) {
-      int64_t gq = s0 - halo + t;
-      lds[t] = (gq >= 0 && gq < plane) ? to_d(s[zoff + gq]) : 0.0;
-    }
-  };
 
+  const double h = g.h;
   if (DIM == 2) {
-    fill(0);
+    issue(0);
+    In in[P];
+#pragma unroll
+    for (int p = 0; p < P; p++)
+      if (valid[p]) in[p] = epi.load(s0 + tid + kThreads * p);
+    commit();
     __syncthreads();
     double pm[P], pk[P], cen[P];
     plane_partials(pm, pk, cen);
@@ -169,7 +196,7 @@ __global__ void __launch_bounds__(kThreads)
       if (!valid[p]) continue;
       int nb = (ii[p] == 0 || ii[p] == N) + (jj[p] == 0 || jj[p] == N);
       int64_t idx = s0 + tid + kThreads * p;
-      epi(idx, nb, cmass * pm[p], cstiff * pk[p], cen[p]);
+      epi.store(idx, nb, cmass * pm[p], cstiff * pk[p], cen[p], in[p]);
     }
     return;
   }
@@ -181,19 +208,27 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int p = 0; p < P; p++) pma[p] = pmb[p] = pka[p] = pkb[p] = cb[p] = 0.0;
   const double cmass = h * h * h / 216.0, cstiff = h / 36.0;
+  if (z0 - 1 >= 0) issue((int64_t)(z0 - 1) * plane);
   for (int pz = z0 - 1; pz <= z1; pz++) {
-    double pmn[P], pkn[P], cn[P];
     const bool inside = (pz >= 0 && pz <= N);
+    const int o = pz - 1;  // output plane
     __syncthreads();
-    if (inside) fill((int64_t)pz * plane);
+    if (inside) commit();
     __syncthreads();
+    In in[P];
+    if (o >= z0) {
+#pragma unroll
+      for (int p = 0; p < P; p++)
+        if (valid[p]) in[p] = epi.load((int64_t)o * plane + s0 + tid + kThreads * p);
+    }
+    if (pz + 1 <= z1 && pz + 1 <= N) issue((int64_t)(pz + 1) * plane);
+    double pmn[P], pkn[P], cn[P];
     if (inside) {
       plane_partials(pmn, pkn, cn);
     } else {
 #pragma unroll
       for (int p = 0; p < P; p++) pmn[p] = pkn[p] = cn[p] = 0.0;
     }
-    const int o = pz - 1;  // output plane
     if (o >= z0) {
       double az0, az1, az2, bz0, bz1, bz2;
       pattern<SCALED>(o, N, az0, az1, az2, bz0, bz1, bz2);
@@ -206,7 +241,7 @@ __global__ void __launch_bounds__(kThreads)
                               bz1 * pmb[p] + bz2 * pmn[p]);
         int nb = (ii[p] == 0 || ii[p] == N) + (jj[p] == 0 || jj[p] == N) + nbz;
         int64_t idx = (int64_t)o * plane + s0 + tid + kThreads * p;
-        epi(idx, nb, ms, ks, cb[p]);
+        epi.store(idx, nb, ms, ks, cb[p], in[p]);
       }
     }
 #pragma unroll
@@ -220,29 +255,43 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+template <int D, int PP, bool SCALED, class TS, class Epi>
+static void launch_h(int hx, dim3 grid, dim3 block, size_t lds, hipStream_t st, const TS* s,
+                     const Grid& g, const StencilShape& sh, const Epi& e) {
+  switch (hx) {
+    case 3: hipLaunchKernelGGL((k_stencil<D, PP, PP + 3, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
+    case 5: hipLaunchKernelGGL((k_stencil<D, PP, PP + 5, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
+    case 9: hipLaunchKernelGGL((k_stencil<D, PP, PP + 9, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
+    default: hipLaunchKernelGGL((k_stencil<D, PP, PP + 17, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
+  }
+}
+
 template <bool SCALED, class TS, class Epi>
 static hipError_t run_stencil(const Grid& g, const TS* s, const Epi& e, hipStream_t st) {
   StencilShape sh = stencil_shape(g);
-  size_t lds = (size_t)(sh.chunk + 2 * (g.nn + 1)) * sizeof(double);
+  const int ldsn = sh.chunk + 2 * (g.nn + 1);
+  size_t lds = (size_t)ldsn * sizeof(double);
+  // prefetch registers beyond the chunk: ceil(2*halo/256) rounded up to 3, 5, 9, 17
+  int extra = (ldsn - sh.chunk + kThreads - 1) / kThreads;
+  int hx = extra <= 3 ? 3 : (extra <= 5 ? 5 : (extra <= 9 ? 9 : 17));
+  if (extra > 17) return hipErrorInvalidValue;
   dim3 grid(sh.blocks), block(kThreads);
-#define OKD_LAUNCH(D, PP)                                                                   \
-  hipLaunchKernelGGL((k_stencil<D, PP, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e)
   if (g.dim == 2) {
     switch (sh.items) {
-      case 8: OKD_LAUNCH(2, 8); break;
-      case 4: OKD_LAUNCH(2, 4); break;
-      case 2: OKD_LAUNCH(2, 2); break;
-      default: OKD_LAUNCH(2, 1); break;
+      case 8: launch_h<2, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+      case 4: launch_h<2, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+      case 2: launch_h<2, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+      default: launch_h<2, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
     }
   } else {
+    if (hx > 5) return hipErrorInvalidValue;
     switch (sh.items) {
-      case 8: OKD_LAUNCH(3, 8); break;
-      case 4: OKD_LAUNCH(3, 4); break;
-      case 2: OKD_LAUNCH(3, 2); break;
-      default: OKD_LAUNCH(3, 1); break;
+      case 8: launch_h<3, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+      case 4: launch_h<3, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+      case 2: launch_h<3, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+      default: launch_h<3, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
     }
   }
-#undef OKD_LAUNCH
   return hipGetLastError();
 }
 
@@ -253,16 +302,24 @@ __device__ __forceinline__ double dinv_at(double dinv_int, int nb) {
   return dinv_int * (double)(1 << nb);
 }
 
+struct In0 {};
+struct In1 {
+  double a;
+};
+struct In2 {
+  double a, b;
+};
+
 // out = add + a*(M s) + b*(K s)
 template <class TA, class TO>
 struct EpiAxpy {
+  using In = In1;
   const TA* add;
   double a, b;
   TO* out;
-  __device__ void operator()(int64_t i, int, double ms, double ks, double) const {
-    double v = a * ms + b * ks;
-    if (add) v += to_d(add[i]);
-    out[i] = (TO)v;
+  __device__ In load(int64_t i) const { return In{add ? to_d(add[i]) : 0.0}; }
+  __device__ void store(int64_t i, int, double ms, double ks, double, const In& in) const {
+    out[i] = (TO)(in.a + a * ms + b * ks);
   }
 };
 
@@ -271,12 +328,14 @@ struct EpiAxpy {
 // A d0 = (dinv_int/theta) (cm M + ck K) W^-1 b.
 template <class T, class TX, bool LAST>
 struct EpiChebFirst {
+  using In = In0;
   Op A;
   double inv_theta, c1, c2, out_scale;
   TX* x;
   T* r;
   T* d;
-  __device__ void operator()(int64_t i, int nb, double ms, double ks, double bi) const {
+  __device__ In load(int64_t) const { return In{}; }
+  __device__ void store(int64_t i, int nb, double ms, double ks, double bi, const In&) const {
     double dv = dinv_at(A.dinv_int, nb);
     double ad0 = A.dinv_int * inv_theta * (A.cm * ms + A.ck * ks);
     double d0 = dv * bi * inv_theta;
@@ -297,16 +356,18 @@ struct EpiChebFirst {
 // x_{k+2} = x_{k+1} + d_{k+1}, and writes only x.
 template <class T, class TX, bool LAST>
 struct EpiChebStep {
+  using In = In2;
   Op A;
   double c1, c2, out_scale;
   const TX* xin;
   TX* x;
   T* r;
   T* dn;
-  __device__ void operator()(int64_t i, int nb, double ms, double ks, double dk) const {
+  __device__ In load(int64_t i) const { return In{to_d(xin[i]), to_d(r[i])}; }
+  __device__ void store(int64_t i, int nb, double ms, double ks, double dk, const In& in) const {
     double dv = dinv_at(A.dinv_int, nb);
-    double xv = to_d(xin[i]) + dk;
-    double rv = to_d(r[i]) - (A.cm * ms + A.ck * ks);
+    double xv = in.a + dk;
+    double rv = in.b - (A.cm * ms + A.ck * ks);
     double d1 = c1 * dk + c2 * dv * rv;
     if (LAST) {
       x[i] = (TX)(out_scale * (xv + d1));
@@ -321,13 +382,15 @@ struct EpiChebStep {
 // Start from a given x (stencil input x): r0 = b - A x, d0 = D^-1 r0 / theta.
 template <class T>
 struct EpiChebStart {
+  using In = In1;
   Op A;
   double inv_theta;
   const T* b;
   T* r;
   T* d;
-  __device__ void operator()(int64_t i, int nb, double ms, double ks, double) const {
-    double r0 = to_d(b[i]) - (A.cm * ms + A.ck * ks);
+  __device__ In load(int64_t i) const { return In{to_d(b[i])}; }
+  __device__ void store(int64_t i, int nb, double ms, double ks, double, const In& in) const {
+    double r0 = in.a - (A.cm * ms + A.ck * ks);
     r[i] = (T)r0;
     d[i] = (T)(dinv_at(A.dinv_int, nb) * r0 * inv_theta);
   }
@@ -336,10 +399,12 @@ struct EpiChebStart {
 // One Chebyshev iteration from x0 = 0: x = D^-1 b / theta (pointwise).
 template <class T, class TX>
 struct EpiChebOne {
+  using In = In0;
   Op A;
   double inv_theta, out_scale;
   TX* x;
-  __device__ void operator()(int64_t i, int nb, double, double, double bi) const {
+  __device__ In load(int64_t) const { return In{}; }
+  __device__ void store(int64_t i, int nb, double, double, double bi, const In&) const {
     x[i] = (TX)(out_scale * dinv_at(A.dinv_int, nb) * bi * inv_theta);
   }
 };
@@ -347,11 +412,13 @@ struct EpiChebOne {
 // r = b - A x
 template <class T>
 struct EpiResid {
+  using In = In1;
   Op A;
   const T* b;
   T* r;
-  __device__ void operator()(int64_t i, int, double ms, double ks, double) const {
-    r[i] = (T)(to_d(b[i]) - (A.cm * ms + A.ck * ks));
+  __device__ In load(int64_t i) const { return In{to_d(b[i])}; }
+  __device__ void store(int64_t i, int, double ms, double ks, double, const In& in) const {
+    r[i] = (T)(in.a - (A.cm * ms + A.ck * ks));
   }
 };
 
