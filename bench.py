@@ -67,6 +67,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -87,6 +88,7 @@ def main():
     u0d = torch.from_numpy(u0).to(dev)
     w0d = torch.from_numpy(w0).to(dev)
     u, w = u0d.clone(), w0d.clone()
+    tuned = 0 if args.no_autotune else P.autotune()
     for _ in range(args.warmup):
         P.timestep(u, w, 1)
     u.copy_(u0d)
@@ -139,6 +141,7 @@ def main():
         "newton_its": stats.per_step(),
         "fgmres_its": its,
         "roofline": roofline,
+        "autotuned_shapes": tuned,
     }
     if not args.no_cpu_baseline:
         per_step = stats.fgmres_its_total / max(stats.steps_done, 1)

@@ -189,6 +189,16 @@ enum ok_kernel_class {
 int ok_profile_enable(ok_ctx *ctx, int32_t kernel_class);
 int ok_profile_read(ok_ctx *ctx, int64_t *launches, double *total_ms, double *bytes);
 
+/* Tile autotuner: time the candidate launch shapes (nodes per thread x planes
+ * per block) of the stencil kernels on this problem's grids -- every
+ * multigrid level for the one-field kernels, the finest grid for the
+ * two-field Jacobian kernel -- with HIP events on `stream`, and keep the
+ * fastest.  The choice is stored process-wide, keyed by (d, N+1, fields,
+ * precision), and used by every later launch on such a grid.  Results are
+ * bitwise the same for every shape.  *entries (may be NULL) receives the
+ * number of table entries set.  Synchronises; run it outside timed regions. */
+int ok_autotune(ok_ctx *ctx, void *stream, int32_t *entries);
+
 /* Destroy a context (frees host state only; the caller frees its memory). */
 int ok_destroy(ok_ctx *ctx);
 

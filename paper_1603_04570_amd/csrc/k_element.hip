@@ -1,8 +1,10 @@
 // Element quadrature of the u-dependent terms on the finest Q1 grid:
-//   (M_E(u) x)_i = int (3u^2 - 1) x phi_i      (Sec. 2, entries of M_E)
-//   N(u)_i       = int (u^3 - u) phi_i          (weak form of u(u^2-1) in (okb))
+//   G(u, x)_i = int u^2 x phi_i,  so that  M_E(u) x = 3 G(u, x) - M x
+//               (Sec. 2, entries of M_E: int (3u^2 - 1) phi_i phi_j)
+//   N(u)_i    = int (u^3 - u) phi_i      (weak form of u(u^2-1) in (okb))
 // with u, x the Q1 interpolants.  The integrands are of degree 4 per
-// direction, so the 3-point Gauss-Legendre rule per direction is exact.
+// direction, so the 3-point Gauss-Legendre rule per direction is exact.  The
+// -M x part of M_E x is applied by the node-stencil kernels that consume G.
 //
 // Layout of the work: a block of 8 wavefronts covers 7 node rows of the x-y
 // plane and streams along z one element layer at a time.  Wavefront w owns
@@ -38,14 +40,16 @@ __device__ __forceinline__ void lerp3(double v0, double v1, double* o) {
   o[2] = v1 - kG0 * d;
 }
 
-// Transpose of lerp3: contributions of 3 Gauss-point values to the 2 ends.
+// Transpose of lerp3 with the Gauss weights folded in: contributions of the
+// 3 Gauss-point values of one direction to the 2 ends.
+constexpr double kPa = (1.0 - kG0) * kW0;
+constexpr double kPb = 0.5 * kW1;
+constexpr double kPc = kG0 * kW0;
 __device__ __forceinline__ void proj3(const double* t, double& o0, double& o1) {
-  double m = 0.5 * t[1];
-  o0 = (1.0 - kG0) * t[0] + m + kG0 * t[2];
-  o1 = kG0 * t[0] + m + (1.0 - kG0) * t[2];
+  double m = kPb * t[1];
+  o0 = kPa * t[0] + m + kPc * t[2];
+  o1 = kPc * t[0] + m + kPa * t[2];
 }
-
-__device__ __forceinline__ double wq(int q) { return q == 1 ? kW1 : kW0; }
 
 __device__ __forceinline__ int remap(int b, int nb) {
   int q = nb / 8, r = nb % 8;
@@ -93,16 +97,15 @@ __device__ __forceinline__ void element3(const double (&u)[2][2][2], const doubl
         for (int qz = 0; qz < 3; qz++) xq[qz][qy][qx] = t[qz];
       }
   }
-  // integrand times the Gauss weights
+  // integrand (the Gauss weights are folded into proj3)
   for (int qz = 0; qz < 3; qz++)
     for (int qy = 0; qy < 3; qy++)
       for (int qx = 0; qx < 3; qx++) {
-        double w = wq(qx) * wq(qy) * wq(qz);
         double v = uq[qz][qy][qx];
         if (MODE == 0)
-          uq[qz][qy][qx] = w * (3.0 * v * v - 1.0) * xq[qz][qy][qx];
+          uq[qz][qy][qx] = (v * v) * xq[qz][qy][qx];
         else
-          uq[qz][qy][qx] = w * (v * v * v - v);
+          uq[qz][qy][qx] = (v * v) * v - v;
       }
   // project back: z, then y, then x
   double b[2][3][3];
@@ -145,12 +148,11 @@ __device__ __forceinline__ void element2(const double (&u)[2][2], const double (
   }
   for (int qy = 0; qy < 3; qy++)
     for (int qx = 0; qx < 3; qx++) {
-      double w = wq(qx) * wq(qy);
       double v = uq[qy][qx];
       if (MODE == 0)
-        uq[qy][qx] = w * (3.0 * v * v - 1.0) * xq[qy][qx];
+        uq[qy][qx] = (v * v) * xq[qy][qx];
       else
-        uq[qy][qx] = w * (v * v * v - v);
+        uq[qy][qx] = (v * v) * v - v;
     }
   double a[2][3];
   for (int qx = 0; qx < 3; qx++) {

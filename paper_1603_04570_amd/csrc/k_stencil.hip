@@ -17,6 +17,9 @@
 #include "ok_internal.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace okd {
 
@@ -31,31 +34,55 @@ Grid make_grid(int dim, int N) {
   return g;
 }
 
-StencilShape stencil_shape(const Grid& g) {
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune;  // (dim, nn, nf, word) -> (items, zc)
+}  // namespace
+
+void stencil_tune_set(int dim, int nn, int nf, int word, int items, int zc) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (items <= 0)
+    g_tune.erase(std::make_tuple(dim, nn, nf, word));
+  else
+    g_tune[std::make_tuple(dim, nn, nf, word)] = std::make_pair(items, zc);
+}
+
+static StencilShape shape_with(const Grid& g, int items, int zc) {
   StencilShape s;
-  if (g.dim == 2) {
-    s.items = g.plane >= 8192 * 64 ? 8 : (g.plane >= 2048 * 64 ? 4 : (g.plane >= 512 * 16 ? 2 : 1));
-    s.chunk = kThreads * s.items;
-    s.nchunks = (int)((g.plane + s.chunk - 1) / s.chunk);
-    s.zc = 1;
-    s.nzc = 1;
-  } else {
-    // Largest per-thread item count that still gives ~1024 blocks with at
-    // least 8 planes per block; small grids fall back to 1 item, 4 planes.
-    const int target = 1024;
-    int items = 8;
-    for (; items > 1; items /= 2) {
-      int64_t nch = (g.plane + kThreads * items - 1) / (kThreads * items);
-      if (nch * ((g.nn + 7) / 8) >= target) break;
-    }
-    s.items = items;
-    s.chunk = kThreads * items;
-    s.nchunks = (int)((g.plane + s.chunk - 1) / s.chunk);
-    int64_t zc = ((int64_t)g.nn * s.nchunks) / target;
-    zc = std::max<int64_t>(4, std::min<int64_t>(zc, 32));
-    s.zc = (int)std::min<int64_t>(zc, g.nn);
-    s.nzc = (g.nn + s.zc - 1) / s.zc;
+  const int64_t plane = (g.dim == 3) ? g.plane : (int64_t)g.nn;
+  s.items = items;
+  s.chunk = kThreads * items;
+  s.nchunks = (int)((plane + s.chunk - 1) / s.chunk);
+  s.zc = std::max(1, std::min(zc, g.nn));
+  s.nzc = (g.nn + s.zc - 1) / s.zc;
+  s.blocks = s.nchunks * s.nzc;
+  return s;
+}
+
+StencilShape stencil_shape(const Grid& g, int nf, int word) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(g.dim, g.nn, nf, word));
+    if (it != g_tune.end()) return shape_with(g, it->second.first, it->second.second);
   }
+  StencilShape s;
+  const int target = 1024;
+  // nodes per streaming plane: an x-y plane in 3D, an x row in 2D
+  const int64_t plane = (g.dim == 3) ? g.plane : (int64_t)g.nn;
+  // Largest per-thread item count that still gives ~1024 blocks with at
+  // least 8 planes per block; small grids fall back to 1 item, 4 planes.
+  int items = (nf > 1) ? 4 : 8;
+  for (; items > 1; items /= 2) {
+    int64_t nch = (plane + kThreads * items - 1) / (kThreads * items);
+    if (nch * ((g.nn + 7) / 8) >= target) break;
+  }
+  s.items = items;
+  s.chunk = kThreads * items;
+  s.nchunks = (int)((plane + s.chunk - 1) / s.chunk);
+  int64_t zc = ((int64_t)g.nn * s.nchunks) / target;
+  zc = std::max<int64_t>(4, std::min<int64_t>(zc, 32));
+  s.zc = (int)std::min<int64_t>(zc, g.nn);
+  s.nzc = (g.nn + s.zc - 1) / s.zc;
   s.blocks = s.nchunks * s.nzc;
   return s;
 }
@@ -110,15 +137,20 @@ __device__ __forceinline__ double to_d(double v) { return v; }
 __device__ __forceinline__ double to_d(float v) { return (double)v; }
 
 // ---------------------------------------------------------------------------
-// The streaming kernel.  For each owned node the epilogue first issues its
-// pointwise loads (Epi::load) and later receives
-// (index, #boundary coordinates, (M s)_i, (K s)_i, s_i, loaded values).
-// Plane pz+1 is prefetched into registers (F loads per thread, all issued
-// back to back) while plane pz is processed from LDS.
+// The streaming kernel over NF stenciled fields.  For each owned node the
+// epilogue first issues its pointwise loads (Epi::load) and later receives
+// (index, #boundary coordinates, (M s_f)_i, (K s_f)_i, (s_f)_i for f < NF,
+// loaded values).  Plane pz+1 is prefetched into registers (F loads per thread
+// and field, all issued back to back) while plane pz is processed from LDS.
 // ---------------------------------------------------------------------------
-template <int DIM, int P, int F, bool SCALED, class TS, class Epi>
+template <class TS, int NF>
+struct Src {
+  const TS* p[NF];
+};
+
+template <int DIM, int NF, int P, int F, bool SCALED, class TS, class Epi>
 __global__ void __launch_bounds__(kThreads)
-    k_stencil(const TS* __restrict__ s, Grid g, StencilShape sh, Epi epi) {
+    k_stencil(Src<TS, NF> src, Grid g, StencilShape sh, Epi epi) {
   extern __shared__ double lds[];
   using In = typename Epi::In;
   const int tid = threadIdx.x;
@@ -126,8 +158,9 @@ __global__ void __launch_bounds__(kThreads)
   const int chunk = b % sh.nchunks;
   const int zch = b / sh.nchunks;
   const int nn = g.nn, N = g.N;
-  const int64_t plane = g.plane;
-  const int halo = nn + 1;
+  // Streaming "plane": an x-y plane in 3D, an x row in 2D.
+  const int64_t plane = (DIM == 3) ? g.plane : (int64_t)nn;
+  const int halo = (DIM == 3) ? nn + 1 : 1;
   const int ldsn = sh.chunk + 2 * halo;
   const int64_t s0 = (int64_t)chunk * sh.chunk;
 
@@ -137,77 +170,87 @@ __global__ void __launch_bounds__(kThreads)
   for (int p = 0; p < P; p++) {
     int64_t q = s0 + tid + kThreads * p;
     valid[p] = q < plane;
-    int j = (int)(q / nn);
-    jj[p] = j;
-    ii[p] = (int)(q - (int64_t)j * nn);
+    if (DIM == 3) {
+      int j = (int)(q / nn);
+      jj[p] = j;
+      ii[p] = (int)(q - (int64_t)j * nn);
+    } else {
+      jj[p] = 0;
+      ii[p] = (int)q;
+    }
   }
 
-  double pre[F];
+  double pre[NF][F];
   auto issue = [&](int64_t zoff) {
 #pragma unroll
-    for (int f = 0; f < F; f++) {
-      const int t = tid + kThreads * f;
-      const int64_t gq = s0 - halo + t;
-      pre[f] = (t < ldsn && gq >= 0 && gq < plane) ? to_d(s[zoff + gq]) : 0.0;
-    }
+    for (int f = 0; f < NF; f++)
+#pragma unroll
+      for (int k = 0; k < F; k++) {
+        const int t = tid + kThreads * k;
+        const int64_t gq = s0 - halo + t;
+        pre[f][k] = (t < ldsn && gq >= 0 && gq < plane) ? to_d(src.p[f][zoff + gq]) : 0.0;
+      }
   };
   auto commit = [&]() {
 #pragma unroll
-    for (int f = 0; f < F; f++) {
-      const int t = tid + kThreads * f;
-      if (t < ldsn) lds[t] = pre[f];
-    }
+    for (int f = 0; f < NF; f++)
+#pragma unroll
+      for (int k = 0; k < F; k++) {
+        const int t = tid + kThreads * k;
+        if (t < ldsn) lds[f * ldsn + t] = pre[f][k];
+      }
   };
-  auto plane_partials = [&](double* pm, double* pk, double* cen) {
+  // In-plane partial products: 3D P_M = (M1 x M1) s, P_K = (K1 x M1 + M1 x K1) s;
+  // 2D P_M = M1 s, P_K = K1 s along x (constants applied later).
+  auto plane_partials = [&](double (*pm)[P], double (*pk)[P], double (*cen)[P]) {
 #pragma unroll
     for (int p = 0; p < P; p++) {
       const int L = tid + kThreads * p + halo;
-      double ax0, ax1, ax2, bx0, bx1, bx2, ay0, ay1, ay2, by0, by1, by2;
+      double ax0, ax1, ax2, bx0, bx1, bx2;
       pattern<SCALED>(ii[p], N, ax0, ax1, ax2, bx0, bx1, bx2);
-      pattern<SCALED>(jj[p], N, ay0, ay1, ay2, by0, by1, by2);
-      double mr[3], kr[3];
+      if (DIM == 3) {
+        double ay0, ay1, ay2, by0, by1, by2;
+        pattern<SCALED>(jj[p], N, ay0, ay1, ay2, by0, by1, by2);
 #pragma unroll
-      for (int r = 0; r < 3; r++) {
-        const int base = L + (r - 1) * nn;
-        double va = lds[base - 1], vb = lds[base], vc = lds[base + 1];
-        mr[r] = ax0 * va + ax1 * vb + ax2 * vc;
-        kr[r] = bx0 * va + bx1 * vb + bx2 * vc;
+        for (int f = 0; f < NF; f++) {
+          const double* lf = lds + f * ldsn;
+          double mr[3], kr[3];
+#pragma unroll
+          for (int r = 0; r < 3; r++) {
+            const int base = L + (r - 1) * nn;
+            double va = lf[base - 1], vb = lf[base], vc = lf[base + 1];
+            mr[r] = ax0 * va + ax1 * vb + ax2 * vc;
+            kr[r] = bx0 * va + bx1 * vb + bx2 * vc;
+          }
+          pm[f][p] = ay0 * mr[0] + ay1 * mr[1] + ay2 * mr[2];
+          pk[f][p] = ay0 * kr[0] + ay1 * kr[1] + ay2 * kr[2] + by0 * mr[0] + by1 * mr[1] +
+                     by2 * mr[2];
+          cen[f][p] = lf[L];
+        }
+      } else {
+#pragma unroll
+        for (int f = 0; f < NF; f++) {
+          const double* lf = lds + f * ldsn;
+          double va = lf[L - 1], vb = lf[L], vc = lf[L + 1];
+          pm[f][p] = ax0 * va + ax1 * vb + ax2 * vc;
+          pk[f][p] = bx0 * va + bx1 * vb + bx2 * vc;
+          cen[f][p] = vb;
+        }
       }
-      pm[p] = ay0 * mr[0] + ay1 * mr[1] + ay2 * mr[2];
-      pk[p] = ay0 * kr[0] + ay1 * kr[1] + ay2 * kr[2] + by0 * mr[0] + by1 * mr[1] + by2 * mr[2];
-      cen[p] = lds[L];
     }
   };
 
+  // Stream planes z0-1 .. z1 along the last axis, output planes z0 .. z1-1.
   const double h = g.h;
-  if (DIM == 2) {
-    issue(0);
-    In in[P];
-#pragma unroll
-    for (int p = 0; p < P; p++)
-      if (valid[p]) in[p] = epi.load(s0 + tid + kThreads * p);
-    commit();
-    __syncthreads();
-    double pm[P], pk[P], cen[P];
-    plane_partials(pm, pk, cen);
-    const double cmass = h * h / 36.0, cstiff = 1.0 / 6.0;
-#pragma unroll
-    for (int p = 0; p < P; p++) {
-      if (!valid[p]) continue;
-      int nb = (ii[p] == 0 || ii[p] == N) + (jj[p] == 0 || jj[p] == N);
-      int64_t idx = s0 + tid + kThreads * p;
-      epi.store(idx, nb, cmass * pm[p], cstiff * pk[p], cen[p], in[p]);
-    }
-    return;
-  }
-
-  // 3D: stream planes z0-1 .. z1, output planes z0 .. z1-1.
+  const double cmass = (DIM == 3) ? h * h * h / 216.0 : h * h / 36.0;
+  const double cstiff = (DIM == 3) ? h / 36.0 : 1.0 / 6.0;
   const int z0 = zch * sh.zc;
   const int z1 = min(z0 + sh.zc, nn);
-  double pma[P], pmb[P], pka[P], pkb[P], cb[P];
+  double pma[NF][P], pmb[NF][P], pka[NF][P], pkb[NF][P], cb[NF][P];
 #pragma unroll
-  for (int p = 0; p < P; p++) pma[p] = pmb[p] = pka[p] = pkb[p] = cb[p] = 0.0;
-  const double cmass = h * h * h / 216.0, cstiff = h / 36.0;
+  for (int f = 0; f < NF; f++)
+#pragma unroll
+    for (int p = 0; p < P; p++) pma[f][p] = pmb[f][p] = pka[f][p] = pkb[f][p] = cb[f][p] = 0.0;
   if (z0 - 1 >= 0) issue((int64_t)(z0 - 1) * plane);
   for (int pz = z0 - 1; pz <= z1; pz++) {
     const bool inside = (pz >= 0 && pz <= N);
@@ -222,12 +265,14 @@ __global__ void __launch_bounds__(kThreads)
         if (valid[p]) in[p] = epi.load((int64_t)o * plane + s0 + tid + kThreads * p);
     }
     if (pz + 1 <= z1 && pz + 1 <= N) issue((int64_t)(pz + 1) * plane);
-    double pmn[P], pkn[P], cn[P];
+    double pmn[NF][P], pkn[NF][P], cn[NF][P];
     if (inside) {
       plane_partials(pmn, pkn, cn);
     } else {
 #pragma unroll
-      for (int p = 0; p < P; p++) pmn[p] = pkn[p] = cn[p] = 0.0;
+      for (int f = 0; f < NF; f++)
+#pragma unroll
+        for (int p = 0; p < P; p++) pmn[f][p] = pkn[f][p] = cn[f][p] = 0.0;
     }
     if (o >= z0) {
       double az0, az1, az2, bz0, bz1, bz2;
@@ -236,63 +281,96 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
       for (int p = 0; p < P; p++) {
         if (!valid[p]) continue;
-        double ms = cmass * (az0 * pma[p] + az1 * pmb[p] + az2 * pmn[p]);
-        double ks = cstiff * (az0 * pka[p] + az1 * pkb[p] + az2 * pkn[p] + bz0 * pma[p] +
-                              bz1 * pmb[p] + bz2 * pmn[p]);
-        int nb = (ii[p] == 0 || ii[p] == N) + (jj[p] == 0 || jj[p] == N) + nbz;
+        double ms[NF], ks[NF], cc[NF];
+#pragma unroll
+        for (int f = 0; f < NF; f++) {
+          ms[f] = cmass * (az0 * pma[f][p] + az1 * pmb[f][p] + az2 * pmn[f][p]);
+          ks[f] = cstiff * (az0 * pka[f][p] + az1 * pkb[f][p] + az2 * pkn[f][p] +
+                            bz0 * pma[f][p] + bz1 * pmb[f][p] + bz2 * pmn[f][p]);
+          cc[f] = cb[f][p];
+        }
+        int nb = (ii[p] == 0 || ii[p] == N) + nbz;
+        if (DIM == 3) nb += (jj[p] == 0 || jj[p] == N);
         int64_t idx = (int64_t)o * plane + s0 + tid + kThreads * p;
-        epi.store(idx, nb, ms, ks, cb[p], in[p]);
+        epi.store(idx, nb, ms, ks, cc, in[p]);
       }
     }
 #pragma unroll
-    for (int p = 0; p < P; p++) {
-      pma[p] = pmb[p];
-      pmb[p] = pmn[p];
-      pka[p] = pkb[p];
-      pkb[p] = pkn[p];
-      cb[p] = cn[p];
-    }
+    for (int f = 0; f < NF; f++)
+#pragma unroll
+      for (int p = 0; p < P; p++) {
+        pma[f][p] = pmb[f][p];
+        pmb[f][p] = pmn[f][p];
+        pka[f][p] = pkb[f][p];
+        pkb[f][p] = pkn[f][p];
+        cb[f][p] = cn[f][p];
+      }
   }
 }
 
-template <int D, int PP, bool SCALED, class TS, class Epi>
-static void launch_h(int hx, dim3 grid, dim3 block, size_t lds, hipStream_t st, const TS* s,
-                     const Grid& g, const StencilShape& sh, const Epi& e) {
+template <int D, int NF, int PP, bool SCALED, class TS, class Epi>
+static void launch_h(int hx, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                     const Src<TS, NF>& s, const Grid& g, const StencilShape& sh, const Epi& e) {
   switch (hx) {
-    case 3: hipLaunchKernelGGL((k_stencil<D, PP, PP + 3, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
-    case 5: hipLaunchKernelGGL((k_stencil<D, PP, PP + 5, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
-    case 9: hipLaunchKernelGGL((k_stencil<D, PP, PP + 9, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
-    default: hipLaunchKernelGGL((k_stencil<D, PP, PP + 17, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
+    case 3: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 3, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
+    case 5: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 5, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
+    case 9: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 9, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
+    default: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 17, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
   }
+}
+
+template <bool SCALED, class TS, int NF, class Epi>
+static hipError_t run_stencil_n(const Grid& g, const Src<TS, NF>& s, const Epi& e,
+                                hipStream_t st) {
+  StencilShape sh = stencil_shape(g, NF, (int)sizeof(TS));
+  const int ldsn = sh.chunk + 2 * (g.dim == 3 ? g.nn + 1 : 1);
+  size_t lds = (size_t)NF * ldsn * sizeof(double);
+  // prefetch registers beyond the chunk: ceil(2*halo/256) rounded up to 3, 5, 9, 17
+  int extra = (ldsn - sh.chunk + kThreads - 1) / kThreads;
+  int hx = extra <= 3 ? 3 : (extra <= 5 ? 5 : (extra <= 9 ? 9 : 17));
+  if (extra > 17 || lds > 65536) return hipErrorInvalidValue;
+  dim3 grid(sh.blocks), block(kThreads);
+  if (g.dim == 2) {
+    if (NF == 1) {
+      switch (sh.items) {
+        case 8: launch_h<2, NF, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        case 4: launch_h<2, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        case 2: launch_h<2, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        default: launch_h<2, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+      }
+    } else {
+      if (sh.items > 4) return hipErrorInvalidValue;
+      switch (sh.items) {
+        case 4: launch_h<2, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        case 2: launch_h<2, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        default: launch_h<2, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+      }
+    }
+  } else {
+    if (hx > 5) return hipErrorInvalidValue;
+    if (NF == 1) {
+      switch (sh.items) {
+        case 8: launch_h<3, NF, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        case 4: launch_h<3, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        case 2: launch_h<3, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        default: launch_h<3, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+      }
+    } else {
+      if (sh.items > 4) return hipErrorInvalidValue;
+      switch (sh.items) {
+        case 4: launch_h<3, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        case 2: launch_h<3, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        default: launch_h<3, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+      }
+    }
+  }
+  return hipGetLastError();
 }
 
 template <bool SCALED, class TS, class Epi>
 static hipError_t run_stencil(const Grid& g, const TS* s, const Epi& e, hipStream_t st) {
-  StencilShape sh = stencil_shape(g);
-  const int ldsn = sh.chunk + 2 * (g.nn + 1);
-  size_t lds = (size_t)ldsn * sizeof(double);
-  // prefetch registers beyond the chunk: ceil(2*halo/256) rounded up to 3, 5, 9, 17
-  int extra = (ldsn - sh.chunk + kThreads - 1) / kThreads;
-  int hx = extra <= 3 ? 3 : (extra <= 5 ? 5 : (extra <= 9 ? 9 : 17));
-  if (extra > 17) return hipErrorInvalidValue;
-  dim3 grid(sh.blocks), block(kThreads);
-  if (g.dim == 2) {
-    switch (sh.items) {
-      case 8: launch_h<2, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-      case 4: launch_h<2, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-      case 2: launch_h<2, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-      default: launch_h<2, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-    }
-  } else {
-    if (hx > 5) return hipErrorInvalidValue;
-    switch (sh.items) {
-      case 8: launch_h<3, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-      case 4: launch_h<3, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-      case 2: launch_h<3, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-      default: launch_h<3, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-    }
-  }
-  return hipGetLastError();
+  Src<TS, 1> src{{s}};
+  return run_stencil_n<SCALED, TS, 1>(g, src, e, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -318,8 +396,9 @@ struct EpiAxpy {
   double a, b;
   TO* out;
   __device__ In load(int64_t i) const { return In{add ? to_d(add[i]) : 0.0}; }
-  __device__ void store(int64_t i, int, double ms, double ks, double, const In& in) const {
-    out[i] = (TO)(in.a + a * ms + b * ks);
+  __device__ void store(int64_t i, int, const double* ms, const double* ks, const double*,
+                        const In& in) const {
+    out[i] = (TO)(in.a + a * ms[0] + b * ks[0]);
   }
 };
 
@@ -335,9 +414,11 @@ struct EpiChebFirst {
   T* r;
   T* d;
   __device__ In load(int64_t) const { return In{}; }
-  __device__ void store(int64_t i, int nb, double ms, double ks, double bi, const In&) const {
+  __device__ void store(int64_t i, int nb, const double* ms, const double* ks, const double* cen,
+                        const In&) const {
+    const double bi = cen[0];
     double dv = dinv_at(A.dinv_int, nb);
-    double ad0 = A.dinv_int * inv_theta * (A.cm * ms + A.ck * ks);
+    double ad0 = A.dinv_int * inv_theta * (A.cm * ms[0] + A.ck * ks[0]);
     double d0 = dv * bi * inv_theta;
     double r1 = bi - ad0;
     double d1 = c1 * d0 + c2 * dv * r1;
@@ -364,10 +445,12 @@ struct EpiChebStep {
   T* r;
   T* dn;
   __device__ In load(int64_t i) const { return In{to_d(xin[i]), to_d(r[i])}; }
-  __device__ void store(int64_t i, int nb, double ms, double ks, double dk, const In& in) const {
+  __device__ void store(int64_t i, int nb, const double* ms, const double* ks, const double* cen,
+                        const In& in) const {
+    const double dk = cen[0];
     double dv = dinv_at(A.dinv_int, nb);
     double xv = in.a + dk;
-    double rv = in.b - (A.cm * ms + A.ck * ks);
+    double rv = in.b - (A.cm * ms[0] + A.ck * ks[0]);
     double d1 = c1 * dk + c2 * dv * rv;
     if (LAST) {
       x[i] = (TX)(out_scale * (xv + d1));
@@ -389,8 +472,9 @@ struct EpiChebStart {
   T* r;
   T* d;
   __device__ In load(int64_t i) const { return In{to_d(b[i])}; }
-  __device__ void store(int64_t i, int nb, double ms, double ks, double, const In& in) const {
-    double r0 = in.a - (A.cm * ms + A.ck * ks);
+  __device__ void store(int64_t i, int nb, const double* ms, const double* ks, const double*,
+                        const In& in) const {
+    double r0 = in.a - (A.cm * ms[0] + A.ck * ks[0]);
     r[i] = (T)r0;
     d[i] = (T)(dinv_at(A.dinv_int, nb) * r0 * inv_theta);
   }
@@ -404,8 +488,9 @@ struct EpiChebOne {
   double inv_theta, out_scale;
   TX* x;
   __device__ In load(int64_t) const { return In{}; }
-  __device__ void store(int64_t i, int nb, double, double, double bi, const In&) const {
-    x[i] = (TX)(out_scale * dinv_at(A.dinv_int, nb) * bi * inv_theta);
+  __device__ void store(int64_t i, int nb, const double*, const double*, const double* cen,
+                        const In&) const {
+    x[i] = (TX)(out_scale * dinv_at(A.dinv_int, nb) * cen[0] * inv_theta);
   }
 };
 
@@ -417,8 +502,30 @@ struct EpiResid {
   const T* b;
   T* r;
   __device__ In load(int64_t i) const { return In{to_d(b[i])}; }
-  __device__ void store(int64_t i, int, double ms, double ks, double, const In& in) const {
-    r[i] = (T)(in.a - (A.cm * ms + A.ck * ks));
+  __device__ void store(int64_t i, int, const double* ms, const double* ks, const double*,
+                        const In& in) const {
+    r[i] = (T)(in.a - (A.cm * ms[0] + A.ck * ks[0]));
+  }
+};
+
+// Two stenciled fields s0, s1 and up to two outputs:
+//   out0 = add0 + c0[0] M s0 + c0[1] K s0 + c0[2] M s1 + c0[3] K s1
+//   out1 = add1 + c1[0] M s0 + c1[1] K s0 + c1[2] M s1 + c1[3] K s1   (if out1)
+template <class TO>
+struct EpiLin2 {
+  using In = In2;
+  const double* add0;
+  const double* add1;
+  double c0[4], c1[4];
+  TO* out0;
+  TO* out1;
+  __device__ In load(int64_t i) const {
+    return In{add0 ? add0[i] : 0.0, add1 ? add1[i] : 0.0};
+  }
+  __device__ void store(int64_t i, int, const double* ms, const double* ks, const double*,
+                        const In& in) const {
+    out0[i] = (TO)(in.a + c0[0] * ms[0] + c0[1] * ks[0] + c0[2] * ms[1] + c0[3] * ks[1]);
+    if (out1) out1[i] = (TO)(in.b + c1[0] * ms[0] + c1[1] * ks[0] + c1[2] * ms[1] + c1[3] * ks[1]);
   }
 };
 
@@ -496,6 +603,24 @@ hipError_t launch_resid(const Grid& g, const Op& A, const T* b, const T* x, T* r
   EpiResid<T> e{A, b, r};
   return run_stencil<false>(g, x, e, st);
 }
+
+template <class TS>
+hipError_t launch_stencil_lin2(const Grid& g, const TS* s0, const TS* s1, const double* add0,
+                               const double* add1, const double* c0, const double* c1,
+                               double* out0, double* out1, hipStream_t st) {
+  EpiLin2<double> e{add0, add1, {c0[0], c0[1], c0[2], c0[3]},
+                    {c1 ? c1[0] : 0.0, c1 ? c1[1] : 0.0, c1 ? c1[2] : 0.0, c1 ? c1[3] : 0.0},
+                    out0, out1};
+  Src<TS, 2> src{{s0, s1}};
+  return run_stencil_n<false, TS, 2>(g, src, e, st);
+}
+
+template hipError_t launch_stencil_lin2<double>(const Grid&, const double*, const double*,
+                                                const double*, const double*, const double*,
+                                                const double*, double*, double*, hipStream_t);
+template hipError_t launch_stencil_lin2<float>(const Grid&, const float*, const float*,
+                                               const double*, const double*, const double*,
+                                               const double*, double*, double*, hipStream_t);
 
 // Explicit instantiations.
 template hipError_t launch_mass<double, double>(const Grid&, const double*, double*, double,

@@ -1,6 +1,7 @@
 // C ABI of libok.so: problem setup, the block preconditioner, flexible GMRES,
 // Newton and the timestep loop.  Host code only orchestrates; every vector
 // operation runs in the HIP kernels of this library.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -17,6 +18,7 @@ namespace {
 struct ProfPair {
   hipEvent_t a, b;
   double bytes;
+  int count;  // kernel launches between the two events
 };
 
 }  // namespace
@@ -213,7 +215,7 @@ struct ProfScope {
   bool on;
   ProfPair* pp = nullptr;
   hipStream_t st;
-  ProfScope(ok_ctx* cc, int cls, double bytes, hipStream_t s) : c(cc), st(s) {
+  ProfScope(ok_ctx* cc, int cls, double bytes, hipStream_t s, int count = 1) : c(cc), st(s) {
     on = (c->prof_class == cls) || (c->prof_class == OK_K_STENCIL_ANY && cls != OK_K_KRYLOV &&
                                      cls != OK_K_ELEMENT);
     if (!on) return;
@@ -225,6 +227,7 @@ struct ProfScope {
     }
     pp = &c->prof[c->prof_used++];
     pp->bytes = bytes;
+    pp->count = count;
     (void)hipEventRecord(pp->a, st);
   }
   ~ProfScope() {
@@ -267,16 +270,25 @@ int cheb_zero(ok_ctx* c, int cls, int step_cls, const Grid& g, const Op& A, cons
     ProfScope ps(c, cls, wb + (K == 2 ? w : 3.0 * w), st);
     OK_HIP(c, launch_cheb_first<TB, P>(g, A, it, c1, c2, out_scale, K == 2, b, x, r, da, st));
   }
+  if (K == 2) return OK_SUCCESS;
   P* dc = da;
   P* dn = db;
-  for (int k = 1; k <= K - 2; k++) {
+  // middle iterations (x, r, d -> x, r, d) back to back, timed as one run
+  {
+    const int mid = K > 3 ? K - 3 : 0;
+    ProfScope ps(c, step_cls, 6.0 * w * mid, st, mid);
+    for (int k = 1; k <= K - 3; k++) {
+      rr.next(c1, c2);
+      OK_HIP(c, launch_cheb_step<P>(g, A, c1, c2, out_scale, false, x, r, dc, dn, st));
+      P* t = dc;
+      dc = dn;
+      dn = t;
+    }
+  }
+  {
     rr.next(c1, c2);
-    const bool last = (k == K - 2);
-    ProfScope ps(c, last ? cls : step_cls, last ? 4.0 * w : 6.0 * w, st);
-    OK_HIP(c, launch_cheb_step<P>(g, A, c1, c2, out_scale, last, x, r, dc, dn, st));
-    P* t = dc;
-    dc = dn;
-    dn = t;
+    ProfScope ps(c, cls, 4.0 * w, st);
+    OK_HIP(c, launch_cheb_step<P>(g, A, c1, c2, out_scale, true, x, r, dc, dn, st));
   }
   return OK_SUCCESS;
 }
@@ -371,10 +383,11 @@ int precond(ok_ctx* c, const double* u, const double* r, P* z, hipStream_t st) {
   // y = r2 - C z1 = r2 + eps^2 K z1 + M_E(u) z1  (M_E in FP64)
   {
     ProfScope ps(c, OK_K_ELEMENT, (double)n * (8.0 + 8.0 + c->psz + 8.0), st);
-    OK_HIP(c, launch_element<P, double>(g, 0, u, z1, r2, 1.0, 1.0, c->G, st));
+    OK_HIP(c, launch_element<P, double>(g, 0, u, z1, r2, 3.0, 1.0, c->G, st));  // 3G + r2
   }
   P* y = (P*)c->y;
-  OK_HIP(c, launch_stencil_axpy<P, double, P>(g, z1, c->G, 0.0, c->p.eps * c->p.eps, y, st));
+  // y = r2 + 3G - M z1 + eps^2 K z1 = r2 + M_E z1 + eps^2 K z1
+  OK_HIP(c, launch_stencil_axpy<P, double, P>(g, z1, c->G, -1.0, c->p.eps * c->p.eps, y, st));
   if (c->p.schur_richardson > 1) return fail(c, OK_E_INVALID, "schur_richardson > 1 not built");
   // z2 = S^^-1 M S^^-1 y
   P* t = (P*)c->t;
@@ -397,12 +410,16 @@ int jac_apply(ok_ctx* c, const double* u, const TX* x, double* y, hipStream_t st
   const double e2 = c->p.eps * c->p.eps;
   {
     ProfScope ps(c, OK_K_ELEMENT, (double)n * (8.0 + sizeof(TX) + 8.0), st);
-    OK_HIP(c, launch_element<TX, double>(g, 0, u, x1, nullptr, -1.0, 0.0, c->G, st));  // -M_E x1
+    OK_HIP(c, launch_element<TX, double>(g, 0, u, x1, nullptr, -3.0, 0.0, c->G, st));  // -3G
   }
-  OK_HIP(c, launch_stencil_axpy<TX, double, double>(g, x1, nullptr, c->sA, 0.0, y1, st));
-  OK_HIP(c, launch_stencil_axpy<TX, double, double>(g, x2, y1, 0.0, c->dth, y1, st));
-  OK_HIP(c, launch_stencil_axpy<TX, double, double>(g, x1, c->G, 0.0, -e2, y2, st));
-  OK_HIP(c, launch_stencil_axpy<TX, double, double>(g, x2, y2, 1.0, 0.0, y2, st));
+  // y1 = sA M x1 + dt th K x2;
+  // y2 = -M_E x1 - eps^2 K x1 + M x2 = -3G + M x1 - eps^2 K x1 + M x2
+  const double c0[4] = {c->sA, 0.0, 0.0, c->dth};
+  const double c1[4] = {1.0, -e2, 1.0, 0.0};
+  {
+    ProfScope ps(c, OK_K_NONE, (double)n * (2.0 * sizeof(TX) + 3.0 * 8.0), st);
+    OK_HIP(c, launch_stencil_lin2<TX>(g, x1, x2, nullptr, c->G, c0, c1, y1, y2, st));
+  }
   return OK_SUCCESS;
 }
 
@@ -417,12 +434,12 @@ int residual(ok_ctx* c, const double* u, const double* w, const double* un, cons
                                  p.theta, p.m, t1, t2, n, st));
   double* F1 = F;
   double* F2 = F + n;
-  OK_HIP(c, launch_stencil_axpy<double, double, double>(g, t1, nullptr, 1.0, 0.0, F1, st));
-  OK_HIP(c, launch_stencil_axpy<double, double, double>(g, t2, F1, 0.0, 1.0, F1, st));
+  const double a0[4] = {1.0, 0.0, 0.0, 1.0};  // F1 = M t1 + K t2
+  OK_HIP(c, launch_stencil_lin2<double>(g, t1, t2, nullptr, nullptr, a0, nullptr, F1, nullptr, st));
   OK_HIP(c, launch_element<double, double>(g, 1, u, (const double*)nullptr, nullptr, -1.0, 0.0,
                                            c->G, st));
-  OK_HIP(c, launch_stencil_axpy<double, double, double>(g, u, c->G, 0.0, -p.eps * p.eps, F2, st));
-  OK_HIP(c, launch_stencil_axpy<double, double, double>(g, w, F2, 1.0, 0.0, F2, st));
+  const double b0[4] = {1.0, 0.0, 0.0, -p.eps * p.eps};  // F2 = -N(u) + M w - eps^2 K u
+  OK_HIP(c, launch_stencil_lin2<double>(g, w, u, c->G, nullptr, b0, nullptr, F2, nullptr, st));
   if (norm) {
     OK_HIP(c, launch_dot_partial(F, F, 2 * n, c->pA, st));
     OK_HIP(c, launch_reduce_final(c->pA, c->nrm, st));
@@ -799,6 +816,99 @@ int ok_timestep(ok_ctx* c, double* u, double* w, int32_t nsteps, ok_stats* stats
   return status;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Time one candidate launch shape: one warm launch, then the best of three.
+template <class F>
+double time_best(hipStream_t st, F&& launch) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return 1e30;
+  if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return 1e30; }
+  double best = 1e30;
+  if (launch() == hipSuccess) {
+    for (int r = 0; r < 3; r++) {
+      (void)hipEventRecord(a, st);
+      if (launch() != hipSuccess) { best = 1e30; break; }
+      (void)hipEventRecord(b, st);
+      (void)hipEventSynchronize(b);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      best = std::min(best, (double)ms);
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return best;
+}
+
+template <class P>
+int autotune_impl(ok_ctx* c, hipStream_t st, int* entries) {
+  const int zcs[4] = {4, 8, 16, 32};
+  const int word = (int)sizeof(P);
+  for (int l = 0; l < c->L; l++) {
+    const Grid& g = c->lev[l];
+    if (l == c->L - 1 && c->L > 1) break;  // the coarsest level is a direct solve
+    P *x, *r, *d0, *d1;
+    if (l == 0) {
+      x = (P*)c->y; r = (P*)c->cr; d0 = (P*)c->cda; d1 = (P*)c->cdb;
+    } else {
+      x = (P*)c->mg[l][0]; r = (P*)c->mg[l][2]; d0 = (P*)c->mg[l][3]; d1 = (P*)c->mg[l][4];
+    }
+    const Op A = c->opA[l];
+    double best = 1e30;
+    int bi = 0, bz = 0;
+    for (int items = 1; items <= 8; items *= 2)
+      for (int zc : zcs) {
+        if (zc > g.nn && zc != 4) continue;
+        stencil_tune_set(g.dim, g.nn, 1, word, items, zc);
+        double t = time_best(st, [&]() {
+          return launch_cheb_step<P>(g, A, 0.5, 0.5, 1.0, false, x, r, d0, d1, st);
+        });
+        if (t < best) { best = t; bi = items; bz = zc; }
+      }
+    if (bi) { stencil_tune_set(g.dim, g.nn, 1, word, bi, bz); (*entries)++; }
+    else stencil_tune_set(g.dim, g.nn, 1, word, 0, 0);
+  }
+  // two-field kernels (Jacobian apply) on the finest grid, for Z's precision
+  {
+    const Grid& g = c->lev[0];
+    const P* z = (const P*)c->Z;
+    const double c0[4] = {1.0, 0.0, 0.0, 1.0}, c1[4] = {0.0, 1.0, 1.0, 0.0};
+    double best = 1e30;
+    int bi = 0, bz = 0;
+    for (int items = 1; items <= 4; items *= 2)
+      for (int zc : zcs) {
+        if (zc > g.nn && zc != 4) continue;
+        stencil_tune_set(g.dim, g.nn, 2, word, items, zc);
+        double t = time_best(st, [&]() {
+          return launch_stencil_lin2<P>(g, z, z + c->n, nullptr, c->G, c0, c1, c->T1,
+                                        c->T1 + c->n, st);
+        });
+        if (t < best) { best = t; bi = items; bz = zc; }
+      }
+    if (bi) { stencil_tune_set(g.dim, g.nn, 2, word, bi, bz); (*entries)++; }
+    else stencil_tune_set(g.dim, g.nn, 2, word, 0, 0);
+  }
+  return OK_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ok_autotune(ok_ctx* c, void* stream, int32_t* entries) {
+  if (!c) return OK_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  int n = 0;
+  int e = c->mixed ? autotune_impl<float>(c, st, &n) : autotune_impl<double>(c, st, &n);
+  if (entries) *entries = n;
+  if (e) return e;
+  OK_HIP(c, hipStreamSynchronize(st));
+  return OK_SUCCESS;
+}
+
 int ok_profile_enable(ok_ctx* c, int32_t kernel_class) {
   if (!c) return OK_E_INVALID;
   c->prof_class = kernel_class;
@@ -809,14 +919,16 @@ int ok_profile_enable(ok_ctx* c, int32_t kernel_class) {
 int ok_profile_read(ok_ctx* c, int64_t* launches, double* total_ms, double* bytes) {
   if (!c) return OK_E_INVALID;
   double ms = 0.0, by = 0.0;
+  int64_t cnt = 0;
   for (size_t i = 0; i < c->prof_used; i++) {
+    cnt += c->prof[i].count;
     (void)hipEventSynchronize(c->prof[i].b);
     float t = 0.f;
     (void)hipEventElapsedTime(&t, c->prof[i].a, c->prof[i].b);
     ms += t;
     by += c->prof[i].bytes;
   }
-  if (launches) *launches = (int64_t)c->prof_used;
+  if (launches) *launches = cnt;
   if (total_ms) *total_ms = ms;
   if (bytes) *bytes = by;
   c->prof_used = 0;

@@ -37,7 +37,13 @@ struct StencilShape {
   int nzc;        // z-chunks
   int blocks;     // nchunks*nzc
 };
-StencilShape stencil_shape(const Grid& g);
+StencilShape stencil_shape(const Grid& g, int nf, int word);
+// Launch-shape table of the stencil kernels, keyed by (dim, nodes per
+// direction, stenciled fields, bytes per stenciled word); items <= 0 removes
+// the entry (back to the heuristic).
+// Results do not depend on the shape: every node is computed by the same
+// arithmetic in the same order whatever the tiling.
+void stencil_tune_set(int dim, int nn, int nf, int word, int items, int zc);
 
 // Operator A = cm*M + ck*K on a grid and its Jacobi diagonal:
 // diag(A) at a node = dint * 2^-(number of coordinates on the boundary).
@@ -90,9 +96,18 @@ template <class TS, class TA, class TO>
 hipError_t launch_stencil_axpy(const Grid& g, const TS* s, const TA* add, double a, double b,
                                TO* out, hipStream_t st);
 
+// Two stenciled fields, up to two outputs (out1 may be null):
+//   out0 = add0 + c0[0] M s0 + c0[1] K s0 + c0[2] M s1 + c0[3] K s1
+//   out1 = add1 + c1[0] M s0 + c1[1] K s0 + c1[2] M s1 + c1[3] K s1
+template <class TS>
+hipError_t launch_stencil_lin2(const Grid& g, const TS* s0, const TS* s1, const double* add0,
+                               const double* add1, const double* c0, const double* c1,
+                               double* out0, double* out1, hipStream_t st);
+
 // Element quadrature kernels on the finest grid:
-// mode 0: out = alpha * M_E(u) x + beta * add       (add may be null)
-// mode 1: out = alpha * N(u)
+// mode 0: out = alpha * G(u,x) + beta * add,  G_i = int u^2 x phi_i  (add may be null)
+//         (M_E(u) x = 3 G(u,x) - M x)
+// mode 1: out = alpha * N(u),  N_i = int (u^3 - u) phi_i
 template <class TX, class TO>
 hipError_t launch_element(const Grid& g, int mode, const double* u, const TX* x,
                           const double* add, double alpha, double beta, TO* out, hipStream_t st);

@@ -86,6 +86,7 @@ def load():
     lib.ok_fgmres.argtypes = [vp, vp, vp, vp, P(i32), vp]
     lib.ok_newton_step.argtypes = [vp, vp, vp, vp, vp, P(NewtonInfo), vp]
     lib.ok_timestep.argtypes = [vp, vp, vp, i32, P(Stats), vp]
+    lib.ok_autotune.argtypes = [vp, vp, P(i32)]
     lib.ok_profile_enable.argtypes = [vp, i32]
     lib.ok_profile_read.argtypes = [vp, P(C.c_int64), P(d), P(d)]
     lib.ok_destroy.argtypes = [vp]
@@ -223,6 +224,11 @@ class Problem:
         if check:
             self._check(st, "ok_timestep")
         return stats
+
+    def autotune(self):
+        n = C.c_int32()
+        self._check(self.lib.ok_autotune(self.ctx, _stream(self.stream), C.byref(n)), "ok_autotune")
+        return n.value
 
     def profile_enable(self, kernel_class):
         self._check(self.lib.ok_profile_enable(self.ctx, kernel_class), "ok_profile_enable")

@@ -157,3 +157,23 @@ def test_newton_step_matches():
     assert st == 0 and st_o == 0 and info.fgmres_its == its_o
     assert abs(info.fnorm - fn_o) <= 1e-13 * fn_o
     assert relnorm(host(u), u1) < 1e-10 and relnorm(host(w), w1) < 1e-10
+
+
+@pytest.mark.parametrize("dim,n", [(2, 32), (3, 16)])
+@pytest.mark.parametrize("K", [1, 2, 3, 4])
+def test_chebyshev_iteration_counts(dim, n, K):
+    """Every branch of the Chebyshev driver: one iteration, first+last fused,
+    first+last, first+middle+last."""
+    say("cheb K", dim, n, K)
+    o, P = make(dim, n, CFG2, cheb_A_its=K)
+    r = uniform01(42, o.nodes) - 0.5
+    assert relmax(host(P.cheb_mass(dev(r))), o.cheb_mass(r)) < 1e-12
+
+
+@pytest.mark.parametrize("dim,n", [(2, 32), (3, 16)])
+@pytest.mark.parametrize("pre,post,cycles", [(1, 1, 2), (3, 1, 1), (1, 3, 2), (4, 4, 1)])
+def test_multigrid_smoothing_counts(dim, n, pre, post, cycles):
+    say("mg counts", dim, n, pre, post, cycles)
+    o, P = make(dim, n, CFG2, mg_pre=pre, mg_post=post)
+    b = uniform01(52, o.nodes) - 0.5
+    assert relmax(host(P.mg_apply(dev(b), cycles=cycles)), o.mg(b, cycles)) < 1e-12
