@@ -199,6 +199,39 @@ int ok_profile_read(ok_ctx *ctx, int64_t *launches, double *total_ms, double *by
  * number of table entries set.  Synchronises; run it outside timed regions. */
 int ok_autotune(ok_ctx *ctx, void *stream, int32_t *entries);
 
+/* ---- Batched sweeps: many independent problems in lockstep ----
+ * Instances whose parameters agree on (dim, n, precision and the solver
+ * counts) form a class; each class is one set of grouped kernel launches
+ * (grid = blocks of one instance x instances in the class), with the
+ * per-instance physics (eps, sigma, m, dt, theta, tolerances) in a device
+ * table and per-instance activity flags, so an instance that has converged
+ * costs nothing in later launches.  The solver state (u, w) of every instance
+ * lives in the batch workspace; ok_batch_set_state / ok_batch_get_state copy
+ * it in and out (device to device).  The arithmetic of each instance is the
+ * same as in a single-problem run: results are bitwise identical. */
+typedef struct ok_batch ok_batch;
+
+/* Workspace bytes for `count` instances with parameters params[0..count). */
+int ok_batch_workspace_bytes(const ok_params *params, int32_t count, size_t *bytes);
+/* Create a batch over the caller's workspace (256-byte aligned, at least
+ * ok_batch_workspace_bytes bytes).  Synchronises `stream`. */
+int ok_batch_create(const ok_params *params, int32_t count, void *d_ws, size_t ws_bytes,
+                    void *stream, ok_batch **out);
+/* Copy instance i's state in (from) or out (to) device arrays of n entries each. */
+int ok_batch_set_state(ok_batch *b, int32_t i, const double *d_u, const double *d_w,
+                       void *stream);
+int ok_batch_get_state(ok_batch *b, int32_t i, double *d_u, double *d_w, void *stream);
+/* nsteps timesteps of every instance (Newton and FGMRES in lockstep across
+ * all instances and classes).  stats (may be NULL): `count` entries.
+ * Returns the first failure of any instance (its stats carry its status). */
+int ok_batch_timestep(ok_batch *b, int32_t nsteps, ok_stats *stats, void *stream);
+/* ok_autotune for every class of the batch. */
+int ok_batch_autotune(ok_batch *b, void *stream, int32_t *entries);
+/* Number of classes (grouped launch sets) the instances fell into. */
+int ok_batch_classes(const ok_batch *b);
+int ok_batch_destroy(ok_batch *b);
+const char *ok_batch_last_error(const ok_batch *b);
+
 /* Destroy a context (frees host state only; the caller frees its memory). */
 int ok_destroy(ok_ctx *ctx);
 

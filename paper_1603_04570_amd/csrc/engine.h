@@ -1,0 +1,123 @@
+// Host engine of libok.so: a class of B instances that share the grid and the
+// precision, its device memory layout, and the lockstep solver operations
+// (preconditioner, Jacobian, residual, FGMRES, Newton, timestep) over groups
+// of classes.  A single solve is one class with B = 1.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "ok_internal.h"
+
+namespace okd {
+
+// Profiling of one kernel class with HIP events on the launch stream.
+struct ProfPair {
+  hipEvent_t a, b;
+  double bytes;
+  int count;  // kernel launches between the two events
+};
+struct Prof {
+  int cls = OK_K_NONE;
+  bool capturing = false;  // no events while a graph is being captured
+  std::vector<ProfPair> ev;
+  size_t used = 0;
+  ~Prof();
+};
+
+// Per-instance results of a group operation.
+struct InstOut {
+  int status = 0;      // ok_status of this instance's last operation
+  int fgmres_its = 0;  // FGMRES iterations of the last linear solve
+  int restarts = 0;
+  double fnorm = 0.0;  // ||F|| of the last residual evaluation
+  double lin_res = 0.0;
+};
+
+struct ClassCtx {
+  // ---- configuration (common to the class) ----
+  ok_params shape{};  // dim, n, precision, solver counts (physics per instance below)
+  int B = 0;          // instances
+  int dim = 0, L = 0, m = 0;
+  bool mixed = false;
+  size_t psz = 8;  // bytes per preconditioner word
+  int64_t n = 0;   // finest nodes per instance
+  Grid lev[kMaxLevels]{};
+  std::vector<ok_params> ip;      // per-instance parameters
+  std::vector<InstCoef> hcoef;    // host copy of the constants table
+  // ---- device memory (SoA: every array is [instance][length]) ----
+  InstCoef* coef = nullptr;
+  int *act = nullptr, *part = nullptr, *incyc = nullptr;  // [B] flags
+  double *V = nullptr, *X = nullptr, *Bv = nullptr, *T1 = nullptr;
+  double *un = nullptr, *wn = nullptr, *G = nullptr, *su = nullptr, *sw = nullptr;
+  double *pA = nullptr, *pB = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr;
+  double *g = nullptr, *y = nullptr, *kr = nullptr, *nrm = nullptr;
+  void *Z = nullptr, *zt = nullptr;
+  void *cr = nullptr, *cda = nullptr, *cdb = nullptr, *yv = nullptr, *tv = nullptr, *sv = nullptr;
+  void* mg[kMaxLevels][5]{};  // x, b, r, d, d' per level
+  // ---- host mirrors ----
+  std::vector<int> h_act, h_part;
+  std::vector<double> h_kr, h_nrm;
+  std::vector<InstOut> out;
+  std::vector<int> nits;  // Newton iterations of the current timestep, per instance
+  Prof* prof = nullptr;  // shared profiling state (may be null)
+  std::string* err = nullptr;
+
+  int64_t n2() const { return 2 * n; }
+  Batch batch(const int* flags) const { return Batch{B, coef, flags}; }
+};
+
+// Parameter checks shared by every entry point.
+int validate_params(const ok_params* p, std::string& why);
+int levels_for(const ok_params* p);
+// Two parameter sets can share a class (same grid, precision and solver counts).
+bool same_class(const ok_params& a, const ok_params& b);
+
+// Layout: bytes of device memory for a class of B instances of `shape`.
+size_t class_bytes(const ok_params& shape, int B, bool with_state);
+// Carve a class out of `base` (256-byte aligned) and upload its constants.
+int class_init(ClassCtx& c, const ok_params* ps, int B, char* base, bool with_state,
+               hipStream_t st, std::string& err);
+
+// ---- group operations (lockstep over all classes of a group) ----
+using Group = std::vector<ClassCtx*>;
+// y = J(u) x  (u: n, x/y: 2n per instance; FP64 x)
+int jac_apply_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const double> x,
+                Vec<double> y, hipStream_t st);
+// z = P^-1 r (FP64 in/out; mixed classes stage through FP32)
+int precond_apply_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const double> r,
+                    Vec<double> z, hipStream_t st);
+int cheb_mass_d(ClassCtx& c, const int* flags, Vec<const double> r, Vec<double> x, hipStream_t st);
+int mg_apply_d(ClassCtx& c, const int* flags, Vec<const double> b, Vec<double> x, int cycles,
+               hipStream_t st);
+// F and ||F|| per instance (norms in c.out[i].fnorm); F may be null (uses Bv).
+int residual_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const double> w,
+               Vec<const double> un, Vec<const double> wn, Vec<double> F, hipStream_t st);
+// Solve J x = b by FGMRES for the instances with part[i] set (host masks in
+// h_part of each class).  Results per instance in out[].
+int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,
+                 const std::vector<Vec<const double>>& b, const std::vector<Vec<double>>& x,
+                 hipStream_t st);
+// Newton until ||F|| <= atol for the participating instances (h_part);
+// un/wn: previous time level.  Records per-instance Newton and FGMRES counts.
+struct NewtonLog {
+  std::vector<std::vector<int>> its;       // per instance: FGMRES its per Newton iteration
+  std::vector<std::vector<double>> fnorm;  // per instance: ||F|| per residual evaluation
+};
+int newton_group(const Group& grp, const std::vector<Vec<double>>& u,
+                 const std::vector<Vec<double>>& w, const std::vector<Vec<const double>>& un,
+                 const std::vector<Vec<const double>>& wn, std::vector<NewtonLog>& log,
+                 hipStream_t st);
+// At most max_iters Newton updates (max_iters < 0: until every participating
+// instance stops).  Each update is preceded by the residual test; a bounded
+// call ends right after its last update (status 1 = still iterating).
+int newton_group_iters(const Group& grp, const std::vector<Vec<double>>& u,
+                       const std::vector<Vec<double>>& w, const std::vector<Vec<const double>>& un,
+                       const std::vector<Vec<const double>>& wn, std::vector<NewtonLog>& log,
+                       int max_iters, hipStream_t st);
+// Upload host flags (h_part) to the device part/act arrays.
+int push_part(ClassCtx& c, hipStream_t st);
+// Tile autotuner over the class's grids.
+int autotune_class(ClassCtx& c, hipStream_t st, int* entries);
+
+}  // namespace okd

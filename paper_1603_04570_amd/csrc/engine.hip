@@ -1,0 +1,975 @@
+// Host engine: class layout, per-instance constants, and the lockstep solver
+// operations.  Every vector operation runs in the kernels of this library;
+// the host only sequences launches and reads back a few flags and norms.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace okd {
+
+Prof::~Prof() {
+  for (auto& e : ev) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+}
+
+namespace {
+
+int set_err(std::string* err, int code, const std::string& msg) {
+  if (err) *err = msg;
+  return code;
+}
+
+#define OKE(c, ...)                                                                          \
+  do {                                                                                       \
+    hipError_t e_ = (__VA_ARGS__);                                                           \
+    if (e_ != hipSuccess)                                                                    \
+      return set_err((c).err, OK_E_HIP,                                                      \
+                     std::string(#__VA_ARGS__).substr(0, 60) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// HIP-event bracket around launches of one kernel class (see ok_profile_*).
+struct ProfScope {
+  Prof* p;
+  ProfPair* pp = nullptr;
+  hipStream_t st;
+  ProfScope(const ClassCtx& c, int cls, double bytes, hipStream_t s, int count = 1)
+      : p(c.prof), st(s) {
+    if (!p || p->capturing || cls == OK_K_NONE) return;
+    bool on = (p->cls == cls) || (p->cls == OK_K_STENCIL_ANY && cls != OK_K_KRYLOV &&
+                                  cls != OK_K_ELEMENT);
+    if (!on) return;
+    if (p->used == p->ev.size()) {
+      ProfPair q{};
+      (void)hipEventCreate(&q.a);
+      (void)hipEventCreate(&q.b);
+      p->ev.push_back(q);
+    }
+    pp = &p->ev[p->used++];
+    pp->bytes = bytes;
+    pp->count = count;
+    (void)hipEventRecord(pp->a, st);
+  }
+  ~ProfScope() {
+    if (pp) (void)hipEventRecord(pp->b, st);
+  }
+};
+
+// Bump allocator over a 256-byte aligned region (base == nullptr: size only).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// D^-1 (M + alpha K) on the DCT-I mode with cosines c_d (multilinear in c).
+double dct_lambda(const Grid& g, double alpha, const double* c) {
+  double h = g.h, num = 1.0, sk = 0.0;
+  for (int d = 0; d < g.dim; d++) num *= (h / 3.0) * (2.0 + c[d]);
+  for (int d = 0; d < g.dim; d++) {
+    double t = (2.0 / h) * (1.0 - c[d]);
+    for (int e = 0; e < g.dim; e++)
+      if (e != d) t *= (h / 3.0) * (2.0 + c[e]);
+    sk += t;
+  }
+  double mi = 2.0 * h / 3.0;
+  double den = std::pow(mi, g.dim) + alpha * g.dim * (2.0 / h) * std::pow(mi, g.dim - 1);
+  return (num + alpha * sk) / den;
+}
+
+// Fill a LevelCoef: operator cm M + ck K on grid g with Chebyshev interval [lo, hi].
+void level_coef(LevelCoef& L, const Grid& g, double cm, double ck, double lo, double hi) {
+  double mi = 2.0 * g.h / 3.0, ki = 2.0 / g.h;
+  double dm = 1.0, dk = g.dim * ki;
+  for (int d = 0; d < g.dim; d++) dm *= mi;
+  for (int d = 0; d < g.dim - 1; d++) dk *= mi;
+  L.cm = cm;
+  L.ck = ck;
+  L.dinv = 1.0 / (cm * dm + ck * dk);
+  // Saad, Alg. 12.1: theta, delta, sigma1; rho_0 = 1/sigma1,
+  // rho_{k+1} = 1/(2 sigma1 - rho_k), c1 = rho_{k+1} rho_k, c2 = 2 rho_{k+1}/delta.
+  double th = 0.5 * (hi + lo), de = 0.5 * (hi - lo), s1 = th / de;
+  L.it = 1.0 / th;
+  double rho = 1.0 / s1;
+  for (int k = 0; k < kMaxCheb; k++) {
+    double rho1 = 1.0 / (2.0 * s1 - rho);
+    L.c1[k] = rho1 * rho;
+    L.c2[k] = 2.0 * rho1 / de;
+    rho = rho1;
+  }
+}
+
+// Smoother interval of D^-1 (M + alpha K): the largest eigenvalue (a corner of
+// the cosine box) and the smallest over the upper half of the spectrum
+// (vertices with some cosine in {-1, 0}); exact for Q1 on uniform grids.
+void smoother_interval(const Grid& g, double alpha, double& lo, double& hi) {
+  lo = 1e300;
+  hi = -1e300;
+  int nv = 1;
+  for (int d = 0; d < g.dim; d++) nv *= 3;
+  for (int s = 0; s < nv; s++) {
+    int t[3] = {s % 3, (s / 3) % 3, s / 9};
+    double c[3];
+    bool corner = true, high = false;
+    for (int d = 0; d < g.dim; d++) {
+      c[d] = t[d] == 0 ? -1.0 : (t[d] == 1 ? 0.0 : 1.0);
+      if (t[d] == 1) corner = false;
+      if (t[d] <= 1) high = true;
+    }
+    double l = dct_lambda(g, alpha, c);
+    if (corner && l > hi) hi = l;
+    if (high && l < lo) lo = l;
+  }
+}
+
+void inst_coef(InstCoef& C, const ok_params& p, const Grid* lev, int L) {
+  std::memset(&C, 0, sizeof(C));
+  // Sec. 2: c = dt theta / (1 + dt theta sigma), S^ = M + eps sqrt(c) K.
+  C.dth = p.dt * p.theta;
+  C.sA = 1.0 + C.dth * p.sigma;
+  C.inv_sA = 1.0 / C.sA;
+  const double cc = C.dth / C.sA;
+  C.alpha = p.eps * std::sqrt(cc);
+  C.e2 = p.eps * p.eps;
+  C.dt = p.dt;
+  C.sigma = p.sigma;
+  C.theta = p.theta;
+  C.m = p.m;
+  C.rtol = p.gmres_rtol;
+  C.atol = p.newton_atol;
+  // D^-1 M has spectrum [2^-d, (3/2)^d].
+  level_coef(C.mass, lev[0], 1.0, 0.0, std::pow(0.5, p.dim), std::pow(1.5, p.dim));
+  for (int l = 0; l < L; l++) {
+    double lo, hi;
+    smoother_interval(lev[l], C.alpha, lo, hi);
+    level_coef(C.lev[l], lev[l], 1.0, C.alpha, lo, hi);
+  }
+}
+
+void carve(ClassCtx& c, char* base, bool with_state, size_t* total) {
+  Carver cv{base};
+  const int B = c.B, m = c.m;
+  const int64_t n = c.n, n2 = 2 * n;
+  const size_t ps = c.psz;
+  c.coef = cv.take<InstCoef>(B);
+  c.act = cv.take<int>(B);
+  c.part = cv.take<int>(B);
+  c.incyc = cv.take<int>(B);
+  c.V = cv.take<double>((size_t)B * (m + 1) * n2);
+  c.Z = cv.take<char>((size_t)B * m * n2 * ps);
+  c.X = cv.take<double>((size_t)B * n2);
+  c.Bv = cv.take<double>((size_t)B * n2);
+  c.T1 = cv.take<double>((size_t)B * n2);
+  c.un = cv.take<double>((size_t)B * n);
+  c.wn = cv.take<double>((size_t)B * n);
+  c.G = cv.take<double>((size_t)B * n);
+  c.su = with_state ? cv.take<double>((size_t)B * n) : nullptr;
+  c.sw = with_state ? cv.take<double>((size_t)B * n) : nullptr;
+  c.zt = c.mixed ? cv.take<char>((size_t)B * n2 * ps) : nullptr;
+  c.cr = cv.take<char>((size_t)B * n * ps);
+  c.cda = cv.take<char>((size_t)B * n * ps);
+  c.cdb = cv.take<char>((size_t)B * n * ps);
+  c.yv = cv.take<char>((size_t)B * n * ps);
+  c.tv = cv.take<char>((size_t)B * n * ps);
+  c.sv = cv.take<char>((size_t)B * n * ps);
+  for (int l = 0; l < c.L; l++) {
+    const int64_t nl = c.lev[l].nodes;
+    for (int k = 0; k < 5; k++)
+      c.mg[l][k] = (l == 0 && k < 2) ? nullptr : cv.take<char>((size_t)B * nl * ps);
+  }
+  c.pA = cv.take<double>((size_t)B * kMaxRedBlocks);
+  c.pB = cv.take<double>((size_t)B * kMaxRedBlocks);
+  c.H = cv.take<double>((size_t)B * (m + 1) * m);
+  c.cs = cv.take<double>((size_t)B * (m + 1));
+  c.sn = cv.take<double>((size_t)B * (m + 1));
+  c.g = cv.take<double>((size_t)B * (m + 1));
+  c.y = cv.take<double>((size_t)B * (m + 1));
+  c.kr = cv.take<double>((size_t)B * 8);
+  c.nrm = cv.take<double>((size_t)B * 8);
+  *total = (cv.off + 255) & ~(size_t)255;
+}
+
+void setup_shape(ClassCtx& c, const ok_params& shape, int B) {
+  c.shape = shape;
+  c.B = B;
+  c.dim = shape.dim;
+  c.L = levels_for(&shape);
+  c.m = shape.gmres_restart;
+  c.mixed = (shape.precision == OK_MIXED);
+  c.psz = c.mixed ? sizeof(float) : sizeof(double);
+  int nl = shape.n;
+  for (int l = 0; l < c.L; l++) {
+    c.lev[l] = make_grid(shape.dim, nl);
+    nl /= 2;
+  }
+  c.n = c.lev[0].nodes;
+}
+
+// ---------------------------------------------------------------------------
+// Strides of the SoA arrays.
+// ---------------------------------------------------------------------------
+inline int64_t sV(const ClassCtx& c) { return (int64_t)(c.m + 1) * c.n2(); }
+inline int64_t sZ(const ClassCtx& c) { return (int64_t)c.m * c.n2(); }
+inline int64_t sH(const ClassCtx& c) { return (int64_t)(c.m + 1) * c.m; }
+inline int64_t sM(const ClassCtx& c) { return (int64_t)c.m + 1; }
+
+template <class P>
+Vec<P> pvec(void* p, int64_t s) {
+  return Vec<P>{(P*)p, s};
+}
+template <class T>
+Vec<const T> cst(Vec<T> v) {
+  return Vec<const T>{v.p, v.s};
+}
+template <class T>
+Vec<T> off(Vec<T> v, int64_t o) {
+  return Vec<T>{v.p + o, v.s};
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev drivers (Saad, Alg. 12.1); coefficients come from the constants
+// table, iteration k uses c1[k], c2[k].  `cls` tags launches for profiling;
+// `step_cls` the middle iterations, which are timed as one contiguous run.
+// ---------------------------------------------------------------------------
+template <class TB, class P>
+int cheb_zero(ClassCtx& c, const int* fl, int cls, int step_cls, const Grid& g, int lev, int osc,
+              int K, Vec<const TB> b, Vec<P> x, Vec<P> r, Vec<P> da, Vec<P> db, hipStream_t st) {
+  const Batch B = c.batch(fl);
+  const double w = (double)c.psz * g.nodes * c.B, wb = (double)sizeof(TB) * g.nodes * c.B;
+  if (K > kMaxCheb) return set_err(c.err, OK_E_INVALID, "too many Chebyshev iterations");
+  if (K <= 1) {
+    ProfScope ps(c, cls, wb + w, st);
+    OKE(c, launch_cheb_one<TB, P>(g, B, lev, osc, b, x, st));
+    return OK_SUCCESS;
+  }
+  {
+    ProfScope ps(c, cls, wb + (K == 2 ? w : 3.0 * w), st);
+    OKE(c, launch_cheb_first<TB, P>(g, B, lev, osc, K == 2, b, x, r, da, st));
+  }
+  if (K == 2) return OK_SUCCESS;
+  Vec<P> dc = da, dn = db;
+  {
+    const int mid = K > 3 ? K - 3 : 0;
+    ProfScope ps(c, step_cls, 6.0 * w * mid, st, mid);
+    for (int k = 1; k <= K - 3; k++) {
+      OKE(c, launch_cheb_step<P>(g, B, lev, k, osc, false, x, r, cst(dc), dn, st));
+      std::swap(dc, dn);
+    }
+  }
+  {
+    ProfScope ps(c, cls, 4.0 * w, st);
+    OKE(c, launch_cheb_step<P>(g, B, lev, K - 2, osc, true, x, r, cst(dc), dn, st));
+  }
+  return OK_SUCCESS;
+}
+
+template <class P>
+int cheb_from(ClassCtx& c, const int* fl, int cls, const Grid& g, int lev, int K, Vec<const P> b,
+              Vec<P> x, Vec<P> r, Vec<P> da, Vec<P> db, hipStream_t st) {
+  const Batch B = c.batch(fl);
+  const double w = (double)c.psz * g.nodes * c.B;
+  if (K > kMaxCheb + 1) return set_err(c.err, OK_E_INVALID, "too many Chebyshev iterations");
+  {
+    ProfScope ps(c, cls, 4.0 * w, st);
+    OKE(c, launch_cheb_start<P>(g, B, lev, b, cst(x), r, da, st));
+  }
+  if (K <= 1) {
+    OKE(c, launch_add_inplace<P>(B, x, cst(da), g.nodes, st));
+    return OK_SUCCESS;
+  }
+  Vec<P> dc = da, dn = db;
+  for (int k = 0; k <= K - 2; k++) {
+    const bool last = (k == K - 2);
+    ProfScope ps(c, cls, last ? 4.0 * w : 6.0 * w, st);
+    OKE(c, launch_cheb_step<P>(g, B, lev, k, CF_ONE, last, x, r, cst(dc), dn, st));
+    std::swap(dc, dn);
+  }
+  return OK_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------
+// Multigrid V-cycle for S^ = M + alpha K (Sec. 2 after eq. (schurinv)).
+// ---------------------------------------------------------------------------
+template <class P>
+int mg_vcycle(ClassCtx& c, const int* fl, int l, Vec<const P> b, Vec<P> x, bool zero_start,
+              hipStream_t st) {
+  const Grid& g = c.lev[l];
+  const Batch B = c.batch(fl);
+  if (l == c.L - 1) {
+    OKE(c, launch_coarse_solve<P>(g, B, b, x, st));
+    return OK_SUCCESS;
+  }
+  const int64_t nl = g.nodes;
+  Vec<P> r = pvec<P>(c.mg[l][2], nl), da = pvec<P>(c.mg[l][3], nl), db = pvec<P>(c.mg[l][4], nl);
+  const int cls = (l == 0) ? OK_K_MG_SMOOTH : OK_K_NONE;
+  int e = zero_start
+              ? cheb_zero<P, P>(c, fl, cls, cls, g, l, CF_ONE, c.shape.mg_pre, b, x, r, da, db, st)
+              : cheb_from<P>(c, fl, cls, g, l, c.shape.mg_pre, b, x, r, da, db, st);
+  if (e) return e;
+  {
+    ProfScope ps(c, cls, 3.0 * c.psz * nl * c.B, st);
+    OKE(c, launch_resid<P>(g, B, l, b, cst(x), r, st));
+  }
+  const Grid& gc = c.lev[l + 1];
+  Vec<P> xc = pvec<P>(c.mg[l + 1][0], gc.nodes), bc = pvec<P>(c.mg[l + 1][1], gc.nodes);
+  OKE(c, launch_restrict<P>(g, gc, B, cst(r), bc, st));
+  e = mg_vcycle<P>(c, fl, l + 1, cst(bc), xc, true, st);
+  if (e) return e;
+  OKE(c, launch_prolong_add<P>(g, gc, B, cst(xc), x, st));
+  return cheb_from<P>(c, fl, cls, g, l, c.shape.mg_post, b, x, r, da, db, st);
+}
+
+template <class P>
+int mg_apply(ClassCtx& c, const int* fl, Vec<const P> b, Vec<P> x, int cycles, hipStream_t st) {
+  for (int k = 0; k < cycles; k++) {
+    int e = mg_vcycle<P>(c, fl, 0, b, x, k == 0, st);
+    if (e) return e;
+  }
+  return OK_SUCCESS;
+}
+
+// z = [z1; z2] = P^-1 [r1; r2], eq. (prec) with S~^-1 = S^^-1 M S^^-1.
+template <class P>
+int precond(ClassCtx& c, const int* fl, Vec<const double> u, Vec<const double> r, Vec<P> z,
+            hipStream_t st) {
+  const Grid& g = c.lev[0];
+  const Batch B = c.batch(fl);
+  const int64_t n = c.n;
+  Vec<const double> r1 = r, r2 = off(r, n);
+  Vec<P> z1 = z, z2 = off(z, n);
+  Vec<P> cr = pvec<P>(c.cr, n), cda = pvec<P>(c.cda, n), cdb = pvec<P>(c.cdb, n);
+  // z1 = A~^-1 r1: Chebyshev on M, scaled by 1/(1 + dt th sigma).
+  int e = cheb_zero<double, P>(c, fl, OK_K_NONE, OK_K_CHEB_MASS, g, -1, CF_INV_SA,
+                               c.shape.cheb_A_its, r1, z1, cr, cda, cdb, st);
+  if (e) return e;
+  // y = r2 - C z1 = r2 + eps^2 K z1 + M_E(u) z1, M_E z1 = 3G - M z1 (G in FP64).
+  Vec<double> G = vec(c.G, n);
+  {
+    ProfScope ps(c, OK_K_ELEMENT, (double)n * c.B * (8.0 + 8.0 + c.psz + 8.0), st);
+    OKE(c, launch_element<P, double>(g, B, 0, u, cst(z1), r2, 3.0, 1.0, G, st));
+  }
+  Vec<P> y = pvec<P>(c.yv, n), t = pvec<P>(c.tv, n), s = pvec<P>(c.sv, n);
+  OKE(c, launch_stencil_axpy<P, double, P>(g, B, cst(z1), cst(G), -1.0, CF_ONE, 1.0, CF_E2, y, st));
+  if (c.shape.schur_richardson > 1)
+    return set_err(c.err, OK_E_INVALID, "schur_richardson > 1 is not built on the GPU");
+  // z2 = S^^-1 M S^^-1 y
+  e = mg_apply<P>(c, fl, cst(y), t, c.shape.mg_cycles, st);
+  if (e) return e;
+  OKE(c, launch_stencil_axpy<P, P, P>(g, B, cst(t), Vec<const P>{nullptr, 0}, 1.0, CF_ONE, 0.0,
+                                      CF_ONE, s, st));
+  return mg_apply<P>(c, fl, cst(s), z2, c.shape.mg_cycles, st);
+}
+
+// y = J(u) x, eq. (newton); x of type TX (2n), y FP64 (2n).
+template <class TX>
+int jac(ClassCtx& c, const int* fl, Vec<const double> u, Vec<const TX> x, Vec<double> y,
+        hipStream_t st) {
+  const Grid& g = c.lev[0];
+  const Batch B = c.batch(fl);
+  const int64_t n = c.n;
+  Vec<double> G = vec(c.G, n);
+  {
+    ProfScope ps(c, OK_K_ELEMENT, (double)n * c.B * (8.0 + sizeof(TX) + 8.0), st);
+    OKE(c, launch_element<TX, double>(g, B, 0, u, x, Vec<const double>{nullptr, 0}, -3.0, 0.0,
+                                      G, st));
+  }
+  // y1 = sA M x1 + dt th K x2;  y2 = -M_E x1 - eps^2 K x1 + M x2 = -3G + M x1 - eps^2 K x1 + M x2
+  const double cf[2][4] = {{1.0, 0.0, 0.0, 1.0}, {1.0, -1.0, 1.0, 0.0}};
+  const int ff[2][4] = {{CF_SA, CF_ONE, CF_ONE, CF_DTH}, {CF_ONE, CF_E2, CF_ONE, CF_ONE}};
+  OKE(c, launch_stencil_lin2<TX>(g, B, x, off(x, n), Vec<const double>{nullptr, 0}, cst(G), cf, ff,
+                                 y, off(y, n), st));
+  return OK_SUCCESS;
+}
+
+template <class T>
+int d2h(ClassCtx& c, std::vector<T>& h, const T* d, size_t count, hipStream_t st) {
+  h.resize(count);
+  OKE(c, hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, st));
+  return OK_SUCCESS;
+}
+
+int sync(ClassCtx& c, hipStream_t st) {
+  OKE(c, hipStreamSynchronize(st));
+  return OK_SUCCESS;
+}
+
+int push_flags(ClassCtx& c, int* dflags, const std::vector<int>& h, hipStream_t st) {
+  OKE(c, hipMemcpyAsync(dflags, h.data(), sizeof(int) * c.B, hipMemcpyHostToDevice, st));
+  // The host vector may change right after this call returns: make the copy complete.
+  OKE(c, hipStreamSynchronize(st));
+  return OK_SUCCESS;
+}
+
+// One FGMRES iteration j (Arnoldi step + Givens) for the active instances.
+template <class P>
+int fgmres_iteration(ClassCtx& c, int j, Vec<const double> u, hipStream_t st) {
+  const int64_t n2 = c.n2();
+  const Batch B = c.batch(c.act);
+  Vec<double> Vj = Vec<double>{c.V + (int64_t)j * n2, sV(c)};
+  Vec<double> W = Vec<double>{c.V + (int64_t)(j + 1) * n2, sV(c)};
+  Vec<P> Zj = Vec<P>{(P*)c.Z + (int64_t)j * n2, sZ(c)};
+  int e = precond<P>(c, c.act, u, cst(Vj), Zj, st);
+  if (e) return e;
+  e = jac<P>(c, c.act, u, cst(Zj), W, st);
+  if (e) return e;
+  Vec<double> pin = vec(c.pA, (int64_t)kMaxRedBlocks), pout = vec(c.pB, (int64_t)kMaxRedBlocks);
+  {
+    ProfScope ps(c, OK_K_KRYLOV, 16.0 * n2 * c.B, st);
+    OKE(c, launch_dot_partial(B, cst(W), Vec<const double>{c.V, sV(c)}, n2, pin, st));
+  }
+  for (int i = 0; i <= j; i++) {
+    Vec<const double> vi{c.V + (int64_t)i * n2, sV(c)};
+    Vec<const double> vn{(i < j) ? c.V + (int64_t)(i + 1) * n2 : nullptr, sV(c)};
+    ProfScope ps(c, OK_K_KRYLOV, (i < j ? 32.0 : 24.0) * n2 * c.B, st);
+    OKE(c, launch_mgs_step(B, W, vi, vn, n2, cst(pin), pout,
+                           Vec<double>{c.H + (int64_t)j * (c.m + 1) + i, sH(c)}, st));
+    std::swap(pin, pout);
+  }
+  OKE(c, launch_givens(B, c.act, j, c.m, vec(c.H, sH(c)), vec(c.cs, sM(c)), vec(c.sn, sM(c)),
+                       vec(c.g, sM(c)), cst(pin), n2, vec(c.kr, (int64_t)8), st));
+  OKE(c, launch_scale_by(B, cst(W), W, Vec<const double>{c.kr, 8}, n2, st));
+  return OK_SUCCESS;
+}
+
+template <class P>
+int lsq_update(ClassCtx& c, Vec<double> x, hipStream_t st) {
+  const Batch B = c.batch(c.incyc);
+  OKE(c, launch_lsq_update<P>(B, c.m, Vec<const double>{c.H, sH(c)},
+                              Vec<const double>{c.g, sM(c)}, vec(c.y, sM(c)),
+                              Vec<const double>{c.kr, 8}, Vec<const P>{(const P*)c.Z, sZ(c)},
+                              c.n2(), x, c.n2(), st));
+  return OK_SUCCESS;
+}
+
+bool any(const std::vector<int>& v) {
+  for (int a : v)
+    if (a) return true;
+  return false;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Parameters and layout
+// ---------------------------------------------------------------------------
+int levels_for(const ok_params* p) {
+  if (p->mg_levels > 0) return p->mg_levels;
+  int L = 1, n = p->n;
+  while (n > 8 && n % 2 == 0 && L < kMaxLevels) {
+    n /= 2;
+    L++;
+  }
+  return L;
+}
+
+int validate_params(const ok_params* p, std::string& why) {
+  auto bad = [&](const char* w) {
+    why = w;
+    return OK_E_INVALID;
+  };
+  if (!p) return bad("null params");
+  if (p->dim != 2 && p->dim != 3) return bad("dim must be 2 or 3");
+  if (p->n < 2) return bad("n must be >= 2");
+  if (p->dim == 3 && p->n > 512) return bad("3D n must be <= 512");
+  if (p->dim == 2 && p->n > 4096) return bad("2D n must be <= 4096");
+  if (!(p->eps > 0) || !std::isfinite(p->eps)) return bad("eps must be > 0");
+  if (!(p->sigma >= 0) || !std::isfinite(p->sigma)) return bad("sigma must be >= 0");
+  if (!(std::fabs(p->m) < 1)) return bad("|m| must be < 1");
+  if (!(p->dt > 0) || !std::isfinite(p->dt)) return bad("dt must be > 0");
+  if (!(p->theta > 0 && p->theta <= 1)) return bad("theta must be in (0,1]");
+  if (p->precision != OK_FP64 && p->precision != OK_MIXED) return bad("bad precision");
+  if (p->gmres_restart < 1 || p->gmres_restart > 64) return bad("gmres_restart in 1..64");
+  if (p->gmres_max_restarts < 0) return bad("gmres_max_restarts >= 0");
+  if (!(p->gmres_rtol > 0)) return bad("gmres_rtol > 0");
+  if (!(p->newton_atol >= 0)) return bad("newton_atol >= 0");
+  if (p->newton_max_it < 0) return bad("newton_max_it >= 0");
+  if (p->cheb_A_its < 1 || p->cheb_A_its > kMaxCheb) return bad("cheb_A_its in 1..32");
+  if (p->schur_richardson < 1) return bad("schur_richardson >= 1");
+  if (p->mg_pre < 1 || p->mg_post < 1 || p->mg_cycles < 1) return bad("mg_pre/post/cycles >= 1");
+  if (p->mg_pre > kMaxCheb || p->mg_post > kMaxCheb) return bad("mg_pre/post <= 32");
+  int L = levels_for(p);
+  if (L < 1 || L > kMaxLevels) return bad("bad mg_levels");
+  if (p->n % (1 << (L - 1))) return bad("n not divisible by 2^(levels-1)");
+  int nc = p->n >> (L - 1);
+  int64_t cn = (int64_t)(nc + 1) * (nc + 1) * (p->dim == 3 ? (nc + 1) : 1);
+  if (nc < 1 || cn > 1024 || nc + 1 > 64) return bad("coarsest grid must have <= 1024 nodes");
+  return OK_SUCCESS;
+}
+
+bool same_class(const ok_params& a, const ok_params& b) {
+  return a.dim == b.dim && a.n == b.n && a.precision == b.precision &&
+         a.gmres_restart == b.gmres_restart && a.gmres_max_restarts == b.gmres_max_restarts &&
+         a.newton_max_it == b.newton_max_it && a.cheb_A_its == b.cheb_A_its &&
+         a.schur_richardson == b.schur_richardson && levels_for(&a) == levels_for(&b) &&
+         a.mg_pre == b.mg_pre && a.mg_post == b.mg_post && a.mg_cycles == b.mg_cycles;
+}
+
+size_t class_bytes(const ok_params& shape, int B, bool with_state) {
+  ClassCtx c;
+  setup_shape(c, shape, B);
+  size_t total = 0;
+  carve(c, nullptr, with_state, &total);
+  return total;
+}
+
+int class_init(ClassCtx& c, const ok_params* ps, int B, char* base, bool with_state,
+               hipStream_t st, std::string& err) {
+  setup_shape(c, ps[0], B);
+  size_t total = 0;
+  carve(c, base, with_state, &total);
+  c.ip.assign(ps, ps + B);
+  c.hcoef.resize(B);
+  for (int i = 0; i < B; i++) inst_coef(c.hcoef[i], ps[i], c.lev, c.L);
+  c.h_act.assign(B, 0);
+  c.h_part.assign(B, 0);
+  c.out.assign(B, InstOut{});
+  c.nits.assign(B, 0);
+  hipError_t e = hipMemcpyAsync(c.coef, c.hcoef.data(), sizeof(InstCoef) * B,
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(c.act, 0, sizeof(int) * 3 * B, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    err = std::string("class setup: ") + hipGetErrorString(e);
+    return OK_E_HIP;
+  }
+  return OK_SUCCESS;
+}
+
+int push_part(ClassCtx& c, hipStream_t st) { return push_flags(c, c.part, c.h_part, st); }
+
+// ---------------------------------------------------------------------------
+// Single operations (FP64 in/out)
+// ---------------------------------------------------------------------------
+int jac_apply_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const double> x,
+                Vec<double> y, hipStream_t st) {
+  return jac<double>(c, flags, u, x, y, st);
+}
+
+int precond_apply_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const double> r,
+                    Vec<double> z, hipStream_t st) {
+  if (!c.mixed) return precond<double>(c, flags, u, r, z, st);
+  Vec<float> zt = pvec<float>(c.zt, c.n2());
+  int e = precond<float>(c, flags, u, r, zt, st);
+  if (e) return e;
+  OKE(c, launch_copy_scale<float, double>(c.batch(flags), cst(zt), z, 1.0, c.n2(), st));
+  return OK_SUCCESS;
+}
+
+int cheb_mass_d(ClassCtx& c, const int* flags, Vec<const double> r, Vec<double> x,
+                hipStream_t st) {
+  const Grid& g = c.lev[0];
+  const int64_t n = c.n;
+  if (!c.mixed)
+    return cheb_zero<double, double>(c, flags, OK_K_NONE, OK_K_CHEB_MASS, g, -1, CF_ONE,
+                                     c.shape.cheb_A_its, r, x, pvec<double>(c.cr, n),
+                                     pvec<double>(c.cda, n), pvec<double>(c.cdb, n), st);
+  Vec<float> xf = pvec<float>(c.zt, c.n2());
+  int e = cheb_zero<double, float>(c, flags, OK_K_NONE, OK_K_CHEB_MASS, g, -1, CF_ONE,
+                                   c.shape.cheb_A_its, r, xf, pvec<float>(c.cr, n),
+                                   pvec<float>(c.cda, n), pvec<float>(c.cdb, n), st);
+  if (e) return e;
+  OKE(c, launch_copy_scale<float, double>(c.batch(flags), cst(xf), x, 1.0, n, st));
+  return OK_SUCCESS;
+}
+
+int mg_apply_d(ClassCtx& c, const int* flags, Vec<const double> b, Vec<double> x, int cycles,
+               hipStream_t st) {
+  if (!c.mixed) return mg_apply<double>(c, flags, b, x, cycles, st);
+  const int64_t n = c.n;
+  Vec<float> bf = Vec<float>{(float*)c.zt, c.n2()}, xf = Vec<float>{(float*)c.zt + n, c.n2()};
+  OKE(c, launch_copy_scale<double, float>(c.batch(flags), b, bf, 1.0, n, st));
+  int e = mg_apply<float>(c, flags, cst(bf), xf, cycles, st);
+  if (e) return e;
+  OKE(c, launch_copy_scale<float, double>(c.batch(flags), cst(xf), x, 1.0, n, st));
+  return OK_SUCCESS;
+}
+
+int residual_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const double> w,
+               Vec<const double> un, Vec<const double> wn, Vec<double> F, hipStream_t st) {
+  const Grid& g = c.lev[0];
+  const Batch B = c.batch(flags);
+  const int64_t n = c.n;
+  if (F.null()) F = vec(c.Bv, c.n2());
+  Vec<double> t1 = vec(c.T1, c.n2()), t2 = off(vec(c.T1, c.n2()), n);
+  Vec<const double> wnv = (c.shape.theta < 1.0 || !wn.null()) ? wn : Vec<const double>{nullptr, 0};
+  OKE(c, launch_residual_prep(B, u, un, w, wnv, t1, t2, n, st));
+  Vec<double> F1 = F, F2 = off(F, n);
+  const double a[2][4] = {{1.0, 0.0, 0.0, 1.0}, {0.0, 0.0, 0.0, 0.0}};  // F1 = M t1 + K t2
+  const int fa[2][4] = {{CF_ONE, CF_ONE, CF_ONE, CF_ONE}, {CF_ONE, CF_ONE, CF_ONE, CF_ONE}};
+  OKE(c, launch_stencil_lin2<double>(g, B, cst(t1), cst(t2), Vec<const double>{nullptr, 0},
+                                     Vec<const double>{nullptr, 0}, a, fa, F1,
+                                     Vec<double>{nullptr, 0}, st));
+  Vec<double> G = vec(c.G, n);
+  OKE(c, launch_element<double, double>(g, B, 1, u, Vec<const double>{nullptr, 0},
+                                        Vec<const double>{nullptr, 0}, -1.0, 0.0, G, st));
+  // F2 = -N(u) + M w - eps^2 K u
+  const double b2[2][4] = {{1.0, 0.0, 0.0, -1.0}, {0.0, 0.0, 0.0, 0.0}};
+  const int fb[2][4] = {{CF_ONE, CF_ONE, CF_ONE, CF_E2}, {CF_ONE, CF_ONE, CF_ONE, CF_ONE}};
+  OKE(c, launch_stencil_lin2<double>(g, B, w, u, cst(G), Vec<const double>{nullptr, 0}, b2, fb, F2,
+                                     Vec<double>{nullptr, 0}, st));
+  OKE(c, launch_dot_partial(B, cst(F), cst(F), c.n2(), vec(c.pA, (int64_t)kMaxRedBlocks), st));
+  OKE(c, launch_reduce_final(B, Vec<const double>{c.pA, kMaxRedBlocks}, c.n2(), vec(c.nrm, 8), st));
+  if (d2h(c, c.h_nrm, c.nrm, (size_t)8 * c.B, st)) return OK_E_HIP;
+  if (sync(c, st)) return OK_E_HIP;
+  std::vector<int> hf(c.B, 1);
+  if (flags == c.part) hf = c.h_part;
+  else if (flags == c.act) hf = c.h_act;
+  for (int i = 0; i < c.B; i++)
+    if (hf[i]) c.out[i].fnorm = c.h_nrm[8 * i + 1];
+  return OK_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES (Saad 1993) in lockstep over a group of classes
+// ---------------------------------------------------------------------------
+int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,
+                 const std::vector<Vec<const double>>& b, const std::vector<Vec<double>>& x,
+                 hipStream_t st) {
+  const size_t nc = grp.size();
+  std::vector<std::vector<double>> bnorm(nc), tol(nc);
+  // x = 0, ||b||
+  for (size_t k = 0; k < nc; k++) {
+    ClassCtx& c = *grp[k];
+    for (int i = 0; i < c.B; i++)
+      if (c.h_part[i]) c.out[i] = InstOut{0, 0, 0, c.out[i].fnorm, 0.0};
+    if (!any(c.h_part)) continue;
+    const Batch B = c.batch(c.part);
+    OKE(c, launch_fill(B, x[k], 0.0, c.n2(), st));
+    OKE(c, launch_dot_partial(B, b[k], b[k], c.n2(), vec(c.pA, (int64_t)kMaxRedBlocks), st));
+    OKE(c, launch_reduce_final(B, Vec<const double>{c.pA, kMaxRedBlocks}, c.n2(), vec(c.nrm, 8),
+                               st));
+    if (d2h(c, c.h_nrm, c.nrm, (size_t)8 * c.B, st)) return OK_E_HIP;
+  }
+  for (size_t k = 0; k < nc; k++)
+    if (any(grp[k]->h_part) && sync(*grp[k], st)) return OK_E_HIP;
+  for (size_t k = 0; k < nc; k++) {
+    ClassCtx& c = *grp[k];
+    bnorm[k].assign(c.B, 0.0);
+    tol[k].assign(c.B, 0.0);
+    c.h_kr.assign((size_t)8 * c.B, 0.0);
+    for (int i = 0; i < c.B; i++) {
+      c.h_act[i] = 0;
+      if (!c.h_part[i]) continue;
+      const double bn = c.h_nrm[8 * i + 1];
+      bnorm[k][i] = bn;
+      if (!std::isfinite(bn)) {
+        c.out[i].status = OK_E_NONFINITE;
+        continue;
+      }
+      if (bn == 0.0) continue;
+      tol[k][i] = c.ip[i].gmres_rtol * bn;
+      c.h_kr[8 * i + 0] = bn;
+      c.h_kr[8 * i + 1] = tol[k][i];
+      c.h_act[i] = 1;
+      c.out[i].status = OK_E_GMRES_MAXIT;
+    }
+    if (!any(c.h_act)) continue;
+    OKE(c, hipMemcpyAsync(c.kr, c.h_kr.data(), sizeof(double) * 8 * c.B, hipMemcpyHostToDevice,
+                          st));
+    if (push_flags(c, c.act, c.h_act, st)) return OK_E_HIP;
+  }
+  std::vector<bool> first(nc, true);
+  const int max_restarts = grp.empty() ? 0 : grp[0]->shape.gmres_max_restarts;
+  for (int cycle = 0; cycle <= max_restarts; cycle++) {
+    bool anyact = false;
+    for (size_t k = 0; k < nc; k++) {
+      ClassCtx& c = *grp[k];
+      if (!any(c.h_act)) continue;
+      anyact = true;
+      const Batch B = c.batch(c.act);
+      Vec<const double> src = first[k] ? b[k] : Vec<const double>{c.T1, c.n2()};
+      OKE(c, launch_scale_inv(B, src, Vec<double>{c.V, sV(c)}, Vec<const double>{c.nrm, 8},
+                              c.n2(), st));
+      OKE(c, launch_cycle_init(B, c.m, vec(c.g, sM(c)), Vec<const double>{c.nrm, 8},
+                               vec(c.kr, (int64_t)8), st));
+      OKE(c, hipMemcpyAsync(c.incyc, c.act, sizeof(int) * c.B, hipMemcpyDeviceToDevice, st));
+      first[k] = false;
+    }
+    if (!anyact) break;
+    std::vector<std::vector<int>> incyc(nc);
+    for (size_t k = 0; k < nc; k++) incyc[k] = grp[k]->h_act;
+    const int m = grp[0]->m;
+    for (int j = 0; j < m; j++) {
+      bool launched = false;
+      for (size_t k = 0; k < nc; k++) {
+        ClassCtx& c = *grp[k];
+        if (!any(c.h_act)) continue;
+        int e = c.mixed ? fgmres_iteration<float>(c, j, u[k], st)
+                        : fgmres_iteration<double>(c, j, u[k], st);
+        if (e) return e;
+        if (d2h(c, c.h_act, c.act, (size_t)c.B, st)) return OK_E_HIP;
+        launched = true;
+      }
+      if (!launched) break;
+      bool still = false;
+      for (size_t k = 0; k < nc; k++) {
+        ClassCtx& c = *grp[k];
+        if (sync(c, st)) return OK_E_HIP;
+        still = still || any(c.h_act);
+      }
+      if (!still) break;
+    }
+    // least squares and x update for the instances of this cycle; stop tests
+    bool restart_any = false;
+    for (size_t k = 0; k < nc; k++) {
+      ClassCtx& c = *grp[k];
+      if (!any(incyc[k])) continue;
+      int e = c.mixed ? lsq_update<float>(c, x[k], st) : lsq_update<double>(c, x[k], st);
+      if (e) return e;
+      if (d2h(c, c.h_kr, c.kr, (size_t)8 * c.B, st)) return OK_E_HIP;
+      if (sync(c, st)) return OK_E_HIP;
+      for (int i = 0; i < c.B; i++) {
+        c.h_act[i] = 0;
+        if (!incyc[k][i]) continue;
+        const double* kr = &c.h_kr[8 * i];
+        c.out[i].fgmres_its += (int)kr[6];
+        c.out[i].lin_res = kr[3] / bnorm[k][i];
+        if (kr[7] == 1.0) {
+          c.out[i].status = OK_SUCCESS;
+        } else if (kr[7] == 2.0) {
+          c.out[i].status = OK_E_NONFINITE;
+        } else if (cycle < max_restarts) {
+          c.h_act[i] = 1;  // restart from the true residual
+          restart_any = true;
+        } else {
+          c.out[i].status = OK_E_GMRES_MAXIT;
+        }
+      }
+    }
+    if (!restart_any) break;
+    // restart: r = b - J x for the instances still going
+    for (size_t k = 0; k < nc; k++) {
+      ClassCtx& c = *grp[k];
+      if (!any(c.h_act)) continue;
+      if (push_flags(c, c.act, c.h_act, st)) return OK_E_HIP;
+      const Batch B = c.batch(c.act);
+      Vec<double> T1 = vec(c.T1, c.n2());
+      int e = jac<double>(c, c.act, u[k], cst(x[k]), T1, st);
+      if (e) return e;
+      OKE(c, launch_axpby(B, 1.0, b[k], -1.0, cst(T1), T1, c.n2(), st));
+      OKE(c, launch_dot_partial(B, cst(T1), cst(T1), c.n2(), vec(c.pA, (int64_t)kMaxRedBlocks),
+                                st));
+      OKE(c, launch_reduce_final(B, Vec<const double>{c.pA, kMaxRedBlocks}, c.n2(),
+                                 vec(c.nrm, 8), st));
+      if (d2h(c, c.h_nrm, c.nrm, (size_t)8 * c.B, st)) return OK_E_HIP;
+      if (sync(c, st)) return OK_E_HIP;
+      for (int i = 0; i < c.B; i++) {
+        if (!c.h_act[i]) continue;
+        const double beta = c.h_nrm[8 * i + 1];
+        c.out[i].lin_res = beta / bnorm[k][i];
+        if (!std::isfinite(beta)) {
+          c.out[i].status = OK_E_NONFINITE;
+          c.h_act[i] = 0;
+        } else if (beta <= tol[k][i]) {
+          c.out[i].status = OK_SUCCESS;
+          c.h_act[i] = 0;
+        } else {
+          c.out[i].restarts++;
+        }
+      }
+      if (push_flags(c, c.act, c.h_act, st)) return OK_E_HIP;
+    }
+  }
+  return OK_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------
+// Newton in lockstep (Sec. 2: one linear solve per Newton iteration)
+// ---------------------------------------------------------------------------
+int newton_group_iters(const Group& grp, const std::vector<Vec<double>>& u,
+                       const std::vector<Vec<double>>& w, const std::vector<Vec<const double>>& un,
+                       const std::vector<Vec<const double>>& wn, std::vector<NewtonLog>& log,
+                       int max_iters, hipStream_t st) {
+  const size_t nc = grp.size();
+  for (int it = 0;; it++) {
+    bool anyp = false;
+    for (size_t k = 0; k < nc; k++) {
+      ClassCtx& c = *grp[k];
+      if (!any(c.h_part)) continue;
+      if (push_part(c, st)) return OK_E_HIP;
+      int e = residual_d(c, c.part, cst(u[k]), cst(w[k]), un[k], wn[k], vec(c.Bv, c.n2()), st);
+      if (e) return e;
+      for (int i = 0; i < c.B; i++) {
+        if (!c.h_part[i]) continue;
+        const double f = c.out[i].fnorm;
+        log[k].fnorm[i].push_back(f);
+        if (!std::isfinite(f)) {
+          c.out[i].status = OK_E_NONFINITE;
+          c.h_part[i] = 0;
+        } else if (f <= c.ip[i].newton_atol) {
+          c.out[i].status = OK_SUCCESS;
+          c.h_part[i] = 0;
+        } else if (c.nits[i] >= c.shape.newton_max_it) {
+          c.out[i].status = OK_E_NEWTON_MAXIT;
+          c.h_part[i] = 0;
+        } else {
+          c.out[i].status = 1;  // still iterating
+        }
+      }
+      anyp = anyp || any(c.h_part);
+    }
+    if (!anyp) break;
+    std::vector<Vec<const double>> bb(nc);
+    std::vector<Vec<double>> xx(nc);
+    std::vector<Vec<const double>> uu(nc);
+    for (size_t k = 0; k < nc; k++) {
+      ClassCtx& c = *grp[k];
+      bb[k] = Vec<const double>{c.Bv, c.n2()};
+      xx[k] = vec(c.X, c.n2());
+      uu[k] = cst(u[k]);
+      if (!any(c.h_part)) continue;
+      if (push_part(c, st)) return OK_E_HIP;
+      OKE(c, launch_copy_scale<double, double>(c.batch(c.part), bb[k], vec(c.Bv, c.n2()), -1.0,
+                                               c.n2(), st));
+    }
+    int e = fgmres_group(grp, uu, bb, xx, st);
+    if (e) return e;
+    for (size_t k = 0; k < nc; k++) {
+      ClassCtx& c = *grp[k];
+      if (!any(c.h_part)) continue;
+      for (int i = 0; i < c.B; i++) {
+        if (!c.h_part[i]) continue;
+        log[k].its[i].push_back(c.out[i].fgmres_its);
+        c.nits[i]++;
+        if (c.out[i].status == OK_E_NONFINITE) c.h_part[i] = 0;
+      }
+      if (push_part(c, st)) return OK_E_HIP;
+      const Batch B = c.batch(c.part);
+      OKE(c, launch_axpby(B, 1.0, cst(u[k]), 1.0, Vec<const double>{c.X, c.n2()}, u[k], c.n, st));
+      OKE(c, launch_axpby(B, 1.0, cst(w[k]), 1.0, Vec<const double>{c.X + c.n, c.n2()}, w[k], c.n,
+                          st));
+      // instances whose linear solve failed to converge still took the step;
+      // they keep iterating (the Newton test decides)
+      for (int i = 0; i < c.B; i++)
+        if (c.h_part[i] && c.out[i].status == OK_E_GMRES_MAXIT) c.out[i].status = 1;
+    }
+    // a bounded call (one serving tick) ends after its updates; the next call
+    // starts with the residual test
+    if (max_iters >= 0 && it + 1 >= max_iters) break;
+  }
+  return OK_SUCCESS;
+}
+
+int newton_group(const Group& grp, const std::vector<Vec<double>>& u,
+                 const std::vector<Vec<double>>& w, const std::vector<Vec<const double>>& un,
+                 const std::vector<Vec<const double>>& wn, std::vector<NewtonLog>& log,
+                 hipStream_t st) {
+  return newton_group_iters(grp, u, w, un, wn, log, -1, st);
+}
+
+// ---------------------------------------------------------------------------
+// Tile autotuner
+// ---------------------------------------------------------------------------
+namespace {
+
+template <class F>
+double time_best(hipStream_t st, F&& launch) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return 1e30;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return 1e30;
+  }
+  double best = 1e30;
+  if (launch() == hipSuccess) {
+    for (int r = 0; r < 3; r++) {
+      (void)hipEventRecord(a, st);
+      if (launch() != hipSuccess) {
+        best = 1e30;
+        break;
+      }
+      (void)hipEventRecord(b, st);
+      (void)hipEventSynchronize(b);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      best = std::min(best, (double)ms);
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return best;
+}
+
+template <class P>
+int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
+  const int zcs[4] = {4, 8, 16, 32};
+  const int word = (int)sizeof(P);
+  const Batch B = c.batch(nullptr);
+  for (int l = 0; l < c.L; l++) {
+    const Grid& g = c.lev[l];
+    if (l == c.L - 1 && c.L > 1) break;  // the coarsest level is a direct solve
+    const int64_t nl = g.nodes;
+    Vec<P> x, r, d0, d1;
+    if (l == 0) {
+      x = pvec<P>(c.yv, nl); r = pvec<P>(c.cr, nl); d0 = pvec<P>(c.cda, nl); d1 = pvec<P>(c.cdb, nl);
+    } else {
+      x = pvec<P>(c.mg[l][0], nl); r = pvec<P>(c.mg[l][2], nl);
+      d0 = pvec<P>(c.mg[l][3], nl); d1 = pvec<P>(c.mg[l][4], nl);
+    }
+    double best = 1e30;
+    int bi = 0, bz = 0;
+    for (int items = 1; items <= 8; items *= 2)
+      for (int zc : zcs) {
+        if (zc > g.nn && zc != 4) continue;
+        stencil_tune_set(g.dim, g.nn, 1, word, items, zc);
+        double t = time_best(st, [&]() {
+          return launch_cheb_step<P>(g, B, l, 0, CF_ONE, false, x, r, cst(d0), d1, st);
+        });
+        if (t < best) {
+          best = t;
+          bi = items;
+          bz = zc;
+        }
+      }
+    stencil_tune_set(g.dim, g.nn, 1, word, bi, bz);
+    if (bi) (*entries)++;
+  }
+  {
+    const Grid& g = c.lev[0];
+    Vec<const P> z{(const P*)c.Z, sZ(c)};
+    const double cf[2][4] = {{1.0, 0.0, 0.0, 1.0}, {1.0, -1.0, 1.0, 0.0}};
+    const int ff[2][4] = {{CF_SA, CF_ONE, CF_ONE, CF_DTH}, {CF_ONE, CF_E2, CF_ONE, CF_ONE}};
+    double best = 1e30;
+    int bi = 0, bz = 0;
+    for (int items = 1; items <= 4; items *= 2)
+      for (int zc : zcs) {
+        if (zc > g.nn && zc != 4) continue;
+        stencil_tune_set(g.dim, g.nn, 2, word, items, zc);
+        double t = time_best(st, [&]() {
+          return launch_stencil_lin2<P>(g, B, z, off(z, c.n), Vec<const double>{nullptr, 0},
+                                        Vec<const double>{c.G, c.n}, cf, ff, vec(c.T1, c.n2()),
+                                        off(vec(c.T1, c.n2()), c.n), st);
+        });
+        if (t < best) {
+          best = t;
+          bi = items;
+          bz = zc;
+        }
+      }
+    stencil_tune_set(g.dim, g.nn, 2, word, bi, bz);
+    if (bi) (*entries)++;
+  }
+  return OK_SUCCESS;
+}
+
+}  // namespace
+
+int autotune_class(ClassCtx& c, hipStream_t st, int* entries) {
+  int n = 0;
+  int e = c.mixed ? autotune_impl<float>(c, st, &n) : autotune_impl<double>(c, st, &n);
+  if (entries) *entries = n;
+  if (e) return e;
+  OKE(c, hipStreamSynchronize(st));
+  return OK_SUCCESS;
+}
+
+}  // namespace okd

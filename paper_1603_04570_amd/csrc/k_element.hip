@@ -188,16 +188,23 @@ EShape element_shape(const Grid& g) {
 // registers); EPLT == 0: taken from the shape (2D, no carry).
 template <int DIM, int MODE, int EPLT, class TX, class TO>
 __global__ void __launch_bounds__(64 * kWaves)
-    k_element(const double* __restrict__ u, const TX* __restrict__ x,
-              const double* __restrict__ add, TO* __restrict__ out, Grid g, EShape sh,
-              double alpha, double beta) {
+    k_element(Vec<const double> uv, Vec<const TX> xv, Vec<const double> addv, Vec<TO> outv,
+              Grid g, EShape sh, Batch B, double alpha, double beta) {
   constexpr int NZ = (DIM == 3) ? 2 : 1;  // corner layers per element
   __shared__ double xch[2][kWaves][NZ][64];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int b = remap(blockIdx.x, gridDim.x);
+  const int lb = remap(blockIdx.x, gridDim.x);
+  const int per = sh.rowtiles * sh.nzc;
+  const int inst = lb / per;
+  if (B.act && !B.act[inst]) return;
+  const int b = lb - inst * per;
   const int rt = b % sh.rowtiles;
   const int zch = b / sh.rowtiles;
+  const double* __restrict__ u = uv.at(inst);
+  const TX* __restrict__ x = xv.null() ? nullptr : xv.at(inst);
+  const double* __restrict__ add = addv.null() ? nullptr : addv.at(inst);
+  TO* __restrict__ out = outv.at(inst);
   const int N = g.N, nn = g.nn;
   const int64_t plane = g.plane;
   const int y0 = rt * kRows;
@@ -313,14 +320,16 @@ __global__ void __launch_bounds__(64 * kWaves)
 }  // namespace
 
 template <class TX, class TO>
-hipError_t launch_element(const Grid& g, int mode, const double* u, const TX* x,
-                          const double* add, double alpha, double beta, TO* out, hipStream_t st) {
+hipError_t launch_element(const Grid& g, const Batch& B, int mode, Vec<const double> u,
+                          Vec<const TX> x, Vec<const double> add, double alpha, double beta,
+                          Vec<TO> out, hipStream_t st) {
   EShape sh = element_shape(g);
-  int blocks = sh.rowtiles * sh.nzc;
-  dim3 grid(blocks), block(64 * kWaves);
+  int64_t blocks = (int64_t)sh.rowtiles * sh.nzc * B.count;
+  if (blocks > 0x7fffffff || B.count < 1) return hipErrorInvalidValue;
+  dim3 grid((unsigned)blocks), block(64 * kWaves);
 #define OKD_EL(D, M, E)                                                                     \
   hipLaunchKernelGGL((k_element<D, M, E, TX, TO>), grid, block, 0, st, u, x, add, out, g, sh, \
-                     alpha, beta)
+                     B, alpha, beta)
   if (g.dim == 2) {
     if (mode == 0) OKD_EL(2, 0, 0); else OKD_EL(2, 1, 0);
   } else {
@@ -338,11 +347,13 @@ hipError_t launch_element(const Grid& g, int mode, const double* u, const TX* x,
   return hipGetLastError();
 }
 
-template hipError_t launch_element<double, double>(const Grid&, int, const double*,
-                                                   const double*, const double*, double, double,
-                                                   double*, hipStream_t);
-template hipError_t launch_element<float, double>(const Grid&, int, const double*, const float*,
-                                                  const double*, double, double, double*,
-                                                  hipStream_t);
+template hipError_t launch_element<double, double>(const Grid&, const Batch&, int,
+                                                   Vec<const double>, Vec<const double>,
+                                                   Vec<const double>, double, double,
+                                                   Vec<double>, hipStream_t);
+template hipError_t launch_element<float, double>(const Grid&, const Batch&, int,
+                                                  Vec<const double>, Vec<const float>,
+                                                  Vec<const double>, double, double,
+                                                  Vec<double>, hipStream_t);
 
 }  // namespace okd

@@ -25,8 +25,12 @@ __device__ __forceinline__ double ld(const float* p) { return (double)*p; }
 
 template <int DIM, class T>
 __global__ void __launch_bounds__(256)
-    k_restrict(const T* __restrict__ r, T* __restrict__ bc, Grid f, Grid c) {
-  int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    k_restrict(Vec<const T> rv, Vec<T> bcv, Grid f, Grid c, Batch B, int per) {
+  const int inst = blockIdx.x / per;
+  if (B.act && !B.act[inst]) return;
+  const T* __restrict__ r = rv.at(inst);
+  T* __restrict__ bc = bcv.at(inst);
+  int64_t I = (int64_t)(blockIdx.x % per) * blockDim.x + threadIdx.x;
   if (I >= c.nodes) return;
   int ci = (int)(I % c.nn);
   int cj = (int)((I / c.nn) % c.nn);
@@ -54,8 +58,12 @@ __global__ void __launch_bounds__(256)
 
 template <int DIM, class T>
 __global__ void __launch_bounds__(256)
-    k_prolong_add(const T* __restrict__ ec, T* __restrict__ x, Grid f, Grid c) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    k_prolong_add(Vec<const T> ecv, Vec<T> xv, Grid f, Grid c, Batch B, int per) {
+  const int inst = blockIdx.x / per;
+  if (B.act && !B.act[inst]) return;
+  const T* __restrict__ ec = ecv.at(inst);
+  T* __restrict__ x = xv.at(inst);
+  int64_t i = (int64_t)(blockIdx.x % per) * blockDim.x + threadIdx.x;
   if (i >= f.nodes) return;
   int fi = (int)(i % f.nn);
   int fj = (int)((i / f.nn) % f.nn);
@@ -86,10 +94,16 @@ __global__ void __launch_bounds__(256)
 constexpr int kCoarseMax = 1024;   // nodes of the coarse grid
 constexpr int kCoarseLine = 64;    // nodes per direction
 
-// One block solves (M + alpha K) x = b exactly on a grid of at most 1024 nodes.
+// One block per instance solves (M + alpha K) x = b exactly on a grid of at
+// most 1024 nodes.
 template <int DIM, class T>
 __global__ void __launch_bounds__(1024)
-    k_coarse(const T* __restrict__ b, T* __restrict__ x, Grid g, double alpha) {
+    k_coarse(Vec<const T> bv, Vec<T> xv, Grid g, Batch bt) {
+  const int inst = blockIdx.x;
+  if (bt.act && !bt.act[inst]) return;
+  const T* __restrict__ b = bv.at(inst);
+  T* __restrict__ x = xv.at(inst);
+  const double alpha = bt.coef[inst].alpha;
   __shared__ double A[kCoarseMax], B[kCoarseMax];
   __shared__ double V[kCoarseLine * kCoarseLine];
   __shared__ double mu[kCoarseLine], kap[kCoarseLine], gam[kCoarseLine];
@@ -162,48 +176,49 @@ __global__ void __launch_bounds__(1024)
 }  // namespace
 
 template <class T>
-hipError_t launch_restrict(const Grid& fine, const Grid& coarse, const T* r, T* bc,
-                           hipStream_t st) {
-  dim3 grid((unsigned)((coarse.nodes + 255) / 256)), block(256);
+hipError_t launch_restrict(const Grid& fine, const Grid& coarse, const Batch& B, Vec<const T> r,
+                           Vec<T> bc, hipStream_t st) {
+  int per = (int)((coarse.nodes + 255) / 256);
+  dim3 grid((unsigned)(per * B.count)), block(256);
   if (fine.dim == 2)
-    hipLaunchKernelGGL((k_restrict<2, T>), grid, block, 0, st, r, bc, fine, coarse);
+    hipLaunchKernelGGL((k_restrict<2, T>), grid, block, 0, st, r, bc, fine, coarse, B, per);
   else
-    hipLaunchKernelGGL((k_restrict<3, T>), grid, block, 0, st, r, bc, fine, coarse);
+    hipLaunchKernelGGL((k_restrict<3, T>), grid, block, 0, st, r, bc, fine, coarse, B, per);
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_prolong_add(const Grid& fine, const Grid& coarse, const T* ec, T* x,
-                              hipStream_t st) {
-  dim3 grid((unsigned)((fine.nodes + 255) / 256)), block(256);
+hipError_t launch_prolong_add(const Grid& fine, const Grid& coarse, const Batch& B,
+                              Vec<const T> ec, Vec<T> x, hipStream_t st) {
+  int per = (int)((fine.nodes + 255) / 256);
+  dim3 grid((unsigned)(per * B.count)), block(256);
   if (fine.dim == 2)
-    hipLaunchKernelGGL((k_prolong_add<2, T>), grid, block, 0, st, ec, x, fine, coarse);
+    hipLaunchKernelGGL((k_prolong_add<2, T>), grid, block, 0, st, ec, x, fine, coarse, B, per);
   else
-    hipLaunchKernelGGL((k_prolong_add<3, T>), grid, block, 0, st, ec, x, fine, coarse);
+    hipLaunchKernelGGL((k_prolong_add<3, T>), grid, block, 0, st, ec, x, fine, coarse, B, per);
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_coarse_solve(const Grid& g, double alpha, const T* b, T* x, hipStream_t st) {
+hipError_t launch_coarse_solve(const Grid& g, const Batch& B, Vec<const T> b, Vec<T> x,
+                               hipStream_t st) {
   if (g.nodes > kCoarseMax || g.nn > kCoarseLine) return hipErrorInvalidValue;
   if (g.dim == 2)
-    hipLaunchKernelGGL((k_coarse<2, T>), dim3(1), dim3(1024), 0, st, b, x, g, alpha);
+    hipLaunchKernelGGL((k_coarse<2, T>), dim3(B.count), dim3(1024), 0, st, b, x, g, B);
   else
-    hipLaunchKernelGGL((k_coarse<3, T>), dim3(1), dim3(1024), 0, st, b, x, g, alpha);
+    hipLaunchKernelGGL((k_coarse<3, T>), dim3(B.count), dim3(1024), 0, st, b, x, g, B);
   return hipGetLastError();
 }
 
-template hipError_t launch_restrict<double>(const Grid&, const Grid&, const double*, double*,
-                                            hipStream_t);
-template hipError_t launch_restrict<float>(const Grid&, const Grid&, const float*, float*,
-                                           hipStream_t);
-template hipError_t launch_prolong_add<double>(const Grid&, const Grid&, const double*, double*,
-                                               hipStream_t);
-template hipError_t launch_prolong_add<float>(const Grid&, const Grid&, const float*, float*,
-                                              hipStream_t);
-template hipError_t launch_coarse_solve<double>(const Grid&, double, const double*, double*,
-                                                hipStream_t);
-template hipError_t launch_coarse_solve<float>(const Grid&, double, const float*, float*,
-                                               hipStream_t);
+#define OKD_MG(T)                                                                              \
+  template hipError_t launch_restrict<T>(const Grid&, const Grid&, const Batch&, Vec<const T>,  \
+                                         Vec<T>, hipStream_t);                                  \
+  template hipError_t launch_prolong_add<T>(const Grid&, const Grid&, const Batch&,             \
+                                            Vec<const T>, Vec<T>, hipStream_t);                 \
+  template hipError_t launch_coarse_solve<T>(const Grid&, const Batch&, Vec<const T>, Vec<T>,   \
+                                             hipStream_t);
+OKD_MG(double)
+OKD_MG(float)
+#undef OKD_MG
 
 }  // namespace okd

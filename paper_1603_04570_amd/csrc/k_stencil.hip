@@ -59,6 +59,13 @@ static StencilShape shape_with(const Grid& g, int items, int zc) {
   return s;
 }
 
+int red_blocks(int64_t n) {
+  int64_t b = (n + 4095) / 4096;
+  if (b > kMaxRedBlocks) b = kMaxRedBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
 StencilShape stencil_shape(const Grid& g, int nf, int word) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -87,19 +94,6 @@ StencilShape stencil_shape(const Grid& g, int nf, int word) {
   return s;
 }
 
-Op make_op(const Grid& g, double cm, double ck) {
-  // Interior diagonal: M1 -> 2h/3, K1 -> 2/h.
-  double mi = 2.0 * g.h / 3.0, ki = 2.0 / g.h;
-  double dm = 1.0, dk = 0.0;
-  for (int d = 0; d < g.dim; d++) dm *= mi;
-  dk = g.dim * ki;
-  for (int d = 0; d < g.dim - 1; d++) dk *= mi;
-  Op o;
-  o.cm = cm;
-  o.ck = ck;
-  o.dinv_int = 1.0 / (cm * dm + ck * dk);
-  return o;
-}
 
 // Hardware places block b on XCD b % 8.  Renumber blocks so that each XCD
 // receives a contiguous range of logical blocks (neighbouring chunks), which
@@ -137,32 +131,41 @@ __device__ __forceinline__ double to_d(double v) { return v; }
 __device__ __forceinline__ double to_d(float v) { return (double)v; }
 
 // ---------------------------------------------------------------------------
-// The streaming kernel over NF stenciled fields.  For each owned node the
-// epilogue first issues its pointwise loads (Epi::load) and later receives
-// (index, #boundary coordinates, (M s_f)_i, (K s_f)_i, (s_f)_i for f < NF,
-// loaded values).  Plane pz+1 is prefetched into registers (F loads per thread
-// and field, all issued back to back) while plane pz is processed from LDS.
+// The streaming kernel over NF stenciled fields of a class of instances.
+// For each owned node the epilogue first issues its pointwise loads
+// (Epi::load) and later receives (instance, index, #boundary coordinates,
+// (M s_f)_i, (K s_f)_i, (s_f)_i for f < NF, loaded values, the instance's
+// scalars).  Plane pz+1 is prefetched into registers (F loads per thread and
+// field, all issued back to back) while plane pz is processed from LDS.
 // ---------------------------------------------------------------------------
 template <class TS, int NF>
 struct Src {
   const TS* p[NF];
+  int64_t s[NF];
 };
 
 template <int DIM, int NF, int P, int F, bool SCALED, class TS, class Epi>
 __global__ void __launch_bounds__(kThreads)
-    k_stencil(Src<TS, NF> src, Grid g, StencilShape sh, Epi epi) {
+    k_stencil(Src<TS, NF> src, Grid g, StencilShape sh, Batch B, Epi epi) {
   extern __shared__ double lds[];
   using In = typename Epi::In;
   const int tid = threadIdx.x;
-  const int b = block_remap(blockIdx.x, gridDim.x);
+  const int lb = block_remap(blockIdx.x, gridDim.x);
+  const int inst = lb / sh.blocks;
+  if (B.act && !B.act[inst]) return;
+  const int b = lb - inst * sh.blocks;
   const int chunk = b % sh.nchunks;
   const int zch = b / sh.nchunks;
+  const typename Epi::K kk = epi.prep(B.coef[inst]);
   const int nn = g.nn, N = g.N;
   // Streaming "plane": an x-y plane in 3D, an x row in 2D.
   const int64_t plane = (DIM == 3) ? g.plane : (int64_t)nn;
   const int halo = (DIM == 3) ? nn + 1 : 1;
   const int ldsn = sh.chunk + 2 * halo;
   const int64_t s0 = (int64_t)chunk * sh.chunk;
+  const TS* sp[NF];
+#pragma unroll
+  for (int f = 0; f < NF; f++) sp[f] = src.p[f] + (int64_t)inst * src.s[f];
 
   int ii[P], jj[P];
   bool valid[P];
@@ -188,7 +191,7 @@ __global__ void __launch_bounds__(kThreads)
       for (int k = 0; k < F; k++) {
         const int t = tid + kThreads * k;
         const int64_t gq = s0 - halo + t;
-        pre[f][k] = (t < ldsn && gq >= 0 && gq < plane) ? to_d(src.p[f][zoff + gq]) : 0.0;
+        pre[f][k] = (t < ldsn && gq >= 0 && gq < plane) ? to_d(sp[f][zoff + gq]) : 0.0;
       }
   };
   auto commit = [&]() {
@@ -262,7 +265,7 @@ __global__ void __launch_bounds__(kThreads)
     if (o >= z0) {
 #pragma unroll
       for (int p = 0; p < P; p++)
-        if (valid[p]) in[p] = epi.load((int64_t)o * plane + s0 + tid + kThreads * p);
+        if (valid[p]) in[p] = epi.load(inst, (int64_t)o * plane + s0 + tid + kThreads * p);
     }
     if (pz + 1 <= z1 && pz + 1 <= N) issue((int64_t)(pz + 1) * plane);
     double pmn[NF][P], pkn[NF][P], cn[NF][P];
@@ -292,7 +295,7 @@ __global__ void __launch_bounds__(kThreads)
         int nb = (ii[p] == 0 || ii[p] == N) + nbz;
         if (DIM == 3) nb += (jj[p] == 0 || jj[p] == N);
         int64_t idx = (int64_t)o * plane + s0 + tid + kThreads * p;
-        epi.store(idx, nb, ms, ks, cc, in[p]);
+        epi.store(inst, idx, nb, ms, ks, cc, in[p], kk);
       }
     }
 #pragma unroll
@@ -310,17 +313,18 @@ __global__ void __launch_bounds__(kThreads)
 
 template <int D, int NF, int PP, bool SCALED, class TS, class Epi>
 static void launch_h(int hx, dim3 grid, dim3 block, size_t lds, hipStream_t st,
-                     const Src<TS, NF>& s, const Grid& g, const StencilShape& sh, const Epi& e) {
+                     const Src<TS, NF>& s, const Grid& g, const StencilShape& sh, const Batch& B,
+                     const Epi& e) {
   switch (hx) {
-    case 3: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 3, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
-    case 5: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 5, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
-    case 9: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 9, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
-    default: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 17, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, e); break;
+    case 3: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 3, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, B, e); break;
+    case 5: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 5, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, B, e); break;
+    case 9: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 9, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, B, e); break;
+    default: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 17, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, B, e); break;
   }
 }
 
 template <bool SCALED, class TS, int NF, class Epi>
-static hipError_t run_stencil_n(const Grid& g, const Src<TS, NF>& s, const Epi& e,
+static hipError_t run_stencil_n(const Grid& g, const Batch& B, const Src<TS, NF>& s, const Epi& e,
                                 hipStream_t st) {
   StencilShape sh = stencil_shape(g, NF, (int)sizeof(TS));
   const int ldsn = sh.chunk + 2 * (g.dim == 3 ? g.nn + 1 : 1);
@@ -328,39 +332,41 @@ static hipError_t run_stencil_n(const Grid& g, const Src<TS, NF>& s, const Epi& 
   // prefetch registers beyond the chunk: ceil(2*halo/256) rounded up to 3, 5, 9, 17
   int extra = (ldsn - sh.chunk + kThreads - 1) / kThreads;
   int hx = extra <= 3 ? 3 : (extra <= 5 ? 5 : (extra <= 9 ? 9 : 17));
-  if (extra > 17 || lds > 65536) return hipErrorInvalidValue;
-  dim3 grid(sh.blocks), block(kThreads);
+  if (extra > 17 || lds > 65536 || B.count < 1) return hipErrorInvalidValue;
+  int64_t nblk = (int64_t)sh.blocks * B.count;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  dim3 grid((unsigned)nblk), block(kThreads);
   if (g.dim == 2) {
     if (NF == 1) {
       switch (sh.items) {
-        case 8: launch_h<2, NF, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-        case 4: launch_h<2, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-        case 2: launch_h<2, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-        default: launch_h<2, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        case 8: launch_h<2, NF, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        case 4: launch_h<2, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        case 2: launch_h<2, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        default: launch_h<2, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
       }
     } else {
       if (sh.items > 4) return hipErrorInvalidValue;
       switch (sh.items) {
-        case 4: launch_h<2, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-        case 2: launch_h<2, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-        default: launch_h<2, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        case 4: launch_h<2, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        case 2: launch_h<2, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        default: launch_h<2, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
       }
     }
   } else {
     if (hx > 5) return hipErrorInvalidValue;
     if (NF == 1) {
       switch (sh.items) {
-        case 8: launch_h<3, NF, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-        case 4: launch_h<3, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-        case 2: launch_h<3, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-        default: launch_h<3, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        case 8: launch_h<3, NF, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        case 4: launch_h<3, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        case 2: launch_h<3, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        default: launch_h<3, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
       }
     } else {
       if (sh.items > 4) return hipErrorInvalidValue;
       switch (sh.items) {
-        case 4: launch_h<3, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-        case 2: launch_h<3, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
-        default: launch_h<3, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, e); break;
+        case 4: launch_h<3, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        case 2: launch_h<3, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        default: launch_h<3, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
       }
     }
   }
@@ -368,13 +374,14 @@ static hipError_t run_stencil_n(const Grid& g, const Src<TS, NF>& s, const Epi& 
 }
 
 template <bool SCALED, class TS, class Epi>
-static hipError_t run_stencil(const Grid& g, const TS* s, const Epi& e, hipStream_t st) {
-  Src<TS, 1> src{{s}};
-  return run_stencil_n<SCALED, TS, 1>(g, src, e, st);
+static hipError_t run_stencil(const Grid& g, const Batch& B, Vec<const TS> s, const Epi& e,
+                              hipStream_t st) {
+  Src<TS, 1> src{{s.p}, {s.s}};
+  return run_stencil_n<SCALED, TS, 1>(g, B, src, e, st);
 }
 
 // ---------------------------------------------------------------------------
-// Epilogues
+// Epilogues.  prep() reads the instance's scalars once per block.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double dinv_at(double dinv_int, int nb) {
   return dinv_int * (double)(1 << nb);
@@ -387,47 +394,104 @@ struct In1 {
 struct In2 {
   double a, b;
 };
+struct OpK {
+  double cm, ck, dinv, it, c1, c2, osc;
+};
+__device__ __forceinline__ const LevelCoef& level_of(const InstCoef& C, int lev) {
+  return lev < 0 ? C.mass : C.lev[lev];
+}
+__device__ __forceinline__ OpK op_k(const InstCoef& C, int lev, int k, int osc) {
+  const LevelCoef& L = level_of(C, lev);
+  OpK o;
+  o.cm = L.cm;
+  o.ck = L.ck;
+  o.dinv = L.dinv;
+  o.it = L.it;
+  o.c1 = (k >= 0) ? L.c1[k] : 0.0;
+  o.c2 = (k >= 0) ? L.c2[k] : 0.0;
+  o.osc = coef_field(C, osc);
+  return o;
+}
 
 // out = add + a*(M s) + b*(K s)
 template <class TA, class TO>
 struct EpiAxpy {
   using In = In1;
-  const TA* add;
-  double a, b;
-  TO* out;
-  __device__ In load(int64_t i) const { return In{add ? to_d(add[i]) : 0.0}; }
-  __device__ void store(int64_t i, int, const double* ms, const double* ks, const double*,
-                        const In& in) const {
-    out[i] = (TO)(in.a + a * ms[0] + b * ks[0]);
+  struct K {
+    double a, b;
+  };
+  Vec<const TA> add;
+  double ca, cb;
+  int fa, fb;
+  Vec<TO> out;
+  __device__ K prep(const InstCoef& C) const {
+    return K{ca * coef_field(C, fa), cb * coef_field(C, fb)};
+  }
+  __device__ In load(int inst, int64_t i) const {
+    return In{add.null() ? 0.0 : to_d(add.at(inst)[i])};
+  }
+  __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
+                        const double*, const In& in, const K& k) const {
+    out.at(inst)[i] = (TO)(in.a + k.a * ms[0] + k.b * ks[0]);
+  }
+};
+
+// Two stenciled fields s0, s1 and up to two outputs:
+//   out_o = add_o + c[o][0] M s0 + c[o][1] K s0 + c[o][2] M s1 + c[o][3] K s1
+template <class TO>
+struct EpiLin2 {
+  using In = In2;
+  struct K {
+    double c[2][4];
+  };
+  Vec<const double> add0, add1;
+  double c[2][4];
+  int f[2][4];
+  Vec<TO> out0, out1;
+  __device__ K prep(const InstCoef& C) const {
+    K k;
+    for (int o = 0; o < 2; o++)
+      for (int q = 0; q < 4; q++) k.c[o][q] = c[o][q] * coef_field(C, f[o][q]);
+    return k;
+  }
+  __device__ In load(int inst, int64_t i) const {
+    return In{add0.null() ? 0.0 : add0.at(inst)[i], add1.null() ? 0.0 : add1.at(inst)[i]};
+  }
+  __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
+                        const double*, const In& in, const K& k) const {
+    out0.at(inst)[i] =
+        (TO)(in.a + k.c[0][0] * ms[0] + k.c[0][1] * ks[0] + k.c[0][2] * ms[1] + k.c[0][3] * ks[1]);
+    if (!out1.null())
+      out1.at(inst)[i] = (TO)(in.b + k.c[1][0] * ms[0] + k.c[1][1] * ks[0] + k.c[1][2] * ms[1] +
+                              k.c[1][3] * ks[1]);
   }
 };
 
 // First Chebyshev iteration from x0 = 0; the stencil input is b and is
 // applied with SCALED patterns, so (cm M + ck K) W^-1 b is available and
-// A d0 = (dinv_int/theta) (cm M + ck K) W^-1 b.
-template <class T, class TX, bool LAST>
+// A d0 = dinv * it * (cm M + ck K) W^-1 b.
+template <class T, bool LAST>
 struct EpiChebFirst {
   using In = In0;
-  Op A;
-  double inv_theta, c1, c2, out_scale;
-  TX* x;
-  T* r;
-  T* d;
-  __device__ In load(int64_t) const { return In{}; }
-  __device__ void store(int64_t i, int nb, const double* ms, const double* ks, const double* cen,
-                        const In&) const {
+  using K = OpK;
+  int lev, osc;
+  Vec<T> x, r, d;
+  __device__ K prep(const InstCoef& C) const { return op_k(C, lev, 0, osc); }
+  __device__ In load(int, int64_t) const { return In{}; }
+  __device__ void store(int inst, int64_t i, int nb, const double* ms, const double* ks,
+                        const double* cen, const In&, const K& k) const {
     const double bi = cen[0];
-    double dv = dinv_at(A.dinv_int, nb);
-    double ad0 = A.dinv_int * inv_theta * (A.cm * ms[0] + A.ck * ks[0]);
-    double d0 = dv * bi * inv_theta;
+    double dv = dinv_at(k.dinv, nb);
+    double ad0 = k.dinv * k.it * (k.cm * ms[0] + k.ck * ks[0]);
+    double d0 = dv * bi * k.it;
     double r1 = bi - ad0;
-    double d1 = c1 * d0 + c2 * dv * r1;
+    double d1 = k.c1 * d0 + k.c2 * dv * r1;
     if (LAST) {
-      x[i] = (TX)(out_scale * (d0 + d1));
+      x.at(inst)[i] = (T)(k.osc * (d0 + d1));
     } else {
-      x[i] = (TX)d0;
-      r[i] = (T)r1;
-      d[i] = (T)d1;
+      x.at(inst)[i] = (T)d0;
+      r.at(inst)[i] = (T)r1;
+      d.at(inst)[i] = (T)d1;
     }
   }
 };
@@ -435,62 +499,63 @@ struct EpiChebFirst {
 // Iteration k: stencil input d_k.  x_{k+1} = x_k + d_k, r_{k+1} = r_k - A d_k,
 // d_{k+1} = c1 d_k + c2 D^-1 r_{k+1}.  LAST also adds the final step:
 // x_{k+2} = x_{k+1} + d_{k+1}, and writes only x.
-template <class T, class TX, bool LAST>
+template <class T, bool LAST>
 struct EpiChebStep {
   using In = In2;
-  Op A;
-  double c1, c2, out_scale;
-  const TX* xin;
-  TX* x;
-  T* r;
-  T* dn;
-  __device__ In load(int64_t i) const { return In{to_d(xin[i]), to_d(r[i])}; }
-  __device__ void store(int64_t i, int nb, const double* ms, const double* ks, const double* cen,
-                        const In& in) const {
+  using K = OpK;
+  int lev, k, osc;
+  Vec<T> x, r, dn;
+  __device__ K prep(const InstCoef& C) const { return op_k(C, lev, k, osc); }
+  __device__ In load(int inst, int64_t i) const {
+    return In{to_d(x.at(inst)[i]), to_d(r.at(inst)[i])};
+  }
+  __device__ void store(int inst, int64_t i, int nb, const double* ms, const double* ks,
+                        const double* cen, const In& in, const K& kk) const {
     const double dk = cen[0];
-    double dv = dinv_at(A.dinv_int, nb);
+    double dv = dinv_at(kk.dinv, nb);
     double xv = in.a + dk;
-    double rv = in.b - (A.cm * ms[0] + A.ck * ks[0]);
-    double d1 = c1 * dk + c2 * dv * rv;
+    double rv = in.b - (kk.cm * ms[0] + kk.ck * ks[0]);
+    double d1 = kk.c1 * dk + kk.c2 * dv * rv;
     if (LAST) {
-      x[i] = (TX)(out_scale * (xv + d1));
+      x.at(inst)[i] = (T)(kk.osc * (xv + d1));
     } else {
-      x[i] = (TX)xv;
-      r[i] = (T)rv;
-      dn[i] = (T)d1;
+      x.at(inst)[i] = (T)xv;
+      r.at(inst)[i] = (T)rv;
+      dn.at(inst)[i] = (T)d1;
     }
   }
 };
 
-// Start from a given x (stencil input x): r0 = b - A x, d0 = D^-1 r0 / theta.
+// Start from a given x (stencil input x): r0 = b - A x, d0 = D^-1 r0 it.
 template <class T>
 struct EpiChebStart {
   using In = In1;
-  Op A;
-  double inv_theta;
-  const T* b;
-  T* r;
-  T* d;
-  __device__ In load(int64_t i) const { return In{to_d(b[i])}; }
-  __device__ void store(int64_t i, int nb, const double* ms, const double* ks, const double*,
-                        const In& in) const {
-    double r0 = in.a - (A.cm * ms[0] + A.ck * ks[0]);
-    r[i] = (T)r0;
-    d[i] = (T)(dinv_at(A.dinv_int, nb) * r0 * inv_theta);
+  using K = OpK;
+  int lev;
+  Vec<const T> b;
+  Vec<T> r, d;
+  __device__ K prep(const InstCoef& C) const { return op_k(C, lev, -1, CF_ONE); }
+  __device__ In load(int inst, int64_t i) const { return In{to_d(b.at(inst)[i])}; }
+  __device__ void store(int inst, int64_t i, int nb, const double* ms, const double* ks,
+                        const double*, const In& in, const K& k) const {
+    double r0 = in.a - (k.cm * ms[0] + k.ck * ks[0]);
+    r.at(inst)[i] = (T)r0;
+    d.at(inst)[i] = (T)(dinv_at(k.dinv, nb) * r0 * k.it);
   }
 };
 
-// One Chebyshev iteration from x0 = 0: x = D^-1 b / theta (pointwise).
-template <class T, class TX>
+// One Chebyshev iteration from x0 = 0: x = D^-1 b it (pointwise).
+template <class T>
 struct EpiChebOne {
   using In = In0;
-  Op A;
-  double inv_theta, out_scale;
-  TX* x;
-  __device__ In load(int64_t) const { return In{}; }
-  __device__ void store(int64_t i, int nb, const double*, const double*, const double* cen,
-                        const In&) const {
-    x[i] = (TX)(out_scale * dinv_at(A.dinv_int, nb) * cen[0] * inv_theta);
+  using K = OpK;
+  int lev, osc;
+  Vec<T> x;
+  __device__ K prep(const InstCoef& C) const { return op_k(C, lev, -1, osc); }
+  __device__ In load(int, int64_t) const { return In{}; }
+  __device__ void store(int inst, int64_t i, int nb, const double*, const double*,
+                        const double* cen, const In&, const K& k) const {
+    x.at(inst)[i] = (T)(k.osc * dinv_at(k.dinv, nb) * cen[0] * k.it);
   }
 };
 
@@ -498,171 +563,158 @@ struct EpiChebOne {
 template <class T>
 struct EpiResid {
   using In = In1;
-  Op A;
-  const T* b;
-  T* r;
-  __device__ In load(int64_t i) const { return In{to_d(b[i])}; }
-  __device__ void store(int64_t i, int, const double* ms, const double* ks, const double*,
-                        const In& in) const {
-    r[i] = (T)(in.a - (A.cm * ms[0] + A.ck * ks[0]));
+  using K = OpK;
+  int lev;
+  Vec<const T> b;
+  Vec<T> r;
+  __device__ K prep(const InstCoef& C) const { return op_k(C, lev, -1, CF_ONE); }
+  __device__ In load(int inst, int64_t i) const { return In{to_d(b.at(inst)[i])}; }
+  __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
+                        const double*, const In& in, const K& k) const {
+    r.at(inst)[i] = (T)(in.a - (k.cm * ms[0] + k.ck * ks[0]));
   }
 };
 
-// Two stenciled fields s0, s1 and up to two outputs:
-//   out0 = add0 + c0[0] M s0 + c0[1] K s0 + c0[2] M s1 + c0[3] K s1
-//   out1 = add1 + c1[0] M s0 + c1[1] K s0 + c1[2] M s1 + c1[3] K s1   (if out1)
-template <class TO>
-struct EpiLin2 {
-  using In = In2;
-  const double* add0;
-  const double* add1;
-  double c0[4], c1[4];
-  TO* out0;
-  TO* out1;
-  __device__ In load(int64_t i) const {
-    return In{add0 ? add0[i] : 0.0, add1 ? add1[i] : 0.0};
-  }
-  __device__ void store(int64_t i, int, const double* ms, const double* ks, const double*,
-                        const In& in) const {
-    out0[i] = (TO)(in.a + c0[0] * ms[0] + c0[1] * ks[0] + c0[2] * ms[1] + c0[3] * ks[1]);
-    if (out1) out1[i] = (TO)(in.b + c1[0] * ms[0] + c1[1] * ks[0] + c1[2] * ms[1] + c1[3] * ks[1]);
-  }
-};
+template <class T>
+__global__ void __launch_bounds__(256)
+    k_add_inplace(Batch B, Vec<T> x, Vec<const T> d, int64_t n, int per) {
+  const int inst = blockIdx.x / per;
+  if (B.act && !B.act[inst]) return;
+  T* xi = x.at(inst);
+  const T* di = d.at(inst);
+  for (int64_t i = (int64_t)(blockIdx.x % per) * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)per * blockDim.x)
+    xi[i] = (T)(to_d(xi[i]) + to_d(di[i]));
+}
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <class TI, class TO>
-hipError_t launch_mass(const Grid& g, const TI* s, TO* out, double scale, hipStream_t st) {
-  EpiAxpy<TO, TO> e{nullptr, scale, 0.0, out};
-  return run_stencil<false>(g, s, e, st);
-}
-
 template <class TS, class TA, class TO>
-hipError_t launch_stencil_axpy(const Grid& g, const TS* s, const TA* add, double a, double b,
-                               TO* out, hipStream_t st) {
-  EpiAxpy<TA, TO> e{add, a, b, out};
-  return run_stencil<false>(g, s, e, st);
+hipError_t launch_stencil_axpy(const Grid& g, const Batch& B, Vec<const TS> s, Vec<const TA> add,
+                               double ca, int fa, double cb, int fb, Vec<TO> out, hipStream_t st) {
+  EpiAxpy<TA, TO> e{add, ca, cb, fa, fb, out};
+  return run_stencil<false>(g, B, s, e, st);
 }
 
-template <class T>
-__global__ void k_add_inplace(T* x, const T* d, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) x[i] = (T)(to_d(x[i]) + to_d(d[i]));
+template <class TS>
+hipError_t launch_stencil_lin2(const Grid& g, const Batch& B, Vec<const TS> s0, Vec<const TS> s1,
+                               Vec<const double> add0, Vec<const double> add1,
+                               const double (&c)[2][4], const int (&f)[2][4], Vec<double> out0,
+                               Vec<double> out1, hipStream_t st) {
+  EpiLin2<double> e;
+  e.add0 = add0;
+  e.add1 = add1;
+  for (int o = 0; o < 2; o++)
+    for (int q = 0; q < 4; q++) {
+      e.c[o][q] = c[o][q];
+      e.f[o][q] = f[o][q];
+    }
+  e.out0 = out0;
+  e.out1 = out1;
+  Src<TS, 2> src{{s0.p, s1.p}, {s0.s, s1.s}};
+  return run_stencil_n<false, TS, 2>(g, B, src, e, st);
 }
 
 template <class TB, class T>
-hipError_t launch_cheb_one(const Grid& g, const Op& A, double inv_theta, double out_scale,
-                           const TB* b, T* x, hipStream_t st) {
-  EpiChebOne<T, T> e{A, inv_theta, out_scale, x};
-  return run_stencil<true>(g, b, e, st);
+hipError_t launch_cheb_one(const Grid& g, const Batch& B, int lev, int osc, Vec<const TB> b,
+                           Vec<T> x, hipStream_t st) {
+  EpiChebOne<T> e{lev, osc, x};
+  return run_stencil<true>(g, B, b, e, st);
 }
 
 template <class TB, class T>
-hipError_t launch_cheb_first(const Grid& g, const Op& A, double inv_theta, double c1, double c2,
-                             double out_scale, bool last, const TB* b, T* x, T* r, T* d,
-                             hipStream_t st) {
+hipError_t launch_cheb_first(const Grid& g, const Batch& B, int lev, int osc, bool last,
+                             Vec<const TB> b, Vec<T> x, Vec<T> r, Vec<T> d, hipStream_t st) {
   if (last) {
-    EpiChebFirst<T, T, true> e{A, inv_theta, c1, c2, out_scale, x, r, d};
-    return run_stencil<true>(g, b, e, st);
+    EpiChebFirst<T, true> e{lev, osc, x, r, d};
+    return run_stencil<true>(g, B, b, e, st);
   }
-  EpiChebFirst<T, T, false> e{A, inv_theta, c1, c2, 1.0, x, r, d};
-  return run_stencil<true>(g, b, e, st);
+  EpiChebFirst<T, false> e{lev, osc, x, r, d};
+  return run_stencil<true>(g, B, b, e, st);
 }
 
 template <class T>
-hipError_t launch_cheb_step(const Grid& g, const Op& A, double c1, double c2, double out_scale,
-                            bool last, T* x, T* r, const T* din, T* dout, hipStream_t st) {
+hipError_t launch_cheb_step(const Grid& g, const Batch& B, int lev, int k, int osc, bool last,
+                            Vec<T> x, Vec<T> r, Vec<const T> din, Vec<T> dout, hipStream_t st) {
+  if (k < 0 || k >= kMaxCheb) return hipErrorInvalidValue;
   if (last) {
-    EpiChebStep<T, T, true> e{A, c1, c2, out_scale, x, x, r, dout};
-    return run_stencil<false>(g, din, e, st);
+    EpiChebStep<T, true> e{lev, k, osc, x, r, dout};
+    return run_stencil<false>(g, B, din, e, st);
   }
-  EpiChebStep<T, T, false> e{A, c1, c2, 1.0, x, x, r, dout};
-  return run_stencil<false>(g, din, e, st);
+  EpiChebStep<T, false> e{lev, k, osc, x, r, dout};
+  return run_stencil<false>(g, B, din, e, st);
 }
 
 template <class T>
-hipError_t launch_cheb_start(const Grid& g, const Op& A, double inv_theta, const T* b,
-                             const T* x, T* r, T* d, hipStream_t st) {
-  EpiChebStart<T> e{A, inv_theta, b, r, d};
-  return run_stencil<false>(g, x, e, st);
+hipError_t launch_cheb_start(const Grid& g, const Batch& B, int lev, Vec<const T> b,
+                             Vec<const T> x, Vec<T> r, Vec<T> d, hipStream_t st) {
+  EpiChebStart<T> e{lev, b, r, d};
+  return run_stencil<false>(g, B, x, e, st);
 }
 
 template <class T>
-hipError_t launch_add_inplace(T* x, const T* d, int64_t n, hipStream_t st) {
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_add_inplace<T>, dim3((unsigned)blocks), dim3(256), 0, st, x, d, n);
+hipError_t launch_add_inplace(const Batch& B, Vec<T> x, Vec<const T> d, int64_t n,
+                              hipStream_t st) {
+  int per = (int)std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 4096);
+  hipLaunchKernelGGL(k_add_inplace<T>, dim3((unsigned)(per * B.count)), dim3(256), 0, st, B, x, d,
+                     n, per);
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_resid(const Grid& g, const Op& A, const T* b, const T* x, T* r,
-                        hipStream_t st) {
-  EpiResid<T> e{A, b, r};
-  return run_stencil<false>(g, x, e, st);
+hipError_t launch_resid(const Grid& g, const Batch& B, int lev, Vec<const T> b, Vec<const T> x,
+                        Vec<T> r, hipStream_t st) {
+  EpiResid<T> e{lev, b, r};
+  return run_stencil<false>(g, B, x, e, st);
 }
-
-template <class TS>
-hipError_t launch_stencil_lin2(const Grid& g, const TS* s0, const TS* s1, const double* add0,
-                               const double* add1, const double* c0, const double* c1,
-                               double* out0, double* out1, hipStream_t st) {
-  EpiLin2<double> e{add0, add1, {c0[0], c0[1], c0[2], c0[3]},
-                    {c1 ? c1[0] : 0.0, c1 ? c1[1] : 0.0, c1 ? c1[2] : 0.0, c1 ? c1[3] : 0.0},
-                    out0, out1};
-  Src<TS, 2> src{{s0, s1}};
-  return run_stencil_n<false, TS, 2>(g, src, e, st);
-}
-
-template hipError_t launch_stencil_lin2<double>(const Grid&, const double*, const double*,
-                                                const double*, const double*, const double*,
-                                                const double*, double*, double*, hipStream_t);
-template hipError_t launch_stencil_lin2<float>(const Grid&, const float*, const float*,
-                                               const double*, const double*, const double*,
-                                               const double*, double*, double*, hipStream_t);
 
 // Explicit instantiations.
-template hipError_t launch_mass<double, double>(const Grid&, const double*, double*, double,
+template hipError_t launch_stencil_axpy<double, double, double>(const Grid&, const Batch&,
+                                                                Vec<const double>,
+                                                                Vec<const double>, double, int,
+                                                                double, int, Vec<double>,
+                                                                hipStream_t);
+template hipError_t launch_stencil_axpy<float, float, float>(const Grid&, const Batch&,
+                                                             Vec<const float>, Vec<const float>,
+                                                             double, int, double, int,
+                                                             Vec<float>, hipStream_t);
+template hipError_t launch_stencil_axpy<float, double, float>(const Grid&, const Batch&,
+                                                              Vec<const float>,
+                                                              Vec<const double>, double, int,
+                                                              double, int, Vec<float>,
+                                                              hipStream_t);
+template hipError_t launch_stencil_lin2<double>(const Grid&, const Batch&, Vec<const double>,
+                                                Vec<const double>, Vec<const double>,
+                                                Vec<const double>, const double (&)[2][4],
+                                                const int (&)[2][4], Vec<double>, Vec<double>,
                                                 hipStream_t);
-template hipError_t launch_mass<float, float>(const Grid&, const float*, float*, double,
-                                              hipStream_t);
-template hipError_t launch_stencil_axpy<double, double, double>(const Grid&, const double*,
-                                                                const double*, double, double,
-                                                                double*, hipStream_t);
-template hipError_t launch_stencil_axpy<float, double, float>(const Grid&, const float*,
-                                                              const double*, double, double,
-                                                              float*, hipStream_t);
-template hipError_t launch_stencil_axpy<double, double, float>(const Grid&, const double*,
-                                                               const double*, double, double,
-                                                               float*, hipStream_t);
-template hipError_t launch_stencil_axpy<float, double, double>(const Grid&, const float*,
-                                                               const double*, double, double,
-                                                               double*, hipStream_t);
-template hipError_t launch_stencil_axpy<float, float, float>(const Grid&, const float*,
-                                                             const float*, double, double,
-                                                             float*, hipStream_t);
+template hipError_t launch_stencil_lin2<float>(const Grid&, const Batch&, Vec<const float>,
+                                               Vec<const float>, Vec<const double>,
+                                               Vec<const double>, const double (&)[2][4],
+                                               const int (&)[2][4], Vec<double>, Vec<double>,
+                                               hipStream_t);
 #define OKD_CHEB_TB(TB, T)                                                                    \
-  template hipError_t launch_cheb_one<TB, T>(const Grid&, const Op&, double, double, const TB*,  \
-                                             T*, hipStream_t);                                   \
-  template hipError_t launch_cheb_first<TB, T>(const Grid&, const Op&, double, double, double,   \
-                                               double, bool, const TB*, T*, T*, T*, hipStream_t);
+  template hipError_t launch_cheb_one<TB, T>(const Grid&, const Batch&, int, int,              \
+                                             Vec<const TB>, Vec<T>, hipStream_t);              \
+  template hipError_t launch_cheb_first<TB, T>(const Grid&, const Batch&, int, int, bool,      \
+                                               Vec<const TB>, Vec<T>, Vec<T>, Vec<T>,          \
+                                               hipStream_t);
 OKD_CHEB_TB(double, double)
 OKD_CHEB_TB(float, float)
 OKD_CHEB_TB(double, float)
 #undef OKD_CHEB_TB
-#define OKD_CHEB_T(T)                                                                           \
-  template hipError_t launch_cheb_step<T>(const Grid&, const Op&, double, double, double, bool,  \
-                                          T*, T*, const T*, T*, hipStream_t);                    \
-  template hipError_t launch_cheb_start<T>(const Grid&, const Op&, double, const T*, const T*,   \
-                                           T*, T*, hipStream_t);                                 \
-  template hipError_t launch_add_inplace<T>(T*, const T*, int64_t, hipStream_t);
+#define OKD_CHEB_T(T)                                                                         \
+  template hipError_t launch_cheb_step<T>(const Grid&, const Batch&, int, int, int, bool,      \
+                                          Vec<T>, Vec<T>, Vec<const T>, Vec<T>, hipStream_t);  \
+  template hipError_t launch_cheb_start<T>(const Grid&, const Batch&, int, Vec<const T>,      \
+                                           Vec<const T>, Vec<T>, Vec<T>, hipStream_t);         \
+  template hipError_t launch_add_inplace<T>(const Batch&, Vec<T>, Vec<const T>, int64_t,       \
+                                            hipStream_t);                                      \
+  template hipError_t launch_resid<T>(const Grid&, const Batch&, int, Vec<const T>,            \
+                                      Vec<const T>, Vec<T>, hipStream_t);
 OKD_CHEB_T(double)
 OKD_CHEB_T(float)
 #undef OKD_CHEB_T
-template hipError_t launch_resid<double>(const Grid&, const Op&, const double*, const double*,
-                                         double*, hipStream_t);
-template hipError_t launch_resid<float>(const Grid&, const Op&, const float*, const float*,
-                                        float*, hipStream_t);
 
 }  // namespace okd

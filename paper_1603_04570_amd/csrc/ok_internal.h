@@ -1,4 +1,14 @@
 // Internal declarations shared by the HIP sources of libok.so.
+//
+// Every kernel works on a *class* of B independent instances that share the
+// grid (d, N) and the precision: the launch grid is (blocks of one instance)
+// x B, block b serves instance b / (blocks of one instance), every vector
+// argument is a (base pointer, element stride between instances) pair, the
+// per-instance constants live in a device table of InstCoef records, and an
+// optional per-instance `act` flag makes the blocks of an inactive instance
+// return at once.  A single solve is the class with B = 1.  The arithmetic
+// of one instance does not depend on B, on the other instances or on the
+// launch shape, so batched results equal solo results bit for bit.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,8 +21,8 @@
 namespace okd {
 
 constexpr int kMaxLevels = 16;
-constexpr int kThreads = 256;          // node-stencil and vector kernels
-constexpr int kRedBlocks = 1024;       // fixed grid of every reduction (determinism)
+constexpr int kThreads = 256;   // node-stencil and vector kernels
+constexpr int kMaxCheb = 32;    // Chebyshev iterations per application
 
 // ---------------------------------------------------------------------------
 // Geometry of one uniform Q1 grid level.
@@ -25,137 +35,199 @@ struct Grid {
   int64_t nodes;  // nn^dim
   double h;       // 1/N
 };
-
 Grid make_grid(int dim, int N);
+
+// A vector argument of a class launch: instance i starts at p + i*s.
+template <class T>
+struct Vec {
+  T* p;
+  int64_t s;
+  __host__ __device__ T* at(int i) const { return p + (int64_t)i * s; }
+  __host__ __device__ bool null() const { return p == nullptr; }
+};
+template <class T>
+inline Vec<T> vec(T* p, int64_t s) {
+  return Vec<T>{p, s};
+}
+template <class T>
+inline Vec<const T> cvec(const T* p, int64_t s) {
+  return Vec<const T>{p, s};
+}
+
+// Per-level operator A = cm M + ck K and its Chebyshev-Jacobi coefficients.
+// diag(A) at a node = dint * 2^-(number of coordinates on the boundary),
+// dinv = 1/dint.  Iteration k of Saad's Alg. 12.1 forms
+// d_{k+1} = c1[k] d_k + c2[k] D^-1 r_{k+1};  it = 1/theta of the interval.
+struct LevelCoef {
+  double cm, ck, dinv, it;
+  double c1[kMaxCheb], c2[kMaxCheb];
+};
+
+// Per-instance constants, one record per instance in device memory.
+struct InstCoef {
+  LevelCoef mass;             // Chebyshev on M on the finest grid
+  LevelCoef lev[kMaxLevels];  // M_l + alpha K_l on each multigrid level
+  double alpha;               // eps sqrt(c)
+  double sA, inv_sA;          // 1 + dt theta sigma and its inverse
+  double dth;                 // dt theta
+  double e2;                  // eps^2
+  double dt, sigma, theta, m;
+  double rtol, atol;
+};
+
+// Named per-instance scalars for stencil epilogue coefficients.
+enum CoefField { CF_ONE = 0, CF_SA = 1, CF_DTH = 2, CF_E2 = 3, CF_INV_SA = 4 };
+__host__ __device__ inline double coef_field(const InstCoef& c, int f) {
+  switch (f) {
+    case CF_SA: return c.sA;
+    case CF_DTH: return c.dth;
+    case CF_E2: return c.e2;
+    case CF_INV_SA: return c.inv_sA;
+    default: return 1.0;
+  }
+}
+
+// Class of B instances: constants table and activity flags (may be null).
+struct Batch {
+  int count;
+  const InstCoef* coef;
+  const int* act;
+};
 
 // Launch shape of the z-streaming node-stencil kernels on a grid.
 struct StencilShape {
-  int items;      // nodes per thread per plane (1,2,4,8)
-  int chunk;      // nodes per block per plane (kThreads*items)
-  int nchunks;    // chunks per plane
-  int zc;         // planes per block (3D)
-  int nzc;        // z-chunks
-  int blocks;     // nchunks*nzc
+  int items;    // nodes per thread per plane (1,2,4,8)
+  int chunk;    // nodes per block per plane (kThreads*items)
+  int nchunks;  // chunks per plane
+  int zc;       // planes per block
+  int nzc;      // z-chunks
+  int blocks;   // nchunks*nzc (per instance)
 };
 StencilShape stencil_shape(const Grid& g, int nf, int word);
 // Launch-shape table of the stencil kernels, keyed by (dim, nodes per
 // direction, stenciled fields, bytes per stenciled word); items <= 0 removes
-// the entry (back to the heuristic).
-// Results do not depend on the shape: every node is computed by the same
-// arithmetic in the same order whatever the tiling.
+// the entry (back to the heuristic).  Results do not depend on the shape.
 void stencil_tune_set(int dim, int nn, int nf, int word, int items, int zc);
 
-// Operator A = cm*M + ck*K on a grid and its Jacobi diagonal:
-// diag(A) at a node = dint * 2^-(number of coordinates on the boundary).
-struct Op {
-  double cm, ck;
-  double dinv_int;  // 1/dint
-};
-Op make_op(const Grid& g, double cm, double ck);
-
-// Chebyshev coefficients of Saad's Alg. 12.1 for an interval [a,b].
-struct Cheb {
-  double theta, delta, sigma1;
-};
+// Reduction blocks per instance for vectors of length n (a fixed function of
+// n, so solo and batched runs sum in the same order).
+int red_blocks(int64_t n);
+constexpr int kMaxRedBlocks = 1024;
 
 // ---------------------------------------------------------------------------
-// Kernel launchers (asynchronous on `st`).  T is the storage type of the
-// preconditioner vectors (double or float); arithmetic is FP64.
+// Node-stencil launchers (asynchronous on `st`).  `lev` selects the operator
+// of an instance: -1 = M on the finest grid (Chebyshev for A~^-1), l >= 0 =
+// M_l + alpha K_l.  `osc` selects the output scale (a CoefField).  T is the
+// storage type of the preconditioner vectors.
 // ---------------------------------------------------------------------------
-// out = scale * (M s)
-template <class TI, class TO>
-hipError_t launch_mass(const Grid& g, const TI* s, TO* out, double scale, hipStream_t st);
-
-// Chebyshev-Jacobi building blocks (Saad, Alg. 12.1), on A with D = diag(A):
-// one iteration from x0 = 0: x = out_scale * D^-1 b / theta
+// out = add + a*(M s) + b*(K s), a = ca*field(fa), b = cb*field(fb)
+template <class TS, class TA, class TO>
+hipError_t launch_stencil_axpy(const Grid& g, const Batch& B, Vec<const TS> s, Vec<const TA> add,
+                               double ca, int fa, double cb, int fb, Vec<TO> out, hipStream_t st);
+// Two stenciled fields, up to two outputs (out1 may be null); coefficient
+// slot q of output o is c[o][q] * field(f[o][q]) for
+//   out_o = add_o + c0 M s0 + c1 K s0 + c2 M s1 + c3 K s1
+template <class TS>
+hipError_t launch_stencil_lin2(const Grid& g, const Batch& B, Vec<const TS> s0, Vec<const TS> s1,
+                               Vec<const double> add0, Vec<const double> add1,
+                               const double (&c)[2][4], const int (&f)[2][4], Vec<double> out0,
+                               Vec<double> out1, hipStream_t st);
+// Chebyshev-Jacobi building blocks (Saad, Alg. 12.1):
+// one iteration from x0 = 0: x = oscale * D^-1 b * it
 template <class TB, class T>
-hipError_t launch_cheb_one(const Grid& g, const Op& A, double inv_theta, double out_scale,
-                           const TB* b, T* x, hipStream_t st);
-// iteration 0 from x0 = 0: d0 = D^-1 b/theta, r1 = b - A d0, d1 = c1 d0 + c2 D^-1 r1;
-// writes x = d0, r = r1, d = d1, or (last) x = out_scale*(d0 + d1) only.
+hipError_t launch_cheb_one(const Grid& g, const Batch& B, int lev, int osc, Vec<const TB> b,
+                           Vec<T> x, hipStream_t st);
+// iteration 0 from x0 = 0: d0 = D^-1 b it, r1 = b - A d0, d1 = c1[0] d0 + c2[0] D^-1 r1;
+// writes x = d0, r = r1, d = d1, or (last) x = oscale*(d0 + d1) only.
 template <class TB, class T>
-hipError_t launch_cheb_first(const Grid& g, const Op& A, double inv_theta, double c1, double c2,
-                             double out_scale, bool last, const TB* b, T* x, T* r, T* d,
-                             hipStream_t st);
-// iteration k: x += d_k, r -= A d_k, d_{k+1} = c1 d_k + c2 D^-1 r (into dout);
-// last: x = out_scale*(x + d_k + d_{k+1}) only.
+hipError_t launch_cheb_first(const Grid& g, const Batch& B, int lev, int osc, bool last,
+                             Vec<const TB> b, Vec<T> x, Vec<T> r, Vec<T> d, hipStream_t st);
+// iteration k: x += d_k, r -= A d_k, d_{k+1} = c1[k] d_k + c2[k] D^-1 r (into dout);
+// last: x = oscale*(x + d_k + d_{k+1}) only.
 template <class T>
-hipError_t launch_cheb_step(const Grid& g, const Op& A, double c1, double c2, double out_scale,
-                            bool last, T* x, T* r, const T* din, T* dout, hipStream_t st);
-// start from a given x: r = b - A x, d = D^-1 r / theta (x unchanged)
+hipError_t launch_cheb_step(const Grid& g, const Batch& B, int lev, int k, int osc, bool last,
+                            Vec<T> x, Vec<T> r, Vec<const T> din, Vec<T> dout, hipStream_t st);
+// start from a given x: r = b - A x, d = D^-1 r it (x unchanged)
 template <class T>
-hipError_t launch_cheb_start(const Grid& g, const Op& A, double inv_theta, const T* b,
-                             const T* x, T* r, T* d, hipStream_t st);
+hipError_t launch_cheb_start(const Grid& g, const Batch& B, int lev, Vec<const T> b,
+                             Vec<const T> x, Vec<T> r, Vec<T> d, hipStream_t st);
+// x += d
 template <class T>
-hipError_t launch_add_inplace(T* x, const T* d, int64_t n, hipStream_t st);
+hipError_t launch_add_inplace(const Batch& B, Vec<T> x, Vec<const T> d, int64_t n,
+                              hipStream_t st);
 // r = b - A x
 template <class T>
-hipError_t launch_resid(const Grid& g, const Op& A, const T* b, const T* x, T* r, hipStream_t st);
-// out = add + a*(M s) + b*(K s)  (add may be null)
-template <class TS, class TA, class TO>
-hipError_t launch_stencil_axpy(const Grid& g, const TS* s, const TA* add, double a, double b,
-                               TO* out, hipStream_t st);
+hipError_t launch_resid(const Grid& g, const Batch& B, int lev, Vec<const T> b, Vec<const T> x,
+                        Vec<T> r, hipStream_t st);
 
-// Two stenciled fields, up to two outputs (out1 may be null):
-//   out0 = add0 + c0[0] M s0 + c0[1] K s0 + c0[2] M s1 + c0[3] K s1
-//   out1 = add1 + c1[0] M s0 + c1[1] K s0 + c1[2] M s1 + c1[3] K s1
-template <class TS>
-hipError_t launch_stencil_lin2(const Grid& g, const TS* s0, const TS* s1, const double* add0,
-                               const double* add1, const double* c0, const double* c1,
-                               double* out0, double* out1, hipStream_t st);
-
-// Element quadrature kernels on the finest grid:
-// mode 0: out = alpha * G(u,x) + beta * add,  G_i = int u^2 x phi_i  (add may be null)
-//         (M_E(u) x = 3 G(u,x) - M x)
+// Element quadrature on the finest grid:
+// mode 0: out = alpha * G(u,x) + beta * add,  G_i = int u^2 x phi_i   (M_E(u) x = 3G - M x)
 // mode 1: out = alpha * N(u),  N_i = int (u^3 - u) phi_i
 template <class TX, class TO>
-hipError_t launch_element(const Grid& g, int mode, const double* u, const TX* x,
-                          const double* add, double alpha, double beta, TO* out, hipStream_t st);
+hipError_t launch_element(const Grid& g, const Batch& B, int mode, Vec<const double> u,
+                          Vec<const TX> x, Vec<const double> add, double alpha, double beta,
+                          Vec<TO> out, hipStream_t st);
 
-// Multigrid transfers and the coarse solve.
+// Multigrid transfers and the exact coarse solve (M + alpha K)^-1 (DCT-I basis).
 template <class T>
-hipError_t launch_restrict(const Grid& fine, const Grid& coarse, const T* r, T* bc, hipStream_t st);
+hipError_t launch_restrict(const Grid& fine, const Grid& coarse, const Batch& B, Vec<const T> r,
+                           Vec<T> bc, hipStream_t st);
 template <class T>
-hipError_t launch_prolong_add(const Grid& fine, const Grid& coarse, const T* ec, T* x,
-                              hipStream_t st);
-// Exact (M + alpha K)^-1 on a small grid by the DCT-I eigenbasis.
+hipError_t launch_prolong_add(const Grid& fine, const Grid& coarse, const Batch& B,
+                              Vec<const T> ec, Vec<T> x, hipStream_t st);
 template <class T>
-hipError_t launch_coarse_solve(const Grid& g, double alpha, const T* b, T* x, hipStream_t st);
+hipError_t launch_coarse_solve(const Grid& g, const Batch& B, Vec<const T> b, Vec<T> x,
+                               hipStream_t st);
 
+// ---------------------------------------------------------------------------
 // Vector and Krylov kernels (FP64 unless templated).
+// ---------------------------------------------------------------------------
 template <class TI, class TO>
-hipError_t launch_copy_scale(const TI* in, TO* out, double a, int64_t n, hipStream_t st);
-hipError_t launch_axpby(double a, const double* x, double b, const double* y, double* out,
-                        int64_t n, hipStream_t st);
-hipError_t launch_fill(double* x, double v, int64_t n, hipStream_t st);
-// partials[k] (kRedBlocks) of sum a*b
-hipError_t launch_dot_partial(const double* a, const double* b, int64_t n, double* partials,
-                              hipStream_t st);
-// out[0] = sum(partials), out[1] = sqrt(out[0])
-hipError_t launch_reduce_final(const double* partials, double* out, hipStream_t st);
-// One fused modified Gram-Schmidt step: h = sum(pin); Hij = h; w -= h*vi;
-// pout = partials of <w, vnext> (vnext == nullptr: <w, w>).
-hipError_t launch_mgs_step(double* w, const double* vi, const double* vnext, int64_t n,
-                           const double* pin, double* pout, double* Hij, hipStream_t st);
-// Givens update of Hessenberg column j (column-major H[col*(m+1)+row]); writes
-// scal[0] = |g_{j+1}|, scal[1] = h_{j+1,j}, scal[2] = 1/h_{j+1,j}.
-hipError_t launch_givens(int j, int m, double* H, double* cs, double* sn, double* g,
-                         const double* pnorm, double* scal, hipStream_t st);
-// v = w * scal[2]
-hipError_t launch_scale_by(const double* w, double* v, const double* scal, int64_t n,
-                           hipStream_t st);
-// y = H(0:k,0:k)^-1 g(0:k), then x += sum_j y_j Z_j
+hipError_t launch_copy_scale(const Batch& B, Vec<const TI> in, Vec<TO> out, double a, int64_t n,
+                             hipStream_t st);
+// out = a*x + b*y
+hipError_t launch_axpby(const Batch& B, double a, Vec<const double> x, double b,
+                        Vec<const double> y, Vec<double> out, int64_t n, hipStream_t st);
+hipError_t launch_fill(const Batch& B, Vec<double> x, double v, int64_t n, hipStream_t st);
+// partials (red_blocks(n) per instance) of sum a*b
+hipError_t launch_dot_partial(const Batch& B, Vec<const double> a, Vec<const double> b,
+                              int64_t n, Vec<double> partials, hipStream_t st);
+// out[0] = sum(partials), out[1] = sqrt(out[0])   (partials of length red_blocks(n))
+hipError_t launch_reduce_final(const Batch& B, Vec<const double> partials, int64_t n,
+                               Vec<double> out, hipStream_t st);
+// Fused modified Gram-Schmidt step: h = sum(pin); Hij = h; w -= h*vi;
+// pout = partials of <w, vnext> (vnext null: <w, w>).
+hipError_t launch_mgs_step(const Batch& B, Vec<double> w, Vec<const double> vi,
+                           Vec<const double> vnext, int64_t n, Vec<const double> pin,
+                           Vec<double> pout, Vec<double> Hij, hipStream_t st);
+// FGMRES bookkeeping of one instance (all in device memory, per instance):
+//   kr: [0] ||b||, [1] tol = rtol ||b||, [2] beta, [3] |g_{j+1}|, [4] h_{j+1,j},
+//       [5] 1/h_{j+1,j}, [6] iterations of this cycle (k), [7] status flags
+// Givens update of Hessenberg column j (column-major, leading dim m+1); an
+// instance whose |g_{j+1}| <= tol or h_{j+1,j} == 0 is marked converged
+// (act = 0, status bit 1); a non-finite value sets status bit 2 and act = 0.
+hipError_t launch_givens(const Batch& B, int* act, int j, int m, Vec<double> H, Vec<double> cs,
+                         Vec<double> sn, Vec<double> g, Vec<const double> pnorm, int64_t n,
+                         Vec<double> kr, hipStream_t st);
+// v = w * kr[5]  (normalise the new Arnoldi vector)
+hipError_t launch_scale_by(const Batch& B, Vec<const double> w, Vec<double> v,
+                           Vec<const double> kr, int64_t n, hipStream_t st);
+// v = b / nrm[1]
+hipError_t launch_scale_inv(const Batch& B, Vec<const double> b, Vec<double> v,
+                            Vec<const double> nrm, int64_t n, hipStream_t st);
+// Start of a cycle: g = [beta, 0, ...], kr[6] = 0 (with beta = nrm[1]).
+hipError_t launch_cycle_init(const Batch& B, int m, Vec<double> g, Vec<const double> nrm,
+                             Vec<double> kr, hipStream_t st);
+// y = H(0:k,0:k)^-1 g(0:k) with k = kr[6], then x += sum_j y_j Z_j
 template <class TZ>
-hipError_t launch_lsq_update(int k, int m, const double* H, const double* g, double* y,
-                             const TZ* Z, int64_t zstride, double* x, int64_t n, hipStream_t st);
-// V0 = b * (1/scal), with scal = ||b|| read from device
-hipError_t launch_scale_inv(const double* b, double* v, const double* nrm, int64_t n,
-                            hipStream_t st);
+hipError_t launch_lsq_update(const Batch& B, int m, Vec<const double> H, Vec<const double> g,
+                             Vec<double> y, Vec<const double> kr, Vec<const TZ> Z,
+                             int64_t zstride, Vec<double> x, int64_t n, hipStream_t st);
 
-// Residual assembly helpers (FP64):
+// Residual assembly helper (FP64):
 // t1 = (u - un) + dt*sigma*(th*u + (1-th)*un - m),  t2 = dt*(th*w + (1-th)*wn)
-hipError_t launch_residual_prep(const double* u, const double* un, const double* w,
-                                const double* wn, double dt, double sigma, double th, double m,
-                                double* t1, double* t2, int64_t n, hipStream_t st);
+hipError_t launch_residual_prep(const Batch& B, Vec<const double> u, Vec<const double> un,
+                                Vec<const double> w, Vec<const double> wn, Vec<double> t1,
+                                Vec<double> t2, int64_t n, hipStream_t st);
 
 }  // namespace okd

@@ -90,6 +90,16 @@ def load():
     lib.ok_profile_enable.argtypes = [vp, i32]
     lib.ok_profile_read.argtypes = [vp, P(C.c_int64), P(d), P(d)]
     lib.ok_destroy.argtypes = [vp]
+    lib.ok_batch_workspace_bytes.argtypes = [P(Params), i32, P(C.c_size_t)]
+    lib.ok_batch_create.argtypes = [P(Params), i32, vp, C.c_size_t, vp, P(vp)]
+    lib.ok_batch_set_state.argtypes = [vp, i32, vp, vp, vp]
+    lib.ok_batch_get_state.argtypes = [vp, i32, vp, vp, vp]
+    lib.ok_batch_timestep.argtypes = [vp, i32, P(Stats), vp]
+    lib.ok_batch_autotune.argtypes = [vp, vp, P(i32)]
+    lib.ok_batch_classes.argtypes = [vp]
+    lib.ok_batch_destroy.argtypes = [vp]
+    lib.ok_batch_last_error.argtypes = [vp]
+    lib.ok_batch_last_error.restype = C.c_char_p
     lib.ok_error_string.argtypes = [C.c_int]
     lib.ok_error_string.restype = C.c_char_p
     lib.ok_last_error.argtypes = [vp]
@@ -238,6 +248,78 @@ class Problem:
         self._check(self.lib.ok_profile_read(self.ctx, C.byref(n), C.byref(ms), C.byref(by)),
                     "ok_profile_read")
         return n.value, ms.value, by.value
+
+
+class Batch:
+    """Many independent problems (ok_batch_*) sharing one torch-owned workspace."""
+
+    def __init__(self, params_list, device="cuda", stream=None):
+        import torch
+        self.lib = load()
+        self.count = len(params_list)
+        self.params = (Params * self.count)(*params_list)
+        self.device = torch.device(device)
+        self.stream = stream
+        b = C.c_size_t()
+        st = self.lib.ok_batch_workspace_bytes(self.params, self.count, C.byref(b))
+        if st:
+            raise OkError(st, "ok_batch_workspace_bytes")
+        self.ws_bytes = b.value
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self.ctx = C.c_void_p()
+        st = self.lib.ok_batch_create(self.params, self.count, C.c_void_p(base + off),
+                                      C.c_size_t(self.ws_bytes), _stream(stream),
+                                      C.byref(self.ctx))
+        if st:
+            raise OkError(st, "ok_batch_create")
+        self.nodes = [(p.n + 1) ** p.dim for p in params_list]
+
+    def _check(self, st, what):
+        if st:
+            raise OkError(st, f"{what}: {self.lib.ok_batch_last_error(self.ctx).decode()}")
+
+    def classes(self):
+        return self.lib.ok_batch_classes(self.ctx)
+
+    def set_state(self, i, u, w):
+        self._check(self.lib.ok_batch_set_state(self.ctx, i, _ptr(u), _ptr(w),
+                                                _stream(self.stream)), "ok_batch_set_state")
+
+    def get_state(self, i, u=None, w=None):
+        import torch
+        if u is None:
+            u = torch.empty(self.nodes[i], dtype=torch.float64, device=self.device)
+        if w is None:
+            w = torch.empty(self.nodes[i], dtype=torch.float64, device=self.device)
+        self._check(self.lib.ok_batch_get_state(self.ctx, i, _ptr(u), _ptr(w),
+                                                _stream(self.stream)), "ok_batch_get_state")
+        return u, w
+
+    def timestep(self, nsteps=1, check=True):
+        stats = (Stats * self.count)()
+        st = self.lib.ok_batch_timestep(self.ctx, nsteps, stats, _stream(self.stream))
+        if check:
+            self._check(st, "ok_batch_timestep")
+        return list(stats)
+
+    def autotune(self):
+        n = C.c_int32()
+        self._check(self.lib.ok_batch_autotune(self.ctx, _stream(self.stream), C.byref(n)),
+                    "ok_batch_autotune")
+        return n.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.ok_batch_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def error_string(status: int) -> str:

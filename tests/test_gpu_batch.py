@@ -1,0 +1,78 @@
+"""Batched sweeps: many independent instances in grouped, lockstep launches.
+
+Each instance's result in the batch must equal its solo run bit for bit
+(same kernels, same per-instance arithmetic and reduction order), with the
+same Newton/FGMRES iteration counts, and the solo runs agree with the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle.okref import Oracle
+from paper_1603_04570_amd.inputs import noise_state, sweep_instance
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def params_for(spec, precision):
+    from paper_1603_04570_amd import ok
+    return ok.default_params(dim=spec["dim"], n=spec["n"], eps=spec["eps"], sigma=spec["sigma"],
+                             m=spec["m"], dt=spec["dt"], theta=spec["theta"], precision=precision)
+
+
+def run_batch_and_solo(specs, precision, steps=1):
+    from paper_1603_04570_amd import ok
+    plist = [params_for(s, precision) for s in specs]
+    B = ok.Batch(plist)
+    init = []
+    for i, s in enumerate(specs):
+        u0, w0 = noise_state(s["dim"], s["n"], s["m"], s["seed"])
+        init.append((u0, w0))
+        B.set_state(i, torch.from_numpy(u0).cuda(), torch.from_numpy(w0).cuda())
+    bst = B.timestep(steps)
+    out = []
+    for i, s in enumerate(specs):
+        ub, wb = B.get_state(i)
+        P = ok.Problem(plist[i])
+        u = torch.from_numpy(init[i][0]).cuda()
+        w = torch.from_numpy(init[i][1]).cuda()
+        sst = P.timestep(u, w, steps)
+        out.append((ub.cpu().numpy(), wb.cpu().numpy(), u.cpu().numpy(), w.cpu().numpy(),
+                    bst[i], sst))
+    return B, out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_solo_2d_sweep(precision):
+    specs = [sweep_instance(i, sizes=(32, 64, 128)) for i in range(8)]
+    print("batch 2D sweep", [s["n"] for s in specs], flush=True)
+    B, out = run_batch_and_solo(specs, precision)
+    assert B.classes() == len({s["n"] for s in specs})
+    for (ub, wb, us, ws, bs, ss), s in zip(out, specs):
+        assert bs.its() == ss.its(), (s, bs.its(), ss.its())
+        assert np.array_equal(ub, us) and np.array_equal(wb, ws), s
+
+
+def test_batch_mixed_dims_two_steps():
+    specs = [sweep_instance(0, sizes=(64,)), dict(dim=3, n=16, eps=0.02, sigma=100.0, m=0.1,
+                                                 theta=1.0, dt=2e-4, seed=9),
+             sweep_instance(1, sizes=(64,)), dict(dim=3, n=16, eps=0.03, sigma=30.0, m=-0.2,
+                                                 theta=1.0, dt=4e-4, seed=10)]
+    print("batch mixed dims", flush=True)
+    B, out = run_batch_and_solo(specs, 0, steps=2)
+    assert B.classes() == 2
+    for (ub, wb, us, ws, bs, ss), s in zip(out, specs):
+        assert bs.its() == ss.its()
+        assert np.array_equal(ub, us) and np.array_equal(wb, ws)
+
+
+def test_batch_instance_matches_oracle():
+    specs = [sweep_instance(i, sizes=(32, 64)) for i in range(3)]
+    B, out = run_batch_and_solo(specs, 0)
+    for (ub, wb, _, _, bs, _), s in zip(out, specs):
+        o = Oracle(2, s["n"], s["eps"], s["sigma"], s["m"], s["dt"], s["theta"])
+        u0, w0 = noise_state(2, s["n"], s["m"], s["seed"])
+        uo, wo, info, st = o.timestep(u0, w0, 1)
+        assert st == 0 and bs.its() == info.its()
+        assert np.linalg.norm(ub - uo) / np.linalg.norm(uo) < 1e-10
+        assert np.linalg.norm(wb - wo) / np.linalg.norm(wo) < 1e-10
