@@ -642,6 +642,7 @@ int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,
     for (int i = 0; i < c.B; i++)
       if (c.h_part[i]) c.out[i] = InstOut{0, 0, 0, c.out[i].fnorm, 0.0};
     if (!any(c.h_part)) continue;
+    if (push_part(c, st)) return OK_E_HIP;
     const Batch B = c.batch(c.part);
     OKE(c, launch_fill(B, x[k], 0.0, c.n2(), st));
     OKE(c, launch_dot_partial(B, b[k], b[k], c.n2(), vec(c.pA, (int64_t)kMaxRedBlocks), st));
