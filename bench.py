@@ -8,6 +8,17 @@ configured synthetic field.  Prints ONE JSON line.
 Default workload: 3D unit cube, Q1 hex on a uniform 128^3 mesh (2,146,689
 nodes, 4,293,378 DOFs), eps=0.01, sigma=1000, m=0.1, theta=1, dt=2e-5,
 u0 = m + 0.05*U(-1,1) seeded (seed 2), w0 = 0, FP64 throughout.
+
+Other workloads:
+  --config sweep64  64 independent 2D instances, N uniform over
+                    {128,256,512,1024}, eps~U[0.01,0.05], sigma~logU[10,1000],
+                    m~U[-0.4,0.4], dt=eps^2/2 (seeds 4000+i), mixed precision,
+                    one batched timestep against the sum of the 64 solo runs.
+  --config serve    256 resident simulations (70% 2D N in {256..2048}, 30% 3D
+                    N in {64,128}; seeds 5000+s), one Poisson stream of
+                    timestep requests (seed 5999) at --rates req/s for
+                    --duration s each, mixed precision; p50/p99 latency
+                    (arrival to done) and sustained DOFs/s.
 """
 import argparse
 import json
@@ -58,6 +69,174 @@ def cpu_baseline(cfg, its_per_step, sample_its=4):
                        f"nproc {os.cpu_count()}")}
 
 
+def calibrate_copy(torch, mib=1024, reps=5):
+    """A plain elementwise copy (y = -x, FP64) of `mib` MiB: it reads and writes
+    exactly that many bytes, so hardware byte counters of this kernel give the
+    scale from counter units to bytes."""
+    n = mib * 2**20 // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.neg(x, out=y)  # load the kernel before timing
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        torch.neg(x, out=y)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "reps": reps,
+                      "avg_ms": ms, "GBs": 2 * n * 8 / ms / 1e6}), flush=True)
+
+
+def _params(ok, spec, precision):
+    return ok.default_params(dim=spec["dim"], n=spec["n"], eps=spec["eps"], sigma=spec["sigma"],
+                             m=spec["m"], dt=spec["dt"], theta=spec["theta"], precision=precision)
+
+
+def _base_line(metric_value, steps, warmup, ms_per_step, dtype, config):
+    return {"metric": "timestep DOFs/s", "value": metric_value, "unit": "DOFs/s", "n_gpus": 1,
+            "steps": steps, "warmup": warmup, "ms_per_step": ms_per_step,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def bench_sweep(args, torch, ok):
+    """Batched sweep: all 64 instances advance one timestep per step in
+    grouped launches (classes by N on streams of their own, FGMRES iterations
+    replayed from captured graphs), against the sum of the solo runs."""
+    from paper_1603_04570_amd.inputs import dofs, noise_state, sweep_instance
+    prec = ok.OK_FP64 if args.precision == "fp64" else ok.OK_MIXED
+    specs = [sweep_instance(i) for i in range(64)]
+    plist = [_params(ok, s, prec) for s in specs]
+    init = [noise_state(s["dim"], s["n"], s["m"], s["seed"]) for s in specs]
+    init = [(torch.from_numpy(u).cuda(), torch.from_numpy(w).cuda()) for u, w in init]
+    B = ok.Batch(plist)
+    tuned = 0 if args.no_autotune else B.autotune()
+
+    def reset():
+        for i, (u, w) in enumerate(init):
+            B.set_state(i, u, w)
+        torch.cuda.synchronize()
+
+    reset()
+    for _ in range(args.warmup):
+        B.timestep(1)
+    reset()
+    t0 = time.perf_counter()
+    st = B.timestep(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    total = sum(dofs(s["dim"], s["n"]) for s in specs)
+    # the same instances one at a time (same launch mode, warm)
+    solo = 0.0
+    solo_its = []
+    for i, s in enumerate(specs):
+        P = ok.Problem(plist[i])
+        P.use_graphs(True)
+        u, w = init[i][0].clone(), init[i][1].clone()
+        P.timestep(u, w, 1)  # warm: graphs captured, code loaded
+        u.copy_(init[i][0])
+        w.copy_(init[i][1])
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        ss = P.timestep(u, w, args.steps)
+        torch.cuda.synchronize()
+        solo += time.perf_counter() - a
+        solo_its.append(ss.its())
+        assert ss.its() == st[i].its(), (i, ss.its(), st[i].its())
+    sizes = sorted({s["n"] for s in specs})
+    out = _base_line(total * args.steps / elapsed, args.steps, args.warmup,
+                     elapsed * 1e3 / args.steps, "f64" if prec == ok.OK_FP64 else "f64+f32",
+                     {"workload": "sweep64: 64 x 2D Q1, N in {128,256,512,1024} (seeds 4000+i), "
+                                  "eps~U[.01,.05], sigma~logU[10,1000], m~U[-.4,.4], "
+                                  "dt=eps^2/2, theta=1",
+                      "dofs": total, "instances": 64,
+                      "instances_per_N": {str(n): sum(s["n"] == n for s in specs) for n in sizes},
+                      "global_batch": 64, "parallelism": "none (1 GPU)"})
+    out.update({"classes": B.classes(), "solo_sum_s": solo, "batched_s": elapsed,
+                "vs_solo_sum": solo / elapsed, "autotuned_shapes": tuned,
+                "fgmres_its_total": sum(sum(x.its()) for x in st), "roofline": None})
+    return out
+
+
+def bench_serve(args, torch, ok):
+    """Serving loop: resident simulations, Poisson timestep requests,
+    admission by HBM budget, continuous batching (native worker threads)."""
+    from paper_1603_04570_amd.inputs import noise_state, poisson_arrivals, serving_simulation
+    prec = ok.OK_FP64 if args.precision == "fp64" else ok.OK_MIXED
+    sims = [serving_simulation(s) for s in range(256)]
+    plist = [_params(ok, s, prec) for s in sims]
+    cfg = ok.server_config(max_queue=args.max_queue, max_slots_per_pool=16)
+    S = ok.Server(plist, int(args.budget_gib * 2**30), config=cfg)
+    for i, s in enumerate(sims):
+        u0, w0 = noise_state(s["dim"], s["n"], s["m"], s["seed"])
+        S.set_state(i, torch.from_numpy(u0).cuda(), torch.from_numpy(w0).cuda())
+    torch.cuda.synchronize()
+    dofs_of = [2 * (s["n"] + 1) ** s["dim"] for s in sims]
+    S.start()
+    # warm-up: one request per class (pools created, code loaded, graphs captured)
+    firsts = {}
+    for i, s in enumerate(sims):
+        firsts.setdefault((s["dim"], s["n"]), i)
+    for i in firsts.values():
+        S.submit(i, 1)
+    got = 0
+    while got < len(firsts):
+        got += len(S.poll(4096, wait_s=1.0))
+    runs = []
+    for rate in [float(r) for r in args.rates.split(",")]:
+        S.reset_stats()
+        count = max(1, int(rate * args.duration))
+        t, sim = poisson_arrivals(rate, count, len(sims), seed=5999)
+        t0 = S.now() + 0.2
+        for k in range(count):
+            S.submit(int(sim[k]), 1, t0 + float(t[k]))
+        res, last = [], time.perf_counter()
+        while len(res) < count:
+            res += S.poll(65536, wait_s=1.0)
+            if time.perf_counter() - last > 10:
+                print(f"serve rate {rate}: {len(res)}/{count} requests finished", file=sys.stderr,
+                      flush=True)
+                last = time.perf_counter()
+        st = S.stats()
+        done = [r for r in res if r["status"] == 0]
+        lat = np.array([r["t_done"] - r["t_arrival"] for r in done]) * 1e3
+        t_end = max(r["t_done"] for r in done) if done else t0
+        dof_steps = sum(dofs_of[r["sim"]] * r["steps_done"] for r in done)
+        runs.append({"offered_rate": rate, "requests": count, "completed": len(done),
+                     "rejected": st["rejected"], "deferred": st["deferred"],
+                     "failed": st["failed"],
+                     "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+                     "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+                     "dofs_per_s": dof_steps / max(t_end - t0, 1e-9),
+                     "completed_per_s": len(done) / max(t_end - t0, 1e-9),
+                     "busy_s": st["busy_s"], "wall_s": t_end - t0, "ticks": st["ticks"],
+                     "max_active": st["max_active"], "max_queue_seen": st["max_queue_seen"],
+                     "pools_created": st["pools_created"], "pools_freed": st["pools_freed"],
+                     "peak_pool_bytes": st["peak_bytes"],
+                     "newton_its_mean": float(np.mean([r["newton_its"] for r in done]))
+                     if done else None,
+                     "fgmres_its_mean": float(np.mean([r["fgmres_its"] for r in done]))
+                     if done else None})
+    S.stop(drain=True)
+    S.close()
+    head = runs[-1]
+    out = _base_line(head["dofs_per_s"], head["completed"], 0,
+                     head["wall_s"] * 1e3 / max(head["completed"], 1),
+                     "f64" if prec == ok.OK_FP64 else "f64+f32",
+                     {"workload": "serve: 256 simulations (70% 2D N in {256,512,1024,2048}, 30% "
+                                  "3D N in {64,128}; seeds 5000+s), Poisson timestep requests "
+                                  f"(seed 5999) at {head['offered_rate']} req/s for "
+                                  f"{args.duration} s, queue bound {args.max_queue}, pool budget "
+                                  f"{args.budget_gib} GiB",
+                      "simulations": 256, "global_batch": "continuous",
+                      "parallelism": "none (1 GPU)"})
+    out.update({"latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"]},
+                "serving": runs, "roofline": None})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,15 +247,32 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain copy kernel of known size (for counter scaling)")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay captured FGMRES iterations (single-problem configs)")
+    ap.add_argument("--rates", default="2000", help="serve: offered request rates (req/s)")
+    ap.add_argument("--duration", type=float, default=8.0, help="serve: seconds of arrivals")
+    ap.add_argument("--budget-gib", type=float, default=160.0, help="serve: pool HBM budget")
+    ap.add_argument("--max-queue", type=int, default=256, help="serve: queue bound")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
     from paper_1603_04570_amd import ok
     from paper_1603_04570_amd.inputs import CONFIGS, dofs, noise_state
 
+    if args.config == "sweep64":
+        print(json.dumps(bench_sweep(args, torch, ok)), flush=True)
+        return
+    if args.config == "serve":
+        print(json.dumps(bench_serve(args, torch, ok)), flush=True)
+        return
     cfg = dict(CONFIGS[args.config])
     prec = args.precision or cfg["precision"]
     p = ok.default_params(dim=cfg["dim"], n=cfg["n"], eps=cfg["eps"], sigma=cfg["sigma"],
@@ -89,6 +285,8 @@ def main():
     w0d = torch.from_numpy(w0).to(dev)
     u, w = u0d.clone(), w0d.clone()
     tuned = 0 if args.no_autotune else P.autotune()
+    if args.graphs:
+        P.use_graphs(True)
     for _ in range(args.warmup):
         P.timestep(u, w, 1)
     u.copy_(u0d)

@@ -60,7 +60,8 @@ enum ok_status {
   OK_E_HIP = -3,           /* a HIP runtime call or kernel launch failed */
   OK_E_GMRES_MAXIT = -4,   /* FGMRES hit gmres_max_restarts without converging */
   OK_E_NEWTON_MAXIT = -5,  /* Newton hit newton_max_it without converging */
-  OK_E_NONFINITE = -6      /* NaN/Inf in ||F|| or in the Krylov recurrence */
+  OK_E_NONFINITE = -6,     /* NaN/Inf in ||F|| or in the Krylov recurrence */
+  OK_E_REJECTED = -7       /* serving: request refused (queue full) or dropped at a stop */
 };
 
 /* Preconditioner precision. */
@@ -199,6 +200,16 @@ int ok_profile_read(ok_ctx *ctx, int64_t *launches, double *total_ms, double *by
  * number of table entries set.  Synchronises; run it outside timed regions. */
 int ok_autotune(ok_ctx *ctx, void *stream, int32_t *entries);
 
+/* Launch mode of the FGMRES iterations.  enable != 0: the context gets a HIP
+ * stream of its own (default priority) and captures each Arnoldi iteration j
+ * (preconditioner, Jacobian, Gram-Schmidt, Givens) once as a HIP graph, keyed
+ * by the state pointer, and replays it; later calls with another state
+ * pointer, or an ok_autotune, re-capture.  Results are bitwise the same as
+ * with enable == 0 (kernels launched one by one on the caller's stream, the
+ * default).  While a kernel class is profiled (ok_profile_enable) kernels are
+ * launched one by one. */
+int ok_use_graphs(ok_ctx *ctx, int32_t enable);
+
 /* ---- Batched sweeps: many independent problems in lockstep ----
  * Instances whose parameters agree on (dim, n, precision and the solver
  * counts) form a class; each class is one set of grouped kernel launches
@@ -229,8 +240,85 @@ int ok_batch_timestep(ok_batch *b, int32_t nsteps, ok_stats *stats, void *stream
 int ok_batch_autotune(ok_batch *b, void *stream, int32_t *entries);
 /* Number of classes (grouped launch sets) the instances fell into. */
 int ok_batch_classes(const ok_batch *b);
+/* As ok_use_graphs, for every class of the batch.  A batch starts with
+ * graphs on: each class runs its FGMRES iterations from captured graphs on a
+ * stream of its own, so the classes of a batch overlap on the device. */
+int ok_batch_use_graphs(ok_batch *b, int32_t enable);
 int ok_batch_destroy(ok_batch *b);
 const char *ok_batch_last_error(const ok_batch *b);
+
+/* ---- Serving: timestep requests of many resident simulations ----
+ * A server holds the state (u, w) of `nsims` simulations resident in the
+ * caller's workspace and advances them on request.  A request (simulation,
+ * nsteps, arrival time) waits in a bounded queue until its simulation has no
+ * other request in flight (FIFO per simulation) and a slot is free: slots
+ * live in pools, one pool per class (same grid, precision and solver
+ * counts), carved on demand from the rest of the workspace (the HBM budget);
+ * idle pools are released when a waiting request of another class needs the
+ * room.  The worker thread runs ticks: one Newton iteration (residual test,
+ * FGMRES solve, update, residual test, Sec. 2) of every occupied slot of
+ * every pool in grouped launches; requests admitted between ticks join the
+ * next tick (continuous batching).  Each simulation's arithmetic is that of a
+ * single-problem ok_timestep: results are bitwise the same alone and in the
+ * mix.  Times are seconds since the server was created (ok_server_now). */
+typedef struct ok_server ok_server;
+typedef struct {
+  int32_t max_queue;           /* arrived requests waiting for a slot; arrivals
+                                  beyond it are rejected (OK_E_REJECTED); 256 */
+  int32_t max_slots_per_pool;  /* instances per pool (upper bound); 16 */
+  int32_t graphs;              /* replay captured FGMRES iterations; 1 */
+  int32_t reserved;
+  double pool_bytes;           /* a pool holds fewer slots if its bytes would
+                                  exceed this; 32 GiB */
+} ok_server_config;
+typedef struct {
+  int64_t ticket;
+  int32_t sim, nsteps, status, steps_done, newton_its, fgmres_its;
+  double t_arrival, t_admit, t_done; /* t_admit < 0: never admitted */
+} ok_request_result;
+typedef struct {
+  int64_t submitted, admitted, completed, failed, rejected, deferred;
+  int64_t ticks, pools_created, pools_freed, pools_live;
+  int64_t max_active, max_queue_seen, peak_bytes, bytes_in_use;
+  double dof_steps;   /* sum over completed requests of 2(N+1)^d x steps */
+  double busy_s;      /* wall time spent in ticks */
+  double now;         /* ok_server_now at the time of the call */
+} ok_server_stats;
+
+int ok_server_default_config(ok_server_config *cfg);
+/* Bytes of resident state (u and w of every simulation, 256-byte aligned). */
+int ok_server_state_bytes(const ok_params *sims, int32_t nsims, size_t *bytes);
+/* Create a server over the caller's workspace (256-byte aligned): the first
+ * ok_server_state_bytes hold the states, the rest is the pool budget, which
+ * must hold at least one slot of the largest class.  cfg may be NULL.  The
+ * server creates a stream of its own (default priority); `stream` is unused. */
+int ok_server_create(const ok_params *sims, int32_t nsims, const ok_server_config *cfg,
+                     void *d_ws, size_t ws_bytes, void *stream, ok_server **out);
+/* Copy a simulation's state in or out (n entries each); only while stopped. */
+int ok_server_set_state(ok_server *s, int32_t sim, const double *d_u, const double *d_w,
+                        void *stream);
+int ok_server_get_state(ok_server *s, int32_t sim, double *d_u, double *d_w, void *stream);
+/* Start the worker thread (on the calling thread's current device). */
+int ok_server_start(ok_server *s);
+double ok_server_now(const ok_server *s);
+/* Enqueue `nsteps` timesteps of simulation `sim`, arriving at t_arrival
+ * (seconds, ok_server_now's clock; < 0: now).  Thread-safe. */
+int ok_server_submit(ok_server *s, int32_t sim, int32_t nsteps, double t_arrival,
+                     int64_t *ticket);
+/* Up to `max` finished requests (done, failed or rejected) into out[];
+ * waits up to wait_s seconds for the first one while the server runs. */
+int ok_server_poll(ok_server *s, ok_request_result *out, int32_t max, int32_t *count,
+                   double wait_s);
+/* Stop the worker.  drain != 0: first serve every submitted request
+ * (including future arrivals); drain == 0: stop after the current tick,
+ * reporting unstarted and unfinished requests as OK_E_REJECTED (the state
+ * of an unfinished one is its last Newton iterate).  Returns a fatal error
+ * of the worker, if any. */
+int ok_server_stop(ok_server *s, int32_t drain);
+int ok_server_get_stats(ok_server *s, ok_server_stats *out);
+int ok_server_reset_stats(ok_server *s);
+int ok_server_destroy(ok_server *s);
+const char *ok_server_last_error(const ok_server *s);
 
 /* Destroy a context (frees host state only; the caller frees its memory). */
 int ok_destroy(ok_ctx *ctx);

@@ -4,6 +4,7 @@
 // of classes.  A single solve is one class with B = 1.
 #pragma once
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -34,6 +35,19 @@ struct InstOut {
   double lin_res = 0.0;
 };
 
+// Execution resources of a class that runs its FGMRES iterations from captured
+// graphs on a stream of its own (owned; released with the class).
+struct ClassExec {
+  hipStream_t xs = nullptr;           // class stream (default priority, non-blocking)
+  hipEvent_t fork = nullptr, join = nullptr;
+  std::vector<hipGraphExec_t> iter;   // one graph per Arnoldi index j
+  int* hflags = nullptr;              // pinned host copy of the activity flags [B]
+  const void* key = nullptr;          // state pointer the graphs were captured with
+  bool graphs = true;
+  void clear_graphs();
+  ~ClassExec();
+};
+
 struct ClassCtx {
   // ---- configuration (common to the class) ----
   ok_params shape{};  // dim, n, precision, solver counts (physics per instance below)
@@ -47,7 +61,7 @@ struct ClassCtx {
   std::vector<InstCoef> hcoef;    // host copy of the constants table
   // ---- device memory (SoA: every array is [instance][length]) ----
   InstCoef* coef = nullptr;
-  int *act = nullptr, *part = nullptr, *incyc = nullptr;  // [B] flags
+  int *act = nullptr, *part = nullptr, *incyc = nullptr, *aux = nullptr;  // [B] flags
   double *V = nullptr, *X = nullptr, *Bv = nullptr, *T1 = nullptr;
   double *un = nullptr, *wn = nullptr, *G = nullptr, *su = nullptr, *sw = nullptr;
   double *pA = nullptr, *pB = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr;
@@ -56,12 +70,15 @@ struct ClassCtx {
   void *cr = nullptr, *cda = nullptr, *cdb = nullptr, *yv = nullptr, *tv = nullptr, *sv = nullptr;
   void* mg[kMaxLevels][5]{};  // x, b, r, d, d' per level
   // ---- host mirrors ----
-  std::vector<int> h_act, h_part;
+  std::vector<int> h_act, h_part, h_aux;
+  std::vector<int> h_hasF;  // Bv holds F of the current iterate (Newton ticks)
   std::vector<double> h_kr, h_nrm;
   std::vector<InstOut> out;
   std::vector<int> nits;  // Newton iterations of the current timestep, per instance
   Prof* prof = nullptr;  // shared profiling state (may be null)
   std::string* err = nullptr;
+  std::unique_ptr<ClassExec> ex;  // null: iterations are launched one kernel at a time on
+                                  // the caller's stream
 
   int64_t n2() const { return 2 * n; }
   Batch batch(const int* flags) const { return Batch{B, coef, flags}; }
@@ -109,14 +126,22 @@ int newton_group(const Group& grp, const std::vector<Vec<double>>& u,
                  const std::vector<Vec<const double>>& wn, std::vector<NewtonLog>& log,
                  hipStream_t st);
 // At most max_iters Newton updates (max_iters < 0: until every participating
-// instance stops).  Each update is preceded by the residual test; a bounded
-// call ends right after its last update (status 1 = still iterating).
+// instance stops).  Instances without a current residual (h_hasF == 0) are
+// tested first; every update is followed by the residual and its test, so a
+// bounded call (one serving tick) ends with each instance's status known:
+// OK_SUCCESS when converged, 1 while still iterating, or an error.
 int newton_group_iters(const Group& grp, const std::vector<Vec<double>>& u,
                        const std::vector<Vec<double>>& w, const std::vector<Vec<const double>>& un,
                        const std::vector<Vec<const double>>& wn, std::vector<NewtonLog>& log,
                        int max_iters, hipStream_t st);
 // Upload host flags (h_part) to the device part/act arrays.
 int push_part(ClassCtx& c, hipStream_t st);
+// Replace the physical parameters of instance i (same class) and upload its
+// constants; stream-ordered.
+int set_instance(ClassCtx& c, int i, const ok_params& p, hipStream_t st);
+// Give the class its own stream and graph cache (graphs: capture FGMRES
+// iterations once per state pointer and replay them).
+int enable_exec(ClassCtx& c, bool graphs);
 // Tile autotuner over the class's grids.
 int autotune_class(ClassCtx& c, hipStream_t st, int* entries);
 

@@ -9,6 +9,21 @@
 
 namespace okd {
 
+void ClassExec::clear_graphs() {
+  for (auto& g : iter)
+    if (g) (void)hipGraphExecDestroy(g);
+  iter.clear();
+  key = nullptr;
+}
+
+ClassExec::~ClassExec() {
+  clear_graphs();
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
+  if (xs) (void)hipStreamDestroy(xs);
+  if (hflags) (void)hipHostFree(hflags);
+}
+
 Prof::~Prof() {
   for (auto& e : ev) {
     (void)hipEventDestroy(e.a);
@@ -164,6 +179,7 @@ void carve(ClassCtx& c, char* base, bool with_state, size_t* total) {
   c.act = cv.take<int>(B);
   c.part = cv.take<int>(B);
   c.incyc = cv.take<int>(B);
+  c.aux = cv.take<int>(B);
   c.V = cv.take<double>((size_t)B * (m + 1) * n2);
   c.Z = cv.take<char>((size_t)B * m * n2 * ps);
   c.X = cv.take<double>((size_t)B * n2);
@@ -440,6 +456,41 @@ int fgmres_iteration(ClassCtx& c, int j, Vec<const double> u, hipStream_t st) {
   return OK_SUCCESS;
 }
 
+// Iteration j on stream s: replayed from a graph captured on the class stream
+// (kernel arguments depend only on j, the state pointer and the tuned launch
+// shapes), or launched kernel by kernel.  No graphs while kernels are profiled.
+int run_iteration(ClassCtx& c, int j, Vec<const double> u, hipStream_t s) {
+  ClassExec* x = c.ex.get();
+  const bool profiling = c.prof && c.prof->cls != OK_K_NONE;
+  if (!x || !x->graphs || profiling)
+    return c.mixed ? fgmres_iteration<float>(c, j, u, s) : fgmres_iteration<double>(c, j, u, s);
+  if (x->key != (const void*)u.p || (int)x->iter.size() != c.m) {
+    x->clear_graphs();
+    x->iter.assign(c.m, nullptr);
+    x->key = u.p;
+  }
+  if (!x->iter[j]) {
+    OKE(c, hipStreamBeginCapture(x->xs, hipStreamCaptureModeThreadLocal));
+    if (c.prof) c.prof->capturing = true;
+    int e = c.mixed ? fgmres_iteration<float>(c, j, u, x->xs)
+                    : fgmres_iteration<double>(c, j, u, x->xs);
+    if (c.prof) c.prof->capturing = false;
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(x->xs, &g);
+    if (e || ee != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      if (e) return e;
+      OKE(c, ee);
+    }
+    hipError_t ei = hipGraphInstantiate(&x->iter[j], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) x->iter[j] = nullptr;
+    OKE(c, ei);
+  }
+  OKE(c, hipGraphLaunch(x->iter[j], s));
+  return OK_SUCCESS;
+}
+
 template <class P>
 int lsq_update(ClassCtx& c, Vec<double> x, hipStream_t st) {
   const Batch B = c.batch(c.incyc);
@@ -531,11 +582,14 @@ int class_init(ClassCtx& c, const ok_params* ps, int B, char* base, bool with_st
   for (int i = 0; i < B; i++) inst_coef(c.hcoef[i], ps[i], c.lev, c.L);
   c.h_act.assign(B, 0);
   c.h_part.assign(B, 0);
+  c.h_aux.assign(B, 0);
+  c.h_hasF.assign(B, 0);
   c.out.assign(B, InstOut{});
   c.nits.assign(B, 0);
   hipError_t e = hipMemcpyAsync(c.coef, c.hcoef.data(), sizeof(InstCoef) * B,
                                 hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemsetAsync(c.act, 0, sizeof(int) * 3 * B, st);
+  for (int* f : {c.act, c.part, c.incyc, c.aux})
+    if (e == hipSuccess) e = hipMemsetAsync(f, 0, sizeof(int) * B, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     err = std::string("class setup: ") + hipGetErrorString(e);
@@ -545,6 +599,29 @@ int class_init(ClassCtx& c, const ok_params* ps, int B, char* base, bool with_st
 }
 
 int push_part(ClassCtx& c, hipStream_t st) { return push_flags(c, c.part, c.h_part, st); }
+
+int set_instance(ClassCtx& c, int i, const ok_params& p, hipStream_t st) {
+  if (i < 0 || i >= c.B || !same_class(c.shape, p)) return OK_E_INVALID;
+  c.ip[i] = p;
+  inst_coef(c.hcoef[i], p, c.lev, c.L);
+  OKE(c, hipMemcpyAsync(c.coef + i, &c.hcoef[i], sizeof(InstCoef), hipMemcpyHostToDevice, st));
+  // the host entry may be rewritten by the next call: complete the copy
+  OKE(c, hipStreamSynchronize(st));
+  return OK_SUCCESS;
+}
+
+int enable_exec(ClassCtx& c, bool graphs) {
+  if (!c.ex) {
+    c.ex.reset(new ClassExec());
+    OKE(c, hipStreamCreateWithFlags(&c.ex->xs, hipStreamNonBlocking));
+    OKE(c, hipEventCreateWithFlags(&c.ex->fork, hipEventDisableTiming));
+    OKE(c, hipEventCreateWithFlags(&c.ex->join, hipEventDisableTiming));
+    OKE(c, hipHostMalloc((void**)&c.ex->hflags, sizeof(int) * c.B, hipHostMallocDefault));
+  }
+  c.ex->graphs = graphs;
+  c.ex->clear_graphs();
+  return OK_SUCCESS;
+}
 
 // ---------------------------------------------------------------------------
 // Single operations (FP64 in/out)
@@ -623,6 +700,7 @@ int residual_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const dou
   std::vector<int> hf(c.B, 1);
   if (flags == c.part) hf = c.h_part;
   else if (flags == c.act) hf = c.h_act;
+  else if (flags == c.aux) hf = c.h_aux;
   for (int i = 0; i < c.B; i++)
     if (hf[i]) c.out[i].fnorm = c.h_nrm[8 * i + 1];
   return OK_SUCCESS;
@@ -699,25 +777,46 @@ int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,
     std::vector<std::vector<int>> incyc(nc);
     for (size_t k = 0; k < nc; k++) incyc[k] = grp[k]->h_act;
     const int m = grp[0]->m;
+    // Classes with a stream of their own run their iterations there, so the
+    // classes of a group overlap on the device; the host waits for each class
+    // once per iteration (its activity flags decide whether to go on).
+    for (size_t k = 0; k < nc; k++) {
+      ClassCtx& c = *grp[k];
+      if (!c.ex || !any(c.h_act)) continue;
+      OKE(c, hipEventRecord(c.ex->fork, st));
+      OKE(c, hipStreamWaitEvent(c.ex->xs, c.ex->fork, 0));
+    }
     for (int j = 0; j < m; j++) {
       bool launched = false;
       for (size_t k = 0; k < nc; k++) {
         ClassCtx& c = *grp[k];
         if (!any(c.h_act)) continue;
-        int e = c.mixed ? fgmres_iteration<float>(c, j, u[k], st)
-                        : fgmres_iteration<double>(c, j, u[k], st);
+        hipStream_t s = c.ex ? c.ex->xs : st;
+        int e = run_iteration(c, j, u[k], s);
         if (e) return e;
-        if (d2h(c, c.h_act, c.act, (size_t)c.B, st)) return OK_E_HIP;
+        if (c.ex) {  // pinned: the copy does not hold up the launches of the next class
+          OKE(c, hipMemcpyAsync(c.ex->hflags, c.act, sizeof(int) * c.B, hipMemcpyDeviceToHost, s));
+        } else if (d2h(c, c.h_act, c.act, (size_t)c.B, s)) {
+          return OK_E_HIP;
+        }
         launched = true;
       }
       if (!launched) break;
       bool still = false;
       for (size_t k = 0; k < nc; k++) {
         ClassCtx& c = *grp[k];
-        if (sync(c, st)) return OK_E_HIP;
+        if (!any(incyc[k])) continue;
+        if (sync(c, c.ex ? c.ex->xs : st)) return OK_E_HIP;
+        if (c.ex && any(c.h_act)) c.h_act.assign(c.ex->hflags, c.ex->hflags + c.B);
         still = still || any(c.h_act);
       }
       if (!still) break;
+    }
+    for (size_t k = 0; k < nc; k++) {
+      ClassCtx& c = *grp[k];
+      if (!c.ex || !any(incyc[k])) continue;
+      OKE(c, hipEventRecord(c.ex->join, c.ex->xs));
+      OKE(c, hipStreamWaitEvent(st, c.ex->join, 0));
     }
     // least squares and x update for the instances of this cycle; stop tests
     bool restart_any = false;
@@ -791,33 +890,45 @@ int newton_group_iters(const Group& grp, const std::vector<Vec<double>>& u,
                        const std::vector<Vec<const double>>& wn, std::vector<NewtonLog>& log,
                        int max_iters, hipStream_t st) {
   const size_t nc = grp.size();
-  for (int it = 0;; it++) {
-    bool anyp = false;
-    for (size_t k = 0; k < nc; k++) {
-      ClassCtx& c = *grp[k];
-      if (!any(c.h_part)) continue;
-      if (push_part(c, st)) return OK_E_HIP;
-      int e = residual_d(c, c.part, cst(u[k]), cst(w[k]), un[k], wn[k], vec(c.Bv, c.n2()), st);
-      if (e) return e;
-      for (int i = 0; i < c.B; i++) {
-        if (!c.h_part[i]) continue;
-        const double f = c.out[i].fnorm;
-        log[k].fnorm[i].push_back(f);
-        if (!std::isfinite(f)) {
-          c.out[i].status = OK_E_NONFINITE;
-          c.h_part[i] = 0;
-        } else if (f <= c.ip[i].newton_atol) {
-          c.out[i].status = OK_SUCCESS;
-          c.h_part[i] = 0;
-        } else if (c.nits[i] >= c.shape.newton_max_it) {
-          c.out[i].status = OK_E_NEWTON_MAXIT;
-          c.h_part[i] = 0;
-        } else {
-          c.out[i].status = 1;  // still iterating
-        }
+  // Sec. 2 (C3 order): test ||F|| <= atol, else solve J dx = -F and update.
+  auto test = [&](ClassCtx& c, size_t k, const std::vector<int>& which) {
+    for (int i = 0; i < c.B; i++) {
+      if (!which[i]) continue;
+      const double f = c.out[i].fnorm;
+      log[k].fnorm[i].push_back(f);
+      c.h_hasF[i] = 1;
+      if (!std::isfinite(f)) {
+        c.out[i].status = OK_E_NONFINITE;
+        c.h_part[i] = 0;
+      } else if (f <= c.ip[i].newton_atol) {
+        c.out[i].status = OK_SUCCESS;
+        c.h_part[i] = 0;
+      } else if (c.nits[i] >= c.shape.newton_max_it) {
+        c.out[i].status = OK_E_NEWTON_MAXIT;
+        c.h_part[i] = 0;
+      } else {
+        c.out[i].status = 1;  // still iterating
       }
-      anyp = anyp || any(c.h_part);
     }
+  };
+  // residual of the instances that have none for their current iterate
+  for (size_t k = 0; k < nc; k++) {
+    ClassCtx& c = *grp[k];
+    bool fresh = false;
+    for (int i = 0; i < c.B; i++) {
+      c.h_aux[i] = c.h_part[i] && !c.h_hasF[i];
+      fresh = fresh || c.h_aux[i];
+    }
+    if (!fresh) continue;
+    if (push_flags(c, c.aux, c.h_aux, st)) return OK_E_HIP;
+    int e = residual_d(c, c.aux, cst(u[k]), cst(w[k]), un[k], wn[k], vec(c.Bv, c.n2()), st);
+    if (e) return e;
+    std::vector<int> which = c.h_aux;
+    test(c, k, which);
+  }
+  for (int it = 0; max_iters < 0 || it < max_iters; it++) {
+    bool anyp = false;
+    for (size_t k = 0; k < nc; k++) anyp = anyp || any(grp[k]->h_part);
     if (!anyp) break;
     std::vector<Vec<const double>> bb(nc);
     std::vector<Vec<double>> xx(nc);
@@ -841,21 +952,21 @@ int newton_group_iters(const Group& grp, const std::vector<Vec<double>>& u,
         if (!c.h_part[i]) continue;
         log[k].its[i].push_back(c.out[i].fgmres_its);
         c.nits[i]++;
+        // a linear solve that stopped at its iteration limit still gives the
+        // step; the Newton test decides
         if (c.out[i].status == OK_E_NONFINITE) c.h_part[i] = 0;
       }
+      if (!any(c.h_part)) continue;
       if (push_part(c, st)) return OK_E_HIP;
       const Batch B = c.batch(c.part);
       OKE(c, launch_axpby(B, 1.0, cst(u[k]), 1.0, Vec<const double>{c.X, c.n2()}, u[k], c.n, st));
       OKE(c, launch_axpby(B, 1.0, cst(w[k]), 1.0, Vec<const double>{c.X + c.n, c.n2()}, w[k], c.n,
                           st));
-      // instances whose linear solve failed to converge still took the step;
-      // they keep iterating (the Newton test decides)
-      for (int i = 0; i < c.B; i++)
-        if (c.h_part[i] && c.out[i].status == OK_E_GMRES_MAXIT) c.out[i].status = 1;
+      e = residual_d(c, c.part, cst(u[k]), cst(w[k]), un[k], wn[k], vec(c.Bv, c.n2()), st);
+      if (e) return e;
+      std::vector<int> which = c.h_part;
+      test(c, k, which);
     }
-    // a bounded call (one serving tick) ends after its updates; the next call
-    // starts with the residual test
-    if (max_iters >= 0 && it + 1 >= max_iters) break;
   }
   return OK_SUCCESS;
 }
@@ -965,6 +1076,7 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
 }  // namespace
 
 int autotune_class(ClassCtx& c, hipStream_t st, int* entries) {
+  if (c.ex) c.ex->clear_graphs();  // captured launch shapes would be stale
   int n = 0;
   int e = c.mixed ? autotune_impl<float>(c, st, &n) : autotune_impl<double>(c, st, &n);
   if (entries) *entries = n;

@@ -29,7 +29,8 @@ namespace {
 
 const char* kStatusNames[] = {"success", "invalid argument", "workspace too small or misaligned",
                               "HIP error", "FGMRES did not converge",
-                              "Newton did not converge", "non-finite value"};
+                              "Newton did not converge", "non-finite value",
+                              "request rejected"};
 
 int fail(std::string* err, int code, const std::string& msg) {
   if (err) *err = msg;
@@ -80,6 +81,7 @@ int timestep_group(const Group& grp, const std::vector<Vec<double>>& u,
       un[k] = Vec<const double>{c.un, c.n};
       wn[k] = Vec<const double>{c.wn, c.n};
       c.h_part.assign(c.B, 1);
+      c.h_hasF.assign(c.B, 0);
       c.nits.assign(c.B, 0);
       log[k].its.assign(c.B, {});
       log[k].fnorm.assign(c.B, {});
@@ -109,7 +111,7 @@ int timestep_group(const Group& grp, const std::vector<Vec<double>>& u,
           S.status = st_i;
           if (status == OK_SUCCESS) {
             status = st_i;
-            if (err && st_i < 0 && st_i >= -6)
+            if (err && st_i < 0 && st_i >= -7)
               *err = std::string("instance failed: ") + kStatusNames[-st_i];
           }
         } else {
@@ -297,6 +299,12 @@ int ok_timestep(ok_ctx* c, double* u, double* w, int32_t nsteps, ok_stats* stats
   return e;
 }
 
+int ok_use_graphs(ok_ctx* c, int32_t enable) {
+  if (!c) return OK_E_INVALID;
+  if (!enable && !c->cls.ex) return OK_SUCCESS;
+  return enable_exec(c->cls, enable != 0);
+}
+
 int ok_autotune(ok_ctx* c, void* stream, int32_t* entries) {
   if (!c) return OK_E_INVALID;
   int n = 0;
@@ -334,7 +342,7 @@ int ok_profile_read(ok_ctx* c, int64_t* launches, double* total_ms, double* byte
 
 const char* ok_error_string(int status) {
   int i = -status;
-  if (i < 0 || i > 6) return "unknown status";
+  if (i < 0 || i > 7) return "unknown status";
   return kStatusNames[i];
 }
 
@@ -417,6 +425,11 @@ int ok_batch_create(const ok_params* params, int32_t count, void* d_ws, size_t w
       return e;
     }
     base += class_bytes(ps[0], (int)ps.size(), true);
+    e = enable_exec(c, true);
+    if (e) {
+      delete b;
+      return e;
+    }
   }
   *out = b;
   return OK_SUCCESS;
@@ -479,6 +492,15 @@ int ok_batch_autotune(ok_batch* b, void* stream, int32_t* entries) {
     total += n;
   }
   if (entries) *entries = total;
+  return OK_SUCCESS;
+}
+
+int ok_batch_use_graphs(ok_batch* b, int32_t enable) {
+  if (!b) return OK_E_INVALID;
+  for (auto& c : b->classes) {
+    int e = enable_exec(c, enable != 0);
+    if (e) return e;
+  }
   return OK_SUCCESS;
 }
 

@@ -17,7 +17,9 @@ OK_K_NONE, OK_K_CHEB_MASS, OK_K_MG_SMOOTH, OK_K_ELEMENT, OK_K_STENCIL_ANY, OK_K_
 HIST = 256
 
 STATUS = {0: "OK_SUCCESS", -1: "OK_E_INVALID", -2: "OK_E_WORKSPACE", -3: "OK_E_HIP",
-          -4: "OK_E_GMRES_MAXIT", -5: "OK_E_NEWTON_MAXIT", -6: "OK_E_NONFINITE"}
+          -4: "OK_E_GMRES_MAXIT", -5: "OK_E_NEWTON_MAXIT", -6: "OK_E_NONFINITE",
+          -7: "OK_E_REJECTED"}
+OK_E_REJECTED = -7
 
 
 class Params(C.Structure):
@@ -54,6 +56,32 @@ class Stats(C.Structure):
 
     def ms(self):
         return [self.step_ms[i] for i in range(min(self.steps_done, HIST))]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("max_queue", C.c_int32), ("max_slots_per_pool", C.c_int32),
+                ("graphs", C.c_int32), ("reserved", C.c_int32), ("pool_bytes", C.c_double)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("ticket", C.c_int64), ("sim", C.c_int32), ("nsteps", C.c_int32),
+                ("status", C.c_int32), ("steps_done", C.c_int32), ("newton_its", C.c_int32),
+                ("fgmres_its", C.c_int32), ("t_arrival", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "submitted", "admitted", "completed", "failed", "rejected", "deferred", "ticks",
+        "pools_created", "pools_freed", "pools_live", "max_active", "max_queue_seen",
+        "peak_bytes", "bytes_in_use")] + [("dof_steps", C.c_double), ("busy_s", C.c_double),
+                                          ("now", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class OkError(RuntimeError):
@@ -100,6 +128,24 @@ def load():
     lib.ok_batch_destroy.argtypes = [vp]
     lib.ok_batch_last_error.argtypes = [vp]
     lib.ok_batch_last_error.restype = C.c_char_p
+    lib.ok_use_graphs.argtypes = [vp, i32]
+    lib.ok_batch_use_graphs.argtypes = [vp, i32]
+    lib.ok_server_default_config.argtypes = [P(ServerConfig)]
+    lib.ok_server_state_bytes.argtypes = [P(Params), i32, P(C.c_size_t)]
+    lib.ok_server_create.argtypes = [P(Params), i32, P(ServerConfig), vp, C.c_size_t, vp, P(vp)]
+    lib.ok_server_set_state.argtypes = [vp, i32, vp, vp, vp]
+    lib.ok_server_get_state.argtypes = [vp, i32, vp, vp, vp]
+    lib.ok_server_start.argtypes = [vp]
+    lib.ok_server_now.argtypes = [vp]
+    lib.ok_server_now.restype = d
+    lib.ok_server_submit.argtypes = [vp, i32, i32, d, P(C.c_int64)]
+    lib.ok_server_poll.argtypes = [vp, P(RequestResult), i32, P(i32), d]
+    lib.ok_server_stop.argtypes = [vp, i32]
+    lib.ok_server_get_stats.argtypes = [vp, P(ServerStats)]
+    lib.ok_server_reset_stats.argtypes = [vp]
+    lib.ok_server_destroy.argtypes = [vp]
+    lib.ok_server_last_error.argtypes = [vp]
+    lib.ok_server_last_error.restype = C.c_char_p
     lib.ok_error_string.argtypes = [C.c_int]
     lib.ok_error_string.restype = C.c_char_p
     lib.ok_last_error.argtypes = [vp]
@@ -240,6 +286,9 @@ class Problem:
         self._check(self.lib.ok_autotune(self.ctx, _stream(self.stream), C.byref(n)), "ok_autotune")
         return n.value
 
+    def use_graphs(self, enable=True):
+        self._check(self.lib.ok_use_graphs(self.ctx, int(bool(enable))), "ok_use_graphs")
+
     def profile_enable(self, kernel_class):
         self._check(self.lib.ok_profile_enable(self.ctx, kernel_class), "ok_profile_enable")
 
@@ -248,6 +297,17 @@ class Problem:
         self._check(self.lib.ok_profile_read(self.ctx, C.byref(n), C.byref(ms), C.byref(by)),
                     "ok_profile_read")
         return n.value, ms.value, by.value
+
+
+def batch_workspace_bytes(params_list) -> int:
+    """ok_batch_workspace_bytes: device bytes of a batch (also one server pool
+    when every entry shares a class)."""
+    arr = (Params * len(params_list))(*params_list)
+    b = C.c_size_t()
+    st = load().ok_batch_workspace_bytes(arr, len(params_list), C.byref(b))
+    if st:
+        raise OkError(st, "ok_batch_workspace_bytes")
+    return b.value
 
 
 class Batch:
@@ -310,9 +370,111 @@ class Batch:
                     "ok_batch_autotune")
         return n.value
 
+    def use_graphs(self, enable=True):
+        self._check(self.lib.ok_batch_use_graphs(self.ctx, int(bool(enable))),
+                    "ok_batch_use_graphs")
+
     def close(self):
         if getattr(self, "ctx", None):
             self.lib.ok_batch_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def server_config(**kw) -> ServerConfig:
+    c = ServerConfig()
+    load().ok_server_default_config(C.byref(c))
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+class Server:
+    """Serving loop (ok_server_*): resident simulations, timestep requests,
+    admission by HBM budget, continuous batching on a native worker thread.
+    `budget_bytes` is the device memory for slot pools (the resident states
+    come on top of it)."""
+
+    def __init__(self, params_list, budget_bytes, config=None, device="cuda"):
+        import torch
+        self.lib = load()
+        self.count = len(params_list)
+        self.params = (Params * self.count)(*params_list)
+        self.device = torch.device(device)
+        b = C.c_size_t()
+        st = self.lib.ok_server_state_bytes(self.params, self.count, C.byref(b))
+        if st:
+            raise OkError(st, "ok_server_state_bytes")
+        self.state_bytes = b.value
+        self.ws_bytes = self.state_bytes + int(budget_bytes)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        self.config = config if config is not None else server_config()
+        self.ctx = C.c_void_p()
+        st = self.lib.ok_server_create(self.params, self.count, C.byref(self.config),
+                                       C.c_void_p(base + off), C.c_size_t(self.ws_bytes),
+                                       None, C.byref(self.ctx))
+        if st:
+            raise OkError(st, "ok_server_create")
+        self.nodes = [(p.n + 1) ** p.dim for p in params_list]
+
+    def _check(self, st, what):
+        if st:
+            raise OkError(st, f"{what}: {self.lib.ok_server_last_error(self.ctx).decode()}")
+
+    def set_state(self, i, u, w):
+        self._check(self.lib.ok_server_set_state(self.ctx, i, _ptr(u), _ptr(w), _stream(None)),
+                    "ok_server_set_state")
+
+    def get_state(self, i):
+        import torch
+        u = torch.empty(self.nodes[i], dtype=torch.float64, device=self.device)
+        w = torch.empty(self.nodes[i], dtype=torch.float64, device=self.device)
+        self._check(self.lib.ok_server_get_state(self.ctx, i, _ptr(u), _ptr(w), _stream(None)),
+                    "ok_server_get_state")
+        return u, w
+
+    def start(self):
+        self._check(self.lib.ok_server_start(self.ctx), "ok_server_start")
+
+    def now(self):
+        return self.lib.ok_server_now(self.ctx)
+
+    def submit(self, sim, nsteps=1, t_arrival=-1.0):
+        t = C.c_int64()
+        self._check(self.lib.ok_server_submit(self.ctx, sim, nsteps, float(t_arrival),
+                                              C.byref(t)), "ok_server_submit")
+        return t.value
+
+    def poll(self, max_results=4096, wait_s=0.0):
+        buf = (RequestResult * max_results)()
+        n = C.c_int32()
+        self._check(self.lib.ok_server_poll(self.ctx, buf, max_results, C.byref(n),
+                                            float(wait_s)), "ok_server_poll")
+        return [buf[i].as_dict() for i in range(n.value)]
+
+    def stop(self, drain=True):
+        self._check(self.lib.ok_server_stop(self.ctx, int(bool(drain))), "ok_server_stop")
+
+    def stats(self):
+        s = ServerStats()
+        self._check(self.lib.ok_server_get_stats(self.ctx, C.byref(s)), "ok_server_get_stats")
+        return s.as_dict()
+
+    def reset_stats(self):
+        self._check(self.lib.ok_server_reset_stats(self.ctx), "ok_server_reset_stats")
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.ok_server_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):

@@ -1,0 +1,106 @@
+"""Summaries of rocprofv3 CSV output (``--output-format csv``).
+
+    python -m paper_1603_04570_amd.profsum stats KERNEL_STATS_CSV [TOP]
+        per-kernel totals from ``--kernel-trace --stats`` (kt_kernel_stats.csv)
+
+    python -m paper_1603_04570_amd.profsum traffic --fetch F.csv --write W.csv \
+        --copy-fetch CF.csv --copy-write CW.csv --copy-bytes BYTES --kernel SUBSTRING \
+        [--main-grid]
+        per-dispatch HBM bytes of the kernels whose name contains SUBSTRING
+        (with --main-grid: only their dispatches of the most dispatched grid
+        size, i.e. the launch shape the run used most -- autotuner trials and
+        other levels excluded), from
+        two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs, each scaled by
+        what the same counter reads for a plain copy kernel of BYTES bytes read
+        and BYTES bytes written (the copy runs of ``bench.py --calibrate-copy``).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import re
+import statistics
+
+
+def short_name(name: str, width: int = 110) -> str:
+    n = re.sub(r"okd::\(anonymous namespace\)::", "", name).replace("okd::", "")
+    return n if len(n) <= width else n[: width - 3] + "..."
+
+
+def stats(path: str, top: int = 25) -> str:
+    rows = list(csv.DictReader(open(path)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = [f"total kernel time {tot / 1e6:.2f} ms over {sum(int(r['Calls']) for r in rows)} "
+           f"dispatches", f"{'ms':>9} {'%':>5} {'calls':>6} {'avg us':>9}  kernel"]
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    for r in rows[:top]:
+        t = float(r["TotalDurationNs"])
+        out.append(f"{t / 1e6:9.3f} {100 * t / tot:5.1f} {int(r['Calls']):6d} "
+                   f"{float(r['AverageNs']) / 1e3:9.2f}  {short_name(r['Name'])}")
+    return "\n".join(out)
+
+
+def _counter(path: str, counter: str, substring: str | None = None):
+    vals = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        if substring is not None and substring not in r["Kernel_Name"]:
+            continue
+        vals.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+    return vals
+
+
+def _copy_scale(path: str, counter: str, nbytes: int) -> float:
+    """Bytes per counter unit: the copy dispatches (the largest grid) of the
+    calibration run, median counter value."""
+    vals = _counter(path, counter)
+    big = max(g for _, g, _ in vals)
+    v = statistics.median(x for _, g, x in vals if g == big)
+    return nbytes / v
+
+
+def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, kernel, main_grid=False):
+    sf = _copy_scale(copy_fetch, "FETCH_SIZE", copy_bytes)
+    sw = _copy_scale(copy_write, "WRITE_SIZE", copy_bytes)
+    f = _counter(fetch, "FETCH_SIZE", kernel)
+    w = _counter(write, "WRITE_SIZE", kernel)
+    if not f or not w:
+        raise SystemExit(f"no dispatch of a kernel containing {kernel!r}")
+    if main_grid:
+        sizes = [x[1] for x in f]
+        g = max(set(sizes), key=sizes.count)
+        f = [x for x in f if x[1] == g]
+        w = [x for x in w if x[1] == g]
+    fb = statistics.mean(x for _, _, x in f) * sf
+    wb = statistics.mean(x for _, _, x in w) * sw
+    return {"kernel": short_name(f[0][0], 200), "grid_size": f[0][1],
+            "dispatches": [len(f), len(w)],
+            "fetch_scale_bytes_per_unit": sf, "write_scale_bytes_per_unit": sw,
+            "fetch_bytes_per_dispatch": fb, "write_bytes_per_dispatch": wb,
+            "traffic_bytes_per_dispatch": fb + wb}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("top", nargs="?", type=int, default=25)
+    b = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy-fetch", "copy-write", "kernel"):
+        b.add_argument("--" + k, required=True)
+    b.add_argument("--copy-bytes", type=int, required=True)
+    b.add_argument("--main-grid", action="store_true")
+    args = ap.parse_args()
+    if args.cmd == "stats":
+        print(stats(args.csv, args.top))
+    else:
+        r = traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.copy_bytes,
+                    args.kernel, args.main_grid)
+        for k, v in r.items():
+            print(f"{k}: {v}")
+
+
+if __name__ == "__main__":
+    main()

@@ -76,3 +76,45 @@ def test_batch_instance_matches_oracle():
         assert st == 0 and bs.its() == info.its()
         assert np.linalg.norm(ub - uo) / np.linalg.norm(uo) < 1e-10
         assert np.linalg.norm(wb - wo) / np.linalg.norm(wo) < 1e-10
+
+
+@pytest.mark.parametrize("dim,n,precision", [(2, 64, 0), (3, 16, 1)])
+def test_graph_replay_equals_direct_launches(dim, n, precision):
+    """Captured FGMRES iterations replay the same kernels: bitwise equal to
+    launching them one by one, also after a re-capture for another state
+    pointer."""
+    from paper_1603_04570_amd import ok
+    spec = dict(dim=dim, n=n, eps=0.02, sigma=100.0, m=0.1, theta=1.0,
+                dt=2e-4 if dim == 3 else 1e-4, seed=21)
+    p = params_for(spec, precision)
+    u0, w0 = noise_state(dim, n, spec["m"], spec["seed"])
+    outs = []
+    for graphs in (False, True):
+        P = ok.Problem(p)
+        if graphs:
+            P.use_graphs(True)
+        u = torch.from_numpy(u0).cuda()
+        w = torch.from_numpy(w0).cuda()
+        st = P.timestep(u, w, 2)
+        u2, w2 = u.clone(), w.clone()  # another state pointer: graphs re-captured
+        st2 = P.timestep(u2, w2, 1)
+        outs.append((u2.cpu().numpy(), w2.cpu().numpy(), st.its() + st2.its()))
+    assert outs[0][2] == outs[1][2]
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_batch_without_graphs_equals_with():
+    from paper_1603_04570_amd import ok
+    specs = [sweep_instance(i, sizes=(32, 64)) for i in range(4)]
+    res = []
+    for graphs in (True, False):
+        plist = [params_for(s, 1) for s in specs]
+        B = ok.Batch(plist)
+        B.use_graphs(graphs)
+        for i, s in enumerate(specs):
+            u0, w0 = noise_state(s["dim"], s["n"], s["m"], s["seed"])
+            B.set_state(i, torch.from_numpy(u0).cuda(), torch.from_numpy(w0).cuda())
+        st = B.timestep(1)
+        res.append([(B.get_state(i)[0].cpu().numpy(), st[i].its()) for i in range(len(specs))])
+    for a, b in zip(*res):
+        assert a[1] == b[1] and np.array_equal(a[0], b[0])
