@@ -34,6 +34,30 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# sources whose change invalidates a stored hardware-counter traffic figure
+TRAFFIC_SOURCES = ("paper_1603_04570_amd/csrc/k_stencil.hip", "paper_1603_04570_amd/csrc/ok_internal.h")
+
+
+def stored_traffic(config):
+    """HBM bytes per launch of the Chebyshev step measured with hardware
+    counters (profiles/cheb_step_<config>_traffic.txt), or None when there is
+    no such record or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"cheb_step_{config}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        rec[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if rec.get("source_sha256") != h.hexdigest():
+        return None
+    return float(rec["traffic_bytes_per_dispatch"])
 
 
 def cpu_model():
@@ -311,7 +335,8 @@ def main():
         per_launch = kbytes / launches
         ach = per_launch / avg_s / 1e9
         roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "traffic": stored_traffic(args.config) if prec == "fp64" else None,
                     "kernel": "Chebyshev-Jacobi iteration on M (k_stencil, EpiChebStep)",
                     "bytes_per_launch": per_launch, "avg_us": round(avg_s * 1e6, 2),
                     "launches": launches}
