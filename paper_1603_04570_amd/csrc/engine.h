@@ -64,6 +64,7 @@ struct ClassCtx {
   int *act = nullptr, *part = nullptr, *incyc = nullptr, *aux = nullptr;  // [B] flags
   double *V = nullptr, *X = nullptr, *Bv = nullptr, *T1 = nullptr;
   double *un = nullptr, *wn = nullptr, *G = nullptr, *su = nullptr, *sw = nullptr;
+  double* Q = nullptr;  // -(M_E(u) z1 + eps^2 K z1) of the last preconditioner application
   double *pA = nullptr, *pB = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr;
   double *g = nullptr, *y = nullptr, *kr = nullptr, *nrm = nullptr;
   void *Z = nullptr, *zt = nullptr;

@@ -188,6 +188,7 @@ void carve(ClassCtx& c, char* base, bool with_state, size_t* total) {
   c.un = cv.take<double>((size_t)B * n);
   c.wn = cv.take<double>((size_t)B * n);
   c.G = cv.take<double>((size_t)B * n);
+  c.Q = cv.take<double>((size_t)B * n);
   c.su = with_state ? cv.take<double>((size_t)B * n) : nullptr;
   c.sw = with_state ? cv.take<double>((size_t)B * n) : nullptr;
   c.zt = c.mixed ? cv.take<char>((size_t)B * n2 * ps) : nullptr;
@@ -367,14 +368,16 @@ int precond(ClassCtx& c, const int* fl, Vec<const double> u, Vec<const double> r
   int e = cheb_zero<double, P>(c, fl, OK_K_NONE, OK_K_CHEB_MASS, g, -1, CF_INV_SA,
                                c.shape.cheb_A_its, r1, z1, cr, cda, cdb, st);
   if (e) return e;
-  // y = r2 - C z1 = r2 + eps^2 K z1 + M_E(u) z1, M_E z1 = 3G - M z1 (G in FP64).
+  // y = r2 - C z1 = r2 + eps^2 K z1 + M_E(u) z1, M_E z1 = 3G - M z1 (G in FP64);
+  // Q = -(eps^2 K z1 + M_E(u) z1) is kept: the Jacobian applied to this z needs it.
   Vec<double> G = vec(c.G, n);
   {
-    ProfScope ps(c, OK_K_ELEMENT, (double)n * c.B * (8.0 + 8.0 + c.psz + 8.0), st);
-    OKE(c, launch_element<P, double>(g, B, 0, u, cst(z1), r2, 3.0, 1.0, G, st));
+    ProfScope ps(c, OK_K_ELEMENT, (double)n * c.B * (8.0 + c.psz + 8.0), st);
+    OKE(c, launch_element<P, double>(g, B, 0, u, cst(z1), Vec<const double>{nullptr, 0}, 3.0, 0.0,
+                                     G, st));
   }
   Vec<P> y = pvec<P>(c.yv, n), t = pvec<P>(c.tv, n), s = pvec<P>(c.sv, n);
-  OKE(c, launch_stencil_axpy<P, double, P>(g, B, cst(z1), cst(G), -1.0, CF_ONE, 1.0, CF_E2, y, st));
+  OKE(c, launch_couple<P>(g, B, cst(z1), cst(G), r2, y, vec(c.Q, n), st));
   if (c.shape.schur_richardson > 1)
     return set_err(c.err, OK_E_INVALID, "schur_richardson > 1 is not built on the GPU");
   // z2 = S^^-1 M S^^-1 y
@@ -403,6 +406,21 @@ int jac(ClassCtx& c, const int* fl, Vec<const double> u, Vec<const TX> x, Vec<do
   const int ff[2][4] = {{CF_SA, CF_ONE, CF_ONE, CF_DTH}, {CF_ONE, CF_E2, CF_ONE, CF_ONE}};
   OKE(c, launch_stencil_lin2<TX>(g, B, x, off(x, n), Vec<const double>{nullptr, 0}, cst(G), cf, ff,
                                  y, off(y, n), st));
+  return OK_SUCCESS;
+}
+
+// y = J(u) z for z = P^-1 v just computed by precond (same instances): the
+// coupling term of row 2 is the stored Q, so no quadrature pass is needed.
+//   y1 = sA M z1 + dt th K z2;  y2 = Q + M z2
+template <class P>
+int jac_z(ClassCtx& c, const int* fl, Vec<const P> z, Vec<double> y, hipStream_t st) {
+  const Grid& g = c.lev[0];
+  const Batch B = c.batch(fl);
+  const int64_t n = c.n;
+  const double cf[2][4] = {{1.0, 0.0, 0.0, 1.0}, {0.0, 0.0, 1.0, 0.0}};
+  const int ff[2][4] = {{CF_SA, CF_ONE, CF_ONE, CF_DTH}, {CF_ONE, CF_ONE, CF_ONE, CF_ONE}};
+  OKE(c, launch_stencil_lin2<P>(g, B, z, off(z, n), Vec<const double>{nullptr, 0},
+                                Vec<const double>{c.Q, n}, cf, ff, y, off(y, n), st));
   return OK_SUCCESS;
 }
 
@@ -435,7 +453,7 @@ int fgmres_iteration(ClassCtx& c, int j, Vec<const double> u, hipStream_t st) {
   Vec<P> Zj = Vec<P>{(P*)c.Z + (int64_t)j * n2, sZ(c)};
   int e = precond<P>(c, c.act, u, cst(Vj), Zj, st);
   if (e) return e;
-  e = jac<P>(c, c.act, u, cst(Zj), W, st);
+  e = jac_z<P>(c, c.act, cst(Zj), W, st);
   if (e) return e;
   Vec<double> pin = vec(c.pA, (int64_t)kMaxRedBlocks), pout = vec(c.pB, (int64_t)kMaxRedBlocks);
   {

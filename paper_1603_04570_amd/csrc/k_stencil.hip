@@ -183,15 +183,19 @@ __global__ void __launch_bounds__(kThreads)
     }
   }
 
-  double pre[NF][F];
+  // Prefetch registers hold the raw storage words; every load is issued
+  // unconditionally from a clamped (in-bounds) index, so no load sits in a
+  // lane-divergent branch and the loads of the next plane stay in flight
+  // until commit() converts them (out-of-range positions become 0 there).
+  TS pre[NF][F];
   auto issue = [&](int64_t zoff) {
 #pragma unroll
     for (int f = 0; f < NF; f++)
 #pragma unroll
       for (int k = 0; k < F; k++) {
-        const int t = tid + kThreads * k;
-        const int64_t gq = s0 - halo + t;
-        pre[f][k] = (t < ldsn && gq >= 0 && gq < plane) ? to_d(sp[f][zoff + gq]) : 0.0;
+        const int64_t gq = s0 - halo + tid + kThreads * k;
+        const int64_t gc = gq < 0 ? 0 : (gq >= plane ? plane - 1 : gq);
+        pre[f][k] = sp[f][zoff + gc];
       }
   };
   auto commit = [&]() {
@@ -200,7 +204,8 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
       for (int k = 0; k < F; k++) {
         const int t = tid + kThreads * k;
-        if (t < ldsn) lds[f * ldsn + t] = pre[f][k];
+        const int64_t gq = s0 - halo + t;
+        if (t < ldsn) lds[f * ldsn + t] = (gq >= 0 && gq < plane) ? to_d(pre[f][k]) : 0.0;
       }
   };
   // In-plane partial products: 3D P_M = (M1 x M1) s, P_K = (K1 x M1 + M1 x K1) s;
@@ -254,7 +259,11 @@ __global__ void __launch_bounds__(kThreads)
   for (int f = 0; f < NF; f++)
 #pragma unroll
     for (int p = 0; p < P; p++) pma[f][p] = pmb[f][p] = pka[f][p] = pkb[f][p] = cb[f][p] = 0.0;
-  if (z0 - 1 >= 0) issue((int64_t)(z0 - 1) * plane);
+  // Loads are never skipped by a branch (a skipped load would make the
+  // compiler wait for every outstanding load where the paths join): the
+  // first and last trips reload a clamped plane that is already cached.
+  const int zlast = min(z1, N);
+  issue((int64_t)max(z0 - 1, 0) * plane);
   for (int pz = z0 - 1; pz <= z1; pz++) {
     const bool inside = (pz >= 0 && pz <= N);
     const int o = pz - 1;  // output plane
@@ -262,12 +271,15 @@ __global__ void __launch_bounds__(kThreads)
     if (inside) commit();
     __syncthreads();
     In in[P];
-    if (o >= z0) {
+    {
+      const int oc = o < z0 ? z0 : o;
 #pragma unroll
-      for (int p = 0; p < P; p++)
-        if (valid[p]) in[p] = epi.load(inst, (int64_t)o * plane + s0 + tid + kThreads * p);
+      for (int p = 0; p < P; p++) {  // clamped: loaded by every lane, used if valid
+        const int64_t q = s0 + tid + kThreads * p;
+        in[p] = epi.load(inst, (int64_t)oc * plane + (q < plane ? q : plane - 1));
+      }
     }
-    if (pz + 1 <= z1 && pz + 1 <= N) issue((int64_t)(pz + 1) * plane);
+    issue((int64_t)min(pz + 1, zlast) * plane);
     double pmn[NF][P], pkn[NF][P], cn[NF][P];
     if (inside) {
       plane_partials(pmn, pkn, cn);
@@ -387,12 +399,17 @@ __device__ __forceinline__ double dinv_at(double dinv_int, int nb) {
   return dinv_int * (double)(1 << nb);
 }
 
+// Epilogue inputs in their storage types (converted where used, so the
+// loads stay in flight until the stencil sums are ready).
 struct In0 {};
+template <class A>
 struct In1 {
-  double a;
+  A a;
 };
+template <class A, class B>
 struct In2 {
-  double a, b;
+  A a;
+  B b;
 };
 struct OpK {
   double cm, ck, dinv, it, c1, c2, osc;
@@ -416,7 +433,7 @@ __device__ __forceinline__ OpK op_k(const InstCoef& C, int lev, int k, int osc) 
 // out = add + a*(M s) + b*(K s)
 template <class TA, class TO>
 struct EpiAxpy {
-  using In = In1;
+  using In = In1<TA>;
   struct K {
     double a, b;
   };
@@ -428,11 +445,11 @@ struct EpiAxpy {
     return K{ca * coef_field(C, fa), cb * coef_field(C, fb)};
   }
   __device__ In load(int inst, int64_t i) const {
-    return In{add.null() ? 0.0 : to_d(add.at(inst)[i])};
+    return In{add.null() ? (TA)0 : add.at(inst)[i]};
   }
   __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
                         const double*, const In& in, const K& k) const {
-    out.at(inst)[i] = (TO)(in.a + k.a * ms[0] + k.b * ks[0]);
+    out.at(inst)[i] = (TO)(to_d(in.a) + k.a * ms[0] + k.b * ks[0]);
   }
 };
 
@@ -440,7 +457,7 @@ struct EpiAxpy {
 //   out_o = add_o + c[o][0] M s0 + c[o][1] K s0 + c[o][2] M s1 + c[o][3] K s1
 template <class TO>
 struct EpiLin2 {
-  using In = In2;
+  using In = In2<double, double>;
   struct K {
     double c[2][4];
   };
@@ -464,6 +481,28 @@ struct EpiLin2 {
     if (!out1.null())
       out1.at(inst)[i] = (TO)(in.b + k.c[1][0] * ms[0] + k.c[1][1] * ks[0] + k.c[1][2] * ms[1] +
                               k.c[1][3] * ks[1]);
+  }
+};
+
+// Coupling of the block preconditioner (eq. (prec), factor [I,0;-CA^-1,I]):
+// with G = 3 int u^2 z1 phi, q = M_E(u) z1 + eps^2 K z1 = G - M z1 + eps^2 K z1;
+// writes y = r2 + q and nq = -q (kept for the Jacobian applied to this z).
+template <class TY>
+struct EpiCouple {
+  using In = In2<double, double>;
+  struct K {
+    double e2;
+  };
+  Vec<const double> g, r2;
+  Vec<TY> y;
+  Vec<double> nq;
+  __device__ K prep(const InstCoef& C) const { return K{C.e2}; }
+  __device__ In load(int inst, int64_t i) const { return In{g.at(inst)[i], r2.at(inst)[i]}; }
+  __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
+                        const double*, const In& in, const K& k) const {
+    const double q = in.a - ms[0] + k.e2 * ks[0];
+    y.at(inst)[i] = (TY)(in.b + q);
+    nq.at(inst)[i] = -q;
   }
 };
 
@@ -501,20 +540,20 @@ struct EpiChebFirst {
 // x_{k+2} = x_{k+1} + d_{k+1}, and writes only x.
 template <class T, bool LAST>
 struct EpiChebStep {
-  using In = In2;
+  using In = In2<T, T>;
   using K = OpK;
   int lev, k, osc;
   Vec<T> x, r, dn;
   __device__ K prep(const InstCoef& C) const { return op_k(C, lev, k, osc); }
   __device__ In load(int inst, int64_t i) const {
-    return In{to_d(x.at(inst)[i]), to_d(r.at(inst)[i])};
+    return In{x.at(inst)[i], r.at(inst)[i]};
   }
   __device__ void store(int inst, int64_t i, int nb, const double* ms, const double* ks,
                         const double* cen, const In& in, const K& kk) const {
     const double dk = cen[0];
     double dv = dinv_at(kk.dinv, nb);
-    double xv = in.a + dk;
-    double rv = in.b - (kk.cm * ms[0] + kk.ck * ks[0]);
+    double xv = to_d(in.a) + dk;
+    double rv = to_d(in.b) - (kk.cm * ms[0] + kk.ck * ks[0]);
     double d1 = kk.c1 * dk + kk.c2 * dv * rv;
     if (LAST) {
       x.at(inst)[i] = (T)(kk.osc * (xv + d1));
@@ -529,16 +568,16 @@ struct EpiChebStep {
 // Start from a given x (stencil input x): r0 = b - A x, d0 = D^-1 r0 it.
 template <class T>
 struct EpiChebStart {
-  using In = In1;
+  using In = In1<T>;
   using K = OpK;
   int lev;
   Vec<const T> b;
   Vec<T> r, d;
   __device__ K prep(const InstCoef& C) const { return op_k(C, lev, -1, CF_ONE); }
-  __device__ In load(int inst, int64_t i) const { return In{to_d(b.at(inst)[i])}; }
+  __device__ In load(int inst, int64_t i) const { return In{b.at(inst)[i]}; }
   __device__ void store(int inst, int64_t i, int nb, const double* ms, const double* ks,
                         const double*, const In& in, const K& k) const {
-    double r0 = in.a - (k.cm * ms[0] + k.ck * ks[0]);
+    double r0 = to_d(in.a) - (k.cm * ms[0] + k.ck * ks[0]);
     r.at(inst)[i] = (T)r0;
     d.at(inst)[i] = (T)(dinv_at(k.dinv, nb) * r0 * k.it);
   }
@@ -562,16 +601,16 @@ struct EpiChebOne {
 // r = b - A x
 template <class T>
 struct EpiResid {
-  using In = In1;
+  using In = In1<T>;
   using K = OpK;
   int lev;
   Vec<const T> b;
   Vec<T> r;
   __device__ K prep(const InstCoef& C) const { return op_k(C, lev, -1, CF_ONE); }
-  __device__ In load(int inst, int64_t i) const { return In{to_d(b.at(inst)[i])}; }
+  __device__ In load(int inst, int64_t i) const { return In{b.at(inst)[i]}; }
   __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
                         const double*, const In& in, const K& k) const {
-    r.at(inst)[i] = (T)(in.a - (k.cm * ms[0] + k.ck * ks[0]));
+    r.at(inst)[i] = (T)(to_d(in.a) - (k.cm * ms[0] + k.ck * ks[0]));
   }
 };
 
@@ -614,6 +653,13 @@ hipError_t launch_stencil_lin2(const Grid& g, const Batch& B, Vec<const TS> s0, 
   e.out1 = out1;
   Src<TS, 2> src{{s0.p, s1.p}, {s0.s, s1.s}};
   return run_stencil_n<false, TS, 2>(g, B, src, e, st);
+}
+
+template <class T>
+hipError_t launch_couple(const Grid& g, const Batch& B, Vec<const T> z1, Vec<const double> G,
+                         Vec<const double> r2, Vec<T> y, Vec<double> nq, hipStream_t st) {
+  EpiCouple<T> e{G, r2, y, nq};
+  return run_stencil<false>(g, B, z1, e, st);
 }
 
 template <class TB, class T>
@@ -694,6 +740,12 @@ template hipError_t launch_stencil_lin2<float>(const Grid&, const Batch&, Vec<co
                                                Vec<const double>, const double (&)[2][4],
                                                const int (&)[2][4], Vec<double>, Vec<double>,
                                                hipStream_t);
+template hipError_t launch_couple<double>(const Grid&, const Batch&, Vec<const double>,
+                                          Vec<const double>, Vec<const double>, Vec<double>,
+                                          Vec<double>, hipStream_t);
+template hipError_t launch_couple<float>(const Grid&, const Batch&, Vec<const float>,
+                                         Vec<const double>, Vec<const double>, Vec<float>,
+                                         Vec<double>, hipStream_t);
 #define OKD_CHEB_TB(TB, T)                                                                    \
   template hipError_t launch_cheb_one<TB, T>(const Grid&, const Batch&, int, int,              \
                                              Vec<const TB>, Vec<T>, hipStream_t);              \

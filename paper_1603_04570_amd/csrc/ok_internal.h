@@ -132,6 +132,11 @@ hipError_t launch_stencil_lin2(const Grid& g, const Batch& B, Vec<const TS> s0, 
                                Vec<const double> add0, Vec<const double> add1,
                                const double (&c)[2][4], const int (&f)[2][4], Vec<double> out0,
                                Vec<double> out1, hipStream_t st);
+// Preconditioner coupling: q = G - M z1 + eps^2 K z1 (G = 3 int u^2 z1 phi);
+// y = r2 + q, nq = -q.
+template <class T>
+hipError_t launch_couple(const Grid& g, const Batch& B, Vec<const T> z1, Vec<const double> G,
+                         Vec<const double> r2, Vec<T> y, Vec<double> nq, hipStream_t st);
 // Chebyshev-Jacobi building blocks (Saad, Alg. 12.1):
 // one iteration from x0 = 0: x = oscale * D^-1 b * it
 template <class TB, class T>
