@@ -178,17 +178,24 @@ int ok_newton_step(ok_ctx *ctx, double *d_u, double *d_w, const double *d_un,
 int ok_timestep(ok_ctx *ctx, double *d_u, double *d_w, int32_t nsteps, ok_stats *stats,
                 void *stream);
 
-/* Per-kernel timing for roofline reporting: after ok_profile_enable(ctx, k)
- * every launch of kernel class k is bracketed by HIP events on the stream it
- * runs on; ok_profile_read returns the number of launches, their summed
- * duration and the algorithmic bytes they moved (each vector read once and
- * written once), then clears the counters.  Classes are listed below. */
+/* Per-kernel timing for roofline reporting: after ok_profile_enable(ctx,
+ * mask) every launch of a kernel class c with bit (1 << c) set in mask is
+ * bracketed by HIP events on the stream it runs on (captured graphs are not
+ * used meanwhile); ok_profile_read(ctx, c, ...) returns, for class c, the
+ * number of launches, their summed duration and the algorithmic bytes they
+ * moved (each vector read once and written once).  ok_profile_enable resets
+ * the records; mask 0 stops profiling.
+ *   OK_K_CHEB_MASS: middle Chebyshev iterations on M (the A~^-1 block)
+ *   OK_K_MG_SMOOTH: finest-level smoother and residual launches of the V-cycle
+ *   OK_K_ELEMENT:   quadrature passes (M_E(u) x, N(u))
+ *   OK_K_KRYLOV:    Gram-Schmidt steps and dot products of FGMRES */
 enum ok_kernel_class {
   OK_K_NONE = 0, OK_K_CHEB_MASS = 1, OK_K_MG_SMOOTH = 2, OK_K_ELEMENT = 3,
-  OK_K_STENCIL_ANY = 4, OK_K_KRYLOV = 5
+  OK_K_KRYLOV = 5
 };
-int ok_profile_enable(ok_ctx *ctx, int32_t kernel_class);
-int ok_profile_read(ok_ctx *ctx, int64_t *launches, double *total_ms, double *bytes);
+int ok_profile_enable(ok_ctx *ctx, int32_t class_mask);
+int ok_profile_read(ok_ctx *ctx, int32_t kernel_class, int64_t *launches, double *total_ms,
+                    double *bytes);
 
 /* Tile autotuner: time the candidate launch shapes (nodes per thread x planes
  * per block) of the stencil kernels on this problem's grids -- every
@@ -199,6 +206,13 @@ int ok_profile_read(ok_ctx *ctx, int64_t *launches, double *total_ms, double *by
  * bitwise the same for every shape.  *entries (may be NULL) receives the
  * number of table entries set.  Synchronises; run it outside timed regions. */
 int ok_autotune(ok_ctx *ctx, void *stream, int32_t *entries);
+
+/* Process-wide tuning options (results are bitwise the same either way):
+ *   OK_OPT_FUSE_CHEB: 1 (default) runs consecutive middle iterations of the
+ *   Chebyshev iteration on M two per pass (each vector read and written once
+ *   per pair); 0 runs them one per pass. */
+enum ok_option { OK_OPT_FUSE_CHEB = 1 };
+int ok_set_option(int32_t option, int32_t value);
 
 /* Launch mode of the FGMRES iterations.  enable != 0: the context gets a HIP
  * stream of its own (default priority) and captures each Arnoldi iteration j

@@ -17,9 +17,10 @@ struct ProfPair {
   hipEvent_t a, b;
   double bytes;
   int count;  // kernel launches between the two events
+  int cls;    // kernel class of those launches
 };
 struct Prof {
-  int cls = OK_K_NONE;
+  int mask = 0;  // bit c set: launches of kernel class c are timed
   bool capturing = false;  // no events while a graph is being captured
   std::vector<ProfPair> ev;
   size_t used = 0;
@@ -69,6 +70,8 @@ struct ClassCtx {
   double *g = nullptr, *y = nullptr, *kr = nullptr, *nrm = nullptr;
   void *Z = nullptr, *zt = nullptr;
   void *cr = nullptr, *cda = nullptr, *cdb = nullptr, *yv = nullptr, *tv = nullptr, *sv = nullptr;
+  void* cr2 = nullptr;  // second Chebyshev residual (fused iterations ping-pong r)
+  void* rich = nullptr;  // Richardson on S (schur_richardson > 1): 4 vectors of n
   void* mg[kMaxLevels][5]{};  // x, b, r, d, d' per level
   // ---- host mirrors ----
   std::vector<int> h_act, h_part, h_aux;

@@ -54,9 +54,7 @@ struct ProfScope {
   ProfScope(const ClassCtx& c, int cls, double bytes, hipStream_t s, int count = 1)
       : p(c.prof), st(s) {
     if (!p || p->capturing || cls == OK_K_NONE) return;
-    bool on = (p->cls == cls) || (p->cls == OK_K_STENCIL_ANY && cls != OK_K_KRYLOV &&
-                                  cls != OK_K_ELEMENT);
-    if (!on) return;
+    if (!((p->mask >> cls) & 1)) return;
     if (p->used == p->ev.size()) {
       ProfPair q{};
       (void)hipEventCreate(&q.a);
@@ -66,6 +64,7 @@ struct ProfScope {
     pp = &p->ev[p->used++];
     pp->bytes = bytes;
     pp->count = count;
+    pp->cls = cls;
     (void)hipEventRecord(pp->a, st);
   }
   ~ProfScope() {
@@ -193,6 +192,8 @@ void carve(ClassCtx& c, char* base, bool with_state, size_t* total) {
   c.sw = with_state ? cv.take<double>((size_t)B * n) : nullptr;
   c.zt = c.mixed ? cv.take<char>((size_t)B * n2 * ps) : nullptr;
   c.cr = cv.take<char>((size_t)B * n * ps);
+  c.cr2 = cv.take<char>((size_t)B * n * ps);
+  c.rich = c.shape.schur_richardson > 1 ? cv.take<char>((size_t)B * 4 * n * ps) : nullptr;
   c.cda = cv.take<char>((size_t)B * n * ps);
   c.cdb = cv.take<char>((size_t)B * n * ps);
   c.yv = cv.take<char>((size_t)B * n * ps);
@@ -259,7 +260,8 @@ Vec<T> off(Vec<T> v, int64_t o) {
 // ---------------------------------------------------------------------------
 template <class TB, class P>
 int cheb_zero(ClassCtx& c, const int* fl, int cls, int step_cls, const Grid& g, int lev, int osc,
-              int K, Vec<const TB> b, Vec<P> x, Vec<P> r, Vec<P> da, Vec<P> db, hipStream_t st) {
+              int K, Vec<const TB> b, Vec<P> x, Vec<P> r, Vec<P> da, Vec<P> db, hipStream_t st,
+              Vec<P> r2 = Vec<P>{nullptr, 0}) {
   const Batch B = c.batch(fl);
   const double w = (double)c.psz * g.nodes * c.B, wb = (double)sizeof(TB) * g.nodes * c.B;
   if (K > kMaxCheb) return set_err(c.err, OK_E_INVALID, "too many Chebyshev iterations");
@@ -274,6 +276,26 @@ int cheb_zero(ClassCtx& c, const int* fl, int cls, int step_cls, const Grid& g, 
   }
   if (K == 2) return OK_SUCCESS;
   Vec<P> dc = da, dn = db;
+  if (lev < 0 && K >= 4 && !r2.null() && cheb_fusion_on(g, (int)sizeof(P))) {
+    // iterations 1 .. K-2 (the last one final) in fused pairs; an odd count
+    // starts with one single iteration; r alternates between r and r2
+    Vec<P> rc = r, rn = r2;
+    int k = 1;
+    if ((K - 2) % 2) {
+      ProfScope ps(c, step_cls, 6.0 * w, st);
+      OKE(c, launch_cheb_step<P>(g, B, lev, k, osc, false, x, rc, cst(dc), dn, st));
+      std::swap(dc, dn);
+      k++;
+    }
+    for (; k <= K - 2; k += 2) {
+      const bool last2 = (k + 1 == K - 2);
+      ProfScope ps(c, last2 ? cls : step_cls, (last2 ? 4.0 : 6.0) * w, st);
+      OKE(c, launch_cheb_step2<P>(g, B, k, osc, last2, x, cst(rc), rn, cst(dc), dn, st));
+      std::swap(dc, dn);
+      std::swap(rc, rn);
+    }
+    return OK_SUCCESS;
+  }
   {
     const int mid = K > 3 ? K - 3 : 0;
     ProfScope ps(c, step_cls, 6.0 * w * mid, st, mid);
@@ -354,6 +376,19 @@ int mg_apply(ClassCtx& c, const int* fl, Vec<const P> b, Vec<P> x, int cycles, h
   return OK_SUCCESS;
 }
 
+// x = S~^-1 b = S^^-1 M S^^-1 b, eq. (schurinv); t, s: work vectors.
+template <class P>
+int schur_tilde_inv(ClassCtx& c, const int* fl, Vec<const P> b, Vec<P> x, Vec<P> t, Vec<P> s,
+                    hipStream_t st) {
+  const Grid& g = c.lev[0];
+  const Batch B = c.batch(fl);
+  int e = mg_apply<P>(c, fl, b, t, c.shape.mg_cycles, st);
+  if (e) return e;
+  OKE(c, launch_stencil_axpy<P, P, P>(g, B, cst(t), Vec<const P>{nullptr, 0}, 1.0, CF_ONE, 0.0,
+                                      CF_ONE, s, st));
+  return mg_apply<P>(c, fl, cst(s), x, c.shape.mg_cycles, st);
+}
+
 // z = [z1; z2] = P^-1 [r1; r2], eq. (prec) with S~^-1 = S^^-1 M S^^-1.
 template <class P>
 int precond(ClassCtx& c, const int* fl, Vec<const double> u, Vec<const double> r, Vec<P> z,
@@ -366,7 +401,7 @@ int precond(ClassCtx& c, const int* fl, Vec<const double> u, Vec<const double> r
   Vec<P> cr = pvec<P>(c.cr, n), cda = pvec<P>(c.cda, n), cdb = pvec<P>(c.cdb, n);
   // z1 = A~^-1 r1: Chebyshev on M, scaled by 1/(1 + dt th sigma).
   int e = cheb_zero<double, P>(c, fl, OK_K_NONE, OK_K_CHEB_MASS, g, -1, CF_INV_SA,
-                               c.shape.cheb_A_its, r1, z1, cr, cda, cdb, st);
+                               c.shape.cheb_A_its, r1, z1, cr, cda, cdb, st, pvec<P>(c.cr2, n));
   if (e) return e;
   // y = r2 - C z1 = r2 + eps^2 K z1 + M_E(u) z1, M_E z1 = 3G - M z1 (G in FP64);
   // Q = -(eps^2 K z1 + M_E(u) z1) is kept: the Jacobian applied to this z needs it.
@@ -378,14 +413,30 @@ int precond(ClassCtx& c, const int* fl, Vec<const double> u, Vec<const double> r
   }
   Vec<P> y = pvec<P>(c.yv, n), t = pvec<P>(c.tv, n), s = pvec<P>(c.sv, n);
   OKE(c, launch_couple<P>(g, B, cst(z1), cst(G), r2, y, vec(c.Q, n), st));
-  if (c.shape.schur_richardson > 1)
-    return set_err(c.err, OK_E_INVALID, "schur_richardson > 1 is not built on the GPU");
-  // z2 = S^^-1 M S^^-1 y
-  e = mg_apply<P>(c, fl, cst(y), t, c.shape.mg_cycles, st);
+  // z2 = S~^-1 y = S^^-1 M S^^-1 y
+  e = schur_tilde_inv<P>(c, fl, cst(y), z2, t, s, st);
   if (e) return e;
-  OKE(c, launch_stencil_axpy<P, P, P>(g, B, cst(t), Vec<const P>{nullptr, 0}, 1.0, CF_ONE, 0.0,
-                                      CF_ONE, s, st));
-  return mg_apply<P>(c, fl, cst(s), z2, c.shape.mg_cycles, st);
+  // Sec. 4: further Richardson iterations z2 += S~^-1 (y - S z2), with
+  // S z2 = M z2 + (eps^2 K + M_E(u)) A~^-1 (dt th K z2) applied matrix-free
+  if (c.shape.schur_richardson > 1) {
+    const int64_t sp = (int64_t)4 * n;
+    Vec<P> rt = pvec<P>(c.rich, sp), ra = off(rt, n), res = off(rt, 2 * n), cor = off(rt, 3 * n);
+    rt.s = ra.s = res.s = cor.s = sp;
+    for (int it = 1; it < c.shape.schur_richardson; it++) {
+      OKE(c, launch_stencil_axpy<P, P, P>(g, B, cst(z2), Vec<const P>{nullptr, 0}, 0.0, CF_ONE,
+                                          1.0, CF_DTH, rt, st));
+      e = cheb_zero<P, P>(c, fl, OK_K_NONE, OK_K_NONE, g, -1, CF_INV_SA, c.shape.cheb_A_its,
+                          cst(rt), ra, cr, cda, cdb, st, pvec<P>(c.cr2, n));
+      if (e) return e;
+      OKE(c, launch_element<P, double>(g, B, 0, u, cst(ra), Vec<const double>{nullptr, 0}, 3.0,
+                                       0.0, G, st));
+      OKE(c, launch_schur_res<P>(g, B, cst(ra), cst(z2), cst(G), cst(y), res, st));
+      e = schur_tilde_inv<P>(c, fl, cst(res), cor, t, s, st);
+      if (e) return e;
+      OKE(c, launch_add_inplace<P>(B, z2, cst(cor), n, st));
+    }
+  }
+  return OK_SUCCESS;
 }
 
 // y = J(u) x, eq. (newton); x of type TX (2n), y FP64 (2n).
@@ -479,7 +530,7 @@ int fgmres_iteration(ClassCtx& c, int j, Vec<const double> u, hipStream_t st) {
 // shapes), or launched kernel by kernel.  No graphs while kernels are profiled.
 int run_iteration(ClassCtx& c, int j, Vec<const double> u, hipStream_t s) {
   ClassExec* x = c.ex.get();
-  const bool profiling = c.prof && c.prof->cls != OK_K_NONE;
+  const bool profiling = c.prof && c.prof->mask != 0;
   if (!x || !x->graphs || profiling)
     return c.mixed ? fgmres_iteration<float>(c, j, u, s) : fgmres_iteration<double>(c, j, u, s);
   if (x->key != (const void*)u.p || (int)x->iter.size() != c.m) {
@@ -666,11 +717,13 @@ int cheb_mass_d(ClassCtx& c, const int* flags, Vec<const double> r, Vec<double> 
   if (!c.mixed)
     return cheb_zero<double, double>(c, flags, OK_K_NONE, OK_K_CHEB_MASS, g, -1, CF_ONE,
                                      c.shape.cheb_A_its, r, x, pvec<double>(c.cr, n),
-                                     pvec<double>(c.cda, n), pvec<double>(c.cdb, n), st);
+                                     pvec<double>(c.cda, n), pvec<double>(c.cdb, n), st,
+                                     pvec<double>(c.cr2, n));
   Vec<float> xf = pvec<float>(c.zt, c.n2());
   int e = cheb_zero<double, float>(c, flags, OK_K_NONE, OK_K_CHEB_MASS, g, -1, CF_ONE,
                                    c.shape.cheb_A_its, r, xf, pvec<float>(c.cr, n),
-                                   pvec<float>(c.cda, n), pvec<float>(c.cdb, n), st);
+                                   pvec<float>(c.cda, n), pvec<float>(c.cdb, n), st,
+                                   pvec<float>(c.cr2, n));
   if (e) return e;
   OKE(c, launch_copy_scale<float, double>(c.batch(flags), cst(xf), x, 1.0, n, st));
   return OK_SUCCESS;
@@ -1062,6 +1115,42 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
       }
     stencil_tune_set(g.dim, g.nn, 1, word, bi, bz);
     if (bi) (*entries)++;
+  }
+  stencil_tune_set(c.lev[0].dim, c.lev[0].nn, kFusedKey, word, 0, 0);
+  if (cheb_fusion_on(c.lev[0], word)) {  // fused pairs of Chebyshev iterations on M
+    const Grid& g = c.lev[0];
+    const int64_t nl = g.nodes;
+    Vec<P> x = pvec<P>(c.yv, nl), r = pvec<P>(c.cr, nl), d0 = pvec<P>(c.cda, nl),
+           d1 = pvec<P>(c.cdb, nl);
+    double best = 1e30;
+    int bi = 0, bz = 0;
+    for (int items = 1; items <= 2; items *= 2)
+      for (int zc : zcs) {
+        if (zc > g.nn && zc != 4) continue;
+        stencil_tune_set(g.dim, g.nn, kFusedKey, word, items, zc);
+        if (!cheb_fusion_on(g, word)) continue;
+        double t = time_best(st, [&]() {
+          return launch_cheb_step2<P>(g, B, 1, CF_ONE, false, x, cst(r), pvec<P>(c.cr2, nl),
+                                      cst(d0), d1, st);
+        });
+        if (t < best) {
+          best = t;
+          bi = items;
+          bz = zc;
+        }
+      }
+    // keep the fusion only where a pair beats two single iterations on M
+    const double single = time_best(st, [&]() {
+      hipError_t e = launch_cheb_step<P>(g, B, -1, 1, CF_ONE, false, x, r, cst(d0), d1, st);
+      if (e == hipSuccess)
+        e = launch_cheb_step<P>(g, B, -1, 2, CF_ONE, false, x, r, cst(d1), d0, st);
+      return e;
+    });
+    if (bi && best < single)
+      stencil_tune_set(g.dim, g.nn, kFusedKey, word, bi, bz);
+    else
+      stencil_tune_set(g.dim, g.nn, kFusedKey, word, -1, 0);
+    (*entries)++;
   }
   {
     const Grid& g = c.lev[0];

@@ -23,37 +23,50 @@ namespace {
 __device__ __forceinline__ double ld(const double* p) { return *p; }
 __device__ __forceinline__ double ld(const float* p) { return (double)*p; }
 
+// One thread per node of the output grid, flat index per instance (< 2^31
+// nodes), decomposed with 32-bit divisions.
+template <int DIM>
+__device__ __forceinline__ void node_ijk(unsigned q, unsigned nn, int& i, int& j, int& k) {
+  const unsigned row = q / nn;
+  i = (int)(q - row * nn);
+  if (DIM == 3) {
+    j = (int)(row % nn);
+    k = (int)(row / nn);
+  } else {
+    j = (int)row;
+    k = 0;
+  }
+}
+
 template <int DIM, class T>
 __global__ void __launch_bounds__(256)
     k_restrict(Vec<const T> rv, Vec<T> bcv, Grid f, Grid c, Batch B, int per) {
   const int inst = blockIdx.x / per;
   if (B.act && !B.act[inst]) return;
+  const unsigned q = (unsigned)(blockIdx.x - inst * per) * blockDim.x + threadIdx.x;
+  if (q >= (unsigned)c.nodes) return;
+  int ci, cj, ck;
+  node_ijk<DIM>(q, (unsigned)c.nn, ci, cj, ck);
   const T* __restrict__ r = rv.at(inst);
-  T* __restrict__ bc = bcv.at(inst);
-  int64_t I = (int64_t)(blockIdx.x % per) * blockDim.x + threadIdx.x;
-  if (I >= c.nodes) return;
-  int ci = (int)(I % c.nn);
-  int cj = (int)((I / c.nn) % c.nn);
-  int ck = (DIM == 3) ? (int)(I / c.plane) : 0;
-  double s = 0.0;
   const int kz = (DIM == 3) ? 1 : 0;
+  double s = 0.0;
   for (int dk = -kz; dk <= kz; dk++) {
-    int fk = 2 * ck + dk;
+    const int fk = 2 * ck + dk;
     if (fk < 0 || fk > f.N) continue;
-    double wk = dk ? 0.5 : 1.0;
+    const double wk = dk ? 0.5 : 1.0;
     for (int dj = -1; dj <= 1; dj++) {
-      int fj = 2 * cj + dj;
+      const int fj = 2 * cj + dj;
       if (fj < 0 || fj > f.N) continue;
-      double wj = wk * (dj ? 0.5 : 1.0);
-      int64_t row = (int64_t)fk * f.plane + (int64_t)fj * f.nn;
+      const double wj = wk * (dj ? 0.5 : 1.0);
+      const T* fr = r + (int64_t)fk * f.plane + (int64_t)fj * f.nn;
       for (int di = -1; di <= 1; di++) {
-        int fi = 2 * ci + di;
+        const int fi = 2 * ci + di;
         if (fi < 0 || fi > f.N) continue;
-        s += wj * (di ? 0.5 : 1.0) * ld(r + row + fi);
+        s += wj * (di ? 0.5 : 1.0) * ld(fr + fi);
       }
     }
   }
-  bc[I] = (T)s;
+  bcv.at(inst)[q] = (T)s;
 }
 
 template <int DIM, class T>
@@ -61,34 +74,33 @@ __global__ void __launch_bounds__(256)
     k_prolong_add(Vec<const T> ecv, Vec<T> xv, Grid f, Grid c, Batch B, int per) {
   const int inst = blockIdx.x / per;
   if (B.act && !B.act[inst]) return;
+  const unsigned q = (unsigned)(blockIdx.x - inst * per) * blockDim.x + threadIdx.x;
+  if (q >= (unsigned)f.nodes) return;
+  int fi, fj, fk;
+  node_ijk<DIM>(q, (unsigned)f.nn, fi, fj, fk);
   const T* __restrict__ ec = ecv.at(inst);
   T* __restrict__ x = xv.at(inst);
-  int64_t i = (int64_t)(blockIdx.x % per) * blockDim.x + threadIdx.x;
-  if (i >= f.nodes) return;
-  int fi = (int)(i % f.nn);
-  int fj = (int)((i / f.nn) % f.nn);
-  int fk = (DIM == 3) ? (int)(i / f.plane) : 0;
-  int lo[3] = {fi >> 1, fj >> 1, fk >> 1};
-  int hi[3] = {(fi + 1) >> 1, (fj + 1) >> 1, (fk + 1) >> 1};
-  double s = 0.0;
+  const int lo0 = fi >> 1, hi0 = (fi + 1) >> 1;
+  const int lo1 = fj >> 1, hi1 = (fj + 1) >> 1, lo2 = fk >> 1, hi2 = (fk + 1) >> 1;
   const int nz = (DIM == 3) ? 2 : 1;
+  double s = 0.0;
   for (int a = 0; a < nz; a++) {
-    int K = a ? hi[2] : lo[2];
-    if (a && hi[2] == lo[2]) continue;
-    double wk = (DIM == 3 && hi[2] != lo[2]) ? 0.5 : 1.0;
+    const int K = a ? hi2 : lo2;
+    if (a && hi2 == lo2) continue;
+    const double wk = (DIM == 3 && hi2 != lo2) ? 0.5 : 1.0;
     for (int bb = 0; bb < 2; bb++) {
-      int J = bb ? hi[1] : lo[1];
-      if (bb && hi[1] == lo[1]) continue;
-      double wj = wk * ((hi[1] != lo[1]) ? 0.5 : 1.0);
+      const int J = bb ? hi1 : lo1;
+      if (bb && hi1 == lo1) continue;
+      const double wj = wk * ((hi1 != lo1) ? 0.5 : 1.0);
+      const T* cr = ec + (int64_t)K * c.plane + (int64_t)J * c.nn;
       for (int cc = 0; cc < 2; cc++) {
-        int Ii = cc ? hi[0] : lo[0];
-        if (cc && hi[0] == lo[0]) continue;
-        double w = wj * ((hi[0] != lo[0]) ? 0.5 : 1.0);
-        s += w * ld(ec + (int64_t)K * c.plane + (int64_t)J * c.nn + Ii);
+        const int I = cc ? hi0 : lo0;
+        if (cc && hi0 == lo0) continue;
+        s += wj * ((hi0 != lo0) ? 0.5 : 1.0) * ld(cr + I);
       }
     }
   }
-  x[i] = (T)(ld(x + i) + s);
+  x[q] = (T)(ld(x + q) + s);
 }
 
 constexpr int kCoarseMax = 1024;   // nodes of the coarse grid
@@ -178,8 +190,8 @@ __global__ void __launch_bounds__(1024)
 template <class T>
 hipError_t launch_restrict(const Grid& fine, const Grid& coarse, const Batch& B, Vec<const T> r,
                            Vec<T> bc, hipStream_t st) {
-  int per = (int)((coarse.nodes + 255) / 256);
-  dim3 grid((unsigned)(per * B.count)), block(256);
+  const int per = (int)((coarse.nodes + 255) / 256);
+  dim3 grid((unsigned)((int64_t)per * B.count)), block(256);
   if (fine.dim == 2)
     hipLaunchKernelGGL((k_restrict<2, T>), grid, block, 0, st, r, bc, fine, coarse, B, per);
   else
@@ -190,8 +202,8 @@ hipError_t launch_restrict(const Grid& fine, const Grid& coarse, const Batch& B,
 template <class T>
 hipError_t launch_prolong_add(const Grid& fine, const Grid& coarse, const Batch& B,
                               Vec<const T> ec, Vec<T> x, hipStream_t st) {
-  int per = (int)((fine.nodes + 255) / 256);
-  dim3 grid((unsigned)(per * B.count)), block(256);
+  const int per = (int)((fine.nodes + 255) / 256);
+  dim3 grid((unsigned)((int64_t)per * B.count)), block(256);
   if (fine.dim == 2)
     hipLaunchKernelGGL((k_prolong_add<2, T>), grid, block, 0, st, ec, x, fine, coarse, B, per);
   else

@@ -20,6 +20,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 namespace okd {
 
@@ -41,7 +42,7 @@ std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune;  // (dim, 
 
 void stencil_tune_set(int dim, int nn, int nf, int word, int items, int zc) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  if (items <= 0)
+  if (items == 0)
     g_tune.erase(std::make_tuple(dim, nn, nf, word));
   else
     g_tune[std::make_tuple(dim, nn, nf, word)] = std::make_pair(items, zc);
@@ -70,7 +71,8 @@ StencilShape stencil_shape(const Grid& g, int nf, int word) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(std::make_tuple(g.dim, g.nn, nf, word));
-    if (it != g_tune.end()) return shape_with(g, it->second.first, it->second.second);
+    if (it != g_tune.end() && it->second.first > 0)
+      return shape_with(g, it->second.first, it->second.second);
   }
   StencilShape s;
   const int target = 1024;
@@ -78,7 +80,7 @@ StencilShape stencil_shape(const Grid& g, int nf, int word) {
   const int64_t plane = (g.dim == 3) ? g.plane : (int64_t)g.nn;
   // Largest per-thread item count that still gives ~1024 blocks with at
   // least 8 planes per block; small grids fall back to 1 item, 4 planes.
-  int items = (nf > 1) ? 4 : 8;
+  int items = (nf == kFusedKey) ? 2 : ((nf > 1) ? 4 : 8);
   for (; items > 1; items /= 2) {
     int64_t nch = (plane + kThreads * items - 1) / (kThreads * items);
     if (nch * ((g.nn + 7) / 8) >= target) break;
@@ -127,6 +129,32 @@ __device__ __forceinline__ void pattern(int i, int N, double& a0, double& a1, do
   b2 = -wr * sr;
 }
 
+// Unscaled 1D rows of node i applied to its neighbours (l, c, r) read from a
+// linearised plane: the neighbours of the end nodes (i = 0, N) lie in other
+// rows and are dropped (hl, hr), the diagonal of M1 is 4 inside and 2 at the
+// ends, of K1 2 and 1 (constants h/6, 1/h applied later).  Kept as masks and
+// one end flag per node instead of six coefficients, which would otherwise
+// occupy registers for the whole streaming loop.
+__device__ __forceinline__ double m1_row(bool hl, bool hr, bool end, double l, double c,
+                                         double r) {
+  return fma(end ? 2.0 : 4.0, c, hl ? l : 0.0) + (hr ? r : 0.0);
+}
+__device__ __forceinline__ double k1_row(bool hl, bool hr, bool end, double l, double c,
+                                         double r) {
+  return fma(end ? 1.0 : 2.0, c, hl ? -l : 0.0) - (hr ? r : 0.0);
+}
+
+// Epilogues of operators without stiffness (the Chebyshev iteration on M)
+// declare kMass = true; the streaming kernel then skips the K partials.
+template <class E, class = void>
+struct MassOnly {
+  static constexpr bool value = false;
+};
+template <class E>
+struct MassOnly<E, std::void_t<decltype(E::kMass)>> {
+  static constexpr bool value = E::kMass;
+};
+
 __device__ __forceinline__ double to_d(double v) { return v; }
 __device__ __forceinline__ double to_d(float v) { return (double)v; }
 
@@ -149,6 +177,7 @@ __global__ void __launch_bounds__(kThreads)
     k_stencil(Src<TS, NF> src, Grid g, StencilShape sh, Batch B, Epi epi) {
   extern __shared__ double lds[];
   using In = typename Epi::In;
+  constexpr bool MASS = MassOnly<Epi>::value;
   const int tid = threadIdx.x;
   const int lb = block_remap(blockIdx.x, gridDim.x);
   const int inst = lb / sh.blocks;
@@ -214,35 +243,70 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
     for (int p = 0; p < P; p++) {
       const int L = tid + kThreads * p + halo;
-      double ax0, ax1, ax2, bx0, bx1, bx2;
-      pattern<SCALED>(ii[p], N, ax0, ax1, ax2, bx0, bx1, bx2);
-      if (DIM == 3) {
-        double ay0, ay1, ay2, by0, by1, by2;
-        pattern<SCALED>(jj[p], N, ay0, ay1, ay2, by0, by1, by2);
+      if constexpr (!SCALED) {
+        const int ix = ii[p];
+        const bool hl = ix > 0, hr = ix < N, ex = (ix == 0 || ix == N);
+        if (DIM == 3) {
+          const bool ey = (jj[p] == 0 || jj[p] == N);  // rows j-1, j+1 outside are zero in LDS
 #pragma unroll
-        for (int f = 0; f < NF; f++) {
-          const double* lf = lds + f * ldsn;
-          double mr[3], kr[3];
+          for (int f = 0; f < NF; f++) {
+            const double* lf = lds + f * ldsn;
+            double mr[3], kr[3];
 #pragma unroll
-          for (int r = 0; r < 3; r++) {
-            const int base = L + (r - 1) * nn;
-            double va = lf[base - 1], vb = lf[base], vc = lf[base + 1];
-            mr[r] = ax0 * va + ax1 * vb + ax2 * vc;
-            kr[r] = bx0 * va + bx1 * vb + bx2 * vc;
+            for (int r = 0; r < 3; r++) {
+              const int base = L + (r - 1) * nn;
+              const double va = lf[base - 1], vb = lf[base], vc = lf[base + 1];
+              mr[r] = m1_row(hl, hr, ex, va, vb, vc);
+              if (!MASS) kr[r] = k1_row(hl, hr, ex, va, vb, vc);
+            }
+            pm[f][p] = m1_row(true, true, ey, mr[0], mr[1], mr[2]);
+            if (!MASS)
+              pk[f][p] = m1_row(true, true, ey, kr[0], kr[1], kr[2]) +
+                         k1_row(true, true, ey, mr[0], mr[1], mr[2]);
+            cen[f][p] = lf[L];
           }
-          pm[f][p] = ay0 * mr[0] + ay1 * mr[1] + ay2 * mr[2];
-          pk[f][p] = ay0 * kr[0] + ay1 * kr[1] + ay2 * kr[2] + by0 * mr[0] + by1 * mr[1] +
-                     by2 * mr[2];
-          cen[f][p] = lf[L];
+        } else {
+#pragma unroll
+          for (int f = 0; f < NF; f++) {
+            const double* lf = lds + f * ldsn;
+            const double va = lf[L - 1], vb = lf[L], vc = lf[L + 1];
+            pm[f][p] = m1_row(hl, hr, ex, va, vb, vc);
+            if (!MASS) pk[f][p] = k1_row(hl, hr, ex, va, vb, vc);
+            cen[f][p] = vb;
+          }
         }
       } else {
+        double ax0, ax1, ax2, bx0, bx1, bx2;
+        pattern<SCALED>(ii[p], N, ax0, ax1, ax2, bx0, bx1, bx2);
+        if (DIM == 3) {
+          double ay0, ay1, ay2, by0, by1, by2;
+          pattern<SCALED>(jj[p], N, ay0, ay1, ay2, by0, by1, by2);
 #pragma unroll
-        for (int f = 0; f < NF; f++) {
-          const double* lf = lds + f * ldsn;
-          double va = lf[L - 1], vb = lf[L], vc = lf[L + 1];
-          pm[f][p] = ax0 * va + ax1 * vb + ax2 * vc;
-          pk[f][p] = bx0 * va + bx1 * vb + bx2 * vc;
-          cen[f][p] = vb;
+          for (int f = 0; f < NF; f++) {
+            const double* lf = lds + f * ldsn;
+            double mr[3], kr[3];
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+              const int base = L + (r - 1) * nn;
+              double va = lf[base - 1], vb = lf[base], vc = lf[base + 1];
+              mr[r] = ax0 * va + ax1 * vb + ax2 * vc;
+              kr[r] = bx0 * va + bx1 * vb + bx2 * vc;
+            }
+            pm[f][p] = ay0 * mr[0] + ay1 * mr[1] + ay2 * mr[2];
+            pk[f][p] = MASS ? 0.0
+                            : ay0 * kr[0] + ay1 * kr[1] + ay2 * kr[2] + by0 * mr[0] +
+                                  by1 * mr[1] + by2 * mr[2];
+            cen[f][p] = lf[L];
+          }
+        } else {
+#pragma unroll
+          for (int f = 0; f < NF; f++) {
+            const double* lf = lds + f * ldsn;
+            double va = lf[L - 1], vb = lf[L], vc = lf[L + 1];
+            pm[f][p] = ax0 * va + ax1 * vb + ax2 * vc;
+            pk[f][p] = MASS ? 0.0 : bx0 * va + bx1 * vb + bx2 * vc;
+            cen[f][p] = vb;
+          }
         }
       }
     }
@@ -300,8 +364,9 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
         for (int f = 0; f < NF; f++) {
           ms[f] = cmass * (az0 * pma[f][p] + az1 * pmb[f][p] + az2 * pmn[f][p]);
-          ks[f] = cstiff * (az0 * pka[f][p] + az1 * pkb[f][p] + az2 * pkn[f][p] +
-                            bz0 * pma[f][p] + bz1 * pmb[f][p] + bz2 * pmn[f][p]);
+          ks[f] = MASS ? 0.0
+                       : cstiff * (az0 * pka[f][p] + az1 * pkb[f][p] + az2 * pkn[f][p] +
+                                   bz0 * pma[f][p] + bz1 * pmb[f][p] + bz2 * pmn[f][p]);
           cc[f] = cb[f][p];
         }
         int nb = (ii[p] == 0 || ii[p] == N) + nbz;
@@ -506,11 +571,34 @@ struct EpiCouple {
   }
 };
 
+// Residual of a Richardson iteration on the Schur complement (Sec. 4):
+// stencil fields s0 = a = A~^-1 (dt th K z2) and s1 = z2, G = 3 int u^2 a phi;
+//   S z2 = M z2 + (eps^2 K + M_E(u)) a = M z2 + G - M a + eps^2 K a,
+//   res  = y - S z2.
+template <class T>
+struct EpiSchurRes {
+  using In = In2<double, T>;
+  struct K {
+    double e2;
+  };
+  Vec<const double> g;
+  Vec<const T> y;
+  Vec<T> res;
+  __device__ K prep(const InstCoef& C) const { return K{C.e2}; }
+  __device__ In load(int inst, int64_t i) const { return In{g.at(inst)[i], y.at(inst)[i]}; }
+  __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
+                        const double*, const In& in, const K& k) const {
+    const double sz = ms[1] + (in.a - ms[0] + k.e2 * ks[0]);
+    res.at(inst)[i] = (T)(to_d(in.b) - sz);
+  }
+};
+
 // First Chebyshev iteration from x0 = 0; the stencil input is b and is
 // applied with SCALED patterns, so (cm M + ck K) W^-1 b is available and
 // A d0 = dinv * it * (cm M + ck K) W^-1 b.
-template <class T, bool LAST>
+template <class T, bool LAST, bool MASSOP = false>
 struct EpiChebFirst {
+  static constexpr bool kMass = MASSOP;
   using In = In0;
   using K = OpK;
   int lev, osc;
@@ -538,8 +626,9 @@ struct EpiChebFirst {
 // Iteration k: stencil input d_k.  x_{k+1} = x_k + d_k, r_{k+1} = r_k - A d_k,
 // d_{k+1} = c1 d_k + c2 D^-1 r_{k+1}.  LAST also adds the final step:
 // x_{k+2} = x_{k+1} + d_{k+1}, and writes only x.
-template <class T, bool LAST>
+template <class T, bool LAST, bool MASSOP = false>
 struct EpiChebStep {
+  static constexpr bool kMass = MASSOP;
   using In = In2<T, T>;
   using K = OpK;
   int lev, k, osc;
@@ -614,6 +703,234 @@ struct EpiResid {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Two consecutive middle Chebyshev iterations k, k+1 on M (Saad, Alg. 12.1)
+// in one streaming pass (temporal blocking along the streaming axis).
+// Stage 1 computes r_{k+1} and d_{k+1} on the chunk plus a one-row halo for
+// plane pz-1 as plane pz of d_k arrives; stage 2 applies M to d_{k+1} and
+// finishes iteration k+1 for plane pz-2.  Every value the unfused kernels
+// would store is rounded to T here at the same point, so the result is
+// bitwise that of two launch_cheb_step calls.  LAST2: iteration k+1 is the
+// final one (writes only x, scaled by osc).  r_k is read on the halo rows,
+// which other blocks own, so r_{k+2} goes to a second buffer (rout != rin).
+// LDS: d_k plane with a two-row halo (E2), d_{k+1} plane with a one-row halo
+// (E1), and two buffers each of r_{k+1} and d_k on the chunk.
+// ---------------------------------------------------------------------------
+template <int DIM, int P, int P1, int FA, class T, bool LAST2>
+__global__ void __launch_bounds__(kThreads)
+    k_cheb2(Grid g, StencilShape sh, Batch B, int kk, int osc, Vec<T> xv, Vec<const T> rinv,
+            Vec<T> routv, Vec<const T> dinv_, Vec<T> doutv) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x;
+  const int lb = block_remap(blockIdx.x, gridDim.x);
+  const int inst = lb / sh.blocks;
+  if (B.act && !B.act[inst]) return;
+  const int b = lb - inst * sh.blocks;
+  const int chunk = b % sh.nchunks;
+  const int zch = b / sh.nchunks;
+  const InstCoef& IC = B.coef[inst];
+  const OpK ka = op_k(IC, -1, kk, CF_ONE), kb = op_k(IC, -1, kk + 1, osc);
+  const int nn = g.nn, N = g.N;
+  const int64_t plane = (DIM == 3) ? g.plane : (int64_t)nn;
+  const int H = (DIM == 3) ? nn + 1 : 1;  // one row (3D) or one node (2D) of halo
+  const int CH = sh.chunk;
+  const int E1 = CH + 2 * H, E2 = CH + 4 * H;
+  double* LA = lds;          // d_k, positions s0-2H .. s0+CH+2H
+  double* LB = LA + E2;      // d_{k+1}, positions s0-H .. s0+CH+H
+  double* LR = LB + E1;      // r_{k+1} on the chunk, two buffers
+  double* LD = LR + 2 * CH;  // d_k on the chunk, two buffers
+  const int64_t s0 = (int64_t)chunk * CH;
+  T* __restrict__ x = xv.at(inst);
+  const T* __restrict__ r = rinv.at(inst);
+  T* __restrict__ rout = LAST2 ? nullptr : routv.at(inst);
+  const T* __restrict__ din = dinv_.at(inst);
+  T* __restrict__ dout = doutv.at(inst);
+  const int ystep = (DIM == 3) ? nn : 0;
+
+  // stage-1 items: ext1 position e = tid + 256 q, in-plane index s0 - H + e
+  int i1[P1], j1[P1];
+  bool v1[P1];
+#pragma unroll
+  for (int q = 0; q < P1; q++) {
+    const int e = tid + kThreads * q;
+    const int64_t gq = s0 - H + e;
+    v1[q] = (e < E1) && gq >= 0 && gq < plane;
+    const int64_t gc = gq < 0 ? 0 : (gq >= plane ? plane - 1 : gq);
+    j1[q] = (DIM == 3) ? (int)(gc / nn) : 0;
+    i1[q] = (int)(gc - (int64_t)j1[q] * nn);
+  }
+  // stage-2 items: chunk position c = tid + 256 p
+  int i2[P], j2[P];
+  bool v2[P];
+#pragma unroll
+  for (int p = 0; p < P; p++) {
+    const int64_t gq = s0 + tid + kThreads * p;
+    v2[p] = gq < plane;
+    const int64_t gc = gq < plane ? gq : plane - 1;
+    j2[p] = (DIM == 3) ? (int)(gc / nn) : 0;
+    i2[p] = (int)(gc - (int64_t)j2[p] * nn);
+  }
+  auto clampq = [&](int64_t gq) { return gq < 0 ? (int64_t)0 : (gq >= plane ? plane - 1 : gq); };
+
+  // prefetch registers (raw words, clamped in-bounds loads)
+  T pa[FA], pr[P1], px[P];
+  auto issue_a = [&](int64_t zoff) {
+#pragma unroll
+    for (int k = 0; k < FA; k++) pa[k] = din[zoff + clampq(s0 - 2 * H + tid + kThreads * k)];
+  };
+  auto issue_rx = [&](int zr, int zx) {
+#pragma unroll
+    for (int q = 0; q < P1; q++)
+      pr[q] = r[(int64_t)zr * plane + clampq(s0 - H + tid + kThreads * q)];
+#pragma unroll
+    for (int p = 0; p < P; p++) px[p] = x[(int64_t)zx * plane + clampq(s0 + tid + kThreads * p)];
+  };
+  // in-plane mass partial (M1 x M1) v at LDS position L of buffer v (the
+  // arithmetic of the one-iteration kernel)
+  auto mpart = [&](const double* v, int L, int i, int j) {
+    const bool hl = i > 0, hr = i < N, ex = (i == 0 || i == N);
+    if (DIM == 3) {
+      const bool ey = (j == 0 || j == N);
+      double m[3];
+#pragma unroll
+      for (int rr = 0; rr < 3; rr++) {
+        const int bse = L + (rr - 1) * ystep;
+        m[rr] = m1_row(hl, hr, ex, v[bse - 1], v[bse], v[bse + 1]);
+      }
+      return m1_row(true, true, ey, m[0], m[1], m[2]);
+    }
+    return m1_row(hl, hr, ex, v[L - 1], v[L], v[L + 1]);
+  };
+
+  const double h = g.h;
+  const double cmass = (DIM == 3) ? h * h * h / 216.0 : h * h / 36.0;
+  const int z0 = zch * sh.zc;
+  const int z1 = min(z0 + sh.zc, nn);
+  const int zlast = min(z1 + 1, N);
+  double pa1[P1], pb1[P1], cb1[P1];  // stage 1: partials of planes pz-2, pz-1; d_k(pz-1)
+  double pa2[P], pb2[P], cb2[P];     // stage 2: partials of d_{k+1} planes pz-3, pz-2; d_{k+1}(pz-2)
+#pragma unroll
+  for (int q = 0; q < P1; q++) pa1[q] = pb1[q] = cb1[q] = 0.0;
+#pragma unroll
+  for (int p = 0; p < P; p++) pa2[p] = pb2[p] = cb2[p] = 0.0;
+  issue_a((int64_t)max(z0 - 2, 0) * plane);
+  issue_rx(max(z0 - 1, 0), max(z0, 0));
+  for (int pz = z0 - 2; pz <= z1 + 1; pz++) {
+    const bool insideA = (pz >= 0 && pz <= N);
+    const int q1 = pz - 1;  // stage-1 output plane
+    const int o = pz - 2;   // stage-2 output plane
+    const int buf = pz & 1;
+    __syncthreads();
+    if (insideA) {
+#pragma unroll
+      for (int k = 0; k < FA; k++) {
+        const int t = tid + kThreads * k;
+        const int64_t gq = s0 - 2 * H + t;
+        if (t < E2) LA[t] = (gq >= 0 && gq < plane) ? to_d(pa[k]) : 0.0;
+      }
+    }
+    __syncthreads();
+    // stage-1 pointwise inputs of plane q1 and stage-2 x of plane o arrived last trip
+    T rq[P1], xq[P];
+#pragma unroll
+    for (int q = 0; q < P1; q++) rq[q] = pr[q];
+#pragma unroll
+    for (int p = 0; p < P; p++) xq[p] = px[p];
+    issue_a((int64_t)min(pz + 1, zlast) * plane);
+    issue_rx(min(max(q1 + 1, 0), N), min(max(o + 1, 0), N));
+    // stage 1: partials of d_k at plane pz over the extended chunk
+    double pn1[P1], cn1[P1];
+#pragma unroll
+    for (int q = 0; q < P1; q++) {
+      const int L = tid + kThreads * q + H;
+      const bool use = insideA && (tid + kThreads * q < E1);
+      pn1[q] = use ? mpart(LA, L, i1[q], j1[q]) : 0.0;
+      cn1[q] = use ? LA[L] : 0.0;
+    }
+    if (q1 >= z0 - 1 && q1 <= z1) {
+      const bool inq = (q1 >= 0 && q1 <= N);
+      double az0 = 0, az1 = 0, az2 = 0, bz0, bz1, bz2;
+      if (inq) pattern<false>(q1, N, az0, az1, az2, bz0, bz1, bz2);
+      const int nbz = (q1 == 0 || q1 == N);
+#pragma unroll
+      for (int q = 0; q < P1; q++) {
+        const int e = tid + kThreads * q;
+        if (e >= E1) continue;
+        double d1 = 0.0;
+        if (inq && v1[q]) {
+          const double ms = cmass * (az0 * pa1[q] + az1 * pb1[q] + az2 * pn1[q]);
+          const double dk = cb1[q];
+          int nb = (i1[q] == 0 || i1[q] == N) + nbz;
+          if (DIM == 3) nb += (j1[q] == 0 || j1[q] == N);
+          const double dv = dinv_at(ka.dinv, nb);
+          const double ru = to_d(rq[q]) - ka.cm * ms;
+          const double rv1 = to_d((T)ru);
+          d1 = to_d((T)(ka.c1 * dk + ka.c2 * dv * ru));
+          const int c = e - H;
+          if (c >= 0 && c < CH) {
+            LR[buf * CH + c] = rv1;
+            LD[buf * CH + c] = dk;
+          }
+        }
+        LB[e] = d1;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < P1; q++) {
+      pa1[q] = pb1[q];
+      pb1[q] = pn1[q];
+      cb1[q] = cn1[q];
+    }
+    __syncthreads();
+    // stage 2: partials of d_{k+1} at plane q1 over the chunk; finish plane o
+    if (q1 >= z0 - 1 && q1 <= z1) {
+      double pn2[P], cn2[P];
+#pragma unroll
+      for (int p = 0; p < P; p++) {
+        const int L = tid + kThreads * p + H;
+        pn2[p] = mpart(LB, L, i2[p], j2[p]);
+        cn2[p] = LB[L];
+      }
+      if (o >= z0 && o < z1) {
+        double az0, az1, az2, bz0, bz1, bz2;
+        pattern<false>(o, N, az0, az1, az2, bz0, bz1, bz2);
+        const int nbz = (o == 0 || o == N);
+        const int pb = buf ^ 1;
+#pragma unroll
+        for (int p = 0; p < P; p++) {
+          if (!v2[p]) continue;
+          const int c = tid + kThreads * p;
+          const double ms = cmass * (az0 * pa2[p] + az1 * pb2[p] + az2 * pn2[p]);
+          const double d1 = cb2[p];
+          const double rv1 = LR[pb * CH + c];
+          const double dk = LD[pb * CH + c];
+          int nb = (i2[p] == 0 || i2[p] == N) + nbz;
+          if (DIM == 3) nb += (j2[p] == 0 || j2[p] == N);
+          const double dv = dinv_at(kb.dinv, nb);
+          const double xv1 = to_d((T)(to_d(xq[p]) + dk));
+          const double xv2 = xv1 + d1;
+          const double rv2 = rv1 - kb.cm * ms;
+          const double d2 = kb.c1 * d1 + kb.c2 * dv * rv2;
+          const int64_t idx = (int64_t)o * plane + s0 + c;
+          if (LAST2) {
+            x[idx] = (T)(kb.osc * (xv2 + d2));
+          } else {
+            x[idx] = (T)xv2;
+            rout[idx] = (T)rv2;
+            dout[idx] = (T)d2;
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < P; p++) {
+        pa2[p] = pb2[p];
+        pb2[p] = pn2[p];
+        cb2[p] = cn2[p];
+      }
+    }
+  }
+}
+
 template <class T>
 __global__ void __launch_bounds__(256)
     k_add_inplace(Batch B, Vec<T> x, Vec<const T> d, int64_t n, int per) {
@@ -662,6 +979,14 @@ hipError_t launch_couple(const Grid& g, const Batch& B, Vec<const T> z1, Vec<con
   return run_stencil<false>(g, B, z1, e, st);
 }
 
+template <class T>
+hipError_t launch_schur_res(const Grid& g, const Batch& B, Vec<const T> a, Vec<const T> z2,
+                            Vec<const double> G, Vec<const T> y, Vec<T> res, hipStream_t st) {
+  EpiSchurRes<T> e{G, y, res};
+  Src<T, 2> src{{a.p, z2.p}, {a.s, z2.s}};
+  return run_stencil_n<false, T, 2>(g, B, src, e, st);
+}
+
 template <class TB, class T>
 hipError_t launch_cheb_one(const Grid& g, const Batch& B, int lev, int osc, Vec<const TB> b,
                            Vec<T> x, hipStream_t st) {
@@ -672,6 +997,14 @@ hipError_t launch_cheb_one(const Grid& g, const Batch& B, int lev, int osc, Vec<
 template <class TB, class T>
 hipError_t launch_cheb_first(const Grid& g, const Batch& B, int lev, int osc, bool last,
                              Vec<const TB> b, Vec<T> x, Vec<T> r, Vec<T> d, hipStream_t st) {
+  if (lev < 0) {  // M only: no stiffness partials
+    if (last) {
+      EpiChebFirst<T, true, true> e{lev, osc, x, r, d};
+      return run_stencil<true>(g, B, b, e, st);
+    }
+    EpiChebFirst<T, false, true> e{lev, osc, x, r, d};
+    return run_stencil<true>(g, B, b, e, st);
+  }
   if (last) {
     EpiChebFirst<T, true> e{lev, osc, x, r, d};
     return run_stencil<true>(g, B, b, e, st);
@@ -684,12 +1017,101 @@ template <class T>
 hipError_t launch_cheb_step(const Grid& g, const Batch& B, int lev, int k, int osc, bool last,
                             Vec<T> x, Vec<T> r, Vec<const T> din, Vec<T> dout, hipStream_t st) {
   if (k < 0 || k >= kMaxCheb) return hipErrorInvalidValue;
+  if (lev < 0) {  // M only: no stiffness partials
+    if (last) {
+      EpiChebStep<T, true, true> e{lev, k, osc, x, r, dout};
+      return run_stencil<false>(g, B, din, e, st);
+    }
+    EpiChebStep<T, false, true> e{lev, k, osc, x, r, dout};
+    return run_stencil<false>(g, B, din, e, st);
+  }
   if (last) {
     EpiChebStep<T, true> e{lev, k, osc, x, r, dout};
     return run_stencil<false>(g, B, din, e, st);
   }
   EpiChebStep<T, false> e{lev, k, osc, x, r, dout};
   return run_stencil<false>(g, B, din, e, st);
+}
+
+namespace {
+int g_fuse_cheb = 1;
+
+template <int DIM, int P, int EX1, int EXA, class T>
+hipError_t launch_cheb2_p(const Grid& g, const Batch& B, const StencilShape& sh, int k, int osc,
+                          bool last2, Vec<T> x, Vec<const T> r, Vec<T> rout, Vec<const T> din,
+                          Vec<T> dout, hipStream_t st) {
+  const int H = (DIM == 3) ? g.nn + 1 : 1;
+  const size_t lds = (size_t)(sh.chunk + 4 * H + sh.chunk + 2 * H + 4 * sh.chunk) * sizeof(double);
+  if (lds > 65536) return hipErrorInvalidValue;
+  const int64_t nblk = (int64_t)sh.blocks * B.count;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  dim3 grid((unsigned)nblk), block(kThreads);
+  if (last2)
+    hipLaunchKernelGGL((k_cheb2<DIM, P, P + EX1, P + EXA, T, true>), grid, block, lds, st, g, sh,
+                       B, k, osc, x, r, rout, din, dout);
+  else
+    hipLaunchKernelGGL((k_cheb2<DIM, P, P + EX1, P + EXA, T, false>), grid, block, lds, st, g,
+                       sh, B, k, osc, x, r, rout, din, dout);
+  return hipGetLastError();
+}
+
+template <int DIM, int EX1, int EXA, class T>
+hipError_t launch_cheb2_ex(const Grid& g, const Batch& B, const StencilShape& sh, int k, int osc,
+                           bool last2, Vec<T> x, Vec<const T> r, Vec<T> rout, Vec<const T> din,
+                           Vec<T> dout, hipStream_t st) {
+  if (sh.items == 1)
+    return launch_cheb2_p<DIM, 1, EX1, EXA, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout,
+                                               st);
+  return launch_cheb2_p<DIM, 2, EX1, EXA, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
+}
+}  // namespace
+
+void cheb_fusion_set(int enable) { g_fuse_cheb = enable ? 1 : 0; }
+
+bool cheb_fusion_on(const Grid& g, int word) {
+  if (!g_fuse_cheb) return false;
+  {
+    // the autotuner records items < 0 where fused pairs lost to single steps
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(g.dim, g.nn, kFusedKey, word));
+    if (it != g_tune.end() && it->second.first < 0) return false;
+  }
+  StencilShape sh = stencil_shape(g, kFusedKey, word);
+  const int items = sh.items > 2 ? 2 : sh.items;
+  const int H = (g.dim == 3) ? g.nn + 1 : 1;
+  const int ex1 = (2 * H + kThreads - 1) / kThreads, exa = (4 * H + kThreads - 1) / kThreads;
+  const bool combo = (g.dim == 2) ? (ex1 == 1 && exa == 1)
+                                  : ((ex1 == 1 && exa <= 2) || (ex1 == 2 && exa == 3) ||
+                                     (ex1 == 3 && exa == 5) || (ex1 == 5 && exa == 9));
+  const int ch = kThreads * items;
+  return combo && (size_t)(6 * ch + 6 * H) * sizeof(double) <= 65536;
+}
+
+template <class T>
+hipError_t launch_cheb_step2(const Grid& g, const Batch& B, int k, int osc, bool last2, Vec<T> x,
+                             Vec<const T> r, Vec<T> rout, Vec<const T> din, Vec<T> dout,
+                             hipStream_t st) {
+  if (k < 0 || k + 1 >= kMaxCheb || B.count < 1) return hipErrorInvalidValue;
+  if (!last2 && (rout.p == r.p || rout.null())) return hipErrorInvalidValue;
+  StencilShape sh = stencil_shape(g, kFusedKey, (int)sizeof(T));
+  if (sh.items > 2) sh = shape_with(g, 2, sh.zc);
+  const int H = (g.dim == 3) ? g.nn + 1 : 1;
+  const int ex1 = (2 * H + kThreads - 1) / kThreads, exa = (4 * H + kThreads - 1) / kThreads;
+  if (g.dim == 2) {
+    if (ex1 != 1 || exa != 1) return hipErrorInvalidValue;
+    return launch_cheb2_ex<2, 1, 1, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
+  }
+  if (ex1 == 1 && exa == 1)
+    return launch_cheb2_ex<3, 1, 1, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
+  if (ex1 == 1 && exa == 2)
+    return launch_cheb2_ex<3, 1, 2, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
+  if (ex1 == 2 && exa == 3)
+    return launch_cheb2_ex<3, 2, 3, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
+  if (ex1 == 3 && exa == 5)
+    return launch_cheb2_ex<3, 3, 5, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
+  if (ex1 == 5 && exa == 9)
+    return launch_cheb2_ex<3, 5, 9, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
+  return hipErrorInvalidValue;
 }
 
 template <class T>
@@ -740,6 +1162,12 @@ template hipError_t launch_stencil_lin2<float>(const Grid&, const Batch&, Vec<co
                                                Vec<const double>, const double (&)[2][4],
                                                const int (&)[2][4], Vec<double>, Vec<double>,
                                                hipStream_t);
+template hipError_t launch_schur_res<double>(const Grid&, const Batch&, Vec<const double>,
+                                             Vec<const double>, Vec<const double>,
+                                             Vec<const double>, Vec<double>, hipStream_t);
+template hipError_t launch_schur_res<float>(const Grid&, const Batch&, Vec<const float>,
+                                            Vec<const float>, Vec<const double>, Vec<const float>,
+                                            Vec<float>, hipStream_t);
 template hipError_t launch_couple<double>(const Grid&, const Batch&, Vec<const double>,
                                           Vec<const double>, Vec<const double>, Vec<double>,
                                           Vec<double>, hipStream_t);
@@ -759,6 +1187,9 @@ OKD_CHEB_TB(double, float)
 #define OKD_CHEB_T(T)                                                                         \
   template hipError_t launch_cheb_step<T>(const Grid&, const Batch&, int, int, int, bool,      \
                                           Vec<T>, Vec<T>, Vec<const T>, Vec<T>, hipStream_t);  \
+  template hipError_t launch_cheb_step2<T>(const Grid&, const Batch&, int, int, bool, Vec<T>,  \
+                                           Vec<const T>, Vec<T>, Vec<const T>, Vec<T>,         \
+                                           hipStream_t);                                       \
   template hipError_t launch_cheb_start<T>(const Grid&, const Batch&, int, Vec<const T>,      \
                                            Vec<const T>, Vec<T>, Vec<T>, hipStream_t);         \
   template hipError_t launch_add_inplace<T>(const Batch&, Vec<T>, Vec<const T>, int64_t,       \

@@ -299,6 +299,16 @@ int ok_timestep(ok_ctx* c, double* u, double* w, int32_t nsteps, ok_stats* stats
   return e;
 }
 
+int ok_set_option(int32_t option, int32_t value) {
+  switch (option) {
+    case OK_OPT_FUSE_CHEB:
+      cheb_fusion_set(value);
+      return OK_SUCCESS;
+    default:
+      return OK_E_INVALID;
+  }
+}
+
 int ok_use_graphs(ok_ctx* c, int32_t enable) {
   if (!c) return OK_E_INVALID;
   if (!enable && !c->cls.ex) return OK_SUCCESS;
@@ -313,19 +323,21 @@ int ok_autotune(ok_ctx* c, void* stream, int32_t* entries) {
   return e;
 }
 
-int ok_profile_enable(ok_ctx* c, int32_t kernel_class) {
-  if (!c) return OK_E_INVALID;
-  c->prof.cls = kernel_class;
+int ok_profile_enable(ok_ctx* c, int32_t class_mask) {
+  if (!c || class_mask < 0) return OK_E_INVALID;
+  c->prof.mask = class_mask;
   c->prof.used = 0;
   return OK_SUCCESS;
 }
 
-int ok_profile_read(ok_ctx* c, int64_t* launches, double* total_ms, double* bytes) {
+int ok_profile_read(ok_ctx* c, int32_t kernel_class, int64_t* launches, double* total_ms,
+                    double* bytes) {
   if (!c) return OK_E_INVALID;
   double ms = 0.0, by = 0.0;
   int64_t cnt = 0;
   for (size_t i = 0; i < c->prof.used; i++) {
     ProfPair& q = c->prof.ev[i];
+    if (q.cls != kernel_class) continue;
     cnt += q.count;
     (void)hipEventSynchronize(q.b);
     float t = 0.f;
@@ -336,7 +348,6 @@ int ok_profile_read(ok_ctx* c, int64_t* launches, double* total_ms, double* byte
   if (launches) *launches = cnt;
   if (total_ms) *total_ms = ms;
   if (bytes) *bytes = by;
-  c->prof.used = 0;
   return OK_SUCCESS;
 }
 

@@ -104,8 +104,11 @@ struct StencilShape {
   int blocks;   // nchunks*nzc (per instance)
 };
 StencilShape stencil_shape(const Grid& g, int nf, int word);
+// Shape-table key of the fused two-iteration Chebyshev kernel (in place of nf).
+constexpr int kFusedKey = 17;
 // Launch-shape table of the stencil kernels, keyed by (dim, nodes per
-// direction, stenciled fields, bytes per stenciled word); items <= 0 removes
+// direction, stenciled fields, bytes per stenciled word); items < 0 marks the
+// fused Chebyshev kernel as slower than single steps on that grid; items == 0 removes
 // the entry (back to the heuristic).  Results do not depend on the shape.
 void stencil_tune_set(int dim, int nn, int nf, int word, int items, int zc);
 
@@ -132,6 +135,24 @@ hipError_t launch_stencil_lin2(const Grid& g, const Batch& B, Vec<const TS> s0, 
                                Vec<const double> add0, Vec<const double> add1,
                                const double (&c)[2][4], const int (&f)[2][4], Vec<double> out0,
                                Vec<double> out1, hipStream_t st);
+// Two consecutive middle iterations k, k+1 of the Chebyshev iteration on M
+// (finest grid) in one pass, bitwise equal to two launch_cheb_step calls;
+// last2: iteration k+1 is the final one.  r_{k+2} is written to rout, which
+// must differ from r (r_k is read on rows other blocks own).  Returns
+// hipErrorInvalidValue for grids it does not support.
+template <class T>
+hipError_t launch_cheb_step2(const Grid& g, const Batch& B, int k, int osc, bool last2, Vec<T> x,
+                             Vec<const T> r, Vec<T> rout, Vec<const T> din, Vec<T> dout,
+                             hipStream_t st);
+// Process-wide switch of that fusion (on by default); results do not change.
+// cheb_fusion_on: the switch is on and the fused kernel supports grid g.
+void cheb_fusion_set(int enable);
+bool cheb_fusion_on(const Grid& g, int word);
+// Richardson residual on the Schur complement: with a = A~^-1 (dt th K z2)
+// and G = 3 int u^2 a phi, res = y - (M z2 + G - M a + eps^2 K a).
+template <class T>
+hipError_t launch_schur_res(const Grid& g, const Batch& B, Vec<const T> a, Vec<const T> z2,
+                            Vec<const double> G, Vec<const T> y, Vec<T> res, hipStream_t st);
 // Preconditioner coupling: q = G - M z1 + eps^2 K z1 (G = 3 int u^2 z1 phi);
 // y = r2 + q, nq = -q.
 template <class T>

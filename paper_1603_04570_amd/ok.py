@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(PKG, "libok.so")
 
 OK_FP64, OK_MIXED = 0, 1
-OK_K_NONE, OK_K_CHEB_MASS, OK_K_MG_SMOOTH, OK_K_ELEMENT, OK_K_STENCIL_ANY, OK_K_KRYLOV = range(6)
+OK_K_NONE, OK_K_CHEB_MASS, OK_K_MG_SMOOTH, OK_K_ELEMENT, OK_K_KRYLOV = 0, 1, 2, 3, 5
 HIST = 256
 
 STATUS = {0: "OK_SUCCESS", -1: "OK_E_INVALID", -2: "OK_E_WORKSPACE", -3: "OK_E_HIP",
@@ -116,7 +116,7 @@ def load():
     lib.ok_timestep.argtypes = [vp, vp, vp, i32, P(Stats), vp]
     lib.ok_autotune.argtypes = [vp, vp, P(i32)]
     lib.ok_profile_enable.argtypes = [vp, i32]
-    lib.ok_profile_read.argtypes = [vp, P(C.c_int64), P(d), P(d)]
+    lib.ok_profile_read.argtypes = [vp, i32, P(C.c_int64), P(d), P(d)]
     lib.ok_destroy.argtypes = [vp]
     lib.ok_batch_workspace_bytes.argtypes = [P(Params), i32, P(C.c_size_t)]
     lib.ok_batch_create.argtypes = [P(Params), i32, vp, C.c_size_t, vp, P(vp)]
@@ -129,6 +129,7 @@ def load():
     lib.ok_batch_last_error.argtypes = [vp]
     lib.ok_batch_last_error.restype = C.c_char_p
     lib.ok_use_graphs.argtypes = [vp, i32]
+    lib.ok_set_option.argtypes = [i32, i32]
     lib.ok_batch_use_graphs.argtypes = [vp, i32]
     lib.ok_server_default_config.argtypes = [P(ServerConfig)]
     lib.ok_server_state_bytes.argtypes = [P(Params), i32, P(C.c_size_t)]
@@ -289,13 +290,16 @@ class Problem:
     def use_graphs(self, enable=True):
         self._check(self.lib.ok_use_graphs(self.ctx, int(bool(enable))), "ok_use_graphs")
 
-    def profile_enable(self, kernel_class):
-        self._check(self.lib.ok_profile_enable(self.ctx, kernel_class), "ok_profile_enable")
+    def profile_enable(self, *kernel_classes):
+        mask = 0
+        for k in kernel_classes:
+            mask |= 1 << k
+        self._check(self.lib.ok_profile_enable(self.ctx, mask), "ok_profile_enable")
 
-    def profile_read(self):
+    def profile_read(self, kernel_class):
         n, ms, by = C.c_int64(), C.c_double(), C.c_double()
-        self._check(self.lib.ok_profile_read(self.ctx, C.byref(n), C.byref(ms), C.byref(by)),
-                    "ok_profile_read")
+        self._check(self.lib.ok_profile_read(self.ctx, kernel_class, C.byref(n), C.byref(ms),
+                                             C.byref(by)), "ok_profile_read")
         return n.value, ms.value, by.value
 
 
@@ -384,6 +388,16 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+OK_OPT_FUSE_CHEB = 1
+
+
+def set_option(option: int, value: int):
+    """ok_set_option: process-wide tuning switches (results unchanged)."""
+    st = load().ok_set_option(option, value)
+    if st:
+        raise OkError(st, "ok_set_option")
 
 
 def server_config(**kw) -> ServerConfig:

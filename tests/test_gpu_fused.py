@@ -1,0 +1,66 @@
+"""The fused two-iteration Chebyshev kernel (OK_OPT_FUSE_CHEB) against the
+one-iteration kernels: bitwise equal results (it rounds every intermediate
+to the storage type where the unfused kernels store it), on grids of every
+halo class the fused kernel supports, in FP64 and mixed precision."""
+import numpy as np
+import pytest
+
+from paper_1603_04570_amd.inputs import noise_state, uniform01
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def run_both(fn):
+    from paper_1603_04570_amd import ok
+    out = []
+    for fuse in (0, 1):
+        ok.set_option(ok.OK_OPT_FUSE_CHEB, fuse)
+        try:
+            out.append(fn())
+        finally:
+            ok.set_option(ok.OK_OPT_FUSE_CHEB, 1)
+    return out
+
+
+# (dim, n): 2D rows; 3D halo classes of nn = 17, 65, 129, 257
+CASES = [(2, 64), (2, 1024), (3, 16), (3, 64), (3, 128), (3, 256)]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("dim,n", CASES)
+def test_fused_cheb_mass_bitwise(dim, n, precision):
+    from paper_1603_04570_amd import ok
+    p = ok.default_params(dim=dim, n=n, precision=precision)
+    P = ok.Problem(p)
+    nodes = (n + 1) ** dim
+    r = torch.from_numpy(uniform01(11 + n, nodes) - 0.5).cuda()
+    print("fused cheb", dim, n, precision, flush=True)
+
+    def once():
+        x = torch.empty(nodes, dtype=torch.float64, device="cuda")
+        P.cheb_mass(r, x)
+        torch.cuda.synchronize()
+        return x.cpu().numpy()
+
+    a, b = run_both(once)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dim,n,precision", [(2, 64, 0), (3, 32, 1), (3, 64, 0)])
+def test_fused_timestep_bitwise(dim, n, precision):
+    from paper_1603_04570_amd import ok
+    p = ok.default_params(dim=dim, n=n, eps=0.02, sigma=100.0, m=0.1,
+                          dt=2e-4 if dim == 3 else 1e-4, precision=precision)
+    u0, w0 = noise_state(dim, n, 0.1, 13)
+
+    def once():
+        P = ok.Problem(p)
+        u = torch.from_numpy(u0).cuda()
+        w = torch.from_numpy(w0).cuda()
+        st = P.timestep(u, w, 1)
+        return u.cpu().numpy(), w.cpu().numpy(), st.its()
+
+    (ua, wa, ia), (ub, wb, ib) = run_both(once)
+    assert ia == ib
+    assert np.array_equal(ua, ub) and np.array_equal(wa, wb)

@@ -177,3 +177,34 @@ def test_multigrid_smoothing_counts(dim, n, pre, post, cycles):
     o, P = make(dim, n, CFG2, mg_pre=pre, mg_post=post)
     b = uniform01(52, o.nodes) - 0.5
     assert relmax(host(P.mg_apply(dev(b), cycles=cycles)), o.mg(b, cycles)) < 1e-12
+
+
+# The paper's preset (Sec. 4): S^-1 by two Richardson iterations of S~^-1 on
+# S = D - C A~^-1 B (matrix-free), five V-cycles per S^^-1.
+PAPER_PRESET = dict(schur_richardson=2, mg_cycles=5)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 16), (2, 64), (3, 16)])
+@pytest.mark.parametrize("preset", [dict(schur_richardson=2), dict(schur_richardson=3),
+                                    PAPER_PRESET])
+def test_preconditioner_richardson(dim, n, preset):
+    say("precond richardson", dim, n, preset)
+    o, P = make(dim, n, CFG2, **preset)
+    u, _ = noise_state(dim, n, 0.1, 2)
+    r = uniform01(62, 2 * o.nodes) - 0.5
+    z = host(P.precond_apply(dev(u), dev(r)))
+    assert relmax(z, o.precond_apply(u, r)) < 1e-12
+
+
+@pytest.mark.parametrize("dim,n", [(2, 64), (3, 16)])
+def test_timestep_paper_preset(dim, n):
+    say("timestep paper preset", dim, n)
+    o, P = make(dim, n, CFG1, **PAPER_PRESET)
+    u0, w0 = noise_state(dim, n, CFG1["m"], 1)
+    u_o, w_o, info, st_o = o.timestep(u0, w0, 1)
+    u, w = dev(u0), dev(w0)
+    stats = P.timestep(u, w, 1)
+    assert st_o == 0 and stats.status == 0
+    assert stats.its() == info.its()
+    assert relnorm(host(u), u_o) < 1e-10
+    assert relnorm(host(w), w_o) < 1e-10
