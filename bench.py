@@ -14,6 +14,12 @@ Other workloads:
                     {128,256,512,1024}, eps~U[0.01,0.05], sigma~logU[10,1000],
                     m~U[-0.4,0.4], dt=eps^2/2 (seeds 4000+i), mixed precision,
                     one batched timestep against the sum of the 64 solo runs.
+  --config robustness  the paper's robustness experiments (Sec. 5) on Q1:
+                    Table 2 analogue (2D, eps in {0.02,0.01,0.005}, N = 2/eps,
+                    dt = eps^2) and Table 1 analogue (3D N in {16..128}, eps =
+                    0.02, dt = 4e-4), m = 0.4, sigma = 100, theta = 1/2, cosine
+                    initial condition; average FGMRES iterations per Newton step
+                    for the default solver and the paper's preset.
   --config serve    256 resident simulations (70% 2D N in {256..2048}, 30% 3D
                     N in {64,128}; seeds 5000+s), one Poisson stream of
                     timestep requests (seed 5999) at --rates req/s for
@@ -207,6 +213,52 @@ def bench_sweep(args, torch, ok):
     return out
 
 
+def bench_robustness(args, torch, ok):
+    """Average FGMRES iterations per Newton step (the paper's Tables 1-2
+    measure) and timestep throughput, per case and solver preset."""
+    from paper_1603_04570_amd.inputs import cosine_state, dofs, table1_cases, table2_cases
+    presets = {"default": {}, "paper": dict(schur_richardson=2, mg_cycles=5)}
+    steps = args.steps
+    rows, tot_dofs, tot_s = [], 0.0, 0.0
+    for table, cases in (("table2_eps", table2_cases()),
+                         ("table1_refinement", table1_cases(3, (16, 32, 64, 128)))):
+        for case in cases:
+            for name, pre in presets.items():
+                p = ok.default_params(dim=case["dim"], n=case["n"], eps=case["eps"],
+                                      sigma=case["sigma"], m=case["m"], dt=case["dt"],
+                                      theta=case["theta"], **pre)
+                P = ok.Problem(p)
+                u0, w0 = cosine_state(case["dim"], case["n"], case["m"])
+                u, w = torch.from_numpy(u0).cuda(), torch.from_numpy(w0).cuda()
+                P.autotune()
+                P.timestep(u.clone(), w.clone(), 1)  # warm
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = P.timestep(u, w, steps)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                nd = dofs(case["dim"], case["n"])
+                tot_dofs += nd * steps
+                tot_s += el
+                its = st.its()
+                rows.append({"table": table, "dim": case["dim"], "n": case["n"],
+                             "eps": case["eps"], "dt": case["dt"], "solver": name,
+                             "newton_its": st.newton_its, "fgmres_its": its,
+                             "fgmres_per_newton": round(float(np.mean(its)), 2),
+                             "dofs_per_s": nd * steps / el})
+                print(f"{table} N={case['n']} eps={case['eps']} {name}: "
+                      f"{rows[-1]['fgmres_per_newton']} its/Newton", file=sys.stderr, flush=True)
+    return {"metric": "timestep DOFs/s", "value": tot_dofs / tot_s, "unit": "DOFs/s",
+            "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": tot_s * 1e3 / len(rows) / steps,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "robustness: paper's Sec. 5 workload on Q1 (m=0.4, sigma=100, "
+                                   "theta=1/2, cosine IC, w0=0); Table 2 analogue 2D eps sweep "
+                                   "N=2/eps dt=eps^2; Table 1 analogue 3D N=16..128 eps=0.02 "
+                                   "dt=4e-4", "parallelism": "none (1 GPU)"},
+            "paper_reference_its": 8.0, "cases": rows, "roofline": None}
+
+
 def bench_serve(args, torch, ok):
     """Serving loop: resident simulations, Poisson timestep requests,
     admission by HBM budget, continuous batching (native worker threads)."""
@@ -320,6 +372,9 @@ def main():
         ok.set_option(ok.OK_OPT_FUSE_CHEB, 0)
     if args.config == "sweep64":
         print(json.dumps(bench_sweep(args, torch, ok)), flush=True)
+        return
+    if args.config == "robustness":
+        print(json.dumps(bench_robustness(args, torch, ok)), flush=True)
         return
     if args.config == "serve":
         print(json.dumps(bench_serve(args, torch, ok)), flush=True)

@@ -71,6 +71,33 @@ def noise_state(dim: int, n: int, m: float, seed: int, amp: float = 0.05,
     return u0, w0
 
 
+def cosine_state(dim: int, n: int, m: float, amp: float = 1.0 / 50.0):
+    """(u0, w0) of the paper's experiment (Sec. 5): u0 = m + amp * prod_d
+    cos(2 pi x_d) at the nodes, w0 = 0.  The perturbation is a DCT-I mode of
+    index 2 per direction, orthogonal to the constant in the trapezoid (and
+    the Q1 mass) inner product, so its discrete integral is zero."""
+    x = np.arange(n + 1, dtype=np.float64) / n
+    c = np.cos(2.0 * np.pi * x)
+    p = c
+    for _ in range(dim - 1):
+        p = np.multiply.outer(c, p)
+    u0 = m + amp * p.reshape(-1)
+    return u0, np.zeros_like(u0)
+
+
+# Robustness experiments (Sec. 5, Tables 1-2): parameters of the paper's run
+# with theta = 1/2 and dt = eps^2.
+def table2_cases():
+    """eps sweep with h = eps/2 (N = 2/eps) and dt = eps^2, 2D."""
+    return [dict(dim=2, n=int(round(2.0 / e)), eps=e, sigma=100.0, m=0.4, theta=0.5, dt=e * e)
+            for e in (0.02, 0.01, 0.005)]
+
+
+def table1_cases(dim: int = 3, sizes=(16, 32, 64, 128)):
+    """mesh refinement at fixed parameters eps = 0.02, sigma = 100, m = 0.4."""
+    return [dict(dim=dim, n=n, eps=0.02, sigma=100.0, m=0.4, theta=0.5, dt=4e-4) for n in sizes]
+
+
 # --------------------------------------------------------------------------- #
 # Workload recipes (the benchmark's configurations and the sweep/serving mixes) #
 # --------------------------------------------------------------------------- #
