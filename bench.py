@@ -20,6 +20,12 @@ Other workloads:
                     0.02, dt = 4e-4), m = 0.4, sigma = 100, theta = 1/2, cosine
                     initial condition; average FGMRES iterations per Newton step
                     for the default solver and the paper's preset.
+  --config paper    the paper's experiment (Sec. 5) on Q1: 3D N = --paper-n
+                    (25*2^k; 100 by default, 400 = 129M DOFs), m = 0.4,
+                    eps = 0.02, sigma = 100, theta = 1/2, dt = eps^2, cosine
+                    initial condition, w0 from (okb), paper solver preset
+                    (2 Richardson iterations of S~^-1, 5 V-cycles); --steps of
+                    the T = 300 dt run.
   --config serve    256 resident simulations (70% 2D N in {256..2048}, 30% 3D
                     N in {64,128}; seeds 5000+s), one Poisson stream of
                     timestep requests (seed 5999) at --rates req/s for
@@ -213,6 +219,46 @@ def bench_sweep(args, torch, ok):
     return out
 
 
+def bench_paper(args, torch, ok):
+    """The paper's experiment on Q1, timed over --steps timesteps after one
+    warm-up step (the state is reset to u0, w0 afterwards)."""
+    from paper_1603_04570_amd.inputs import cosine_state, dofs
+    n = args.paper_n
+    p = ok.default_params(dim=3, n=n, eps=0.02, sigma=100.0, m=0.4, dt=4e-4, theta=0.5,
+                          schur_richardson=2, mg_cycles=5,
+                          precision=ok.OK_MIXED if args.precision == "mixed" else ok.OK_FP64)
+    P = ok.Problem(p)
+    u0, _ = cosine_state(3, n, 0.4)
+    u0d = torch.from_numpy(u0).cuda()
+    w0d = P.initial_w(u0d)
+    tuned = 0 if args.no_autotune else P.autotune()
+    u, w = u0d.clone(), w0d.clone()
+    for _ in range(args.warmup):
+        P.timestep(u, w, 1)
+    u.copy_(u0d)
+    w.copy_(w0d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = P.timestep(u, w, args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    nd = dofs(3, n)
+    its = st.its()
+    out = _base_line(nd * args.steps / el, args.steps, args.warmup, el * 1e3 / args.steps,
+                     "f64" if args.precision != "mixed" else "f64+f32",
+                     {"workload": f"paper: Sec. 5 experiment on Q1, 3D N={n} ({nd} DOFs), m=0.4, "
+                                  "eps=0.02, sigma=100, theta=1/2, dt=eps^2, cosine u0, w0 from "
+                                  "(okb), 2 Richardson iterations of S~^-1, 5 V-cycles",
+                      "dofs": nd, "global_batch": 1, "parallelism": "none (1 GPU)"})
+    step_ms = np.array(st.ms())
+    out.update({"latency_ms": {"p50": float(np.percentile(step_ms, 50)),
+                               "p99": float(np.percentile(step_ms, 99))},
+                "newton_its": st.per_step(), "fgmres_its": its,
+                "fgmres_per_newton": round(float(np.mean(its)), 2),
+                "paper_reference_its": 8.0, "autotuned_shapes": tuned, "roofline": None})
+    return out
+
+
 def bench_robustness(args, torch, ok):
     """Average FGMRES iterations per Newton step (the paper's Tables 1-2
     measure) and timestep throughput, per case and solver preset."""
@@ -353,6 +399,7 @@ def main():
     ap.add_argument("--graphs", action="store_true",
                     help="replay captured FGMRES iterations (single-problem configs)")
     ap.add_argument("--rates", default="2000", help="serve: offered request rates (req/s)")
+    ap.add_argument("--paper-n", type=int, default=100, help="paper: elements per direction")
     ap.add_argument("--duration", type=float, default=8.0, help="serve: seconds of arrivals")
     ap.add_argument("--budget-gib", type=float, default=160.0, help="serve: pool HBM budget")
     ap.add_argument("--max-queue", type=int, default=256, help="serve: queue bound")
@@ -372,6 +419,9 @@ def main():
         ok.set_option(ok.OK_OPT_FUSE_CHEB, 0)
     if args.config == "sweep64":
         print(json.dumps(bench_sweep(args, torch, ok)), flush=True)
+        return
+    if args.config == "paper":
+        print(json.dumps(bench_paper(args, torch, ok)), flush=True)
         return
     if args.config == "robustness":
         print(json.dumps(bench_robustness(args, torch, ok)), flush=True)

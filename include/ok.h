@@ -207,6 +207,12 @@ int ok_profile_read(ok_ctx *ctx, int32_t kernel_class, int64_t *launches, double
  * number of table entries set.  Synchronises; run it outside timed regions. */
 int ok_autotune(ok_ctx *ctx, void *stream, int32_t *entries);
 
+/* Initial chemical potential from (okb) in weak form (Sec. 5: "the initial
+ * condition for w was computed from u0"): solves M w = eps^2 K u + N(u) by
+ * restarted Chebyshev iterations on M in FP64 until the residual is below
+ * 1e-15 of the right-hand side.  d_u, d_w: n entries; synchronises. */
+int ok_initial_w(ok_ctx *ctx, const double *d_u, double *d_w, void *stream);
+
 /* Process-wide tuning options (results are bitwise the same either way):
  *   OK_OPT_FUSE_CHEB: 1 (default) runs consecutive middle iterations of the
  *   Chebyshev iteration on M two per pass (each vector read and written once

@@ -29,6 +29,10 @@
  */
 #include "okref.h"
 
+/* Coarse grids up to this many nodes are solved with a dense Cholesky
+ * factor; larger ones (e.g. 26^3 nodes when N = 25 * 2^k) with CG. */
+#define OKREF_DENSE_COARSE 4096
+
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -565,7 +569,7 @@ int okref_create(const okref_params *p, okref **out) {
       if (!h->P[l]) goto nomem;
     }
   }
-  {
+  if (h->A[L - 1]->nrows <= OKREF_DENSE_COARSE) {
     const csr_t *Ac = h->A[L - 1];
     int64_t n = Ac->nrows;
     h->ncoarse = n;
@@ -636,6 +640,58 @@ static double dot(const double *a, const double *b, int64_t n) {
   double s = 0.0;
   for (int64_t i = 0; i < n; i++) s += a[i] * b[i];
   return s;
+}
+
+/* Conjugate gradients (Hestenes-Stiefel) on an SPD CSR matrix from x = 0,
+ * until ||b - A x|| <= tol ||b|| or maxit iterations.  Used for coarse grids
+ * too large for a dense factor, and for the mass solve of w0. */
+static void cg_solve(const csr_t *A, const double *b, double *x, double tol, int maxit) {
+  int64_t n = A->nrows;
+  double *r = (double *)malloc(sizeof(double) * n);
+  double *pv = (double *)malloc(sizeof(double) * n);
+  double *q = (double *)malloc(sizeof(double) * n);
+  for (int64_t i = 0; i < n; i++) {
+    x[i] = 0.0;
+    r[i] = b[i];
+    pv[i] = b[i];
+  }
+  double rr = dot(r, r, n);
+  const double stop = tol * tol * rr;
+  for (int it = 0; it < maxit && rr > stop && rr > 0.0; it++) {
+    csr_mv(A, pv, q);
+    double al = rr / dot(pv, q, n);
+    for (int64_t i = 0; i < n; i++) {
+      x[i] += al * pv[i];
+      r[i] -= al * q[i];
+    }
+    double rn = dot(r, r, n);
+    double be = rn / rr;
+    rr = rn;
+    for (int64_t i = 0; i < n; i++) pv[i] = r[i] + be * pv[i];
+  }
+  free(r);
+  free(pv);
+  free(q);
+}
+
+/* w from u by (okb) in weak form: M w = eps^2 K u + N(u) (the initial
+ * chemical potential of the paper's experiment, Sec. 5). */
+int okref_initial_w(okref *h, const double *u, double *w) {
+  int64_t n = h->lev[0].nodes;
+  double *rhs = (double *)malloc(sizeof(double) * n);
+  double *t = (double *)malloc(sizeof(double) * n);
+  if (!rhs || !t) {
+    free(rhs);
+    free(t);
+    return OKREF_E_NOMEM;
+  }
+  csr_mv(h->K, u, t);
+  assemble_N(&h->lev[0], u, rhs);
+  for (int64_t i = 0; i < n; i++) rhs[i] += h->p.eps * h->p.eps * t[i];
+  cg_solve(h->M, rhs, w, 1e-15, 10000);
+  free(rhs);
+  free(t);
+  return OKREF_OK;
 }
 
 /* F1 = M(u - un) + dt K (th w + (1-th) wn) + dt sigma M (th u + (1-th) un - m 1)
@@ -737,7 +793,10 @@ int okref_cheb_mass(okref *h, const double *r, double *x) {
 static void vcycle(okref *h, int l, const double *b, double *x, int zero_start) {
   int64_t n = h->lev[l].nodes;
   if (l == h->L - 1) {
-    dense_chol_solve(h->chol, h->ncoarse, b, x);
+    if (h->chol)
+      dense_chol_solve(h->chol, h->ncoarse, b, x);
+    else
+      cg_solve(h->A[l], b, x, 1e-15, 5000);
     return;
   }
   const csr_t *A = h->A[l];

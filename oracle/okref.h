@@ -56,6 +56,7 @@ int okref_matrix(okref *h, int which, int level, const double *u,
                  int64_t *nrows, int64_t *ncols, int64_t *nnz,
                  int64_t *rp, int32_t *ci, double *v);
 int okref_nonlinear(okref *h, const double *u, double *nvec);          /* N(u)   */
+int okref_initial_w(okref *h, const double *u, double *w);  /* M w = eps^2 K u + N(u) (okb) */
 int okref_cheb_interval(const okref *h, int level, int mass, double *lo, double *hi);
 
 double okref_residual(okref *h, const double *u, const double *w, const double *un,

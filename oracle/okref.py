@@ -57,6 +57,7 @@ def _load():
     lib.okref_matrix.argtypes = [C.c_void_p, C.c_int, C.c_int, d, P(C.c_int64), P(C.c_int64),
                                  P(C.c_int64), P(C.c_int64), P(C.c_int32), d]
     lib.okref_nonlinear.argtypes = [C.c_void_p, d, d]
+    lib.okref_initial_w.argtypes = [C.c_void_p, d, d]
     lib.okref_cheb_interval.argtypes = [C.c_void_p, C.c_int, C.c_int, d, d]
     lib.okref_residual.argtypes = [C.c_void_p, d, d, d, d, d]
     lib.okref_residual.restype = C.c_double
@@ -148,6 +149,14 @@ class Oracle:
     def nonlinear(self, u):
         out = np.zeros(self.nodes)
         self.lib.okref_nonlinear(self.h, _dp(u), _dp(out))
+        return out
+
+    def initial_w(self, u):
+        """w from u by (okb): M w = eps^2 K u + N(u) (CG to round-off)."""
+        out = np.zeros(self.nodes)
+        st = self.lib.okref_initial_w(self.h, _dp(u), _dp(out))
+        if st:
+            raise RuntimeError(f"okref_initial_w failed: {st}")
         return out
 
     def cheb_interval(self, level=0, mass=False):

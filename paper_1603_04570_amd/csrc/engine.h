@@ -114,6 +114,10 @@ int mg_apply_d(ClassCtx& c, const int* flags, Vec<const double> b, Vec<double> x
 // F and ||F|| per instance (norms in c.out[i].fnorm); F may be null (uses Bv).
 int residual_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const double> w,
                Vec<const double> un, Vec<const double> wn, Vec<double> F, hipStream_t st);
+// w from u by (okb): M w = eps^2 K u + N(u), restarted Chebyshev on M (FP64)
+// until ||rhs - M w|| <= 1e-15 ||rhs|| (at most 8 rounds of 32 iterations).
+// Single instance (B = 1); rounds: restarts used.
+int initial_w_d(ClassCtx& c, Vec<const double> u, Vec<double> w, int* rounds, hipStream_t st);
 // Solve J x = b by FGMRES for the instances with part[i] set (host masks in
 // h_part of each class).  Results per instance in out[].
 int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,

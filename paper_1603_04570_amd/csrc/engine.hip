@@ -344,7 +344,8 @@ int mg_vcycle(ClassCtx& c, const int* fl, int l, Vec<const P> b, Vec<P> x, bool 
   const Grid& g = c.lev[l];
   const Batch B = c.batch(fl);
   if (l == c.L - 1) {
-    OKE(c, launch_coarse_solve<P>(g, B, b, x, st));
+    OKE(c, launch_coarse_solve<P>(g, B, b, x, pvec<P>(c.mg[l][2], g.nodes),
+                                  pvec<P>(c.mg[l][3], g.nodes), st));
     return OK_SUCCESS;
   }
   const int64_t nl = g.nodes;
@@ -620,8 +621,7 @@ int validate_params(const ok_params* p, std::string& why) {
   if (L < 1 || L > kMaxLevels) return bad("bad mg_levels");
   if (p->n % (1 << (L - 1))) return bad("n not divisible by 2^(levels-1)");
   int nc = p->n >> (L - 1);
-  int64_t cn = (int64_t)(nc + 1) * (nc + 1) * (p->dim == 3 ? (nc + 1) : 1);
-  if (nc < 1 || cn > 1024 || nc + 1 > 64) return bad("coarsest grid must have <= 1024 nodes");
+  if (nc < 1 || nc + 1 > 64) return bad("coarsest grid must have <= 64 nodes per direction");
   return OK_SUCCESS;
 }
 
@@ -738,6 +738,48 @@ int mg_apply_d(ClassCtx& c, const int* flags, Vec<const double> b, Vec<double> x
   int e = mg_apply<float>(c, flags, cst(bf), xf, cycles, st);
   if (e) return e;
   OKE(c, launch_copy_scale<float, double>(c.batch(flags), cst(xf), x, 1.0, n, st));
+  return OK_SUCCESS;
+}
+
+int initial_w_d(ClassCtx& c, Vec<const double> u, Vec<double> w, int* rounds, hipStream_t st) {
+  const Grid& g = c.lev[0];
+  const Batch B = c.batch(nullptr);
+  const int64_t n = c.n;
+  // rhs = N(u) + eps^2 K u  (weak form of (okb) at u)
+  Vec<double> G = vec(c.G, n), rhs = vec(c.Bv, c.n2()), res = vec(c.T1, c.n2()),
+              dl = vec(c.X, c.n2());
+  OKE(c, launch_element<double, double>(g, B, 1, u, Vec<const double>{nullptr, 0},
+                                        Vec<const double>{nullptr, 0}, 1.0, 0.0, G, st));
+  OKE(c, launch_stencil_axpy<double, double, double>(g, B, u, cst(G), 0.0, CF_ONE, 1.0, CF_E2,
+                                                      rhs, st));
+  OKE(c, launch_fill(B, w, 0.0, n, st));
+  // Chebyshev work vectors in the (idle) Krylov basis, FP64 in every precision
+  const int64_t sv = sV(c);
+  Vec<double> cr{c.V, sv}, ca{c.V + n, sv}, cb{c.V + 2 * n, sv}, cr2{c.V + 3 * n, sv};
+  auto norm = [&](Vec<const double> v, double* out) -> int {
+    OKE(c, launch_dot_partial(B, v, v, n, vec(c.pA, (int64_t)kMaxRedBlocks), st));
+    OKE(c, launch_reduce_final(B, Vec<const double>{c.pA, kMaxRedBlocks}, n, vec(c.nrm, 8), st));
+    if (d2h(c, c.h_nrm, c.nrm, (size_t)8 * c.B, st) || sync(c, st)) return OK_E_HIP;
+    *out = c.h_nrm[1];
+    return OK_SUCCESS;
+  };
+  double bn = 0.0;
+  if (norm(cst(rhs), &bn)) return OK_E_HIP;
+  int k = 0;
+  for (; k < 8; k++) {
+    // res = rhs - M w; w += Cheb_M(res)
+    OKE(c, launch_stencil_axpy<double, double, double>(g, B, cst(w), cst(rhs), -1.0, CF_ONE, 0.0,
+                                                        CF_ONE, res, st));
+    double rn = 0.0;
+    if (norm(cst(res), &rn)) return OK_E_HIP;
+    if (!std::isfinite(rn)) return set_err(c.err, OK_E_NONFINITE, "non-finite initial w");
+    if (rn <= 1e-15 * bn) break;
+    int e = cheb_zero<double, double>(c, nullptr, OK_K_NONE, OK_K_NONE, g, -1, CF_ONE, kMaxCheb,
+                                      cst(res), dl, cr, ca, cb, st, cr2);
+    if (e) return e;
+    OKE(c, launch_add_inplace<double>(B, w, cst(dl), n, st));
+  }
+  if (rounds) *rounds = k;
   return OK_SUCCESS;
 }
 

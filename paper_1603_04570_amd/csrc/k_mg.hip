@@ -185,6 +185,64 @@ __global__ void __launch_bounds__(1024)
   for (int q = t; q < n; q += blockDim.x) x[q] = (T)src[q];
 }
 
+// Coarse grids larger than one block's LDS: the same fast diagonalisation,
+// one pass per axis through global scratch.  Pass `ax` maps in -> out with
+// out[..k..] = sum_j V[j][k] in[..j..] along axis ax (V symmetric, so the
+// forward and backward transforms are the same pass); k_coarse_scale divides
+// by Lambda Gamma.  V is rebuilt in LDS by every block (nn <= 64).
+template <class TI, class TO>
+__global__ void __launch_bounds__(256)
+    k_coarse_axis(Vec<const TI> inv, Vec<TO> outv, Grid g, Batch bt, int ax, int per) {
+  const int inst = blockIdx.x / per;
+  if (bt.act && !bt.act[inst]) return;
+  __shared__ double V[kCoarseLine * kCoarseLine];
+  const int nn = g.nn, N = g.N;
+  for (int q = threadIdx.x; q < nn * nn; q += blockDim.x) {
+    const int j = q / nn, k = q % nn;
+    V[q] = cospi((double)(j * k % (2 * N)) / (double)N);
+  }
+  __syncthreads();
+  const unsigned q = (unsigned)(blockIdx.x - inst * per) * blockDim.x + threadIdx.x;
+  if (q >= (unsigned)g.nodes) return;
+  const unsigned stride = (ax == 0) ? 1u : (ax == 1 ? (unsigned)nn : (unsigned)(nn * nn));
+  const int k = (int)((q / stride) % (unsigned)nn);
+  const unsigned base = q - (unsigned)k * stride;
+  const TI* in = inv.at(inst);
+  double s = 0.0;
+  for (int j = 0; j < nn; j++) s += V[j * nn + k] * ld(in + base + (unsigned)j * stride);
+  outv.at(inst)[q] = (TO)s;
+}
+
+template <int DIM, class T>
+__global__ void __launch_bounds__(256)
+    k_coarse_scale(Vec<T> xv, Grid g, Batch bt, int per) {
+  const int inst = blockIdx.x / per;
+  if (bt.act && !bt.act[inst]) return;
+  const unsigned q = (unsigned)(blockIdx.x - inst * per) * blockDim.x + threadIdx.x;
+  if (q >= (unsigned)g.nodes) return;
+  const int nn = g.nn, N = g.N;
+  const double alpha = bt.coef[inst].alpha;
+  int k0, k1, k2;
+  node_ijk<DIM>(q, (unsigned)nn, k0, k1, k2);
+  auto mu = [&](int t) { return (g.h / 3.0) * (2.0 + cospi((double)t / (double)N)); };
+  auto kap = [&](int t) { return (2.0 / g.h) * (1.0 - cospi((double)t / (double)N)); };
+  auto gam = [&](int t) { return (t == 0 || t == N) ? (double)N : 0.5 * N; };
+  double lam, gg;
+  if (DIM == 3) {
+    const double m0 = mu(k0), m1 = mu(k1), m2 = mu(k2);
+    const double pm = m0 * m1 * m2;
+    const double sk = kap(k0) * m1 * m2 + m0 * kap(k1) * m2 + m0 * m1 * kap(k2);
+    lam = pm + alpha * sk;
+    gg = gam(k0) * gam(k1) * gam(k2);
+  } else {
+    const double m0 = mu(k0), m1 = mu(k1);
+    lam = m0 * m1 + alpha * (kap(k0) * m1 + m0 * kap(k1));
+    gg = gam(k0) * gam(k1);
+  }
+  T* x = xv.at(inst);
+  x[q] = (T)(ld(x + q) / (lam * gg));
+}
+
 }  // namespace
 
 template <class T>
@@ -213,12 +271,38 @@ hipError_t launch_prolong_add(const Grid& fine, const Grid& coarse, const Batch&
 
 template <class T>
 hipError_t launch_coarse_solve(const Grid& g, const Batch& B, Vec<const T> b, Vec<T> x,
-                               hipStream_t st) {
-  if (g.nodes > kCoarseMax || g.nn > kCoarseLine) return hipErrorInvalidValue;
+                               Vec<T> s1, Vec<T> s2, hipStream_t st) {
+  if (g.nn > kCoarseLine) return hipErrorInvalidValue;
+  if (g.nodes <= kCoarseMax) {
+    if (g.dim == 2)
+      hipLaunchKernelGGL((k_coarse<2, T>), dim3(B.count), dim3(1024), 0, st, b, x, g, B);
+    else
+      hipLaunchKernelGGL((k_coarse<3, T>), dim3(B.count), dim3(1024), 0, st, b, x, g, B);
+    return hipGetLastError();
+  }
+  if (s1.null() || s2.null()) return hipErrorInvalidValue;
+  const int per = (int)((g.nodes + 255) / 256);
+  const dim3 grid((unsigned)((int64_t)per * B.count)), block(256);
+  // forward: b -> s1 -> s2 (-> s1 in 3D), scale, backward to x
+  Vec<const T> src = b;
+  Vec<T> bufs[2] = {s1, s2};
+  int w = 0;
+  for (int ax = 0; ax < g.dim; ax++) {
+    hipLaunchKernelGGL((k_coarse_axis<T, T>), grid, block, 0, st, src, bufs[w], g, B, ax, per);
+    src = Vec<const T>{bufs[w].p, bufs[w].s};
+    w ^= 1;
+  }
+  Vec<T> cur{const_cast<T*>(src.p), src.s};
   if (g.dim == 2)
-    hipLaunchKernelGGL((k_coarse<2, T>), dim3(B.count), dim3(1024), 0, st, b, x, g, B);
+    hipLaunchKernelGGL((k_coarse_scale<2, T>), grid, block, 0, st, cur, g, B, per);
   else
-    hipLaunchKernelGGL((k_coarse<3, T>), dim3(B.count), dim3(1024), 0, st, b, x, g, B);
+    hipLaunchKernelGGL((k_coarse_scale<3, T>), grid, block, 0, st, cur, g, B, per);
+  for (int ax = 0; ax < g.dim; ax++) {
+    Vec<T> dst = (ax == g.dim - 1) ? x : bufs[w];
+    hipLaunchKernelGGL((k_coarse_axis<T, T>), grid, block, 0, st, src, dst, g, B, ax, per);
+    src = Vec<const T>{dst.p, dst.s};
+    w ^= 1;
+  }
   return hipGetLastError();
 }
 
@@ -228,7 +312,7 @@ hipError_t launch_coarse_solve(const Grid& g, const Batch& B, Vec<const T> b, Ve
   template hipError_t launch_prolong_add<T>(const Grid&, const Grid&, const Batch&,             \
                                             Vec<const T>, Vec<T>, hipStream_t);                 \
   template hipError_t launch_coarse_solve<T>(const Grid&, const Batch&, Vec<const T>, Vec<T>,   \
-                                             hipStream_t);
+                                             Vec<T>, Vec<T>, hipStream_t);
 OKD_MG(double)
 OKD_MG(float)
 #undef OKD_MG

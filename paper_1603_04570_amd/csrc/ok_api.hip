@@ -299,6 +299,13 @@ int ok_timestep(ok_ctx* c, double* u, double* w, int32_t nsteps, ok_stats* stats
   return e;
 }
 
+int ok_initial_w(ok_ctx* c, const double* u, double* w, void* stream) {
+  if (!c) return OK_E_INVALID;
+  if (!u || !w || u == w) return fail(&c->err, OK_E_INVALID, "null or aliased vectors");
+  if (!aligned8(u) || !aligned8(w)) return fail(&c->err, OK_E_INVALID, "misaligned");
+  return initial_w_d(c->cls, one(u), one(w), nullptr, (hipStream_t)stream);
+}
+
 int ok_set_option(int32_t option, int32_t value) {
   switch (option) {
     case OK_OPT_FUSE_CHEB:

@@ -201,9 +201,12 @@ hipError_t launch_restrict(const Grid& fine, const Grid& coarse, const Batch& B,
 template <class T>
 hipError_t launch_prolong_add(const Grid& fine, const Grid& coarse, const Batch& B,
                               Vec<const T> ec, Vec<T> x, hipStream_t st);
+// Coarse solve: grids of at most 1024 nodes in one block per instance, larger
+// ones (at most 64 nodes per direction) axis by axis through the scratch
+// vectors s1, s2 (nodes of g per instance).
 template <class T>
 hipError_t launch_coarse_solve(const Grid& g, const Batch& B, Vec<const T> b, Vec<T> x,
-                               hipStream_t st);
+                               Vec<T> s1, Vec<T> s2, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Vector and Krylov kernels (FP64 unless templated).

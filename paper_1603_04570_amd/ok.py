@@ -130,6 +130,7 @@ def load():
     lib.ok_batch_last_error.restype = C.c_char_p
     lib.ok_use_graphs.argtypes = [vp, i32]
     lib.ok_set_option.argtypes = [i32, i32]
+    lib.ok_initial_w.argtypes = [vp, vp, vp, vp]
     lib.ok_batch_use_graphs.argtypes = [vp, i32]
     lib.ok_server_default_config.argtypes = [P(ServerConfig)]
     lib.ok_server_state_bytes.argtypes = [P(Params), i32, P(C.c_size_t)]
@@ -289,6 +290,13 @@ class Problem:
 
     def use_graphs(self, enable=True):
         self._check(self.lib.ok_use_graphs(self.ctx, int(bool(enable))), "ok_use_graphs")
+
+    def initial_w(self, u, w=None):
+        """w from u by (okb): M w = eps^2 K u + N(u)."""
+        w = self.field(1) if w is None else w
+        self._check(self.lib.ok_initial_w(self.ctx, _ptr(u), _ptr(w), _stream(self.stream)),
+                    "ok_initial_w")
+        return w
 
     def profile_enable(self, *kernel_classes):
         mask = 0

@@ -52,11 +52,22 @@ def test_default_params_and_workspace(lib):
     assert ok.workspace_bytes(pm) < b
 
 
+def test_non_power_of_two_meshes_accepted(lib):
+    """N = 25 * 2^k coarsens to 25 elements per direction (26^d coarse nodes)."""
+    from paper_1603_04570_amd import ok
+    for dim, n in [(2, 100), (3, 50), (3, 100), (2, 400)]:
+        p = ok.default_params(dim=dim, n=n)
+        b = C.c_size_t()
+        assert lib.ok_workspace_bytes(C.byref(p), C.byref(b)) == 0 and b.value > 0
+
+
 @pytest.mark.parametrize("field,value", [("dim", 4), ("n", 1), ("eps", 0.0), ("dt", -1.0),
                                          ("theta", 0.0), ("theta", 1.5), ("m", 1.0),
                                          ("precision", 7), ("gmres_restart", 0),
                                          ("gmres_restart", 65), ("cheb_A_its", 0),
-                                         ("mg_pre", 0), ("mg_levels", 9), ("n", 100)])
+                                         ("mg_pre", 0), ("mg_levels", 9),
+                                         # 130 -> 65 elements: 66 coarse nodes per direction
+                                         ("n", 130)])
 def test_invalid_params_rejected(lib, field, value):
     from paper_1603_04570_amd import ok
     p = ok.default_params(**{field: value})

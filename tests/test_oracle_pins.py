@@ -459,3 +459,46 @@ def test_local_rows_match_assembled(dim, n, theta):
     y = o.jacobian_apply(u, x)
     y1, y2 = local_jacobian(o.params, u, x, nodes)
     assert np.abs(np.concatenate([y1, y2]) - y).max() <= 1e-14 * np.abs(y).max()
+
+
+# --------------------------------------------------------------------------- #
+# P17: initial chemical potential from (okb), M w = eps^2 K u + N(u)           #
+# --------------------------------------------------------------------------- #
+def test_initial_w_constant_state():
+    """u = c 1: K u = 0 and N(c 1) = (c^3 - c) M 1, so w = (c^3 - c) 1."""
+    for dim, n in [(2, 16), (3, 8)]:
+        o = Oracle(dim, n, 0.02, 100.0, 0.4, 4e-4, 0.5)
+        for c in (0.3, -0.7):
+            w = o.initial_w(np.full(o.nodes, c))
+            assert np.abs(w - (c ** 3 - c)).max() < 1e-12
+
+
+def test_initial_w_small_dct_mode():
+    """u = a v with v a DCT-I mode and a -> 0: N(a v) = -a M v + O(a^3) and
+    K v = lambda M v, so w = a (eps^2 lambda - 1) v + O(a^3)."""
+    eps, a = 0.03, 1e-6
+    for dim, n, ks in [(2, 32, (3, 1)), (3, 16, (2, 0, 1))]:
+        o = Oracle(dim, n, eps, 100.0, 0.0, 4e-4, 1.0)
+        v = fr.dct_mode(dim, n, ks)
+        lam = sum(fr.gen_eig_1d(n, k) for k in ks)
+        w = o.initial_w(a * v)
+        ref = a * (eps ** 2 * lam - 1.0) * v
+        assert np.linalg.norm(w - ref) / np.linalg.norm(ref) < 1e-9
+
+
+# --------------------------------------------------------------------------- #
+# P18: multigrid with a CG coarse solve (coarse grid of 26^3 nodes, N = 50)    #
+# --------------------------------------------------------------------------- #
+def test_multigrid_cg_coarse_converges_to_exact_solve():
+    """N = 50 coarsens to 25 elements (26^3 coarse nodes, beyond the dense
+    factor): many V-cycles reach the exact (M + alpha K)^-1 b of the DCT-I
+    fast diagonalisation."""
+    dim, n, eps, sigma, dt, theta = 3, 50, 0.02, 100.0, 4e-4, 0.5
+    o = Oracle(dim, n, eps, sigma, 0.4, dt, theta)
+    assert o.levels == 2
+    c = dt * theta / (1.0 + dt * theta * sigma)
+    alpha = eps * np.sqrt(c)
+    b = uniform01(17, o.nodes) - 0.5
+    x = o.mg(b, 25)
+    ref = fr.fast_diag_solve(dim, n, alpha, b)
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-10
