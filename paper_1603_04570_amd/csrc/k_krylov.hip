@@ -18,6 +18,13 @@ namespace {
 
 __device__ __forceinline__ double ld(const double* p) { return *p; }
 __device__ __forceinline__ double ld(const float* p) { return (double)*p; }
+// Streaming accesses of the Krylov vectors (each touched once per pass and
+// far larger than the caches at the sizes that matter): nontemporal hints.
+__device__ __forceinline__ double ldnt(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void stnt(double v, double* p) { __builtin_nontemporal_store(v, p); }
+
+// Threads per block of the reduction kernels (k_dot, k_mgs).
+constexpr int kRedThreads = 512;
 
 // Sum over the block (256 threads); result valid in every thread.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -44,20 +51,20 @@ __device__ __forceinline__ bool inactive(const Batch& B, int inst) {
 }
 
 // Element order of a reduction over a vector of length n: thread t of
-// reduction block kb visits i = kb*256 + t + k*nblk*256, k = 0, 1, ..., in
-// that order (explicit fma).  Scalar loads: on gfx950 this streams faster
-// than 16-byte loads for these three-vector passes.
-__global__ void __launch_bounds__(256)
+// reduction block kb visits i = kb*T + t + k*nblk*T (T = kRedThreads),
+// k = 0, 1, ..., in that order (explicit fma).  Scalar nontemporal loads:
+// on gfx950 this streams faster than 16-byte loads for these passes.
+__global__ void __launch_bounds__(kRedThreads)
     k_dot(Batch B, Vec<const double> av, Vec<const double> bv, int64_t n, Vec<double> pv,
           int nblk) {
-  __shared__ double sh[8];
+  __shared__ double sh[kRedThreads / 64];
   const int inst = blockIdx.x / nblk, kb = blockIdx.x % nblk;
   if (inactive(B, inst)) return;
   const double* a = av.at(inst);
   const double* b = bv.at(inst);
   double v = 0.0;
   for (int64_t i = (int64_t)kb * blockDim.x + threadIdx.x; i < n; i += (int64_t)nblk * blockDim.x)
-    v = fma(a[i], b[i], v);
+    v = fma(ldnt(a + i), ldnt(b + i), v);
   v = block_sum(v, sh);
   if (threadIdx.x == 0) pv.at(inst)[kb] = v;
 }
@@ -79,10 +86,10 @@ __global__ void __launch_bounds__(256)
 // partials of <w, v_next> (of <w, w> when v_next is null).  Same element
 // order as k_dot.
 template <bool NORM>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kRedThreads)
     k_mgs(Batch B, Vec<double> wv, Vec<const double> viv, Vec<const double> vnv, int64_t n,
           Vec<const double> pinv, Vec<double> poutv, Vec<double> Hv, int nblk) {
-  __shared__ double sh[8];
+  __shared__ double sh[kRedThreads / 64];
   const int inst = blockIdx.x / nblk, kb = blockIdx.x % nblk;
   if (inactive(B, inst)) return;
   const double h = sum_partials(pinv.at(inst), nblk, sh);
@@ -93,9 +100,9 @@ __global__ void __launch_bounds__(256)
   double v = 0.0;
   for (int64_t i = (int64_t)kb * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)nblk * blockDim.x) {
-    const double x = fma(-h, vi[i], w[i]);
-    w[i] = x;
-    v = fma(x, NORM ? x : vn[i], v);
+    const double x = fma(-h, ldnt(vi + i), ldnt(w + i));
+    stnt(x, w + i);
+    v = fma(x, NORM ? x : ldnt(vn + i), v);
   }
   v = block_sum(v, sh);
   if (threadIdx.x == 0) poutv.at(inst)[kb] = v;
@@ -154,7 +161,7 @@ __global__ void __launch_bounds__(256)
   double* v = vv.at(inst);
   for (int64_t i = (int64_t)(blockIdx.x % per) * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)per * blockDim.x)
-    v[i] = w[i] * s;
+    stnt(ldnt(w + i) * s, v + i);
 }
 
 __global__ void __launch_bounds__(256)
@@ -291,7 +298,7 @@ dim3 grid_of(int per, const Batch& B) { return dim3((unsigned)((int64_t)per * B.
 hipError_t launch_dot_partial(const Batch& B, Vec<const double> a, Vec<const double> b,
                               int64_t n, Vec<double> partials, hipStream_t st) {
   const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_dot, grid_of(nb, B), dim3(256), 0, st, B, a, b, n, partials, nb);
+  hipLaunchKernelGGL(k_dot, grid_of(nb, B), dim3(kRedThreads), 0, st, B, a, b, n, partials, nb);
   return hipGetLastError();
 }
 
@@ -307,11 +314,11 @@ hipError_t launch_mgs_step(const Batch& B, Vec<double> w, Vec<const double> vi,
                            Vec<double> pout, Vec<double> Hij, hipStream_t st) {
   const int nb = red_blocks(n);
   if (vnext.null())
-    hipLaunchKernelGGL(k_mgs<true>, grid_of(nb, B), dim3(256), 0, st, B, w, vi, vnext, n, pin,
-                       pout, Hij, nb);
+    hipLaunchKernelGGL(k_mgs<true>, grid_of(nb, B), dim3(kRedThreads), 0, st, B, w, vi, vnext, n,
+                       pin, pout, Hij, nb);
   else
-    hipLaunchKernelGGL(k_mgs<false>, grid_of(nb, B), dim3(256), 0, st, B, w, vi, vnext, n, pin,
-                       pout, Hij, nb);
+    hipLaunchKernelGGL(k_mgs<false>, grid_of(nb, B), dim3(kRedThreads), 0, st, B, w, vi, vnext, n,
+                       pin, pout, Hij, nb);
   return hipGetLastError();
 }
 
