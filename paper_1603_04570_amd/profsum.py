@@ -5,8 +5,8 @@
 
     python -m paper_1603_04570_amd.profsum traffic --fetch F.csv --write W.csv \
         --copy-fetch CF.csv --copy-write CW.csv --copy-bytes BYTES --kernel SUBSTRING \
-        [--main-grid]
-        per-dispatch HBM bytes of the kernels whose name contains SUBSTRING
+        [--kernel SUBSTRING ...] [--main-grid]
+        per-dispatch HBM bytes of the kernels whose name contains any SUBSTRING
         (with --main-grid: only their dispatches of the most dispatched grid
         size, i.e. the launch shape the run used most -- autotuner trials and
         other levels excluded), from
@@ -40,12 +40,12 @@ def stats(path: str, top: int = 25) -> str:
     return "\n".join(out)
 
 
-def _counter(path: str, counter: str, substring: str | None = None):
+def _counter(path: str, counter: str, substrings=None):
     vals = []
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
-        if substring is not None and substring not in r["Kernel_Name"]:
+        if substrings is not None and not any(k in r["Kernel_Name"] for k in substrings):
             continue
         vals.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
     return vals
@@ -63,8 +63,9 @@ def _copy_scale(path: str, counter: str, nbytes: int) -> float:
 def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, kernel, main_grid=False):
     sf = _copy_scale(copy_fetch, "FETCH_SIZE", copy_bytes)
     sw = _copy_scale(copy_write, "WRITE_SIZE", copy_bytes)
-    f = _counter(fetch, "FETCH_SIZE", kernel)
-    w = _counter(write, "WRITE_SIZE", kernel)
+    kernels = [kernel] if isinstance(kernel, str) else list(kernel)
+    f = _counter(fetch, "FETCH_SIZE", kernels)
+    w = _counter(write, "WRITE_SIZE", kernels)
     if not f or not w:
         raise SystemExit(f"no dispatch of a kernel containing {kernel!r}")
     if main_grid:
@@ -74,7 +75,8 @@ def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, kernel, main_grid=
         w = [x for x in w if x[1] == g]
     fb = statistics.mean(x for _, _, x in f) * sf
     wb = statistics.mean(x for _, _, x in w) * sw
-    return {"kernel": short_name(f[0][0], 200), "grid_size": f[0][1],
+    names = sorted({short_name(x[0], 80) for x in f})
+    return {"kernel": "; ".join(names), "grid_size": f[0][1],
             "dispatches": [len(f), len(w)],
             "fetch_scale_bytes_per_unit": sf, "write_scale_bytes_per_unit": sw,
             "fetch_bytes_per_dispatch": fb, "write_bytes_per_dispatch": wb,
@@ -88,8 +90,9 @@ def main():
     a.add_argument("csv")
     a.add_argument("top", nargs="?", type=int, default=25)
     b = sub.add_parser("traffic")
-    for k in ("fetch", "write", "copy-fetch", "copy-write", "kernel"):
+    for k in ("fetch", "write", "copy-fetch", "copy-write"):
         b.add_argument("--" + k, required=True)
+    b.add_argument("--kernel", action="append", required=True)
     b.add_argument("--copy-bytes", type=int, required=True)
     b.add_argument("--main-grid", action="store_true")
     args = ap.parse_args()
