@@ -220,6 +220,28 @@ int ok_initial_w(ok_ctx *ctx, const double *d_u, double *d_w, void *stream);
 enum ok_option { OK_OPT_FUSE_CHEB = 1 };
 int ok_set_option(int32_t option, int32_t value);
 
+/* Launch shape of the streaming node-stencil kernels on one grid: the
+ * process-wide table entry that ok_autotune writes, set by hand (to pin a
+ * shape for timing, or to check that results do not depend on it).
+ *   dim, n: the grid (n elements per direction; any level of a hierarchy);
+ *   kernel: OK_SHAPE_STENCIL (one stenciled field: Chebyshev iterations,
+ *     multigrid residuals, coupling), OK_SHAPE_STENCIL2 (two fields: the
+ *     mass/stiffness pairs of residual and Jacobian), OK_SHAPE_CHEB2 (two
+ *     fused Chebyshev iterations on M);
+ *   precision: OK_FP64 or OK_MIXED (the preconditioner's storage type);
+ *   items: nodes per thread per plane, 1, 2, 4 or 8 (STENCIL2: 1, 2, 4;
+ *     CHEB2: 1 or 2 with 256 threads, 4 = 512 threads of 2 nodes); 0 removes
+ *     the entry (built-in default shape);
+ *   zchunks: the n+1 planes of the streaming axis are split evenly into
+ *     1..n+1 ranges, one block per (plane chunk, range).
+ * Every node's arithmetic is the same for every shape, so results are
+ * bitwise equal.  Launches read the table when issued; HIP graphs captured
+ * earlier (ok_use_graphs) keep the shapes they were captured with.  Returns
+ * OK_E_INVALID for an argument out of range. */
+enum ok_shape_kernel { OK_SHAPE_STENCIL = 1, OK_SHAPE_STENCIL2 = 2, OK_SHAPE_CHEB2 = 3 };
+int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precision, int32_t items,
+                        int32_t zchunks);
+
 /* Launch mode of the FGMRES iterations.  enable != 0: the context gets a HIP
  * stream of its own (default priority) and captures each Arnoldi iteration j
  * (preconditioner, Jacobian, Gram-Schmidt, Givens) once as a HIP graph, keyed

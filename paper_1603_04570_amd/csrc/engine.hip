@@ -1124,9 +1124,23 @@ double time_best(hipStream_t st, F&& launch) {
   return best;
 }
 
+// Candidate z-chunk counts of a streaming stencil launch: chunks of 4 to 32
+// planes, and the counts that make the whole grid (all instances) about
+// 512 ... 6144 blocks, i.e. one or a few full rounds of resident blocks.
+std::vector<int> zchunk_candidates(const Grid& g, int items, int count) {
+  const int64_t plane = (g.dim == 3) ? g.plane : (int64_t)g.nn;
+  const int64_t nch = (plane + 256 * items - 1) / (256 * items);
+  std::vector<int> v;
+  for (int zc : {4, 8, 16, 32}) v.push_back((g.nn + zc - 1) / zc);
+  for (int64_t t : {512, 1024, 2048, 3072, 4096, 6144}) v.push_back((int)(t / (nch * count)));
+  for (int& z : v) z = std::max(1, std::min(z, g.nn));
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+  return v;
+}
+
 template <class P>
 int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
-  const int zcs[4] = {4, 8, 16, 32};
   const int word = (int)sizeof(P);
   const Batch B = c.batch(nullptr);
   for (int l = 0; l < c.L; l++) {
@@ -1143,8 +1157,7 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
     double best = 1e30;
     int bi = 0, bz = 0;
     for (int items = 1; items <= 8; items *= 2)
-      for (int zc : zcs) {
-        if (zc > g.nn && zc != 4) continue;
+      for (int zc : zchunk_candidates(g, items, B.count)) {
         stencil_tune_set(g.dim, g.nn, 1, word, items, zc);
         double t = time_best(st, [&]() {
           return launch_cheb_step<P>(g, B, l, 0, CF_ONE, false, x, r, cst(d0), d1, st);
@@ -1166,9 +1179,8 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
            d1 = pvec<P>(c.cdb, nl);
     double best = 1e30;
     int bi = 0, bz = 0;
-    for (int items = 1; items <= 2; items *= 2)
-      for (int zc : zcs) {
-        if (zc > g.nn && zc != 4) continue;
+    for (int items = 1; items <= 4; items *= 2)
+      for (int zc : zchunk_candidates(g, items, B.count)) {
         stencil_tune_set(g.dim, g.nn, kFusedKey, word, items, zc);
         if (!cheb_fusion_on(g, word)) continue;
         double t = time_best(st, [&]() {
@@ -1202,8 +1214,7 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
     double best = 1e30;
     int bi = 0, bz = 0;
     for (int items = 1; items <= 4; items *= 2)
-      for (int zc : zcs) {
-        if (zc > g.nn && zc != 4) continue;
+      for (int zc : zchunk_candidates(g, items, B.count)) {
         stencil_tune_set(g.dim, g.nn, 2, word, items, zc);
         double t = time_best(st, [&]() {
           return launch_stencil_lin2<P>(g, B, z, off(z, c.n), Vec<const double>{nullptr, 0},

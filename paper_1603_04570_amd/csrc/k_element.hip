@@ -51,12 +51,6 @@ __device__ __forceinline__ void proj3(const double* t, double& o0, double& o1) {
   o1 = kPc * t[0] + m + kPa * t[2];
 }
 
-__device__ __forceinline__ int remap(int b, int nb) {
-  int q = nb / 8, r = nb % 8;
-  int x = b % 8, t = b / 8;
-  return ((x < r) ? x * (q + 1) : r * (q + 1) + (x - r) * q) + t;
-}
-
 // One 3D element: corners v[az][ay][ax] of u and x; returns corner
 // contributions E[az][ay][ax] without the h^3 factor.
 template <int MODE>
@@ -165,7 +159,7 @@ __device__ __forceinline__ void element2(const double (&u)[2][2], const double (
 struct EShape {
   int epl;       // elements per lane along x: ceil(N/64)
   int rowtiles;  // ceil((N+1)/kRows)
-  int zc, nzc;   // planes per block, z-chunks
+  int zc, nzc;   // most planes per block, z-chunks (planes split evenly)
 };
 
 EShape element_shape(const Grid& g) {
@@ -178,8 +172,9 @@ EShape element_shape(const Grid& g) {
   } else {
     int64_t zc = ((int64_t)g.nn * s.rowtiles + 599) / 600;
     zc = std::max<int64_t>(4, std::min<int64_t>(zc, 32));
-    s.zc = (int)std::min<int64_t>(zc, g.nn);
-    s.nzc = (g.nn + s.zc - 1) / s.zc;
+    zc = std::min<int64_t>(zc, g.nn);
+    s.nzc = (int)((g.nn + zc - 1) / zc);
+    s.zc = (g.nn + s.nzc - 1) / s.nzc;
   }
   return s;
 }
@@ -194,7 +189,7 @@ __global__ void __launch_bounds__(64 * kWaves)
   __shared__ double xch[2][kWaves][NZ][64];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int lb = remap(blockIdx.x, gridDim.x);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int per = sh.rowtiles * sh.nzc;
   const int inst = lb / per;
   if (B.act && !B.act[inst]) return;
@@ -216,8 +211,8 @@ __global__ void __launch_bounds__(64 * kWaves)
 
   int z0 = 0, z1 = 1;
   if (DIM == 3) {
-    z0 = zch * sh.zc;
-    z1 = min(z0 + sh.zc, nn);
+    z0 = (int)(((int64_t)zch * nn) / sh.nzc);
+    z1 = (int)(((int64_t)(zch + 1) * nn) / sh.nzc);
   }
   const int epl = (EPLT > 0) ? EPLT : sh.epl;
   double carry[EPLT + 1];

@@ -23,46 +23,98 @@ namespace {
 __device__ __forceinline__ double ld(const double* p) { return *p; }
 __device__ __forceinline__ double ld(const float* p) { return (double)*p; }
 
-// One thread per node of the output grid, flat index per instance (< 2^31
-// nodes), decomposed with 32-bit divisions.
+// q / nn and q % nn for q < 2^31 without an integer division: the double
+// product q * (1/nn) is within 5e-7 of q/nn, whose fractional part is 0 or at
+// least 1/nn, so its truncation is the quotient or one less; the remainder
+// test corrects it.
+__device__ __forceinline__ unsigned qdiv(unsigned q, unsigned nn, double rnn, unsigned& rem) {
+  unsigned d = (unsigned)((double)q * rnn);
+  int r = (int)(q - d * nn);
+  if (r < 0) {
+    d--;
+    r += (int)nn;
+  } else if (r >= (int)nn) {
+    d++;
+    r -= (int)nn;
+  }
+  rem = (unsigned)r;
+  return d;
+}
+
+// One thread per node of the output grid, flat index q per instance (< 2^31
+// nodes): q = i + nn (j + nn k).
 template <int DIM>
-__device__ __forceinline__ void node_ijk(unsigned q, unsigned nn, int& i, int& j, int& k) {
-  const unsigned row = q / nn;
-  i = (int)(q - row * nn);
+__device__ __forceinline__ void node_ijk(unsigned q, const Grid& g, int& i, int& j, int& k) {
+  const unsigned nn = (unsigned)g.nn;
+  unsigned ri, rj;
+  const unsigned row = qdiv(q, nn, g.rnn, ri);
+  i = (int)ri;
   if (DIM == 3) {
-    j = (int)(row % nn);
-    k = (int)(row / nn);
+    k = (int)qdiv(row, nn, g.rnn, rj);
+    j = (int)rj;
   } else {
     j = (int)row;
     k = 0;
   }
 }
 
+// Every load of a transfer is issued before the first one is used, from
+// clamped (in-bounds) indices: terms outside the grid are loaded anyway and
+// then left out of the sum, which keeps the summation order (and so every
+// bit) of the plain nested loops over the stencil while no load waits behind
+// a lane-dependent branch.
 template <int DIM, class T>
 __global__ void __launch_bounds__(256)
     k_restrict(Vec<const T> rv, Vec<T> bcv, Grid f, Grid c, Batch B, int per) {
-  const int inst = blockIdx.x / per;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int inst = lb / per;
   if (B.act && !B.act[inst]) return;
-  const unsigned q = (unsigned)(blockIdx.x - inst * per) * blockDim.x + threadIdx.x;
+  const unsigned q = (unsigned)(lb - inst * per) * blockDim.x + threadIdx.x;
   if (q >= (unsigned)c.nodes) return;
   int ci, cj, ck;
-  node_ijk<DIM>(q, (unsigned)c.nn, ci, cj, ck);
+  node_ijk<DIM>(q, c, ci, cj, ck);
   const T* __restrict__ r = rv.at(inst);
-  const int kz = (DIM == 3) ? 1 : 0;
+  constexpr int NZ = (DIM == 3) ? 3 : 1;
+  int64_t off[NZ][3];
+  int fi[3];
+  bool ok[NZ][3], oki[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const int x = 2 * ci + d - 1;
+    oki[d] = (x >= 0 && x <= f.N);
+    fi[d] = x < 0 ? 0 : (x > f.N ? f.N : x);
+  }
+#pragma unroll
+  for (int a = 0; a < NZ; a++) {
+    const int z = (DIM == 3) ? 2 * ck + a - 1 : 0;
+    const bool okz = (z >= 0 && z <= f.N);
+    const int zc = z < 0 ? 0 : (z > f.N ? f.N : z);
+#pragma unroll
+    for (int bb = 0; bb < 3; bb++) {
+      const int y = 2 * cj + bb - 1;
+      ok[a][bb] = okz && (y >= 0 && y <= f.N);
+      const int yc = y < 0 ? 0 : (y > f.N ? f.N : y);
+      off[a][bb] = (int64_t)zc * f.plane + (int64_t)yc * f.nn;
+    }
+  }
+  T v[NZ][3][3];
+#pragma unroll
+  for (int a = 0; a < NZ; a++)
+#pragma unroll
+    for (int bb = 0; bb < 3; bb++)
+#pragma unroll
+      for (int d = 0; d < 3; d++) v[a][bb][d] = r[off[a][bb] + fi[d]];
   double s = 0.0;
-  for (int dk = -kz; dk <= kz; dk++) {
-    const int fk = 2 * ck + dk;
-    if (fk < 0 || fk > f.N) continue;
-    const double wk = dk ? 0.5 : 1.0;
-    for (int dj = -1; dj <= 1; dj++) {
-      const int fj = 2 * cj + dj;
-      if (fj < 0 || fj > f.N) continue;
-      const double wj = wk * (dj ? 0.5 : 1.0);
-      const T* fr = r + (int64_t)fk * f.plane + (int64_t)fj * f.nn;
-      for (int di = -1; di <= 1; di++) {
-        const int fi = 2 * ci + di;
-        if (fi < 0 || fi > f.N) continue;
-        s += wj * (di ? 0.5 : 1.0) * ld(fr + fi);
+#pragma unroll
+  for (int a = 0; a < NZ; a++) {
+    const double wk = (DIM == 3 && a != 1) ? 0.5 : 1.0;
+#pragma unroll
+    for (int bb = 0; bb < 3; bb++) {
+      const double wj = wk * (bb != 1 ? 0.5 : 1.0);
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        const double t = wj * (d != 1 ? 0.5 : 1.0) * ld(&v[a][bb][d]);
+        s += (ok[a][bb] && oki[d]) ? t : 0.0;
       }
     }
   }
@@ -72,35 +124,47 @@ __global__ void __launch_bounds__(256)
 template <int DIM, class T>
 __global__ void __launch_bounds__(256)
     k_prolong_add(Vec<const T> ecv, Vec<T> xv, Grid f, Grid c, Batch B, int per) {
-  const int inst = blockIdx.x / per;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int inst = lb / per;
   if (B.act && !B.act[inst]) return;
-  const unsigned q = (unsigned)(blockIdx.x - inst * per) * blockDim.x + threadIdx.x;
+  const unsigned q = (unsigned)(lb - inst * per) * blockDim.x + threadIdx.x;
   if (q >= (unsigned)f.nodes) return;
   int fi, fj, fk;
-  node_ijk<DIM>(q, (unsigned)f.nn, fi, fj, fk);
+  node_ijk<DIM>(q, f, fi, fj, fk);
   const T* __restrict__ ec = ecv.at(inst);
   T* __restrict__ x = xv.at(inst);
-  const int lo0 = fi >> 1, hi0 = (fi + 1) >> 1;
-  const int lo1 = fj >> 1, hi1 = (fj + 1) >> 1, lo2 = fk >> 1, hi2 = (fk + 1) >> 1;
-  const int nz = (DIM == 3) ? 2 : 1;
-  double s = 0.0;
-  for (int a = 0; a < nz; a++) {
-    const int K = a ? hi2 : lo2;
-    if (a && hi2 == lo2) continue;
-    const double wk = (DIM == 3 && hi2 != lo2) ? 0.5 : 1.0;
+  // coarse neighbours along each axis: one (even fine index, weight 1) or
+  // two (odd, weights 1/2); a single one is loaded twice and added once
+  const int I[2] = {fi >> 1, (fi + 1) >> 1};
+  const int J[2] = {fj >> 1, (fj + 1) >> 1};
+  const int K[2] = {fk >> 1, (fk + 1) >> 1};
+  const bool two_i = I[1] != I[0], two_j = J[1] != J[0], two_k = (DIM == 3) && K[1] != K[0];
+  constexpr int NZ = (DIM == 3) ? 2 : 1;
+  const T xo = x[q];
+  T v[NZ][2][2];
+#pragma unroll
+  for (int a = 0; a < NZ; a++)
+#pragma unroll
     for (int bb = 0; bb < 2; bb++) {
-      const int J = bb ? hi1 : lo1;
-      if (bb && hi1 == lo1) continue;
-      const double wj = wk * ((hi1 != lo1) ? 0.5 : 1.0);
-      const T* cr = ec + (int64_t)K * c.plane + (int64_t)J * c.nn;
-      for (int cc = 0; cc < 2; cc++) {
-        const int I = cc ? hi0 : lo0;
-        if (cc && hi0 == lo0) continue;
-        s += wj * ((hi0 != lo0) ? 0.5 : 1.0) * ld(cr + I);
-      }
+      const T* cr = ec + (int64_t)K[a] * c.plane + (int64_t)J[bb] * c.nn;
+#pragma unroll
+      for (int cc = 0; cc < 2; cc++) v[a][bb][cc] = cr[I[cc]];
     }
-  }
-  x[q] = (T)(ld(x + q) + s);
+  const double wk = two_k ? 0.5 : 1.0;
+  const double wj = wk * (two_j ? 0.5 : 1.0);
+  const double wi = two_i ? 0.5 : 1.0;
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < NZ; a++)
+#pragma unroll
+    for (int bb = 0; bb < 2; bb++)
+#pragma unroll
+      for (int cc = 0; cc < 2; cc++) {
+        const bool use = (a == 0 || two_k) && (bb == 0 || two_j) && (cc == 0 || two_i);
+        const double t = wj * wi * ld(&v[a][bb][cc]);
+        s += use ? t : 0.0;
+      }
+  x[q] = (T)(ld(&xo) + s);
 }
 
 constexpr int kCoarseMax = 1024;   // nodes of the coarse grid
@@ -223,7 +287,7 @@ __global__ void __launch_bounds__(256)
   const int nn = g.nn, N = g.N;
   const double alpha = bt.coef[inst].alpha;
   int k0, k1, k2;
-  node_ijk<DIM>(q, (unsigned)nn, k0, k1, k2);
+  node_ijk<DIM>(q, g, k0, k1, k2);
   auto mu = [&](int t) { return (g.h / 3.0) * (2.0 + cospi((double)t / (double)N)); };
   auto kap = [&](int t) { return (2.0 / g.h) * (1.0 - cospi((double)t / (double)N)); };
   auto gam = [&](int t) { return (t == 0 || t == N) ? (double)N : 0.5 * N; };

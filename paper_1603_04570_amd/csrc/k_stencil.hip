@@ -13,7 +13,7 @@
 // are formed from LDS and kept in registers for three consecutive planes, and
 // the z-direction 1D stencil combines them.  Every node is read once from HBM
 // per plane pass; the halo rows come from L2 because neighbouring chunks run
-// on the same XCD (see block_remap).
+// on the same XCD (see xcd_remap).
 #include "ok_internal.h"
 
 #include <algorithm>
@@ -21,6 +21,12 @@
 #include <mutex>
 #include <tuple>
 #include <type_traits>
+
+// Floating-point contraction is off in this file and every fused
+// multiply-add is written out (fma): the instantiations for every launch
+// shape and the fused two-iteration kernel then evaluate the same
+// expressions to the same bits, whatever the compiler's scheduling.
+#pragma clang fp contract(off)
 
 namespace okd {
 
@@ -32,30 +38,31 @@ Grid make_grid(int dim, int N) {
   g.plane = (int64_t)g.nn * g.nn;
   g.nodes = (dim == 3) ? g.plane * g.nn : g.plane;
   g.h = 1.0 / N;
+  g.rnn = 1.0 / g.nn;
   return g;
 }
 
 namespace {
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune;  // (dim, nn, nf, word) -> (items, zc)
+std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune;  // (dim, nn, nf, word) -> (items, nzc)
 }  // namespace
 
-void stencil_tune_set(int dim, int nn, int nf, int word, int items, int zc) {
+void stencil_tune_set(int dim, int nn, int nf, int word, int items, int nzc) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (items == 0)
     g_tune.erase(std::make_tuple(dim, nn, nf, word));
   else
-    g_tune[std::make_tuple(dim, nn, nf, word)] = std::make_pair(items, zc);
+    g_tune[std::make_tuple(dim, nn, nf, word)] = std::make_pair(items, nzc);
 }
 
-static StencilShape shape_with(const Grid& g, int items, int zc) {
+static StencilShape shape_with(const Grid& g, int items, int nzc) {
   StencilShape s;
   const int64_t plane = (g.dim == 3) ? g.plane : (int64_t)g.nn;
   s.items = items;
   s.chunk = kThreads * items;
   s.nchunks = (int)((plane + s.chunk - 1) / s.chunk);
-  s.zc = std::max(1, std::min(zc, g.nn));
-  s.nzc = (g.nn + s.zc - 1) / s.zc;
+  s.nzc = std::max(1, std::min(nzc, g.nn));
+  s.zc = (g.nn + s.nzc - 1) / s.nzc;
   s.blocks = s.nchunks * s.nzc;
   return s;
 }
@@ -90,22 +97,13 @@ StencilShape stencil_shape(const Grid& g, int nf, int word) {
   s.nchunks = (int)((plane + s.chunk - 1) / s.chunk);
   int64_t zc = ((int64_t)g.nn * s.nchunks) / target;
   zc = std::max<int64_t>(4, std::min<int64_t>(zc, 32));
-  s.zc = (int)std::min<int64_t>(zc, g.nn);
-  s.nzc = (g.nn + s.zc - 1) / s.zc;
+  zc = std::min<int64_t>(zc, g.nn);
+  s.nzc = (int)((g.nn + zc - 1) / zc);
+  s.zc = (g.nn + s.nzc - 1) / s.nzc;
   s.blocks = s.nchunks * s.nzc;
   return s;
 }
 
-
-// Hardware places block b on XCD b % 8.  Renumber blocks so that each XCD
-// receives a contiguous range of logical blocks (neighbouring chunks), which
-// keeps the halo rows of a chunk in that XCD's L2.
-__device__ __forceinline__ int block_remap(int b, int nb) {
-  int q = nb / 8, r = nb % 8;
-  int x = b % 8, t = b / 8;
-  int base = (x < r) ? x * (q + 1) : r * (q + 1) + (x - r) * q;
-  return base + t;
-}
 
 // 1D stencil patterns of node i on N elements (constants h/6, 1/h applied
 // later).  M pattern: [wl, 2(wl+wr), wr];  K pattern: [-wl, wl+wr, -wr].
@@ -144,6 +142,12 @@ __device__ __forceinline__ double k1_row(bool hl, bool hr, bool end, double l, d
   return fma(end ? 1.0 : 2.0, c, hl ? -l : 0.0) - (hr ? r : 0.0);
 }
 
+// a0 p0 + a1 p1 + a2 p2 (the 1D three-point stencil along one axis)
+__device__ __forceinline__ double sum3(double a0, double a1, double a2, double p0, double p1,
+                                       double p2) {
+  return fma(a2, p2, fma(a1, p1, a0 * p0));
+}
+
 // Epilogues of operators without stiffness (the Chebyshev iteration on M)
 // declare kMass = true; the streaming kernel then skips the K partials.
 template <class E, class = void>
@@ -179,7 +183,7 @@ __global__ void __launch_bounds__(kThreads)
   using In = typename Epi::In;
   constexpr bool MASS = MassOnly<Epi>::value;
   const int tid = threadIdx.x;
-  const int lb = block_remap(blockIdx.x, gridDim.x);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = lb / sh.blocks;
   if (B.act && !B.act[inst]) return;
   const int b = lb - inst * sh.blocks;
@@ -289,13 +293,13 @@ __global__ void __launch_bounds__(kThreads)
             for (int r = 0; r < 3; r++) {
               const int base = L + (r - 1) * nn;
               double va = lf[base - 1], vb = lf[base], vc = lf[base + 1];
-              mr[r] = ax0 * va + ax1 * vb + ax2 * vc;
-              kr[r] = bx0 * va + bx1 * vb + bx2 * vc;
+              mr[r] = sum3(ax0, ax1, ax2, va, vb, vc);
+              kr[r] = sum3(bx0, bx1, bx2, va, vb, vc);
             }
-            pm[f][p] = ay0 * mr[0] + ay1 * mr[1] + ay2 * mr[2];
+            pm[f][p] = sum3(ay0, ay1, ay2, mr[0], mr[1], mr[2]);
             pk[f][p] = MASS ? 0.0
-                            : ay0 * kr[0] + ay1 * kr[1] + ay2 * kr[2] + by0 * mr[0] +
-                                  by1 * mr[1] + by2 * mr[2];
+                            : sum3(ay0, ay1, ay2, kr[0], kr[1], kr[2]) +
+                                  sum3(by0, by1, by2, mr[0], mr[1], mr[2]);
             cen[f][p] = lf[L];
           }
         } else {
@@ -303,8 +307,8 @@ __global__ void __launch_bounds__(kThreads)
           for (int f = 0; f < NF; f++) {
             const double* lf = lds + f * ldsn;
             double va = lf[L - 1], vb = lf[L], vc = lf[L + 1];
-            pm[f][p] = ax0 * va + ax1 * vb + ax2 * vc;
-            pk[f][p] = MASS ? 0.0 : bx0 * va + bx1 * vb + bx2 * vc;
+            pm[f][p] = sum3(ax0, ax1, ax2, va, vb, vc);
+            pk[f][p] = MASS ? 0.0 : sum3(bx0, bx1, bx2, va, vb, vc);
             cen[f][p] = vb;
           }
         }
@@ -316,8 +320,8 @@ __global__ void __launch_bounds__(kThreads)
   const double h = g.h;
   const double cmass = (DIM == 3) ? h * h * h / 216.0 : h * h / 36.0;
   const double cstiff = (DIM == 3) ? h / 36.0 : 1.0 / 6.0;
-  const int z0 = zch * sh.zc;
-  const int z1 = min(z0 + sh.zc, nn);
+  int z0, z1;
+  zrange(sh, nn, zch, z0, z1);
   double pma[NF][P], pmb[NF][P], pka[NF][P], pkb[NF][P], cb[NF][P];
 #pragma unroll
   for (int f = 0; f < NF; f++)
@@ -363,10 +367,10 @@ __global__ void __launch_bounds__(kThreads)
         double ms[NF], ks[NF], cc[NF];
 #pragma unroll
         for (int f = 0; f < NF; f++) {
-          ms[f] = cmass * (az0 * pma[f][p] + az1 * pmb[f][p] + az2 * pmn[f][p]);
+          ms[f] = cmass * sum3(az0, az1, az2, pma[f][p], pmb[f][p], pmn[f][p]);
           ks[f] = MASS ? 0.0
-                       : cstiff * (az0 * pka[f][p] + az1 * pkb[f][p] + az2 * pkn[f][p] +
-                                   bz0 * pma[f][p] + bz1 * pmb[f][p] + bz2 * pmn[f][p]);
+                       : cstiff * (sum3(az0, az1, az2, pka[f][p], pkb[f][p], pkn[f][p]) +
+                                   sum3(bz0, bz1, bz2, pma[f][p], pmb[f][p], pmn[f][p]));
           cc[f] = cb[f][p];
         }
         int nb = (ii[p] == 0 || ii[p] == N) + nbz;
@@ -495,6 +499,16 @@ __device__ __forceinline__ OpK op_k(const InstCoef& C, int lev, int k, int osc) 
   return o;
 }
 
+// A s = cm (M s) + ck (K s) of a level operator, and the Chebyshev direction
+// c1 d + c2 D^-1 r (Saad, Alg. 12.1); shared by the one-iteration epilogues
+// and the fused two-iteration kernel.
+__device__ __forceinline__ double op_apply(const OpK& k, double ms, double ks) {
+  return fma(k.cm, ms, k.ck * ks);
+}
+__device__ __forceinline__ double cheb_dir(const OpK& k, double d, double dv, double r) {
+  return fma(k.c1, d, k.c2 * dv * r);
+}
+
 // out = add + a*(M s) + b*(K s)
 template <class TA, class TO>
 struct EpiAxpy {
@@ -514,7 +528,7 @@ struct EpiAxpy {
   }
   __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
                         const double*, const In& in, const K& k) const {
-    out.at(inst)[i] = (TO)(to_d(in.a) + k.a * ms[0] + k.b * ks[0]);
+    out.at(inst)[i] = (TO)fma(k.b, ks[0], fma(k.a, ms[0], to_d(in.a)));
   }
 };
 
@@ -541,11 +555,11 @@ struct EpiLin2 {
   }
   __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
                         const double*, const In& in, const K& k) const {
-    out0.at(inst)[i] =
-        (TO)(in.a + k.c[0][0] * ms[0] + k.c[0][1] * ks[0] + k.c[0][2] * ms[1] + k.c[0][3] * ks[1]);
+    out0.at(inst)[i] = (TO)fma(k.c[0][3], ks[1],
+                               fma(k.c[0][2], ms[1], fma(k.c[0][1], ks[0], fma(k.c[0][0], ms[0], in.a))));
     if (!out1.null())
-      out1.at(inst)[i] = (TO)(in.b + k.c[1][0] * ms[0] + k.c[1][1] * ks[0] + k.c[1][2] * ms[1] +
-                              k.c[1][3] * ks[1]);
+      out1.at(inst)[i] = (TO)fma(k.c[1][3], ks[1],
+                                 fma(k.c[1][2], ms[1], fma(k.c[1][1], ks[0], fma(k.c[1][0], ms[0], in.b))));
   }
 };
 
@@ -565,7 +579,7 @@ struct EpiCouple {
   __device__ In load(int inst, int64_t i) const { return In{g.at(inst)[i], r2.at(inst)[i]}; }
   __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
                         const double*, const In& in, const K& k) const {
-    const double q = in.a - ms[0] + k.e2 * ks[0];
+    const double q = fma(k.e2, ks[0], in.a - ms[0]);
     y.at(inst)[i] = (TY)(in.b + q);
     nq.at(inst)[i] = -q;
   }
@@ -588,7 +602,7 @@ struct EpiSchurRes {
   __device__ In load(int inst, int64_t i) const { return In{g.at(inst)[i], y.at(inst)[i]}; }
   __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
                         const double*, const In& in, const K& k) const {
-    const double sz = ms[1] + (in.a - ms[0] + k.e2 * ks[0]);
+    const double sz = ms[1] + fma(k.e2, ks[0], in.a - ms[0]);
     res.at(inst)[i] = (T)(to_d(in.b) - sz);
   }
 };
@@ -609,10 +623,10 @@ struct EpiChebFirst {
                         const double* cen, const In&, const K& k) const {
     const double bi = cen[0];
     double dv = dinv_at(k.dinv, nb);
-    double ad0 = k.dinv * k.it * (k.cm * ms[0] + k.ck * ks[0]);
+    double ad0 = k.dinv * k.it * op_apply(k, ms[0], ks[0]);
     double d0 = dv * bi * k.it;
     double r1 = bi - ad0;
-    double d1 = k.c1 * d0 + k.c2 * dv * r1;
+    double d1 = cheb_dir(k, d0, dv, r1);
     if (LAST) {
       x.at(inst)[i] = (T)(k.osc * (d0 + d1));
     } else {
@@ -642,8 +656,8 @@ struct EpiChebStep {
     const double dk = cen[0];
     double dv = dinv_at(kk.dinv, nb);
     double xv = to_d(in.a) + dk;
-    double rv = to_d(in.b) - (kk.cm * ms[0] + kk.ck * ks[0]);
-    double d1 = kk.c1 * dk + kk.c2 * dv * rv;
+    double rv = to_d(in.b) - op_apply(kk, ms[0], ks[0]);
+    double d1 = cheb_dir(kk, dk, dv, rv);
     if (LAST) {
       x.at(inst)[i] = (T)(kk.osc * (xv + d1));
     } else {
@@ -666,7 +680,7 @@ struct EpiChebStart {
   __device__ In load(int inst, int64_t i) const { return In{b.at(inst)[i]}; }
   __device__ void store(int inst, int64_t i, int nb, const double* ms, const double* ks,
                         const double*, const In& in, const K& k) const {
-    double r0 = to_d(in.a) - (k.cm * ms[0] + k.ck * ks[0]);
+    double r0 = to_d(in.a) - op_apply(k, ms[0], ks[0]);
     r.at(inst)[i] = (T)r0;
     d.at(inst)[i] = (T)(dinv_at(k.dinv, nb) * r0 * k.it);
   }
@@ -699,7 +713,7 @@ struct EpiResid {
   __device__ In load(int inst, int64_t i) const { return In{b.at(inst)[i]}; }
   __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
                         const double*, const In& in, const K& k) const {
-    r.at(inst)[i] = (T)(to_d(in.a) - (k.cm * ms[0] + k.ck * ks[0]));
+    r.at(inst)[i] = (T)(to_d(in.a) - op_apply(k, ms[0], ks[0]));
   }
 };
 
@@ -714,15 +728,16 @@ struct EpiResid {
 // final one (writes only x, scaled by osc).  r_k is read on the halo rows,
 // which other blocks own, so r_{k+2} goes to a second buffer (rout != rin).
 // LDS: d_k plane with a two-row halo (E2), d_{k+1} plane with a one-row halo
-// (E1), and two buffers each of r_{k+1} and d_k on the chunk.
+// (E1), and two buffers each of r_{k+1} and d_k on the chunk.  NT threads of
+// P nodes each cover a chunk; a larger chunk shortens the relative halo.
 // ---------------------------------------------------------------------------
-template <int DIM, int P, int P1, int FA, class T, bool LAST2>
-__global__ void __launch_bounds__(kThreads)
+template <int DIM, int NT, int P, int P1, int FA, class T, bool LAST2>
+__global__ void __launch_bounds__(NT)
     k_cheb2(Grid g, StencilShape sh, Batch B, int kk, int osc, Vec<T> xv, Vec<const T> rinv,
             Vec<T> routv, Vec<const T> dinv_, Vec<T> doutv) {
   extern __shared__ double lds[];
   const int tid = threadIdx.x;
-  const int lb = block_remap(blockIdx.x, gridDim.x);
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = lb / sh.blocks;
   if (B.act && !B.act[inst]) return;
   const int b = lb - inst * sh.blocks;
@@ -752,7 +767,7 @@ __global__ void __launch_bounds__(kThreads)
   bool v1[P1];
 #pragma unroll
   for (int q = 0; q < P1; q++) {
-    const int e = tid + kThreads * q;
+    const int e = tid + NT * q;
     const int64_t gq = s0 - H + e;
     v1[q] = (e < E1) && gq >= 0 && gq < plane;
     const int64_t gc = gq < 0 ? 0 : (gq >= plane ? plane - 1 : gq);
@@ -764,7 +779,7 @@ __global__ void __launch_bounds__(kThreads)
   bool v2[P];
 #pragma unroll
   for (int p = 0; p < P; p++) {
-    const int64_t gq = s0 + tid + kThreads * p;
+    const int64_t gq = s0 + tid + NT * p;
     v2[p] = gq < plane;
     const int64_t gc = gq < plane ? gq : plane - 1;
     j2[p] = (DIM == 3) ? (int)(gc / nn) : 0;
@@ -776,14 +791,14 @@ __global__ void __launch_bounds__(kThreads)
   T pa[FA], pr[P1], px[P];
   auto issue_a = [&](int64_t zoff) {
 #pragma unroll
-    for (int k = 0; k < FA; k++) pa[k] = din[zoff + clampq(s0 - 2 * H + tid + kThreads * k)];
+    for (int k = 0; k < FA; k++) pa[k] = din[zoff + clampq(s0 - 2 * H + tid + NT * k)];
   };
   auto issue_rx = [&](int zr, int zx) {
 #pragma unroll
     for (int q = 0; q < P1; q++)
-      pr[q] = r[(int64_t)zr * plane + clampq(s0 - H + tid + kThreads * q)];
+      pr[q] = r[(int64_t)zr * plane + clampq(s0 - H + tid + NT * q)];
 #pragma unroll
-    for (int p = 0; p < P; p++) px[p] = x[(int64_t)zx * plane + clampq(s0 + tid + kThreads * p)];
+    for (int p = 0; p < P; p++) px[p] = x[(int64_t)zx * plane + clampq(s0 + tid + NT * p)];
   };
   // in-plane mass partial (M1 x M1) v at LDS position L of buffer v (the
   // arithmetic of the one-iteration kernel)
@@ -804,8 +819,8 @@ __global__ void __launch_bounds__(kThreads)
 
   const double h = g.h;
   const double cmass = (DIM == 3) ? h * h * h / 216.0 : h * h / 36.0;
-  const int z0 = zch * sh.zc;
-  const int z1 = min(z0 + sh.zc, nn);
+  int z0, z1;
+  zrange(sh, nn, zch, z0, z1);
   const int zlast = min(z1 + 1, N);
   double pa1[P1], pb1[P1], cb1[P1];  // stage 1: partials of planes pz-2, pz-1; d_k(pz-1)
   double pa2[P], pb2[P], cb2[P];     // stage 2: partials of d_{k+1} planes pz-3, pz-2; d_{k+1}(pz-2)
@@ -824,7 +839,7 @@ __global__ void __launch_bounds__(kThreads)
     if (insideA) {
 #pragma unroll
       for (int k = 0; k < FA; k++) {
-        const int t = tid + kThreads * k;
+        const int t = tid + NT * k;
         const int64_t gq = s0 - 2 * H + t;
         if (t < E2) LA[t] = (gq >= 0 && gq < plane) ? to_d(pa[k]) : 0.0;
       }
@@ -842,8 +857,8 @@ __global__ void __launch_bounds__(kThreads)
     double pn1[P1], cn1[P1];
 #pragma unroll
     for (int q = 0; q < P1; q++) {
-      const int L = tid + kThreads * q + H;
-      const bool use = insideA && (tid + kThreads * q < E1);
+      const int L = tid + NT * q + H;
+      const bool use = insideA && (tid + NT * q < E1);
       pn1[q] = use ? mpart(LA, L, i1[q], j1[q]) : 0.0;
       cn1[q] = use ? LA[L] : 0.0;
     }
@@ -854,18 +869,18 @@ __global__ void __launch_bounds__(kThreads)
       const int nbz = (q1 == 0 || q1 == N);
 #pragma unroll
       for (int q = 0; q < P1; q++) {
-        const int e = tid + kThreads * q;
+        const int e = tid + NT * q;
         if (e >= E1) continue;
         double d1 = 0.0;
         if (inq && v1[q]) {
-          const double ms = cmass * (az0 * pa1[q] + az1 * pb1[q] + az2 * pn1[q]);
+          const double ms = cmass * sum3(az0, az1, az2, pa1[q], pb1[q], pn1[q]);
           const double dk = cb1[q];
           int nb = (i1[q] == 0 || i1[q] == N) + nbz;
           if (DIM == 3) nb += (j1[q] == 0 || j1[q] == N);
           const double dv = dinv_at(ka.dinv, nb);
-          const double ru = to_d(rq[q]) - ka.cm * ms;
+          const double ru = to_d(rq[q]) - op_apply(ka, ms, 0.0);
           const double rv1 = to_d((T)ru);
-          d1 = to_d((T)(ka.c1 * dk + ka.c2 * dv * ru));
+          d1 = to_d((T)cheb_dir(ka, dk, dv, ru));
           const int c = e - H;
           if (c >= 0 && c < CH) {
             LR[buf * CH + c] = rv1;
@@ -887,7 +902,7 @@ __global__ void __launch_bounds__(kThreads)
       double pn2[P], cn2[P];
 #pragma unroll
       for (int p = 0; p < P; p++) {
-        const int L = tid + kThreads * p + H;
+        const int L = tid + NT * p + H;
         pn2[p] = mpart(LB, L, i2[p], j2[p]);
         cn2[p] = LB[L];
       }
@@ -899,8 +914,8 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
         for (int p = 0; p < P; p++) {
           if (!v2[p]) continue;
-          const int c = tid + kThreads * p;
-          const double ms = cmass * (az0 * pa2[p] + az1 * pb2[p] + az2 * pn2[p]);
+          const int c = tid + NT * p;
+          const double ms = cmass * sum3(az0, az1, az2, pa2[p], pb2[p], pn2[p]);
           const double d1 = cb2[p];
           const double rv1 = LR[pb * CH + c];
           const double dk = LD[pb * CH + c];
@@ -909,8 +924,8 @@ __global__ void __launch_bounds__(kThreads)
           const double dv = dinv_at(kb.dinv, nb);
           const double xv1 = to_d((T)(to_d(xq[p]) + dk));
           const double xv2 = xv1 + d1;
-          const double rv2 = rv1 - kb.cm * ms;
-          const double d2 = kb.c1 * d1 + kb.c2 * dv * rv2;
+          const double rv2 = rv1 - op_apply(kb, ms, 0.0);
+          const double d2 = cheb_dir(kb, d1, dv, rv2);
           const int64_t idx = (int64_t)o * plane + s0 + c;
           if (LAST2) {
             x[idx] = (T)(kb.osc * (xv2 + d2));
@@ -1036,33 +1051,62 @@ hipError_t launch_cheb_step(const Grid& g, const Batch& B, int lev, int k, int o
 namespace {
 int g_fuse_cheb = 1;
 
-template <int DIM, int P, int EX1, int EXA, class T>
+template <int DIM, int NT, int P, int EX1, int EXA, class T>
 hipError_t launch_cheb2_p(const Grid& g, const Batch& B, const StencilShape& sh, int k, int osc,
                           bool last2, Vec<T> x, Vec<const T> r, Vec<T> rout, Vec<const T> din,
                           Vec<T> dout, hipStream_t st) {
   const int H = (DIM == 3) ? g.nn + 1 : 1;
+  if (sh.chunk != NT * P) return hipErrorInvalidValue;
   const size_t lds = (size_t)(sh.chunk + 4 * H + sh.chunk + 2 * H + 4 * sh.chunk) * sizeof(double);
   if (lds > 65536) return hipErrorInvalidValue;
   const int64_t nblk = (int64_t)sh.blocks * B.count;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  dim3 grid((unsigned)nblk), block(kThreads);
+  dim3 grid((unsigned)nblk), block(NT);
   if (last2)
-    hipLaunchKernelGGL((k_cheb2<DIM, P, P + EX1, P + EXA, T, true>), grid, block, lds, st, g, sh,
-                       B, k, osc, x, r, rout, din, dout);
-  else
-    hipLaunchKernelGGL((k_cheb2<DIM, P, P + EX1, P + EXA, T, false>), grid, block, lds, st, g,
+    hipLaunchKernelGGL((k_cheb2<DIM, NT, P, P + EX1, P + EXA, T, true>), grid, block, lds, st, g,
                        sh, B, k, osc, x, r, rout, din, dout);
+  else
+    hipLaunchKernelGGL((k_cheb2<DIM, NT, P, P + EX1, P + EXA, T, false>), grid, block, lds, st,
+                       g, sh, B, k, osc, x, r, rout, din, dout);
   return hipGetLastError();
 }
 
-template <int DIM, int EX1, int EXA, class T>
-hipError_t launch_cheb2_ex(const Grid& g, const Batch& B, const StencilShape& sh, int k, int osc,
-                           bool last2, Vec<T> x, Vec<const T> r, Vec<T> rout, Vec<const T> din,
-                           Vec<T> dout, hipStream_t st) {
-  if (sh.items == 1)
-    return launch_cheb2_p<DIM, 1, EX1, EXA, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout,
-                                               st);
-  return launch_cheb2_p<DIM, 2, EX1, EXA, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
+// Launch geometry of the fused kernel for a shape's item count: 1 and 2 are
+// 256 threads of 1 or 2 nodes, 4 is 512 threads of 2 nodes.  ex1 and exa are
+// the extra per-thread slots of the one- and two-row halos.
+struct Cheb2Geom {
+  int nt, p, ex1, exa;
+};
+Cheb2Geom cheb2_geom(const Grid& g, int items) {
+  Cheb2Geom c;
+  c.nt = items >= 4 ? 512 : 256;
+  c.p = items >= 2 ? 2 : 1;
+  const int H = (g.dim == 3) ? g.nn + 1 : 1;
+  c.ex1 = (2 * H + c.nt - 1) / c.nt;
+  c.exa = (4 * H + c.nt - 1) / c.nt;
+  return c;
+}
+
+template <int DIM, int NT, int P, class T>
+hipError_t launch_cheb2_ex(const Grid& g, const Batch& B, const StencilShape& sh,
+                           const Cheb2Geom& c, int k, int osc, bool last2, Vec<T> x,
+                           Vec<const T> r, Vec<T> rout, Vec<const T> din, Vec<T> dout,
+                           hipStream_t st) {
+#define OK_CHEB2(E1, EA)                                                                       \
+  if (c.ex1 == E1 && c.exa == EA)                                                              \
+    return launch_cheb2_p<DIM, NT, P, E1, EA, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, \
+                                                 st);
+  if (DIM == 2) {
+    OK_CHEB2(1, 1)
+    return hipErrorInvalidValue;
+  }
+  OK_CHEB2(1, 1)
+  OK_CHEB2(1, 2)
+  OK_CHEB2(2, 3)
+  OK_CHEB2(3, 5)
+  OK_CHEB2(5, 9)
+#undef OK_CHEB2
+  return hipErrorInvalidValue;
 }
 }  // namespace
 
@@ -1077,13 +1121,13 @@ bool cheb_fusion_on(const Grid& g, int word) {
     if (it != g_tune.end() && it->second.first < 0) return false;
   }
   StencilShape sh = stencil_shape(g, kFusedKey, word);
-  const int items = sh.items > 2 ? 2 : sh.items;
+  const Cheb2Geom c = cheb2_geom(g, sh.items);
+  if (g.dim == 2 && c.nt != 256) return false;
   const int H = (g.dim == 3) ? g.nn + 1 : 1;
-  const int ex1 = (2 * H + kThreads - 1) / kThreads, exa = (4 * H + kThreads - 1) / kThreads;
-  const bool combo = (g.dim == 2) ? (ex1 == 1 && exa == 1)
-                                  : ((ex1 == 1 && exa <= 2) || (ex1 == 2 && exa == 3) ||
-                                     (ex1 == 3 && exa == 5) || (ex1 == 5 && exa == 9));
-  const int ch = kThreads * items;
+  const bool combo = (g.dim == 2) ? (c.ex1 == 1 && c.exa == 1)
+                                  : ((c.ex1 == 1 && c.exa <= 2) || (c.ex1 == 2 && c.exa == 3) ||
+                                     (c.ex1 == 3 && c.exa == 5) || (c.ex1 == 5 && c.exa == 9));
+  const int ch = c.nt * c.p;
   return combo && (size_t)(6 * ch + 6 * H) * sizeof(double) <= 65536;
 }
 
@@ -1094,24 +1138,20 @@ hipError_t launch_cheb_step2(const Grid& g, const Batch& B, int k, int osc, bool
   if (k < 0 || k + 1 >= kMaxCheb || B.count < 1) return hipErrorInvalidValue;
   if (!last2 && (rout.p == r.p || rout.null())) return hipErrorInvalidValue;
   StencilShape sh = stencil_shape(g, kFusedKey, (int)sizeof(T));
-  if (sh.items > 2) sh = shape_with(g, 2, sh.zc);
-  const int H = (g.dim == 3) ? g.nn + 1 : 1;
-  const int ex1 = (2 * H + kThreads - 1) / kThreads, exa = (4 * H + kThreads - 1) / kThreads;
+  if (sh.items > 4) sh = shape_with(g, 4, sh.nzc);
+  if (sh.items == 3) sh = shape_with(g, 2, sh.nzc);
+  const Cheb2Geom c = cheb2_geom(g, sh.items);
   if (g.dim == 2) {
-    if (ex1 != 1 || exa != 1) return hipErrorInvalidValue;
-    return launch_cheb2_ex<2, 1, 1, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
+    if (c.nt != 256) return hipErrorInvalidValue;
+    if (c.p == 1)
+      return launch_cheb2_ex<2, 256, 1, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
+    return launch_cheb2_ex<2, 256, 2, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
   }
-  if (ex1 == 1 && exa == 1)
-    return launch_cheb2_ex<3, 1, 1, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
-  if (ex1 == 1 && exa == 2)
-    return launch_cheb2_ex<3, 1, 2, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
-  if (ex1 == 2 && exa == 3)
-    return launch_cheb2_ex<3, 2, 3, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
-  if (ex1 == 3 && exa == 5)
-    return launch_cheb2_ex<3, 3, 5, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
-  if (ex1 == 5 && exa == 9)
-    return launch_cheb2_ex<3, 5, 9, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, st);
-  return hipErrorInvalidValue;
+  if (c.nt == 512)
+    return launch_cheb2_ex<3, 512, 2, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
+  if (c.p == 1)
+    return launch_cheb2_ex<3, 256, 1, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
+  return launch_cheb2_ex<3, 256, 2, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
 }
 
 template <class T>

@@ -34,6 +34,7 @@ struct Grid {
   int64_t plane;  // nodes per z-plane (nn*nn); the whole grid in 2D
   int64_t nodes;  // nn^dim
   double h;       // 1/N
+  double rnn;     // 1/nn, for index decompositions without integer division
 };
 Grid make_grid(int dim, int N);
 
@@ -99,10 +100,25 @@ struct StencilShape {
   int items;    // nodes per thread per plane (1,2,4,8)
   int chunk;    // nodes per block per plane (kThreads*items)
   int nchunks;  // chunks per plane
-  int zc;       // planes per block
-  int nzc;      // z-chunks
+  int zc;       // most planes of a block: ceil(nn/nzc)
+  int nzc;      // z-chunks; chunk c owns planes [c*nn/nzc, (c+1)*nn/nzc)
   int blocks;   // nchunks*nzc (per instance)
 };
+// Hardware places block b on XCD b % 8.  xcd_remap renumbers blocks so that
+// each XCD receives a contiguous range of logical blocks (neighbouring
+// tiles), which keeps the halo rows shared by neighbours in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb / 8, r = nb % 8;
+  const int x = b % 8, t = b / 8;
+  return ((x < r) ? x * (q + 1) : r * (q + 1) + (x - r) * q) + t;
+}
+
+// Planes [z0, z1) of z-chunk zch: the nn planes split as evenly as possible,
+// so no block is left with a short remainder.
+__device__ __forceinline__ void zrange(const StencilShape& sh, int nn, int zch, int& z0, int& z1) {
+  z0 = (int)(((int64_t)zch * nn) / sh.nzc);
+  z1 = (int)(((int64_t)(zch + 1) * nn) / sh.nzc);
+}
 StencilShape stencil_shape(const Grid& g, int nf, int word);
 // Shape-table key of the fused two-iteration Chebyshev kernel (in place of nf).
 constexpr int kFusedKey = 17;
@@ -110,7 +126,7 @@ constexpr int kFusedKey = 17;
 // direction, stenciled fields, bytes per stenciled word); items < 0 marks the
 // fused Chebyshev kernel as slower than single steps on that grid; items == 0 removes
 // the entry (back to the heuristic).  Results do not depend on the shape.
-void stencil_tune_set(int dim, int nn, int nf, int word, int items, int zc);
+void stencil_tune_set(int dim, int nn, int nf, int word, int items, int nzc);
 
 // Reduction blocks per instance for vectors of length n (a fixed function of
 // n, so solo and batched runs sum in the same order).

@@ -3,6 +3,10 @@
     python -m paper_1603_04570_amd.profsum stats KERNEL_STATS_CSV [TOP]
         per-kernel totals from ``--kernel-trace --stats`` (kt_kernel_stats.csv)
 
+    python -m paper_1603_04570_amd.profsum bygrid KERNEL_TRACE_CSV [TOP]
+        per (kernel, grid size) totals from ``--kernel-trace`` (kt_kernel_trace.csv):
+        separates the multigrid levels and the grids of one kernel template
+
     python -m paper_1603_04570_amd.profsum traffic --fetch F.csv --write W.csv \
         --copy-fetch CF.csv --copy-write CW.csv --copy-bytes BYTES --kernel SUBSTRING \
         [--kernel SUBSTRING ...] [--main-grid]
@@ -37,6 +41,23 @@ def stats(path: str, top: int = 25) -> str:
         t = float(r["TotalDurationNs"])
         out.append(f"{t / 1e6:9.3f} {100 * t / tot:5.1f} {int(r['Calls']):6d} "
                    f"{float(r['AverageNs']) / 1e3:9.2f}  {short_name(r['Name'])}")
+    return "\n".join(out)
+
+
+def bygrid(path: str, top: int = 40) -> str:
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        g = int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0)
+        t = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        k = (r["Kernel_Name"], g)
+        n, s = acc.get(k, (0, 0))
+        acc[k] = (n + 1, s + t)
+    tot = sum(s for _, s in acc.values())
+    out = [f"total kernel time {tot / 1e6:.2f} ms over {sum(n for n, _ in acc.values())} "
+           f"dispatches", f"{'ms':>9} {'%':>5} {'calls':>6} {'avg us':>9} {'grid':>9}  kernel"]
+    for (name, g), (n, s) in sorted(acc.items(), key=lambda kv: -kv[1][1])[:top]:
+        out.append(f"{s / 1e6:9.3f} {100 * s / tot:5.1f} {n:6d} {s / n / 1e3:9.2f} {g:9d}  "
+                   f"{short_name(name, 100)}")
     return "\n".join(out)
 
 
@@ -89,6 +110,9 @@ def main():
     a = sub.add_parser("stats")
     a.add_argument("csv")
     a.add_argument("top", nargs="?", type=int, default=25)
+    c = sub.add_parser("bygrid")
+    c.add_argument("csv")
+    c.add_argument("top", nargs="?", type=int, default=40)
     b = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy-fetch", "copy-write"):
         b.add_argument("--" + k, required=True)
@@ -98,6 +122,8 @@ def main():
     args = ap.parse_args()
     if args.cmd == "stats":
         print(stats(args.csv, args.top))
+    elif args.cmd == "bygrid":
+        print(bygrid(args.csv, args.top))
     else:
         r = traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.copy_bytes,
                     args.kernel, args.main_grid)

@@ -103,3 +103,22 @@ def test_null_context_calls(lib):
     assert lib.ok_destroy(None) == -1
     assert lib.ok_jacobian_apply(None, None, None, None, None) == -1
     assert lib.ok_timestep(None, None, None, 1, None, None) == -1
+
+
+def test_launch_shape_arguments(lib):
+    """ok_set_launch_shape only edits the host-side shape table: argument
+    checks run without a GPU."""
+    E = -1  # OK_E_INVALID
+    assert lib.ok_set_launch_shape(3, 64, 1, 0, 4, 5) == 0
+    assert lib.ok_set_launch_shape(3, 64, 1, 0, 0, 0) == 0       # clear
+    assert lib.ok_set_launch_shape(3, 64, 3, 1, 4, 65) == 0      # 512-thread fused pair
+    assert lib.ok_set_launch_shape(3, 64, 3, 1, 0, 0) == 0
+    assert lib.ok_set_launch_shape(4, 64, 1, 0, 4, 5) == E       # dim
+    assert lib.ok_set_launch_shape(3, 0, 1, 0, 4, 5) == E        # n
+    assert lib.ok_set_launch_shape(3, 64, 9, 0, 4, 5) == E       # kernel
+    assert lib.ok_set_launch_shape(3, 64, 1, 2, 4, 5) == E       # precision
+    assert lib.ok_set_launch_shape(3, 64, 1, 0, 3, 5) == E       # items
+    assert lib.ok_set_launch_shape(3, 64, 2, 0, 8, 5) == E       # two-field: at most 4
+    assert lib.ok_set_launch_shape(2, 64, 3, 0, 4, 5) == E       # 512-thread pair is 3D only
+    assert lib.ok_set_launch_shape(3, 64, 1, 0, 4, 0) == E       # zchunks
+    assert lib.ok_set_launch_shape(3, 64, 1, 0, 4, 66) == E

@@ -1,0 +1,83 @@
+"""Launch shapes of the streaming stencil kernels (ok_set_launch_shape).
+
+Every node's arithmetic is the same whatever the shape, so results must be
+bitwise equal for every item count per thread, for 256- and 512-thread
+fused blocks, and for every split of the planes into z-ranges (one range,
+uneven ranges, one plane per range).
+"""
+import numpy as np
+import pytest
+
+from paper_1603_04570_amd.inputs import noise_state, uniform01
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def cheb_mass(P, r, nodes):
+    x = torch.empty(nodes, dtype=torch.float64, device="cuda")
+    P.cheb_mass(r, x)
+    torch.cuda.synchronize()
+    return x.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("dim,n", [(2, 256), (3, 64), (3, 128), (3, 256)])
+def test_fused_chebyshev_shapes_bitwise(dim, n, precision):
+    from paper_1603_04570_amd import ok
+    p = ok.default_params(dim=dim, n=n, precision=precision)
+    P = ok.Problem(p)
+    nodes = (n + 1) ** dim
+    r = torch.from_numpy(uniform01(23 + n, nodes) - 0.5).cuda()
+    ok.set_option(ok.OK_OPT_FUSE_CHEB, 0)
+    try:
+        ref = cheb_mass(P, r, nodes)
+    finally:
+        ok.set_option(ok.OK_OPT_FUSE_CHEB, 1)
+    items_list = (1, 2, 4) if dim == 3 else (1, 2)
+    try:
+        for items in items_list:
+            for zch in (1, 3, 7, n + 1):
+                print("fused shape", dim, n, precision, items, zch, flush=True)
+                ok.set_launch_shape(dim, n, ok.OK_SHAPE_CHEB2, precision, items, zch)
+                assert np.array_equal(cheb_mass(P, r, nodes), ref), (items, zch)
+    finally:
+        ok.set_launch_shape(dim, n, ok.OK_SHAPE_CHEB2, precision, 0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_stencil_shapes_timestep_bitwise(precision):
+    """A 3D 32^3 timestep (every stencil kernel of the path) with the one- and
+    two-field stencil shapes of the two finest levels pinned to each item
+    count and several z-splits."""
+    from paper_1603_04570_amd import ok
+    dim, n = 3, 32
+    p = ok.default_params(dim=dim, n=n, eps=0.02, sigma=100.0, m=0.1, dt=2e-4,
+                          precision=precision)
+    u0, w0 = noise_state(dim, n, 0.1, 17)
+
+    def once():
+        P = ok.Problem(p)
+        u = torch.from_numpy(u0).cuda()
+        w = torch.from_numpy(w0).cuda()
+        st = P.timestep(u, w, 1)
+        return u.cpu().numpy(), w.cpu().numpy(), st.its()
+
+    ref = once()
+    try:
+        for items, zch in [(1, 1), (2, 4), (4, 33), (8, 5), (8, 1)]:
+            print("stencil shape", precision, items, zch, flush=True)
+            for lev_n in (n, n // 2):
+                for word in (0, 1):  # FP64 and FP32 storage entries
+                    ok.set_launch_shape(dim, lev_n, ok.OK_SHAPE_STENCIL, word, items,
+                                        min(zch, lev_n + 1))
+                    ok.set_launch_shape(dim, lev_n, ok.OK_SHAPE_STENCIL2, word, min(items, 4),
+                                        min(zch, lev_n + 1))
+            got = once()
+            assert got[2] == ref[2]
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (items, zch)
+    finally:
+        for lev_n in (n, n // 2):
+            for word in (0, 1):
+                ok.set_launch_shape(dim, lev_n, ok.OK_SHAPE_STENCIL, word, 0)
+                ok.set_launch_shape(dim, lev_n, ok.OK_SHAPE_STENCIL2, word, 0)
