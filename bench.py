@@ -51,8 +51,8 @@ K_CHEB_MASS, K_KRYLOV = 1, 5
 KERNELS = {
     K_KRYLOV: ("mgs", "fused modified Gram-Schmidt step + dot products of FGMRES (k_mgs, k_dot)",
                ("paper_1603_04570_amd/csrc/k_krylov.hip", "paper_1603_04570_amd/csrc/ok_internal.h")),
-    K_CHEB_MASS: ("cheb_step", "Chebyshev-Jacobi iteration on M (k_stencil, EpiChebStep)",
-                  ("paper_1603_04570_amd/csrc/k_stencil.hip",
+    K_CHEB_MASS: ("cheb_step", "Chebyshev-Jacobi iterations on M (k_cheb2 pairs, k_stencil EpiChebStep)",
+                  ("paper_1603_04570_amd/csrc/k_stencil_impl.h",
                    "paper_1603_04570_amd/csrc/ok_internal.h")),
 }
 

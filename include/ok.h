@@ -229,9 +229,11 @@ int ok_set_option(int32_t option, int32_t value);
  *     mass/stiffness pairs of residual and Jacobian), OK_SHAPE_CHEB2 (two
  *     fused Chebyshev iterations on M);
  *   precision: OK_FP64 or OK_MIXED (the preconditioner's storage type);
- *   items: nodes per thread per plane, 1, 2, 4 or 8 (STENCIL2: 1, 2, 4;
- *     CHEB2: 1 or 2 with 256 threads, 4 = 512 threads of 2 nodes); 0 removes
- *     the entry (built-in default shape);
+ *   items, threads: a block of `threads` threads covers items*threads nodes
+ *     of a plane.  STENCIL: 256 threads of 1, 2, 4 or 8 nodes, in 3D also 512
+ *     threads of 1, 2 or 4; STENCIL2: 256 threads of 1, 2 or 4; CHEB2: 256
+ *     threads (3D also 512) of 1 or 2.  items = 0 removes the entry (built-in
+ *     default shape; threads and zchunks are then ignored);
  *   zchunks: the n+1 planes of the streaming axis are split evenly into
  *     1..n+1 ranges, one block per (plane chunk, range).
  * Every node's arithmetic is the same for every shape, so results are
@@ -240,7 +242,7 @@ int ok_set_option(int32_t option, int32_t value);
  * OK_E_INVALID for an argument out of range. */
 enum ok_shape_kernel { OK_SHAPE_STENCIL = 1, OK_SHAPE_STENCIL2 = 2, OK_SHAPE_CHEB2 = 3 };
 int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precision, int32_t items,
-                        int32_t zchunks);
+                        int32_t threads, int32_t zchunks);
 
 /* Launch mode of the FGMRES iterations.  enable != 0: the context gets a HIP
  * stream of its own (default priority) and captures each Arnoldi iteration j

@@ -1127,9 +1127,9 @@ double time_best(hipStream_t st, F&& launch) {
 // Candidate z-chunk counts of a streaming stencil launch: chunks of 4 to 32
 // planes, and the counts that make the whole grid (all instances) about
 // 512 ... 6144 blocks, i.e. one or a few full rounds of resident blocks.
-std::vector<int> zchunk_candidates(const Grid& g, int items, int count) {
+std::vector<int> zchunk_candidates(const Grid& g, int chunk, int count) {
   const int64_t plane = (g.dim == 3) ? g.plane : (int64_t)g.nn;
-  const int64_t nch = (plane + 256 * items - 1) / (256 * items);
+  const int64_t nch = (plane + chunk - 1) / chunk;
   std::vector<int> v;
   for (int zc : {4, 8, 16, 32}) v.push_back((g.nn + zc - 1) / zc);
   for (int64_t t : {512, 1024, 2048, 3072, 4096, 6144}) v.push_back((int)(t / (nch * count)));
@@ -1155,20 +1155,24 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
       d0 = pvec<P>(c.mg[l][3], nl); d1 = pvec<P>(c.mg[l][4], nl);
     }
     double best = 1e30;
-    int bi = 0, bz = 0;
-    for (int items = 1; items <= 8; items *= 2)
-      for (int zc : zchunk_candidates(g, items, B.count)) {
-        stencil_tune_set(g.dim, g.nn, 1, word, items, zc);
-        double t = time_best(st, [&]() {
-          return launch_cheb_step<P>(g, B, l, 0, CF_ONE, false, x, r, cst(d0), d1, st);
-        });
-        if (t < best) {
-          best = t;
-          bi = items;
-          bz = zc;
+    int bi = 0, bz = 0, bt = 256;
+    for (int threads : {256, 512})
+      for (int items = 1; items <= 8; items *= 2) {
+        if (!stencil_shape_ok(g.dim, 1, items, threads)) continue;
+        for (int zc : zchunk_candidates(g, items * threads, B.count)) {
+          stencil_tune_set(g.dim, g.nn, 1, word, items, zc, threads);
+          double t = time_best(st, [&]() {
+            return launch_cheb_step<P>(g, B, l, 0, CF_ONE, false, x, r, cst(d0), d1, st);
+          });
+          if (t < best) {
+            best = t;
+            bi = items;
+            bz = zc;
+            bt = threads;
+          }
         }
       }
-    stencil_tune_set(g.dim, g.nn, 1, word, bi, bz);
+    stencil_tune_set(g.dim, g.nn, 1, word, bi, bz, bt);
     if (bi) (*entries)++;
   }
   stencil_tune_set(c.lev[0].dim, c.lev[0].nn, kFusedKey, word, 0, 0);
@@ -1178,19 +1182,23 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
     Vec<P> x = pvec<P>(c.yv, nl), r = pvec<P>(c.cr, nl), d0 = pvec<P>(c.cda, nl),
            d1 = pvec<P>(c.cdb, nl);
     double best = 1e30;
-    int bi = 0, bz = 0;
-    for (int items = 1; items <= 4; items *= 2)
-      for (int zc : zchunk_candidates(g, items, B.count)) {
-        stencil_tune_set(g.dim, g.nn, kFusedKey, word, items, zc);
-        if (!cheb_fusion_on(g, word)) continue;
-        double t = time_best(st, [&]() {
-          return launch_cheb_step2<P>(g, B, 1, CF_ONE, false, x, cst(r), pvec<P>(c.cr2, nl),
-                                      cst(d0), d1, st);
-        });
-        if (t < best) {
-          best = t;
-          bi = items;
-          bz = zc;
+    int bi = 0, bz = 0, bt = 256;
+    for (int threads : {256, 512})
+      for (int items = 1; items <= 2; items++) {
+        if (!cheb2_shape_ok(g.dim, items, threads)) continue;
+        for (int zc : zchunk_candidates(g, items * threads, B.count)) {
+          stencil_tune_set(g.dim, g.nn, kFusedKey, word, items, zc, threads);
+          if (!cheb_fusion_on(g, word)) continue;
+          double t = time_best(st, [&]() {
+            return launch_cheb_step2<P>(g, B, 1, CF_ONE, false, x, cst(r), pvec<P>(c.cr2, nl),
+                                        cst(d0), d1, st);
+          });
+          if (t < best) {
+            best = t;
+            bi = items;
+            bz = zc;
+            bt = threads;
+          }
         }
       }
     // keep the fusion only where a pair beats two single iterations on M
@@ -1201,7 +1209,7 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
       return e;
     });
     if (bi && best < single)
-      stencil_tune_set(g.dim, g.nn, kFusedKey, word, bi, bz);
+      stencil_tune_set(g.dim, g.nn, kFusedKey, word, bi, bz, bt);
     else
       stencil_tune_set(g.dim, g.nn, kFusedKey, word, -1, 0);
     (*entries)++;
@@ -1214,7 +1222,7 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
     double best = 1e30;
     int bi = 0, bz = 0;
     for (int items = 1; items <= 4; items *= 2)
-      for (int zc : zchunk_candidates(g, items, B.count)) {
+      for (int zc : zchunk_candidates(g, items * 256, B.count)) {
         stencil_tune_set(g.dim, g.nn, 2, word, items, zc);
         double t = time_best(st, [&]() {
           return launch_stencil_lin2<P>(g, B, z, off(z, c.n), Vec<const double>{nullptr, 0},

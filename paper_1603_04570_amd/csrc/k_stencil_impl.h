@@ -14,6 +14,12 @@
 // the z-direction 1D stencil combines them.  Every node is read once from HBM
 // per plane pass; the halo rows come from L2 because neighbouring chunks run
 // on the same XCD (see xcd_remap).
+// This file is compiled twice (k_stencil_f64.hip, k_stencil_f32.hip) with
+// OKD_STENCIL_PART 0 (host tables and FP64 kernels) and 1 (FP32 and mixed
+// kernels), so that the two halves build in parallel.
+#ifndef OKD_STENCIL_PART
+#error "define OKD_STENCIL_PART (0 or 1) before including k_stencil_impl.h"
+#endif
 #include "ok_internal.h"
 
 #include <algorithm>
@@ -30,6 +36,7 @@
 
 namespace okd {
 
+#if OKD_STENCIL_PART == 0
 Grid make_grid(int dim, int N) {
   Grid g;
   g.dim = dim;
@@ -44,22 +51,24 @@ Grid make_grid(int dim, int N) {
 
 namespace {
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune;  // (dim, nn, nf, word) -> (items, nzc)
+// (dim, nn, nf, word) -> (items, nzc, threads)
+std::map<std::tuple<int, int, int, int>, std::tuple<int, int, int>> g_tune;
 }  // namespace
 
-void stencil_tune_set(int dim, int nn, int nf, int word, int items, int nzc) {
+void stencil_tune_set(int dim, int nn, int nf, int word, int items, int nzc, int threads) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (items == 0)
     g_tune.erase(std::make_tuple(dim, nn, nf, word));
   else
-    g_tune[std::make_tuple(dim, nn, nf, word)] = std::make_pair(items, nzc);
+    g_tune[std::make_tuple(dim, nn, nf, word)] = std::make_tuple(items, nzc, threads);
 }
 
-static StencilShape shape_with(const Grid& g, int items, int nzc) {
+static StencilShape shape_with(const Grid& g, int items, int nzc, int threads = kThreads) {
   StencilShape s;
   const int64_t plane = (g.dim == 3) ? g.plane : (int64_t)g.nn;
   s.items = items;
-  s.chunk = kThreads * items;
+  s.threads = threads;
+  s.chunk = threads * items;
   s.nchunks = (int)((plane + s.chunk - 1) / s.chunk);
   s.nzc = std::max(1, std::min(nzc, g.nn));
   s.zc = (g.nn + s.nzc - 1) / s.nzc;
@@ -78,8 +87,9 @@ StencilShape stencil_shape(const Grid& g, int nf, int word) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(std::make_tuple(g.dim, g.nn, nf, word));
-    if (it != g_tune.end() && it->second.first > 0)
-      return shape_with(g, it->second.first, it->second.second);
+    if (it != g_tune.end() && std::get<0>(it->second) > 0)
+      return shape_with(g, std::get<0>(it->second), std::get<1>(it->second),
+                        std::get<2>(it->second));
   }
   StencilShape s;
   const int target = 1024;
@@ -93,6 +103,7 @@ StencilShape stencil_shape(const Grid& g, int nf, int word) {
     if (nch * ((g.nn + 7) / 8) >= target) break;
   }
   s.items = items;
+  s.threads = kThreads;
   s.chunk = kThreads * items;
   s.nchunks = (int)((plane + s.chunk - 1) / s.chunk);
   int64_t zc = ((int64_t)g.nn * s.nchunks) / target;
@@ -103,7 +114,7 @@ StencilShape stencil_shape(const Grid& g, int nf, int word) {
   s.blocks = s.nchunks * s.nzc;
   return s;
 }
-
+#endif  // OKD_STENCIL_PART == 0
 
 // 1D stencil patterns of node i on N elements (constants h/6, 1/h applied
 // later).  M pattern: [wl, 2(wl+wr), wr];  K pattern: [-wl, wl+wr, -wr].
@@ -176,8 +187,8 @@ struct Src {
   int64_t s[NF];
 };
 
-template <int DIM, int NF, int P, int F, bool SCALED, class TS, class Epi>
-__global__ void __launch_bounds__(kThreads)
+template <int DIM, int NF, int NT, int P, int F, bool SCALED, class TS, class Epi>
+__global__ void __launch_bounds__(NT)
     k_stencil(Src<TS, NF> src, Grid g, StencilShape sh, Batch B, Epi epi) {
   extern __shared__ double lds[];
   using In = typename Epi::In;
@@ -204,7 +215,7 @@ __global__ void __launch_bounds__(kThreads)
   bool valid[P];
 #pragma unroll
   for (int p = 0; p < P; p++) {
-    int64_t q = s0 + tid + kThreads * p;
+    int64_t q = s0 + tid + NT * p;
     valid[p] = q < plane;
     if (DIM == 3) {
       int j = (int)(q / nn);
@@ -226,7 +237,7 @@ __global__ void __launch_bounds__(kThreads)
     for (int f = 0; f < NF; f++)
 #pragma unroll
       for (int k = 0; k < F; k++) {
-        const int64_t gq = s0 - halo + tid + kThreads * k;
+        const int64_t gq = s0 - halo + tid + NT * k;
         const int64_t gc = gq < 0 ? 0 : (gq >= plane ? plane - 1 : gq);
         pre[f][k] = sp[f][zoff + gc];
       }
@@ -236,7 +247,7 @@ __global__ void __launch_bounds__(kThreads)
     for (int f = 0; f < NF; f++)
 #pragma unroll
       for (int k = 0; k < F; k++) {
-        const int t = tid + kThreads * k;
+        const int t = tid + NT * k;
         const int64_t gq = s0 - halo + t;
         if (t < ldsn) lds[f * ldsn + t] = (gq >= 0 && gq < plane) ? to_d(pre[f][k]) : 0.0;
       }
@@ -246,7 +257,7 @@ __global__ void __launch_bounds__(kThreads)
   auto plane_partials = [&](double (*pm)[P], double (*pk)[P], double (*cen)[P]) {
 #pragma unroll
     for (int p = 0; p < P; p++) {
-      const int L = tid + kThreads * p + halo;
+      const int L = tid + NT * p + halo;
       if constexpr (!SCALED) {
         const int ix = ii[p];
         const bool hl = ix > 0, hr = ix < N, ex = (ix == 0 || ix == N);
@@ -343,7 +354,7 @@ __global__ void __launch_bounds__(kThreads)
       const int oc = o < z0 ? z0 : o;
 #pragma unroll
       for (int p = 0; p < P; p++) {  // clamped: loaded by every lane, used if valid
-        const int64_t q = s0 + tid + kThreads * p;
+        const int64_t q = s0 + tid + NT * p;
         in[p] = epi.load(inst, (int64_t)oc * plane + (q < plane ? q : plane - 1));
       }
     }
@@ -375,7 +386,7 @@ __global__ void __launch_bounds__(kThreads)
         }
         int nb = (ii[p] == 0 || ii[p] == N) + nbz;
         if (DIM == 3) nb += (jj[p] == 0 || jj[p] == N);
-        int64_t idx = (int64_t)o * plane + s0 + tid + kThreads * p;
+        int64_t idx = (int64_t)o * plane + s0 + tid + NT * p;
         epi.store(inst, idx, nb, ms, ks, cc, in[p], kk);
       }
     }
@@ -392,62 +403,80 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-template <int D, int NF, int PP, bool SCALED, class TS, class Epi>
+template <int D, int NF, int NT, int PP, bool SCALED, class TS, class Epi>
 static void launch_h(int hx, dim3 grid, dim3 block, size_t lds, hipStream_t st,
                      const Src<TS, NF>& s, const Grid& g, const StencilShape& sh, const Batch& B,
                      const Epi& e) {
   switch (hx) {
-    case 3: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 3, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, B, e); break;
-    case 5: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 5, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, B, e); break;
-    case 9: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 9, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, B, e); break;
-    default: hipLaunchKernelGGL((k_stencil<D, NF, PP, PP + 17, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, B, e); break;
+    case 3: hipLaunchKernelGGL((k_stencil<D, NF, NT, PP, PP + 3, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, B, e); break;
+    case 5: hipLaunchKernelGGL((k_stencil<D, NF, NT, PP, PP + 5, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, B, e); break;
+    case 9: hipLaunchKernelGGL((k_stencil<D, NF, NT, PP, PP + 9, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, B, e); break;
+    default: hipLaunchKernelGGL((k_stencil<D, NF, NT, PP, PP + 17, SCALED, TS, Epi>), grid, block, lds, st, s, g, sh, B, e); break;
   }
 }
+
+#if OKD_STENCIL_PART == 0
+// Launch shapes with instantiated kernels: 256 threads of 1, 2, 4 or 8 nodes
+// (two stenciled fields: up to 4); in 3D, one stenciled field, also 512
+// threads of 1, 2 or 4 nodes.
+bool stencil_shape_ok(int dim, int nf, int items, int threads) {
+  if (threads == kThreads) return items == 1 || items == 2 || items == 4 || (items == 8 && nf == 1);
+  return threads == 512 && dim == 3 && nf == 1 && (items == 1 || items == 2 || items == 4);
+}
+#endif
 
 template <bool SCALED, class TS, int NF, class Epi>
 static hipError_t run_stencil_n(const Grid& g, const Batch& B, const Src<TS, NF>& s, const Epi& e,
                                 hipStream_t st) {
   StencilShape sh = stencil_shape(g, NF, (int)sizeof(TS));
+  if (!stencil_shape_ok(g.dim, NF, sh.items, sh.threads)) return hipErrorInvalidValue;
+  const int NTh = sh.threads;
   const int ldsn = sh.chunk + 2 * (g.dim == 3 ? g.nn + 1 : 1);
   size_t lds = (size_t)NF * ldsn * sizeof(double);
-  // prefetch registers beyond the chunk: ceil(2*halo/256) rounded up to 3, 5, 9, 17
-  int extra = (ldsn - sh.chunk + kThreads - 1) / kThreads;
+  // prefetch registers beyond the chunk: ceil(2*halo/threads) rounded up to 3, 5, 9, 17
+  int extra = (ldsn - sh.chunk + NTh - 1) / NTh;
   int hx = extra <= 3 ? 3 : (extra <= 5 ? 5 : (extra <= 9 ? 9 : 17));
   if (extra > 17 || lds > 65536 || B.count < 1) return hipErrorInvalidValue;
   int64_t nblk = (int64_t)sh.blocks * B.count;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
-  dim3 grid((unsigned)nblk), block(kThreads);
+  dim3 grid((unsigned)nblk), block(NTh);
   if (g.dim == 2) {
     if (NF == 1) {
       switch (sh.items) {
-        case 8: launch_h<2, NF, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
-        case 4: launch_h<2, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
-        case 2: launch_h<2, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
-        default: launch_h<2, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        case 8: launch_h<2, NF, 256, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        case 4: launch_h<2, NF, 256, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        case 2: launch_h<2, NF, 256, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        default: launch_h<2, NF, 256, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
       }
     } else {
-      if (sh.items > 4) return hipErrorInvalidValue;
       switch (sh.items) {
-        case 4: launch_h<2, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
-        case 2: launch_h<2, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
-        default: launch_h<2, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        case 4: launch_h<2, NF, 256, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        case 2: launch_h<2, NF, 256, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        default: launch_h<2, NF, 256, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
       }
     }
   } else {
     if (hx > 5) return hipErrorInvalidValue;
     if (NF == 1) {
-      switch (sh.items) {
-        case 8: launch_h<3, NF, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
-        case 4: launch_h<3, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
-        case 2: launch_h<3, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
-        default: launch_h<3, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+      if (NTh == 512) {
+        switch (sh.items) {
+          case 4: launch_h<3, NF, 512, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+          case 2: launch_h<3, NF, 512, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+          default: launch_h<3, NF, 512, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        }
+      } else {
+        switch (sh.items) {
+          case 8: launch_h<3, NF, 256, 8, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+          case 4: launch_h<3, NF, 256, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+          case 2: launch_h<3, NF, 256, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+          default: launch_h<3, NF, 256, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        }
       }
     } else {
-      if (sh.items > 4) return hipErrorInvalidValue;
       switch (sh.items) {
-        case 4: launch_h<3, NF, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
-        case 2: launch_h<3, NF, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
-        default: launch_h<3, NF, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        case 4: launch_h<3, NF, 256, 4, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        case 2: launch_h<3, NF, 256, 2, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
+        default: launch_h<3, NF, 256, 1, SCALED>(hx, grid, block, lds, st, s, g, sh, B, e); break;
       }
     }
   }
@@ -1049,7 +1078,6 @@ hipError_t launch_cheb_step(const Grid& g, const Batch& B, int lev, int k, int o
 }
 
 namespace {
-int g_fuse_cheb = 1;
 
 template <int DIM, int NT, int P, int EX1, int EXA, class T>
 hipError_t launch_cheb2_p(const Grid& g, const Batch& B, const StencilShape& sh, int k, int osc,
@@ -1071,16 +1099,15 @@ hipError_t launch_cheb2_p(const Grid& g, const Batch& B, const StencilShape& sh,
   return hipGetLastError();
 }
 
-// Launch geometry of the fused kernel for a shape's item count: 1 and 2 are
-// 256 threads of 1 or 2 nodes, 4 is 512 threads of 2 nodes.  ex1 and exa are
-// the extra per-thread slots of the one- and two-row halos.
+// Launch geometry of the fused kernel: threads of 1 or 2 nodes each.  ex1
+// and exa are the extra per-thread slots of the one- and two-row halos.
 struct Cheb2Geom {
   int nt, p, ex1, exa;
 };
-Cheb2Geom cheb2_geom(const Grid& g, int items) {
+Cheb2Geom cheb2_geom(const Grid& g, const StencilShape& sh) {
   Cheb2Geom c;
-  c.nt = items >= 4 ? 512 : 256;
-  c.p = items >= 2 ? 2 : 1;
+  c.nt = sh.threads;
+  c.p = sh.items;
   const int H = (g.dim == 3) ? g.nn + 1 : 1;
   c.ex1 = (2 * H + c.nt - 1) / c.nt;
   c.exa = (4 * H + c.nt - 1) / c.nt;
@@ -1110,7 +1137,19 @@ hipError_t launch_cheb2_ex(const Grid& g, const Batch& B, const StencilShape& sh
 }
 }  // namespace
 
+#if OKD_STENCIL_PART == 0
+namespace {
+int g_fuse_cheb = 1;
+}  // namespace
+
 void cheb_fusion_set(int enable) { g_fuse_cheb = enable ? 1 : 0; }
+
+// Shapes of the fused kernel: 256 threads of 1 or 2 nodes, and in 3D 512
+// threads of 1 or 2 nodes.
+bool cheb2_shape_ok(int dim, int items, int threads) {
+  if (items != 1 && items != 2) return false;
+  return threads == 256 || (threads == 512 && dim == 3);
+}
 
 bool cheb_fusion_on(const Grid& g, int word) {
   if (!g_fuse_cheb) return false;
@@ -1118,11 +1157,11 @@ bool cheb_fusion_on(const Grid& g, int word) {
     // the autotuner records items < 0 where fused pairs lost to single steps
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(std::make_tuple(g.dim, g.nn, kFusedKey, word));
-    if (it != g_tune.end() && it->second.first < 0) return false;
+    if (it != g_tune.end() && std::get<0>(it->second) < 0) return false;
   }
   StencilShape sh = stencil_shape(g, kFusedKey, word);
-  const Cheb2Geom c = cheb2_geom(g, sh.items);
-  if (g.dim == 2 && c.nt != 256) return false;
+  if (!cheb2_shape_ok(g.dim, sh.items, sh.threads)) return false;
+  const Cheb2Geom c = cheb2_geom(g, sh);
   const int H = (g.dim == 3) ? g.nn + 1 : 1;
   const bool combo = (g.dim == 2) ? (c.ex1 == 1 && c.exa == 1)
                                   : ((c.ex1 == 1 && c.exa <= 2) || (c.ex1 == 2 && c.exa == 3) ||
@@ -1130,6 +1169,7 @@ bool cheb_fusion_on(const Grid& g, int word) {
   const int ch = c.nt * c.p;
   return combo && (size_t)(6 * ch + 6 * H) * sizeof(double) <= 65536;
 }
+#endif  // OKD_STENCIL_PART == 0
 
 template <class T>
 hipError_t launch_cheb_step2(const Grid& g, const Batch& B, int k, int osc, bool last2, Vec<T> x,
@@ -1137,18 +1177,19 @@ hipError_t launch_cheb_step2(const Grid& g, const Batch& B, int k, int osc, bool
                              hipStream_t st) {
   if (k < 0 || k + 1 >= kMaxCheb || B.count < 1) return hipErrorInvalidValue;
   if (!last2 && (rout.p == r.p || rout.null())) return hipErrorInvalidValue;
-  StencilShape sh = stencil_shape(g, kFusedKey, (int)sizeof(T));
-  if (sh.items > 4) sh = shape_with(g, 4, sh.nzc);
-  if (sh.items == 3) sh = shape_with(g, 2, sh.nzc);
-  const Cheb2Geom c = cheb2_geom(g, sh.items);
+  const StencilShape sh = stencil_shape(g, kFusedKey, (int)sizeof(T));
+  if (!cheb2_shape_ok(g.dim, sh.items, sh.threads)) return hipErrorInvalidValue;
+  const Cheb2Geom c = cheb2_geom(g, sh);
   if (g.dim == 2) {
-    if (c.nt != 256) return hipErrorInvalidValue;
     if (c.p == 1)
       return launch_cheb2_ex<2, 256, 1, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
     return launch_cheb2_ex<2, 256, 2, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
   }
-  if (c.nt == 512)
+  if (c.nt == 512) {
+    if (c.p == 1)
+      return launch_cheb2_ex<3, 512, 1, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
     return launch_cheb2_ex<3, 512, 2, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
+  }
   if (c.p == 1)
     return launch_cheb2_ex<3, 256, 1, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
   return launch_cheb2_ex<3, 256, 2, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
@@ -1177,12 +1218,25 @@ hipError_t launch_resid(const Grid& g, const Batch& B, int lev, Vec<const T> b, 
   return run_stencil<false>(g, B, x, e, st);
 }
 
-// Explicit instantiations.
+// Explicit instantiations: FP64 in part 0, FP32 and mixed in part 1.
+#if OKD_STENCIL_PART == 0
 template hipError_t launch_stencil_axpy<double, double, double>(const Grid&, const Batch&,
                                                                 Vec<const double>,
                                                                 Vec<const double>, double, int,
                                                                 double, int, Vec<double>,
                                                                 hipStream_t);
+template hipError_t launch_stencil_lin2<double>(const Grid&, const Batch&, Vec<const double>,
+                                                Vec<const double>, Vec<const double>,
+                                                Vec<const double>, const double (&)[2][4],
+                                                const int (&)[2][4], Vec<double>, Vec<double>,
+                                                hipStream_t);
+template hipError_t launch_schur_res<double>(const Grid&, const Batch&, Vec<const double>,
+                                             Vec<const double>, Vec<const double>,
+                                             Vec<const double>, Vec<double>, hipStream_t);
+template hipError_t launch_couple<double>(const Grid&, const Batch&, Vec<const double>,
+                                          Vec<const double>, Vec<const double>, Vec<double>,
+                                          Vec<double>, hipStream_t);
+#else
 template hipError_t launch_stencil_axpy<float, float, float>(const Grid&, const Batch&,
                                                              Vec<const float>, Vec<const float>,
                                                              double, int, double, int,
@@ -1192,38 +1246,24 @@ template hipError_t launch_stencil_axpy<float, double, float>(const Grid&, const
                                                               Vec<const double>, double, int,
                                                               double, int, Vec<float>,
                                                               hipStream_t);
-template hipError_t launch_stencil_lin2<double>(const Grid&, const Batch&, Vec<const double>,
-                                                Vec<const double>, Vec<const double>,
-                                                Vec<const double>, const double (&)[2][4],
-                                                const int (&)[2][4], Vec<double>, Vec<double>,
-                                                hipStream_t);
 template hipError_t launch_stencil_lin2<float>(const Grid&, const Batch&, Vec<const float>,
                                                Vec<const float>, Vec<const double>,
                                                Vec<const double>, const double (&)[2][4],
                                                const int (&)[2][4], Vec<double>, Vec<double>,
                                                hipStream_t);
-template hipError_t launch_schur_res<double>(const Grid&, const Batch&, Vec<const double>,
-                                             Vec<const double>, Vec<const double>,
-                                             Vec<const double>, Vec<double>, hipStream_t);
 template hipError_t launch_schur_res<float>(const Grid&, const Batch&, Vec<const float>,
                                             Vec<const float>, Vec<const double>, Vec<const float>,
                                             Vec<float>, hipStream_t);
-template hipError_t launch_couple<double>(const Grid&, const Batch&, Vec<const double>,
-                                          Vec<const double>, Vec<const double>, Vec<double>,
-                                          Vec<double>, hipStream_t);
 template hipError_t launch_couple<float>(const Grid&, const Batch&, Vec<const float>,
                                          Vec<const double>, Vec<const double>, Vec<float>,
                                          Vec<double>, hipStream_t);
+#endif
 #define OKD_CHEB_TB(TB, T)                                                                    \
   template hipError_t launch_cheb_one<TB, T>(const Grid&, const Batch&, int, int,              \
                                              Vec<const TB>, Vec<T>, hipStream_t);              \
   template hipError_t launch_cheb_first<TB, T>(const Grid&, const Batch&, int, int, bool,      \
                                                Vec<const TB>, Vec<T>, Vec<T>, Vec<T>,          \
                                                hipStream_t);
-OKD_CHEB_TB(double, double)
-OKD_CHEB_TB(float, float)
-OKD_CHEB_TB(double, float)
-#undef OKD_CHEB_TB
 #define OKD_CHEB_T(T)                                                                         \
   template hipError_t launch_cheb_step<T>(const Grid&, const Batch&, int, int, int, bool,      \
                                           Vec<T>, Vec<T>, Vec<const T>, Vec<T>, hipStream_t);  \
@@ -1236,8 +1276,15 @@ OKD_CHEB_TB(double, float)
                                             hipStream_t);                                      \
   template hipError_t launch_resid<T>(const Grid&, const Batch&, int, Vec<const T>,            \
                                       Vec<const T>, Vec<T>, hipStream_t);
+#if OKD_STENCIL_PART == 0
+OKD_CHEB_TB(double, double)
 OKD_CHEB_T(double)
+#else
+OKD_CHEB_TB(float, float)
+OKD_CHEB_TB(double, float)
 OKD_CHEB_T(float)
+#endif
+#undef OKD_CHEB_TB
 #undef OKD_CHEB_T
 
 }  // namespace okd

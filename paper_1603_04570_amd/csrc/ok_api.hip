@@ -317,34 +317,25 @@ int ok_set_option(int32_t option, int32_t value) {
 }
 
 int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precision, int32_t items,
-                        int32_t zchunks) {
+                        int32_t threads, int32_t zchunks) {
   if ((dim != 2 && dim != 3) || n < 1 || n > (1 << 20)) return OK_E_INVALID;
   if (precision != OK_FP64 && precision != OK_MIXED) return OK_E_INVALID;
   int nf;
-  bool ok_items;
   switch (kernel) {
-    case OK_SHAPE_STENCIL:
-      nf = 1;
-      ok_items = items == 1 || items == 2 || items == 4 || items == 8;
-      break;
-    case OK_SHAPE_STENCIL2:
-      nf = 2;
-      ok_items = items == 1 || items == 2 || items == 4;
-      break;
-    case OK_SHAPE_CHEB2:
-      nf = kFusedKey;
-      ok_items = items == 1 || items == 2 || (items == 4 && dim == 3);
-      break;
-    default:
-      return OK_E_INVALID;
+    case OK_SHAPE_STENCIL: nf = 1; break;
+    case OK_SHAPE_STENCIL2: nf = 2; break;
+    case OK_SHAPE_CHEB2: nf = kFusedKey; break;
+    default: return OK_E_INVALID;
   }
   const int word = precision == OK_MIXED ? 4 : 8;
   if (items == 0) {
     stencil_tune_set(dim, n + 1, nf, word, 0, 0);
     return OK_SUCCESS;
   }
-  if (!ok_items || zchunks < 1 || zchunks > n + 1) return OK_E_INVALID;
-  stencil_tune_set(dim, n + 1, nf, word, items, zchunks);
+  const bool ok_shape = (nf == kFusedKey) ? cheb2_shape_ok(dim, items, threads)
+                                          : stencil_shape_ok(dim, nf, items, threads);
+  if (!ok_shape || zchunks < 1 || zchunks > n + 1) return OK_E_INVALID;
+  stencil_tune_set(dim, n + 1, nf, word, items, zchunks, threads);
   return OK_SUCCESS;
 }
 

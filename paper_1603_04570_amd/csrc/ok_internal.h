@@ -98,7 +98,8 @@ struct Batch {
 // Launch shape of the z-streaming node-stencil kernels on a grid.
 struct StencilShape {
   int items;    // nodes per thread per plane (1,2,4,8)
-  int chunk;    // nodes per block per plane (kThreads*items)
+  int threads;  // threads per block (256, or 512 for some 3D kernels)
+  int chunk;    // nodes per block per plane (threads*items)
   int nchunks;  // chunks per plane
   int zc;       // most planes of a block: ceil(nn/nzc)
   int nzc;      // z-chunks; chunk c owns planes [c*nn/nzc, (c+1)*nn/nzc)
@@ -126,7 +127,7 @@ constexpr int kFusedKey = 17;
 // direction, stenciled fields, bytes per stenciled word); items < 0 marks the
 // fused Chebyshev kernel as slower than single steps on that grid; items == 0 removes
 // the entry (back to the heuristic).  Results do not depend on the shape.
-void stencil_tune_set(int dim, int nn, int nf, int word, int items, int nzc);
+void stencil_tune_set(int dim, int nn, int nf, int word, int items, int nzc, int threads = 256);
 
 // Reduction blocks per instance for vectors of length n (a fixed function of
 // n, so solo and batched runs sum in the same order).
@@ -164,6 +165,9 @@ hipError_t launch_cheb_step2(const Grid& g, const Batch& B, int k, int osc, bool
 // cheb_fusion_on: the switch is on and the fused kernel supports grid g.
 void cheb_fusion_set(int enable);
 bool cheb_fusion_on(const Grid& g, int word);
+// Launch shapes that have instantiated kernels (items per thread, threads).
+bool stencil_shape_ok(int dim, int nf, int items, int threads);
+bool cheb2_shape_ok(int dim, int items, int threads);
 // Richardson residual on the Schur complement: with a = A~^-1 (dt th K z2)
 // and G = 3 int u^2 a phi, res = y - (M z2 + G - M a + eps^2 K a).
 template <class T>

@@ -130,7 +130,7 @@ def load():
     lib.ok_batch_last_error.restype = C.c_char_p
     lib.ok_use_graphs.argtypes = [vp, i32]
     lib.ok_set_option.argtypes = [i32, i32]
-    lib.ok_set_launch_shape.argtypes = [i32] * 6
+    lib.ok_set_launch_shape.argtypes = [i32] * 7
     lib.ok_initial_w.argtypes = [vp, vp, vp, vp]
     lib.ok_batch_use_graphs.argtypes = [vp, i32]
     lib.ok_server_default_config.argtypes = [P(ServerConfig)]
@@ -412,10 +412,11 @@ def set_option(option: int, value: int):
 OK_SHAPE_STENCIL, OK_SHAPE_STENCIL2, OK_SHAPE_CHEB2 = 1, 2, 3
 
 
-def set_launch_shape(dim: int, n: int, kernel: int, precision: int, items: int, zchunks: int = 1):
+def set_launch_shape(dim: int, n: int, kernel: int, precision: int, items: int,
+                     threads: int = 256, zchunks: int = 1):
     """ok_set_launch_shape: pin (items > 0) or clear (items = 0) the launch
     shape of one stencil kernel class on one grid."""
-    st = load().ok_set_launch_shape(dim, n, kernel, precision, items, zchunks)
+    st = load().ok_set_launch_shape(dim, n, kernel, precision, items, threads, zchunks)
     if st:
         raise OkError(st, "ok_set_launch_shape")
 

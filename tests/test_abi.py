@@ -109,16 +109,22 @@ def test_launch_shape_arguments(lib):
     """ok_set_launch_shape only edits the host-side shape table: argument
     checks run without a GPU."""
     E = -1  # OK_E_INVALID
-    assert lib.ok_set_launch_shape(3, 64, 1, 0, 4, 5) == 0
-    assert lib.ok_set_launch_shape(3, 64, 1, 0, 0, 0) == 0       # clear
-    assert lib.ok_set_launch_shape(3, 64, 3, 1, 4, 65) == 0      # 512-thread fused pair
-    assert lib.ok_set_launch_shape(3, 64, 3, 1, 0, 0) == 0
-    assert lib.ok_set_launch_shape(4, 64, 1, 0, 4, 5) == E       # dim
-    assert lib.ok_set_launch_shape(3, 0, 1, 0, 4, 5) == E        # n
-    assert lib.ok_set_launch_shape(3, 64, 9, 0, 4, 5) == E       # kernel
-    assert lib.ok_set_launch_shape(3, 64, 1, 2, 4, 5) == E       # precision
-    assert lib.ok_set_launch_shape(3, 64, 1, 0, 3, 5) == E       # items
-    assert lib.ok_set_launch_shape(3, 64, 2, 0, 8, 5) == E       # two-field: at most 4
-    assert lib.ok_set_launch_shape(2, 64, 3, 0, 4, 5) == E       # 512-thread pair is 3D only
-    assert lib.ok_set_launch_shape(3, 64, 1, 0, 4, 0) == E       # zchunks
-    assert lib.ok_set_launch_shape(3, 64, 1, 0, 4, 66) == E
+    f = lib.ok_set_launch_shape  # (dim, n, kernel, precision, items, threads, zchunks)
+    assert f(3, 64, 1, 0, 4, 256, 5) == 0
+    assert f(3, 64, 1, 0, 4, 512, 5) == 0      # 512 threads of 4 nodes
+    assert f(3, 64, 1, 0, 0, 0, 0) == 0        # clear
+    assert f(3, 64, 3, 1, 2, 512, 65) == 0     # 512-thread fused pair
+    assert f(3, 64, 3, 1, 0, 0, 0) == 0
+    assert f(4, 64, 1, 0, 4, 256, 5) == E      # dim
+    assert f(3, 0, 1, 0, 4, 256, 5) == E       # n
+    assert f(3, 64, 9, 0, 4, 256, 5) == E      # kernel
+    assert f(3, 64, 1, 2, 4, 256, 5) == E      # precision
+    assert f(3, 64, 1, 0, 3, 256, 5) == E      # items
+    assert f(3, 64, 1, 0, 8, 512, 5) == E      # 512 threads: at most 4 nodes
+    assert f(2, 64, 1, 0, 2, 512, 5) == E      # 512 threads: 3D only
+    assert f(3, 64, 1, 0, 4, 128, 5) == E      # threads
+    assert f(3, 64, 2, 0, 8, 256, 5) == E      # two fields: at most 4 nodes
+    assert f(3, 64, 3, 0, 4, 256, 5) == E      # fused pair: 1 or 2 nodes
+    assert f(2, 64, 3, 0, 2, 512, 5) == E      # fused 512-thread pair: 3D only
+    assert f(3, 64, 1, 0, 4, 256, 0) == E      # zchunks
+    assert f(3, 64, 1, 0, 4, 256, 66) == E

@@ -34,13 +34,13 @@ def test_fused_chebyshev_shapes_bitwise(dim, n, precision):
         ref = cheb_mass(P, r, nodes)
     finally:
         ok.set_option(ok.OK_OPT_FUSE_CHEB, 1)
-    items_list = (1, 2, 4) if dim == 3 else (1, 2)
+    shapes = [(1, 256), (2, 256)] + ([(1, 512), (2, 512)] if dim == 3 else [])
     try:
-        for items in items_list:
+        for items, threads in shapes:
             for zch in (1, 3, 7, n + 1):
-                print("fused shape", dim, n, precision, items, zch, flush=True)
-                ok.set_launch_shape(dim, n, ok.OK_SHAPE_CHEB2, precision, items, zch)
-                assert np.array_equal(cheb_mass(P, r, nodes), ref), (items, zch)
+                print("fused shape", dim, n, precision, items, threads, zch, flush=True)
+                ok.set_launch_shape(dim, n, ok.OK_SHAPE_CHEB2, precision, items, threads, zch)
+                assert np.array_equal(cheb_mass(P, r, nodes), ref), (items, threads, zch)
     finally:
         ok.set_launch_shape(dim, n, ok.OK_SHAPE_CHEB2, precision, 0)
 
@@ -65,17 +65,19 @@ def test_stencil_shapes_timestep_bitwise(precision):
 
     ref = once()
     try:
-        for items, zch in [(1, 1), (2, 4), (4, 33), (8, 5), (8, 1)]:
-            print("stencil shape", precision, items, zch, flush=True)
+        for items, threads, zch in [(1, 256, 1), (2, 256, 4), (4, 256, 33), (8, 256, 5),
+                                    (8, 256, 1), (1, 512, 3), (2, 512, 1), (4, 512, 33)]:
+            print("stencil shape", precision, items, threads, zch, flush=True)
             for lev_n in (n, n // 2):
                 for word in (0, 1):  # FP64 and FP32 storage entries
-                    ok.set_launch_shape(dim, lev_n, ok.OK_SHAPE_STENCIL, word, items,
+                    ok.set_launch_shape(dim, lev_n, ok.OK_SHAPE_STENCIL, word, items, threads,
                                         min(zch, lev_n + 1))
                     ok.set_launch_shape(dim, lev_n, ok.OK_SHAPE_STENCIL2, word, min(items, 4),
-                                        min(zch, lev_n + 1))
+                                        256, min(zch, lev_n + 1))
             got = once()
             assert got[2] == ref[2]
-            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (items, zch)
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), \
+                (items, threads, zch)
     finally:
         for lev_n in (n, n // 2):
             for word in (0, 1):
