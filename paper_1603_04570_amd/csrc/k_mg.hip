@@ -58,8 +58,9 @@ __device__ __forceinline__ void node_ijk(unsigned q, const Grid& g, int& i, int&
   }
 }
 
-// Every load of a transfer is issued before the first one is used, from
-// clamped (in-bounds) indices: terms outside the grid are loaded anyway and
+// Restriction gathers straight from global memory (its 27 loads per coarse
+// node keep enough bytes in flight); every load is issued before the first
+// one is used, from clamped (in-bounds) indices: terms outside the grid are loaded anyway and
 // then left out of the sum, which keeps the summation order (and so every
 // bit) of the plain nested loops over the stencil while no load waits behind
 // a lane-dependent branch.
@@ -121,50 +122,68 @@ __global__ void __launch_bounds__(256)
   bcv.at(inst)[q] = (T)s;
 }
 
+// Prolongation works on one coarse row (J, K) and a segment of at most
+// kProlongW coarse nodes along x per block: the four coarse rows that the
+// segment's fine nodes interpolate from are staged in LDS with coalesced
+// loads, and every fine node gathers its (up to) eight coarse values from
+// LDS; gathering them from global memory costs more than the HBM traffic of
+// the transfer.  Sums run in the order of the nested loops over the stencil
+// (z, then y, then x offsets), skipping the terms a fine node does not have.
+constexpr int kProlongW = 256;    // coarse nodes per prolongation block
+
 template <int DIM, class T>
 __global__ void __launch_bounds__(256)
-    k_prolong_add(Vec<const T> ecv, Vec<T> xv, Grid f, Grid c, Batch B, int per) {
+    k_prolong_add(Vec<const T> ecv, Vec<T> xv, Grid f, Grid c, Batch B, int nseg) {
+  constexpr int NZ = (DIM == 3) ? 2 : 1;  // coarse planes K, K+1
+  constexpr int LW = kProlongW + 1;       // coarse x values per staged row
+  __shared__ double cr[NZ][2][LW];
+  const int per = nseg * c.nn * (DIM == 3 ? c.nn : 1);
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = lb / per;
   if (B.act && !B.act[inst]) return;
-  const unsigned q = (unsigned)(lb - inst * per) * blockDim.x + threadIdx.x;
-  if (q >= (unsigned)f.nodes) return;
-  int fi, fj, fk;
-  node_ijk<DIM>(q, f, fi, fj, fk);
+  int rem = lb - inst * per;
+  const int seg = rem % nseg;
+  rem /= nseg;
+  const int J = rem % c.nn, K = (DIM == 3) ? rem / c.nn : 0;
+  const int I0 = (int)((int64_t)seg * c.nn / nseg), I1 = (int)((int64_t)(seg + 1) * c.nn / nseg);
   const T* __restrict__ ec = ecv.at(inst);
   T* __restrict__ x = xv.at(inst);
-  // coarse neighbours along each axis: one (even fine index, weight 1) or
-  // two (odd, weights 1/2); a single one is loaded twice and added once
-  const int I[2] = {fi >> 1, (fi + 1) >> 1};
-  const int J[2] = {fj >> 1, (fj + 1) >> 1};
-  const int K[2] = {fk >> 1, (fk + 1) >> 1};
-  const bool two_i = I[1] != I[0], two_j = J[1] != J[0], two_k = (DIM == 3) && K[1] != K[0];
-  constexpr int NZ = (DIM == 3) ? 2 : 1;
-  const T xo = x[q];
-  T v[NZ][2][2];
+  // coarse rows J, J+1 of planes K, K+1 (clamped to the grid; a clamped row
+  // only feeds fine rows that do not exist)
+  for (int t = threadIdx.x; t < NZ * 2 * LW; t += blockDim.x) {
+    const int o = t % LW, rr = t / LW;
+    const int dy = rr & 1, dz = rr >> 1;
+    const int Ic = min(I0 + o, c.N), Jc = min(J + dy, c.N), Kc = min(K + dz, c.N);
+    cr[dz][dy][o] = ld(ec + ((int64_t)Kc * c.plane + (int64_t)Jc * c.nn + Ic));
+  }
+  __syncthreads();
+  // fine nodes (2I0 .. min(2 I1, nn_f) - 1) x rows 2J + a x planes 2K + b
+  const int nfx = min(2 * I1, f.nn) - 2 * I0;
+  const int nrow = 2 * NZ;
+  for (int e = threadIdx.x; e < nrow * nfx; e += blockDim.x) {
+    const int rr = e / nfx, ix = e - rr * nfx;
+    const int a = rr & 1, b = rr >> 1;  // fine row 2J + a, plane 2K + b
+    const int fj = 2 * J + a, fk = 2 * K + b, fi = 2 * I0 + ix;
+    if (fj > f.N || (DIM == 3 && fk > f.N)) continue;
+    const int li0 = (fi >> 1) - I0, li1 = ((fi + 1) >> 1) - I0;
+    const bool two_i = (fi & 1) != 0, two_j = a != 0, two_k = b != 0;
+    const double wk = two_k ? 0.5 : 1.0;
+    const double wj = wk * (two_j ? 0.5 : 1.0);
+    const double wi = two_i ? 0.5 : 1.0;
+    double s = 0.0;
 #pragma unroll
-  for (int a = 0; a < NZ; a++)
+    for (int za = 0; za < NZ; za++) {
+      if (za && !two_k) break;
 #pragma unroll
-    for (int bb = 0; bb < 2; bb++) {
-      const T* cr = ec + (int64_t)K[a] * c.plane + (int64_t)J[bb] * c.nn;
-#pragma unroll
-      for (int cc = 0; cc < 2; cc++) v[a][bb][cc] = cr[I[cc]];
-    }
-  const double wk = two_k ? 0.5 : 1.0;
-  const double wj = wk * (two_j ? 0.5 : 1.0);
-  const double wi = two_i ? 0.5 : 1.0;
-  double s = 0.0;
-#pragma unroll
-  for (int a = 0; a < NZ; a++)
-#pragma unroll
-    for (int bb = 0; bb < 2; bb++)
-#pragma unroll
-      for (int cc = 0; cc < 2; cc++) {
-        const bool use = (a == 0 || two_k) && (bb == 0 || two_j) && (cc == 0 || two_i);
-        const double t = wj * wi * ld(&v[a][bb][cc]);
-        s += use ? t : 0.0;
+      for (int yb = 0; yb < 2; yb++) {
+        if (yb && !two_j) break;
+        s += wj * wi * cr[za][yb][li0];
+        if (two_i) s += wj * wi * cr[za][yb][li1];
       }
-  x[q] = (T)(ld(&xo) + s);
+    }
+    const int64_t q = (DIM == 3) ? ((int64_t)fk * f.nn + fj) * f.nn + fi : (int64_t)fj * f.nn + fi;
+    x[q] = (T)(ld(x + q) + s);
+  }
 }
 
 constexpr int kCoarseMax = 1024;   // nodes of the coarse grid
@@ -324,12 +343,14 @@ hipError_t launch_restrict(const Grid& fine, const Grid& coarse, const Batch& B,
 template <class T>
 hipError_t launch_prolong_add(const Grid& fine, const Grid& coarse, const Batch& B,
                               Vec<const T> ec, Vec<T> x, hipStream_t st) {
-  const int per = (int)((fine.nodes + 255) / 256);
-  dim3 grid((unsigned)((int64_t)per * B.count)), block(256);
+  const int nseg = (coarse.nn + kProlongW - 1) / kProlongW;
+  const int64_t nblk = (int64_t)nseg * coarse.nn * (fine.dim == 3 ? coarse.nn : 1) * B.count;
+  if (fine.N != 2 * coarse.N || nblk > 0x7fffffff) return hipErrorInvalidValue;
+  dim3 grid((unsigned)nblk), block(256);
   if (fine.dim == 2)
-    hipLaunchKernelGGL((k_prolong_add<2, T>), grid, block, 0, st, ec, x, fine, coarse, B, per);
+    hipLaunchKernelGGL((k_prolong_add<2, T>), grid, block, 0, st, ec, x, fine, coarse, B, nseg);
   else
-    hipLaunchKernelGGL((k_prolong_add<3, T>), grid, block, 0, st, ec, x, fine, coarse, B, per);
+    hipLaunchKernelGGL((k_prolong_add<3, T>), grid, block, 0, st, ec, x, fine, coarse, B, nseg);
   return hipGetLastError();
 }
 
