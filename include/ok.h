@@ -216,8 +216,13 @@ int ok_initial_w(ok_ctx *ctx, const double *d_u, double *d_w, void *stream);
 /* Process-wide tuning options (results are bitwise the same either way):
  *   OK_OPT_FUSE_CHEB: 1 (default) runs consecutive middle iterations of the
  *   Chebyshev iteration on M two per pass (each vector read and written once
- *   per pair); 0 runs them one per pass. */
-enum ok_option { OK_OPT_FUSE_CHEB = 1 };
+ *   per pair); 0 runs them one per pass.
+ *   OK_OPT_FUSE_MG: 1 (default) runs, on multigrid levels where the
+ *   autotuner (or the default shape) keeps it, the two pre-smoothing
+ *   iterations with the residual in one pass and the two post-smoothing
+ *   iterations in one pass (V(2,2) cycles); 0 runs every iteration and the
+ *   residual in passes of their own. */
+enum ok_option { OK_OPT_FUSE_CHEB = 1, OK_OPT_FUSE_MG = 2 };
 int ok_set_option(int32_t option, int32_t value);
 
 /* Launch shape of the streaming node-stencil kernels on one grid: the
@@ -227,12 +232,13 @@ int ok_set_option(int32_t option, int32_t value);
  *   kernel: OK_SHAPE_STENCIL (one stenciled field: Chebyshev iterations,
  *     multigrid residuals, coupling), OK_SHAPE_STENCIL2 (two fields: the
  *     mass/stiffness pairs of residual and Jacobian), OK_SHAPE_CHEB2 (two
- *     fused Chebyshev iterations on M);
+ *     fused Chebyshev iterations on M), OK_SHAPE_MG_PRE / OK_SHAPE_MG_POST
+ *     (the fused smoothers of a multigrid level);
  *   precision: OK_FP64 or OK_MIXED (the preconditioner's storage type);
  *   items, threads: a block of `threads` threads covers items*threads nodes
  *     of a plane.  STENCIL: 256 threads of 1, 2, 4 or 8 nodes, in 3D also 512
- *     threads of 1, 2 or 4; STENCIL2: 256 threads of 1, 2 or 4; CHEB2: 256
- *     threads (3D also 512) of 1 or 2.  items = 0 removes the entry (built-in
+ *     threads of 1, 2 or 4; STENCIL2: 256 threads of 1, 2 or 4; CHEB2,
+ *     MG_PRE, MG_POST: 256 threads (3D also 512) of 1 or 2.  items = 0 removes the entry (built-in
  *     default shape; threads and zchunks are then ignored);
  *   zchunks: the n+1 planes of the streaming axis are split evenly into
  *     1..n+1 ranges, one block per (plane chunk, range).
@@ -240,7 +246,13 @@ int ok_set_option(int32_t option, int32_t value);
  * bitwise equal.  Launches read the table when issued; HIP graphs captured
  * earlier (ok_use_graphs) keep the shapes they were captured with.  Returns
  * OK_E_INVALID for an argument out of range. */
-enum ok_shape_kernel { OK_SHAPE_STENCIL = 1, OK_SHAPE_STENCIL2 = 2, OK_SHAPE_CHEB2 = 3 };
+enum ok_shape_kernel {
+  OK_SHAPE_STENCIL = 1,
+  OK_SHAPE_STENCIL2 = 2,
+  OK_SHAPE_CHEB2 = 3,
+  OK_SHAPE_MG_PRE = 4,  /* fused pre-smoothing + residual of a multigrid level */
+  OK_SHAPE_MG_POST = 5  /* fused post-smoothing of a multigrid level */
+};
 int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precision, int32_t items,
                         int32_t threads, int32_t zchunks);
 

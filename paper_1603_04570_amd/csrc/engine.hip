@@ -351,6 +351,24 @@ int mg_vcycle(ClassCtx& c, const int* fl, int l, Vec<const P> b, Vec<P> x, bool 
   const int64_t nl = g.nodes;
   Vec<P> r = pvec<P>(c.mg[l][2], nl), da = pvec<P>(c.mg[l][3], nl), db = pvec<P>(c.mg[l][4], nl);
   const int cls = (l == 0) ? OK_K_MG_SMOOTH : OK_K_NONE;
+  const Grid& gc = c.lev[l + 1];
+  Vec<P> xc = pvec<P>(c.mg[l + 1][0], gc.nodes), bc = pvec<P>(c.mg[l + 1][1], gc.nodes);
+  if (zero_start && c.shape.mg_pre == 2 && c.shape.mg_post == 2 &&
+      mg_fusion_on(g, (int)sizeof(P))) {
+    // pre-smoothing and residual in one pass (smoothed x kept in db), the
+    // coarse-grid correction added to db, post-smoothing from db into x
+    {
+      ProfScope ps(c, cls, 3.0 * c.psz * nl * c.B, st);
+      OKE(c, launch_mg_pre2<P>(g, B, l, b, db, r, st));
+    }
+    OKE(c, launch_restrict<P>(g, gc, B, cst(r), bc, st));
+    int e = mg_vcycle<P>(c, fl, l + 1, cst(bc), xc, true, st);
+    if (e) return e;
+    OKE(c, launch_prolong_add<P>(g, gc, B, cst(xc), db, st));
+    ProfScope ps(c, cls, 3.0 * c.psz * nl * c.B, st);
+    OKE(c, launch_mg_post2<P>(g, B, l, b, cst(db), x, st));
+    return OK_SUCCESS;
+  }
   int e = zero_start
               ? cheb_zero<P, P>(c, fl, cls, cls, g, l, CF_ONE, c.shape.mg_pre, b, x, r, da, db, st)
               : cheb_from<P>(c, fl, cls, g, l, c.shape.mg_pre, b, x, r, da, db, st);
@@ -359,8 +377,6 @@ int mg_vcycle(ClassCtx& c, const int* fl, int l, Vec<const P> b, Vec<P> x, bool 
     ProfScope ps(c, cls, 3.0 * c.psz * nl * c.B, st);
     OKE(c, launch_resid<P>(g, B, l, b, cst(x), r, st));
   }
-  const Grid& gc = c.lev[l + 1];
-  Vec<P> xc = pvec<P>(c.mg[l + 1][0], gc.nodes), bc = pvec<P>(c.mg[l + 1][1], gc.nodes);
   OKE(c, launch_restrict<P>(g, gc, B, cst(r), bc, st));
   e = mg_vcycle<P>(c, fl, l + 1, cst(bc), xc, true, st);
   if (e) return e;
@@ -1174,6 +1190,49 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
       }
     stencil_tune_set(g.dim, g.nn, 1, word, bi, bz, bt);
     if (bi) (*entries)++;
+    // fused smoothers of this level (pre-smoothing + residual, post-
+    // smoothing): shapes tuned one kernel at a time, kept where the pair
+    // beats the four one-iteration kernels it replaces
+    stencil_tune_set(g.dim, g.nn, kMgPreKey, word, 0, 0);
+    stencil_tune_set(g.dim, g.nn, kMgPostKey, word, 0, 0);
+    if (c.shape.mg_pre == 2 && c.shape.mg_post == 2 && mg_fusion_on(g, word)) {
+      Vec<P> bb = (l == 0) ? pvec<P>(c.cr2, nl) : pvec<P>(c.mg[l][1], nl);
+      const double unfused = time_best(st, [&]() {
+        hipError_t e = launch_cheb_first<P, P>(g, B, l, CF_ONE, true, cst(bb), x, r, d0, st);
+        if (e == hipSuccess) e = launch_resid<P>(g, B, l, cst(bb), cst(x), r, st);
+        if (e == hipSuccess) e = launch_cheb_start<P>(g, B, l, cst(bb), cst(x), r, d0, st);
+        if (e == hipSuccess)
+          e = launch_cheb_step<P>(g, B, l, 0, CF_ONE, true, x, r, cst(d0), d1, st);
+        return e;
+      });
+      double fused = 0.0;
+      for (int key : {kMgPreKey, kMgPostKey}) {
+        double kbest = 1e30;
+        int ki = 0, kz = 0, kt = 256;
+        for (int threads : {256, 512})
+          for (int items = 1; items <= 2; items++) {
+            if (!cheb2_shape_ok(g.dim, items, threads)) continue;
+            for (int zc : zchunk_candidates(g, items * threads, B.count)) {
+              stencil_tune_set(g.dim, g.nn, key, word, items, zc, threads);
+              if (!mg_fusion_on(g, word)) continue;
+              double t = time_best(st, [&]() {
+                return key == kMgPreKey ? launch_mg_pre2<P>(g, B, l, cst(bb), x, r, st)
+                                        : launch_mg_post2<P>(g, B, l, cst(bb), cst(x), d1, st);
+              });
+              if (t < kbest) {
+                kbest = t;
+                ki = items;
+                kz = zc;
+                kt = threads;
+              }
+            }
+          }
+        stencil_tune_set(g.dim, g.nn, key, word, ki, kz, kt);
+        fused += ki ? kbest : 1e30;
+      }
+      if (!(fused < unfused)) stencil_tune_set(g.dim, g.nn, kMgPostKey, word, -1, 0);
+      (*entries)++;
+    }
   }
   stencil_tune_set(c.lev[0].dim, c.lev[0].nn, kFusedKey, word, 0, 0);
   if (cheb_fusion_on(c.lev[0], word)) {  // fused pairs of Chebyshev iterations on M

@@ -97,7 +97,7 @@ StencilShape stencil_shape(const Grid& g, int nf, int word) {
   const int64_t plane = (g.dim == 3) ? g.plane : (int64_t)g.nn;
   // Largest per-thread item count that still gives ~1024 blocks with at
   // least 8 planes per block; small grids fall back to 1 item, 4 planes.
-  int items = (nf == kFusedKey) ? 2 : ((nf > 1) ? 4 : 8);
+  int items = (nf >= kFusedKey) ? 2 : ((nf > 1) ? 4 : 8);
   for (; items > 1; items /= 2) {
     int64_t nch = (plane + kThreads * items - 1) / (kThreads * items);
     if (nch * ((g.nn + 7) / 8) >= target) break;
@@ -880,7 +880,7 @@ __global__ void __launch_bounds__(NT)
     for (int q = 0; q < P1; q++) rq[q] = pr[q];
 #pragma unroll
     for (int p = 0; p < P; p++) xq[p] = px[p];
-    issue_a((int64_t)min(pz + 1, zlast) * plane);
+    issue_a((int64_t)max(min(pz + 1, zlast), 0) * plane);  // plane -1 is never read
     issue_rx(min(max(q1 + 1, 0), N), min(max(o + 1, 0), N));
     // stage 1: partials of d_k at plane pz over the extended chunk
     double pn1[P1], cn1[P1];
@@ -969,6 +969,280 @@ __global__ void __launch_bounds__(NT)
       for (int p = 0; p < P; p++) {
         pa2[p] = pb2[p];
         pb2[p] = pn2[p];
+        cb2[p] = cn2[p];
+      }
+    }
+  }
+}
+
+// In-plane partial products of M and K at LDS position L of plane buffer v
+// (node (i, j)): the arithmetic of the one-field streaming kernel, unscaled
+// or with the W^-1-scaled patterns (SCALED).
+template <int DIM, bool SCALED>
+__device__ __forceinline__ void mk_partials(const double* v, int L, int ystep, int i, int j, int N,
+                                            double& pm, double& pk) {
+  if constexpr (!SCALED) {
+    const bool hl = i > 0, hr = i < N, ex = (i == 0 || i == N);
+    if (DIM == 3) {
+      const bool ey = (j == 0 || j == N);
+      double mr[3], kr[3];
+#pragma unroll
+      for (int r = 0; r < 3; r++) {
+        const int base = L + (r - 1) * ystep;
+        const double va = v[base - 1], vb = v[base], vc = v[base + 1];
+        mr[r] = m1_row(hl, hr, ex, va, vb, vc);
+        kr[r] = k1_row(hl, hr, ex, va, vb, vc);
+      }
+      pm = m1_row(true, true, ey, mr[0], mr[1], mr[2]);
+      pk = m1_row(true, true, ey, kr[0], kr[1], kr[2]) + k1_row(true, true, ey, mr[0], mr[1], mr[2]);
+    } else {
+      const double va = v[L - 1], vb = v[L], vc = v[L + 1];
+      pm = m1_row(hl, hr, ex, va, vb, vc);
+      pk = k1_row(hl, hr, ex, va, vb, vc);
+    }
+  } else {
+    double ax0, ax1, ax2, bx0, bx1, bx2;
+    pattern<true>(i, N, ax0, ax1, ax2, bx0, bx1, bx2);
+    if (DIM == 3) {
+      double ay0, ay1, ay2, by0, by1, by2;
+      pattern<true>(j, N, ay0, ay1, ay2, by0, by1, by2);
+      double mr[3], kr[3];
+#pragma unroll
+      for (int r = 0; r < 3; r++) {
+        const int base = L + (r - 1) * ystep;
+        const double va = v[base - 1], vb = v[base], vc = v[base + 1];
+        mr[r] = sum3(ax0, ax1, ax2, va, vb, vc);
+        kr[r] = sum3(bx0, bx1, bx2, va, vb, vc);
+      }
+      pm = sum3(ay0, ay1, ay2, mr[0], mr[1], mr[2]);
+      pk = sum3(ay0, ay1, ay2, kr[0], kr[1], kr[2]) + sum3(by0, by1, by2, mr[0], mr[1], mr[2]);
+    } else {
+      const double va = v[L - 1], vb = v[L], vc = v[L + 1];
+      pm = sum3(ax0, ax1, ax2, va, vb, vc);
+      pk = sum3(bx0, bx1, bx2, va, vb, vc);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The two Chebyshev iterations of a multigrid smoother (Saad, Alg. 12.1, on
+// A = M + alpha K of level lev) fused with their neighbour in the V-cycle, in
+// one streaming pass (temporal blocking along the streaming axis as in
+// k_cheb2):
+//   PRE  (pre-smoothing from x = 0, then the residual): stage 1 forms
+//        x2 = osc (d0 + d1), d0 = D^-1 b it, on the chunk plus a one-row halo
+//        from the W^-1-scaled stencil of b; stage 2 applies A to x2 and
+//        writes x2 (out1) and r = b - A x2 (out2).
+//   POST (post-smoothing from a given x): stage 1 forms r0 = b - A x and
+//        d0 = D^-1 r0 it on the chunk plus halo; stage 2 applies A to d0 and
+//        writes x + d0 + d1 to out1, a buffer other than x (x is read on halo
+//        rows that other blocks own).
+// Every value the one-iteration kernels store is rounded to T at the same
+// point, so the outputs are bitwise those of launch_cheb_first + launch_resid
+// (PRE) and launch_cheb_start + launch_cheb_step (POST).  av: the stenciled
+// input (PRE b, POST x); bv: POST b.  LDS as in k_cheb2: the input plane with
+// a two-row halo, the stage-1 field with a one-row halo, and two buffers each
+// of the chunk values stage 2 needs (POST r0; the input's chunk values).
+// ---------------------------------------------------------------------------
+template <int DIM, int NT, int P, int P1, int FA, class T, bool PRE>
+__global__ void __launch_bounds__(NT)
+    k_mg2(Grid g, StencilShape sh, Batch B, int lev, Vec<const T> av, Vec<const T> bv,
+          Vec<T> out1v, Vec<T> out2v) {
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int inst = lb / sh.blocks;
+  if (B.act && !B.act[inst]) return;
+  const int b = lb - inst * sh.blocks;
+  const int chunk = b % sh.nchunks;
+  const int zch = b / sh.nchunks;
+  const InstCoef& IC = B.coef[inst];
+  const OpK k1 = PRE ? op_k(IC, lev, 0, CF_ONE) : op_k(IC, lev, -1, CF_ONE);
+  const OpK k2 = PRE ? op_k(IC, lev, -1, CF_ONE) : op_k(IC, lev, 0, CF_ONE);
+  const int nn = g.nn, N = g.N;
+  const int64_t plane = (DIM == 3) ? g.plane : (int64_t)nn;
+  const int H = (DIM == 3) ? nn + 1 : 1;
+  const int CH = sh.chunk;
+  const int E1 = CH + 2 * H, E2 = CH + 4 * H;
+  double* LA = lds;
+  double* LB = LA + E2;
+  double* LR = LB + E1;
+  double* LD = LR + 2 * CH;
+  const int64_t s0 = (int64_t)chunk * CH;
+  const T* __restrict__ a = av.at(inst);
+  const T* __restrict__ bsrc = PRE ? nullptr : bv.at(inst);
+  T* __restrict__ o1 = out1v.at(inst);
+  T* __restrict__ o2 = PRE ? out2v.at(inst) : nullptr;
+  const int ystep = (DIM == 3) ? nn : 0;
+
+  int i1[P1], j1[P1];
+  bool v1[P1];
+#pragma unroll
+  for (int q = 0; q < P1; q++) {
+    const int e = tid + NT * q;
+    const int64_t gq = s0 - H + e;
+    v1[q] = (e < E1) && gq >= 0 && gq < plane;
+    const int64_t gc = gq < 0 ? 0 : (gq >= plane ? plane - 1 : gq);
+    j1[q] = (DIM == 3) ? (int)(gc / nn) : 0;
+    i1[q] = (int)(gc - (int64_t)j1[q] * nn);
+  }
+  int i2[P], j2[P];
+  bool v2[P];
+#pragma unroll
+  for (int p = 0; p < P; p++) {
+    const int64_t gq = s0 + tid + NT * p;
+    v2[p] = gq < plane;
+    const int64_t gc = gq < plane ? gq : plane - 1;
+    j2[p] = (DIM == 3) ? (int)(gc / nn) : 0;
+    i2[p] = (int)(gc - (int64_t)j2[p] * nn);
+  }
+  auto clampq = [&](int64_t gq) { return gq < 0 ? (int64_t)0 : (gq >= plane ? plane - 1 : gq); };
+
+  T pa[FA], pr[P1];
+  auto issue_a = [&](int64_t zoff) {
+#pragma unroll
+    for (int k = 0; k < FA; k++) pa[k] = a[zoff + clampq(s0 - 2 * H + tid + NT * k)];
+  };
+  auto issue_b = [&](int zr) {
+    if constexpr (!PRE) {
+#pragma unroll
+      for (int q = 0; q < P1; q++) pr[q] = bsrc[(int64_t)zr * plane + clampq(s0 - H + tid + NT * q)];
+    }
+  };
+
+  const double h = g.h;
+  const double cmass = (DIM == 3) ? h * h * h / 216.0 : h * h / 36.0;
+  const double cstiff = (DIM == 3) ? h / 36.0 : 1.0 / 6.0;
+  int z0, z1;
+  zrange(sh, nn, zch, z0, z1);
+  const int zlast = min(z1 + 1, N);
+  double pa1[P1], pb1[P1], qa1[P1], qb1[P1], cb1[P1];
+  double pa2[P], pb2[P], qa2[P], qb2[P], cb2[P];
+#pragma unroll
+  for (int q = 0; q < P1; q++) pa1[q] = pb1[q] = qa1[q] = qb1[q] = cb1[q] = 0.0;
+#pragma unroll
+  for (int p = 0; p < P; p++) pa2[p] = pb2[p] = qa2[p] = qb2[p] = cb2[p] = 0.0;
+  issue_a((int64_t)max(z0 - 2, 0) * plane);
+  issue_b(max(z0 - 1, 0));
+  for (int pz = z0 - 2; pz <= z1 + 1; pz++) {
+    const bool insideA = (pz >= 0 && pz <= N);
+    const int q1 = pz - 1;  // stage-1 output plane
+    const int o = pz - 2;   // stage-2 output plane
+    const int buf = pz & 1;
+    __syncthreads();
+    if (insideA) {
+#pragma unroll
+      for (int k = 0; k < FA; k++) {
+        const int t = tid + NT * k;
+        const int64_t gq = s0 - 2 * H + t;
+        if (t < E2) LA[t] = (gq >= 0 && gq < plane) ? to_d(pa[k]) : 0.0;
+      }
+    }
+    __syncthreads();
+    T bq[P1];
+#pragma unroll
+    for (int q = 0; q < P1; q++) bq[q] = pr[q];
+    issue_a((int64_t)max(min(pz + 1, zlast), 0) * plane);  // plane -1 is never read
+    issue_b(min(max(q1 + 1, 0), N));
+    double pn1[P1], qn1[P1], cn1[P1];
+#pragma unroll
+    for (int q = 0; q < P1; q++) {
+      const int L = tid + NT * q + H;
+      pn1[q] = qn1[q] = cn1[q] = 0.0;
+      if (insideA && (tid + NT * q < E1)) {
+        mk_partials<DIM, PRE>(LA, L, ystep, i1[q], j1[q], N, pn1[q], qn1[q]);
+        cn1[q] = LA[L];
+      }
+    }
+    if (q1 >= z0 - 1 && q1 <= z1) {
+      const bool inq = (q1 >= 0 && q1 <= N);
+      double az0 = 0, az1 = 0, az2 = 0, bz0 = 0, bz1 = 0, bz2 = 0;
+      if (inq) pattern<PRE>(q1, N, az0, az1, az2, bz0, bz1, bz2);
+      const int nbz = (q1 == 0 || q1 == N);
+#pragma unroll
+      for (int q = 0; q < P1; q++) {
+        const int e = tid + NT * q;
+        if (e >= E1) continue;
+        double f1 = 0.0;
+        if (inq && v1[q]) {
+          const double ms = cmass * sum3(az0, az1, az2, pa1[q], pb1[q], pn1[q]);
+          const double ks = cstiff * (sum3(az0, az1, az2, qa1[q], qb1[q], qn1[q]) +
+                                      sum3(bz0, bz1, bz2, pa1[q], pb1[q], pn1[q]));
+          int nb = (i1[q] == 0 || i1[q] == N) + nbz;
+          if (DIM == 3) nb += (j1[q] == 0 || j1[q] == N);
+          const double dv = dinv_at(k1.dinv, nb);
+          const int c = e - H;
+          if constexpr (PRE) {
+            const double bi = cb1[q];
+            const double ad0 = k1.dinv * k1.it * op_apply(k1, ms, ks);
+            const double d0 = dv * bi * k1.it;
+            const double r1 = bi - ad0;
+            const double d1 = cheb_dir(k1, d0, dv, r1);
+            f1 = to_d((T)(k1.osc * (d0 + d1)));
+            if (c >= 0 && c < CH) LD[buf * CH + c] = bi;
+          } else {
+            const double r0 = to_d(bq[q]) - op_apply(k1, ms, ks);
+            f1 = to_d((T)(dv * r0 * k1.it));
+            if (c >= 0 && c < CH) {
+              LR[buf * CH + c] = to_d((T)r0);
+              LD[buf * CH + c] = cb1[q];
+            }
+          }
+        }
+        LB[e] = f1;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < P1; q++) {
+      pa1[q] = pb1[q];
+      pb1[q] = pn1[q];
+      qa1[q] = qb1[q];
+      qb1[q] = qn1[q];
+      cb1[q] = cn1[q];
+    }
+    __syncthreads();
+    if (q1 >= z0 - 1 && q1 <= z1) {
+      double pn2[P], qn2[P], cn2[P];
+#pragma unroll
+      for (int p = 0; p < P; p++) {
+        const int L = tid + NT * p + H;
+        mk_partials<DIM, false>(LB, L, ystep, i2[p], j2[p], N, pn2[p], qn2[p]);
+        cn2[p] = LB[L];
+      }
+      if (o >= z0 && o < z1) {
+        double az0, az1, az2, bz0, bz1, bz2;
+        pattern<false>(o, N, az0, az1, az2, bz0, bz1, bz2);
+        const int nbz = (o == 0 || o == N);
+        const int pb = buf ^ 1;
+#pragma unroll
+        for (int p = 0; p < P; p++) {
+          if (!v2[p]) continue;
+          const int c = tid + NT * p;
+          const double ms = cmass * sum3(az0, az1, az2, pa2[p], pb2[p], pn2[p]);
+          const double ks = cstiff * (sum3(az0, az1, az2, qa2[p], qb2[p], qn2[p]) +
+                                      sum3(bz0, bz1, bz2, pa2[p], pb2[p], pn2[p]));
+          const int64_t idx = (int64_t)o * plane + s0 + c;
+          if constexpr (PRE) {
+            o1[idx] = (T)cb2[p];
+            o2[idx] = (T)(LD[pb * CH + c] - op_apply(k2, ms, ks));
+          } else {
+            int nb = (i2[p] == 0 || i2[p] == N) + nbz;
+            if (DIM == 3) nb += (j2[p] == 0 || j2[p] == N);
+            const double dk = cb2[p];
+            const double dv = dinv_at(k2.dinv, nb);
+            const double xv = LD[pb * CH + c] + dk;
+            const double rv = LR[pb * CH + c] - op_apply(k2, ms, ks);
+            const double d1 = cheb_dir(k2, dk, dv, rv);
+            o1[idx] = (T)(k2.osc * (xv + d1));
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < P; p++) {
+        pa2[p] = pb2[p];
+        pb2[p] = pn2[p];
+        qa2[p] = qb2[p];
+        qb2[p] = qn2[p];
         cb2[p] = cn2[p];
       }
     }
@@ -1140,7 +1414,31 @@ hipError_t launch_cheb2_ex(const Grid& g, const Batch& B, const StencilShape& sh
 #if OKD_STENCIL_PART == 0
 namespace {
 int g_fuse_cheb = 1;
+int g_fuse_mg = 1;
 }  // namespace
+
+void mg_fusion_set(int enable) { g_fuse_mg = enable ? 1 : 0; }
+
+bool mg_fusion_on(const Grid& g, int word) {
+  if (!g_fuse_mg) return false;
+  {
+    // the autotuner records items < 0 where the fused smoothers lost
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(g.dim, g.nn, kMgPostKey, word));
+    if (it != g_tune.end() && std::get<0>(it->second) < 0) return false;
+  }
+  const int H = (g.dim == 3) ? g.nn + 1 : 1;
+  for (int key : {kMgPreKey, kMgPostKey}) {
+    const StencilShape sh = stencil_shape(g, key, word);
+    if (!cheb2_shape_ok(g.dim, sh.items, sh.threads)) return false;
+    const Cheb2Geom c = cheb2_geom(g, sh);
+    const bool combo = (g.dim == 2) ? (c.ex1 == 1 && c.exa == 1)
+                                    : ((c.ex1 == 1 && c.exa <= 2) || (c.ex1 == 2 && c.exa == 3) ||
+                                       (c.ex1 == 3 && c.exa == 5) || (c.ex1 == 5 && c.exa == 9));
+    if (!combo || (size_t)(6 * sh.chunk + 6 * H) * sizeof(double) > 65536) return false;
+  }
+  return true;
+}
 
 void cheb_fusion_set(int enable) { g_fuse_cheb = enable ? 1 : 0; }
 
@@ -1193,6 +1491,78 @@ hipError_t launch_cheb_step2(const Grid& g, const Batch& B, int k, int osc, bool
   if (c.p == 1)
     return launch_cheb2_ex<3, 256, 1, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
   return launch_cheb2_ex<3, 256, 2, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
+}
+
+namespace {
+template <int DIM, int NT, int P, int EX1, int EXA, class T, bool PRE>
+hipError_t launch_mg2_p(const Grid& g, const Batch& B, const StencilShape& sh, int lev,
+                        Vec<const T> a, Vec<const T> b, Vec<T> o1, Vec<T> o2, hipStream_t st) {
+  const int H = (DIM == 3) ? g.nn + 1 : 1;
+  if (sh.chunk != NT * P) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(sh.chunk + 4 * H + sh.chunk + 2 * H + 4 * sh.chunk) * sizeof(double);
+  if (lds > 65536) return hipErrorInvalidValue;
+  const int64_t nblk = (int64_t)sh.blocks * B.count;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_mg2<DIM, NT, P, P + EX1, P + EXA, T, PRE>), dim3((unsigned)nblk), dim3(NT),
+                     lds, st, g, sh, B, lev, a, b, o1, o2);
+  return hipGetLastError();
+}
+
+template <int DIM, int NT, int P, class T, bool PRE>
+hipError_t launch_mg2_ex(const Grid& g, const Batch& B, const StencilShape& sh,
+                         const Cheb2Geom& c, int lev, Vec<const T> a, Vec<const T> b, Vec<T> o1,
+                         Vec<T> o2, hipStream_t st) {
+#define OK_MG2(E1, EA)                                                                          \
+  if (c.ex1 == E1 && c.exa == EA)                                                               \
+    return launch_mg2_p<DIM, NT, P, E1, EA, T, PRE>(g, B, sh, lev, a, b, o1, o2, st);
+  if (DIM == 2) {
+    OK_MG2(1, 1)
+    return hipErrorInvalidValue;
+  }
+  OK_MG2(1, 1)
+  OK_MG2(1, 2)
+  OK_MG2(2, 3)
+  OK_MG2(3, 5)
+  OK_MG2(5, 9)
+#undef OK_MG2
+  return hipErrorInvalidValue;
+}
+
+template <class T, bool PRE>
+hipError_t launch_mg2(const Grid& g, const Batch& B, int lev, Vec<const T> a, Vec<const T> b,
+                      Vec<T> o1, Vec<T> o2, hipStream_t st) {
+  if (lev < 0 || lev >= kMaxLevels || B.count < 1) return hipErrorInvalidValue;
+  const StencilShape sh = stencil_shape(g, PRE ? kMgPreKey : kMgPostKey, (int)sizeof(T));
+  if (!cheb2_shape_ok(g.dim, sh.items, sh.threads)) return hipErrorInvalidValue;
+  const Cheb2Geom c = cheb2_geom(g, sh);
+  if (g.dim == 2) {
+    if (c.p == 1)
+      return launch_mg2_ex<2, 256, 1, T, PRE>(g, B, sh, c, lev, a, b, o1, o2, st);
+    return launch_mg2_ex<2, 256, 2, T, PRE>(g, B, sh, c, lev, a, b, o1, o2, st);
+  }
+  if (c.nt == 512) {
+    if (c.p == 1)
+      return launch_mg2_ex<3, 512, 1, T, PRE>(g, B, sh, c, lev, a, b, o1, o2, st);
+    return launch_mg2_ex<3, 512, 2, T, PRE>(g, B, sh, c, lev, a, b, o1, o2, st);
+  }
+  if (c.p == 1)
+    return launch_mg2_ex<3, 256, 1, T, PRE>(g, B, sh, c, lev, a, b, o1, o2, st);
+  return launch_mg2_ex<3, 256, 2, T, PRE>(g, B, sh, c, lev, a, b, o1, o2, st);
+}
+}  // namespace
+
+template <class T>
+hipError_t launch_mg_pre2(const Grid& g, const Batch& B, int lev, Vec<const T> b, Vec<T> x2,
+                          Vec<T> r, hipStream_t st) {
+  if (x2.null() || r.null() || x2.p == r.p) return hipErrorInvalidValue;
+  return launch_mg2<T, true>(g, B, lev, b, Vec<const T>{nullptr, 0}, x2, r, st);
+}
+
+template <class T>
+hipError_t launch_mg_post2(const Grid& g, const Batch& B, int lev, Vec<const T> b,
+                           Vec<const T> x, Vec<T> xout, hipStream_t st) {
+  if (xout.null() || (const T*)xout.p == x.p) return hipErrorInvalidValue;
+  return launch_mg2<T, false>(g, B, lev, x, b, xout, Vec<T>{nullptr, 0}, st);
 }
 
 template <class T>
@@ -1275,7 +1645,11 @@ template hipError_t launch_couple<float>(const Grid&, const Batch&, Vec<const fl
   template hipError_t launch_add_inplace<T>(const Batch&, Vec<T>, Vec<const T>, int64_t,       \
                                             hipStream_t);                                      \
   template hipError_t launch_resid<T>(const Grid&, const Batch&, int, Vec<const T>,            \
-                                      Vec<const T>, Vec<T>, hipStream_t);
+                                      Vec<const T>, Vec<T>, hipStream_t);                      \
+  template hipError_t launch_mg_pre2<T>(const Grid&, const Batch&, int, Vec<const T>, Vec<T>,  \
+                                        Vec<T>, hipStream_t);                                  \
+  template hipError_t launch_mg_post2<T>(const Grid&, const Batch&, int, Vec<const T>,         \
+                                         Vec<const T>, Vec<T>, hipStream_t);
 #if OKD_STENCIL_PART == 0
 OKD_CHEB_TB(double, double)
 OKD_CHEB_T(double)

@@ -311,6 +311,9 @@ int ok_set_option(int32_t option, int32_t value) {
     case OK_OPT_FUSE_CHEB:
       cheb_fusion_set(value);
       return OK_SUCCESS;
+    case OK_OPT_FUSE_MG:
+      mg_fusion_set(value);
+      return OK_SUCCESS;
     default:
       return OK_E_INVALID;
   }
@@ -325,6 +328,8 @@ int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precisio
     case OK_SHAPE_STENCIL: nf = 1; break;
     case OK_SHAPE_STENCIL2: nf = 2; break;
     case OK_SHAPE_CHEB2: nf = kFusedKey; break;
+    case OK_SHAPE_MG_PRE: nf = kMgPreKey; break;
+    case OK_SHAPE_MG_POST: nf = kMgPostKey; break;
     default: return OK_E_INVALID;
   }
   const int word = precision == OK_MIXED ? 4 : 8;
@@ -332,7 +337,7 @@ int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precisio
     stencil_tune_set(dim, n + 1, nf, word, 0, 0);
     return OK_SUCCESS;
   }
-  const bool ok_shape = (nf == kFusedKey) ? cheb2_shape_ok(dim, items, threads)
+  const bool ok_shape = (nf >= kFusedKey) ? cheb2_shape_ok(dim, items, threads)
                                           : stencil_shape_ok(dim, nf, items, threads);
   if (!ok_shape || zchunks < 1 || zchunks > n + 1) return OK_E_INVALID;
   stencil_tune_set(dim, n + 1, nf, word, items, zchunks, threads);

@@ -123,6 +123,9 @@ __device__ __forceinline__ void zrange(const StencilShape& sh, int nn, int zch, 
 StencilShape stencil_shape(const Grid& g, int nf, int word);
 // Shape-table key of the fused two-iteration Chebyshev kernel (in place of nf).
 constexpr int kFusedKey = 17;
+// Shape-table keys of the fused multigrid smoother kernels (pre-smoothing +
+// residual, post-smoothing).
+constexpr int kMgPreKey = 18, kMgPostKey = 19;
 // Launch-shape table of the stencil kernels, keyed by (dim, nodes per
 // direction, stenciled fields, bytes per stenciled word); items < 0 marks the
 // fused Chebyshev kernel as slower than single steps on that grid; items == 0 removes
@@ -165,6 +168,16 @@ hipError_t launch_cheb_step2(const Grid& g, const Batch& B, int k, int osc, bool
 // cheb_fusion_on: the switch is on and the fused kernel supports grid g.
 void cheb_fusion_set(int enable);
 bool cheb_fusion_on(const Grid& g, int word);
+// Fused multigrid smoothers (two Chebyshev iterations before and after the
+// coarse-grid correction, each in one pass with its neighbour).
+void mg_fusion_set(int enable);
+bool mg_fusion_on(const Grid& g, int word);
+template <class T>
+hipError_t launch_mg_pre2(const Grid& g, const Batch& B, int lev, Vec<const T> b, Vec<T> x2,
+                          Vec<T> r, hipStream_t st);
+template <class T>
+hipError_t launch_mg_post2(const Grid& g, const Batch& B, int lev, Vec<const T> b,
+                           Vec<const T> x, Vec<T> xout, hipStream_t st);
 // Launch shapes that have instantiated kernels (items per thread, threads).
 bool stencil_shape_ok(int dim, int nf, int items, int threads);
 bool cheb2_shape_ok(int dim, int items, int threads);

@@ -400,6 +400,7 @@ class Batch:
 
 
 OK_OPT_FUSE_CHEB = 1
+OK_OPT_FUSE_MG = 2
 
 
 def set_option(option: int, value: int):
@@ -409,7 +410,7 @@ def set_option(option: int, value: int):
         raise OkError(st, "ok_set_option")
 
 
-OK_SHAPE_STENCIL, OK_SHAPE_STENCIL2, OK_SHAPE_CHEB2 = 1, 2, 3
+OK_SHAPE_STENCIL, OK_SHAPE_STENCIL2, OK_SHAPE_CHEB2, OK_SHAPE_MG_PRE, OK_SHAPE_MG_POST = 1, 2, 3, 4, 5
 
 
 def set_launch_shape(dim: int, n: int, kernel: int, precision: int, items: int,

@@ -118,6 +118,7 @@ def test_launch_shape_arguments(lib):
     assert f(4, 64, 1, 0, 4, 256, 5) == E      # dim
     assert f(3, 0, 1, 0, 4, 256, 5) == E       # n
     assert f(3, 64, 9, 0, 4, 256, 5) == E      # kernel
+    assert f(3, 64, 6, 0, 2, 256, 5) == E
     assert f(3, 64, 1, 2, 4, 256, 5) == E      # precision
     assert f(3, 64, 1, 0, 3, 256, 5) == E      # items
     assert f(3, 64, 1, 0, 8, 512, 5) == E      # 512 threads: at most 4 nodes
@@ -126,5 +127,9 @@ def test_launch_shape_arguments(lib):
     assert f(3, 64, 2, 0, 8, 256, 5) == E      # two fields: at most 4 nodes
     assert f(3, 64, 3, 0, 4, 256, 5) == E      # fused pair: 1 or 2 nodes
     assert f(2, 64, 3, 0, 2, 512, 5) == E      # fused 512-thread pair: 3D only
+    assert f(3, 64, 4, 0, 2, 512, 9) == 0      # fused multigrid smoothers
+    assert f(3, 64, 5, 1, 1, 256, 9) == 0
+    assert f(3, 64, 4, 0, 0, 0, 0) == 0 and f(3, 64, 5, 1, 0, 0, 0) == 0
+    assert f(3, 64, 5, 0, 4, 256, 9) == E
     assert f(3, 64, 1, 0, 4, 256, 0) == E      # zchunks
     assert f(3, 64, 1, 0, 4, 256, 66) == E
