@@ -217,11 +217,11 @@ int ok_initial_w(ok_ctx *ctx, const double *d_u, double *d_w, void *stream);
  *   OK_OPT_FUSE_CHEB: 1 (default) runs consecutive middle iterations of the
  *   Chebyshev iteration on M two per pass (each vector read and written once
  *   per pair); 0 runs them one per pass.
- *   OK_OPT_FUSE_MG: 1 (default) runs, on multigrid levels where the
- *   autotuner (or the default shape) keeps it, the two pre-smoothing
- *   iterations with the residual in one pass and the two post-smoothing
- *   iterations in one pass (V(2,2) cycles); 0 runs every iteration and the
- *   residual in passes of their own. */
+ *   OK_OPT_FUSE_MG: 1 (default) runs, on multigrid levels where ok_autotune
+ *   found it faster (or where ok_set_launch_shape set OK_SHAPE_MG_POST), the
+ *   two pre-smoothing iterations with the residual in one pass and the two
+ *   post-smoothing iterations in one pass (V(2,2) cycles); 0 runs every
+ *   iteration and the residual in passes of their own everywhere. */
 enum ok_option { OK_OPT_FUSE_CHEB = 1, OK_OPT_FUSE_MG = 2 };
 int ok_set_option(int32_t option, int32_t value);
 

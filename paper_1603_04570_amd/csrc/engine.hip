@@ -1195,7 +1195,7 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
     // beats the four one-iteration kernels it replaces
     stencil_tune_set(g.dim, g.nn, kMgPreKey, word, 0, 0);
     stencil_tune_set(g.dim, g.nn, kMgPostKey, word, 0, 0);
-    if (c.shape.mg_pre == 2 && c.shape.mg_post == 2 && mg_fusion_on(g, word)) {
+    if (c.shape.mg_pre == 2 && c.shape.mg_post == 2 && mg_fusion_enabled()) {
       Vec<P> bb = (l == 0) ? pvec<P>(c.cr2, nl) : pvec<P>(c.mg[l][1], nl);
       const double unfused = time_best(st, [&]() {
         hipError_t e = launch_cheb_first<P, P>(g, B, l, CF_ONE, true, cst(bb), x, r, d0, st);
@@ -1214,7 +1214,7 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
             if (!cheb2_shape_ok(g.dim, items, threads)) continue;
             for (int zc : zchunk_candidates(g, items * threads, B.count)) {
               stencil_tune_set(g.dim, g.nn, key, word, items, zc, threads);
-              if (!mg_fusion_on(g, word)) continue;
+              if (!mg2_shape_valid(g, key, word)) continue;
               double t = time_best(st, [&]() {
                 return key == kMgPreKey ? launch_mg_pre2<P>(g, B, l, cst(bb), x, r, st)
                                         : launch_mg_post2<P>(g, B, l, cst(bb), cst(x), d1, st);
@@ -1230,7 +1230,10 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
         stencil_tune_set(g.dim, g.nn, key, word, ki, kz, kt);
         fused += ki ? kbest : 1e30;
       }
-      if (!(fused < unfused)) stencil_tune_set(g.dim, g.nn, kMgPostKey, word, -1, 0);
+      if (!(fused < unfused)) {
+        stencil_tune_set(g.dim, g.nn, kMgPreKey, word, 0, 0);
+        stencil_tune_set(g.dim, g.nn, kMgPostKey, word, 0, 0);
+      }
       (*entries)++;
     }
   }

@@ -1397,17 +1397,18 @@ hipError_t launch_cheb2_ex(const Grid& g, const Batch& B, const StencilShape& sh
   if (c.ex1 == E1 && c.exa == EA)                                                              \
     return launch_cheb2_p<DIM, NT, P, E1, EA, T>(g, B, sh, k, osc, last2, x, r, rout, din, dout, \
                                                  st);
-  if (DIM == 2) {
+  if constexpr (DIM == 2) {
     OK_CHEB2(1, 1)
     return hipErrorInvalidValue;
-  }
+  } else {
   OK_CHEB2(1, 1)
   OK_CHEB2(1, 2)
   OK_CHEB2(2, 3)
   OK_CHEB2(3, 5)
   OK_CHEB2(5, 9)
-#undef OK_CHEB2
   return hipErrorInvalidValue;
+  }
+#undef OK_CHEB2
 }
 }  // namespace
 
@@ -1419,25 +1420,30 @@ int g_fuse_mg = 1;
 
 void mg_fusion_set(int enable) { g_fuse_mg = enable ? 1 : 0; }
 
+bool mg_fusion_enabled() { return g_fuse_mg != 0; }
+
+bool mg2_shape_valid(const Grid& g, int key, int word) {
+  const int H = (g.dim == 3) ? g.nn + 1 : 1;
+  const StencilShape sh = stencil_shape(g, key, word);
+  if (!cheb2_shape_ok(g.dim, sh.items, sh.threads)) return false;
+  const Cheb2Geom c = cheb2_geom(g, sh);
+  const bool combo = (g.dim == 2) ? (c.ex1 == 1 && c.exa == 1)
+                                  : ((c.ex1 == 1 && c.exa <= 2) || (c.ex1 == 2 && c.exa == 3) ||
+                                     (c.ex1 == 3 && c.exa == 5) || (c.ex1 == 5 && c.exa == 9));
+  return combo && (size_t)(6 * sh.chunk + 6 * H) * sizeof(double) <= 65536;
+}
+
+// The fused smoothers hold many more registers than the one-iteration
+// kernels and win only on some grids: a level uses them only where the
+// autotuner (or ok_set_launch_shape) has set the post-smoothing shape.
 bool mg_fusion_on(const Grid& g, int word) {
   if (!g_fuse_mg) return false;
   {
-    // the autotuner records items < 0 where the fused smoothers lost
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(std::make_tuple(g.dim, g.nn, kMgPostKey, word));
-    if (it != g_tune.end() && std::get<0>(it->second) < 0) return false;
+    if (it == g_tune.end() || std::get<0>(it->second) <= 0) return false;
   }
-  const int H = (g.dim == 3) ? g.nn + 1 : 1;
-  for (int key : {kMgPreKey, kMgPostKey}) {
-    const StencilShape sh = stencil_shape(g, key, word);
-    if (!cheb2_shape_ok(g.dim, sh.items, sh.threads)) return false;
-    const Cheb2Geom c = cheb2_geom(g, sh);
-    const bool combo = (g.dim == 2) ? (c.ex1 == 1 && c.exa == 1)
-                                    : ((c.ex1 == 1 && c.exa <= 2) || (c.ex1 == 2 && c.exa == 3) ||
-                                       (c.ex1 == 3 && c.exa == 5) || (c.ex1 == 5 && c.exa == 9));
-    if (!combo || (size_t)(6 * sh.chunk + 6 * H) * sizeof(double) > 65536) return false;
-  }
-  return true;
+  return mg2_shape_valid(g, kMgPreKey, word) && mg2_shape_valid(g, kMgPostKey, word);
 }
 
 void cheb_fusion_set(int enable) { g_fuse_cheb = enable ? 1 : 0; }
@@ -1515,17 +1521,18 @@ hipError_t launch_mg2_ex(const Grid& g, const Batch& B, const StencilShape& sh,
 #define OK_MG2(E1, EA)                                                                          \
   if (c.ex1 == E1 && c.exa == EA)                                                               \
     return launch_mg2_p<DIM, NT, P, E1, EA, T, PRE>(g, B, sh, lev, a, b, o1, o2, st);
-  if (DIM == 2) {
+  if constexpr (DIM == 2) {
     OK_MG2(1, 1)
     return hipErrorInvalidValue;
-  }
+  } else {
   OK_MG2(1, 1)
   OK_MG2(1, 2)
   OK_MG2(2, 3)
   OK_MG2(3, 5)
   OK_MG2(5, 9)
-#undef OK_MG2
   return hipErrorInvalidValue;
+  }
+#undef OK_MG2
 }
 
 template <class T, bool PRE>

@@ -171,6 +171,8 @@ bool cheb_fusion_on(const Grid& g, int word);
 // Fused multigrid smoothers (two Chebyshev iterations before and after the
 // coarse-grid correction, each in one pass with its neighbour).
 void mg_fusion_set(int enable);
+bool mg_fusion_enabled();
+bool mg2_shape_valid(const Grid& g, int key, int word);
 bool mg_fusion_on(const Grid& g, int word);
 template <class T>
 hipError_t launch_mg_pre2(const Grid& g, const Batch& B, int lev, Vec<const T> b, Vec<T> x2,

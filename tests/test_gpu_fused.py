@@ -82,13 +82,21 @@ def run_both_mg(fn):
                                              (3, 128, 0)])
 def test_fused_multigrid_smoothers_bitwise(dim, n, precision):
     """V(2,2) cycles with the fused smoother kernels (pre-smoothing with the
-    residual, post-smoothing in one pass) reproduce the one-iteration kernels
-    bit for bit over a whole timestep."""
+    residual, post-smoothing in one pass) on every level above the coarsest
+    reproduce the one-iteration kernels bit for bit over a whole timestep."""
     from paper_1603_04570_amd import ok
     p = ok.default_params(dim=dim, n=n, eps=0.02, sigma=100.0, m=0.1,
                           dt=2e-4 if dim == 3 else 1e-4, precision=precision)
     u0, w0 = noise_state(dim, n, 0.1, 29)
     print("fused mg", dim, n, precision, flush=True)
+    levels = []
+    k = n
+    while k > 8:  # the levels the smoothers run on (coarsest: 8 elements)
+        levels.append(k)
+        k //= 2
+    for lev_n in levels:  # pin a shape: the levels then use the fused kernels
+        for kern in (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST):
+            ok.set_launch_shape(dim, lev_n, kern, precision, 1, 256, max(1, (lev_n + 1) // 4))
 
     def once():
         P = ok.Problem(p)
@@ -97,6 +105,11 @@ def test_fused_multigrid_smoothers_bitwise(dim, n, precision):
         st = P.timestep(u, w, 1)
         return u.cpu().numpy(), w.cpu().numpy(), st.its()
 
-    (ua, wa, ia), (ub, wb, ib) = run_both_mg(once)
+    try:
+        (ua, wa, ia), (ub, wb, ib) = run_both_mg(once)
+    finally:
+        for lev_n in levels:
+            for kern in (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST):
+                ok.set_launch_shape(dim, lev_n, kern, precision, 0)
     assert ia == ib
     assert np.array_equal(ua, ub) and np.array_equal(wa, wb)
