@@ -42,11 +42,20 @@ struct ClassExec {
   hipStream_t xs = nullptr;           // class stream (default priority, non-blocking)
   hipEvent_t fork = nullptr, join = nullptr;
   std::vector<hipGraphExec_t> iter;   // one graph per Arnoldi index j
-  int* hflags = nullptr;              // pinned host copy of the activity flags [B]
   const void* key = nullptr;          // state pointer the graphs were captured with
   bool graphs = true;
   void clear_graphs();
   ~ClassExec();
+};
+
+// Pinned two-slot host copy of the activity flags with an event per slot:
+// the FGMRES driver reads the flags that iteration j-1 left while iteration j
+// already runs (owned; released with the class).
+struct FlagPipe {
+  int* h = nullptr;                      // [2][B]
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int pend[2] = {-1, -1};               // iteration whose flags each slot receives
+  ~FlagPipe();
 };
 
 struct ClassCtx {
@@ -83,6 +92,7 @@ struct ClassCtx {
   std::string* err = nullptr;
   std::unique_ptr<ClassExec> ex;  // null: iterations are launched one kernel at a time on
                                   // the caller's stream
+  std::unique_ptr<FlagPipe> fp;   // created by the first FGMRES solve
 
   int64_t n2() const { return 2 * n; }
   Batch batch(const int* flags) const { return Batch{B, coef, flags}; }

@@ -21,7 +21,12 @@ ClassExec::~ClassExec() {
   if (fork) (void)hipEventDestroy(fork);
   if (join) (void)hipEventDestroy(join);
   if (xs) (void)hipStreamDestroy(xs);
-  if (hflags) (void)hipHostFree(hflags);
+}
+
+FlagPipe::~FlagPipe() {
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (h) (void)hipHostFree(h);
 }
 
 Prof::~Prof() {
@@ -287,13 +292,19 @@ int cheb_zero(ClassCtx& c, const int* fl, int cls, int step_cls, const Grid& g, 
       std::swap(dc, dn);
       k++;
     }
-    for (; k <= K - 2; k += 2) {
-      const bool last2 = (k + 1 == K - 2);
-      ProfScope ps(c, last2 ? cls : step_cls, (last2 ? 4.0 : 6.0) * w, st);
-      OKE(c, launch_cheb_step2<P>(g, B, k, osc, last2, x, cst(rc), rn, cst(dc), dn, st));
-      std::swap(dc, dn);
-      std::swap(rc, rn);
+    // the middle pairs timed as one contiguous run (events between launches
+    // would hold up each launch), the final pair on its own
+    const int mid = (K - 1 - k) / 2 - 1;  // K >= 4: at least the final pair
+    if (mid > 0) {
+      ProfScope ps(c, step_cls, 6.0 * w * mid, st, mid);
+      for (int q = 0; q < mid; q++, k += 2) {
+        OKE(c, launch_cheb_step2<P>(g, B, k, osc, false, x, cst(rc), rn, cst(dc), dn, st));
+        std::swap(dc, dn);
+        std::swap(rc, rn);
+      }
     }
+    ProfScope ps(c, cls, 4.0 * w, st);
+    OKE(c, launch_cheb_step2<P>(g, B, k, osc, true, x, cst(rc), rn, cst(dc), dn, st));
     return OK_SUCCESS;
   }
   {
@@ -525,16 +536,17 @@ int fgmres_iteration(ClassCtx& c, int j, Vec<const double> u, hipStream_t st) {
   if (e) return e;
   Vec<double> pin = vec(c.pA, (int64_t)kMaxRedBlocks), pout = vec(c.pB, (int64_t)kMaxRedBlocks);
   {
-    ProfScope ps(c, OK_K_KRYLOV, 16.0 * n2 * c.B, st);
+    // the Gram-Schmidt chain (one dot, j+1 fused steps) timed as one run:
+    // 2 vectors read by the dot, 4 per middle step, 3 by the last one
+    ProfScope ps(c, OK_K_KRYLOV, (16.0 + 32.0 * j + 24.0) * n2 * c.B, st, j + 2);
     OKE(c, launch_dot_partial(B, cst(W), Vec<const double>{c.V, sV(c)}, n2, pin, st));
-  }
-  for (int i = 0; i <= j; i++) {
-    Vec<const double> vi{c.V + (int64_t)i * n2, sV(c)};
-    Vec<const double> vn{(i < j) ? c.V + (int64_t)(i + 1) * n2 : nullptr, sV(c)};
-    ProfScope ps(c, OK_K_KRYLOV, (i < j ? 32.0 : 24.0) * n2 * c.B, st);
-    OKE(c, launch_mgs_step(B, W, vi, vn, n2, cst(pin), pout,
-                           Vec<double>{c.H + (int64_t)j * (c.m + 1) + i, sH(c)}, st));
-    std::swap(pin, pout);
+    for (int i = 0; i <= j; i++) {
+      Vec<const double> vi{c.V + (int64_t)i * n2, sV(c)};
+      Vec<const double> vn{(i < j) ? c.V + (int64_t)(i + 1) * n2 : nullptr, sV(c)};
+      OKE(c, launch_mgs_step(B, W, vi, vn, n2, cst(pin), pout,
+                             Vec<double>{c.H + (int64_t)j * (c.m + 1) + i, sH(c)}, st));
+      std::swap(pin, pout);
+    }
   }
   OKE(c, launch_givens(B, c.act, j, c.m, vec(c.H, sH(c)), vec(c.cs, sM(c)), vec(c.sn, sM(c)),
                        vec(c.g, sM(c)), cst(pin), n2, vec(c.kr, (int64_t)8), st));
@@ -701,7 +713,6 @@ int enable_exec(ClassCtx& c, bool graphs) {
     OKE(c, hipStreamCreateWithFlags(&c.ex->xs, hipStreamNonBlocking));
     OKE(c, hipEventCreateWithFlags(&c.ex->fork, hipEventDisableTiming));
     OKE(c, hipEventCreateWithFlags(&c.ex->join, hipEventDisableTiming));
-    OKE(c, hipHostMalloc((void**)&c.ex->hflags, sizeof(int) * c.B, hipHostMallocDefault));
   }
   c.ex->graphs = graphs;
   c.ex->clear_graphs();
@@ -907,8 +918,10 @@ int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,
     for (size_t k = 0; k < nc; k++) incyc[k] = grp[k]->h_act;
     const int m = grp[0]->m;
     // Classes with a stream of their own run their iterations there, so the
-    // classes of a group overlap on the device; the host waits for each class
-    // once per iteration (its activity flags decide whether to go on).
+    // classes of a group overlap on the device.  Iterations are issued one
+    // ahead of the stop test: the host launches iteration j, then waits for
+    // the activity flags of iteration j-1, so the device does not idle while
+    // the host decides whether to go on.
     for (size_t k = 0; k < nc; k++) {
       ClassCtx& c = *grp[k];
       if (!c.ex || !any(c.h_act)) continue;
@@ -923,24 +936,40 @@ int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,
         hipStream_t s = c.ex ? c.ex->xs : st;
         int e = run_iteration(c, j, u[k], s);
         if (e) return e;
-        if (c.ex) {  // pinned: the copy does not hold up the launches of the next class
-          OKE(c, hipMemcpyAsync(c.ex->hflags, c.act, sizeof(int) * c.B, hipMemcpyDeviceToHost, s));
-        } else if (d2h(c, c.h_act, c.act, (size_t)c.B, s)) {
-          return OK_E_HIP;
+        if (!c.fp) {
+          auto f = std::make_unique<FlagPipe>();
+          OKE(c, hipHostMalloc((void**)&f->h, sizeof(int) * 2 * c.B, hipHostMallocDefault));
+          for (hipEvent_t& ev : f->ev) OKE(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+          c.fp = std::move(f);
         }
+        const int slot = j & 1;
+        OKE(c, hipMemcpyAsync(c.fp->h + (size_t)slot * c.B, c.act, sizeof(int) * c.B,
+                              hipMemcpyDeviceToHost, s));
+        OKE(c, hipEventRecord(c.fp->ev[slot], s));
+        c.fp->pend[slot] = j;
         launched = true;
       }
       if (!launched) break;
+      if (j == 0) continue;
+      // stop test of iteration j-1, read while iteration j runs; an iteration
+      // issued after every instance of a class stopped finds the activity
+      // flags cleared on the device and does nothing
       bool still = false;
       for (size_t k = 0; k < nc; k++) {
         ClassCtx& c = *grp[k];
-        if (!any(incyc[k])) continue;
-        if (sync(c, c.ex ? c.ex->xs : st)) return OK_E_HIP;
-        if (c.ex && any(c.h_act)) c.h_act.assign(c.ex->hflags, c.ex->hflags + c.B);
+        FlagPipe* f = c.fp.get();
+        const int slot = (j - 1) & 1;
+        if (f && f->pend[slot] == j - 1) {
+          OKE(c, hipEventSynchronize(f->ev[slot]));
+          f->pend[slot] = -1;
+          c.h_act.assign(f->h + (size_t)slot * c.B, f->h + (size_t)(slot + 1) * c.B);
+        }
         still = still || any(c.h_act);
       }
       if (!still) break;
     }
+    for (size_t k = 0; k < nc; k++)
+      if (grp[k]->fp) grp[k]->fp->pend[0] = grp[k]->fp->pend[1] = -1;
     for (size_t k = 0; k < nc; k++) {
       ClassCtx& c = *grp[k];
       if (!c.ex || !any(incyc[k])) continue;
