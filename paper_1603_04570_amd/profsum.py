@@ -9,11 +9,12 @@
 
     python -m paper_1603_04570_amd.profsum traffic --fetch F.csv --write W.csv \
         --copy-fetch CF.csv --copy-write CW.csv --copy-bytes BYTES --kernel SUBSTRING \
-        [--kernel SUBSTRING ...] [--main-grid]
+        [--kernel SUBSTRING ...] [--exclude SUBSTRING ...] [--main-grid]
         per-dispatch HBM bytes of the kernels whose name contains any SUBSTRING
+        (and none of the --exclude ones)
         (with --main-grid: only their dispatches of the most dispatched grid
-        size, i.e. the launch shape the run used most -- autotuner trials and
-        other levels excluded), from
+        size of each run, i.e. the launch shape that run used most -- autotuner
+        trials and other levels excluded), from
         two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs, each scaled by
         what the same counter reads for a plain copy kernel of BYTES bytes read
         and BYTES bytes written (the copy runs of ``bench.py --calibrate-copy``).
@@ -61,12 +62,14 @@ def bygrid(path: str, top: int = 40) -> str:
     return "\n".join(out)
 
 
-def _counter(path: str, counter: str, substrings=None):
+def _counter(path: str, counter: str, substrings=None, exclude=()):
     vals = []
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
         if substrings is not None and not any(k in r["Kernel_Name"] for k in substrings):
+            continue
+        if any(k in r["Kernel_Name"] for k in exclude):
             continue
         vals.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
     return vals
@@ -81,23 +84,25 @@ def _copy_scale(path: str, counter: str, nbytes: int) -> float:
     return nbytes / v
 
 
-def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, kernel, main_grid=False):
+def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, kernel, main_grid=False,
+            exclude=()):
     sf = _copy_scale(copy_fetch, "FETCH_SIZE", copy_bytes)
     sw = _copy_scale(copy_write, "WRITE_SIZE", copy_bytes)
     kernels = [kernel] if isinstance(kernel, str) else list(kernel)
-    f = _counter(fetch, "FETCH_SIZE", kernels)
-    w = _counter(write, "WRITE_SIZE", kernels)
+    f = _counter(fetch, "FETCH_SIZE", kernels, exclude)
+    w = _counter(write, "WRITE_SIZE", kernels, exclude)
     if not f or not w:
         raise SystemExit(f"no dispatch of a kernel containing {kernel!r}")
-    if main_grid:
-        sizes = [x[1] for x in f]
-        g = max(set(sizes), key=sizes.count)
-        f = [x for x in f if x[1] == g]
-        w = [x for x in w if x[1] == g]
+    if main_grid:  # per run: the two runs may have tuned different launch shapes
+        def main(vals):
+            sizes = [x[1] for x in vals]
+            g = max(set(sizes), key=sizes.count)
+            return [x for x in vals if x[1] == g]
+        f, w = main(f), main(w)
     fb = statistics.mean(x for _, _, x in f) * sf
     wb = statistics.mean(x for _, _, x in w) * sw
-    names = sorted({short_name(x[0], 80) for x in f})
-    return {"kernel": "; ".join(names), "grid_size": f[0][1],
+    names = sorted({short_name(x[0], 80) for x in f + w})
+    return {"kernel": "; ".join(names), "grid_size": sorted({f[0][1], w[0][1]}),
             "dispatches": [len(f), len(w)],
             "fetch_scale_bytes_per_unit": sf, "write_scale_bytes_per_unit": sw,
             "fetch_bytes_per_dispatch": fb, "write_bytes_per_dispatch": wb,
@@ -119,6 +124,7 @@ def main():
     b.add_argument("--kernel", action="append", required=True)
     b.add_argument("--copy-bytes", type=int, required=True)
     b.add_argument("--main-grid", action="store_true")
+    b.add_argument("--exclude", action="append", default=[])
     args = ap.parse_args()
     if args.cmd == "stats":
         print(stats(args.csv, args.top))
@@ -126,7 +132,7 @@ def main():
         print(bygrid(args.csv, args.top))
     else:
         r = traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.copy_bytes,
-                    args.kernel, args.main_grid)
+                    args.kernel, args.main_grid, args.exclude)
         for k, v in r.items():
             print(f"{k}: {v}")
 
