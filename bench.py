@@ -395,7 +395,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain copy kernel of known size (for counter scaling)")
     ap.add_argument("--no-fuse", action="store_true",
-                    help="run the Chebyshev iterations on M one per pass")
+                    help="run every Chebyshev iteration (on M and in the smoothers) in a pass of its own")
+    ap.add_argument("--issue-ahead", action="store_true",
+                    help="issue each FGMRES iteration before the previous one's stop test is read")
     ap.add_argument("--graphs", action="store_true",
                     help="replay captured FGMRES iterations (single-problem configs)")
     ap.add_argument("--rates", default="2000", help="serve: offered request rates (req/s)")
@@ -417,6 +419,9 @@ def main():
 
     if args.no_fuse:
         ok.set_option(ok.OK_OPT_FUSE_CHEB, 0)
+        ok.set_option(ok.OK_OPT_FUSE_MG, 0)
+    if args.issue_ahead:
+        ok.set_option(ok.OK_OPT_ISSUE_AHEAD, 1)
     if args.config == "sweep64":
         print(json.dumps(bench_sweep(args, torch, ok)), flush=True)
         return

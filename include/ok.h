@@ -221,8 +221,13 @@ int ok_initial_w(ok_ctx *ctx, const double *d_u, double *d_w, void *stream);
  *   found it faster (or where ok_set_launch_shape set OK_SHAPE_MG_POST), the
  *   two pre-smoothing iterations with the residual in one pass and the two
  *   post-smoothing iterations in one pass (V(2,2) cycles); 0 runs every
- *   iteration and the residual in passes of their own everywhere. */
-enum ok_option { OK_OPT_FUSE_CHEB = 1, OK_OPT_FUSE_MG = 2 };
+ *   iteration and the residual in passes of their own everywhere.
+ *   OK_OPT_ISSUE_AHEAD: 0 (default) waits for each FGMRES iteration's stop
+ *   test before issuing the next; 1 issues iteration j before the host reads
+ *   the stop test of iteration j-1 (one iteration after the last is issued
+ *   and does nothing).  Measured on 3D 128^3 and in serving it gained
+ *   nothing, so it is off by default. */
+enum ok_option { OK_OPT_FUSE_CHEB = 1, OK_OPT_FUSE_MG = 2, OK_OPT_ISSUE_AHEAD = 3 };
 int ok_set_option(int32_t option, int32_t value);
 
 /* Launch shape of the streaming node-stencil kernels on one grid: the

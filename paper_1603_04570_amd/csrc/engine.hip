@@ -849,6 +849,11 @@ int residual_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const dou
 // ---------------------------------------------------------------------------
 // FGMRES (Saad 1993) in lockstep over a group of classes
 // ---------------------------------------------------------------------------
+namespace {
+int g_issue_ahead = 0;
+}  // namespace
+void issue_ahead_set(int enable) { g_issue_ahead = enable ? 1 : 0; }
+
 int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,
                  const std::vector<Vec<const double>>& b, const std::vector<Vec<double>>& x,
                  hipStream_t st) {
@@ -950,16 +955,18 @@ int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,
         launched = true;
       }
       if (!launched) break;
-      if (j == 0) continue;
-      // stop test of iteration j-1, read while iteration j runs; an iteration
+      // stop test of iteration j-1, read while iteration j runs (an iteration
       // issued after every instance of a class stopped finds the activity
-      // flags cleared on the device and does nothing
+      // flags cleared on the device and does nothing); without issue-ahead,
+      // the stop test of iteration j itself
+      const int jt = g_issue_ahead ? j - 1 : j;
+      if (jt < 0) continue;
       bool still = false;
       for (size_t k = 0; k < nc; k++) {
         ClassCtx& c = *grp[k];
         FlagPipe* f = c.fp.get();
-        const int slot = (j - 1) & 1;
-        if (f && f->pend[slot] == j - 1) {
+        const int slot = jt & 1;
+        if (f && f->pend[slot] == jt) {
           OKE(c, hipEventSynchronize(f->ev[slot]));
           f->pend[slot] = -1;
           c.h_act.assign(f->h + (size_t)slot * c.B, f->h + (size_t)(slot + 1) * c.B);

@@ -314,6 +314,9 @@ int ok_set_option(int32_t option, int32_t value) {
     case OK_OPT_FUSE_MG:
       mg_fusion_set(value);
       return OK_SUCCESS;
+    case OK_OPT_ISSUE_AHEAD:
+      issue_ahead_set(value);
+      return OK_SUCCESS;
     default:
       return OK_E_INVALID;
   }

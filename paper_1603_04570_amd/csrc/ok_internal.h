@@ -167,6 +167,8 @@ hipError_t launch_cheb_step2(const Grid& g, const Batch& B, int k, int osc, bool
 // Process-wide switch of that fusion (on by default); results do not change.
 // cheb_fusion_on: the switch is on and the fused kernel supports grid g.
 void cheb_fusion_set(int enable);
+// FGMRES iterations issued one ahead of the host-side stop test (default 0).
+void issue_ahead_set(int enable);
 bool cheb_fusion_on(const Grid& g, int word);
 // Fused multigrid smoothers (two Chebyshev iterations before and after the
 // coarse-grid correction, each in one pass with its neighbour).

@@ -113,3 +113,53 @@ def test_fused_multigrid_smoothers_bitwise(dim, n, precision):
                 ok.set_launch_shape(dim, lev_n, kern, precision, 0)
     assert ia == ib
     assert np.array_equal(ua, ub) and np.array_equal(wa, wb)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_issue_ahead_bitwise(precision):
+    """FGMRES iterations issued one ahead of the host-side stop test give the
+    same iterates, counts and final state as waiting for every stop test,
+    for a single problem and for a batch whose instances stop at different
+    iterations."""
+    from paper_1603_04570_amd import ok
+    from paper_1603_04570_amd.inputs import sweep_instance
+    p = ok.default_params(dim=3, n=32, eps=0.02, sigma=100.0, m=0.1, dt=2e-4,
+                          precision=precision)
+    u0, w0 = noise_state(3, 32, 0.1, 41)
+
+    def solo():
+        P = ok.Problem(p)
+        u = torch.from_numpy(u0).cuda()
+        w = torch.from_numpy(w0).cuda()
+        st = P.timestep(u, w, 2)
+        return u.cpu().numpy(), w.cpu().numpy(), st.its()
+
+    specs = [sweep_instance(i, sizes=(32, 64)) for i in range(4)]
+    plist = [ok.default_params(dim=s["dim"], n=s["n"], eps=s["eps"], sigma=s["sigma"], m=s["m"],
+                               dt=s["dt"], theta=s["theta"], precision=precision) for s in specs]
+
+    def batch():
+        Bt = ok.Batch(plist)
+        for i, s in enumerate(specs):
+            a, b = noise_state(s["dim"], s["n"], s["m"], s["seed"])
+            Bt.set_state(i, torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
+        Bt.timestep(1)
+        out = []
+        for i in range(len(specs)):
+            u, w = Bt.get_state(i)
+            out.append(np.concatenate([u.cpu().numpy(), w.cpu().numpy()]))
+        Bt.close()
+        return out
+
+    out = []
+    for ahead in (0, 1):
+        ok.set_option(ok.OK_OPT_ISSUE_AHEAD, ahead)
+        try:
+            out.append((solo(), batch()))
+        finally:
+            ok.set_option(ok.OK_OPT_ISSUE_AHEAD, 0)
+    (sa, ba), (sb, bb) = out
+    assert sa[2] == sb[2]
+    assert np.array_equal(sa[0], sb[0]) and np.array_equal(sa[1], sb[1])
+    for x, y in zip(ba, bb):
+        assert np.array_equal(x, y)
