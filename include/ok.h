@@ -295,7 +295,9 @@ int ok_batch_set_state(ok_batch *b, int32_t i, const double *d_u, const double *
 int ok_batch_get_state(ok_batch *b, int32_t i, double *d_u, double *d_w, void *stream);
 /* nsteps timesteps of every instance (Newton and FGMRES in lockstep across
  * all instances and classes).  stats (may be NULL): `count` entries.
- * Returns the first failure of any instance (its stats carry its status). */
+ * Returns the first failure of any instance (its stats carry its status);
+ * the batch stops after the step in which an instance failed, the others
+ * having completed that step (stats.steps_done). */
 int ok_batch_timestep(ok_batch *b, int32_t nsteps, ok_stats *stats, void *stream);
 /* ok_autotune for every class of the batch. */
 int ok_batch_autotune(ok_batch *b, void *stream, int32_t *entries);
