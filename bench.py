@@ -398,6 +398,9 @@ def main():
                     help="run every Chebyshev iteration (on M and in the smoothers) in a pass of its own")
     ap.add_argument("--issue-ahead", action="store_true",
                     help="issue each FGMRES iteration before the previous one's stop test is read")
+    ap.add_argument("--trace-ranges", action="store_true",
+                    help="ROCTX ranges per timestep, Newton and FGMRES iteration "
+                         "(for rocprofv3 --marker-trace)")
     ap.add_argument("--graphs", action="store_true",
                     help="replay captured FGMRES iterations (single-problem configs)")
     ap.add_argument("--rates", default="2000", help="serve: offered request rates (req/s)")
@@ -422,6 +425,8 @@ def main():
         ok.set_option(ok.OK_OPT_FUSE_MG, 0)
     if args.issue_ahead:
         ok.set_option(ok.OK_OPT_ISSUE_AHEAD, 1)
+    if args.trace_ranges:
+        ok.set_option(ok.OK_OPT_TRACE_RANGES, 1)
     if args.config == "sweep64":
         print(json.dumps(bench_sweep(args, torch, ok)), flush=True)
         return

@@ -226,8 +226,16 @@ int ok_initial_w(ok_ctx *ctx, const double *d_u, double *d_w, void *stream);
  *   test before issuing the next; 1 issues iteration j before the host reads
  *   the stop test of iteration j-1 (one iteration after the last is issued
  *   and does nothing).  Measured on 3D 128^3 and in serving it gained
- *   nothing, so it is off by default. */
-enum ok_option { OK_OPT_FUSE_CHEB = 1, OK_OPT_FUSE_MG = 2, OK_OPT_ISSUE_AHEAD = 3 };
+ *   nothing, so it is off by default.
+ *   OK_OPT_TRACE_RANGES: 0 (default); 1 opens a host-side ROCTX range
+ *   (rocprofv3 --marker-trace) around every timestep ("timestep"), Newton
+ *   iteration ("newton iteration"), FGMRES restart cycle ("fgmres cycle"),
+ *   FGMRES iteration ("fgmres iteration") and serving-pool tick ("serve
+ *   tick").  Ranges cover the host's issue and wait, so with the default
+ *   (no issue-ahead) an FGMRES iteration's range spans its device work. */
+enum ok_option {
+  OK_OPT_FUSE_CHEB = 1, OK_OPT_FUSE_MG = 2, OK_OPT_ISSUE_AHEAD = 3, OK_OPT_TRACE_RANGES = 4
+};
 int ok_set_option(int32_t option, int32_t value);
 
 /* Launch shape of the streaming node-stencil kernels on one grid: the

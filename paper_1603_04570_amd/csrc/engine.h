@@ -163,4 +163,23 @@ int enable_exec(ClassCtx& c, bool graphs);
 // Tile autotuner over the class's grids.
 int autotune_class(ClassCtx& c, hipStream_t st, int* entries);
 
+// Host-side ROCTX ranges for rocprofv3 --marker-trace: one per timestep,
+// Newton iteration, FGMRES restart cycle and FGMRES iteration, and per tick of
+// a serving pool.  Off by default (no ROCTX call is made then).
+extern bool g_trace_ranges;
+void trace_ranges_set(int enable);
+void trace_push(const char* name);
+void trace_pop();
+struct TraceRange {
+  const bool on;
+  explicit TraceRange(const char* name) : on(g_trace_ranges) {
+    if (on) trace_push(name);
+  }
+  ~TraceRange() {
+    if (on) trace_pop();
+  }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+
 }  // namespace okd

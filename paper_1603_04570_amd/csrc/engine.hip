@@ -3,6 +3,8 @@
 // the host only sequences launches and reads back a few flags and norms.
 #include "engine.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -854,6 +856,11 @@ int g_issue_ahead = 0;
 }  // namespace
 void issue_ahead_set(int enable) { g_issue_ahead = enable ? 1 : 0; }
 
+bool g_trace_ranges = false;
+void trace_ranges_set(int enable) { g_trace_ranges = enable != 0; }
+void trace_push(const char* name) { roctxRangePushA(name); }
+void trace_pop() { roctxRangePop(); }
+
 int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,
                  const std::vector<Vec<const double>>& b, const std::vector<Vec<double>>& x,
                  hipStream_t st) {
@@ -904,6 +911,7 @@ int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,
   std::vector<bool> first(nc, true);
   const int max_restarts = grp.empty() ? 0 : grp[0]->shape.gmres_max_restarts;
   for (int cycle = 0; cycle <= max_restarts; cycle++) {
+    TraceRange cycle_range("fgmres cycle");
     bool anyact = false;
     for (size_t k = 0; k < nc; k++) {
       ClassCtx& c = *grp[k];
@@ -934,6 +942,7 @@ int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,
       OKE(c, hipStreamWaitEvent(c.ex->xs, c.ex->fork, 0));
     }
     for (int j = 0; j < m; j++) {
+      TraceRange it_range("fgmres iteration");
       bool launched = false;
       for (size_t k = 0; k < nc; k++) {
         ClassCtx& c = *grp[k];
@@ -1095,6 +1104,7 @@ int newton_group_iters(const Group& grp, const std::vector<Vec<double>>& u,
     bool anyp = false;
     for (size_t k = 0; k < nc; k++) anyp = anyp || any(grp[k]->h_part);
     if (!anyp) break;
+    TraceRange newton_range("newton iteration");
     std::vector<Vec<const double>> bb(nc);
     std::vector<Vec<double>> xx(nc);
     std::vector<Vec<const double>> uu(nc);

@@ -68,6 +68,7 @@ int timestep_group(const Group& grp, const std::vector<Vec<double>>& u,
   OK_HIP(err, hipEventCreate(&e1));
   int status = OK_SUCCESS;
   for (int s = 0; s < nsteps && status == OK_SUCCESS; s++) {
+    TraceRange step_range("timestep");
     OK_HIP(err, hipEventRecord(e0, st));
     std::vector<Vec<const double>> un(nc), wn(nc);
     std::vector<NewtonLog> log(nc);
@@ -316,6 +317,9 @@ int ok_set_option(int32_t option, int32_t value) {
       return OK_SUCCESS;
     case OK_OPT_ISSUE_AHEAD:
       issue_ahead_set(value);
+      return OK_SUCCESS;
+    case OK_OPT_TRACE_RANGES:
+      trace_ranges_set(value);
       return OK_SUCCESS;
     default:
       return OK_E_INVALID;

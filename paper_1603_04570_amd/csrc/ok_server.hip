@@ -261,7 +261,11 @@ void pool_main(ok_server* s, Pool* q, int dev) {
     }
     lk.unlock();
     const double ta = s->now();
-    int e = pool_tick(s, *q, v, last, out);
+    int e;
+    {
+      TraceRange tick_range("serve tick");
+      e = pool_tick(s, *q, v, last, out);
+    }
     const double tb = s->now();
     lk.lock();
     s->stats.ticks++;

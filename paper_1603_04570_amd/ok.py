@@ -402,6 +402,7 @@ class Batch:
 OK_OPT_FUSE_CHEB = 1
 OK_OPT_FUSE_MG = 2
 OK_OPT_ISSUE_AHEAD = 3
+OK_OPT_TRACE_RANGES = 4
 
 
 def set_option(option: int, value: int):

@@ -7,6 +7,10 @@
         per (kernel, grid size) totals from ``--kernel-trace`` (kt_kernel_trace.csv):
         separates the multigrid levels and the grids of one kernel template
 
+    python -m paper_1603_04570_amd.profsum ranges MARKER_TRACE_CSV
+        per ROCTX range name (``--marker-trace``, marker_api_trace.csv): count,
+        total, mean, median and 99th percentile of the range durations
+
     python -m paper_1603_04570_amd.profsum traffic --fetch F.csv --write W.csv \
         --copy-fetch CF.csv --copy-write CW.csv --copy-bytes BYTES --kernel SUBSTRING \
         [--kernel SUBSTRING ...] [--exclude SUBSTRING ...] [--main-grid]
@@ -59,6 +63,23 @@ def bygrid(path: str, top: int = 40) -> str:
     for (name, g), (n, s) in sorted(acc.items(), key=lambda kv: -kv[1][1])[:top]:
         out.append(f"{s / 1e6:9.3f} {100 * s / tot:5.1f} {n:6d} {s / n / 1e3:9.2f} {g:9d}  "
                    f"{short_name(name, 100)}")
+    return "\n".join(out)
+
+
+def ranges(path: str) -> str:
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        name = r.get("Message") or r.get("Function") or ""
+        t = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        if t <= 0:  # instantaneous markers
+            continue
+        acc.setdefault(name, []).append(t)
+    out = [f"{'count':>6} {'total ms':>10} {'mean us':>9} {'p50 us':>9} {'p99 us':>9}  range"]
+    for name, ts in sorted(acc.items(), key=lambda kv: -sum(kv[1])):
+        ts.sort()
+        p99 = ts[min(len(ts) - 1, int(0.99 * len(ts)))]
+        out.append(f"{len(ts):6d} {sum(ts) / 1e6:10.3f} {statistics.mean(ts) / 1e3:9.1f} "
+                   f"{statistics.median(ts) / 1e3:9.1f} {p99 / 1e3:9.1f}  {name}")
     return "\n".join(out)
 
 
@@ -118,6 +139,8 @@ def main():
     c = sub.add_parser("bygrid")
     c.add_argument("csv")
     c.add_argument("top", nargs="?", type=int, default=40)
+    d = sub.add_parser("ranges")
+    d.add_argument("csv")
     b = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy-fetch", "copy-write"):
         b.add_argument("--" + k, required=True)
@@ -130,6 +153,8 @@ def main():
         print(stats(args.csv, args.top))
     elif args.cmd == "bygrid":
         print(bygrid(args.csv, args.top))
+    elif args.cmd == "ranges":
+        print(ranges(args.csv))
     else:
         r = traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.copy_bytes,
                     args.kernel, args.main_grid, args.exclude)

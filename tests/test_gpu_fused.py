@@ -116,11 +116,13 @@ def test_fused_multigrid_smoothers_bitwise(dim, n, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_issue_ahead_bitwise(precision):
-    """FGMRES iterations issued one ahead of the host-side stop test give the
-    same iterates, counts and final state as waiting for every stop test,
-    for a single problem and for a batch whose instances stop at different
-    iterations."""
+@pytest.mark.parametrize("option", ["OK_OPT_ISSUE_AHEAD", "OK_OPT_TRACE_RANGES"])
+def test_host_options_bitwise(precision, option):
+    """Host-side options change no arithmetic.  FGMRES iterations issued one
+    ahead of the host-side stop test (OK_OPT_ISSUE_AHEAD), and ROCTX ranges
+    around the solver loops (OK_OPT_TRACE_RANGES), give the same iterates,
+    counts and final state as the default, for a single problem and for a
+    batch whose instances stop at different iterations."""
     from paper_1603_04570_amd import ok
     from paper_1603_04570_amd.inputs import sweep_instance
     p = ok.default_params(dim=3, n=32, eps=0.02, sigma=100.0, m=0.1, dt=2e-4,
@@ -152,12 +154,14 @@ def test_issue_ahead_bitwise(precision):
         return out
 
     out = []
-    for ahead in (0, 1):
-        ok.set_option(ok.OK_OPT_ISSUE_AHEAD, ahead)
+    code = getattr(ok, option)
+    for value in (0, 1):
+        print(option, value, precision, flush=True)
+        ok.set_option(code, value)
         try:
             out.append((solo(), batch()))
         finally:
-            ok.set_option(ok.OK_OPT_ISSUE_AHEAD, 0)
+            ok.set_option(code, 0)
     (sa, ba), (sb, bb) = out
     assert sa[2] == sb[2]
     assert np.array_equal(sa[0], sb[0]) and np.array_equal(sa[1], sb[1])
