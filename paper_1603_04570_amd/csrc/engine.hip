@@ -1189,9 +1189,8 @@ double time_best(hipStream_t st, F&& launch) {
 // Candidate z-chunk counts of a streaming stencil launch: chunks of 4 to 32
 // planes, and the counts that make the whole grid (all instances) about
 // 512 ... 6144 blocks, i.e. one or a few full rounds of resident blocks.
-std::vector<int> zchunk_candidates(const Grid& g, int chunk, int count) {
-  const int64_t plane = (g.dim == 3) ? g.plane : (int64_t)g.nn;
-  const int64_t nch = (plane + chunk - 1) / chunk;
+// z-range counts to try for a kernel with nch blocks per plane
+std::vector<int> zchunk_candidates_n(const Grid& g, int64_t nch, int count) {
   std::vector<int> v;
   for (int zc : {4, 8, 16, 32}) v.push_back((g.nn + zc - 1) / zc);
   for (int64_t t : {512, 1024, 2048, 3072, 4096, 6144}) v.push_back((int)(t / (nch * count)));
@@ -1199,6 +1198,11 @@ std::vector<int> zchunk_candidates(const Grid& g, int chunk, int count) {
   std::sort(v.begin(), v.end());
   v.erase(std::unique(v.begin(), v.end()), v.end());
   return v;
+}
+
+std::vector<int> zchunk_candidates(const Grid& g, int chunk, int count) {
+  const int64_t plane = (g.dim == 3) ? g.plane : (int64_t)g.nn;
+  return zchunk_candidates_n(g, (plane + chunk - 1) / chunk, count);
 }
 
 template <class P>
@@ -1284,6 +1288,7 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
     }
   }
   stencil_tune_set(c.lev[0].dim, c.lev[0].nn, kFusedKey, word, 0, 0);
+  stencil_tune_set(c.lev[0].dim, c.lev[0].nn, kFusedTileKey, word, 0, 0);
   if (cheb_fusion_on(c.lev[0], word)) {  // fused pairs of Chebyshev iterations on M
     const Grid& g = c.lev[0];
     const int64_t nl = g.nodes;
@@ -1309,6 +1314,31 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
           }
         }
       }
+    // the same pairs on rectangular in-plane tiles (3D)
+    double tbest = 1e30;
+    int ti = 0, tz = 0, tt = 256;
+    stencil_tune_set(g.dim, g.nn, kFusedKey, word, bi, bz, bt);  // bi = 0: built-in shape
+    if (g.dim == 3) {
+      for (int threads : {256, 512})
+        for (int items = 1; items <= 2; items++) {
+          TileGeom tg;
+          if (!cheb2_tile_geom(g, threads, items, tg)) continue;
+          for (int zc : zchunk_candidates_n(g, (int64_t)tg.ntx * tg.nty, B.count)) {
+            stencil_tune_set(g.dim, g.nn, kFusedTileKey, word, items, zc, threads);
+            double t = time_best(st, [&]() {
+              return launch_cheb_step2<P>(g, B, 1, CF_ONE, false, x, cst(r),
+                                          pvec<P>(c.cr2, nl), cst(d0), d1, st);
+            });
+            if (t < tbest) {
+              tbest = t;
+              ti = items;
+              tz = zc;
+              tt = threads;
+            }
+          }
+        }
+      stencil_tune_set(g.dim, g.nn, kFusedTileKey, word, 0, 0);
+    }
     // keep the fusion only where a pair beats two single iterations on M
     const double single = time_best(st, [&]() {
       hipError_t e = launch_cheb_step<P>(g, B, -1, 1, CF_ONE, false, x, r, cst(d0), d1, st);
@@ -1316,10 +1346,12 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
         e = launch_cheb_step<P>(g, B, -1, 2, CF_ONE, false, x, r, cst(d1), d0, st);
       return e;
     });
-    if (bi && best < single)
-      stencil_tune_set(g.dim, g.nn, kFusedKey, word, bi, bz, bt);
-    else
+    if ((bi && best < single) || (ti && tbest < single)) {
+      if (ti && tbest < best)
+        stencil_tune_set(g.dim, g.nn, kFusedTileKey, word, ti, tz, tt);
+    } else {
       stencil_tune_set(g.dim, g.nn, kFusedKey, word, -1, 0);
+    }
     (*entries)++;
   }
   {

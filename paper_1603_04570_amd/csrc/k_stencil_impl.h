@@ -83,6 +83,12 @@ int red_blocks(int64_t n) {
   return (int)b;
 }
 
+bool stencil_tuned(const Grid& g, int nf, int word) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(std::make_tuple(g.dim, g.nn, nf, word));
+  return it != g_tune.end() && std::get<0>(it->second) > 0;
+}
+
 StencilShape stencil_shape(const Grid& g, int nf, int word) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -113,6 +119,30 @@ StencilShape stencil_shape(const Grid& g, int nf, int word) {
   s.zc = (g.nn + s.nzc - 1) / s.nzc;
   s.blocks = s.nchunks * s.nzc;
   return s;
+}
+// Among the tilings of the N+1 columns into ntx tiles of equal width (the
+// last one short), the one with the fewest blocks per plane whose two-node
+// ring fits items + 1 slots per thread and whose LDS fits 64 KB; ties go to
+// the widest tile (longest contiguous row segments).
+bool cheb2_tile_geom(const Grid& g, int threads, int items, TileGeom& tg) {
+  if (g.dim != 3 || (items != 1 && items != 2) || (threads != 256 && threads != 512)) return false;
+  const int nn = g.nn, cap = threads * items, slots = threads * (items + 1);
+  int64_t best = -1;
+  for (int ntx = 1; ntx <= 32 && ntx <= nn; ntx++) {
+    const int tx = (nn + ntx - 1) / ntx;
+    int ty = std::min(nn, cap / tx);
+    while (ty >= 1 && (tx + 4) * (ty + 4) > slots) ty--;
+    if (ty < 1) continue;
+    const size_t lds = (size_t)((tx + 4) * (ty + 4) + (tx + 2) * (ty + 2) + 4 * tx * ty) * 8;
+    if (lds > 65536) continue;
+    const int ntxr = (nn + tx - 1) / tx, nty = (nn + ty - 1) / ty;
+    const int64_t blocks = (int64_t)ntxr * nty;
+    if (best < 0 || blocks < best) {  // ntx ascends: ties keep the wider tile
+      best = blocks;
+      tg = TileGeom{tx, ty, ntxr, nty};
+    }
+  }
+  return best > 0;
 }
 #endif  // OKD_STENCIL_PART == 0
 
@@ -975,6 +1005,240 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same two Chebyshev iterations on M (3D) with a block owning a
+// rectangular tile of TX x TY nodes of each x-y plane instead of a run of
+// consecutive nodes.  A run of C nodes stages halos of whole rows (C + 2H
+// nodes of d_{k+1}, C + 4H of d_k with H = N + 2), a tile the rings
+// (TX+2)(TY+2) and (TX+4)(TY+4): for the same C far fewer when rows are long,
+// so both halo stages fit P + 1 slots per thread.  Nodes outside the grid
+// hold 0 in LDS, as the positions before and after a plane do in k_cheb2,
+// and every node's arithmetic is that of k_cheb2: the results are the same
+// bits.  LDS: d_k on the tile with a two-node ring (pitch TX+4), d_{k+1}
+// with a one-node ring (pitch TX+2), and two buffers each of r_{k+1} and d_k
+// on the tile.
+// ---------------------------------------------------------------------------
+template <int NT, int P, class T, bool LAST2>
+__global__ void __launch_bounds__(NT)
+    k_cheb2t(Grid g, StencilShape sh, TileGeom tg, Batch B, int kk, int osc, Vec<T> xv,
+             Vec<const T> rinv, Vec<T> routv, Vec<const T> dinv_, Vec<T> doutv) {
+  constexpr int P1 = P + 1;
+  extern __shared__ double lds[];
+  const int tid = threadIdx.x;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int inst = lb / sh.blocks;
+  if (B.act && !B.act[inst]) return;
+  const int b = lb - inst * sh.blocks;
+  const int tile = b % sh.nchunks;
+  const int zch = b / sh.nchunks;
+  const InstCoef& IC = B.coef[inst];
+  const OpK ka = op_k(IC, -1, kk, CF_ONE), kb = op_k(IC, -1, kk + 1, osc);
+  const int nn = g.nn, N = g.N;
+  const int64_t plane = g.plane;
+  const int TX = tg.tx, TY = tg.ty;
+  const int x0 = (tile % tg.ntx) * TX, y0 = (tile / tg.ntx) * TY;
+  const int WA = TX + 4, WB = TX + 2;  // LDS row pitches
+  const int EA = WA * (TY + 4), E1 = WB * (TY + 2), CH = TX * TY;
+  double* LA = lds;          // d_k: rows y0-2 .. y0+TY+1, columns x0-2 .. x0+TX+1
+  double* LB = LA + EA;      // d_{k+1}: rows y0-1 .. y0+TY, columns x0-1 .. x0+TX
+  double* LR = LB + E1;      // r_{k+1} on the tile, two buffers
+  double* LD = LR + 2 * CH;  // d_k on the tile, two buffers
+  T* __restrict__ x = xv.at(inst);
+  const T* __restrict__ r = rinv.at(inst);
+  T* __restrict__ rout = LAST2 ? nullptr : routv.at(inst);
+  const T* __restrict__ din = dinv_.at(inst);
+  T* __restrict__ dout = doutv.at(inst);
+  auto cl = [&](int v) { return v < 0 ? 0 : (v > N ? N : v); };
+
+  // d_k staging: LA position t = tid + NT k holds node (x0-2 + t % WA, y0-2 + t / WA)
+  int oa[P1];       // in-plane offset of that node, clamped into the grid
+  unsigned va = 0;  // bit k: the node lies in the grid (else LA holds 0)
+#pragma unroll
+  for (int k = 0; k < P1; k++) {
+    const int t = tid + NT * k;
+    const int ra = t / WA, ca = t - ra * WA;
+    const int gy = y0 - 2 + ra, gx = x0 - 2 + ca;
+    if (t < EA && gy >= 0 && gy <= N && gx >= 0 && gx <= N) va |= 1u << k;
+    oa[k] = cl(gy) * nn + cl(gx);
+  }
+  // stage-1 items: LB position e = tid + NT q (node (x0-1 + e % WB, y0-1 + e / WB))
+  int i1[P1], j1[P1], l1[P1];
+  bool v1[P1];
+#pragma unroll
+  for (int q = 0; q < P1; q++) {
+    const int e = tid + NT * q;
+    const int rb = e / WB, cb = e - rb * WB;
+    const int gy = y0 - 1 + rb, gx = x0 - 1 + cb;
+    v1[q] = e < E1 && gy >= 0 && gy <= N && gx >= 0 && gx <= N;
+    i1[q] = cl(gx);
+    j1[q] = cl(gy);
+    l1[q] = e < E1 ? (rb + 1) * WA + cb + 1 : WA + 1;  // the same node in LA
+  }
+  // stage-2 items: tile position c = tid + NT p (node (x0 + c % TX, y0 + c / TX))
+  int i2[P], j2[P], l2[P];
+  bool v2[P];
+#pragma unroll
+  for (int p = 0; p < P; p++) {
+    const int c = tid + NT * p;
+    const int a = c / TX, bb = c - a * TX;
+    const int gy = y0 + a, gx = x0 + bb;
+    v2[p] = c < CH && gy <= N && gx <= N;
+    i2[p] = cl(gx);
+    j2[p] = cl(gy);
+    l2[p] = c < CH ? (a + 1) * WB + bb + 1 : WB + 1;  // the same node in LB
+  }
+
+  // prefetch registers (raw words, clamped in-bounds loads)
+  T pa[P1], pr[P1], px[P];
+  auto issue_a = [&](int64_t zoff) {
+#pragma unroll
+    for (int k = 0; k < P1; k++) pa[k] = din[zoff + oa[k]];
+  };
+  auto issue_rx = [&](int zr, int zx) {
+#pragma unroll
+    for (int q = 0; q < P1; q++) pr[q] = r[(int64_t)zr * plane + (int64_t)j1[q] * nn + i1[q]];
+#pragma unroll
+    for (int p = 0; p < P; p++) px[p] = x[(int64_t)zx * plane + (int64_t)j2[p] * nn + i2[p]];
+  };
+  // in-plane mass partial (M1 x M1) v at LDS position L of a buffer with row
+  // pitch ys (the arithmetic of the one-iteration kernel)
+  auto mpart = [&](const double* v, int L, int ys, int i, int j) {
+    const bool hl = i > 0, hr = i < N, ex = (i == 0 || i == N);
+    const bool ey = (j == 0 || j == N);
+    double m[3];
+#pragma unroll
+    for (int rr = 0; rr < 3; rr++) {
+      const int bse = L + (rr - 1) * ys;
+      m[rr] = m1_row(hl, hr, ex, v[bse - 1], v[bse], v[bse + 1]);
+    }
+    return m1_row(true, true, ey, m[0], m[1], m[2]);
+  };
+
+  const double h = g.h;
+  const double cmass = h * h * h / 216.0;
+  int z0, z1;
+  zrange(sh, nn, zch, z0, z1);
+  const int zlast = min(z1 + 1, N);
+  double pa1[P1], pb1[P1], cb1[P1];  // stage 1: partials of planes pz-2, pz-1; d_k(pz-1)
+  double pa2[P], pb2[P], cb2[P];     // stage 2: partials of d_{k+1} planes pz-3, pz-2; d_{k+1}(pz-2)
+#pragma unroll
+  for (int q = 0; q < P1; q++) pa1[q] = pb1[q] = cb1[q] = 0.0;
+#pragma unroll
+  for (int p = 0; p < P; p++) pa2[p] = pb2[p] = cb2[p] = 0.0;
+  issue_a((int64_t)max(z0 - 2, 0) * plane);
+  issue_rx(max(z0 - 1, 0), max(z0, 0));
+  for (int pz = z0 - 2; pz <= z1 + 1; pz++) {
+    const bool insideA = (pz >= 0 && pz <= N);
+    const int q1 = pz - 1;  // stage-1 output plane
+    const int o = pz - 2;   // stage-2 output plane
+    const int buf = pz & 1;
+    __syncthreads();
+    if (insideA) {
+#pragma unroll
+      for (int k = 0; k < P1; k++) {
+        const int t = tid + NT * k;
+        if (t < EA) LA[t] = ((va >> k) & 1u) ? to_d(pa[k]) : 0.0;
+      }
+    }
+    __syncthreads();
+    // stage-1 pointwise inputs of plane q1 and stage-2 x of plane o arrived last trip
+    T rq[P1], xq[P];
+#pragma unroll
+    for (int q = 0; q < P1; q++) rq[q] = pr[q];
+#pragma unroll
+    for (int p = 0; p < P; p++) xq[p] = px[p];
+    issue_a((int64_t)max(min(pz + 1, zlast), 0) * plane);  // plane -1 is never read
+    issue_rx(min(max(q1 + 1, 0), N), min(max(o + 1, 0), N));
+    // stage 1: partials of d_k at plane pz over the tile and its one-node ring
+    double pn1[P1], cn1[P1];
+#pragma unroll
+    for (int q = 0; q < P1; q++) {
+      const bool use = insideA && (tid + NT * q < E1);
+      pn1[q] = use ? mpart(LA, l1[q], WA, i1[q], j1[q]) : 0.0;
+      cn1[q] = use ? LA[l1[q]] : 0.0;
+    }
+    if (q1 >= z0 - 1 && q1 <= z1) {
+      const bool inq = (q1 >= 0 && q1 <= N);
+      double az0 = 0, az1 = 0, az2 = 0, bz0, bz1, bz2;
+      if (inq) pattern<false>(q1, N, az0, az1, az2, bz0, bz1, bz2);
+      const int nbz = (q1 == 0 || q1 == N);
+#pragma unroll
+      for (int q = 0; q < P1; q++) {
+        const int e = tid + NT * q;
+        if (e >= E1) continue;
+        double d1 = 0.0;
+        if (inq && v1[q]) {
+          const double ms = cmass * sum3(az0, az1, az2, pa1[q], pb1[q], pn1[q]);
+          const double dk = cb1[q];
+          const int nb = (i1[q] == 0 || i1[q] == N) + nbz + (j1[q] == 0 || j1[q] == N);
+          const double dv = dinv_at(ka.dinv, nb);
+          const double ru = to_d(rq[q]) - op_apply(ka, ms, 0.0);
+          const double rv1 = to_d((T)ru);
+          d1 = to_d((T)cheb_dir(ka, dk, dv, ru));
+          const int ci = i1[q] - x0, cj = j1[q] - y0;
+          if (ci >= 0 && ci < TX && cj >= 0 && cj < TY) {
+            const int c = cj * TX + ci;
+            LR[buf * CH + c] = rv1;
+            LD[buf * CH + c] = dk;
+          }
+        }
+        LB[e] = d1;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < P1; q++) {
+      pa1[q] = pb1[q];
+      pb1[q] = pn1[q];
+      cb1[q] = cn1[q];
+    }
+    __syncthreads();
+    // stage 2: partials of d_{k+1} at plane q1 over the tile; finish plane o
+    if (q1 >= z0 - 1 && q1 <= z1) {
+      double pn2[P], cn2[P];
+#pragma unroll
+      for (int p = 0; p < P; p++) {
+        pn2[p] = mpart(LB, l2[p], WB, i2[p], j2[p]);
+        cn2[p] = LB[l2[p]];
+      }
+      if (o >= z0 && o < z1) {
+        double az0, az1, az2, bz0, bz1, bz2;
+        pattern<false>(o, N, az0, az1, az2, bz0, bz1, bz2);
+        const int nbz = (o == 0 || o == N);
+        const int pb = buf ^ 1;
+#pragma unroll
+        for (int p = 0; p < P; p++) {
+          if (!v2[p]) continue;
+          const int c = tid + NT * p;
+          const double ms = cmass * sum3(az0, az1, az2, pa2[p], pb2[p], pn2[p]);
+          const double d1 = cb2[p];
+          const double rv1 = LR[pb * CH + c];
+          const double dk = LD[pb * CH + c];
+          const int nb = (i2[p] == 0 || i2[p] == N) + nbz + (j2[p] == 0 || j2[p] == N);
+          const double dv = dinv_at(kb.dinv, nb);
+          const double xv1 = to_d((T)(to_d(xq[p]) + dk));
+          const double xv2 = xv1 + d1;
+          const double rv2 = rv1 - op_apply(kb, ms, 0.0);
+          const double d2 = cheb_dir(kb, d1, dv, rv2);
+          const int64_t idx = (int64_t)o * plane + (int64_t)j2[p] * nn + i2[p];
+          if (LAST2) {
+            x[idx] = (T)(kb.osc * (xv2 + d2));
+          } else {
+            x[idx] = (T)xv2;
+            rout[idx] = (T)rv2;
+            dout[idx] = (T)d2;
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < P; p++) {
+        pa2[p] = pb2[p];
+        pb2[p] = pn2[p];
+        cb2[p] = cn2[p];
+      }
+    }
+  }
+}
+
 // In-plane partial products of M and K at LDS position L of plane buffer v
 // (node (i, j)): the arithmetic of the one-field streaming kernel, unscaled
 // or with the W^-1-scaled patterns (SCALED).
@@ -1475,12 +1739,51 @@ bool cheb_fusion_on(const Grid& g, int word) {
 }
 #endif  // OKD_STENCIL_PART == 0
 
+namespace {
+template <int NT, int P, class T>
+hipError_t launch_cheb2t_p(const Grid& g, const Batch& B, const StencilShape& sh0, int k,
+                           int osc, bool last2, Vec<T> x, Vec<const T> r, Vec<T> rout,
+                           Vec<const T> din, Vec<T> dout, hipStream_t st) {
+  TileGeom tg;
+  if (!cheb2_tile_geom(g, NT, P, tg)) return hipErrorInvalidValue;
+  StencilShape sh = sh0;
+  sh.nchunks = tg.ntx * tg.nty;
+  sh.blocks = sh.nchunks * sh.nzc;
+  const size_t lds = (size_t)((tg.tx + 4) * (tg.ty + 4) + (tg.tx + 2) * (tg.ty + 2) +
+                              4 * tg.tx * tg.ty) * sizeof(double);
+  if (lds > 65536 || tg.tx * tg.ty > NT * P || (tg.tx + 4) * (tg.ty + 4) > NT * (P + 1))
+    return hipErrorInvalidValue;
+  const int64_t nblk = (int64_t)sh.blocks * B.count;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  dim3 grid((unsigned)nblk), block(NT);
+  if (last2)
+    hipLaunchKernelGGL((k_cheb2t<NT, P, T, true>), grid, block, lds, st, g, sh, tg, B, k, osc, x,
+                       r, rout, din, dout);
+  else
+    hipLaunchKernelGGL((k_cheb2t<NT, P, T, false>), grid, block, lds, st, g, sh, tg, B, k, osc,
+                       x, r, rout, din, dout);
+  return hipGetLastError();
+}
+}  // namespace
+
 template <class T>
 hipError_t launch_cheb_step2(const Grid& g, const Batch& B, int k, int osc, bool last2, Vec<T> x,
                              Vec<const T> r, Vec<T> rout, Vec<const T> din, Vec<T> dout,
                              hipStream_t st) {
   if (k < 0 || k + 1 >= kMaxCheb || B.count < 1) return hipErrorInvalidValue;
   if (!last2 && (rout.p == r.p || rout.null())) return hipErrorInvalidValue;
+  if (g.dim == 3) {  // tiled kernel where the table selects it
+    const StencilShape ts = stencil_shape(g, kFusedTileKey, (int)sizeof(T));
+    if (stencil_tuned(g, kFusedTileKey, (int)sizeof(T)) && cheb2_shape_ok(3, ts.items, ts.threads)) {
+      if (ts.threads == 512)
+        return ts.items == 1
+                   ? launch_cheb2t_p<512, 1, T>(g, B, ts, k, osc, last2, x, r, rout, din, dout, st)
+                   : launch_cheb2t_p<512, 2, T>(g, B, ts, k, osc, last2, x, r, rout, din, dout, st);
+      return ts.items == 1
+                 ? launch_cheb2t_p<256, 1, T>(g, B, ts, k, osc, last2, x, r, rout, din, dout, st)
+                 : launch_cheb2t_p<256, 2, T>(g, B, ts, k, osc, last2, x, r, rout, din, dout, st);
+    }
+  }
   const StencilShape sh = stencil_shape(g, kFusedKey, (int)sizeof(T));
   if (!cheb2_shape_ok(g.dim, sh.items, sh.threads)) return hipErrorInvalidValue;
   const Cheb2Geom c = cheb2_geom(g, sh);

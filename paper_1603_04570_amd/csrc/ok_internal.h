@@ -121,11 +121,23 @@ __device__ __forceinline__ void zrange(const StencilShape& sh, int nn, int zch, 
   z1 = (int)(((int64_t)(zch + 1) * nn) / sh.nzc);
 }
 StencilShape stencil_shape(const Grid& g, int nf, int word);
+// Whether the table holds an entry (items > 0) for (g, key, word).
+bool stencil_tuned(const Grid& g, int nf, int word);
 // Shape-table key of the fused two-iteration Chebyshev kernel (in place of nf).
 constexpr int kFusedKey = 17;
 // Shape-table keys of the fused multigrid smoother kernels (pre-smoothing +
 // residual, post-smoothing).
 constexpr int kMgPreKey = 18, kMgPostKey = 19;
+// Shape-table key of the 3D fused Chebyshev kernel on rectangular in-plane
+// tiles; where it has an entry (items > 0) the fused pairs use it.
+constexpr int kFusedTileKey = 20;
+// In-plane tile of that kernel: tx x ty nodes, ntx tiles per row of tiles.
+struct TileGeom {
+  int tx, ty, ntx, nty;
+};
+// Tile of the 3D fused pair for `threads` threads of `items` nodes on grid g
+// (false if none fits); blocks per plane = ntx * nty.
+bool cheb2_tile_geom(const Grid& g, int threads, int items, TileGeom& tg);
 // Launch-shape table of the stencil kernels, keyed by (dim, nodes per
 // direction, stenciled fields, bytes per stenciled word); items < 0 marks the
 // fused Chebyshev kernel as slower than single steps on that grid; items == 0 removes

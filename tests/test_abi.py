@@ -118,7 +118,13 @@ def test_launch_shape_arguments(lib):
     assert f(4, 64, 1, 0, 4, 256, 5) == E      # dim
     assert f(3, 0, 1, 0, 4, 256, 5) == E       # n
     assert f(3, 64, 9, 0, 4, 256, 5) == E      # kernel
-    assert f(3, 64, 6, 0, 2, 256, 5) == E
+    assert f(3, 64, 7, 0, 2, 256, 5) == E
+    assert f(3, 64, 6, 0, 2, 512, 5) == 0      # fused pair on in-plane tiles
+    assert f(3, 256, 6, 1, 1, 256, 257) == 0
+    assert f(3, 64, 6, 0, 0, 0, 0) == 0 and f(3, 256, 6, 1, 0, 0, 0) == 0
+    assert f(2, 64, 6, 0, 2, 256, 5) == E      # tiles: 3D only
+    assert f(3, 64, 6, 0, 4, 256, 5) == E      # 1 or 2 nodes per thread
+    assert f(3, 64, 6, 0, 2, 128, 5) == E
     assert f(3, 64, 1, 2, 4, 256, 5) == E      # precision
     assert f(3, 64, 1, 0, 3, 256, 5) == E      # items
     assert f(3, 64, 1, 0, 8, 512, 5) == E      # 512 threads: at most 4 nodes

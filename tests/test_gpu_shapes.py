@@ -2,7 +2,8 @@
 
 Every node's arithmetic is the same whatever the shape, so results must be
 bitwise equal for every item count per thread, for 256- and 512-thread
-fused blocks, and for every split of the planes into z-ranges (one range,
+fused blocks, for row-run and rectangular-tile blocks of the fused
+Chebyshev pair, and for every split of the planes into z-ranges (one range,
 uneven ranges, one plane per range).
 """
 import numpy as np
@@ -43,6 +44,16 @@ def test_fused_chebyshev_shapes_bitwise(dim, n, precision):
                 assert np.array_equal(cheb_mass(P, r, nodes), ref), (items, threads, zch)
     finally:
         ok.set_launch_shape(dim, n, ok.OK_SHAPE_CHEB2, precision, 0)
+    if dim == 3:  # the same pairs on rectangular in-plane tiles
+        try:
+            for items, threads in [(1, 256), (2, 256), (1, 512), (2, 512)]:
+                for zch in (1, 3, 7, n + 1):
+                    print("tiled shape", n, precision, items, threads, zch, flush=True)
+                    ok.set_launch_shape(dim, n, ok.OK_SHAPE_CHEB2_TILE, precision, items, threads,
+                                        zch)
+                    assert np.array_equal(cheb_mass(P, r, nodes), ref), (items, threads, zch)
+        finally:
+            ok.set_launch_shape(dim, n, ok.OK_SHAPE_CHEB2_TILE, precision, 0)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
