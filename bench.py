@@ -51,7 +51,7 @@ K_CHEB_MASS, K_KRYLOV = 1, 5
 KERNELS = {
     K_KRYLOV: ("mgs", "fused modified Gram-Schmidt step + dot products of FGMRES (k_mgs, k_dot)",
                ("paper_1603_04570_amd/csrc/k_krylov.hip", "paper_1603_04570_amd/csrc/ok_internal.h")),
-    K_CHEB_MASS: ("cheb_step", "Chebyshev-Jacobi iterations on M (k_cheb2 pairs, k_stencil EpiChebStep)",
+    K_CHEB_MASS: ("cheb_step", "Chebyshev-Jacobi iterations on M (k_cheb2 or k_cheb2t pairs, k_stencil EpiChebStep)",
                   ("paper_1603_04570_amd/csrc/k_stencil_impl.h",
                    "paper_1603_04570_amd/csrc/ok_internal.h")),
 }
