@@ -220,7 +220,9 @@ struct Src {
 template <int DIM, int NF, int NT, int P, int F, bool SCALED, class TS, class Epi>
 __global__ void __launch_bounds__(NT)
     k_stencil(Src<TS, NF> src, Grid g, StencilShape sh, Batch B, Epi epi) {
-  extern __shared__ double lds[];
+  // staged planes keep the storage type: every value is read as a double
+  extern __shared__ double lds_raw[];
+  TS* const lds = reinterpret_cast<TS*>(lds_raw);
   using In = typename Epi::In;
   constexpr bool MASS = MassOnly<Epi>::value;
   const int tid = threadIdx.x;
@@ -279,7 +281,7 @@ __global__ void __launch_bounds__(NT)
       for (int k = 0; k < F; k++) {
         const int t = tid + NT * k;
         const int64_t gq = s0 - halo + t;
-        if (t < ldsn) lds[f * ldsn + t] = (gq >= 0 && gq < plane) ? to_d(pre[f][k]) : 0.0;
+        if (t < ldsn) lds[f * ldsn + t] = (gq >= 0 && gq < plane) ? pre[f][k] : TS(0);
       }
   };
   // In-plane partial products: 3D P_M = (M1 x M1) s, P_K = (K1 x M1 + M1 x K1) s;
@@ -295,7 +297,7 @@ __global__ void __launch_bounds__(NT)
           const bool ey = (jj[p] == 0 || jj[p] == N);  // rows j-1, j+1 outside are zero in LDS
 #pragma unroll
           for (int f = 0; f < NF; f++) {
-            const double* lf = lds + f * ldsn;
+            const TS* lf = lds + f * ldsn;
             double mr[3], kr[3];
 #pragma unroll
             for (int r = 0; r < 3; r++) {
@@ -313,7 +315,7 @@ __global__ void __launch_bounds__(NT)
         } else {
 #pragma unroll
           for (int f = 0; f < NF; f++) {
-            const double* lf = lds + f * ldsn;
+            const TS* lf = lds + f * ldsn;
             const double va = lf[L - 1], vb = lf[L], vc = lf[L + 1];
             pm[f][p] = m1_row(hl, hr, ex, va, vb, vc);
             if (!MASS) pk[f][p] = k1_row(hl, hr, ex, va, vb, vc);
@@ -328,7 +330,7 @@ __global__ void __launch_bounds__(NT)
           pattern<SCALED>(jj[p], N, ay0, ay1, ay2, by0, by1, by2);
 #pragma unroll
           for (int f = 0; f < NF; f++) {
-            const double* lf = lds + f * ldsn;
+            const TS* lf = lds + f * ldsn;
             double mr[3], kr[3];
 #pragma unroll
             for (int r = 0; r < 3; r++) {
@@ -346,7 +348,7 @@ __global__ void __launch_bounds__(NT)
         } else {
 #pragma unroll
           for (int f = 0; f < NF; f++) {
-            const double* lf = lds + f * ldsn;
+            const TS* lf = lds + f * ldsn;
             double va = lf[L - 1], vb = lf[L], vc = lf[L + 1];
             pm[f][p] = sum3(ax0, ax1, ax2, va, vb, vc);
             pk[f][p] = MASS ? 0.0 : sum3(bx0, bx1, bx2, va, vb, vc);
@@ -462,7 +464,7 @@ static hipError_t run_stencil_n(const Grid& g, const Batch& B, const Src<TS, NF>
   if (!stencil_shape_ok(g.dim, NF, sh.items, sh.threads)) return hipErrorInvalidValue;
   const int NTh = sh.threads;
   const int ldsn = sh.chunk + 2 * (g.dim == 3 ? g.nn + 1 : 1);
-  size_t lds = (size_t)NF * ldsn * sizeof(double);
+  size_t lds = (size_t)NF * ldsn * sizeof(TS);
   // prefetch registers beyond the chunk: ceil(2*halo/threads) rounded up to 3, 5, 9, 17
   int extra = (ldsn - sh.chunk + NTh - 1) / NTh;
   int hx = extra <= 3 ? 3 : (extra <= 5 ? 5 : (extra <= 9 ? 9 : 17));
@@ -794,7 +796,7 @@ template <int DIM, int NT, int P, int P1, int FA, class T, bool LAST2>
 __global__ void __launch_bounds__(NT)
     k_cheb2(Grid g, StencilShape sh, Batch B, int kk, int osc, Vec<T> xv, Vec<const T> rinv,
             Vec<T> routv, Vec<const T> dinv_, Vec<T> doutv) {
-  extern __shared__ double lds[];
+  extern __shared__ double lds_raw[];  // holds words of T: every staged value is T-exact
   const int tid = threadIdx.x;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = lb / sh.blocks;
@@ -809,10 +811,10 @@ __global__ void __launch_bounds__(NT)
   const int H = (DIM == 3) ? nn + 1 : 1;  // one row (3D) or one node (2D) of halo
   const int CH = sh.chunk;
   const int E1 = CH + 2 * H, E2 = CH + 4 * H;
-  double* LA = lds;          // d_k, positions s0-2H .. s0+CH+2H
-  double* LB = LA + E2;      // d_{k+1}, positions s0-H .. s0+CH+H
-  double* LR = LB + E1;      // r_{k+1} on the chunk, two buffers
-  double* LD = LR + 2 * CH;  // d_k on the chunk, two buffers
+  T* LA = reinterpret_cast<T*>(lds_raw);  // d_k, positions s0-2H .. s0+CH+2H
+  T* LB = LA + E2;      // d_{k+1}, positions s0-H .. s0+CH+H
+  T* LR = LB + E1;      // r_{k+1} on the chunk, two buffers
+  T* LD = LR + 2 * CH;  // d_k on the chunk, two buffers
   const int64_t s0 = (int64_t)chunk * CH;
   T* __restrict__ x = xv.at(inst);
   const T* __restrict__ r = rinv.at(inst);
@@ -861,7 +863,7 @@ __global__ void __launch_bounds__(NT)
   };
   // in-plane mass partial (M1 x M1) v at LDS position L of buffer v (the
   // arithmetic of the one-iteration kernel)
-  auto mpart = [&](const double* v, int L, int i, int j) {
+  auto mpart = [&](const T* v, int L, int i, int j) {
     const bool hl = i > 0, hr = i < N, ex = (i == 0 || i == N);
     if (DIM == 3) {
       const bool ey = (j == 0 || j == N);
@@ -900,7 +902,7 @@ __global__ void __launch_bounds__(NT)
       for (int k = 0; k < FA; k++) {
         const int t = tid + NT * k;
         const int64_t gq = s0 - 2 * H + t;
-        if (t < E2) LA[t] = (gq >= 0 && gq < plane) ? to_d(pa[k]) : 0.0;
+        if (t < E2) LA[t] = (gq >= 0 && gq < plane) ? pa[k] : T(0);
       }
     }
     __syncthreads();
@@ -942,11 +944,11 @@ __global__ void __launch_bounds__(NT)
           d1 = to_d((T)cheb_dir(ka, dk, dv, ru));
           const int c = e - H;
           if (c >= 0 && c < CH) {
-            LR[buf * CH + c] = rv1;
-            LD[buf * CH + c] = dk;
+            LR[buf * CH + c] = (T)rv1;
+            LD[buf * CH + c] = (T)dk;
           }
         }
-        LB[e] = d1;
+        LB[e] = (T)d1;
       }
     }
 #pragma unroll
@@ -1023,7 +1025,7 @@ __global__ void __launch_bounds__(NT)
     k_cheb2t(Grid g, StencilShape sh, TileGeom tg, Batch B, int kk, int osc, Vec<T> xv,
              Vec<const T> rinv, Vec<T> routv, Vec<const T> dinv_, Vec<T> doutv) {
   constexpr int P1 = P + 1;
-  extern __shared__ double lds[];
+  extern __shared__ double lds_raw[];  // holds words of T: every staged value is T-exact
   const int tid = threadIdx.x;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = lb / sh.blocks;
@@ -1039,10 +1041,10 @@ __global__ void __launch_bounds__(NT)
   const int x0 = (tile % tg.ntx) * TX, y0 = (tile / tg.ntx) * TY;
   const int WA = TX + 4, WB = TX + 2;  // LDS row pitches
   const int EA = WA * (TY + 4), E1 = WB * (TY + 2), CH = TX * TY;
-  double* LA = lds;          // d_k: rows y0-2 .. y0+TY+1, columns x0-2 .. x0+TX+1
-  double* LB = LA + EA;      // d_{k+1}: rows y0-1 .. y0+TY, columns x0-1 .. x0+TX
-  double* LR = LB + E1;      // r_{k+1} on the tile, two buffers
-  double* LD = LR + 2 * CH;  // d_k on the tile, two buffers
+  T* LA = reinterpret_cast<T*>(lds_raw);  // d_k: rows y0-2 .. y0+TY+1, columns x0-2 .. x0+TX+1
+  T* LB = LA + EA;      // d_{k+1}: rows y0-1 .. y0+TY, columns x0-1 .. x0+TX
+  T* LR = LB + E1;      // r_{k+1} on the tile, two buffers
+  T* LD = LR + 2 * CH;  // d_k on the tile, two buffers
   T* __restrict__ x = xv.at(inst);
   const T* __restrict__ r = rinv.at(inst);
   T* __restrict__ rout = LAST2 ? nullptr : routv.at(inst);
@@ -1102,7 +1104,7 @@ __global__ void __launch_bounds__(NT)
   };
   // in-plane mass partial (M1 x M1) v at LDS position L of a buffer with row
   // pitch ys (the arithmetic of the one-iteration kernel)
-  auto mpart = [&](const double* v, int L, int ys, int i, int j) {
+  auto mpart = [&](const T* v, int L, int ys, int i, int j) {
     const bool hl = i > 0, hr = i < N, ex = (i == 0 || i == N);
     const bool ey = (j == 0 || j == N);
     double m[3];
@@ -1137,7 +1139,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
       for (int k = 0; k < P1; k++) {
         const int t = tid + NT * k;
-        if (t < EA) LA[t] = ((va >> k) & 1u) ? to_d(pa[k]) : 0.0;
+        if (t < EA) LA[t] = ((va >> k) & 1u) ? pa[k] : T(0);
       }
     }
     __syncthreads();
@@ -1178,11 +1180,11 @@ __global__ void __launch_bounds__(NT)
           const int ci = i1[q] - x0, cj = j1[q] - y0;
           if (ci >= 0 && ci < TX && cj >= 0 && cj < TY) {
             const int c = cj * TX + ci;
-            LR[buf * CH + c] = rv1;
-            LD[buf * CH + c] = dk;
+            LR[buf * CH + c] = (T)rv1;
+            LD[buf * CH + c] = (T)dk;
           }
         }
-        LB[e] = d1;
+        LB[e] = (T)d1;
       }
     }
 #pragma unroll
@@ -1242,8 +1244,8 @@ __global__ void __launch_bounds__(NT)
 // In-plane partial products of M and K at LDS position L of plane buffer v
 // (node (i, j)): the arithmetic of the one-field streaming kernel, unscaled
 // or with the W^-1-scaled patterns (SCALED).
-template <int DIM, bool SCALED>
-__device__ __forceinline__ void mk_partials(const double* v, int L, int ystep, int i, int j, int N,
+template <int DIM, bool SCALED, class V>
+__device__ __forceinline__ void mk_partials(const V* v, int L, int ystep, int i, int j, int N,
                                             double& pm, double& pk) {
   if constexpr (!SCALED) {
     const bool hl = i > 0, hr = i < N, ex = (i == 0 || i == N);
@@ -1312,7 +1314,7 @@ template <int DIM, int NT, int P, int P1, int FA, class T, bool PRE>
 __global__ void __launch_bounds__(NT)
     k_mg2(Grid g, StencilShape sh, Batch B, int lev, Vec<const T> av, Vec<const T> bv,
           Vec<T> out1v, Vec<T> out2v) {
-  extern __shared__ double lds[];
+  extern __shared__ double lds_raw[];  // holds words of T: every staged value is T-exact
   const int tid = threadIdx.x;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = lb / sh.blocks;
@@ -1328,10 +1330,10 @@ __global__ void __launch_bounds__(NT)
   const int H = (DIM == 3) ? nn + 1 : 1;
   const int CH = sh.chunk;
   const int E1 = CH + 2 * H, E2 = CH + 4 * H;
-  double* LA = lds;
-  double* LB = LA + E2;
-  double* LR = LB + E1;
-  double* LD = LR + 2 * CH;
+  T* LA = reinterpret_cast<T*>(lds_raw);
+  T* LB = LA + E2;
+  T* LR = LB + E1;
+  T* LD = LR + 2 * CH;
   const int64_t s0 = (int64_t)chunk * CH;
   const T* __restrict__ a = av.at(inst);
   const T* __restrict__ bsrc = PRE ? nullptr : bv.at(inst);
@@ -1399,7 +1401,7 @@ __global__ void __launch_bounds__(NT)
       for (int k = 0; k < FA; k++) {
         const int t = tid + NT * k;
         const int64_t gq = s0 - 2 * H + t;
-        if (t < E2) LA[t] = (gq >= 0 && gq < plane) ? to_d(pa[k]) : 0.0;
+        if (t < E2) LA[t] = (gq >= 0 && gq < plane) ? pa[k] : T(0);
       }
     }
     __syncthreads();
@@ -1443,17 +1445,17 @@ __global__ void __launch_bounds__(NT)
             const double r1 = bi - ad0;
             const double d1 = cheb_dir(k1, d0, dv, r1);
             f1 = to_d((T)(k1.osc * (d0 + d1)));
-            if (c >= 0 && c < CH) LD[buf * CH + c] = bi;
+            if (c >= 0 && c < CH) LD[buf * CH + c] = (T)bi;
           } else {
             const double r0 = to_d(bq[q]) - op_apply(k1, ms, ks);
             f1 = to_d((T)(dv * r0 * k1.it));
             if (c >= 0 && c < CH) {
-              LR[buf * CH + c] = to_d((T)r0);
-              LD[buf * CH + c] = cb1[q];
+              LR[buf * CH + c] = (T)r0;
+              LD[buf * CH + c] = (T)cb1[q];
             }
           }
         }
-        LB[e] = f1;
+        LB[e] = (T)f1;
       }
     }
 #pragma unroll
@@ -1623,7 +1625,7 @@ hipError_t launch_cheb2_p(const Grid& g, const Batch& B, const StencilShape& sh,
                           Vec<T> dout, hipStream_t st) {
   const int H = (DIM == 3) ? g.nn + 1 : 1;
   if (sh.chunk != NT * P) return hipErrorInvalidValue;
-  const size_t lds = (size_t)(sh.chunk + 4 * H + sh.chunk + 2 * H + 4 * sh.chunk) * sizeof(double);
+  const size_t lds = (size_t)(sh.chunk + 4 * H + sh.chunk + 2 * H + 4 * sh.chunk) * sizeof(T);
   if (lds > 65536) return hipErrorInvalidValue;
   const int64_t nblk = (int64_t)sh.blocks * B.count;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
@@ -1694,7 +1696,7 @@ bool mg2_shape_valid(const Grid& g, int key, int word) {
   const bool combo = (g.dim == 2) ? (c.ex1 == 1 && c.exa == 1)
                                   : ((c.ex1 == 1 && c.exa <= 2) || (c.ex1 == 2 && c.exa == 3) ||
                                      (c.ex1 == 3 && c.exa == 5) || (c.ex1 == 5 && c.exa == 9));
-  return combo && (size_t)(6 * sh.chunk + 6 * H) * sizeof(double) <= 65536;
+  return combo && (size_t)(6 * sh.chunk + 6 * H) * (size_t)word <= 65536;
 }
 
 // The fused smoothers hold many more registers than the one-iteration
@@ -1735,7 +1737,7 @@ bool cheb_fusion_on(const Grid& g, int word) {
                                   : ((c.ex1 == 1 && c.exa <= 2) || (c.ex1 == 2 && c.exa == 3) ||
                                      (c.ex1 == 3 && c.exa == 5) || (c.ex1 == 5 && c.exa == 9));
   const int ch = c.nt * c.p;
-  return combo && (size_t)(6 * ch + 6 * H) * sizeof(double) <= 65536;
+  return combo && (size_t)(6 * ch + 6 * H) * (size_t)word <= 65536;
 }
 #endif  // OKD_STENCIL_PART == 0
 
@@ -1750,7 +1752,7 @@ hipError_t launch_cheb2t_p(const Grid& g, const Batch& B, const StencilShape& sh
   sh.nchunks = tg.ntx * tg.nty;
   sh.blocks = sh.nchunks * sh.nzc;
   const size_t lds = (size_t)((tg.tx + 4) * (tg.ty + 4) + (tg.tx + 2) * (tg.ty + 2) +
-                              4 * tg.tx * tg.ty) * sizeof(double);
+                              4 * tg.tx * tg.ty) * sizeof(T);
   if (lds > 65536 || tg.tx * tg.ty > NT * P || (tg.tx + 4) * (tg.ty + 4) > NT * (P + 1))
     return hipErrorInvalidValue;
   const int64_t nblk = (int64_t)sh.blocks * B.count;
@@ -1808,7 +1810,7 @@ hipError_t launch_mg2_p(const Grid& g, const Batch& B, const StencilShape& sh, i
                         Vec<const T> a, Vec<const T> b, Vec<T> o1, Vec<T> o2, hipStream_t st) {
   const int H = (DIM == 3) ? g.nn + 1 : 1;
   if (sh.chunk != NT * P) return hipErrorInvalidValue;
-  const size_t lds = (size_t)(sh.chunk + 4 * H + sh.chunk + 2 * H + 4 * sh.chunk) * sizeof(double);
+  const size_t lds = (size_t)(sh.chunk + 4 * H + sh.chunk + 2 * H + 4 * sh.chunk) * sizeof(T);
   if (lds > 65536) return hipErrorInvalidValue;
   const int64_t nblk = (int64_t)sh.blocks * B.count;
   if (nblk > 0x7fffffff) return hipErrorInvalidValue;
