@@ -1025,7 +1025,7 @@ __global__ void __launch_bounds__(NT)
     k_cheb2t(Grid g, StencilShape sh, TileGeom tg, Batch B, int kk, int osc, Vec<T> xv,
              Vec<const T> rinv, Vec<T> routv, Vec<const T> dinv_, Vec<T> doutv) {
   constexpr int P1 = P + 1;
-  extern __shared__ double lds_raw[];  // holds words of T: every staged value is T-exact
+  extern __shared__ double lds_raw[];  // staged as doubles: reads need no conversion
   const int tid = threadIdx.x;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = lb / sh.blocks;
@@ -1041,10 +1041,10 @@ __global__ void __launch_bounds__(NT)
   const int x0 = (tile % tg.ntx) * TX, y0 = (tile / tg.ntx) * TY;
   const int WA = TX + 4, WB = TX + 2;  // LDS row pitches
   const int EA = WA * (TY + 4), E1 = WB * (TY + 2), CH = TX * TY;
-  T* LA = reinterpret_cast<T*>(lds_raw);  // d_k: rows y0-2 .. y0+TY+1, columns x0-2 .. x0+TX+1
-  T* LB = LA + EA;      // d_{k+1}: rows y0-1 .. y0+TY, columns x0-1 .. x0+TX
-  T* LR = LB + E1;      // r_{k+1} on the tile, two buffers
-  T* LD = LR + 2 * CH;  // d_k on the tile, two buffers
+  double* LA = lds_raw;  // d_k: rows y0-2 .. y0+TY+1, columns x0-2 .. x0+TX+1
+  double* LB = LA + EA;      // d_{k+1}: rows y0-1 .. y0+TY, columns x0-1 .. x0+TX
+  double* LR = LB + E1;      // r_{k+1} on the tile, two buffers
+  double* LD = LR + 2 * CH;  // d_k on the tile, two buffers
   T* __restrict__ x = xv.at(inst);
   const T* __restrict__ r = rinv.at(inst);
   T* __restrict__ rout = LAST2 ? nullptr : routv.at(inst);
@@ -1103,15 +1103,17 @@ __global__ void __launch_bounds__(NT)
     for (int p = 0; p < P; p++) px[p] = x[(int64_t)zx * plane + (int64_t)j2[p] * nn + i2[p]];
   };
   // in-plane mass partial (M1 x M1) v at LDS position L of a buffer with row
-  // pitch ys (the arithmetic of the one-iteration kernel)
-  auto mpart = [&](const T* v, int L, int ys, int i, int j) {
-    const bool hl = i > 0, hr = i < N, ex = (i == 0 || i == N);
+  // pitch ys (the arithmetic of the one-iteration kernel).  The neighbours
+  // that kernel masks out at i = 0 and i = N lie outside the grid here and
+  // hold +0 in LDS, so adding them unmasked gives the same bits.
+  auto mpart = [&](const double* v, int L, int ys, int i, int j) {
+    const bool ex = (i == 0 || i == N);
     const bool ey = (j == 0 || j == N);
     double m[3];
 #pragma unroll
     for (int rr = 0; rr < 3; rr++) {
       const int bse = L + (rr - 1) * ys;
-      m[rr] = m1_row(hl, hr, ex, v[bse - 1], v[bse], v[bse + 1]);
+      m[rr] = m1_row(true, true, ex, v[bse - 1], v[bse], v[bse + 1]);
     }
     return m1_row(true, true, ey, m[0], m[1], m[2]);
   };
@@ -1139,7 +1141,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
       for (int k = 0; k < P1; k++) {
         const int t = tid + NT * k;
-        if (t < EA) LA[t] = ((va >> k) & 1u) ? pa[k] : T(0);
+        if (t < EA) LA[t] = ((va >> k) & 1u) ? to_d(pa[k]) : 0.0;
       }
     }
     __syncthreads();
@@ -1180,11 +1182,11 @@ __global__ void __launch_bounds__(NT)
           const int ci = i1[q] - x0, cj = j1[q] - y0;
           if (ci >= 0 && ci < TX && cj >= 0 && cj < TY) {
             const int c = cj * TX + ci;
-            LR[buf * CH + c] = (T)rv1;
-            LD[buf * CH + c] = (T)dk;
+            LR[buf * CH + c] = rv1;
+            LD[buf * CH + c] = dk;
           }
         }
-        LB[e] = (T)d1;
+        LB[e] = d1;
       }
     }
 #pragma unroll
@@ -1752,7 +1754,7 @@ hipError_t launch_cheb2t_p(const Grid& g, const Batch& B, const StencilShape& sh
   sh.nchunks = tg.ntx * tg.nty;
   sh.blocks = sh.nchunks * sh.nzc;
   const size_t lds = (size_t)((tg.tx + 4) * (tg.ty + 4) + (tg.tx + 2) * (tg.ty + 2) +
-                              4 * tg.tx * tg.ty) * sizeof(T);
+                              4 * tg.tx * tg.ty) * sizeof(double);
   if (lds > 65536 || tg.tx * tg.ty > NT * P || (tg.tx + 4) * (tg.ty + 4) > NT * (P + 1))
     return hipErrorInvalidValue;
   const int64_t nblk = (int64_t)sh.blocks * B.count;
