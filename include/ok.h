@@ -251,9 +251,9 @@ int ok_set_option(int32_t option, int32_t value);
  *   items, threads: a block of `threads` threads covers items*threads nodes
  *     of a plane.  STENCIL: 256 threads of 1, 2, 4 or 8 nodes, in 3D also 512
  *     threads of 1, 2 or 4; STENCIL2: 256 threads of 1, 2 or 4; CHEB2,
- *     MG_PRE, MG_POST: 256 threads (3D also 512) of 1 or 2; CHEB2_TILE (3D
- *     only): 256 or 512 threads of 1 or 2 nodes, the tile (about
- *     items*threads nodes) chosen by the library.  items = 0 removes the entry (built-in
+ *     MG_PRE, MG_POST: 256 threads (3D also 512) of 1 or 2; CHEB2_TILE,
+ *     MG_PRE_TILE, MG_POST_TILE (3D only): 256 or 512 threads of 1 or 2
+ *     nodes, the tile (about items*threads nodes) chosen by the library.  items = 0 removes the entry (built-in
  *     default shape; threads and zchunks are then ignored);
  *   zchunks: the n+1 planes of the streaming axis are split evenly into
  *     1..n+1 ranges, one block per (plane chunk, range).
@@ -267,8 +267,10 @@ enum ok_shape_kernel {
   OK_SHAPE_CHEB2 = 3,
   OK_SHAPE_MG_PRE = 4,  /* fused pre-smoothing + residual of a multigrid level */
   OK_SHAPE_MG_POST = 5, /* fused post-smoothing of a multigrid level */
-  OK_SHAPE_CHEB2_TILE = 6 /* CHEB2 on rectangular in-plane tiles (3D); while set,
-                             the fused pairs of that grid use it */
+  OK_SHAPE_CHEB2_TILE = 6, /* CHEB2 on rectangular in-plane tiles (3D); while set,
+                              the fused pairs of that grid use it */
+  OK_SHAPE_MG_PRE_TILE = 7, /* MG_PRE / MG_POST on in-plane tiles (3D); used while */
+  OK_SHAPE_MG_POST_TILE = 8 /* set on a level whose fused smoothers are on */
 };
 int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precision, int32_t items,
                         int32_t threads, int32_t zchunks);

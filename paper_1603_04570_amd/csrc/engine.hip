@@ -1245,6 +1245,8 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
     // beats the four one-iteration kernels it replaces
     stencil_tune_set(g.dim, g.nn, kMgPreKey, word, 0, 0);
     stencil_tune_set(g.dim, g.nn, kMgPostKey, word, 0, 0);
+    stencil_tune_set(g.dim, g.nn, kMgPreTileKey, word, 0, 0);
+    stencil_tune_set(g.dim, g.nn, kMgPostTileKey, word, 0, 0);
     if (c.shape.mg_pre == 2 && c.shape.mg_post == 2 && mg_fusion_enabled()) {
       Vec<P> bb = (l == 0) ? pvec<P>(c.cr2, nl) : pvec<P>(c.mg[l][1], nl);
       const double unfused = time_best(st, [&]() {
@@ -1278,11 +1280,41 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
             }
           }
         stencil_tune_set(g.dim, g.nn, key, word, ki, kz, kt);
-        fused += ki ? kbest : 1e30;
+        // the same kernel on in-plane tiles (3D); it needs a valid row-run
+        // entry beside it, which switches the fused smoothers on
+        double tbest = 1e30;
+        int ti = 0, tz = 0, tt = 256;
+        const int tkey = key == kMgPreKey ? kMgPreTileKey : kMgPostTileKey;
+        if (g.dim == 3 && ki) {
+          for (int threads : {256, 512})
+            for (int items = 1; items <= 2; items++) {
+              TileGeom tg;
+              if (!cheb2_tile_geom(g, threads, items, tg)) continue;
+              for (int zc : zchunk_candidates_n(g, (int64_t)tg.ntx * tg.nty, B.count)) {
+                stencil_tune_set(g.dim, g.nn, tkey, word, items, zc, threads);
+                double t = time_best(st, [&]() {
+                  return key == kMgPreKey
+                             ? launch_mg_pre2<P>(g, B, l, cst(bb), x, r, st)
+                             : launch_mg_post2<P>(g, B, l, cst(bb), cst(x), d1, st);
+                });
+                if (t < tbest) {
+                  tbest = t;
+                  ti = items;
+                  tz = zc;
+                  tt = threads;
+                }
+              }
+            }
+          stencil_tune_set(g.dim, g.nn, tkey, word, 0, 0);
+          if (ti && tbest < kbest) stencil_tune_set(g.dim, g.nn, tkey, word, ti, tz, tt);
+        }
+        fused += ki ? std::min(kbest, tbest) : 1e30;
       }
       if (!(fused < unfused)) {
         stencil_tune_set(g.dim, g.nn, kMgPreKey, word, 0, 0);
         stencil_tune_set(g.dim, g.nn, kMgPostKey, word, 0, 0);
+        stencil_tune_set(g.dim, g.nn, kMgPreTileKey, word, 0, 0);
+        stencil_tune_set(g.dim, g.nn, kMgPostTileKey, word, 0, 0);
       }
       (*entries)++;
     }

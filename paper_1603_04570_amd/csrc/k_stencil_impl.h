@@ -1246,11 +1246,12 @@ __global__ void __launch_bounds__(NT)
 // In-plane partial products of M and K at LDS position L of plane buffer v
 // (node (i, j)): the arithmetic of the one-field streaming kernel, unscaled
 // or with the W^-1-scaled patterns (SCALED).
-template <int DIM, bool SCALED, class V>
+template <int DIM, bool SCALED, class V, bool NOMASK = false>
 __device__ __forceinline__ void mk_partials(const V* v, int L, int ystep, int i, int j, int N,
                                             double& pm, double& pk) {
   if constexpr (!SCALED) {
-    const bool hl = i > 0, hr = i < N, ex = (i == 0 || i == N);
+    // NOMASK: the neighbours dropped at i = 0 and i = N hold +0 (tiled layouts)
+    const bool hl = NOMASK || i > 0, hr = NOMASK || i < N, ex = (i == 0 || i == N);
     if (DIM == 3) {
       const bool ey = (j == 0 || j == N);
       double mr[3], kr[3];
@@ -1806,6 +1807,227 @@ hipError_t launch_cheb_step2(const Grid& g, const Batch& B, int k, int osc, bool
   return launch_cheb2_ex<3, 256, 2, T>(g, B, sh, c, k, osc, last2, x, r, rout, din, dout, st);
 }
 
+// The fused multigrid smoothers of k_mg2 (3D) on rectangular in-plane tiles,
+// as k_cheb2t is k_cheb2 on tiles: rings of two and one nodes instead of
+// whole halo rows, P + 1 slots per thread for both, LDS positions outside
+// the grid holding +0 so the in-plane stencils need no boundary masks, and
+// each node's arithmetic that of k_mg2 (same bits).
+template <int NT, int P, class T, bool PRE>
+__global__ void __launch_bounds__(NT)
+    k_mg2t(Grid g, StencilShape sh, TileGeom tg, Batch B, int lev, Vec<const T> av,
+           Vec<const T> bv, Vec<T> out1v, Vec<T> out2v) {
+  constexpr int P1 = P + 1;
+  extern __shared__ double lds_raw[];  // staged as doubles: reads need no conversion
+  const int tid = threadIdx.x;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int inst = lb / sh.blocks;
+  if (B.act && !B.act[inst]) return;
+  const int b = lb - inst * sh.blocks;
+  const int tile = b % sh.nchunks;
+  const int zch = b / sh.nchunks;
+  const InstCoef& IC = B.coef[inst];
+  const OpK k1 = PRE ? op_k(IC, lev, 0, CF_ONE) : op_k(IC, lev, -1, CF_ONE);
+  const OpK k2 = PRE ? op_k(IC, lev, -1, CF_ONE) : op_k(IC, lev, 0, CF_ONE);
+  const int nn = g.nn, N = g.N;
+  const int64_t plane = g.plane;
+  const int TX = tg.tx, TY = tg.ty;
+  const int x0 = (tile % tg.ntx) * TX, y0 = (tile / tg.ntx) * TY;
+  const int WA = TX + 4, WB = TX + 2;
+  const int EA = WA * (TY + 4), E1 = WB * (TY + 2), CH = TX * TY;
+  double* LA = lds_raw;      // input: rows y0-2 .. y0+TY+1, columns x0-2 .. x0+TX+1
+  double* LB = LA + EA;      // stage-1 field: rows y0-1 .. y0+TY, columns x0-1 .. x0+TX
+  double* LR = LB + E1;      // POST r0 on the tile, two buffers
+  double* LD = LR + 2 * CH;  // the input on the tile, two buffers
+  const T* __restrict__ a = av.at(inst);
+  const T* __restrict__ bsrc = PRE ? nullptr : bv.at(inst);
+  T* __restrict__ o1 = out1v.at(inst);
+  T* __restrict__ o2 = PRE ? out2v.at(inst) : nullptr;
+  auto cl = [&](int v) { return v < 0 ? 0 : (v > N ? N : v); };
+
+  int oa[P1];
+  unsigned va = 0;
+#pragma unroll
+  for (int k = 0; k < P1; k++) {
+    const int t = tid + NT * k;
+    const int ra = t / WA, ca = t - ra * WA;
+    const int gy = y0 - 2 + ra, gx = x0 - 2 + ca;
+    if (t < EA && gy >= 0 && gy <= N && gx >= 0 && gx <= N) va |= 1u << k;
+    oa[k] = cl(gy) * nn + cl(gx);
+  }
+  int i1[P1], j1[P1], l1[P1];
+  bool v1[P1];
+#pragma unroll
+  for (int q = 0; q < P1; q++) {
+    const int e = tid + NT * q;
+    const int rb = e / WB, cb = e - rb * WB;
+    const int gy = y0 - 1 + rb, gx = x0 - 1 + cb;
+    v1[q] = e < E1 && gy >= 0 && gy <= N && gx >= 0 && gx <= N;
+    i1[q] = cl(gx);
+    j1[q] = cl(gy);
+    l1[q] = e < E1 ? (rb + 1) * WA + cb + 1 : WA + 1;
+  }
+  int i2[P], j2[P], l2[P];
+  bool v2[P];
+#pragma unroll
+  for (int p = 0; p < P; p++) {
+    const int c = tid + NT * p;
+    const int aa = c / TX, bb = c - aa * TX;
+    const int gy = y0 + aa, gx = x0 + bb;
+    v2[p] = c < CH && gy <= N && gx <= N;
+    i2[p] = cl(gx);
+    j2[p] = cl(gy);
+    l2[p] = c < CH ? (aa + 1) * WB + bb + 1 : WB + 1;
+  }
+
+  T pa[P1], pr[P1];
+  auto issue_a = [&](int64_t zoff) {
+#pragma unroll
+    for (int k = 0; k < P1; k++) pa[k] = a[zoff + oa[k]];
+  };
+  auto issue_b = [&](int zr) {
+    if constexpr (!PRE) {
+#pragma unroll
+      for (int q = 0; q < P1; q++)
+        pr[q] = bsrc[(int64_t)zr * plane + (int64_t)j1[q] * nn + i1[q]];
+    }
+  };
+
+  const double h = g.h;
+  const double cmass = h * h * h / 216.0;
+  const double cstiff = h / 36.0;
+  int z0, z1;
+  zrange(sh, nn, zch, z0, z1);
+  const int zlast = min(z1 + 1, N);
+  double pa1[P1], pb1[P1], qa1[P1], qb1[P1], cb1[P1];
+  double pa2[P], pb2[P], qa2[P], qb2[P], cb2[P];
+#pragma unroll
+  for (int q = 0; q < P1; q++) pa1[q] = pb1[q] = qa1[q] = qb1[q] = cb1[q] = 0.0;
+#pragma unroll
+  for (int p = 0; p < P; p++) pa2[p] = pb2[p] = qa2[p] = qb2[p] = cb2[p] = 0.0;
+  issue_a((int64_t)max(z0 - 2, 0) * plane);
+  issue_b(max(z0 - 1, 0));
+  for (int pz = z0 - 2; pz <= z1 + 1; pz++) {
+    const bool insideA = (pz >= 0 && pz <= N);
+    const int q1 = pz - 1;  // stage-1 output plane
+    const int o = pz - 2;   // stage-2 output plane
+    const int buf = pz & 1;
+    __syncthreads();
+    if (insideA) {
+#pragma unroll
+      for (int k = 0; k < P1; k++) {
+        const int t = tid + NT * k;
+        if (t < EA) LA[t] = ((va >> k) & 1u) ? to_d(pa[k]) : 0.0;
+      }
+    }
+    __syncthreads();
+    T bq[P1];
+#pragma unroll
+    for (int q = 0; q < P1; q++) bq[q] = pr[q];
+    issue_a((int64_t)max(min(pz + 1, zlast), 0) * plane);  // plane -1 is never read
+    issue_b(min(max(q1 + 1, 0), N));
+    double pn1[P1], qn1[P1], cn1[P1];
+#pragma unroll
+    for (int q = 0; q < P1; q++) {
+      pn1[q] = qn1[q] = cn1[q] = 0.0;
+      if (insideA && (tid + NT * q < E1)) {
+        mk_partials<3, PRE, double, true>(LA, l1[q], WA, i1[q], j1[q], N, pn1[q], qn1[q]);
+        cn1[q] = LA[l1[q]];
+      }
+    }
+    if (q1 >= z0 - 1 && q1 <= z1) {
+      const bool inq = (q1 >= 0 && q1 <= N);
+      double az0 = 0, az1 = 0, az2 = 0, bz0 = 0, bz1 = 0, bz2 = 0;
+      if (inq) pattern<PRE>(q1, N, az0, az1, az2, bz0, bz1, bz2);
+      const int nbz = (q1 == 0 || q1 == N);
+#pragma unroll
+      for (int q = 0; q < P1; q++) {
+        const int e = tid + NT * q;
+        if (e >= E1) continue;
+        double f1 = 0.0;
+        if (inq && v1[q]) {
+          const double ms = cmass * sum3(az0, az1, az2, pa1[q], pb1[q], pn1[q]);
+          const double ks = cstiff * (sum3(az0, az1, az2, qa1[q], qb1[q], qn1[q]) +
+                                      sum3(bz0, bz1, bz2, pa1[q], pb1[q], pn1[q]));
+          const int nb = (i1[q] == 0 || i1[q] == N) + nbz + (j1[q] == 0 || j1[q] == N);
+          const double dv = dinv_at(k1.dinv, nb);
+          const int ci = i1[q] - x0, cj = j1[q] - y0;
+          const bool own = ci >= 0 && ci < TX && cj >= 0 && cj < TY;
+          const int c = cj * TX + ci;
+          if constexpr (PRE) {
+            const double bi = cb1[q];
+            const double ad0 = k1.dinv * k1.it * op_apply(k1, ms, ks);
+            const double d0 = dv * bi * k1.it;
+            const double r1 = bi - ad0;
+            const double d1 = cheb_dir(k1, d0, dv, r1);
+            f1 = to_d((T)(k1.osc * (d0 + d1)));
+            if (own) LD[buf * CH + c] = bi;
+          } else {
+            const double r0 = to_d(bq[q]) - op_apply(k1, ms, ks);
+            f1 = to_d((T)(dv * r0 * k1.it));
+            if (own) {
+              LR[buf * CH + c] = to_d((T)r0);
+              LD[buf * CH + c] = cb1[q];
+            }
+          }
+        }
+        LB[e] = f1;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < P1; q++) {
+      pa1[q] = pb1[q];
+      pb1[q] = pn1[q];
+      qa1[q] = qb1[q];
+      qb1[q] = qn1[q];
+      cb1[q] = cn1[q];
+    }
+    __syncthreads();
+    if (q1 >= z0 - 1 && q1 <= z1) {
+      double pn2[P], qn2[P], cn2[P];
+#pragma unroll
+      for (int p = 0; p < P; p++) {
+        mk_partials<3, false, double, true>(LB, l2[p], WB, i2[p], j2[p], N, pn2[p], qn2[p]);
+        cn2[p] = LB[l2[p]];
+      }
+      if (o >= z0 && o < z1) {
+        double az0, az1, az2, bz0, bz1, bz2;
+        pattern<false>(o, N, az0, az1, az2, bz0, bz1, bz2);
+        const int nbz = (o == 0 || o == N);
+        const int pb = buf ^ 1;
+#pragma unroll
+        for (int p = 0; p < P; p++) {
+          if (!v2[p]) continue;
+          const int c = tid + NT * p;
+          const double ms = cmass * sum3(az0, az1, az2, pa2[p], pb2[p], pn2[p]);
+          const double ks = cstiff * (sum3(az0, az1, az2, qa2[p], qb2[p], qn2[p]) +
+                                      sum3(bz0, bz1, bz2, pa2[p], pb2[p], pn2[p]));
+          const int64_t idx = (int64_t)o * plane + (int64_t)j2[p] * nn + i2[p];
+          if constexpr (PRE) {
+            o1[idx] = (T)cb2[p];
+            o2[idx] = (T)(LD[pb * CH + c] - op_apply(k2, ms, ks));
+          } else {
+            const int nb = (i2[p] == 0 || i2[p] == N) + nbz + (j2[p] == 0 || j2[p] == N);
+            const double dk = cb2[p];
+            const double dv = dinv_at(k2.dinv, nb);
+            const double xv = LD[pb * CH + c] + dk;
+            const double rv = LR[pb * CH + c] - op_apply(k2, ms, ks);
+            const double d1 = cheb_dir(k2, dk, dv, rv);
+            o1[idx] = (T)(k2.osc * (xv + d1));
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < P; p++) {
+        pa2[p] = pb2[p];
+        pb2[p] = pn2[p];
+        qa2[p] = qb2[p];
+        qb2[p] = qn2[p];
+        cb2[p] = cn2[p];
+      }
+    }
+  }
+}
+
 namespace {
 template <int DIM, int NT, int P, int EX1, int EXA, class T, bool PRE>
 hipError_t launch_mg2_p(const Grid& g, const Batch& B, const StencilShape& sh, int lev,
@@ -1842,10 +2064,40 @@ hipError_t launch_mg2_ex(const Grid& g, const Batch& B, const StencilShape& sh,
 #undef OK_MG2
 }
 
+template <int NT, int P, class T, bool PRE>
+hipError_t launch_mg2t_p(const Grid& g, const Batch& B, const StencilShape& sh0, int lev,
+                         Vec<const T> a, Vec<const T> b, Vec<T> o1, Vec<T> o2, hipStream_t st) {
+  TileGeom tg;
+  if (!cheb2_tile_geom(g, NT, P, tg)) return hipErrorInvalidValue;
+  StencilShape sh = sh0;
+  sh.nchunks = tg.ntx * tg.nty;
+  sh.blocks = sh.nchunks * sh.nzc;
+  const size_t lds = (size_t)((tg.tx + 4) * (tg.ty + 4) + (tg.tx + 2) * (tg.ty + 2) +
+                              4 * tg.tx * tg.ty) * sizeof(double);
+  if (lds > 65536 || tg.tx * tg.ty > NT * P || (tg.tx + 4) * (tg.ty + 4) > NT * (P + 1))
+    return hipErrorInvalidValue;
+  const int64_t nblk = (int64_t)sh.blocks * B.count;
+  if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_mg2t<NT, P, T, PRE>), dim3((unsigned)nblk), dim3(NT), lds, st, g, sh, tg,
+                     B, lev, a, b, o1, o2);
+  return hipGetLastError();
+}
+
 template <class T, bool PRE>
 hipError_t launch_mg2(const Grid& g, const Batch& B, int lev, Vec<const T> a, Vec<const T> b,
                       Vec<T> o1, Vec<T> o2, hipStream_t st) {
   if (lev < 0 || lev >= kMaxLevels || B.count < 1) return hipErrorInvalidValue;
+  if (g.dim == 3) {  // tiled kernels where the table selects them
+    const int tkey = PRE ? kMgPreTileKey : kMgPostTileKey;
+    const StencilShape ts = stencil_shape(g, tkey, (int)sizeof(T));
+    if (stencil_tuned(g, tkey, (int)sizeof(T)) && cheb2_shape_ok(3, ts.items, ts.threads)) {
+      if (ts.threads == 512)
+        return ts.items == 1 ? launch_mg2t_p<512, 1, T, PRE>(g, B, ts, lev, a, b, o1, o2, st)
+                             : launch_mg2t_p<512, 2, T, PRE>(g, B, ts, lev, a, b, o1, o2, st);
+      return ts.items == 1 ? launch_mg2t_p<256, 1, T, PRE>(g, B, ts, lev, a, b, o1, o2, st)
+                           : launch_mg2t_p<256, 2, T, PRE>(g, B, ts, lev, a, b, o1, o2, st);
+    }
+  }
   const StencilShape sh = stencil_shape(g, PRE ? kMgPreKey : kMgPostKey, (int)sizeof(T));
   if (!cheb2_shape_ok(g.dim, sh.items, sh.threads)) return hipErrorInvalidValue;
   const Cheb2Geom c = cheb2_geom(g, sh);

@@ -338,6 +338,8 @@ int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precisio
     case OK_SHAPE_MG_PRE: nf = kMgPreKey; break;
     case OK_SHAPE_MG_POST: nf = kMgPostKey; break;
     case OK_SHAPE_CHEB2_TILE: nf = kFusedTileKey; break;
+    case OK_SHAPE_MG_PRE_TILE: nf = kMgPreTileKey; break;
+    case OK_SHAPE_MG_POST_TILE: nf = kMgPostTileKey; break;
     default: return OK_E_INVALID;
   }
   const int word = precision == OK_MIXED ? 4 : 8;
@@ -347,7 +349,8 @@ int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precisio
   }
   TileGeom tg;
   const bool ok_shape =
-      (nf == kFusedTileKey) ? cheb2_tile_geom(make_grid(dim, n), threads, items, tg)
+      (nf == kFusedTileKey || nf == kMgPreTileKey || nf == kMgPostTileKey)
+          ? cheb2_tile_geom(make_grid(dim, n), threads, items, tg)
       : (nf >= kFusedKey)   ? cheb2_shape_ok(dim, items, threads)
                             : stencil_shape_ok(dim, nf, items, threads);
   if (!ok_shape || zchunks < 1 || zchunks > n + 1) return OK_E_INVALID;

@@ -131,6 +131,8 @@ constexpr int kMgPreKey = 18, kMgPostKey = 19;
 // Shape-table key of the 3D fused Chebyshev kernel on rectangular in-plane
 // tiles; where it has an entry (items > 0) the fused pairs use it.
 constexpr int kFusedTileKey = 20;
+// Keys of the fused multigrid smoothers on in-plane tiles (3D), used where set.
+constexpr int kMgPreTileKey = 21, kMgPostTileKey = 22;
 // In-plane tile of that kernel: tx x ty nodes, ntx tiles per row of tiles.
 struct TileGeom {
   int tx, ty, ntx, nty;

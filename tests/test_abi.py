@@ -118,8 +118,11 @@ def test_launch_shape_arguments(lib):
     assert f(4, 64, 1, 0, 4, 256, 5) == E      # dim
     assert f(3, 0, 1, 0, 4, 256, 5) == E       # n
     assert f(3, 64, 9, 0, 4, 256, 5) == E      # kernel
-    assert f(3, 64, 7, 0, 2, 256, 5) == E
+    assert f(3, 64, 9, 0, 2, 256, 5) == E
     assert f(3, 64, 6, 0, 2, 512, 5) == 0      # fused pair on in-plane tiles
+    assert f(3, 64, 7, 0, 1, 256, 9) == 0 and f(3, 64, 8, 1, 2, 512, 3) == 0  # smoothers
+    assert f(3, 64, 7, 0, 0, 0, 0) == 0 and f(3, 64, 8, 1, 0, 0, 0) == 0
+    assert f(2, 64, 7, 0, 1, 256, 9) == E and f(3, 64, 8, 0, 3, 256, 9) == E
     assert f(3, 256, 6, 1, 1, 256, 257) == 0
     assert f(3, 64, 6, 0, 0, 0, 0) == 0 and f(3, 256, 6, 1, 0, 0, 0) == 0
     assert f(2, 64, 6, 0, 2, 256, 5) == E      # tiles: 3D only

@@ -134,3 +134,48 @@ def test_mg_smoother_shapes_bitwise(precision):
         for lev_n in (n, n // 2):
             for kern in (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST):
                 ok.set_launch_shape(dim, lev_n, kern, precision, 0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mg_smoother_tile_shapes_bitwise(precision):
+    """The fused multigrid smoothers on in-plane tiles (3D), pinned on the two
+    finest levels of a 64^3 timestep for every thread and node count and
+    several z-splits: results equal the one-iteration kernels bit for bit."""
+    from paper_1603_04570_amd import ok
+    dim, n = 3, 64
+    p = ok.default_params(dim=dim, n=n, eps=0.02, sigma=100.0, m=0.1, dt=2e-4,
+                          precision=precision)
+    u0, w0 = noise_state(dim, n, 0.1, 37)
+
+    def once():
+        P = ok.Problem(p)
+        u = torch.from_numpy(u0).cuda()
+        w = torch.from_numpy(w0).cuda()
+        st = P.timestep(u, w, 1)
+        return u.cpu().numpy(), w.cpu().numpy(), st.its()
+
+    ok.set_option(ok.OK_OPT_FUSE_MG, 0)
+    try:
+        ref = once()
+    finally:
+        ok.set_option(ok.OK_OPT_FUSE_MG, 1)
+    kinds = (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST, ok.OK_SHAPE_MG_PRE_TILE,
+             ok.OK_SHAPE_MG_POST_TILE)
+    try:
+        for items, threads, zch in [(1, 256, 1), (2, 256, 5), (1, 512, 65), (2, 512, 3)]:
+            print("mg tile shape", precision, items, threads, zch, flush=True)
+            for lev_n in (n, n // 2):
+                # a row-run entry switches the fused smoothers on; the tile entry selects tiles
+                for kern in (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST):
+                    ok.set_launch_shape(dim, lev_n, kern, precision, 1, 256, 1)
+                for kern in (ok.OK_SHAPE_MG_PRE_TILE, ok.OK_SHAPE_MG_POST_TILE):
+                    ok.set_launch_shape(dim, lev_n, kern, precision, items, threads,
+                                        min(zch, lev_n + 1))
+            got = once()
+            assert got[2] == ref[2]
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), \
+                (items, threads, zch)
+    finally:
+        for lev_n in (n, n // 2):
+            for kern in kinds:
+                ok.set_launch_shape(dim, lev_n, kern, precision, 0)
