@@ -118,3 +118,45 @@ def test_batch_without_graphs_equals_with():
         res.append([(B.get_state(i)[0].cpu().numpy(), st[i].its()) for i in range(len(specs))])
     for a, b in zip(*res):
         assert a[1] == b[1] and np.array_equal(a[0], b[0])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_tiled_kernels_equal_solo(precision):
+    """3D instances of one class (different parameters, so they stop at
+    different FGMRES iterations) with the tiled fused Chebyshev pair and the
+    tiled fused smoothers pinned on the two finest levels: every instance
+    equals its solo run with the built-in kernels, bit for bit."""
+    from paper_1603_04570_amd import ok
+    specs = [dict(dim=3, n=32, eps=e, sigma=s, m=m, theta=1.0, dt=d, seed=70 + i)
+             for i, (e, s, m, d) in enumerate([(0.02, 100.0, 0.1, 2e-4), (0.03, 30.0, -0.2, 4e-4),
+                                                (0.025, 300.0, 0.0, 3e-4)])]
+    plist = [params_for(s, precision) for s in specs]
+    ref = []
+    for p, s in zip(plist, specs):  # solo, no pinned shapes
+        u0, w0 = noise_state(3, 32, s["m"], s["seed"])
+        u, w = torch.from_numpy(u0).cuda(), torch.from_numpy(w0).cuda()
+        st = ok.Problem(p).timestep(u, w, 2)
+        ref.append((u.cpu().numpy(), w.cpu().numpy(), st.its()))
+    pins = [(ok.OK_SHAPE_CHEB2_TILE, 32, 2, 256, 5)]
+    for lev_n in (32, 16):
+        pins += [(ok.OK_SHAPE_MG_PRE, lev_n, 1, 256, 1), (ok.OK_SHAPE_MG_POST, lev_n, 1, 256, 1),
+                 (ok.OK_SHAPE_MG_PRE_TILE, lev_n, 1, 512, 3),
+                 (ok.OK_SHAPE_MG_POST_TILE, lev_n, 2, 256, 4)]
+    try:
+        for kern, lev_n, items, threads, zch in pins:
+            ok.set_launch_shape(3, lev_n, kern, precision, items, threads, zch)
+        print("batch tiled", precision, flush=True)
+        B = ok.Batch(plist)
+        for i, s in enumerate(specs):
+            u0, w0 = noise_state(3, 32, s["m"], s["seed"])
+            B.set_state(i, torch.from_numpy(u0).cuda(), torch.from_numpy(w0).cuda())
+        bst = B.timestep(2)
+        for i in range(len(specs)):
+            ub, wb = B.get_state(i)
+            assert bst[i].its() == ref[i][2], i
+            assert np.array_equal(ub.cpu().numpy(), ref[i][0]), i
+            assert np.array_equal(wb.cpu().numpy(), ref[i][1]), i
+        assert len({tuple(r[2]) for r in ref}) > 1  # the instances stopped at different iterations
+    finally:
+        for kern, lev_n, _, _, _ in pins:
+            ok.set_launch_shape(3, lev_n, kern, precision, 0)
