@@ -520,6 +520,28 @@ def main():
         "roofline_vcycle": roof_mg,
         "autotuned_shapes": tuned,
     }
+    if prec == "mixed":
+        # after the timed region: the FP64 path from the same initial state,
+        # stepped beside the mixed one, and the error of each field per step
+        pf = ok.default_params(dim=cfg["dim"], n=cfg["n"], eps=cfg["eps"], sigma=cfg["sigma"],
+                               m=cfg["m"], dt=cfg["dt"], theta=cfg["theta"],
+                               precision=ok.OK_FP64)
+        Pf = ok.Problem(pf, device=dev)
+        um, wm, uf, wf = u0d.clone(), w0d.clone(), u0d.clone(), w0d.clone()
+        per_step = []
+        for k in range(args.steps):
+            P.timestep(um, wm, 1)
+            Pf.timestep(uf, wf, 1)
+            per_step.append({"step": k + 1,
+                             "u": float(torch.linalg.vector_norm(um - uf) /
+                                        torch.linalg.vector_norm(uf)),
+                             "w": float(torch.linalg.vector_norm(wm - wf) /
+                                        torch.linalg.vector_norm(wf))})
+        out["mixed_vs_fp64"] = {
+            "error": "relative 2-norm of each field after each step, against the FP64 path "
+                     "from the same initial state (both Newton-converged to the same tolerance)",
+            "per_step": per_step}
+        del Pf
     if not args.no_cpu_baseline:
         per_step = stats.fgmres_its_total / max(stats.steps_done, 1)
         out["cpu_baseline"] = cpu_baseline(cfg, int(round(per_step)))
