@@ -208,6 +208,22 @@ def bench_sweep(args, torch, ok):
         solo += time.perf_counter() - a
         solo_its.append(ss.its())
         assert ss.its() == st[i].its(), (i, ss.its(), st[i].its())
+    fp64 = None
+    if prec == ok.OK_MIXED:  # the same batch on the plain FP64 path
+        B64 = ok.Batch([_params(ok, s, ok.OK_FP64) for s in specs])
+        if not args.no_autotune:
+            B64.autotune()
+        for i, (u, w) in enumerate(init):
+            B64.set_state(i, u, w)
+        B64.timestep(1)
+        for i, (u, w) in enumerate(init):
+            B64.set_state(i, u, w)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        B64.timestep(args.steps)
+        torch.cuda.synchronize()
+        fp64 = time.perf_counter() - a
+        B64.close()
     sizes = sorted({s["n"] for s in specs})
     out = _base_line(total * args.steps / elapsed, args.steps, args.warmup,
                      elapsed * 1e3 / args.steps, "f64" if prec == ok.OK_FP64 else "f64+f32",
@@ -219,6 +235,7 @@ def bench_sweep(args, torch, ok):
                       "global_batch": 64, "parallelism": "none (1 GPU)"})
     out.update({"classes": B.classes(), "solo_sum_s": solo, "batched_s": elapsed,
                 "vs_solo_sum": solo / elapsed, "autotuned_shapes": tuned,
+                "fp64_batched_s": fp64, "vs_fp64_batched": (fp64 / elapsed) if fp64 else None,
                 "fgmres_its_total": sum(sum(x.its()) for x in st), "roofline": None})
     return out
 
