@@ -23,7 +23,7 @@ def cheb_mass(P, r, nodes):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("dim,n", [(2, 256), (3, 64), (3, 128), (3, 256)])
+@pytest.mark.parametrize("dim,n", [(2, 256), (3, 64), (3, 100), (3, 128), (3, 256)])
 def test_fused_chebyshev_shapes_bitwise(dim, n, precision):
     from paper_1603_04570_amd import ok
     p = ok.default_params(dim=dim, n=n, precision=precision)
