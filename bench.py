@@ -14,13 +14,13 @@ Other workloads:
                     {128,256,512,1024}, eps~U[0.01,0.05], sigma~logU[10,1000],
                     m~U[-0.4,0.4], dt=eps^2/2 (seeds 4000+i), mixed precision,
                     one batched timestep against the sum of the 64 solo runs.
-  --config robustness  the paper's robustness experiments (Sec. 5) on Q1:
+  --config robustness  the paper's robustness experiments (Sec. 4) on Q1:
                     Table 2 analogue (2D, eps in {0.02,0.01,0.005}, N = 2/eps,
                     dt = eps^2) and Table 1 analogue (3D N in {16..128}, eps =
                     0.02, dt = 4e-4), m = 0.4, sigma = 100, theta = 1/2, cosine
                     initial condition; average FGMRES iterations per Newton step
                     for the default solver and the paper's preset.
-  --config paper    the paper's experiment (Sec. 5) on Q1: 3D N = --paper-n
+  --config paper    the paper's experiment (Sec. 4) on Q1: 3D N = --paper-n
                     (25*2^k; 100 by default, 400 = 129M DOFs), m = 0.4,
                     eps = 0.02, sigma = 100, theta = 1/2, dt = eps^2, cosine
                     initial condition, w0 from (okb), paper solver preset
@@ -267,7 +267,7 @@ def bench_paper(args, torch, ok):
     its = st.its()
     out = _base_line(nd * args.steps / el, args.steps, args.warmup, el * 1e3 / args.steps,
                      "f64" if args.precision != "mixed" else "f64+f32",
-                     {"workload": f"paper: Sec. 5 experiment on Q1, 3D N={n} ({nd} DOFs), m=0.4, "
+                     {"workload": f"paper: Sec. 4 experiment on Q1, 3D N={n} ({nd} DOFs), m=0.4, "
                                   "eps=0.02, sigma=100, theta=1/2, dt=eps^2, cosine u0, w0 from "
                                   "(okb), 2 Richardson iterations of S~^-1, 5 V-cycles",
                       "dofs": nd, "global_batch": 1, "parallelism": "none (1 GPU)"})
@@ -319,7 +319,7 @@ def bench_robustness(args, torch, ok):
             "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": tot_s * 1e3 / len(rows) / steps,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic",
-            "config": {"workload": "robustness: paper's Sec. 5 workload on Q1 (m=0.4, sigma=100, "
+            "config": {"workload": "robustness: paper's Sec. 4 workload on Q1 (m=0.4, sigma=100, "
                                    "theta=1/2, cosine IC, w0=0); Table 2 analogue 2D eps sweep "
                                    "N=2/eps dt=eps^2; Table 1 analogue 3D N=16..128 eps=0.02 "
                                    "dt=4e-4", "parallelism": "none (1 GPU)"},

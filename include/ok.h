@@ -207,8 +207,8 @@ int ok_profile_read(ok_ctx *ctx, int32_t kernel_class, int64_t *launches, double
  * number of table entries set.  Synchronises; run it outside timed regions. */
 int ok_autotune(ok_ctx *ctx, void *stream, int32_t *entries);
 
-/* Initial chemical potential from (okb) in weak form (Sec. 5: "the initial
- * condition for w was computed from u0"): solves M w = eps^2 K u + N(u) by
+/* Initial chemical potential w0 from (okb) in weak form, as the paper's
+ * experiments derive it from u0 (Sec. 4): solves M w = eps^2 K u + N(u) by
  * restarted Chebyshev iterations on M in FP64 until the residual is below
  * 1e-15 of the right-hand side.  d_u, d_w: n entries; synchronises. */
 int ok_initial_w(ok_ctx *ctx, const double *d_u, double *d_w, void *stream);

@@ -675,7 +675,7 @@ static void cg_solve(const csr_t *A, const double *b, double *x, double tol, int
 }
 
 /* w from u by (okb) in weak form: M w = eps^2 K u + N(u) (the initial
- * chemical potential of the paper's experiment, Sec. 5). */
+ * chemical potential of the paper's experiment, Sec. 4). */
 int okref_initial_w(okref *h, const double *u, double *w) {
   int64_t n = h->lev[0].nodes;
   double *rhs = (double *)malloc(sizeof(double) * n);

@@ -72,7 +72,7 @@ def noise_state(dim: int, n: int, m: float, seed: int, amp: float = 0.05,
 
 
 def cosine_state(dim: int, n: int, m: float, amp: float = 1.0 / 50.0):
-    """(u0, w0) of the paper's experiment (Sec. 5): u0 = m + amp * prod_d
+    """(u0, w0) of the paper's experiment (Sec. 4): u0 = m + amp * prod_d
     cos(2 pi x_d) at the nodes, w0 = 0.  The perturbation is a DCT-I mode of
     index 2 per direction, orthogonal to the constant in the trapezoid (and
     the Q1 mass) inner product, so its discrete integral is zero."""
@@ -85,7 +85,7 @@ def cosine_state(dim: int, n: int, m: float, amp: float = 1.0 / 50.0):
     return u0, np.zeros_like(u0)
 
 
-# Robustness experiments (Sec. 5, Tables 1-2): parameters of the paper's run
+# Robustness experiments (Sec. 4, Tables 1-2): parameters of the paper's run
 # with theta = 1/2 and dt = eps^2.
 def table2_cases():
     """eps sweep with h = eps/2 (N = 2/eps) and dt = eps^2, 2D."""

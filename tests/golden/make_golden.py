@@ -3,11 +3,14 @@
 Calls only the FP64 CPU oracle (oracle/) on the seeded synthetic inputs of a
 named workload and stores, after every timestep, the values of u and w at a
 fixed seeded sample of nodes, their global norms and sums, the Newton and
-FGMRES iteration counts and the residual history.  Output: an .npz (no
-pickles) plus a small JSON summary beside this script.
+FGMRES iteration counts and the residual history, and the 2-norm of each
+field over every grid plane normal to each axis (N+1 values per axis, field
+and step), so that an error confined to a few nodes anywhere in the grid
+shows up in three of them.  Output: an .npz (no pickles) plus a small JSON
+summary beside this script.
 
     python tests/golden/make_golden.py 3d128 5     # 3D 128^3, 5 timesteps
-    python tests/golden/make_golden.py 3d256 1     # 3D 256^3, 1 timestep
+    python tests/golden/make_golden.py 3d256 5     # 3D 256^3, 5 timesteps
 """
 import json
 import os
@@ -26,6 +29,17 @@ from paper_1603_04570_amd.inputs import CONFIGS, noise_state, sample_nodes  # no
 NSAMPLE = 2048
 
 
+def plane_norms(v, dim, n):
+    """[axis][plane]: 2-norm of v over each grid plane normal to each axis
+    (axis 0 = x, the fastest index)."""
+    g = v.reshape((n + 1,) * dim)  # indices [z][y][x] in 3D, [y][x] in 2D
+    out = []
+    for ax in range(dim):
+        other = tuple(a for a in range(dim) if a != dim - 1 - ax)
+        out.append(np.sqrt(np.sum(g * g, axis=other)))
+    return np.array(out)
+
+
 def main(name, steps):
     cfg = CONFIGS[name]
     dim, n = cfg["dim"], cfg["n"]
@@ -34,7 +48,8 @@ def main(name, steps):
     print(f"assembled in {time.time() - t0:.1f} s", flush=True)
     u, w = noise_state(dim, n, cfg["m"], cfg["seed"])
     idx = sample_nodes(o.nodes, NSAMPLE, seed=77)
-    rec = {"u": [], "w": [], "unorm": [], "wnorm": [], "usum": [], "wsum": []}
+    rec = {"u": [], "w": [], "unorm": [], "wnorm": [], "usum": [], "wsum": [], "uplanes": [],
+           "wplanes": []}
     meta = {"workload": name, "config": cfg, "steps": steps, "newton_its": [], "fgmres_its": [],
             "fnorms": [], "seconds": []}
     for s in range(steps):
@@ -52,6 +67,8 @@ def main(name, steps):
         rec["wnorm"].append(np.linalg.norm(w))
         rec["usum"].append(u.sum())
         rec["wsum"].append(w.sum())
+        rec["uplanes"].append(plane_norms(u, dim, n))
+        rec["wplanes"].append(plane_norms(w, dim, n))
         print(f"step {s}: newton {info.newton_its} fgmres {info.its()} "
               f"{meta['seconds'][-1]:.1f} s", flush=True)
     np.savez(os.path.join(HERE, f"oracle_{name}.npz"), idx=idx,

@@ -1,4 +1,4 @@
-"""The paper's own workload on Q1 (Sec. 5): theta = 1/2, m = 0.4, eps = 0.02,
+"""The paper's own workload on Q1 (Sec. 4): theta = 1/2, m = 0.4, eps = 0.02,
 sigma = 100, dt = eps^2, cosine initial condition, w0 from (okb), and the
 paper's solver preset (two Richardson iterations of S~^-1, five V-cycles per
 S^^-1), on meshes N = 25 * 2^k whose multigrid coarsens to 25 elements per

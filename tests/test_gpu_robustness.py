@@ -1,4 +1,4 @@
-"""Robustness of the preconditioner (Sec. 5, Tables 1-2 analogues): average
+"""Robustness of the preconditioner (Sec. 4, Tables 1-2 analogues): average
 FGMRES iterations per Newton step under mesh refinement at fixed parameters
 and under eps -> 0 with h = eps/2 and dt = eps^2, for the default solver and
 the paper's preset (two Richardson iterations of S~^-1, five V-cycles per

@@ -293,6 +293,31 @@ def test_fgmres_matches_dense_lu(dim, n):
     assert rel(o.jacobian_apply(u, x), J @ x) < 1e-14
 
 
+@pytest.mark.parametrize("dim,n,restart", [(2, 16, 5), (3, 8, 5), (2, 16, 3)])
+def test_fgmres_restarted_matches_dense_lu(dim, n, restart):
+    """The restart branch of FGMRES (new cycle from the true residual b - J x
+    of the current iterate, normalised) is pinned by a short restart length:
+    FGMRES(restart) at rtol 1e-13 has to restart many times and still reach
+    the dense-LU solution of J x = b, with a true residual at the tolerance.
+    A wrong sign or a stale iterate in that branch would stall or converge
+    to something else."""
+    o = Oracle(dim, n, **CFG1, gmres_restart=restart, gmres_rtol=1e-13,
+               gmres_max_restarts=400)
+    u, _ = noise_state(dim, n, 0.0, 3)
+    M, K, ME, A, B, Cm, D, c = _blocks(o, u)
+    J = np.block([[A, B], [Cm, D]])
+    b = uniform01(8, 2 * o.nodes) - 0.5
+    x, its, st = o.fgmres(u, b)
+    assert st == 0
+    assert its > 2 * restart, its  # several cycles, so several restarts
+    assert rel(x, np.linalg.solve(J, b)) < 1e-11
+    assert np.linalg.norm(b - J @ x) <= 2e-13 * np.linalg.norm(b)
+    # the unrestarted solve of the same system takes fewer iterations
+    o30 = Oracle(dim, n, **CFG1, gmres_rtol=1e-13, gmres_max_restarts=20)
+    _, its30, st30 = o30.fgmres(u, b)
+    assert st30 == 0 and its30 <= its
+
+
 # ----------------------------------------------------------------------------
 # P11: one timestep of a single DCT mode (linearised analytic decay factor)
 # ----------------------------------------------------------------------------
