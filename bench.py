@@ -5,9 +5,15 @@ A step is one timestep of the whole hot path (Newton residual, FGMRES with the
 matching-Schur block preconditioner, Jacobian applies, updates) over the
 configured synthetic field.  Prints ONE JSON line.
 
-Default workload: 3D unit cube, Q1 hex on a uniform 128^3 mesh (2,146,689
-nodes, 4,293,378 DOFs), eps=0.01, sigma=1000, m=0.1, theta=1, dt=2e-5,
-u0 = m + 0.05*U(-1,1) seeded (seed 2), w0 = 0, FP64 throughout.
+Default workload (the headline): 3D unit cube, Q1 hex on a uniform 256^3
+mesh (16,974,593 nodes, 33,949,186 DOFs), eps=0.01, sigma=1000, m=0.1,
+theta=1, dt=2e-5, u0 = m + 0.05*U(-1,1) seeded (seed 2), w0 = 0.  `value` is
+the FP64 path's throughput; the mixed-precision form (FP32 preconditioner,
+FP64 FGMRES, residual, Jacobian and M_E(u)) is timed beside it on the same
+input, with its error against the FP64 path after every step.  Both are
+timed with no profiling events in the timed region; kernel-class rooflines
+come from a profiled rerun of the same timesteps.  --config 3d128 (4.29M
+DOFs) and 2d64 are the smaller cases of the same recipe.
 
 Other workloads:
   --config sweep64  64 independent 2D instances, N uniform over
@@ -46,16 +52,23 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-# kernel classes timed live in the single-problem benchmark (ok.h)
+TARGET_FRAC = 0.60     # roofline fraction asked of the stencil and V-cycle kernels
+# kernel classes timed in the profiled region of the single-problem benchmark (ok.h)
 K_CHEB_MASS, K_MG_SMOOTH, K_KRYLOV = 1, 2, 5
 KERNELS = {
-    K_KRYLOV: ("mgs", "fused modified Gram-Schmidt step + dot products of FGMRES (k_mgs, k_dot)",
+    K_KRYLOV: ("krylov", "Gram-Schmidt chain of one Arnoldi step of FGMRES; algorithmic bytes: "
+                         "3 two-field vectors per projection (w and v_i read, w written), "
+                         "i = 0..j",
                ("paper_1603_04570_amd/csrc/k_krylov.hip", "paper_1603_04570_amd/csrc/ok_internal.h")),
-    K_CHEB_MASS: ("cheb_step", "Chebyshev-Jacobi iterations on M (k_cheb2 or k_cheb2t pairs, k_stencil EpiChebStep)",
+    K_CHEB_MASS: ("cheb_pair", "Chebyshev-Jacobi iterations on M, two per launch (k_cheb2t/k_cheb2); "
+                               "algorithmic bytes: x, r, d read and written once per launch "
+                               "(6 words/node)",
                   ("paper_1603_04570_amd/csrc/k_stencil_impl.h",
                    "paper_1603_04570_amd/csrc/ok_internal.h")),
-    K_MG_SMOOTH: ("mg_smooth", "finest-level V-cycle smoother and residual passes (k_mg2t/k_mg2 "
-                  "fused pre/post pairs, or the k_stencil one-iteration kernels)",
+    K_MG_SMOOTH: ("vcycle_smoother", "finest-level V-cycle smoothing passes (fused pre-smoothing + "
+                                     "residual and fused post-smoothing, k_mg2t/k_mg2, or the "
+                                     "one-iteration kernels); algorithmic bytes: 3 words/node "
+                                     "per fused pass",
                   ("paper_1603_04570_amd/csrc/k_stencil_impl.h",
                    "paper_1603_04570_amd/csrc/ok_internal.h")),
 }
@@ -109,26 +122,36 @@ def cpu_model():
     return platform.processor()
 
 
-def cpu_baseline(cfg, its_per_step, sample_its=4):
-    """The FP64 CSR oracle on one host core: `sample_its` FGMRES iterations of
-    the first Newton solve of timestep 1 (setup excluded, as on the GPU),
-    scaled to a whole timestep by the FGMRES iterations per timestep."""
+def cpu_baseline(cfg, its_per_step, newton_per_step):
+    """The FP64 CSR oracle on one host core, on a bounded sample of the same
+    workload: one residual evaluation and `sample_its` FGMRES iterations of
+    the first Newton solve of timestep 1 (assembly excluded, as setup is on
+    the GPU), each timed, then scaled to one timestep of the GPU run:
+    (Newton iterations + 1) residuals and its FGMRES iterations."""
     from oracle.okref import Oracle
     from paper_1603_04570_amd.inputs import dofs, noise_state
     dim, n = cfg["dim"], cfg["n"]
+    sample_its = 1 if dofs(dim, n) > 10_000_000 else 4
+    t_setup = time.perf_counter()
     o = Oracle(dim, n, cfg["eps"], cfg["sigma"], cfg["m"], cfg["dt"], cfg["theta"],
                gmres_restart=sample_its, gmres_max_restarts=0)
+    t_setup = time.perf_counter() - t_setup
     u, w = noise_state(dim, n, cfg["m"], cfg["seed"])
     t0 = time.perf_counter()
     F, _ = o.residual(u, w, u)
+    t_res = time.perf_counter() - t0
+    t0 = time.perf_counter()
     x, its, st = o.fgmres(u, -F)
-    dt_s = time.perf_counter() - t0
-    per_it = dt_s / max(its, 1)
-    step_s = per_it * its_per_step
+    t_fg = time.perf_counter() - t0
+    per_it = t_fg / max(its, 1)
+    step_s = (newton_per_step + 1.0) * t_res + its_per_step * per_it
     return {"value": dofs(dim, n) / step_s, "unit": "DOFs/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle (serial FP64 CSR) on {dim}D {n}^{dim}: residual + {its} FGMRES "
-                       f"iterations of the first Newton solve ({dt_s:.1f} s), scaled to the "
-                       f"{its_per_step} FGMRES iterations of one timestep; host {cpu_model()}, "
+            "sample": (f"oracle (serial FP64, assembled CSR) on {dim}D {n}^{dim}, the same "
+                       f"workload and seed: one residual ({t_res:.2f} s) and {its} FGMRES "
+                       f"iteration(s) of the first Newton solve ({t_fg:.1f} s), scaled to "
+                       f"{newton_per_step + 1:.2f} residuals and {its_per_step:.2f} FGMRES "
+                       f"iterations per timestep (the GPU run's averages); assembly "
+                       f"{t_setup:.1f} s excluded; one thread on host {cpu_model()}, "
                        f"nproc {os.cpu_count()}")}
 
 
@@ -403,13 +426,166 @@ def bench_serve(args, torch, ok):
     return out
 
 
+def _single_params(ok, cfg, precision):
+    return ok.default_params(dim=cfg["dim"], n=cfg["n"], eps=cfg["eps"], sigma=cfg["sigma"],
+                             m=cfg["m"], dt=cfg["dt"], theta=cfg["theta"], precision=precision)
+
+
+def _timed_run(args, torch, ok, cfg, prec, u0d, w0d):
+    """One problem of the configuration in precision `prec`: autotuned,
+    --warmup untimed timesteps from the initial state, then --steps timesteps
+    from the same initial state timed between two device synchronisations
+    (no profiling events in the timed region)."""
+    P = ok.Problem(_single_params(ok, cfg, prec), device=u0d.device)
+    tuned = 0 if args.no_autotune else P.autotune()
+    if args.graphs:
+        P.use_graphs(True)
+    u, w = u0d.clone(), w0d.clone()
+    for _ in range(args.warmup):
+        P.timestep(u, w, 1)
+    u.copy_(u0d)
+    w.copy_(w0d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = P.timestep(u, w, args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    return P, stats, elapsed, tuned
+
+
+def _latency(torch, P, u0d, w0d, steps):
+    """Per-timestep wall times (HIP events around each step) over `steps`
+    consecutive timesteps from the initial state."""
+    u, w = u0d.clone(), w0d.clone()
+    ms = []
+    while len(ms) < steps:
+        k = min(steps - len(ms), 256)
+        st = P.timestep(u, w, k)
+        ms += st.ms()
+    torch.cuda.synchronize()
+    a = np.array(ms)
+    return {"samples": len(ms), "p50": float(np.percentile(a, 50)),
+            "p99": float(np.percentile(a, 99)), "max": float(a.max()), "mean": float(a.mean())}
+
+
+def _profiled(torch, ok, P, u0d, w0d, steps, config, fp64):
+    """Kernel-class timing in a profiled region: the same timesteps from the
+    same initial state as the timed region, run again with HIP-event
+    brackets on the launch stream around every launch chain of the three
+    kernel classes."""
+    P.profile_enable(ok.OK_K_KRYLOV, ok.OK_K_CHEB_MASS, ok.OK_K_MG_SMOOTH)
+    u, w = u0d.clone(), w0d.clone()
+    torch.cuda.synchronize()
+    P.timestep(u, w, steps)
+    torch.cuda.synchronize()
+    out = {}
+    for cls in (K_KRYLOV, K_CHEB_MASS, K_MG_SMOOTH):
+        r, _ = roofline_of(P, cls, config, fp64)
+        if r:
+            r["window"] = f"profiled region: the {steps} timed timesteps rerun with event brackets"
+            if cls in (K_CHEB_MASS, K_MG_SMOOTH):
+                r["target_frac"] = TARGET_FRAC
+                r["meets_target"] = r["frac"] >= TARGET_FRAC
+        out[KERNELS[cls][0]] = r
+    P.profile_enable()
+    return out
+
+
+def bench_single(args, torch, ok, cfg):
+    """One problem of a named configuration: FP64 timed (the value), the
+    mixed-precision form timed beside it, per-step latency, the mixed path's
+    error against the FP64 path per step, kernel-class rooflines and the
+    oracle's CPU baseline."""
+    from paper_1603_04570_amd.inputs import dofs, noise_state
+    dev = torch.device("cuda:0")
+    u0, w0 = noise_state(cfg["dim"], cfg["n"], cfg["m"], cfg["seed"])
+    u0d, w0d = torch.from_numpy(u0).to(dev), torch.from_numpy(w0).to(dev)
+    nd = dofs(cfg["dim"], cfg["n"])
+    precs = ["fp64", "mixed"] if args.precision in (None, "both") else [args.precision]
+    runs = {}
+    for prec in precs:
+        pcode = ok.OK_FP64 if prec == "fp64" else ok.OK_MIXED
+        P, st, el, tuned = _timed_run(args, torch, ok, cfg, pcode, u0d, w0d)
+        lat = _latency(torch, P, u0d, w0d, args.latency_steps) if args.latency_steps > 0 else None
+        prof = None if args.no_profile else _profiled(torch, ok, P, u0d, w0d, args.steps,
+                                                      args.config, prec == "fp64")
+        runs[prec] = dict(P=P, stats=st, elapsed=el, tuned=tuned, latency=lat, prof=prof)
+        print(f"{args.config} {prec}: {nd * args.steps / el / 1e6:.1f}M DOFs/s, "
+              f"{el * 1e3 / args.steps:.2f} ms/step", file=sys.stderr, flush=True)
+    head = runs[precs[0]]
+    st, el = head["stats"], head["elapsed"]
+    roofline, kernels = None, None
+    if head["prof"]:
+        kernels = head["prof"]
+        timed = [r for r in kernels.values() if r]
+        if timed:  # the dominant kernel class by summed time
+            roofline = max(timed, key=lambda r: r["total_ms"])
+    out = _base_line(nd * args.steps / el, args.steps, args.warmup, el * 1e3 / args.steps,
+                     "f64" if precs[0] == "fp64" else "f64+f32",
+                     {"workload": f"{args.config}: {cfg['dim']}D Q1 {cfg['n']}^{cfg['dim']} "
+                                  f"eps={cfg['eps']} sigma={cfg['sigma']} m={cfg['m']} "
+                                  f"dt={cfg['dt']} theta={cfg['theta']} seed={cfg['seed']} "
+                                  f"precision={precs[0]}",
+                      "dofs": nd, "nodes": nd // 2, "global_batch": 1,
+                      "parallelism": "none (1 GPU)"})
+    step_ms = np.array(st.ms())
+    out.update({
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
+                       "p99": float(np.percentile(step_ms, 99)), "samples": len(step_ms),
+                       "long_run": head["latency"]},
+        "newton_its": st.per_step(), "fgmres_its": st.its(),
+        "roofline": roofline, "roofline_kernels": kernels,
+        "autotuned_shapes": head["tuned"]})
+    if "mixed" in runs and precs[0] != "mixed":
+        mx = runs["mixed"]
+        ms_step = np.array(mx["stats"].ms())
+        out["mixed"] = {
+            "value": nd * args.steps / mx["elapsed"], "unit": "DOFs/s", "dtype": "f64+f32",
+            "ms_per_step": mx["elapsed"] * 1e3 / args.steps,
+            "vs_fp64": el / mx["elapsed"],
+            "latency_ms": {"p50": float(np.percentile(ms_step, 50)),
+                           "p99": float(np.percentile(ms_step, 99)), "samples": len(ms_step),
+                           "long_run": mx["latency"]},
+            "newton_its": mx["stats"].per_step(), "fgmres_its": mx["stats"].its(),
+            "roofline_kernels": mx["prof"]}
+        # the mixed and the FP64 path stepped side by side from the same
+        # initial state: relative error of each field after each step
+        Pm, Pf = mx["P"], head["P"]
+        um, wm, uf, wf = u0d.clone(), w0d.clone(), u0d.clone(), w0d.clone()
+        per_step = []
+        for k in range(args.steps):
+            Pm.timestep(um, wm, 1)
+            Pf.timestep(uf, wf, 1)
+            per_step.append({"step": k + 1,
+                             "u": float(torch.linalg.vector_norm(um - uf) /
+                                        torch.linalg.vector_norm(uf)),
+                             "w": float(torch.linalg.vector_norm(wm - wf) /
+                                        torch.linalg.vector_norm(wf))})
+        out["mixed"]["error_vs_fp64"] = {
+            "error": "relative 2-norm of each field after each step, against the FP64 path "
+                     "from the same initial state (both Newton-converged to the same tolerance)",
+            "per_step": per_step,
+            "max_u": max(p["u"] for p in per_step), "max_w": max(p["w"] for p in per_step)}
+    for r in runs.values():
+        del r["P"]
+    if not args.no_cpu_baseline:
+        per = st.fgmres_its_total / max(st.steps_done, 1)
+        out["cpu_baseline"] = cpu_baseline(cfg, per, st.newton_its / max(st.steps_done, 1))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="3d128")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
+    ap.add_argument("--config", default="3d256",
+                    help="3d256 (default), 3d128, 2d64, sweep64, serve, robustness, paper")
+    ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default=None,
+                    help="single-problem configs: both (default; value = FP64), fp64 or mixed; "
+                         "sweep64/serve: mixed by default")
+    ap.add_argument("--latency-steps", type=int, default=100,
+                    help="single-problem configs: timesteps of the p50/p99 latency run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -419,6 +595,10 @@ def main():
                     help="run every Chebyshev iteration (on M and in the smoothers) in a pass of its own")
     ap.add_argument("--issue-ahead", action="store_true",
                     help="issue each FGMRES iteration before the previous one's stop test is read")
+    ap.add_argument("--gram-schmidt", choices=["icwy", "mgs"], default="icwy",
+                    help="Arnoldi orthogonalisation: icwy (default; two passes, modified "
+                         "Gram-Schmidt in inverse compact WY form) or mgs (one pass per "
+                         "projection)")
     ap.add_argument("--trace-ranges", action="store_true",
                     help="ROCTX ranges per timestep, Newton and FGMRES iteration "
                          "(for rocprofv3 --marker-trace)")
@@ -439,7 +619,7 @@ def main():
         calibrate_copy(torch)
         return
     from paper_1603_04570_amd import ok
-    from paper_1603_04570_amd.inputs import CONFIGS, dofs, noise_state
+    from paper_1603_04570_amd.inputs import CONFIGS
 
     if args.no_fuse:
         ok.set_option(ok.OK_OPT_FUSE_CHEB, 0)
@@ -448,6 +628,8 @@ def main():
         ok.set_option(ok.OK_OPT_ISSUE_AHEAD, 1)
     if args.trace_ranges:
         ok.set_option(ok.OK_OPT_TRACE_RANGES, 1)
+    if args.gram_schmidt == "mgs":
+        ok.set_option(ok.OK_OPT_GRAM_SCHMIDT, 1)
     if args.config == "sweep64":
         print(json.dumps(bench_sweep(args, torch, ok)), flush=True)
         return
@@ -461,108 +643,7 @@ def main():
         print(json.dumps(bench_serve(args, torch, ok)), flush=True)
         return
     cfg = dict(CONFIGS[args.config])
-    prec = args.precision or cfg["precision"]
-    p = ok.default_params(dim=cfg["dim"], n=cfg["n"], eps=cfg["eps"], sigma=cfg["sigma"],
-                          m=cfg["m"], dt=cfg["dt"], theta=cfg["theta"],
-                          precision=ok.OK_MIXED if prec == "mixed" else ok.OK_FP64)
-    dev = torch.device("cuda:0")
-    P = ok.Problem(p, device=dev)
-    u0, w0 = noise_state(cfg["dim"], cfg["n"], cfg["m"], cfg["seed"])
-    u0d = torch.from_numpy(u0).to(dev)
-    w0d = torch.from_numpy(w0).to(dev)
-    u, w = u0d.clone(), w0d.clone()
-    tuned = 0 if args.no_autotune else P.autotune()
-    if args.graphs:
-        P.use_graphs(True)
-    for _ in range(args.warmup):
-        P.timestep(u, w, 1)
-    u.copy_(u0d)
-    w.copy_(w0d)
-    if not args.no_profile:
-        P.profile_enable(ok.OK_K_CHEB_MASS, ok.OK_K_KRYLOV)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = P.timestep(u, w, args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-
-    nd = dofs(cfg["dim"], cfg["n"])
-    value = nd * args.steps / elapsed
-    step_ms = np.array(stats.ms())
-    its = stats.its()
-    roofline, roof_stencil, roof_mg = None, None, None
-    if not args.no_profile:
-        # the dominant kernel (by summed time in the timed region) and the
-        # stencil kernel of the preconditioner
-        rk, tk = roofline_of(P, K_KRYLOV, args.config, prec == "fp64")
-        rc, tc = roofline_of(P, K_CHEB_MASS, args.config, prec == "fp64")
-        roofline, roof_stencil = (rk, rc) if tk >= tc else (rc, rk)
-        # the finest-level V-cycle passes, timed in one extra timestep after
-        # the timed region: an event pair around each of those launches inside
-        # the timed steps would hold back the launches that follow them
-        P.profile_enable(ok.OK_K_MG_SMOOTH)
-        uu, ww = u.clone(), w.clone()
-        P.timestep(uu, ww, 1)
-        torch.cuda.synchronize()
-        roof_mg, _ = roofline_of(P, K_MG_SMOOTH, args.config, False)
-        if roof_mg:
-            roof_mg["window"] = "one extra timestep after the timed region"
-        P.profile_enable()
-    out = {
-        "metric": "timestep DOFs/s",
-        "value": value,
-        "unit": "DOFs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == "fp64" else "f64+f32",
-        "data": "synthetic",
-        "config": {"workload": f"{args.config}: {cfg['dim']}D Q1 {cfg['n']}^{cfg['dim']} "
-                               f"eps={cfg['eps']} sigma={cfg['sigma']} m={cfg['m']} "
-                               f"dt={cfg['dt']} theta={cfg['theta']} seed={cfg['seed']} "
-                               f"precision={prec}",
-                   "dofs": nd, "nodes": nd // 2, "global_batch": 1,
-                   "parallelism": "none (1 GPU)"},
-        "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
-                       "p99": float(np.percentile(step_ms, 99))},
-        "newton_its": stats.per_step(),
-        "fgmres_its": its,
-        "roofline": roofline,
-        "roofline_other": roof_stencil,
-        "roofline_vcycle": roof_mg,
-        "autotuned_shapes": tuned,
-    }
-    if prec == "mixed":
-        # after the timed region: the FP64 path from the same initial state,
-        # stepped beside the mixed one, and the error of each field per step
-        pf = ok.default_params(dim=cfg["dim"], n=cfg["n"], eps=cfg["eps"], sigma=cfg["sigma"],
-                               m=cfg["m"], dt=cfg["dt"], theta=cfg["theta"],
-                               precision=ok.OK_FP64)
-        Pf = ok.Problem(pf, device=dev)
-        um, wm, uf, wf = u0d.clone(), w0d.clone(), u0d.clone(), w0d.clone()
-        per_step = []
-        for k in range(args.steps):
-            P.timestep(um, wm, 1)
-            Pf.timestep(uf, wf, 1)
-            per_step.append({"step": k + 1,
-                             "u": float(torch.linalg.vector_norm(um - uf) /
-                                        torch.linalg.vector_norm(uf)),
-                             "w": float(torch.linalg.vector_norm(wm - wf) /
-                                        torch.linalg.vector_norm(wf))})
-        out["mixed_vs_fp64"] = {
-            "error": "relative 2-norm of each field after each step, against the FP64 path "
-                     "from the same initial state (both Newton-converged to the same tolerance)",
-            "per_step": per_step}
-        del Pf
-    if not args.no_cpu_baseline:
-        per_step = stats.fgmres_its_total / max(stats.steps_done, 1)
-        out["cpu_baseline"] = cpu_baseline(cfg, int(round(per_step)))
-    print(json.dumps(out), flush=True)
+    print(json.dumps(bench_single(args, torch, ok, cfg)), flush=True)
 
 
 if __name__ == "__main__":
