@@ -1,12 +1,15 @@
 """Full-size GPU parity in the launch configuration the benchmark times
 (autotuned stencil shapes, the default solver parameters).
 
-The oracle's results at 3D 128^3 (5 timesteps) and 3D 256^3 (1 timestep) were
+The oracle's results at 3D 128^3 and 3D 256^3 (5 timesteps each) were
 written by tests/golden/make_golden.py, which calls only the oracle: sampled
-node values of u and w after every step, global norms and sums, and the
+node values of u and w after every step, global norms and sums, the 2-norm
+of each field over every grid plane normal to each axis, and the
 Newton/FGMRES iteration counts.  Bars: identical iteration counts; sampled
 values within 1e-10 relative (2-norm over the sample) per field and step;
-global norms within 1e-12.  Properties that hold at any size are checked with
+every plane norm within 1e-10 relative (an error confined to a few nodes
+anywhere moves the norms of the three planes through them); global norms
+within 1e-12.  Properties that hold at any size are checked with
 the oracle's matrix-free local rows: J x at sampled nodes (1e-13) and the
 residual of the final state at sampled nodes (below the Newton tolerance).
 """
@@ -32,6 +35,17 @@ def load_golden(name):
     z = np.load(path)
     meta = json.load(open(os.path.join(GOLDEN, f"oracle_{name}.json")))
     return z, meta
+
+
+def plane_norms(v, dim, n):
+    """[axis][plane]: 2-norm over each grid plane normal to each axis (axis 0
+    = x, the fastest index), as the golden writer computes them."""
+    g = v.reshape((n + 1,) * dim)
+    out = []
+    for ax in range(dim):
+        other = tuple(a for a in range(dim) if a != dim - 1 - ax)
+        out.append(torch.sqrt(torch.sum(g * g, dim=other)))
+    return torch.stack(out).cpu().numpy()
 
 
 def problem(cfg, **kw):
@@ -65,6 +79,13 @@ def test_timesteps_match_oracle(name):
         assert eu < 1e-10 and ew < 1e-10
         assert abs(torch.linalg.norm(u).item() - z["unorm"][s]) <= 1e-12 * z["unorm"][s]
         assert abs(torch.linalg.norm(w).item() - z["wnorm"][s]) <= 1e-12 * z["wnorm"][s]
+        if "uplanes" in z.files:
+            for v, key in ((u, "uplanes"), (w, "wplanes")):
+                got = plane_norms(v, cfg["dim"], cfg["n"])
+                ref = z[key][s]
+                err = np.abs(got - ref) / ref
+                print(f"step {s}: {key} worst plane rel err {err.max():.2e}", flush=True)
+                assert err.max() <= 1e-10, (s, key, np.unravel_index(err.argmax(), err.shape))
 
 
 @pytest.mark.parametrize("name", ["3d128", "3d256"])

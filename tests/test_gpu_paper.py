@@ -4,7 +4,8 @@ paper's solver preset (two Richardson iterations of S~^-1, five V-cycles per
 S^^-1), on meshes N = 25 * 2^k whose multigrid coarsens to 25 elements per
 direction (a 26^3 coarse grid, solved axis by axis on the GPU and by CG in the
 oracle).  Against the oracle: w0 to 1e-12, the V-cycle to 1e-12, one
-timestep to 1e-10 with identical iteration counts."""
+timestep to 1e-10 with identical iteration counts, also with the autotuner's
+launch shapes and fused-kernel choices on the 3D N = 50 hierarchy."""
 import numpy as np
 import pytest
 
@@ -48,10 +49,12 @@ def test_multigrid_large_coarse_grid(dim, n):
         assert np.abs(x - o.mg(b, cycles)).max() / np.abs(x).max() < 1e-12
 
 
-@pytest.mark.parametrize("dim,n", [(2, 100), (3, 50)])
-def test_paper_timestep_matches_oracle(dim, n):
-    print("paper timestep", dim, n, flush=True)
+@pytest.mark.parametrize("dim,n,tuned", [(2, 100, False), (3, 50, False), (3, 50, True)])
+def test_paper_timestep_matches_oracle(dim, n, tuned):
+    print("paper timestep", dim, n, "autotuned" if tuned else "", flush=True)
     P, o = problem(dim, n, **PRESET)
+    if tuned:  # the launch shapes and fused kernels bench --config paper runs
+        P.autotune()
     u0, _ = cosine_state(dim, n, PAPER["m"])
     ud = torch.from_numpy(u0).cuda()
     wd = P.initial_w(ud)

@@ -2,9 +2,13 @@
 
 Every simulation's final state must equal, bit for bit, the state that a
 single-problem ok_timestep reaches from the same initial state in the same
-number of steps: slots share grouped launches but no arithmetic.  Admission
-bookkeeping (FIFO per simulation, bounded queue, HBM budget with pool
-release) is checked from the request records.
+number of steps: slots share grouped launches but no arithmetic.  Each served
+state is also checked against the FP64 CPU oracle run for the same number of
+timesteps (Newton on eq. (newton) of Sec. 2 with the block preconditioner of
+eq. (prec)): FP64 simulations to 1e-10 relative per field with the same
+FGMRES iteration counts, mixed-precision ones to 1e-8.  Admission bookkeeping
+(FIFO per simulation, bounded queue, HBM budget with pool release) is checked
+from the request records.
 """
 import numpy as np
 import pytest
@@ -34,6 +38,38 @@ def solo_state(p, spec, steps):
     if steps:
         ok.Problem(p).timestep(u, w, steps)
     return u.cpu().numpy(), w.cpu().numpy()
+
+
+def oracle_state(spec, steps):
+    from oracle.okref import Oracle
+    u0, w0 = noise_state(spec["dim"], spec["n"], spec["m"], spec["seed"])
+    o = Oracle(spec["dim"], spec["n"], spec["eps"], spec["sigma"], spec["m"], spec["dt"],
+               spec["theta"])
+    u, w, info, st = o.timestep(u0, w0, steps)
+    assert st == 0, st
+    return u, w, info
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def check_against_oracle(S, specs, steps, its_by_sim, precision):
+    """Final served state of every simulation against the oracle after the
+    same number of timesteps."""
+    tol = 1e-10 if precision == 0 else 1e-8
+    for i, s in enumerate(specs):
+        if steps[i] == 0:
+            continue
+        us, ws = S.get_state(i)
+        uo, wo, info = oracle_state(s, int(steps[i]))
+        eu, ew = rel(us.cpu().numpy(), uo), rel(ws.cpu().numpy(), wo)
+        print(f"sim {i} ({s['dim']}D {s['n']}, {steps[i]} steps): vs oracle u {eu:.2e} "
+              f"w {ew:.2e}, FGMRES its served {its_by_sim[i]} oracle {info.fgmres_its_total}",
+              flush=True)
+        assert eu <= tol and ew <= tol, (i, eu, ew)
+        if precision == 0:
+            assert its_by_sim[i] == info.fgmres_its_total, (i, its_by_sim[i], info.its())
 
 
 def start_server(specs, plist, budget, **cfg):
@@ -74,13 +110,17 @@ def test_served_results_equal_solo(precision):
     assert st["completed"] == len(t) and st["rejected"] == 0
     assert st["max_active"] >= 2  # requests shared ticks
     total = np.zeros(len(specs), dtype=int)
+    its = np.zeros(len(specs), dtype=int)
     for k in range(len(t)):
         total[sim[k]] += nsteps[k]
+    for r in res:
+        its[r["sim"]] += r["fgmres_its"]
     for i, s in enumerate(specs):
         us, ws = S.get_state(i)
         uo, wo = solo_state(plist[i], s, int(total[i]))
         assert np.array_equal(us.cpu().numpy(), uo), (i, s)
         assert np.array_equal(ws.cpu().numpy(), wo), (i, s)
+    check_against_oracle(S, specs, total, its, precision)
     S.close()
 
 
@@ -119,12 +159,15 @@ def test_admission_by_budget_and_queue_bound():
     assert st["peak_bytes"] <= budget
     check_fifo(res)
     steps = np.zeros(len(specs), dtype=int)
+    its = np.zeros(len(specs), dtype=int)
     for r in ok_res:
         steps[r["sim"]] += r["steps_done"]
+        its[r["sim"]] += r["fgmres_its"]
     for i, s in enumerate(specs):
         us, ws = S.get_state(i)
         uo, wo = solo_state(plist[i], s, int(steps[i]))
         assert np.array_equal(us.cpu().numpy(), uo) and np.array_equal(ws.cpu().numpy(), wo), i
+    check_against_oracle(S, specs, steps, its, 0)
     S.close()
 
 

@@ -136,13 +136,15 @@ def test_mg_smoother_shapes_bitwise(precision):
                 ok.set_launch_shape(dim, lev_n, kern, precision, 0)
 
 
+@pytest.mark.parametrize("n", [64, 100])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_mg_smoother_tile_shapes_bitwise(precision):
+def test_mg_smoother_tile_shapes_bitwise(precision, n):
     """The fused multigrid smoothers on in-plane tiles (3D), pinned on the two
-    finest levels of a 64^3 timestep for every thread and node count and
-    several z-splits: results equal the one-iteration kernels bit for bit."""
+    finest levels of a 64^3 timestep and of the paper's N = 100 mesh (levels
+    100 and 50) for every thread and node count and several z-splits: results
+    equal the one-iteration kernels bit for bit."""
     from paper_1603_04570_amd import ok
-    dim, n = 3, 64
+    dim = 3
     p = ok.default_params(dim=dim, n=n, eps=0.02, sigma=100.0, m=0.1, dt=2e-4,
                           precision=precision)
     u0, w0 = noise_state(dim, n, 0.1, 37)

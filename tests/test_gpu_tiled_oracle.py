@@ -1,0 +1,94 @@
+"""Elementwise oracle parity of the kernels the autotuner picks at full size.
+
+The tiled fused Chebyshev pair on M (k_cheb2t) and the tiled fused multigrid
+smoothers (k_mg2t, pre-smoothing + residual and post-smoothing) are pinned
+on every grid of a 3D 64^3 hierarchy (64, 32, 16, 8 elements per direction)
+and two timesteps of the 3D 128^3 parameters are run through them, against
+the FP64 CPU oracle on the same seeded input (Newton on eq. (newton) of
+Sec. 2, FGMRES with the block preconditioner of eq. (prec)):
+  FP64:  every node, relative 2-norm per field <= 1e-10 and max-norm <= 1e-9,
+         identical Newton and FGMRES iteration counts;
+  mixed: relative 2-norm per field <= 1e-8 (FP32 preconditioner).
+Also a timestep with the autotuner's own choices on the same mesh."""
+import numpy as np
+import pytest
+
+from oracle.okref import Oracle
+from paper_1603_04570_amd.inputs import noise_state
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+DIM, N = 3, 64
+CFG = dict(eps=0.01, sigma=1000.0, m=0.1, dt=2e-5, theta=1.0)
+STEPS = 2
+_oracle = {}
+
+
+def oracle_run():
+    if "r" not in _oracle:
+        u0, w0 = noise_state(DIM, N, CFG["m"], 2)
+        o = Oracle(DIM, N, **CFG)
+        u, w, info, st = o.timestep(u0, w0, STEPS)
+        assert st == 0
+        _oracle["r"] = (u, w, info.its(), [info.fgmres_its_total])
+    return _oracle["r"]
+
+
+def gpu_run(precision, autotune=False):
+    from paper_1603_04570_amd import ok
+    p = ok.default_params(dim=DIM, n=N, precision=precision, **CFG)
+    P = ok.Problem(p)
+    if autotune:
+        P.autotune()
+    u0, w0 = noise_state(DIM, N, CFG["m"], 2)
+    u, w = torch.from_numpy(u0).cuda(), torch.from_numpy(w0).cuda()
+    st = P.timestep(u, w, STEPS)
+    torch.cuda.synchronize()
+    assert st.status == 0
+    return u.cpu().numpy(), w.cpu().numpy(), st.its()
+
+
+def compare(got, ref, precision):
+    u, w, its = got
+    uo, wo, its_o, _ = ref
+    for a, b, name in ((u, uo, "u"), (w, wo, "w")):
+        e2 = np.linalg.norm(a - b) / np.linalg.norm(b)
+        einf = np.abs(a - b).max() / np.abs(b).max()
+        print(f"{name}: rel 2-norm {e2:.2e}, rel max {einf:.2e}", flush=True)
+        if precision == 0:
+            assert e2 <= 1e-10 and einf <= 1e-9, (name, e2, einf)
+        else:
+            assert e2 <= 1e-8, (name, e2)
+    if precision == 0:
+        assert its == its_o, (its, its_o)
+
+
+@pytest.mark.parametrize("items,threads", [(1, 256), (2, 512)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tiled_kernels_timestep_matches_oracle(precision, items, threads):
+    from paper_1603_04570_amd import ok
+    levels = [N >> k for k in range(4)]  # 64, 32, 16, 8
+    print("tiled kernels vs oracle", precision, items, threads, flush=True)
+    try:
+        ok.set_launch_shape(DIM, N, ok.OK_SHAPE_CHEB2_TILE, precision, items, threads, 5)
+        for ln in levels:
+            for kern in (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST):  # fused smoothers on
+                ok.set_launch_shape(DIM, ln, kern, precision, 1, 256, 1)
+            for kern in (ok.OK_SHAPE_MG_PRE_TILE, ok.OK_SHAPE_MG_POST_TILE):
+                ok.set_launch_shape(DIM, ln, kern, precision, items, threads, min(3, ln + 1))
+        got = gpu_run(precision)
+    finally:
+        ok.set_launch_shape(DIM, N, ok.OK_SHAPE_CHEB2_TILE, precision, 0)
+        for ln in levels:
+            for kern in (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST, ok.OK_SHAPE_MG_PRE_TILE,
+                         ok.OK_SHAPE_MG_POST_TILE):
+                ok.set_launch_shape(DIM, ln, kern, precision, 0)
+    compare(got, oracle_run(), precision)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_autotuned_timestep_matches_oracle(precision):
+    print("autotuned vs oracle", precision, flush=True)
+    # the tuned shapes stay in the process-wide table; results do not depend on them
+    compare(gpu_run(precision, autotune=True), oracle_run(), precision)
