@@ -213,7 +213,8 @@ int ok_autotune(ok_ctx *ctx, void *stream, int32_t *entries);
  * 1e-15 of the right-hand side.  d_u, d_w: n entries; synchronises. */
 int ok_initial_w(ok_ctx *ctx, const double *d_u, double *d_w, void *stream);
 
-/* Process-wide tuning options (results are bitwise the same either way):
+/* Process-wide tuning options (results are bitwise the same either way,
+ * except for OK_OPT_GRAM_SCHMIDT, whose two forms agree to rounding):
  *   OK_OPT_FUSE_CHEB: 1 (default) runs consecutive middle iterations of the
  *   Chebyshev iteration on M two per pass (each vector read and written once
  *   per pair); 0 runs them one per pass.
@@ -232,9 +233,19 @@ int ok_initial_w(ok_ctx *ctx, const double *d_u, double *d_w, void *stream);
  *   iteration ("newton iteration"), FGMRES restart cycle ("fgmres cycle"),
  *   FGMRES iteration ("fgmres iteration") and serving-pool tick ("serve
  *   tick").  Ranges cover the host's issue and wait, so with the default
- *   (no issue-ahead) an FGMRES iteration's range spans its device work. */
+ *   (no issue-ahead) an FGMRES iteration's range spans its device work.
+ *   OK_OPT_GRAM_SCHMIDT: orthogonalisation of each Arnoldi step of FGMRES.
+ *   0 (default): modified Gram-Schmidt in inverse compact WY form (Sec. 4's
+ *   GMRES; Swirydowicz et al., Numer. Linear Algebra Appl. 2021): one pass
+ *   forms <w, v_i> for every basis vector and the new row of V^T V, a
+ *   triangular solve gives modified Gram-Schmidt's coefficients, one pass
+ *   subtracts the projections; basis vectors are kept unnormalised with a
+ *   scale.  1: modified Gram-Schmidt one projection per pass (each fused
+ *   with the next dot product), normalised basis vectors.  Both compute the
+ *   same Arnoldi relation; results agree to rounding. */
 enum ok_option {
-  OK_OPT_FUSE_CHEB = 1, OK_OPT_FUSE_MG = 2, OK_OPT_ISSUE_AHEAD = 3, OK_OPT_TRACE_RANGES = 4
+  OK_OPT_FUSE_CHEB = 1, OK_OPT_FUSE_MG = 2, OK_OPT_ISSUE_AHEAD = 3, OK_OPT_TRACE_RANGES = 4,
+  OK_OPT_GRAM_SCHMIDT = 5
 };
 int ok_set_option(int32_t option, int32_t value);
 

@@ -77,6 +77,10 @@ struct ClassCtx {
   double* Q = nullptr;  // -(M_E(u) z1 + eps^2 K z1) of the last preconditioner application
   double *pA = nullptr, *pB = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr;
   double *g = nullptr, *y = nullptr, *kr = nullptr, *nrm = nullptr;
+  // two-pass Arnoldi projection: basis scales (m+1), lower part of V^T V
+  // ((m+1)^2), update coefficients (m+1), dot partials (2m rows of
+  // red_blocks(2n))
+  double *sc = nullptr, *Lm = nullptr, *hcf = nullptr, *pd = nullptr;
   void *Z = nullptr, *zt = nullptr;
   void *cr = nullptr, *cda = nullptr, *cdb = nullptr, *yv = nullptr, *tv = nullptr, *sv = nullptr;
   void* cr2 = nullptr;  // second Chebyshev residual (fused iterations ping-pong r)
@@ -121,6 +125,17 @@ int precond_apply_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<cons
 int cheb_mass_d(ClassCtx& c, const int* flags, Vec<const double> r, Vec<double> x, hipStream_t st);
 int mg_apply_d(ClassCtx& c, const int* flags, Vec<const double> b, Vec<double> x, int cycles,
                hipStream_t st);
+// The launches of the residual of eq. (newton)'s system on a class: F (2n
+// per instance), with t1, t2, G (n each) and the reduction partials part
+// (kMaxRedBlocks) as scratch, and nrm[0] = ||F||^2, nrm[1] = ||F|| on the
+// device.  wn null: wn is not read (theta = 1).
+hipError_t residual_launch(const Grid& g, const Batch& B, Vec<const double> u,
+                           Vec<const double> w, Vec<const double> un, Vec<const double> wn,
+                           Vec<double> F, Vec<double> t1, Vec<double> t2, Vec<double> G,
+                           Vec<double> part, Vec<double> nrm, hipStream_t st);
+// The constants-table record of one instance and the grids of its multigrid
+// hierarchy (L levels).  p must be valid (validate_params).
+void instance_constants(const ok_params& p, InstCoef& C, Grid* lev, int& L);
 // F and ||F|| per instance (norms in c.out[i].fnorm); F may be null (uses Bv).
 int residual_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const double> w,
                Vec<const double> un, Vec<const double> wn, Vec<double> F, hipStream_t st);
@@ -152,6 +167,11 @@ int newton_group_iters(const Group& grp, const std::vector<Vec<double>>& u,
                        const std::vector<Vec<double>>& w, const std::vector<Vec<const double>>& un,
                        const std::vector<Vec<const double>>& wn, std::vector<NewtonLog>& log,
                        int max_iters, hipStream_t st);
+// Orthogonalisation of the Arnoldi step: 0 (default) two passes over the
+// basis (modified Gram-Schmidt in inverse compact WY form, unnormalised
+// basis vectors with scales); 1 fused modified Gram-Schmidt, one pass per
+// projection, normalised basis vectors.
+void ortho_set(int mode);
 // Upload host flags (h_part) to the device part/act arrays.
 int push_part(ClassCtx& c, hipStream_t st);
 // Replace the physical parameters of instance i (same class) and upload its

@@ -220,6 +220,10 @@ void carve(ClassCtx& c, char* base, bool with_state, size_t* total) {
   c.y = cv.take<double>((size_t)B * (m + 1));
   c.kr = cv.take<double>((size_t)B * 8);
   c.nrm = cv.take<double>((size_t)B * 8);
+  c.sc = cv.take<double>((size_t)B * (m + 1));
+  c.Lm = cv.take<double>((size_t)B * (m + 1) * (m + 1));
+  c.hcf = cv.take<double>((size_t)B * (m + 1));
+  c.pd = cv.take<double>((size_t)B * 2 * m * red_blocks(n2));
   *total = (cv.off + 255) & ~(size_t)255;
 }
 
@@ -246,6 +250,8 @@ inline int64_t sV(const ClassCtx& c) { return (int64_t)(c.m + 1) * c.n2(); }
 inline int64_t sZ(const ClassCtx& c) { return (int64_t)c.m * c.n2(); }
 inline int64_t sH(const ClassCtx& c) { return (int64_t)(c.m + 1) * c.m; }
 inline int64_t sM(const ClassCtx& c) { return (int64_t)c.m + 1; }
+inline int64_t sL(const ClassCtx& c) { return (int64_t)(c.m + 1) * (c.m + 1); }
+inline int64_t sPd(const ClassCtx& c) { return (int64_t)2 * c.m * red_blocks(c.n2()); }
 
 template <class P>
 Vec<P> pvec(void* p, int64_t s) {
@@ -268,18 +274,19 @@ Vec<T> off(Vec<T> v, int64_t o) {
 template <class TB, class P>
 int cheb_zero(ClassCtx& c, const int* fl, int cls, int step_cls, const Grid& g, int lev, int osc,
               int K, Vec<const TB> b, Vec<P> x, Vec<P> r, Vec<P> da, Vec<P> db, hipStream_t st,
-              Vec<P> r2 = Vec<P>{nullptr, 0}) {
+              Vec<P> r2 = Vec<P>{nullptr, 0},
+              Vec<const double> bs = Vec<const double>{nullptr, 0}) {
   const Batch B = c.batch(fl);
   const double w = (double)c.psz * g.nodes * c.B, wb = (double)sizeof(TB) * g.nodes * c.B;
   if (K > kMaxCheb) return set_err(c.err, OK_E_INVALID, "too many Chebyshev iterations");
   if (K <= 1) {
     ProfScope ps(c, cls, wb + w, st);
-    OKE(c, launch_cheb_one<TB, P>(g, B, lev, osc, b, x, st));
+    OKE(c, launch_cheb_one<TB, P>(g, B, lev, osc, b, x, st, bs));
     return OK_SUCCESS;
   }
   {
     ProfScope ps(c, cls, wb + (K == 2 ? w : 3.0 * w), st);
-    OKE(c, launch_cheb_first<TB, P>(g, B, lev, osc, K == 2, b, x, r, da, st));
+    OKE(c, launch_cheb_first<TB, P>(g, B, lev, osc, K == 2, b, x, r, da, st, bs));
   }
   if (K == 2) return OK_SUCCESS;
   Vec<P> dc = da, dn = db;
@@ -420,9 +427,10 @@ int schur_tilde_inv(ClassCtx& c, const int* fl, Vec<const P> b, Vec<P> x, Vec<P>
 }
 
 // z = [z1; z2] = P^-1 [r1; r2], eq. (prec) with S~^-1 = S^^-1 M S^^-1.
+// rs (may be null): r is stored unscaled, its value is rs[0] * r.
 template <class P>
 int precond(ClassCtx& c, const int* fl, Vec<const double> u, Vec<const double> r, Vec<P> z,
-            hipStream_t st) {
+            hipStream_t st, Vec<const double> rs = Vec<const double>{nullptr, 0}) {
   const Grid& g = c.lev[0];
   const Batch B = c.batch(fl);
   const int64_t n = c.n;
@@ -431,7 +439,8 @@ int precond(ClassCtx& c, const int* fl, Vec<const double> u, Vec<const double> r
   Vec<P> cr = pvec<P>(c.cr, n), cda = pvec<P>(c.cda, n), cdb = pvec<P>(c.cdb, n);
   // z1 = A~^-1 r1: Chebyshev on M, scaled by 1/(1 + dt th sigma).
   int e = cheb_zero<double, P>(c, fl, OK_K_NONE, OK_K_CHEB_MASS, g, -1, CF_INV_SA,
-                               c.shape.cheb_A_its, r1, z1, cr, cda, cdb, st, pvec<P>(c.cr2, n));
+                               c.shape.cheb_A_its, r1, z1, cr, cda, cdb, st, pvec<P>(c.cr2, n),
+                               rs);
   if (e) return e;
   // y = r2 - C z1 = r2 + eps^2 K z1 + M_E(u) z1, M_E z1 = 3G - M z1 (G in FP64);
   // Q = -(eps^2 K z1 + M_E(u) z1) is kept: the Jacobian applied to this z needs it.
@@ -442,7 +451,7 @@ int precond(ClassCtx& c, const int* fl, Vec<const double> u, Vec<const double> r
                                      G, st));
   }
   Vec<P> y = pvec<P>(c.yv, n), t = pvec<P>(c.tv, n), s = pvec<P>(c.sv, n);
-  OKE(c, launch_couple<P>(g, B, cst(z1), cst(G), r2, y, vec(c.Q, n), st));
+  OKE(c, launch_couple<P>(g, B, cst(z1), cst(G), r2, rs, y, vec(c.Q, n), st));
   // z2 = S~^-1 y = S^^-1 M S^^-1 y
   e = schur_tilde_inv<P>(c, fl, cst(y), z2, t, s, st);
   if (e) return e;
@@ -524,6 +533,8 @@ int push_flags(ClassCtx& c, int* dflags, const std::vector<int>& h, hipStream_t 
   return OK_SUCCESS;
 }
 
+int g_ortho = 0;
+
 // One FGMRES iteration j (Arnoldi step + Givens) for the active instances.
 template <class P>
 int fgmres_iteration(ClassCtx& c, int j, Vec<const double> u, hipStream_t st) {
@@ -532,15 +543,34 @@ int fgmres_iteration(ClassCtx& c, int j, Vec<const double> u, hipStream_t st) {
   Vec<double> Vj = Vec<double>{c.V + (int64_t)j * n2, sV(c)};
   Vec<double> W = Vec<double>{c.V + (int64_t)(j + 1) * n2, sV(c)};
   Vec<P> Zj = Vec<P>{(P*)c.Z + (int64_t)j * n2, sZ(c)};
-  int e = precond<P>(c, c.act, u, cst(Vj), Zj, st);
+  const bool proj = (g_ortho == 0);
+  int e = precond<P>(c, c.act, u, cst(Vj), Zj, st,
+                     proj ? Vec<const double>{c.sc + j, sM(c)} : Vec<const double>{nullptr, 0});
   if (e) return e;
   e = jac_z<P>(c, c.act, cst(Zj), W, st);
   if (e) return e;
   Vec<double> pin = vec(c.pA, (int64_t)kMaxRedBlocks), pout = vec(c.pB, (int64_t)kMaxRedBlocks);
+  if (proj) {
+    {
+      // modified Gram-Schmidt's algorithmic bytes (w and v_i read, w written
+      // per projection i = 0..j); the two passes move 2j+5 vectors
+      ProfScope ps(c, OK_K_KRYLOV, 24.0 * (j + 1) * n2 * c.B, st, j / kProjGroup + 3);
+      OKE(c, launch_proj(B, W, Vec<const double>{c.V, sV(c)}, n2, j, c.m, n2, vec(c.pd, sPd(c)),
+                         Vec<const double>{c.sc, sM(c)}, vec(c.Lm, sL(c)),
+                         Vec<double>{c.H + (int64_t)j * (c.m + 1), sH(c)}, vec(c.hcf, sM(c)),
+                         pin, st));
+    }
+    OKE(c, launch_givens(B, c.act, j, c.m, vec(c.H, sH(c)), vec(c.cs, sM(c)), vec(c.sn, sM(c)),
+                         vec(c.g, sM(c)), cst(pin), n2, vec(c.kr, (int64_t)8), vec(c.sc, sM(c)),
+                         st));
+    return OK_SUCCESS;
+  }
   {
-    // the Gram-Schmidt chain (one dot, j+1 fused steps) timed as one run:
-    // 2 vectors read by the dot, 4 per middle step, 3 by the last one
-    ProfScope ps(c, OK_K_KRYLOV, (16.0 + 32.0 * j + 24.0) * n2 * c.B, st, j + 2);
+    // the Gram-Schmidt chain (one dot, j+1 fused steps) timed as one run;
+    // algorithmic bytes of modified Gram-Schmidt: per projection i = 0..j,
+    // w and v_i read and w written (the kernels also read v_{i+1} for the
+    // fused next dot, and the dot reads w and v_0 once more)
+    ProfScope ps(c, OK_K_KRYLOV, 24.0 * (j + 1) * n2 * c.B, st, j + 2);
     OKE(c, launch_dot_partial(B, cst(W), Vec<const double>{c.V, sV(c)}, n2, pin, st));
     for (int i = 0; i <= j; i++) {
       Vec<const double> vi{c.V + (int64_t)i * n2, sV(c)};
@@ -551,7 +581,8 @@ int fgmres_iteration(ClassCtx& c, int j, Vec<const double> u, hipStream_t st) {
     }
   }
   OKE(c, launch_givens(B, c.act, j, c.m, vec(c.H, sH(c)), vec(c.cs, sM(c)), vec(c.sn, sM(c)),
-                       vec(c.g, sM(c)), cst(pin), n2, vec(c.kr, (int64_t)8), st));
+                       vec(c.g, sM(c)), cst(pin), n2, vec(c.kr, (int64_t)8),
+                       Vec<double>{nullptr, 0}, st));
   OKE(c, launch_scale_by(B, cst(W), W, Vec<const double>{c.kr, 8}, n2, st));
   return OK_SUCCESS;
 }
@@ -812,6 +843,40 @@ int initial_w_d(ClassCtx& c, Vec<const double> u, Vec<double> w, int* rounds, hi
   return OK_SUCCESS;
 }
 
+hipError_t residual_launch(const Grid& g, const Batch& B, Vec<const double> u,
+                           Vec<const double> w, Vec<const double> un, Vec<const double> wn,
+                           Vec<double> F, Vec<double> t1, Vec<double> t2, Vec<double> G,
+                           Vec<double> part, Vec<double> nrm, hipStream_t st) {
+  const int64_t n = g.nodes;
+  hipError_t e = launch_residual_prep(B, u, un, w, wn, t1, t2, n, st);
+  if (e != hipSuccess) return e;
+  Vec<double> F1 = F, F2 = Vec<double>{F.p + n, F.s};
+  const double a[2][4] = {{1.0, 0.0, 0.0, 1.0}, {0.0, 0.0, 0.0, 0.0}};  // F1 = M t1 + K t2
+  const int fa[2][4] = {{CF_ONE, CF_ONE, CF_ONE, CF_ONE}, {CF_ONE, CF_ONE, CF_ONE, CF_ONE}};
+  e = launch_stencil_lin2<double>(g, B, cst(t1), cst(t2), Vec<const double>{nullptr, 0},
+                                  Vec<const double>{nullptr, 0}, a, fa, F1,
+                                  Vec<double>{nullptr, 0}, st);
+  if (e != hipSuccess) return e;
+  e = launch_element<double, double>(g, B, 1, u, Vec<const double>{nullptr, 0},
+                                     Vec<const double>{nullptr, 0}, -1.0, 0.0, G, st);
+  if (e != hipSuccess) return e;
+  // F2 = -N(u) + M w - eps^2 K u
+  const double b2[2][4] = {{1.0, 0.0, 0.0, -1.0}, {0.0, 0.0, 0.0, 0.0}};
+  const int fb[2][4] = {{CF_ONE, CF_ONE, CF_ONE, CF_E2}, {CF_ONE, CF_ONE, CF_ONE, CF_ONE}};
+  e = launch_stencil_lin2<double>(g, B, w, u, cst(G), Vec<const double>{nullptr, 0}, b2, fb, F2,
+                                  Vec<double>{nullptr, 0}, st);
+  if (e != hipSuccess) return e;
+  e = launch_dot_partial(B, cst(F), cst(F), 2 * n, part, st);
+  if (e != hipSuccess) return e;
+  return launch_reduce_final(B, cst(part), 2 * n, nrm, st);
+}
+
+void instance_constants(const ok_params& p, InstCoef& C, Grid* lev, int& L) {
+  L = levels_for(&p);
+  for (int l = 0; l < L; l++) lev[l] = make_grid(p.dim, p.n >> l);
+  inst_coef(C, p, lev, L);
+}
+
 int residual_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const double> w,
                Vec<const double> un, Vec<const double> wn, Vec<double> F, hipStream_t st) {
   const Grid& g = c.lev[0];
@@ -820,23 +885,8 @@ int residual_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const dou
   if (F.null()) F = vec(c.Bv, c.n2());
   Vec<double> t1 = vec(c.T1, c.n2()), t2 = off(vec(c.T1, c.n2()), n);
   Vec<const double> wnv = (c.shape.theta < 1.0 || !wn.null()) ? wn : Vec<const double>{nullptr, 0};
-  OKE(c, launch_residual_prep(B, u, un, w, wnv, t1, t2, n, st));
-  Vec<double> F1 = F, F2 = off(F, n);
-  const double a[2][4] = {{1.0, 0.0, 0.0, 1.0}, {0.0, 0.0, 0.0, 0.0}};  // F1 = M t1 + K t2
-  const int fa[2][4] = {{CF_ONE, CF_ONE, CF_ONE, CF_ONE}, {CF_ONE, CF_ONE, CF_ONE, CF_ONE}};
-  OKE(c, launch_stencil_lin2<double>(g, B, cst(t1), cst(t2), Vec<const double>{nullptr, 0},
-                                     Vec<const double>{nullptr, 0}, a, fa, F1,
-                                     Vec<double>{nullptr, 0}, st));
-  Vec<double> G = vec(c.G, n);
-  OKE(c, launch_element<double, double>(g, B, 1, u, Vec<const double>{nullptr, 0},
-                                        Vec<const double>{nullptr, 0}, -1.0, 0.0, G, st));
-  // F2 = -N(u) + M w - eps^2 K u
-  const double b2[2][4] = {{1.0, 0.0, 0.0, -1.0}, {0.0, 0.0, 0.0, 0.0}};
-  const int fb[2][4] = {{CF_ONE, CF_ONE, CF_ONE, CF_E2}, {CF_ONE, CF_ONE, CF_ONE, CF_ONE}};
-  OKE(c, launch_stencil_lin2<double>(g, B, w, u, cst(G), Vec<const double>{nullptr, 0}, b2, fb, F2,
-                                     Vec<double>{nullptr, 0}, st));
-  OKE(c, launch_dot_partial(B, cst(F), cst(F), c.n2(), vec(c.pA, (int64_t)kMaxRedBlocks), st));
-  OKE(c, launch_reduce_final(B, Vec<const double>{c.pA, kMaxRedBlocks}, c.n2(), vec(c.nrm, 8), st));
+  OKE(c, residual_launch(g, B, u, w, un, wnv, F, t1, t2, vec(c.G, n),
+                         vec(c.pA, (int64_t)kMaxRedBlocks), vec(c.nrm, 8), st));
   if (d2h(c, c.h_nrm, c.nrm, (size_t)8 * c.B, st)) return OK_E_HIP;
   if (sync(c, st)) return OK_E_HIP;
   std::vector<int> hf(c.B, 1);
@@ -855,6 +905,7 @@ namespace {
 int g_issue_ahead = 0;
 }  // namespace
 void issue_ahead_set(int enable) { g_issue_ahead = enable ? 1 : 0; }
+void ortho_set(int mode) { g_ortho = mode ? 1 : 0; }
 
 bool g_trace_ranges = false;
 void trace_ranges_set(int enable) { g_trace_ranges = enable != 0; }
@@ -922,7 +973,7 @@ int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,
       OKE(c, launch_scale_inv(B, src, Vec<double>{c.V, sV(c)}, Vec<const double>{c.nrm, 8},
                               c.n2(), st));
       OKE(c, launch_cycle_init(B, c.m, vec(c.g, sM(c)), Vec<const double>{c.nrm, 8},
-                               vec(c.kr, (int64_t)8), st));
+                               vec(c.kr, (int64_t)8), vec(c.sc, sM(c)), st));
       OKE(c, hipMemcpyAsync(c.incyc, c.act, sizeof(int) * c.B, hipMemcpyDeviceToDevice, st));
       first[k] = false;
     }

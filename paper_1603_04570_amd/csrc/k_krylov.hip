@@ -10,7 +10,9 @@
 #include "ok_internal.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <utility>
 
 namespace okd {
 
@@ -112,7 +114,7 @@ __global__ void __launch_bounds__(kRedThreads)
 // arithmetic in the order of the textbook recurrence) and the stop test.
 __global__ void k_givens(Batch B, int* act, int j, int m, Vec<double> Hv, Vec<double> csv,
                          Vec<double> snv, Vec<double> gv, Vec<const double> pnv, int nblk,
-                         Vec<double> krv) {
+                         Vec<double> krv, Vec<double> scv) {
   __shared__ double sh[8];
   const int inst = blockIdx.x;
   if (inactive(B, inst)) return;
@@ -142,6 +144,7 @@ __global__ void k_givens(Batch B, int* act, int j, int m, Vec<double> Hv, Vec<do
   kr[4] = hn;
   kr[5] = 1.0 / hn;
   kr[6] = (double)(j + 1);
+  if (!scv.null()) scv.at(inst)[j + 1] = kr[5];  // v_{j+1} = w / h_{j+1,j}, kept unscaled
   if (!isfinite(hn) || !isfinite(res)) {
     kr[7] = 2.0;
     act[inst] = 0;
@@ -178,18 +181,158 @@ __global__ void __launch_bounds__(256)
 }
 
 __global__ void k_cycle_init(Batch B, int m, Vec<double> gv, Vec<const double> nv,
-                             Vec<double> krv) {
+                             Vec<double> krv, Vec<double> scv) {
   const int inst = blockIdx.x;
   if (inactive(B, inst)) return;
   double* g = gv.at(inst);
   const double beta = nv.at(inst)[1];
   for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = (i == 0) ? beta : 0.0;
+  if (!scv.null())
+    for (int i = threadIdx.x; i <= m; i += blockDim.x) scv.at(inst)[i] = 1.0;
   if (threadIdx.x == 0) {
     double* kr = krv.at(inst);
     kr[2] = beta;
     kr[6] = 0.0;
     kr[7] = 0.0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Arnoldi projection in two passes (modified Gram-Schmidt in inverse compact
+// WY form; Swirydowicz, Langou, Ananthan, Yang, Thomas, "Low synchronization
+// Gram-Schmidt and GMRES algorithms", Numer. Linear Algebra Appl. 2021).
+// With V = [v_0..v_j] and L the strictly lower part of V^T V, modified
+// Gram-Schmidt's coefficients satisfy (I + L) h = V^T w: h_i = <w, v_i> -
+// sum_{k<i} <v_i, v_k> h_k, since each projection has already removed the
+// earlier components.  So one pass forms every <w, v_i> and the new row
+// <v_j, v_i> of L, a one-block kernel solves the triangular system, and one
+// pass forms w - V h with the partials of its squared norm: 2j+5 vector
+// passes per Arnoldi step instead of 4j+7.  Basis vectors are stored
+// unnormalised, v_i = s_i V_i with s_i = 1/h_{i,i-1} (s_0 = 1), so no pass
+// rescales the new vector; every reader applies s_i.
+// ---------------------------------------------------------------------------
+
+// Partials of a_i = <W, V_i> and c_i = <V_j, V_i> for i = i0 .. i0+NV-1:
+// pd[(2i) * nblk + kb] and pd[(2i+1) * nblk + kb].  Element order as k_dot.
+template <int NV>
+__global__ void __launch_bounds__(kRedThreads)
+    k_proj_dots(Batch B, Vec<const double> wv, Vec<const double> Vv, int64_t vstride, int i0,
+                int j, int64_t n, Vec<double> pdv, int nblk) {
+  __shared__ double sh[kRedThreads / 64][2 * NV];
+  const int inst = blockIdx.x / nblk, kb = blockIdx.x % nblk;
+  if (inactive(B, inst)) return;
+  const double* w = wv.at(inst);
+  const double* V = Vv.at(inst);
+  const double* vj = V + (int64_t)j * vstride;
+  const double* vi[NV];
+#pragma unroll
+  for (int q = 0; q < NV; q++) vi[q] = V + (int64_t)(i0 + q) * vstride;
+  double a[NV], c[NV];
+#pragma unroll
+  for (int q = 0; q < NV; q++) a[q] = c[q] = 0.0;
+  for (int64_t e = (int64_t)kb * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)nblk * blockDim.x) {
+    const double x = ldnt(w + e), y = ldnt(vj + e);
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+      const double v = ldnt(vi[q] + e);
+      a[q] = fma(x, v, a[q]);
+      c[q] = fma(y, v, c[q]);
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; q++) {
+    double s = a[q], t = c[q];
+    for (int o = 32; o > 0; o >>= 1) {
+      s += __shfl_xor(s, o);
+      t += __shfl_xor(t, o);
+    }
+    if (lane == 0) {
+      sh[wave][2 * q] = s;
+      sh[wave][2 * q + 1] = t;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < 2 * NV) {
+    double s = 0.0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); k++) s += sh[k][threadIdx.x];
+    pdv.at(inst)[(int64_t)(2 * i0 + threadIdx.x) * nblk + kb] = s;
+  }
+}
+
+// One block per instance: sum the partials (wave q%8 sums row q, a fixed
+// order), scale by s_i (and s_j), store row j of L, solve (I + L) h = a by
+// forward substitution, write column j of H and the update coefficients
+// hc_i = h_i s_i of the stored vectors.
+__global__ void __launch_bounds__(512)
+    k_proj_coef(Batch B, int j, int m, Vec<const double> pdv, int nblk, Vec<const double> scv,
+                Vec<double> Lv, Vec<double> Hv, Vec<double> hcv) {
+  __shared__ double sums[2 * 64];
+  __shared__ double hh[64];
+  const int inst = blockIdx.x;
+  if (inactive(B, inst)) return;
+  const double* pd = pdv.at(inst);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int nq = 2 * (j + 1);
+  for (int q = wave; q < nq; q += nw) {
+    double s = 0.0;
+    for (int k = lane; k < nblk; k += 64) s += pd[(int64_t)q * nblk + k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) sums[q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double* sc = scv.at(inst);
+  double* L = Lv.at(inst);  // row-major (m+1) x (m+1): L[i*(m+1)+k] = <v_i, v_k>, k < i
+  double* H = Hv.at(inst);  // column j of the Hessenberg matrix
+  double* hc = hcv.at(inst);
+  const int ld = m + 1;
+  const double sj = sc[j];
+  for (int i = 0; i < j; i++) L[(int64_t)j * ld + i] = sums[2 * i + 1] * sc[i] * sj;
+  for (int i = 0; i <= j; i++) {
+    double h = sums[2 * i] * sc[i];
+    for (int k = 0; k < i; k++) h = fma(-L[(int64_t)i * ld + k], hh[k], h);
+    hh[i] = h;
+    H[i] = h;
+    hc[i] = h * sc[i];
+  }
+}
+
+// w -= sum_i hc_i V_i (i = 0 .. j) and the partials of <w, w>.  Element order
+// as k_dot.
+__global__ void __launch_bounds__(kRedThreads)
+    k_proj_update(Batch B, Vec<double> wv, Vec<const double> Vv, int64_t vstride, int j,
+                  int64_t n, Vec<const double> hcv, Vec<double> pv, int nblk) {
+  __shared__ double sh[kRedThreads / 64];
+  __shared__ double hs[64];
+  const int inst = blockIdx.x / nblk, kb = blockIdx.x % nblk;
+  if (inactive(B, inst)) return;
+  if ((int)threadIdx.x <= j) hs[threadIdx.x] = hcv.at(inst)[threadIdx.x];
+  __syncthreads();
+  double* w = wv.at(inst);
+  const double* V = Vv.at(inst);
+  double acc = 0.0;
+  for (int64_t e = (int64_t)kb * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)nblk * blockDim.x) {
+    double x = ldnt(w + e);
+    int i = 0;
+    for (; i + 4 <= j + 1; i += 4) {  // four loads in flight per trip
+      const double v0 = ldnt(V + (int64_t)i * vstride + e);
+      const double v1 = ldnt(V + (int64_t)(i + 1) * vstride + e);
+      const double v2 = ldnt(V + (int64_t)(i + 2) * vstride + e);
+      const double v3 = ldnt(V + (int64_t)(i + 3) * vstride + e);
+      x = fma(-hs[i], v0, x);
+      x = fma(-hs[i + 1], v1, x);
+      x = fma(-hs[i + 2], v2, x);
+      x = fma(-hs[i + 3], v3, x);
+    }
+    for (; i <= j; i++) x = fma(-hs[i], ldnt(V + (int64_t)i * vstride + e), x);
+    stnt(x, w + e);
+    acc = fma(x, x, acc);
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) pv.at(inst)[kb] = acc;
 }
 
 // Back substitution with the triangular H (column-major, leading dim m+1).
@@ -324,9 +467,41 @@ hipError_t launch_mgs_step(const Batch& B, Vec<double> w, Vec<const double> vi,
 
 hipError_t launch_givens(const Batch& B, int* act, int j, int m, Vec<double> H, Vec<double> cs,
                          Vec<double> sn, Vec<double> g, Vec<const double> pnorm, int64_t n,
-                         Vec<double> kr, hipStream_t st) {
+                         Vec<double> kr, Vec<double> sc, hipStream_t st) {
   hipLaunchKernelGGL(k_givens, dim3(B.count), dim3(256), 0, st, B, act, j, m, H, cs, sn, g, pnorm,
-                     red_blocks(n), kr);
+                     red_blocks(n), kr, sc);
+  return hipGetLastError();
+}
+
+namespace {
+template <int NV>
+void launch_dots_nv(const Batch& B, Vec<const double> w, Vec<const double> V, int64_t vstride,
+                    int i0, int j, int64_t n, Vec<double> pd, int nb, hipStream_t st) {
+  hipLaunchKernelGGL((k_proj_dots<NV>), dim3((unsigned)((int64_t)nb * B.count)),
+                     dim3(kRedThreads), 0, st, B, w, V, vstride, i0, j, n, pd, nb);
+}
+using DotsFn = void (*)(const Batch&, Vec<const double>, Vec<const double>, int64_t, int, int,
+                        int64_t, Vec<double>, int, hipStream_t);
+template <int... K>
+constexpr std::array<DotsFn, sizeof...(K)> dots_table(std::integer_sequence<int, K...>) {
+  return {&launch_dots_nv<K + 1>...};
+}
+}  // namespace
+
+hipError_t launch_proj(const Batch& B, Vec<double> w, Vec<const double> V, int64_t vstride, int j,
+                       int m, int64_t n, Vec<double> pd, Vec<const double> sc, Vec<double> L,
+                       Vec<double> Hcol, Vec<double> hc, Vec<double> pnorm, hipStream_t st) {
+  if (j < 0 || j >= m || m > 64) return hipErrorInvalidValue;
+  static constexpr auto kDots = dots_table(std::make_integer_sequence<int, kProjGroup>{});
+  const int nb = red_blocks(n);
+  for (int i0 = 0; i0 <= j; i0 += kProjGroup) {
+    const int nv = std::min(kProjGroup, j + 1 - i0);
+    kDots[nv - 1](B, Vec<const double>{w.p, w.s}, V, vstride, i0, j, n, pd, nb, st);
+  }
+  hipLaunchKernelGGL(k_proj_coef, dim3(B.count), dim3(512), 0, st, B, j, m,
+                     Vec<const double>{pd.p, pd.s}, nb, sc, L, Hcol, hc);
+  hipLaunchKernelGGL(k_proj_update, dim3((unsigned)((int64_t)nb * B.count)), dim3(kRedThreads), 0,
+                     st, B, w, V, vstride, j, n, Vec<const double>{hc.p, hc.s}, pnorm, nb);
   return hipGetLastError();
 }
 
@@ -345,8 +520,8 @@ hipError_t launch_scale_inv(const Batch& B, Vec<const double> b, Vec<double> v,
 }
 
 hipError_t launch_cycle_init(const Batch& B, int m, Vec<double> g, Vec<const double> nrm,
-                             Vec<double> kr, hipStream_t st) {
-  hipLaunchKernelGGL(k_cycle_init, dim3(B.count), dim3(64), 0, st, B, m, g, nrm, kr);
+                             Vec<double> kr, Vec<double> sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_cycle_init, dim3(B.count), dim3(64), 0, st, B, m, g, nrm, kr, sc);
   return hipGetLastError();
 }
 

@@ -215,6 +215,10 @@ template <class TS, int NF>
 struct Src {
   const TS* p[NF];
   int64_t s[NF];
+  // optional scale of field 0 (per instance: sc0[inst * scs]): the values are
+  // staged as sc0 * p[0], rounded to TS (unnormalised FGMRES basis vectors)
+  const double* sc0 = nullptr;
+  int64_t scs = 0;
 };
 
 template <int DIM, int NF, int NT, int P, int F, bool SCALED, class TS, class Epi>
@@ -232,7 +236,7 @@ __global__ void __launch_bounds__(NT)
   const int b = lb - inst * sh.blocks;
   const int chunk = b % sh.nchunks;
   const int zch = b / sh.nchunks;
-  const typename Epi::K kk = epi.prep(B.coef[inst]);
+  const typename Epi::K kk = epi.prep(B.coef[inst], inst);
   const int nn = g.nn, N = g.N;
   // Streaming "plane": an x-y plane in 3D, an x row in 2D.
   const int64_t plane = (DIM == 3) ? g.plane : (int64_t)nn;
@@ -274,6 +278,8 @@ __global__ void __launch_bounds__(NT)
         pre[f][k] = sp[f][zoff + gc];
       }
   };
+  const bool scaled0 = src.sc0 != nullptr;
+  const double sc0 = scaled0 ? src.sc0[(int64_t)inst * src.scs] : 1.0;
   auto commit = [&]() {
 #pragma unroll
     for (int f = 0; f < NF; f++)
@@ -281,7 +287,9 @@ __global__ void __launch_bounds__(NT)
       for (int k = 0; k < F; k++) {
         const int t = tid + NT * k;
         const int64_t gq = s0 - halo + t;
-        if (t < ldsn) lds[f * ldsn + t] = (gq >= 0 && gq < plane) ? pre[f][k] : TS(0);
+        TS v = pre[f][k];
+        if (f == 0 && scaled0) v = (TS)(to_d(v) * sc0);
+        if (t < ldsn) lds[f * ldsn + t] = (gq >= 0 && gq < plane) ? v : TS(0);
       }
   };
   // In-plane partial products: 3D P_M = (M1 x M1) s, P_K = (K1 x M1 + M1 x K1) s;
@@ -517,8 +525,8 @@ static hipError_t run_stencil_n(const Grid& g, const Batch& B, const Src<TS, NF>
 
 template <bool SCALED, class TS, class Epi>
 static hipError_t run_stencil(const Grid& g, const Batch& B, Vec<const TS> s, const Epi& e,
-                              hipStream_t st) {
-  Src<TS, 1> src{{s.p}, {s.s}};
+                              hipStream_t st, Vec<const double> sc = Vec<const double>{nullptr, 0}) {
+  Src<TS, 1> src{{s.p}, {s.s}, sc.p, sc.s};
   return run_stencil_n<SCALED, TS, 1>(g, B, src, e, st);
 }
 
@@ -581,7 +589,7 @@ struct EpiAxpy {
   double ca, cb;
   int fa, fb;
   Vec<TO> out;
-  __device__ K prep(const InstCoef& C) const {
+  __device__ K prep(const InstCoef& C, int) const {
     return K{ca * coef_field(C, fa), cb * coef_field(C, fb)};
   }
   __device__ In load(int inst, int64_t i) const {
@@ -605,7 +613,7 @@ struct EpiLin2 {
   double c[2][4];
   int f[2][4];
   Vec<TO> out0, out1;
-  __device__ K prep(const InstCoef& C) const {
+  __device__ K prep(const InstCoef& C, int) const {
     K k;
     for (int o = 0; o < 2; o++)
       for (int q = 0; q < 4; q++) k.c[o][q] = c[o][q] * coef_field(C, f[o][q]);
@@ -627,21 +635,25 @@ struct EpiLin2 {
 // Coupling of the block preconditioner (eq. (prec), factor [I,0;-CA^-1,I]):
 // with G = 3 int u^2 z1 phi, q = M_E(u) z1 + eps^2 K z1 = G - M z1 + eps^2 K z1;
 // writes y = r2 + q and nq = -q (kept for the Jacobian applied to this z).
+// r2s (may be null): r2 is stored unscaled and its value is r2s[0] * r2
+// (the basis vectors of FGMRES carry their normalisation as a scale).
 template <class TY>
 struct EpiCouple {
   using In = In2<double, double>;
   struct K {
-    double e2;
+    double e2, s;
   };
-  Vec<const double> g, r2;
+  Vec<const double> g, r2, r2s;
   Vec<TY> y;
   Vec<double> nq;
-  __device__ K prep(const InstCoef& C) const { return K{C.e2}; }
+  __device__ K prep(const InstCoef& C, int inst) const {
+    return K{C.e2, r2s.null() ? 1.0 : r2s.at(inst)[0]};
+  }
   __device__ In load(int inst, int64_t i) const { return In{g.at(inst)[i], r2.at(inst)[i]}; }
   __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
                         const double*, const In& in, const K& k) const {
     const double q = fma(k.e2, ks[0], in.a - ms[0]);
-    y.at(inst)[i] = (TY)(in.b + q);
+    y.at(inst)[i] = (TY)(in.b * k.s + q);
     nq.at(inst)[i] = -q;
   }
 };
@@ -659,7 +671,7 @@ struct EpiSchurRes {
   Vec<const double> g;
   Vec<const T> y;
   Vec<T> res;
-  __device__ K prep(const InstCoef& C) const { return K{C.e2}; }
+  __device__ K prep(const InstCoef& C, int) const { return K{C.e2}; }
   __device__ In load(int inst, int64_t i) const { return In{g.at(inst)[i], y.at(inst)[i]}; }
   __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
                         const double*, const In& in, const K& k) const {
@@ -678,7 +690,7 @@ struct EpiChebFirst {
   using K = OpK;
   int lev, osc;
   Vec<T> x, r, d;
-  __device__ K prep(const InstCoef& C) const { return op_k(C, lev, 0, osc); }
+  __device__ K prep(const InstCoef& C, int) const { return op_k(C, lev, 0, osc); }
   __device__ In load(int, int64_t) const { return In{}; }
   __device__ void store(int inst, int64_t i, int nb, const double* ms, const double* ks,
                         const double* cen, const In&, const K& k) const {
@@ -708,7 +720,7 @@ struct EpiChebStep {
   using K = OpK;
   int lev, k, osc;
   Vec<T> x, r, dn;
-  __device__ K prep(const InstCoef& C) const { return op_k(C, lev, k, osc); }
+  __device__ K prep(const InstCoef& C, int) const { return op_k(C, lev, k, osc); }
   __device__ In load(int inst, int64_t i) const {
     return In{x.at(inst)[i], r.at(inst)[i]};
   }
@@ -737,7 +749,7 @@ struct EpiChebStart {
   int lev;
   Vec<const T> b;
   Vec<T> r, d;
-  __device__ K prep(const InstCoef& C) const { return op_k(C, lev, -1, CF_ONE); }
+  __device__ K prep(const InstCoef& C, int) const { return op_k(C, lev, -1, CF_ONE); }
   __device__ In load(int inst, int64_t i) const { return In{b.at(inst)[i]}; }
   __device__ void store(int inst, int64_t i, int nb, const double* ms, const double* ks,
                         const double*, const In& in, const K& k) const {
@@ -754,7 +766,7 @@ struct EpiChebOne {
   using K = OpK;
   int lev, osc;
   Vec<T> x;
-  __device__ K prep(const InstCoef& C) const { return op_k(C, lev, -1, osc); }
+  __device__ K prep(const InstCoef& C, int) const { return op_k(C, lev, -1, osc); }
   __device__ In load(int, int64_t) const { return In{}; }
   __device__ void store(int inst, int64_t i, int nb, const double*, const double*,
                         const double* cen, const In&, const K& k) const {
@@ -770,7 +782,7 @@ struct EpiResid {
   int lev;
   Vec<const T> b;
   Vec<T> r;
-  __device__ K prep(const InstCoef& C) const { return op_k(C, lev, -1, CF_ONE); }
+  __device__ K prep(const InstCoef& C, int) const { return op_k(C, lev, -1, CF_ONE); }
   __device__ In load(int inst, int64_t i) const { return In{b.at(inst)[i]}; }
   __device__ void store(int inst, int64_t i, int, const double* ms, const double* ks,
                         const double*, const In& in, const K& k) const {
@@ -1561,8 +1573,9 @@ hipError_t launch_stencil_lin2(const Grid& g, const Batch& B, Vec<const TS> s0, 
 
 template <class T>
 hipError_t launch_couple(const Grid& g, const Batch& B, Vec<const T> z1, Vec<const double> G,
-                         Vec<const double> r2, Vec<T> y, Vec<double> nq, hipStream_t st) {
-  EpiCouple<T> e{G, r2, y, nq};
+                         Vec<const double> r2, Vec<const double> r2s, Vec<T> y, Vec<double> nq,
+                         hipStream_t st) {
+  EpiCouple<T> e{G, r2, r2s, y, nq};
   return run_stencil<false>(g, B, z1, e, st);
 }
 
@@ -1576,28 +1589,29 @@ hipError_t launch_schur_res(const Grid& g, const Batch& B, Vec<const T> a, Vec<c
 
 template <class TB, class T>
 hipError_t launch_cheb_one(const Grid& g, const Batch& B, int lev, int osc, Vec<const TB> b,
-                           Vec<T> x, hipStream_t st) {
+                           Vec<T> x, hipStream_t st, Vec<const double> bs) {
   EpiChebOne<T> e{lev, osc, x};
-  return run_stencil<true>(g, B, b, e, st);
+  return run_stencil<true>(g, B, b, e, st, bs);
 }
 
 template <class TB, class T>
 hipError_t launch_cheb_first(const Grid& g, const Batch& B, int lev, int osc, bool last,
-                             Vec<const TB> b, Vec<T> x, Vec<T> r, Vec<T> d, hipStream_t st) {
+                             Vec<const TB> b, Vec<T> x, Vec<T> r, Vec<T> d, hipStream_t st,
+                             Vec<const double> bs) {
   if (lev < 0) {  // M only: no stiffness partials
     if (last) {
       EpiChebFirst<T, true, true> e{lev, osc, x, r, d};
-      return run_stencil<true>(g, B, b, e, st);
+      return run_stencil<true>(g, B, b, e, st, bs);
     }
     EpiChebFirst<T, false, true> e{lev, osc, x, r, d};
-    return run_stencil<true>(g, B, b, e, st);
+    return run_stencil<true>(g, B, b, e, st, bs);
   }
   if (last) {
     EpiChebFirst<T, true> e{lev, osc, x, r, d};
-    return run_stencil<true>(g, B, b, e, st);
+    return run_stencil<true>(g, B, b, e, st, bs);
   }
   EpiChebFirst<T, false> e{lev, osc, x, r, d};
-  return run_stencil<true>(g, B, b, e, st);
+  return run_stencil<true>(g, B, b, e, st, bs);
 }
 
 template <class T>
@@ -2170,8 +2184,9 @@ template hipError_t launch_schur_res<double>(const Grid&, const Batch&, Vec<cons
                                              Vec<const double>, Vec<const double>,
                                              Vec<const double>, Vec<double>, hipStream_t);
 template hipError_t launch_couple<double>(const Grid&, const Batch&, Vec<const double>,
-                                          Vec<const double>, Vec<const double>, Vec<double>,
-                                          Vec<double>, hipStream_t);
+                                          Vec<const double>, Vec<const double>,
+                                          Vec<const double>, Vec<double>, Vec<double>,
+                                          hipStream_t);
 #else
 template hipError_t launch_stencil_axpy<float, float, float>(const Grid&, const Batch&,
                                                              Vec<const float>, Vec<const float>,
@@ -2191,15 +2206,17 @@ template hipError_t launch_schur_res<float>(const Grid&, const Batch&, Vec<const
                                             Vec<const float>, Vec<const double>, Vec<const float>,
                                             Vec<float>, hipStream_t);
 template hipError_t launch_couple<float>(const Grid&, const Batch&, Vec<const float>,
-                                         Vec<const double>, Vec<const double>, Vec<float>,
-                                         Vec<double>, hipStream_t);
+                                         Vec<const double>, Vec<const double>,
+                                         Vec<const double>, Vec<float>, Vec<double>,
+                                         hipStream_t);
 #endif
 #define OKD_CHEB_TB(TB, T)                                                                    \
   template hipError_t launch_cheb_one<TB, T>(const Grid&, const Batch&, int, int,              \
-                                             Vec<const TB>, Vec<T>, hipStream_t);              \
+                                             Vec<const TB>, Vec<T>, hipStream_t,               \
+                                             Vec<const double>);                               \
   template hipError_t launch_cheb_first<TB, T>(const Grid&, const Batch&, int, int, bool,      \
                                                Vec<const TB>, Vec<T>, Vec<T>, Vec<T>,          \
-                                               hipStream_t);
+                                               hipStream_t, Vec<const double>);
 #define OKD_CHEB_T(T)                                                                         \
   template hipError_t launch_cheb_step<T>(const Grid&, const Batch&, int, int, int, bool,      \
                                           Vec<T>, Vec<T>, Vec<const T>, Vec<T>, hipStream_t);  \

@@ -205,20 +205,25 @@ template <class T>
 hipError_t launch_schur_res(const Grid& g, const Batch& B, Vec<const T> a, Vec<const T> z2,
                             Vec<const double> G, Vec<const T> y, Vec<T> res, hipStream_t st);
 // Preconditioner coupling: q = G - M z1 + eps^2 K z1 (G = 3 int u^2 z1 phi);
-// y = r2 + q, nq = -q.
+// y = r2 + q, nq = -q.  r2s (may be null): the value of r2 is r2s[0] * r2
+// (per instance), rounded before the sum.
 template <class T>
 hipError_t launch_couple(const Grid& g, const Batch& B, Vec<const T> z1, Vec<const double> G,
-                         Vec<const double> r2, Vec<T> y, Vec<double> nq, hipStream_t st);
-// Chebyshev-Jacobi building blocks (Saad, Alg. 12.1):
+                         Vec<const double> r2, Vec<const double> r2s, Vec<T> y, Vec<double> nq,
+                         hipStream_t st);
+// Chebyshev-Jacobi building blocks (Saad, Alg. 12.1).  bs (may be null): the
+// value of b is bs[0] * b (per instance), rounded to TB as it is staged.
 // one iteration from x0 = 0: x = oscale * D^-1 b * it
 template <class TB, class T>
 hipError_t launch_cheb_one(const Grid& g, const Batch& B, int lev, int osc, Vec<const TB> b,
-                           Vec<T> x, hipStream_t st);
+                           Vec<T> x, hipStream_t st,
+                           Vec<const double> bs = Vec<const double>{nullptr, 0});
 // iteration 0 from x0 = 0: d0 = D^-1 b it, r1 = b - A d0, d1 = c1[0] d0 + c2[0] D^-1 r1;
 // writes x = d0, r = r1, d = d1, or (last) x = oscale*(d0 + d1) only.
 template <class TB, class T>
 hipError_t launch_cheb_first(const Grid& g, const Batch& B, int lev, int osc, bool last,
-                             Vec<const TB> b, Vec<T> x, Vec<T> r, Vec<T> d, hipStream_t st);
+                             Vec<const TB> b, Vec<T> x, Vec<T> r, Vec<T> d, hipStream_t st,
+                             Vec<const double> bs = Vec<const double>{nullptr, 0});
 // iteration k: x += d_k, r -= A d_k, d_{k+1} = c1[k] d_k + c2[k] D^-1 r (into dout);
 // last: x = oscale*(x + d_k + d_{k+1}) only.
 template <class T>
@@ -286,18 +291,32 @@ hipError_t launch_mgs_step(const Batch& B, Vec<double> w, Vec<const double> vi,
 // Givens update of Hessenberg column j (column-major, leading dim m+1); an
 // instance whose |g_{j+1}| <= tol or h_{j+1,j} == 0 is marked converged
 // (act = 0, status bit 1); a non-finite value sets status bit 2 and act = 0.
+// sc (may be null): sc[j+1] = 1/h_{j+1,j}, the scale of the unnormalised
+// new basis vector.
 hipError_t launch_givens(const Batch& B, int* act, int j, int m, Vec<double> H, Vec<double> cs,
                          Vec<double> sn, Vec<double> g, Vec<const double> pnorm, int64_t n,
-                         Vec<double> kr, hipStream_t st);
+                         Vec<double> kr, Vec<double> sc, hipStream_t st);
+// Arnoldi projection of w against v_i = sc[i] V_i, i = 0..j, in two passes
+// (modified Gram-Schmidt in inverse compact WY form): the dots <w, V_i> and
+// <V_j, V_i> (partials in pd: 2m rows of red_blocks(n)), row j of L =
+// lower part of V^T V (row-major, (m+1)^2), the triangular solve for the
+// coefficients h (Hcol[i] = h_i, column j of the Hessenberg matrix;
+// hc[i] = h_i sc[i]), then w -= sum hc_i V_i with the partials of <w, w> in
+// pnorm.  V: base of the basis, vector i at V + i*vstride.  m <= 64.
+constexpr int kProjGroup = 16;  // basis vectors per dot pass (2 accumulators each per thread)
+hipError_t launch_proj(const Batch& B, Vec<double> w, Vec<const double> V, int64_t vstride, int j,
+                       int m, int64_t n, Vec<double> pd, Vec<const double> sc, Vec<double> L,
+                       Vec<double> Hcol, Vec<double> hc, Vec<double> pnorm, hipStream_t st);
 // v = w * kr[5]  (normalise the new Arnoldi vector)
 hipError_t launch_scale_by(const Batch& B, Vec<const double> w, Vec<double> v,
                            Vec<const double> kr, int64_t n, hipStream_t st);
 // v = b / nrm[1]
 hipError_t launch_scale_inv(const Batch& B, Vec<const double> b, Vec<double> v,
                             Vec<const double> nrm, int64_t n, hipStream_t st);
-// Start of a cycle: g = [beta, 0, ...], kr[6] = 0 (with beta = nrm[1]).
+// Start of a cycle: g = [beta, 0, ...], kr[6] = 0 (with beta = nrm[1]), and
+// the basis scales sc[0..m] = 1 (sc may be null).
 hipError_t launch_cycle_init(const Batch& B, int m, Vec<double> g, Vec<const double> nrm,
-                             Vec<double> kr, hipStream_t st);
+                             Vec<double> kr, Vec<double> sc, hipStream_t st);
 // y = H(0:k,0:k)^-1 g(0:k) with k = kr[6], then x += sum_j y_j Z_j
 template <class TZ>
 hipError_t launch_lsq_update(const Batch& B, int m, Vec<const double> H, Vec<const double> g,

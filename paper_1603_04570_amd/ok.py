@@ -19,7 +19,7 @@ HIST = 256
 STATUS = {0: "OK_SUCCESS", -1: "OK_E_INVALID", -2: "OK_E_WORKSPACE", -3: "OK_E_HIP",
           -4: "OK_E_GMRES_MAXIT", -5: "OK_E_NEWTON_MAXIT", -6: "OK_E_NONFINITE",
           -7: "OK_E_REJECTED"}
-OK_E_REJECTED = -7
+OK_E_WORKSPACE, OK_E_REJECTED = -2, -7
 
 
 class Params(C.Structure):
@@ -403,6 +403,7 @@ OK_OPT_FUSE_CHEB = 1
 OK_OPT_FUSE_MG = 2
 OK_OPT_ISSUE_AHEAD = 3
 OK_OPT_TRACE_RANGES = 4
+OK_OPT_GRAM_SCHMIDT = 5
 
 
 def set_option(option: int, value: int):
