@@ -141,6 +141,24 @@ int ok_assemble_mesh(const ok_params *p, void *d_ws, size_t ws_bytes, void *stre
 int ok_residual(ok_ctx *ctx, const double *d_u, const double *d_w, const double *d_un,
                 const double *d_wn, double *d_F, double *h_norm, void *stream);
 
+/* ok_residual for callers that cannot allocate device memory or take a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same F and ||F||_2, bit for bit, with no ctx
+ * and no workspace.  Its scratch (constants record, three fields of n
+ * doubles, reduction partials) is a static device array of 64 MiB that each
+ * GPU the library runs on holds until the process ends; it calls no
+ * hipMalloc/hipFree and no allocating library routine.  Sizes whose scratch
+ * exceeds 64 MiB (more than about 2.79M nodes: 3D N > 140, 2D N > 1670) are
+ * rejected with OK_E_WORKSPACE before anything runs; invalid parameters,
+ * null or misaligned pointers give OK_E_INVALID.  *p is validated as by
+ * ok_workspace_bytes (only dim, n and the physical parameters are used).
+ * Calls on one GPU share its scratch: they are serialised by a host lock
+ * and each synchronises its stream before returning; kernels of two calls
+ * that overlapped on one GPU would race.  Arguments as for ok_residual. */
+int ok_residual_noalloc(const ok_params *p, const double *d_u, const double *d_w,
+                        const double *d_un, const double *d_wn, double *d_F, double *h_norm,
+                        void *stream);
+
 /* y = J(u) x, eq. (newton): y1 = (1+dt th sigma) M x1 + dt th K x2,
  * y2 = -eps^2 K x1 - M_E(u) x1 + M x2.  u: n; x, y: 2n (x != y).  Async. */
 int ok_jacobian_apply(ok_ctx *ctx, const double *d_u, const double *d_x, double *d_y,

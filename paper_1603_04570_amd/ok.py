@@ -107,6 +107,7 @@ def load():
     lib.ok_workspace_bytes.argtypes = [P(Params), P(C.c_size_t)]
     lib.ok_assemble_mesh.argtypes = [P(Params), vp, C.c_size_t, vp, P(vp)]
     lib.ok_residual.argtypes = [vp, vp, vp, vp, vp, vp, P(d), vp]
+    lib.ok_residual_noalloc.argtypes = [P(Params), vp, vp, vp, vp, vp, P(d), vp]
     lib.ok_jacobian_apply.argtypes = [vp, vp, vp, vp, vp]
     lib.ok_precond_apply.argtypes = [vp, vp, vp, vp, vp]
     lib.ok_cheb_mass.argtypes = [vp, vp, vp, vp]
@@ -187,6 +188,17 @@ def _stream(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def residual_noalloc(p: Params, u, w, un, wn=None, F=None, stream=None) -> float:
+    """ok_residual_noalloc: F (written into F when given) and ||F||_2 with no
+    context and no workspace (the library's static device scratch)."""
+    nrm = C.c_double()
+    st = load().ok_residual_noalloc(C.byref(p), _ptr(u), _ptr(w), _ptr(un), _ptr(wn), _ptr(F),
+                                    C.byref(nrm), _stream(stream))
+    if st:
+        raise OkError(st, "ok_residual_noalloc")
+    return nrm.value
 
 
 class Problem:
