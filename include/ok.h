@@ -282,8 +282,11 @@ int ok_set_option(int32_t option, int32_t value);
  *     threads of 1, 2 or 4; STENCIL2: 256 threads of 1, 2 or 4; CHEB2,
  *     MG_PRE, MG_POST: 256 threads (3D also 512) of 1 or 2; CHEB2_TILE,
  *     MG_PRE_TILE, MG_POST_TILE (3D only): 256 or 512 threads of 1 or 2
- *     nodes, the tile (about items*threads nodes) chosen by the library.  items = 0 removes the entry (built-in
- *     default shape; threads and zchunks are then ignored);
+ *     nodes, the tile (about items*threads nodes) chosen by the library;
+ *     CHEB2_STRIP, MG_PRE_STRIP, MG_POST_STRIP (3D only): items selects the
+ *     window (1: 32x32 nodes, strips of 4; 2: 32x16, strips of 2; 3: 64x16,
+ *     strips of 4), threads must be 256.  items = 0 removes the entry
+ *     (built-in default shape; threads and zchunks are then ignored);
  *   zchunks: the n+1 planes of the streaming axis are split evenly into
  *     1..n+1 ranges, one block per (plane chunk, range).
  * Every node's arithmetic is the same for every shape, so results are
@@ -299,7 +302,10 @@ enum ok_shape_kernel {
   OK_SHAPE_CHEB2_TILE = 6, /* CHEB2 on rectangular in-plane tiles (3D); while set,
                               the fused pairs of that grid use it */
   OK_SHAPE_MG_PRE_TILE = 7, /* MG_PRE / MG_POST on in-plane tiles (3D); used while */
-  OK_SHAPE_MG_POST_TILE = 8 /* set on a level whose fused smoothers are on */
+  OK_SHAPE_MG_POST_TILE = 8, /* set on a level whose fused smoothers are on */
+  OK_SHAPE_CHEB2_STRIP = 9,  /* CHEB2, MG_PRE, MG_POST on overlapping in-plane windows */
+  OK_SHAPE_MG_PRE_STRIP = 10, /* with a column strip of nodes per thread (3D); used */
+  OK_SHAPE_MG_POST_STRIP = 11 /* while set, before any TILE entry */
 };
 int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precision, int32_t items,
                         int32_t threads, int32_t zchunks);

@@ -1298,6 +1298,8 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
     stencil_tune_set(g.dim, g.nn, kMgPostKey, word, 0, 0);
     stencil_tune_set(g.dim, g.nn, kMgPreTileKey, word, 0, 0);
     stencil_tune_set(g.dim, g.nn, kMgPostTileKey, word, 0, 0);
+    stencil_tune_set(g.dim, g.nn, kMgPreStripKey, word, 0, 0);
+    stencil_tune_set(g.dim, g.nn, kMgPostStripKey, word, 0, 0);
     if (c.shape.mg_pre == 2 && c.shape.mg_post == 2 && mg_fusion_enabled()) {
       Vec<P> bb = (l == 0) ? pvec<P>(c.cr2, nl) : pvec<P>(c.mg[l][1], nl);
       const double unfused = time_best(st, [&]() {
@@ -1359,19 +1361,45 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
           stencil_tune_set(g.dim, g.nn, tkey, word, 0, 0);
           if (ti && tbest < kbest) stencil_tune_set(g.dim, g.nn, tkey, word, ti, tz, tt);
         }
-        fused += ki ? std::min(kbest, tbest) : 1e30;
+        // and on overlapping windows with a column strip per thread (3D)
+        double sbest = 1e30;
+        int si = 0, sz = 0;
+        const int skey = key == kMgPreKey ? kMgPreStripKey : kMgPostStripKey;
+        if (g.dim == 3 && ki) {
+          for (int cfg = 1; cfg <= kStripConfigs; cfg++)
+            for (int zc : zchunk_candidates_n(g, strip_windows(g, cfg), B.count)) {
+              stencil_tune_set(g.dim, g.nn, skey, word, cfg, zc, strip_threads(cfg));
+              double t = time_best(st, [&]() {
+                return key == kMgPreKey
+                           ? launch_mg_pre2<P>(g, B, l, cst(bb), x, r, st)
+                           : launch_mg_post2<P>(g, B, l, cst(bb), cst(x), d1, st);
+              });
+              if (t < sbest) {
+                sbest = t;
+                si = cfg;
+                sz = zc;
+              }
+            }
+          stencil_tune_set(g.dim, g.nn, skey, word, 0, 0);
+          if (si && sbest < std::min(kbest, tbest))
+            stencil_tune_set(g.dim, g.nn, skey, word, si, sz, strip_threads(si));
+        }
+        fused += ki ? std::min(std::min(kbest, tbest), sbest) : 1e30;
       }
       if (!(fused < unfused)) {
         stencil_tune_set(g.dim, g.nn, kMgPreKey, word, 0, 0);
         stencil_tune_set(g.dim, g.nn, kMgPostKey, word, 0, 0);
         stencil_tune_set(g.dim, g.nn, kMgPreTileKey, word, 0, 0);
         stencil_tune_set(g.dim, g.nn, kMgPostTileKey, word, 0, 0);
+        stencil_tune_set(g.dim, g.nn, kMgPreStripKey, word, 0, 0);
+        stencil_tune_set(g.dim, g.nn, kMgPostStripKey, word, 0, 0);
       }
       (*entries)++;
     }
   }
   stencil_tune_set(c.lev[0].dim, c.lev[0].nn, kFusedKey, word, 0, 0);
   stencil_tune_set(c.lev[0].dim, c.lev[0].nn, kFusedTileKey, word, 0, 0);
+  stencil_tune_set(c.lev[0].dim, c.lev[0].nn, kFusedStripKey, word, 0, 0);
   if (cheb_fusion_on(c.lev[0], word)) {  // fused pairs of Chebyshev iterations on M
     const Grid& g = c.lev[0];
     const int64_t nl = g.nodes;
@@ -1422,6 +1450,25 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
         }
       stencil_tune_set(g.dim, g.nn, kFusedTileKey, word, 0, 0);
     }
+    // and on overlapping windows with a column strip per thread (3D)
+    double sbest = 1e30;
+    int si = 0, sz = 0;
+    if (g.dim == 3) {
+      for (int cfg = 1; cfg <= kStripConfigs; cfg++)
+        for (int zc : zchunk_candidates_n(g, strip_windows(g, cfg), B.count)) {
+          stencil_tune_set(g.dim, g.nn, kFusedStripKey, word, cfg, zc, strip_threads(cfg));
+          double t = time_best(st, [&]() {
+            return launch_cheb_step2<P>(g, B, 1, CF_ONE, false, x, cst(r), pvec<P>(c.cr2, nl),
+                                        cst(d0), d1, st);
+          });
+          if (t < sbest) {
+            sbest = t;
+            si = cfg;
+            sz = zc;
+          }
+        }
+      stencil_tune_set(g.dim, g.nn, kFusedStripKey, word, 0, 0);
+    }
     // keep the fusion only where a pair beats two single iterations on M
     const double single = time_best(st, [&]() {
       hipError_t e = launch_cheb_step<P>(g, B, -1, 1, CF_ONE, false, x, r, cst(d0), d1, st);
@@ -1429,8 +1476,10 @@ int autotune_impl(ClassCtx& c, hipStream_t st, int* entries) {
         e = launch_cheb_step<P>(g, B, -1, 2, CF_ONE, false, x, r, cst(d1), d0, st);
       return e;
     });
-    if ((bi && best < single) || (ti && tbest < single)) {
-      if (ti && tbest < best)
+    if ((bi && best < single) || (ti && tbest < single) || (si && sbest < single)) {
+      if (si && sbest < std::min(best, tbest))
+        stencil_tune_set(g.dim, g.nn, kFusedStripKey, word, si, sz, strip_threads(si));
+      else if (ti && tbest < best)
         stencil_tune_set(g.dim, g.nn, kFusedTileKey, word, ti, tz, tt);
     } else {
       stencil_tune_set(g.dim, g.nn, kFusedKey, word, -1, 0);

@@ -1758,6 +1758,52 @@ bool cheb_fusion_on(const Grid& g, int word) {
 }
 #endif  // OKD_STENCIL_PART == 0
 
+#include "k_strip2.h"
+
+#if OKD_STENCIL_PART == 0
+int strip_threads(int cfg) { return (cfg >= 1 && cfg <= kStripCfgs) ? strip_cfg(cfg).nt : 0; }
+int64_t strip_windows(const Grid& g, int cfg) {
+  const StripCfg C = strip_cfg(cfg);
+  return (int64_t)((g.nn + C.bx - 3) / (C.bx - 2)) * ((g.nn + C.by - 3) / (C.by - 2));
+}
+static_assert(kStripCfgs == kStripConfigs, "window configurations");
+#endif
+
+namespace {
+// One launch of k_strip2 in window configuration CFG with the z-ranges of the
+// table entry sh0.
+template <int CFG, class T, int MODE, bool LAST2>
+hipError_t launch_strip_cfg(const Grid& g, const Batch& B, const StencilShape& sh0, int lev,
+                            int kk, int osc, Vec<const T> a, Vec<const T> p, Vec<T> x,
+                            Vec<T> o2, Vec<T> o3, hipStream_t st) {
+  constexpr StripCfg C = strip_cfg(CFG);
+  if (g.dim != 3) return hipErrorInvalidValue;
+  const int ntx = (g.nn + C.bx - 3) / (C.bx - 2), nty = (g.nn + C.by - 3) / (C.by - 2);
+  StencilShape sh = sh0;
+  sh.nchunks = ntx * nty;
+  sh.blocks = sh.nchunks * sh.nzc;
+  const size_t lds = (size_t)2 * (C.bx + 2) * (C.by + 2) * sizeof(double);
+  const int64_t nblk = (int64_t)sh.blocks * B.count;
+  if (nblk > 0x7fffffff || lds > 65536) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_strip2<C.bx, C.by, C.p, T, MODE, LAST2>), dim3((unsigned)nblk),
+                     dim3(C.nt), lds, st, g, sh, ntx, B, lev, kk, osc, a, p, x, o2, o3);
+  return hipGetLastError();
+}
+
+template <class T, int MODE, bool LAST2>
+hipError_t launch_strip(const Grid& g, const Batch& B, int key, int lev, int kk, int osc,
+                        Vec<const T> a, Vec<const T> p, Vec<T> x, Vec<T> o2, Vec<T> o3,
+                        hipStream_t st) {
+  const StencilShape sh = stencil_shape(g, key, (int)sizeof(T));
+  switch (sh.items) {
+    case 1: return launch_strip_cfg<1, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, st);
+    case 2: return launch_strip_cfg<2, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, st);
+    case 3: return launch_strip_cfg<3, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace
+
 namespace {
 template <int NT, int P, class T>
 hipError_t launch_cheb2t_p(const Grid& g, const Batch& B, const StencilShape& sh0, int k,
@@ -1791,6 +1837,14 @@ hipError_t launch_cheb_step2(const Grid& g, const Batch& B, int k, int osc, bool
                              hipStream_t st) {
   if (k < 0 || k + 1 >= kMaxCheb || B.count < 1) return hipErrorInvalidValue;
   if (!last2 && (rout.p == r.p || rout.null())) return hipErrorInvalidValue;
+  if (g.dim == 3 && stencil_tuned(g, kFusedStripKey, (int)sizeof(T))) {  // strips where selected
+    const Vec<const T> din_c{din.p, din.s};
+    if (last2)
+      return launch_strip<T, kStripCheb, true>(g, B, kFusedStripKey, -1, k, osc, din_c, r, x,
+                                               rout, dout, st);
+    return launch_strip<T, kStripCheb, false>(g, B, kFusedStripKey, -1, k, osc, din_c, r, x, rout,
+                                              dout, st);
+  }
   if (g.dim == 3) {  // tiled kernel where the table selects it
     const StencilShape ts = stencil_shape(g, kFusedTileKey, (int)sizeof(T));
     if (stencil_tuned(g, kFusedTileKey, (int)sizeof(T)) && cheb2_shape_ok(3, ts.items, ts.threads)) {
@@ -2101,6 +2155,15 @@ template <class T, bool PRE>
 hipError_t launch_mg2(const Grid& g, const Batch& B, int lev, Vec<const T> a, Vec<const T> b,
                       Vec<T> o1, Vec<T> o2, hipStream_t st) {
   if (lev < 0 || lev >= kMaxLevels || B.count < 1) return hipErrorInvalidValue;
+  const int skey = PRE ? kMgPreStripKey : kMgPostStripKey;
+  if (g.dim == 3 && stencil_tuned(g, skey, (int)sizeof(T))) {  // strips where selected
+    if (PRE)
+      return launch_strip<T, kStripPre, false>(g, B, skey, lev, 0, CF_ONE, a,
+                                               Vec<const T>{nullptr, 0}, o1, o2,
+                                               Vec<T>{nullptr, 0}, st);
+    return launch_strip<T, kStripPost, false>(g, B, skey, lev, 0, CF_ONE, a, b, o1,
+                                              Vec<T>{nullptr, 0}, Vec<T>{nullptr, 0}, st);
+  }
   if (g.dim == 3) {  // tiled kernels where the table selects them
     const int tkey = PRE ? kMgPreTileKey : kMgPostTileKey;
     const StencilShape ts = stencil_shape(g, tkey, (int)sizeof(T));

@@ -1,0 +1,340 @@
+// Fused two-stage streaming kernels of the 3D node stencils on overlapping
+// in-plane windows, one column strip of P nodes per thread.  Included by
+// k_stencil_impl.h (inside namespace okd), after the one-iteration and fused
+// kernels whose arithmetic it repeats.
+//
+// A block owns a BX x BY window of every x-y plane of its z-range.  Windows
+// overlap by two nodes: only the (BX-2) x (BY-2) interior of a window is
+// output, and the window origin of tile (tx, ty) is (tx (BX-2) - 1,
+// ty (BY-2) - 1).  Thread t owns column cx = t % BX and rows cy0 .. cy0+P-1,
+// cy0 = (t / BX) P, of the window, in both stages: stage 1 (the first
+// Chebyshev iteration) runs on the whole window, stage 2 (the second, or the
+// residual) on the interior nodes, which need stage 1 on their one-node
+// ring.  So
+//   * what stage 2 needs from stage 1 at a node stays in the thread's
+//     registers (the tiled kernels pass it through LDS);
+//   * the x-row partials of M1 and K1 along the thread's column are formed
+//     once for the P+2 rows it touches and shared by its P nodes, whose
+//     y-combinations only add them (the tiled kernels form 3 rows per node);
+//   * the boundary masks and pattern coefficients of a node are constants of
+//     the thread for the whole stream; per plane only the z pattern changes.
+// LDS holds the input plane on the window plus a one-node ring (LA; nodes
+// outside the grid +0) and the stage-1 field on the window with a +0 ring
+// (LB).  Each node's arithmetic is that of the one-iteration kernels (same
+// expressions, same rounding points, neighbours outside the grid +0 instead
+// of masked, as in the tiled kernels), so results are bitwise those of the
+// single steps, of k_cheb2/k_cheb2t and of k_mg2/k_mg2t.
+//
+// Modes: kStripCheb (two middle Chebyshev iterations k, k+1 on M, as
+// k_cheb2t), kStripPre (pre-smoothing from x = 0 plus the residual, as
+// k_mg2t<PRE>), kStripPost (post-smoothing from a given x, as
+// k_mg2t<POST>).
+#pragma once
+
+constexpr int kStripCheb = 0, kStripPre = 1, kStripPost = 2;
+
+// Window configurations, selected by the `items` field of a shape-table entry.
+struct StripCfg {
+  int bx, by, p, nt;
+};
+__host__ __device__ constexpr StripCfg strip_cfg(int id) {
+  return id == 1 ? StripCfg{32, 32, 4, 256}
+                 : (id == 2 ? StripCfg{32, 16, 2, 256} : StripCfg{64, 16, 4, 256});
+}
+constexpr int kStripCfgs = 3;
+
+template <int BX, int BY, int P, class T, int MODE, bool LAST2>
+__global__ void __launch_bounds__(BX * BY / P)
+    k_strip2(Grid g, StencilShape sh, int ntx, Batch B, int lev, int kk, int osc,
+             Vec<const T> av, Vec<const T> pv, Vec<T> xv, Vec<T> o2v, Vec<T> o3v) {
+  constexpr int NT = BX * BY / P;
+  constexpr int WA = BX + 2;                        // LDS row pitch (window + ring)
+  constexpr int EA = WA * (BY + 2);                 // LDS words per plane buffer
+  constexpr int KA = (EA + NT - 1) / NT;            // staging slots per thread
+  constexpr bool MASS = (MODE == kStripCheb);       // operator M only
+  constexpr bool SC1 = (MODE == kStripPre);         // stage 1 on the W^-1-scaled input
+  extern __shared__ double lds_raw[];
+  double* LA = lds_raw;
+  double* LB = lds_raw + EA;
+  const int tid = threadIdx.x;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int inst = lb / sh.blocks;
+  if (B.act && !B.act[inst]) return;
+  const int b = lb - inst * sh.blocks;
+  const int tile = b % sh.nchunks;
+  const int zch = b / sh.nchunks;
+  const InstCoef& IC = B.coef[inst];
+  const OpK k1 = MODE == kStripCheb ? op_k(IC, -1, kk, CF_ONE)
+                                    : (MODE == kStripPre ? op_k(IC, lev, 0, CF_ONE)
+                                                         : op_k(IC, lev, -1, CF_ONE));
+  const OpK k2 = MODE == kStripCheb ? op_k(IC, -1, kk + 1, osc)
+                                    : (MODE == kStripPre ? op_k(IC, lev, -1, CF_ONE)
+                                                         : op_k(IC, lev, 0, CF_ONE));
+  const int nn = g.nn, N = g.N;
+  const int64_t plane = g.plane;
+  const int X0 = (tile % ntx) * (BX - 2) - 1, Y0 = (tile / ntx) * (BY - 2) - 1;
+  const T* __restrict__ a = av.at(inst);
+  const T* __restrict__ pw = (MODE == kStripPre) ? nullptr : pv.at(inst);
+  T* __restrict__ xo = xv.at(inst);
+  T* __restrict__ o2 = (MODE == kStripPost || (MODE == kStripCheb && LAST2)) ? nullptr
+                                                                              : o2v.at(inst);
+  T* __restrict__ o3 = (MODE == kStripCheb && !LAST2) ? o3v.at(inst) : nullptr;
+
+  // zero the stage-1 buffer once (its ring is never written; the barrier at
+  // the top of the first trip orders this before any stage-1 write)
+  for (int t = tid; t < EA; t += NT) LB[t] = 0.0;
+
+  // input staging: slot t = tid + NT k holds window node (t % WA - 1, t / WA - 1)
+  int oa[KA];       // in-plane offset of that node, clamped into the grid
+  unsigned va = 0;  // bit k: the node lies in the grid (else the slot holds +0)
+#pragma unroll
+  for (int k = 0; k < KA; k++) {
+    const int t = tid + NT * k;
+    const int gy = Y0 - 1 + t / WA, gx = X0 - 1 + t % WA;
+    if (t < EA && gy >= 0 && gy <= N && gx >= 0 && gx <= N) va |= 1u << k;
+    oa[k] = min(max(gy, 0), N) * nn + min(max(gx, 0), N);
+  }
+  // the thread's strip
+  const int cx = tid % BX, cy0 = (tid / BX) * P;
+  const int gx = X0 + cx, ic = min(max(gx, 0), N);
+  const bool xin = gx >= 0 && gx <= N;
+  const bool ex = (ic == 0 || ic == N);
+  const bool xout = cx >= 1 && cx <= BX - 2 && xin;
+  bool in[P], out[P];
+  bool ey[P];
+  int off[P];     // in-plane offset of node p (clamped)
+  int nbxy[P];    // boundary coordinates of node p in the plane
+#pragma unroll
+  for (int p = 0; p < P; p++) {
+    const int cy = cy0 + p, gy = Y0 + cy, jc = min(max(gy, 0), N);
+    in[p] = xin && gy >= 0 && gy <= N;
+    out[p] = in[p] && xout && cy >= 1 && cy <= BY - 2;
+    ey[p] = (jc == 0 || jc == N);
+    off[p] = jc * nn + ic;
+    nbxy[p] = (int)ex + (int)ey[p];
+  }
+  // stage-1 x-pattern of the scaled input (pre-smoothing)
+  double ax0 = 0, ax1 = 0, ax2 = 0, bx0 = 0, bx1 = 0, bx2 = 0;
+  double ay[P][3], by[P][3];
+  if constexpr (SC1) {
+    pattern<true>(ic, N, ax0, ax1, ax2, bx0, bx1, bx2);
+#pragma unroll
+    for (int p = 0; p < P; p++) {
+      const int jc = min(max(Y0 + cy0 + p, 0), N);
+      pattern<true>(jc, N, ay[p][0], ay[p][1], ay[p][2], by[p][0], by[p][1], by[p][2]);
+    }
+  }
+
+  // in-plane partials of the P nodes of the strip from buffer v (pitch WA;
+  // row r of the strip's column is v[(cy0 + r) * WA + cx + 0..2], r = 0..P+1)
+  auto partials = [&](const double* v, bool scaled, double (&pm)[P], double (&pk)[P],
+                      double (&cen)[P]) {
+    double mr[P + 2], kr[P + 2];
+#pragma unroll
+    for (int r = 0; r < P + 2; r++) {
+      const double* row = v + (cy0 + r) * WA + cx;
+      const double l = row[0], c = row[1], rr = row[2];
+      if (r >= 1 && r <= P) cen[r - 1] = c;
+      if (scaled) {
+        mr[r] = sum3(ax0, ax1, ax2, l, c, rr);
+        kr[r] = MASS ? 0.0 : sum3(bx0, bx1, bx2, l, c, rr);
+      } else {
+        mr[r] = m1_row(true, true, ex, l, c, rr);
+        kr[r] = MASS ? 0.0 : k1_row(true, true, ex, l, c, rr);
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < P; p++) {
+      if (scaled) {
+        pm[p] = sum3(ay[p][0], ay[p][1], ay[p][2], mr[p], mr[p + 1], mr[p + 2]);
+        pk[p] = MASS ? 0.0
+                     : sum3(ay[p][0], ay[p][1], ay[p][2], kr[p], kr[p + 1], kr[p + 2]) +
+                           sum3(by[p][0], by[p][1], by[p][2], mr[p], mr[p + 1], mr[p + 2]);
+      } else {
+        pm[p] = m1_row(true, true, ey[p], mr[p], mr[p + 1], mr[p + 2]);
+        pk[p] = MASS ? 0.0
+                     : m1_row(true, true, ey[p], kr[p], kr[p + 1], kr[p + 2]) +
+                           k1_row(true, true, ey[p], mr[p], mr[p + 1], mr[p + 2]);
+      }
+    }
+  };
+
+  const double h = g.h;
+  const double cmass = h * h * h / 216.0;
+  const double cstiff = h / 36.0;
+  int z0, z1;
+  zrange(sh, nn, zch, z0, z1);
+  const int zlast = min(z1 + 1, N);
+  // stage 1: partials of input planes pz-2, pz-1 and the input at pz-1
+  double pa1[P], pb1[P], qa1[P], qb1[P], cb1[P];
+  // stage 2: partials of stage-1 planes pz-3, pz-2 and the stage-1 field at pz-2
+  double pa2[P], pb2[P], qa2[P], qb2[P], cb2[P];
+  // what stage 2 of plane o needs from stage 1 of plane o (two planes in flight)
+  double ca[P], cbv[P], na[P], nbv[P];
+#pragma unroll
+  for (int p = 0; p < P; p++) {
+    pa1[p] = pb1[p] = qa1[p] = qb1[p] = cb1[p] = 0.0;
+    pa2[p] = pb2[p] = qa2[p] = qb2[p] = cb2[p] = 0.0;
+    ca[p] = cbv[p] = na[p] = nbv[p] = 0.0;
+  }
+  // prefetch registers (raw words from clamped, always in-bounds addresses)
+  T pre_a[KA], pre_p[P], pre_x[P];
+#pragma unroll
+  for (int p = 0; p < P; p++) pre_p[p] = pre_x[p] = T(0);
+  auto issue_a = [&](int z) {
+    const int64_t zo = (int64_t)z * plane;
+#pragma unroll
+    for (int k = 0; k < KA; k++) pre_a[k] = a[zo + oa[k]];
+  };
+  auto issue_p = [&](int zq, int zx) {
+    if constexpr (MODE != kStripPre) {
+      const int64_t zo = (int64_t)zq * plane;
+#pragma unroll
+      for (int p = 0; p < P; p++) pre_p[p] = pw[zo + off[p]];
+    }
+    if constexpr (MODE == kStripCheb) {
+      const int64_t zo = (int64_t)zx * plane;
+#pragma unroll
+      for (int p = 0; p < P; p++) pre_x[p] = xo[zo + off[p]];
+    }
+  };
+  issue_a(max(z0 - 2, 0));
+  issue_p(max(z0 - 1, 0), max(z0, 0));
+  for (int pz = z0 - 2; pz <= z1 + 1; pz++) {
+    const bool insideA = (pz >= 0 && pz <= N);
+    const int q1 = pz - 1;  // stage-1 plane
+    const int o = pz - 2;   // stage-2 (output) plane
+    __syncthreads();
+    if (insideA) {
+#pragma unroll
+      for (int k = 0; k < KA; k++) {
+        const int t = tid + NT * k;
+        if (t < EA) LA[t] = ((va >> k) & 1u) ? to_d(pre_a[k]) : 0.0;
+      }
+    }
+    __syncthreads();
+    T pq[P], xq[P];  // stage-1 pointwise input of plane q1, stage-2 x of plane o
+#pragma unroll
+    for (int p = 0; p < P; p++) {
+      pq[p] = pre_p[p];
+      xq[p] = pre_x[p];
+    }
+    issue_a(max(min(pz + 1, zlast), 0));  // plane -1 is never read
+    issue_p(min(max(q1 + 1, 0), N), min(max(o + 1, 0), N));
+    // stage 1: partials of the input at plane pz on the strip
+    double pn1[P], qn1[P], cn1[P];
+    if (insideA) {
+      partials(LA, SC1, pn1, qn1, cn1);
+    } else {
+#pragma unroll
+      for (int p = 0; p < P; p++) pn1[p] = qn1[p] = cn1[p] = 0.0;
+    }
+    const bool s1 = (q1 >= z0 - 1 && q1 <= z1);
+    if (s1) {
+      const bool inq = (q1 >= 0 && q1 <= N);
+      double az0 = 0, az1 = 0, az2 = 0, bz0 = 0, bz1 = 0, bz2 = 0;
+      if (inq) pattern<SC1>(q1, N, az0, az1, az2, bz0, bz1, bz2);
+      const int nbz = (q1 == 0 || q1 == N);
+#pragma unroll
+      for (int p = 0; p < P; p++) {
+        double f1 = 0.0;
+        na[p] = nbv[p] = 0.0;
+        if (inq && in[p]) {
+          const double ms = cmass * sum3(az0, az1, az2, pa1[p], pb1[p], pn1[p]);
+          const double dv = dinv_at(k1.dinv, nbxy[p] + nbz);
+          if constexpr (MODE == kStripCheb) {
+            const double dk = cb1[p];
+            const double ru = to_d(pq[p]) - op_apply(k1, ms, 0.0);
+            na[p] = to_d((T)ru);
+            nbv[p] = dk;
+            f1 = to_d((T)cheb_dir(k1, dk, dv, ru));
+          } else {
+            const double ks = cstiff * (sum3(az0, az1, az2, qa1[p], qb1[p], qn1[p]) +
+                                        sum3(bz0, bz1, bz2, pa1[p], pb1[p], pn1[p]));
+            if constexpr (MODE == kStripPre) {
+              const double bi = cb1[p];
+              const double ad0 = k1.dinv * k1.it * op_apply(k1, ms, ks);
+              const double d0 = dv * bi * k1.it;
+              const double r1 = bi - ad0;
+              const double d1 = cheb_dir(k1, d0, dv, r1);
+              f1 = to_d((T)(k1.osc * (d0 + d1)));
+              na[p] = bi;
+            } else {
+              const double r0 = to_d(pq[p]) - op_apply(k1, ms, ks);
+              f1 = to_d((T)(dv * r0 * k1.it));
+              na[p] = to_d((T)r0);
+              nbv[p] = cb1[p];
+            }
+          }
+        }
+        LB[(cy0 + p + 1) * WA + cx + 1] = f1;
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < P; p++) {
+      pa1[p] = pb1[p];
+      pb1[p] = pn1[p];
+      qa1[p] = qb1[p];
+      qb1[p] = qn1[p];
+      cb1[p] = cn1[p];
+    }
+    __syncthreads();
+    // stage 2: partials of the stage-1 field at plane q1; finish plane o
+    if (s1) {
+      double pn2[P], qn2[P], cn2[P];
+      partials(LB, false, pn2, qn2, cn2);
+      if (o >= z0 && o < z1) {
+        double az0, az1, az2, bz0, bz1, bz2;
+        pattern<false>(o, N, az0, az1, az2, bz0, bz1, bz2);
+        const int nbz = (o == 0 || o == N);
+        const int64_t zo = (int64_t)o * plane;
+#pragma unroll
+        for (int p = 0; p < P; p++) {
+          if (!out[p]) continue;
+          const double ms = cmass * sum3(az0, az1, az2, pa2[p], pb2[p], pn2[p]);
+          const int64_t idx = zo + off[p];
+          if constexpr (MODE == kStripCheb) {
+            const double d1 = cb2[p];
+            const double rv1 = ca[p], dk = cbv[p];
+            const double dv = dinv_at(k2.dinv, nbxy[p] + nbz);
+            const double xv1 = to_d((T)(to_d(xq[p]) + dk));
+            const double xv2 = xv1 + d1;
+            const double rv2 = rv1 - op_apply(k2, ms, 0.0);
+            const double d2 = cheb_dir(k2, d1, dv, rv2);
+            if (LAST2) {
+              xo[idx] = (T)(k2.osc * (xv2 + d2));
+            } else {
+              xo[idx] = (T)xv2;
+              o2[idx] = (T)rv2;
+              o3[idx] = (T)d2;
+            }
+          } else {
+            const double ks = cstiff * (sum3(az0, az1, az2, qa2[p], qb2[p], qn2[p]) +
+                                        sum3(bz0, bz1, bz2, pa2[p], pb2[p], pn2[p]));
+            if constexpr (MODE == kStripPre) {
+              xo[idx] = (T)cb2[p];
+              o2[idx] = (T)(ca[p] - op_apply(k2, ms, ks));
+            } else {
+              const double dk = cb2[p];
+              const double dv = dinv_at(k2.dinv, nbxy[p] + nbz);
+              const double xv = cbv[p] + dk;
+              const double rv = ca[p] - op_apply(k2, ms, ks);
+              const double d1 = cheb_dir(k2, dk, dv, rv);
+              xo[idx] = (T)(k2.osc * (xv + d1));
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < P; p++) {
+        pa2[p] = pb2[p];
+        pb2[p] = pn2[p];
+        qa2[p] = qb2[p];
+        qb2[p] = qn2[p];
+        cb2[p] = cn2[p];
+        ca[p] = na[p];
+        cbv[p] = nbv[p];
+      }
+    }
+  }
+}

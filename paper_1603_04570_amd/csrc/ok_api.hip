@@ -343,6 +343,9 @@ int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precisio
     case OK_SHAPE_CHEB2_TILE: nf = kFusedTileKey; break;
     case OK_SHAPE_MG_PRE_TILE: nf = kMgPreTileKey; break;
     case OK_SHAPE_MG_POST_TILE: nf = kMgPostTileKey; break;
+    case OK_SHAPE_CHEB2_STRIP: nf = kFusedStripKey; break;
+    case OK_SHAPE_MG_PRE_STRIP: nf = kMgPreStripKey; break;
+    case OK_SHAPE_MG_POST_STRIP: nf = kMgPostStripKey; break;
     default: return OK_E_INVALID;
   }
   const int word = precision == OK_MIXED ? 4 : 8;
@@ -351,8 +354,10 @@ int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precisio
     return OK_SUCCESS;
   }
   TileGeom tg;
+  const bool strip = (nf == kFusedStripKey || nf == kMgPreStripKey || nf == kMgPostStripKey);
   const bool ok_shape =
-      (nf == kFusedTileKey || nf == kMgPreTileKey || nf == kMgPostTileKey)
+      strip ? (dim == 3 && strip_threads(items) > 0 && strip_threads(items) == threads)
+      : (nf == kFusedTileKey || nf == kMgPreTileKey || nf == kMgPostTileKey)
           ? cheb2_tile_geom(make_grid(dim, n), threads, items, tg)
       : (nf >= kFusedKey)   ? cheb2_shape_ok(dim, items, threads)
                             : stencil_shape_ok(dim, nf, items, threads);

@@ -133,6 +133,17 @@ constexpr int kMgPreKey = 18, kMgPostKey = 19;
 constexpr int kFusedTileKey = 20;
 // Keys of the fused multigrid smoothers on in-plane tiles (3D), used where set.
 constexpr int kMgPreTileKey = 21, kMgPostTileKey = 22;
+// Keys of the fused kernels on overlapping in-plane windows with one column
+// strip of nodes per thread (3D): Chebyshev pairs on M, multigrid pre- and
+// post-smoothing; the entry's items field selects the window configuration
+// (1..kStripCfgs), threads must be that configuration's.  Used where set (the
+// multigrid ones on levels whose fused smoothers are on).
+constexpr int kFusedStripKey = 23, kMgPreStripKey = 24, kMgPostStripKey = 25;
+// Threads of window configuration `cfg` (0 if there is none), and its
+// windows per plane of grid g.
+int strip_threads(int cfg);
+int64_t strip_windows(const Grid& g, int cfg);
+constexpr int kStripConfigs = 3;
 // In-plane tile of that kernel: tx x ty nodes, ntx tiles per row of tiles.
 struct TileGeom {
   int tx, ty, ntx, nty;

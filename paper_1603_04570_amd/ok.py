@@ -428,6 +428,7 @@ def set_option(option: int, value: int):
 OK_SHAPE_STENCIL, OK_SHAPE_STENCIL2, OK_SHAPE_CHEB2, OK_SHAPE_MG_PRE, OK_SHAPE_MG_POST = 1, 2, 3, 4, 5
 OK_SHAPE_CHEB2_TILE = 6
 OK_SHAPE_MG_PRE_TILE, OK_SHAPE_MG_POST_TILE = 7, 8
+OK_SHAPE_CHEB2_STRIP, OK_SHAPE_MG_PRE_STRIP, OK_SHAPE_MG_POST_STRIP = 9, 10, 11
 
 
 def set_launch_shape(dim: int, n: int, kernel: int, precision: int, items: int,

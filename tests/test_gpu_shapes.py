@@ -15,6 +15,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
+STRIP_CFGS = (1, 2, 3)  # window configurations of the strip kernels (32x32/4, 32x16/2, 64x16/4)
+
+
 def cheb_mass(P, r, nodes):
     x = torch.empty(nodes, dtype=torch.float64, device="cuda")
     P.cheb_mass(r, x)
@@ -54,6 +57,14 @@ def test_fused_chebyshev_shapes_bitwise(dim, n, precision):
                     assert np.array_equal(cheb_mass(P, r, nodes), ref), (items, threads, zch)
         finally:
             ok.set_launch_shape(dim, n, ok.OK_SHAPE_CHEB2_TILE, precision, 0)
+        try:  # and on overlapping windows with a column strip per thread
+            for cfg in STRIP_CFGS:
+                for zch in (1, 3, 7, n + 1):
+                    print("strip shape", n, precision, cfg, zch, flush=True)
+                    ok.set_launch_shape(dim, n, ok.OK_SHAPE_CHEB2_STRIP, precision, cfg, 256, zch)
+                    assert np.array_equal(cheb_mass(P, r, nodes), ref), (cfg, zch)
+        finally:
+            ok.set_launch_shape(dim, n, ok.OK_SHAPE_CHEB2_STRIP, precision, 0)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -177,6 +188,53 @@ def test_mg_smoother_tile_shapes_bitwise(precision, n):
             assert got[2] == ref[2]
             assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), \
                 (items, threads, zch)
+    finally:
+        for lev_n in (n, n // 2):
+            for kern in kinds:
+                ok.set_launch_shape(dim, lev_n, kern, precision, 0)
+
+
+@pytest.mark.parametrize("n", [64, 100])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mg_smoother_strip_shapes_bitwise(precision, n):
+    """The fused multigrid smoothers on overlapping windows with a column strip
+    per thread (3D), pinned on the two finest levels of a 64^3 timestep and of
+    the N = 100 mesh for every window configuration and several z-splits:
+    results equal the one-iteration kernels bit for bit."""
+    from paper_1603_04570_amd import ok
+    dim = 3
+    p = ok.default_params(dim=dim, n=n, eps=0.02, sigma=100.0, m=0.1, dt=2e-4,
+                          precision=precision)
+    u0, w0 = noise_state(dim, n, 0.1, 41)
+
+    def once():
+        P = ok.Problem(p)
+        u = torch.from_numpy(u0).cuda()
+        w = torch.from_numpy(w0).cuda()
+        st = P.timestep(u, w, 1)
+        return u.cpu().numpy(), w.cpu().numpy(), st.its()
+
+    ok.set_option(ok.OK_OPT_FUSE_MG, 0)
+    try:
+        ref = once()
+    finally:
+        ok.set_option(ok.OK_OPT_FUSE_MG, 1)
+    kinds = (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST, ok.OK_SHAPE_MG_PRE_STRIP,
+             ok.OK_SHAPE_MG_POST_STRIP)
+    try:
+        for cfg, zch in [(1, 1), (2, 5), (3, 3), (1, 65), (2, 2), (3, 101)]:
+            print("mg strip shape", precision, n, cfg, zch, flush=True)
+            for lev_n in (n, n // 2):
+                # a row-run entry switches the fused smoothers on; the strip entry selects strips
+                for kern in (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST):
+                    ok.set_launch_shape(dim, lev_n, kern, precision, 1, 256, 1)
+                for kern in (ok.OK_SHAPE_MG_PRE_STRIP, ok.OK_SHAPE_MG_POST_STRIP):
+                    ok.set_launch_shape(dim, lev_n, kern, precision, cfg, 256,
+                                        min(zch, lev_n + 1))
+            got = once()
+            assert got[2] == ref[2]
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), \
+                (cfg, zch)
     finally:
         for lev_n in (n, n // 2):
             for kern in kinds:

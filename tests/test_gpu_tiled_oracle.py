@@ -1,8 +1,9 @@
 """Elementwise oracle parity of the kernels the autotuner picks at full size.
 
 The tiled fused Chebyshev pair on M (k_cheb2t) and the tiled fused multigrid
-smoothers (k_mg2t, pre-smoothing + residual and post-smoothing) are pinned
-on every grid of a 3D 64^3 hierarchy (64, 32, 16, 8 elements per direction)
+smoothers (k_mg2t, pre-smoothing + residual and post-smoothing), and the
+same on overlapping windows with a column strip per thread (k_strip2), are
+pinned on every grid of a 3D 64^3 hierarchy (64, 32, 16, 8 elements per direction)
 and two timesteps of the 3D 128^3 parameters are run through them, against
 the FP64 CPU oracle on the same seeded input (Newton on eq. (newton) of
 Sec. 2, FGMRES with the block preconditioner of eq. (prec)):
@@ -83,6 +84,31 @@ def test_tiled_kernels_timestep_matches_oracle(precision, items, threads):
         for ln in levels:
             for kern in (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST, ok.OK_SHAPE_MG_PRE_TILE,
                          ok.OK_SHAPE_MG_POST_TILE):
+                ok.set_launch_shape(DIM, ln, kern, precision, 0)
+    compare(got, oracle_run(), precision)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_strip_kernels_timestep_matches_oracle(precision, cfg):
+    """The same with the fused pairs and smoothers on overlapping windows with
+    a column strip per thread (window configuration cfg)."""
+    from paper_1603_04570_amd import ok
+    levels = [N >> k for k in range(4)]
+    print("strip kernels vs oracle", precision, cfg, flush=True)
+    try:
+        ok.set_launch_shape(DIM, N, ok.OK_SHAPE_CHEB2_STRIP, precision, cfg, 256, 5)
+        for ln in levels:
+            for kern in (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST):  # fused smoothers on
+                ok.set_launch_shape(DIM, ln, kern, precision, 1, 256, 1)
+            for kern in (ok.OK_SHAPE_MG_PRE_STRIP, ok.OK_SHAPE_MG_POST_STRIP):
+                ok.set_launch_shape(DIM, ln, kern, precision, cfg, 256, min(3, ln + 1))
+        got = gpu_run(precision)
+    finally:
+        ok.set_launch_shape(DIM, N, ok.OK_SHAPE_CHEB2_STRIP, precision, 0)
+        for ln in levels:
+            for kern in (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST, ok.OK_SHAPE_MG_PRE_STRIP,
+                         ok.OK_SHAPE_MG_POST_STRIP):
                 ok.set_launch_shape(DIM, ln, kern, precision, 0)
     compare(got, oracle_run(), precision)
 
