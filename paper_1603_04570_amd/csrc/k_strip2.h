@@ -87,12 +87,17 @@ __global__ void __launch_bounds__(BX * BY / P)
   // input staging: slot t = tid + NT k holds window node (t % WA - 1, t / WA - 1)
   int oa[KA];       // in-plane offset of that node, clamped into the grid
   unsigned va = 0;  // bit k: the node lies in the grid (else the slot holds +0)
+  // pre-smoothing stages its input scaled by 2^(boundary coordinates of the
+  // node), an exact power of two: the unscaled stencil of the scaled input is
+  // then, rounding for rounding, the W^-1-scaled stencil of the input
+  double fsl[KA];
 #pragma unroll
   for (int k = 0; k < KA; k++) {
     const int t = tid + NT * k;
     const int gy = Y0 - 1 + t / WA, gx = X0 - 1 + t % WA;
     if (t < EA && gy >= 0 && gy <= N && gx >= 0 && gx <= N) va |= 1u << k;
     oa[k] = min(max(gy, 0), N) * nn + min(max(gx, 0), N);
+    fsl[k] = (double)(1 << ((gx == 0 || gx == N) + (gy == 0 || gy == N)));
   }
   // the thread's strip
   const int cx = tid % BX, cy0 = (tid / BX) * P;
@@ -102,8 +107,9 @@ __global__ void __launch_bounds__(BX * BY / P)
   const bool xout = cx >= 1 && cx <= BX - 2 && xin;
   bool in[P], out[P];
   bool ey[P];
-  int off[P];     // in-plane offset of node p (clamped)
-  int nbxy[P];    // boundary coordinates of node p in the plane
+  int off[P];      // in-plane offset of node p (clamped)
+  int nbxy[P];     // boundary coordinates of node p in the plane
+  double dvxy[P];  // stage-1 D^-1 without the z factor: dinv 2^nbxy (exact)
 #pragma unroll
   for (int p = 0; p < P; p++) {
     const int cy = cy0 + p, gy = Y0 + cy, jc = min(max(gy, 0), N);
@@ -112,59 +118,54 @@ __global__ void __launch_bounds__(BX * BY / P)
     ey[p] = (jc == 0 || jc == N);
     off[p] = jc * nn + ic;
     nbxy[p] = (int)ex + (int)ey[p];
-  }
-  // stage-1 x-pattern of the scaled input (pre-smoothing)
-  double ax0 = 0, ax1 = 0, ax2 = 0, bx0 = 0, bx1 = 0, bx2 = 0;
-  double ay[P][3], by[P][3];
-  if constexpr (SC1) {
-    pattern<true>(ic, N, ax0, ax1, ax2, bx0, bx1, bx2);
-#pragma unroll
-    for (int p = 0; p < P; p++) {
-      const int jc = min(max(Y0 + cy0 + p, 0), N);
-      pattern<true>(jc, N, ay[p][0], ay[p][1], ay[p][2], by[p][0], by[p][1], by[p][2]);
-    }
+    dvxy[p] = dinv_at(k1.dinv, nbxy[p]);
   }
 
   // in-plane partials of the P nodes of the strip from buffer v (pitch WA;
-  // row r of the strip's column is v[(cy0 + r) * WA + cx + 0..2], r = 0..P+1)
-  auto partials = [&](const double* v, bool scaled, double (&pm)[P], double (&pk)[P],
-                      double (&cen)[P]) {
+  // row r of the strip's column is v[(cy0 + r) * WA + cx + 0..2], r = 0..P+1):
+  // the arithmetic of mk_partials with +0 outside the grid
+  auto partials = [&](const double* v, double (&pm)[P], double (&pk)[P], double (&cen)[P]) {
     double mr[P + 2], kr[P + 2];
 #pragma unroll
     for (int r = 0; r < P + 2; r++) {
       const double* row = v + (cy0 + r) * WA + cx;
       const double l = row[0], c = row[1], rr = row[2];
       if (r >= 1 && r <= P) cen[r - 1] = c;
-      if (scaled) {
-        mr[r] = sum3(ax0, ax1, ax2, l, c, rr);
-        kr[r] = MASS ? 0.0 : sum3(bx0, bx1, bx2, l, c, rr);
-      } else {
-        mr[r] = m1_row(true, true, ex, l, c, rr);
-        kr[r] = MASS ? 0.0 : k1_row(true, true, ex, l, c, rr);
-      }
+      mr[r] = m1_row(true, true, ex, l, c, rr);
+      kr[r] = MASS ? 0.0 : k1_row(true, true, ex, l, c, rr);
     }
 #pragma unroll
     for (int p = 0; p < P; p++) {
-      if (scaled) {
-        pm[p] = sum3(ay[p][0], ay[p][1], ay[p][2], mr[p], mr[p + 1], mr[p + 2]);
-        pk[p] = MASS ? 0.0
-                     : sum3(ay[p][0], ay[p][1], ay[p][2], kr[p], kr[p + 1], kr[p + 2]) +
-                           sum3(by[p][0], by[p][1], by[p][2], mr[p], mr[p + 1], mr[p + 2]);
-      } else {
-        pm[p] = m1_row(true, true, ey[p], mr[p], mr[p + 1], mr[p + 2]);
-        pk[p] = MASS ? 0.0
-                     : m1_row(true, true, ey[p], kr[p], kr[p + 1], kr[p + 2]) +
-                           k1_row(true, true, ey[p], mr[p], mr[p + 1], mr[p + 2]);
-      }
+      pm[p] = m1_row(true, true, ey[p], mr[p], mr[p + 1], mr[p + 2]);
+      pk[p] = MASS ? 0.0
+                   : m1_row(true, true, ey[p], kr[p], kr[p + 1], kr[p + 2]) +
+                         k1_row(true, true, ey[p], mr[p], mr[p + 1], mr[p + 2]);
     }
   };
-
   const double h = g.h;
   const double cmass = h * h * h / 216.0;
   const double cstiff = h / 36.0;
+  // z-combination of the partials of planes z-1, z, z+1 at a node: the
+  // expressions of the one-iteration kernels with the pattern of plane z;
+  // inside the grid the pattern is [1, 4, 1] / [-1, 2, -1], and
+  // sum3(1, 4, 1, a, b, n) = fma(4, b, a) + n, sum3(-1, 2, -1, a, b, n) =
+  // fma(2, b, -a) - n exactly (the unit products are exact)
+  auto zcomb = [&](bool zin, const double (&az)[3], const double (&bz)[3], double pa, double pb,
+                   double pn, double qa, double qb, double qn, double& ms, double& ks) {
+    if (zin) {
+      ms = cmass * (fma(4.0, pb, pa) + pn);
+      if (!MASS) ks = cstiff * ((fma(4.0, qb, qa) + qn) + (fma(2.0, pb, -pa) - pn));
+    } else {
+      ms = cmass * sum3(az[0], az[1], az[2], pa, pb, pn);
+      if (!MASS)
+        ks = cstiff * (sum3(az[0], az[1], az[2], qa, qb, qn) + sum3(bz[0], bz[1], bz[2], pa, pb, pn));
+    }
+  };
+
   int z0, z1;
   zrange(sh, nn, zch, z0, z1);
   const int zlast = min(z1 + 1, N);
+  const int pl = (int)plane;  // a grid of one instance has fewer than 2^31 nodes
   // stage 1: partials of input planes pz-2, pz-1 and the input at pz-1
   double pa1[P], pb1[P], qa1[P], qb1[P], cb1[P];
   // stage 2: partials of stage-1 planes pz-3, pz-2 and the stage-1 field at pz-2
@@ -182,18 +183,18 @@ __global__ void __launch_bounds__(BX * BY / P)
 #pragma unroll
   for (int p = 0; p < P; p++) pre_p[p] = pre_x[p] = T(0);
   auto issue_a = [&](int z) {
-    const int64_t zo = (int64_t)z * plane;
+    const int zo = z * pl;
 #pragma unroll
     for (int k = 0; k < KA; k++) pre_a[k] = a[zo + oa[k]];
   };
   auto issue_p = [&](int zq, int zx) {
     if constexpr (MODE != kStripPre) {
-      const int64_t zo = (int64_t)zq * plane;
+      const int zo = zq * pl;
 #pragma unroll
       for (int p = 0; p < P; p++) pre_p[p] = pw[zo + off[p]];
     }
     if constexpr (MODE == kStripCheb) {
-      const int64_t zo = (int64_t)zx * plane;
+      const int zo = zx * pl;
 #pragma unroll
       for (int p = 0; p < P; p++) pre_x[p] = xo[zo + off[p]];
     }
@@ -206,10 +207,13 @@ __global__ void __launch_bounds__(BX * BY / P)
     const int o = pz - 2;   // stage-2 (output) plane
     __syncthreads();
     if (insideA) {
+      const double fz = (SC1 && (pz == 0 || pz == N)) ? 2.0 : 1.0;
 #pragma unroll
       for (int k = 0; k < KA; k++) {
         const int t = tid + NT * k;
-        if (t < EA) LA[t] = ((va >> k) & 1u) ? to_d(pre_a[k]) : 0.0;
+        double v = ((va >> k) & 1u) ? to_d(pre_a[k]) : 0.0;
+        if (SC1) v = v * fsl[k] * fz;
+        if (t < EA) LA[t] = v;
       }
     }
     __syncthreads();
@@ -224,7 +228,7 @@ __global__ void __launch_bounds__(BX * BY / P)
     // stage 1: partials of the input at plane pz on the strip
     double pn1[P], qn1[P], cn1[P];
     if (insideA) {
-      partials(LA, SC1, pn1, qn1, cn1);
+      partials(LA, pn1, qn1, cn1);
     } else {
 #pragma unroll
       for (int p = 0; p < P; p++) pn1[p] = qn1[p] = cn1[p] = 0.0;
@@ -232,39 +236,40 @@ __global__ void __launch_bounds__(BX * BY / P)
     const bool s1 = (q1 >= z0 - 1 && q1 <= z1);
     if (s1) {
       const bool inq = (q1 >= 0 && q1 <= N);
-      double az0 = 0, az1 = 0, az2 = 0, bz0 = 0, bz1 = 0, bz2 = 0;
-      if (inq) pattern<SC1>(q1, N, az0, az1, az2, bz0, bz1, bz2);
+      const bool zin = (q1 > 0 && q1 < N);
+      double az[3] = {0, 0, 0}, bz[3] = {0, 0, 0};
+      if (inq) pattern<false>(q1, N, az[0], az[1], az[2], bz[0], bz[1], bz[2]);
       const int nbz = (q1 == 0 || q1 == N);
+      const double fz = nbz ? 2.0 : 1.0, fzi = nbz ? 0.5 : 1.0;
 #pragma unroll
       for (int p = 0; p < P; p++) {
         double f1 = 0.0;
         na[p] = nbv[p] = 0.0;
         if (inq && in[p]) {
-          const double ms = cmass * sum3(az0, az1, az2, pa1[p], pb1[p], pn1[p]);
-          const double dv = dinv_at(k1.dinv, nbxy[p] + nbz);
+          double ms, ks = 0.0;
+          zcomb(zin, az, bz, pa1[p], pb1[p], pn1[p], qa1[p], qb1[p], qn1[p], ms, ks);
+          const double dv = dvxy[p] * fz;  // dinv_at(dinv, nbxy + nbz), exactly
           if constexpr (MODE == kStripCheb) {
             const double dk = cb1[p];
             const double ru = to_d(pq[p]) - op_apply(k1, ms, 0.0);
             na[p] = to_d((T)ru);
             nbv[p] = dk;
             f1 = to_d((T)cheb_dir(k1, dk, dv, ru));
+          } else if constexpr (MODE == kStripPre) {
+            // the staged input is b 2^nb: d0 = (dv b) it = (dinv (b 2^nb)) it
+            const double bs = cb1[p];
+            const double bi = bs * (fzi / (double)(1 << nbxy[p]));
+            const double ad0 = k1.dinv * k1.it * op_apply(k1, ms, ks);
+            const double d0 = k1.dinv * bs * k1.it;
+            const double r1 = bi - ad0;
+            const double d1 = cheb_dir(k1, d0, dv, r1);
+            f1 = to_d((T)(k1.osc * (d0 + d1)));
+            na[p] = bi;
           } else {
-            const double ks = cstiff * (sum3(az0, az1, az2, qa1[p], qb1[p], qn1[p]) +
-                                        sum3(bz0, bz1, bz2, pa1[p], pb1[p], pn1[p]));
-            if constexpr (MODE == kStripPre) {
-              const double bi = cb1[p];
-              const double ad0 = k1.dinv * k1.it * op_apply(k1, ms, ks);
-              const double d0 = dv * bi * k1.it;
-              const double r1 = bi - ad0;
-              const double d1 = cheb_dir(k1, d0, dv, r1);
-              f1 = to_d((T)(k1.osc * (d0 + d1)));
-              na[p] = bi;
-            } else {
-              const double r0 = to_d(pq[p]) - op_apply(k1, ms, ks);
-              f1 = to_d((T)(dv * r0 * k1.it));
-              na[p] = to_d((T)r0);
-              nbv[p] = cb1[p];
-            }
+            const double r0 = to_d(pq[p]) - op_apply(k1, ms, ks);
+            f1 = to_d((T)(dv * r0 * k1.it));
+            na[p] = to_d((T)r0);
+            nbv[p] = cb1[p];
           }
         }
         LB[(cy0 + p + 1) * WA + cx + 1] = f1;
@@ -282,21 +287,23 @@ __global__ void __launch_bounds__(BX * BY / P)
     // stage 2: partials of the stage-1 field at plane q1; finish plane o
     if (s1) {
       double pn2[P], qn2[P], cn2[P];
-      partials(LB, false, pn2, qn2, cn2);
+      partials(LB, pn2, qn2, cn2);
       if (o >= z0 && o < z1) {
-        double az0, az1, az2, bz0, bz1, bz2;
-        pattern<false>(o, N, az0, az1, az2, bz0, bz1, bz2);
-        const int nbz = (o == 0 || o == N);
-        const int64_t zo = (int64_t)o * plane;
+        double az[3], bz[3];
+        pattern<false>(o, N, az[0], az[1], az[2], bz[0], bz[1], bz[2]);
+        const bool zin = (o > 0 && o < N);
+        const double fz = (o == 0 || o == N) ? 2.0 : 1.0;
+        const int zo = o * pl;
 #pragma unroll
         for (int p = 0; p < P; p++) {
           if (!out[p]) continue;
-          const double ms = cmass * sum3(az0, az1, az2, pa2[p], pb2[p], pn2[p]);
-          const int64_t idx = zo + off[p];
+          double ms, ks = 0.0;
+          zcomb(zin, az, bz, pa2[p], pb2[p], pn2[p], qa2[p], qb2[p], qn2[p], ms, ks);
+          const int idx = zo + off[p];
           if constexpr (MODE == kStripCheb) {
             const double d1 = cb2[p];
             const double rv1 = ca[p], dk = cbv[p];
-            const double dv = dinv_at(k2.dinv, nbxy[p] + nbz);
+            const double dv = dvxy[p] * fz;  // both iterations use M's diagonal
             const double xv1 = to_d((T)(to_d(xq[p]) + dk));
             const double xv2 = xv1 + d1;
             const double rv2 = rv1 - op_apply(k2, ms, 0.0);
@@ -308,20 +315,16 @@ __global__ void __launch_bounds__(BX * BY / P)
               o2[idx] = (T)rv2;
               o3[idx] = (T)d2;
             }
+          } else if constexpr (MODE == kStripPre) {
+            xo[idx] = (T)cb2[p];
+            o2[idx] = (T)(ca[p] - op_apply(k2, ms, ks));
           } else {
-            const double ks = cstiff * (sum3(az0, az1, az2, qa2[p], qb2[p], qn2[p]) +
-                                        sum3(bz0, bz1, bz2, pa2[p], pb2[p], pn2[p]));
-            if constexpr (MODE == kStripPre) {
-              xo[idx] = (T)cb2[p];
-              o2[idx] = (T)(ca[p] - op_apply(k2, ms, ks));
-            } else {
-              const double dk = cb2[p];
-              const double dv = dinv_at(k2.dinv, nbxy[p] + nbz);
-              const double xv = cbv[p] + dk;
-              const double rv = ca[p] - op_apply(k2, ms, ks);
-              const double d1 = cheb_dir(k2, dk, dv, rv);
-              xo[idx] = (T)(k2.osc * (xv + d1));
-            }
+            const double dk = cb2[p];
+            const double dv = dvxy[p] * fz;  // both iterations on the same level
+            const double xv = cbv[p] + dk;
+            const double rv = ca[p] - op_apply(k2, ms, ks);
+            const double d1 = cheb_dir(k2, dk, dv, rv);
+            xo[idx] = (T)(k2.osc * (xv + d1));
           }
         }
       }
