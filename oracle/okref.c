@@ -996,19 +996,145 @@ int okref_fgmres(okref *h, const double *u, const double *b, double *x, int32_t 
 }
 
 /* ------------------------------------------------------------------------ */
+/* The symmetric rearranged system (Sec. 2, after (schurapprox)) and MINRES */
+/* ------------------------------------------------------------------------ */
+
+/* Row 1 of (newton) divided by 1 + dt th sigma, unknowns in the order
+ * [dw; du]:  y1 = c K x1 + M x2,  y2 = M x1 - eps^2 K x2 - M_E x2. */
+static void sym_apply_assembled(okref *h, const double *x, double *y) {
+  const okref_params *p = &h->p;
+  int64_t n = h->lev[0].nodes;
+  double *t = (double *)malloc(sizeof(double) * n);
+  csr_mv(h->K, x, y);
+  csr_mv(h->M, x + n, t);
+  for (int64_t i = 0; i < n; i++) y[i] = h->c * y[i] + t[i];
+  csr_mv(h->M, x, y + n);
+  csr_mv(h->K, x + n, t);
+  for (int64_t i = 0; i < n; i++) y[n + i] -= p->eps * p->eps * t[i];
+  csr_mv(h->ME, x + n, t);
+  for (int64_t i = 0; i < n; i++) y[n + i] -= t[i];
+  free(t);
+}
+
+int okref_sym_apply(okref *h, const double *u, const double *x, double *y) {
+  ensure_ME(h, u);
+  sym_apply_assembled(h, x, y);
+  return OKREF_OK;
+}
+
+/* Block-diagonal preconditioner of the symmetric system.  The singular
+ * (1,1)-block c K is replaced by the positive definite (c/alpha) S^ =
+ * c K + (sqrt(c)/eps) M; with M_E dropped, the Schur complement of that block,
+ * eps^2 K + M ((c/alpha) S^)^-1 M, is approximated by S^ ((c/alpha) S^)^-1 S^
+ * = (alpha/c) S^.  Both blocks are applied with the V-cycle of S^. */
+static void sym_precond_assembled(okref *h, const double *r, double *z) {
+  int64_t n = h->lev[0].nodes;
+  okref_mg(h, r, z, h->p.mg_cycles);
+  okref_mg(h, r + n, z + n, h->p.mg_cycles);
+  for (int64_t i = 0; i < n; i++) {
+    z[i] *= h->alpha / h->c;
+    z[n + i] *= h->c / h->alpha;
+  }
+}
+
+int okref_sym_precond(okref *h, const double *r, double *z) {
+  sym_precond_assembled(h, r, z);
+  return OKREF_OK;
+}
+
+/* Preconditioned MINRES (Paige and Saunders 1975) for a symmetric matrix
+ * with a symmetric positive definite preconditioner P, in the three-term
+ * Lanczos form in which P^-1 is applied once per iteration (Elman, Silvester
+ * and Wathen, Finite Elements and Fast Iterative Solvers, 2nd ed., Alg. 4.1):
+ * v_{j+1} = A z_j - (delta_j/gamma_j) v_j - (gamma_j/gamma_{j-1}) v_{j-1},
+ * z_{j+1} = P^-1 v_{j+1}, gamma_{j+1} = <z_{j+1}, v_{j+1}>^(1/2), with z_j
+ * scaled to unit P-norm; the QR factorisation of the tridiagonal Lanczos
+ * matrix by Givens rotations (c, s) gives the update direction w_{j+1} and
+ * the P^-1-norm of the residual, |eta|.  x0 = 0. */
+static int minres_assembled(okref *h, const double *b, double *x, int32_t *its_out) {
+  const okref_params *p = &h->p;
+  int64_t n2 = 2 * h->lev[0].nodes;
+  const int maxit = p->gmres_restart * (p->gmres_max_restarts + 1);
+  double *v0 = (double *)calloc(n2, sizeof(double));
+  double *v1 = (double *)malloc(sizeof(double) * n2);
+  double *v2 = (double *)malloc(sizeof(double) * n2);
+  double *z1 = (double *)malloc(sizeof(double) * n2);
+  double *z2 = (double *)malloc(sizeof(double) * n2);
+  double *az = (double *)malloc(sizeof(double) * n2);
+  double *w0 = (double *)calloc(n2, sizeof(double));
+  double *w1 = (double *)calloc(n2, sizeof(double));
+  double *w2 = (double *)malloc(sizeof(double) * n2);
+  int status = OKREF_E_GMRES_MAXIT, its = 0;
+  memset(x, 0, sizeof(double) * n2);
+  memcpy(v1, b, sizeof(double) * n2);
+  sym_precond_assembled(h, v1, z1);
+  double gam1 = sqrt(dot(z1, v1, n2));
+  if (!isfinite(gam1)) { status = OKREF_E_NONFINITE; goto done; }
+  if (gam1 == 0.0) { status = OKREF_OK; goto done; }
+  {
+    double gam0 = 1.0, gam = gam1, eta = gam1;
+    double s0 = 0.0, s = 0.0, c0 = 1.0, cc = 1.0;
+    const double tol = p->gmres_rtol * gam1;
+    for (int j = 1; j <= maxit; j++) {
+      for (int64_t i = 0; i < n2; i++) z1[i] /= gam;
+      sym_apply_assembled(h, z1, az);
+      double delta = dot(az, z1, n2);
+      for (int64_t i = 0; i < n2; i++) v2[i] = az[i] - (delta / gam) * v1[i] - (gam / gam0) * v0[i];
+      sym_precond_assembled(h, v2, z2);
+      double gnew = sqrt(dot(z2, v2, n2));
+      double a0 = cc * delta - c0 * s * gam;
+      double a1 = sqrt(a0 * a0 + gnew * gnew);
+      double a2 = s * delta + c0 * cc * gam;
+      double a3 = s0 * gam;
+      double cn = a0 / a1, sn = gnew / a1;
+      for (int64_t i = 0; i < n2; i++) w2[i] = (z1[i] - a3 * w0[i] - a2 * w1[i]) / a1;
+      for (int64_t i = 0; i < n2; i++) x[i] += cn * eta * w2[i];
+      eta = -sn * eta;
+      its = j;
+      if (!isfinite(eta) || !isfinite(gnew)) { status = OKREF_E_NONFINITE; break; }
+      if (fabs(eta) <= tol || gnew == 0.0) { status = OKREF_OK; break; }
+      /* shift: (v0, v1) <- (v1, v2), z1 <- z2, (w0, w1) <- (w1, w2) */
+      double *t = v0; v0 = v1; v1 = v2; v2 = t;
+      t = z1; z1 = z2; z2 = t;
+      t = w0; w0 = w1; w1 = w2; w2 = t;
+      gam0 = gam; gam = gnew;
+      c0 = cc; cc = cn; s0 = s; s = sn;
+    }
+  }
+done:
+  if (its_out) *its_out = its;
+  free(v0); free(v1); free(v2); free(z1); free(z2); free(az); free(w0); free(w1); free(w2);
+  return status;
+}
+
+int okref_minres(okref *h, const double *u, const double *b, double *x, int32_t *its) {
+  ensure_ME(h, u);
+  return minres_assembled(h, b, x, its);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Newton and the timestep loop (Sec. 2: one linear solve per Newton step)  */
 /* ------------------------------------------------------------------------ */
 
-/* Solve J(u) dx = -F with FGMRES and take the full step (u,w) += dx.  F is
- * overwritten. */
+/* Solve J(u) dx = -F (FGMRES on (newton), or MINRES on its symmetric
+ * rearrangement) and take the full step (u,w) += dx.  F is overwritten. */
 static int newton_update(okref *h, double *u, double *w, double *F, int32_t *its) {
   int64_t n = h->lev[0].nodes;
   double *dx = (double *)malloc(sizeof(double) * 2 * n);
   for (int64_t i = 0; i < 2 * n; i++) F[i] = -F[i];
   ensure_ME(h, u);
-  int st = fgmres_assembled(h, F, dx, its);
-  if (st != OKREF_E_NONFINITE)
-    for (int64_t i = 0; i < n; i++) { u[i] += dx[i]; w[i] += dx[n + i]; }
+  int st;
+  if (h->p.linear_solver == 1) {
+    /* [f1/(1+dt th sigma); f2] for the unknowns [dw; du] */
+    for (int64_t i = 0; i < n; i++) F[i] /= h->sA;
+    st = minres_assembled(h, F, dx, its);
+    if (st != OKREF_E_NONFINITE)
+      for (int64_t i = 0; i < n; i++) { w[i] += dx[i]; u[i] += dx[n + i]; }
+  } else {
+    st = fgmres_assembled(h, F, dx, its);
+    if (st != OKREF_E_NONFINITE)
+      for (int64_t i = 0; i < n; i++) { u[i] += dx[i]; w[i] += dx[n + i]; }
+  }
   free(dx);
   return st;
 }

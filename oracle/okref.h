@@ -27,6 +27,8 @@ typedef struct {
   double gmres_rtol, newton_atol;
   int32_t newton_max_it, cheb_A_its;
   int32_t schur_richardson, mg_levels, mg_pre, mg_post, mg_cycles;
+  int32_t linear_solver;                  /* 0: FGMRES on (newton); 1: MINRES on the
+                                             symmetric rearranged system (Sec. 2)   */
 } okref_params;
 
 #define OKREF_HIST 256
@@ -72,6 +74,17 @@ int okref_newton_step(okref *h, double *u, double *w, const double *un, const do
 int okref_newton_solve(okref *h, double *u, double *w, const double *un, const double *wn,
                        okref_info *info);
 int okref_timestep(okref *h, double *u, double *w, int32_t nsteps, okref_info *info);
+
+/* The symmetric rearrangement of (newton) (Sec. 2, after (schurapprox)):
+ *   [c K, M; M, -eps^2 K - M_E(u)] [dw; du] = [f1/(1+dt th sigma); f2],
+ * x, y: [w-block; u-block] (2n).  Its block-diagonal preconditioner
+ * z = diag((alpha/c) S^^-1, (c/alpha) S^^-1) r with S^ = M + alpha K, alpha =
+ * eps sqrt(c), each S^^-1 mg_cycles V-cycles; and preconditioned MINRES
+ * (x0 = 0; stop when the preconditioned residual norm falls to gmres_rtol of
+ * its initial value; at most gmres_restart*(gmres_max_restarts+1) its). */
+int okref_sym_apply(okref *h, const double *u, const double *x, double *y);
+int okref_sym_precond(okref *h, const double *r, double *z);
+int okref_minres(okref *h, const double *u, const double *b, double *x, int32_t *its);
 
 /* Matrix-free local evaluation at selected nodes (no assembly): the residual
  * rows F_i and Jacobian rows (J x)_i, for sampled checks at sizes where CSR

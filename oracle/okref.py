@@ -24,7 +24,8 @@ class OracleParams(C.Structure):
                 ("gmres_rtol", C.c_double), ("newton_atol", C.c_double),
                 ("newton_max_it", C.c_int32), ("cheb_A_its", C.c_int32),
                 ("schur_richardson", C.c_int32), ("mg_levels", C.c_int32),
-                ("mg_pre", C.c_int32), ("mg_post", C.c_int32), ("mg_cycles", C.c_int32)]
+                ("mg_pre", C.c_int32), ("mg_post", C.c_int32), ("mg_cycles", C.c_int32),
+                ("linear_solver", C.c_int32)]
 
 
 class OracleInfo(C.Structure):
@@ -70,6 +71,9 @@ def _load():
     lib.okref_newton_step.argtypes = [C.c_void_p, d, d, d, d, d, P(C.c_int32)]
     lib.okref_newton_solve.argtypes = [C.c_void_p, d, d, d, d, P(OracleInfo)]
     lib.okref_timestep.argtypes = [C.c_void_p, d, d, C.c_int32, P(OracleInfo)]
+    lib.okref_sym_apply.argtypes = [C.c_void_p, d, d, d]
+    lib.okref_sym_precond.argtypes = [C.c_void_p, d, d]
+    lib.okref_minres.argtypes = [C.c_void_p, d, d, d, P(C.c_int32)]
     lib.okref_local_residual.argtypes = [P(OracleParams), d, d, d, d, P(C.c_int64), C.c_int64, d]
     lib.okref_local_jacobian.argtypes = [P(OracleParams), d, d, P(C.c_int64), C.c_int64, d]
     _lib = lib
@@ -85,10 +89,11 @@ def _dp(a):
 
 def make_params(dim, n, eps, sigma, m, dt, theta=1.0, gmres_restart=30, gmres_max_restarts=10,
                 gmres_rtol=1e-8, newton_atol=1e-10, newton_max_it=25, cheb_A_its=10,
-                schur_richardson=1, mg_levels=0, mg_pre=2, mg_post=2, mg_cycles=1):
+                schur_richardson=1, mg_levels=0, mg_pre=2, mg_post=2, mg_cycles=1,
+                linear_solver=0):
     return OracleParams(dim, n, eps, sigma, m, dt, theta, gmres_restart, gmres_max_restarts,
                         gmres_rtol, newton_atol, newton_max_it, cheb_A_its, schur_richardson,
-                        mg_levels, mg_pre, mg_post, mg_cycles)
+                        mg_levels, mg_pre, mg_post, mg_cycles, linear_solver)
 
 
 class Oracle:
@@ -198,6 +203,23 @@ class Oracle:
         x = np.zeros(2 * self.nodes)
         its = C.c_int32()
         st = self.lib.okref_fgmres(self.h, _dp(u), _dp(b), _dp(x), C.byref(its))
+        return x, its.value, st
+
+    def sym_apply(self, u, x):
+        """The symmetric rearranged operator on x = [dw; du]."""
+        y = np.zeros(2 * self.nodes)
+        self.lib.okref_sym_apply(self.h, _dp(u), _dp(x), _dp(y))
+        return y
+
+    def sym_precond(self, r):
+        z = np.zeros(2 * self.nodes)
+        self.lib.okref_sym_precond(self.h, _dp(r), _dp(z))
+        return z
+
+    def minres(self, u, b):
+        x = np.zeros(2 * self.nodes)
+        its = C.c_int32()
+        st = self.lib.okref_minres(self.h, _dp(u), _dp(b), _dp(x), C.byref(its))
         return x, its.value, st
 
     def newton_step(self, u, w, un, wn=None):

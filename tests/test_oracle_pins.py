@@ -527,3 +527,115 @@ def test_multigrid_cg_coarse_converges_to_exact_solve():
     x = o.mg(b, 25)
     ref = fr.fast_diag_solve(dim, n, alpha, b)
     assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-10
+
+
+# ----------------------------------------------------------------------------
+# The symmetric rearrangement of (newton) (Sec. 2, after (schurapprox)):
+# [c K, M; M, -eps^2 K - M_E] [dw; du] = [f1/(1 + dt th sigma); f2]
+# ----------------------------------------------------------------------------
+def _sym_dense(dim, n, u, p):
+    """The rearranged matrix from independent blocks: Kronecker M and K and a
+    brute-force 5-point-quadrature M_E(u)."""
+    M, K = fr.mass(dim, n), fr.stiffness(dim, n)
+    ME, _ = fr.brute_element_integrals(dim, n, u)
+    dth = p["dt"] * p.get("theta", 1.0)
+    c = dth / (1 + dth * p["sigma"])
+    return np.block([[c * K, M], [M, -p["eps"] ** 2 * K - ME]]), M, K, ME, c
+
+
+@pytest.mark.parametrize("dim,n", [(2, 6), (3, 3)])
+def test_symmetric_operator_is_the_rearranged_jacobian(dim, n):
+    """The oracle's symmetric operator equals the rearranged matrix built from
+    independent blocks, is symmetric, and solving it gives the solution of
+    eq. (newton) (dense LU of both)."""
+    o = Oracle(dim, n, **CFG1, mg_levels=1)
+    u = uniform01(31, o.nodes) - 0.5
+    S, M, K, ME, c = _sym_dense(dim, n, u, CFG1)
+    nn = o.nodes
+    cols = np.stack([o.sym_apply(u, e) for e in np.eye(2 * nn)], axis=1)
+    assert np.abs(cols - S).max() <= 1e-13 * np.abs(S).max()
+    assert np.abs(cols - cols.T).max() <= 1e-13 * np.abs(cols).max()
+    # equivalence with eq. (newton): J [du; dw] = f  <=>  S [dw; du] = [f1/sA; f2]
+    sA = 1 + CFG1["dt"] * CFG1["sigma"]
+    J = np.block([[sA * M, CFG1["dt"] * K], [-CFG1["eps"] ** 2 * K - ME, M]])
+    f = uniform01(32, 2 * nn) - 0.5
+    du_dw = np.linalg.solve(J, f)
+    dw_du = np.linalg.solve(S, np.concatenate([f[:nn] / sA, f[nn:]]))
+    assert rel(np.concatenate([dw_du[nn:], dw_du[:nn]]), du_dw) < 1e-12
+
+
+@pytest.mark.parametrize("dim,n", [(2, 16), (3, 8)])
+def test_minres_matches_dense_lu(dim, n):
+    """Preconditioned MINRES at rtol 1e-13 equals dense LU of the rearranged
+    system (independent blocks)."""
+    o = Oracle(dim, n, **CFG1, gmres_rtol=1e-13, gmres_max_restarts=20)
+    u = 0.3 * (uniform01(33, o.nodes) - 0.5)
+    S, *_ = _sym_dense(dim, n, u, CFG1)
+    b = uniform01(34, 2 * o.nodes) - 0.5
+    x, its, st = o.minres(u, b)
+    assert st == 0 and its > 2
+    assert rel(x, np.linalg.solve(S, b)) < 1e-10
+
+
+def test_symmetric_preconditioner_blocks_and_spectrum():
+    """The block-diagonal preconditioner diag((alpha/c) S^^-1, (c/alpha) S^^-1)
+    with converged V-cycles equals the exact DCT-basis inverse of
+    S^ = M + eps sqrt(c) K, and at u = 1/sqrt(3) (M_E = 0) the preconditioned
+    rearranged matrix has exactly the eigenvalues +-sqrt(1 + x^2)/(1 + x),
+    x = eps sqrt(c) lambda_k over the DCT-I modes, all in [-1, -1/sqrt(2)] U
+    [1/sqrt(2), 1] whatever h, eps and dt."""
+    dim, n = 2, 8
+    o = Oracle(dim, n, **CFG1, mg_cycles=60)
+    dth = CFG1["dt"]
+    c = dth / (1 + dth * CFG1["sigma"])
+    alpha = CFG1["eps"] * np.sqrt(c)
+    nn = o.nodes
+    r = uniform01(35, 2 * nn) - 0.5
+    z = o.sym_precond(r)
+    exact = np.concatenate([(alpha / c) * fr.fast_diag_solve(dim, n, alpha, r[:nn]),
+                            (c / alpha) * fr.fast_diag_solve(dim, n, alpha, r[nn:])])
+    assert rel(z, exact) < 1e-10
+    u = np.full(nn, 1.0 / np.sqrt(3.0))
+    S, M, K, ME, _ = _sym_dense(dim, n, u, CFG1)
+    assert np.abs(ME).max() < 1e-12
+    Sh = M + alpha * K
+    Pinv = np.block([[(alpha / c) * np.linalg.inv(Sh), np.zeros((nn, nn))],
+                     [np.zeros((nn, nn)), (c / alpha) * np.linalg.inv(Sh)]])
+    ev = np.linalg.eigvals(Pinv @ S)
+    assert np.abs(ev.imag).max() < 1e-10
+    lam = np.array([fr.gen_eig_1d(n, kx) + fr.gen_eig_1d(n, ky)
+                    for ky in range(n + 1) for kx in range(n + 1)])
+    x = alpha * lam
+    pred = np.concatenate([np.sqrt(1 + x ** 2) / (1 + x), -np.sqrt(1 + x ** 2) / (1 + x)])
+    assert np.abs(np.sort(ev.real) - np.sort(pred)).max() < 1e-10
+    assert np.abs(ev.real).min() >= 1 / np.sqrt(2) - 1e-12 and np.abs(ev.real).max() <= 1 + 1e-12
+
+
+@pytest.mark.parametrize("dim,n", [(2, 16), (3, 8)])
+def test_minres_newton_timestep_matches_fgmres(dim, n):
+    """Newton with MINRES on the rearranged system reaches the same timestep
+    as Newton with FGMRES on eq. (newton): both stop at ||F|| <= 1e-10."""
+    cfg = dict(eps=0.02, sigma=100.0, m=0.1, dt=2e-4)
+    u0, w0 = noise_state(dim, n, 0.1, 3)
+    um, wm, im, sm = Oracle(dim, n, **cfg, linear_solver=1).timestep(u0, w0, 2)
+    uf, wf, i_f, sf = Oracle(dim, n, **cfg).timestep(u0, w0, 2)
+    assert sm == 0 and sf == 0
+    assert im.newton_its == i_f.newton_its
+    assert rel(um, uf) < 1e-10 and rel(wm, wf) < 1e-10
+
+
+def test_minres_iterations_flat_under_refinement():
+    """The preconditioned spectrum does not depend on h, so the MINRES counts
+    stay flat as the mesh is refined (2D, N = 16 ... 128)."""
+    cfg = dict(eps=0.02, sigma=100.0, m=0.1, dt=2e-4)
+    counts = []
+    for n in (16, 32, 64, 128):
+        o = Oracle(2, n, **cfg, linear_solver=1)
+        u, w = noise_state(2, n, 0.1, 3)
+        F, _ = o.residual(u, w, u)
+        nn = o.nodes
+        b = np.concatenate([-F[:nn] / (1 + cfg["dt"] * cfg["sigma"]), -F[nn:]])
+        x, its, st = o.minres(u, b)
+        assert st == 0
+        counts.append(its)
+    assert max(counts) <= 1.3 * min(counts), counts
