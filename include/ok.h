@@ -92,7 +92,26 @@ typedef struct {
   int32_t mg_levels;       /* 0 = automatic                                      */
   int32_t mg_pre, mg_post; /* Chebyshev smoothing iterations, >= 1 (2, 2)        */
   int32_t mg_cycles;       /* V-cycles per S^^-1 application, >= 1 (1)           */
+  int32_t linear_solver;   /* Newton's linear solver (OK_SOLVER_FGMRES)           */
 } ok_params;
+
+/* Newton's linear solver.
+ *   OK_SOLVER_FGMRES: FGMRES(m) on eq. (newton) with the block preconditioner
+ *     of eq. (prec) (the paper's method).
+ *   OK_SOLVER_MINRES: preconditioned MINRES on the symmetric rearrangement of
+ *     (newton) that Sec. 2 notes after (schurapprox),
+ *       [c K, M; M, -eps^2 K - M_E(u)] [dw; du] = [f1/(1+dt th sigma); f2],
+ *     with the block-diagonal preconditioner diag((alpha/c) S^^-1,
+ *     (c/alpha) S^^-1), S^ = M + alpha K, alpha = eps sqrt(c): the singular
+ *     (1,1)-block c K is replaced by (c/alpha) S^ = c K + (sqrt(c)/eps) M and
+ *     the Schur complement of that block (M_E dropped) by S^ ((c/alpha)
+ *     S^)^-1 S^ = (alpha/c) S^; for M_E = 0 the preconditioned spectrum is
+ *     +-sqrt(1+x^2)/(1+x), x = alpha lambda, inside +-[1/sqrt(2), 1].  Stops
+ *     when the preconditioned residual norm falls to gmres_rtol of its
+ *     initial value, after at most gmres_restart*(gmres_max_restarts+1)
+ *     iterations.  FP64 only (precision must be OK_FP64). */
+#define OK_SOLVER_FGMRES 0
+#define OK_SOLVER_MINRES 1
 
 typedef struct {
   int32_t status;          /* result of this Newton iteration's linear solve    */
@@ -164,6 +183,17 @@ int ok_residual_noalloc(const ok_params *p, const double *d_u, const double *d_w
 int ok_jacobian_apply(ok_ctx *ctx, const double *d_u, const double *d_x, double *d_y,
                       void *stream);
 
+/* The symmetric rearranged system (OK_SOLVER_MINRES above): y = A_sym x with
+ * x, y in the order [w-block; u-block] (2n each, x != y); and its solution by
+ * preconditioned MINRES from x = 0 (b, x in the same order; *its receives
+ * the iterations).  ok_minres synchronises; it returns OK_E_GMRES_MAXIT when
+ * the iteration limit is reached first (x then holds the last iterate).
+ * Both require precision OK_FP64; ok_minres also needs a context created with
+ * linear_solver = OK_SOLVER_MINRES (its work vectors), else OK_E_INVALID. */
+int ok_sym_apply(ok_ctx *ctx, const double *d_u, const double *d_x, double *d_y, void *stream);
+int ok_minres(ok_ctx *ctx, const double *d_u, const double *d_b, double *d_x, int32_t *its,
+              void *stream);
+
 /* z = P^-1 r, eq. (prec) with the matching Schur approximation (schurinv):
  *   z1 = Chebyshev_M(r1) / (1 + dt th sigma)
  *   y  = r2 + eps^2 K z1 + M_E(u) z1                (= r2 - C z1)
@@ -184,7 +214,8 @@ int ok_mg_apply(ok_ctx *ctx, const double *d_b, double *d_x, int32_t cycles, voi
 int ok_fgmres(ok_ctx *ctx, const double *d_u, const double *d_b, double *d_x, int32_t *its,
               void *stream);
 
-/* ONE Newton iteration in place: F(u,w), then J dx = -F by FGMRES, then
+/* ONE Newton iteration in place: F(u,w), then J dx = -F by the context's
+ * linear solver (FGMRES, or MINRES on the symmetric rearrangement), then
  * (u,w) += dx.  un, wn: previous time level (wn may be NULL if theta == 1).
  * info (may be NULL) is filled.  Synchronises. */
 int ok_newton_step(ok_ctx *ctx, double *d_u, double *d_w, const double *d_un,

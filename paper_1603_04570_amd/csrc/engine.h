@@ -63,6 +63,7 @@ struct ClassCtx {
   ok_params shape{};  // dim, n, precision, solver counts (physics per instance below)
   int B = 0;          // instances
   int dim = 0, L = 0, m = 0;
+  int nv = 0;         // vectors of 2n per instance in V (FGMRES basis or MINRES work)
   bool mixed = false;
   size_t psz = 8;  // bytes per preconditioner word
   int64_t n = 0;   // finest nodes per instance
@@ -81,6 +82,7 @@ struct ClassCtx {
   // ((m+1)^2), update coefficients (m+1), dot partials (2m rows of
   // red_blocks(2n))
   double *sc = nullptr, *Lm = nullptr, *hcf = nullptr, *pd = nullptr;
+  double* mr = nullptr;  // MINRES scalars (MR_COUNT per instance)
   void *Z = nullptr, *zt = nullptr;
   void *cr = nullptr, *cda = nullptr, *cdb = nullptr, *yv = nullptr, *tv = nullptr, *sv = nullptr;
   void* cr2 = nullptr;  // second Chebyshev residual (fused iterations ping-pong r)
@@ -143,6 +145,26 @@ int residual_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const dou
 // until ||rhs - M w|| <= 1e-15 ||rhs|| (at most 8 rounds of 32 iterations).
 // Single instance (B = 1); rounds: restarts used.
 int initial_w_d(ClassCtx& c, Vec<const double> u, Vec<double> w, int* rounds, hipStream_t st);
+// y = A_sym x for the symmetric rearrangement of eq. (newton)'s system,
+// x = [dw; du] (2n per instance, FP64 class only):
+//   y1 = c K x1 + M x2,  y2 = M x1 - eps^2 K x2 - M_E(u) x2
+int sym_apply_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const double> x,
+                Vec<double> y, hipStream_t st);
+// Preconditioned MINRES on the symmetric system for the instances with
+// h_part set (FP64 class), from x = 0.  newton: b is the right-hand side of
+// eq. (newton) in its row order, scaled here to [b1/(1 + dt th sigma); b2],
+// and x is returned in the order [du; dw]; otherwise b and x are in the
+// symmetric system's order [dw; du].  Results per instance in out[]
+// (fgmres_its: MINRES iterations; lin_res: final preconditioned residual
+// norm relative to the initial one).
+int minres_class(ClassCtx& c, Vec<const double> u, Vec<const double> b, Vec<double> x,
+                 bool newton, hipStream_t st);
+// Newton's linear solve J x = b on every class of the group, each with its
+// class's solver (FGMRES classes in lockstep, MINRES classes one after
+// another); x in the order [du; dw].
+int newton_solve_group(const Group& grp, const std::vector<Vec<const double>>& u,
+                       const std::vector<Vec<const double>>& b, const std::vector<Vec<double>>& x,
+                       hipStream_t st);
 // Solve J x = b by FGMRES for the instances with part[i] set (host masks in
 // h_part of each class).  Results per instance in out[].
 int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,

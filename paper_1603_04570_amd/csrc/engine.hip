@@ -159,6 +159,7 @@ void inst_coef(InstCoef& C, const ok_params& p, const Grid* lev, int L) {
   C.sA = 1.0 + C.dth * p.sigma;
   C.inv_sA = 1.0 / C.sA;
   const double cc = C.dth / C.sA;
+  C.c = cc;
   C.alpha = p.eps * std::sqrt(cc);
   C.e2 = p.eps * p.eps;
   C.dt = p.dt;
@@ -186,7 +187,7 @@ void carve(ClassCtx& c, char* base, bool with_state, size_t* total) {
   c.part = cv.take<int>(B);
   c.incyc = cv.take<int>(B);
   c.aux = cv.take<int>(B);
-  c.V = cv.take<double>((size_t)B * (m + 1) * n2);
+  c.V = cv.take<double>((size_t)B * c.nv * n2);
   c.Z = cv.take<char>((size_t)B * m * n2 * ps);
   c.X = cv.take<double>((size_t)B * n2);
   c.Bv = cv.take<double>((size_t)B * n2);
@@ -224,6 +225,7 @@ void carve(ClassCtx& c, char* base, bool with_state, size_t* total) {
   c.Lm = cv.take<double>((size_t)B * (m + 1) * (m + 1));
   c.hcf = cv.take<double>((size_t)B * (m + 1));
   c.pd = cv.take<double>((size_t)B * 2 * m * red_blocks(n2));
+  c.mr = cv.take<double>((size_t)B * MR_COUNT);
   *total = (cv.off + 255) & ~(size_t)255;
 }
 
@@ -233,6 +235,8 @@ void setup_shape(ClassCtx& c, const ok_params& shape, int B) {
   c.dim = shape.dim;
   c.L = levels_for(&shape);
   c.m = shape.gmres_restart;
+  // MINRES keeps nine work vectors of 2n (three each of v, z and w) in V
+  c.nv = shape.linear_solver == OK_SOLVER_MINRES ? std::max(c.m + 1, 9) : c.m + 1;
   c.mixed = (shape.precision == OK_MIXED);
   c.psz = c.mixed ? sizeof(float) : sizeof(double);
   int nl = shape.n;
@@ -246,7 +250,7 @@ void setup_shape(ClassCtx& c, const ok_params& shape, int B) {
 // ---------------------------------------------------------------------------
 // Strides of the SoA arrays.
 // ---------------------------------------------------------------------------
-inline int64_t sV(const ClassCtx& c) { return (int64_t)(c.m + 1) * c.n2(); }
+inline int64_t sV(const ClassCtx& c) { return (int64_t)c.nv * c.n2(); }
 inline int64_t sZ(const ClassCtx& c) { return (int64_t)c.m * c.n2(); }
 inline int64_t sH(const ClassCtx& c) { return (int64_t)(c.m + 1) * c.m; }
 inline int64_t sM(const ClassCtx& c) { return (int64_t)c.m + 1; }
@@ -678,6 +682,10 @@ int validate_params(const ok_params* p, std::string& why) {
   if (p->schur_richardson < 1) return bad("schur_richardson >= 1");
   if (p->mg_pre < 1 || p->mg_post < 1 || p->mg_cycles < 1) return bad("mg_pre/post/cycles >= 1");
   if (p->mg_pre > kMaxCheb || p->mg_post > kMaxCheb) return bad("mg_pre/post <= 32");
+  if (p->linear_solver != OK_SOLVER_FGMRES && p->linear_solver != OK_SOLVER_MINRES)
+    return bad("linear_solver must be OK_SOLVER_FGMRES or OK_SOLVER_MINRES");
+  if (p->linear_solver == OK_SOLVER_MINRES && p->precision != OK_FP64)
+    return bad("OK_SOLVER_MINRES requires precision OK_FP64");
   int L = levels_for(p);
   if (L < 1 || L > kMaxLevels) return bad("bad mg_levels");
   if (p->n % (1 << (L - 1))) return bad("n not divisible by 2^(levels-1)");
@@ -691,7 +699,8 @@ bool same_class(const ok_params& a, const ok_params& b) {
          a.gmres_restart == b.gmres_restart && a.gmres_max_restarts == b.gmres_max_restarts &&
          a.newton_max_it == b.newton_max_it && a.cheb_A_its == b.cheb_A_its &&
          a.schur_richardson == b.schur_richardson && levels_for(&a) == levels_for(&b) &&
-         a.mg_pre == b.mg_pre && a.mg_post == b.mg_post && a.mg_cycles == b.mg_cycles;
+         a.mg_pre == b.mg_pre && a.mg_post == b.mg_post && a.mg_cycles == b.mg_cycles &&
+         a.linear_solver == b.linear_solver;
 }
 
 size_t class_bytes(const ok_params& shape, int B, bool with_state) {
@@ -1108,6 +1117,153 @@ int fgmres_group(const Group& grp, const std::vector<Vec<const double>>& u,
 }
 
 // ---------------------------------------------------------------------------
+// The symmetric rearranged system (Sec. 2, after eq. (schurapprox)) and
+// preconditioned MINRES on it
+// ---------------------------------------------------------------------------
+int sym_apply_d(ClassCtx& c, const int* flags, Vec<const double> u, Vec<const double> x,
+                Vec<double> y, hipStream_t st) {
+  if (c.mixed) return set_err(c.err, OK_E_INVALID, "the symmetric system is FP64 only");
+  const Grid& g = c.lev[0];
+  const Batch B = c.batch(flags);
+  const int64_t n = c.n;
+  Vec<double> G = vec(c.G, n);
+  {
+    ProfScope ps(c, OK_K_ELEMENT, (double)n * c.B * 24.0, st);
+    OKE(c, launch_element<double, double>(g, B, 0, u, off(x, n), Vec<const double>{nullptr, 0},
+                                          -3.0, 0.0, G, st));
+  }
+  // y1 = c K x1 + M x2;  y2 = M x1 + M x2 - eps^2 K x2 + G,  G = -3 (u^2 x2, phi)
+  // (M_E x2 = 3 (u^2 x2, phi) - M x2)
+  const double cf[2][4] = {{0.0, 1.0, 1.0, 0.0}, {1.0, 0.0, 1.0, -1.0}};
+  const int ff[2][4] = {{CF_ONE, CF_C, CF_ONE, CF_ONE}, {CF_ONE, CF_ONE, CF_ONE, CF_E2}};
+  OKE(c, launch_stencil_lin2<double>(g, B, x, off(x, n), Vec<const double>{nullptr, 0}, cst(G), cf,
+                                     ff, y, off(y, n), st));
+  return OK_SUCCESS;
+}
+
+namespace {
+
+// z = diag((alpha/c) S^^-1, (c/alpha) S^^-1) v (each block one multigrid
+// application of S^), with the partials of <z, v> in c.pA.
+int sym_precond(ClassCtx& c, const int* fl, Vec<const double> v, Vec<double> z, hipStream_t st) {
+  const int64_t n = c.n;
+  int e = mg_apply<double>(c, fl, v, z, c.shape.mg_cycles, st);
+  if (e) return e;
+  e = mg_apply<double>(c, fl, off(v, n), off(z, n), c.shape.mg_cycles, st);
+  if (e) return e;
+  OKE(c, launch_mr_scale_dot(c.batch(fl), z, v, n, vec(c.pA, (int64_t)kMaxRedBlocks), st));
+  return OK_SUCCESS;
+}
+
+int flag_pipe(ClassCtx& c) {
+  if (c.fp) return OK_SUCCESS;
+  auto f = std::make_unique<FlagPipe>();
+  OKE(c, hipHostMalloc((void**)&f->h, sizeof(int) * 2 * c.B, hipHostMallocDefault));
+  for (hipEvent_t& ev : f->ev) OKE(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  c.fp = std::move(f);
+  return OK_SUCCESS;
+}
+
+}  // namespace
+
+int minres_class(ClassCtx& c, Vec<const double> u, Vec<const double> b, Vec<double> x,
+                 bool newton, hipStream_t st) {
+  if (c.mixed) return set_err(c.err, OK_E_INVALID, "MINRES requires precision OK_FP64");
+  TraceRange range("minres");
+  const int64_t n = c.n, n2 = c.n2();
+  for (int i = 0; i < c.B; i++)
+    if (c.h_part[i]) c.out[i] = InstOut{0, 0, 0, c.out[i].fnorm, 0.0};
+  if (!any(c.h_part)) return OK_SUCCESS;
+  if (push_part(c, st)) return OK_E_HIP;
+  // work vectors in V: v_{j-1}, v_j, v_{j+1}; z_j, z_{j+1}; A z_j; w_{j-1}, w_j, w_{j+1}
+  int v0 = 0, v1 = 1, v2 = 2, z1 = 3, z2 = 4, w0 = 6, w1 = 7, w2 = 8;
+  const int az = 5;
+  auto slot = [&](int k) { return Vec<double>{c.V + (int64_t)k * n2, sV(c)}; };
+  const Batch P = c.batch(c.part), A = c.batch(c.act), R = c.batch(c.incyc);
+  Vec<double> mr = vec(c.mr, (int64_t)MR_COUNT);
+  Vec<double> pa = vec(c.pA, (int64_t)kMaxRedBlocks), pb = vec(c.pB, (int64_t)kMaxRedBlocks);
+  OKE(c, launch_mr_init(P, b, slot(v1), slot(v0), slot(w0), slot(w1), x, n, newton, st));
+  int e = sym_precond(c, c.part, cst(slot(v1)), slot(z1), st);
+  if (e) return e;
+  OKE(c, launch_mr_start(P, c.act, cst(pa), n2, mr, st));
+  e = flag_pipe(c);
+  if (e) return e;
+  const int maxit = c.m * (c.shape.gmres_max_restarts + 1);
+  // Iterations are issued one ahead of the stop test, as in FGMRES: an
+  // iteration issued after every instance stopped finds act cleared on the
+  // device and does nothing.
+  FlagPipe* f = c.fp.get();
+  f->pend[0] = f->pend[1] = -1;
+  for (int j = 0; j < maxit; j++) {
+    TraceRange it_range("minres iteration");
+    e = sym_apply_d(c, c.act, u, cst(slot(z1)), slot(az), st);
+    if (e) return e;
+    OKE(c, launch_dot_partial(A, cst(slot(az)), cst(slot(z1)), n2, pb, st));
+    OKE(c, launch_mr_vupd(A, cst(pb), cst(slot(az)), cst(slot(v1)), cst(slot(v0)), slot(v2), n2,
+                          mr, st));
+    e = sym_precond(c, c.act, cst(slot(v2)), slot(z2), st);
+    if (e) return e;
+    OKE(c, launch_mr_coef(P, c.act, c.incyc, cst(pa), n2, maxit, mr, st));
+    OKE(c, launch_mr_wx(R, cst(slot(z1)), cst(slot(w0)), cst(slot(w1)), slot(w2), x, n, newton,
+                        cst(mr), st));
+    int t = v0;
+    v0 = v1, v1 = v2, v2 = t;
+    std::swap(z1, z2);
+    t = w0;
+    w0 = w1, w1 = w2, w2 = t;
+    const int s = j & 1;
+    OKE(c, hipMemcpyAsync(f->h + (size_t)s * c.B, c.act, sizeof(int) * c.B, hipMemcpyDeviceToHost,
+                          st));
+    OKE(c, hipEventRecord(f->ev[s], st));
+    f->pend[s] = j;
+    const int jt = g_issue_ahead ? j - 1 : j;
+    if (jt < 0) continue;
+    const int ts = jt & 1;
+    if (f->pend[ts] != jt) continue;
+    OKE(c, hipEventSynchronize(f->ev[ts]));
+    f->pend[ts] = -1;
+    bool still = false;
+    for (int i = 0; i < c.B; i++) still = still || f->h[(size_t)ts * c.B + i];
+    if (!still) break;
+  }
+  f->pend[0] = f->pend[1] = -1;
+  std::vector<double> h;
+  if (d2h(c, h, c.mr, (size_t)MR_COUNT * c.B, st)) return OK_E_HIP;
+  if (sync(c, st)) return OK_E_HIP;
+  for (int i = 0; i < c.B; i++) {
+    if (!c.h_part[i]) continue;
+    const double* q = &h[(size_t)MR_COUNT * i];
+    InstOut& o = c.out[i];
+    o.fgmres_its = (int)q[MR_ITS];
+    o.lin_res = q[MR_GAM1] > 0.0 ? std::fabs(q[MR_ETA]) / q[MR_GAM1] : 0.0;
+    const int stt = (int)q[MR_STATUS];
+    o.status = stt == 1 ? OK_SUCCESS : stt == 2 ? OK_E_NONFINITE : OK_E_GMRES_MAXIT;
+  }
+  c.h_act.assign(c.B, 0);
+  return OK_SUCCESS;
+}
+
+int newton_solve_group(const Group& grp, const std::vector<Vec<const double>>& u,
+                       const std::vector<Vec<const double>>& b, const std::vector<Vec<double>>& x,
+                       hipStream_t st) {
+  Group fg;
+  std::vector<Vec<const double>> fu, fb;
+  std::vector<Vec<double>> fx;
+  for (size_t k = 0; k < grp.size(); k++) {
+    if (grp[k]->shape.linear_solver == OK_SOLVER_MINRES) {
+      int e = minres_class(*grp[k], u[k], b[k], x[k], true, st);
+      if (e) return e;
+      continue;
+    }
+    fg.push_back(grp[k]);
+    fu.push_back(u[k]);
+    fb.push_back(b[k]);
+    fx.push_back(x[k]);
+  }
+  return fg.empty() ? OK_SUCCESS : fgmres_group(fg, fu, fb, fx, st);
+}
+
+// ---------------------------------------------------------------------------
 // Newton in lockstep (Sec. 2: one linear solve per Newton iteration)
 // ---------------------------------------------------------------------------
 int newton_group_iters(const Group& grp, const std::vector<Vec<double>>& u,
@@ -1169,7 +1325,7 @@ int newton_group_iters(const Group& grp, const std::vector<Vec<double>>& u,
       OKE(c, launch_copy_scale<double, double>(c.batch(c.part), bb[k], vec(c.Bv, c.n2()), -1.0,
                                                c.n2(), st));
     }
-    int e = fgmres_group(grp, uu, bb, xx, st);
+    int e = newton_solve_group(grp, uu, bb, xx, st);
     if (e) return e;
     for (size_t k = 0; k < nc; k++) {
       ClassCtx& c = *grp[k];

@@ -1,4 +1,5 @@
-// Vector kernels of flexible GMRES (Saad 1993) with modified Gram-Schmidt,
+// Vector kernels of flexible GMRES (Saad 1993) with modified Gram-Schmidt and
+// of preconditioned MINRES (Paige and Saunders 1975),
 // for a class of B instances (see ok_internal.h).
 //
 // Every reduction is deterministic: red_blocks(n) blocks per instance (a
@@ -429,6 +430,174 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Preconditioned MINRES (Elman, Silvester and Wathen, Alg. 4.1) on the
+// symmetric rearranged Newton system.  The reductions follow k_dot's element
+// order over the 2n entries of an instance.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+    k_mr_init(Batch B, Vec<const double> bv, Vec<double> v1v, Vec<double> v0v, Vec<double> w0v,
+              Vec<double> w1v, Vec<double> xv, int64_t n, int scale_first, int per) {
+  const int inst = blockIdx.x / per;
+  if (inactive(B, inst)) return;
+  const double s = scale_first ? B.coef[inst].inv_sA : 1.0;
+  const double* b = bv.at(inst);
+  double *v1 = v1v.at(inst), *v0 = v0v.at(inst), *w0 = w0v.at(inst), *w1 = w1v.at(inst);
+  double* x = xv.at(inst);
+  for (int64_t i = (int64_t)(blockIdx.x % per) * blockDim.x + threadIdx.x; i < 2 * n;
+       i += (int64_t)per * blockDim.x) {
+    v1[i] = i < n ? s * b[i] : b[i];
+    v0[i] = 0.0;
+    w0[i] = 0.0;
+    w1[i] = 0.0;
+    x[i] = 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+    k_mr_scale_dot(Batch B, Vec<double> zv, Vec<const double> vv, int64_t n, Vec<double> pv,
+                   int nblk) {
+  __shared__ double sh[kRedThreads / 64];
+  const int inst = blockIdx.x / nblk, kb = blockIdx.x % nblk;
+  if (inactive(B, inst)) return;
+  const InstCoef& C = B.coef[inst];
+  const double f1 = C.alpha / C.c, f2 = C.c / C.alpha;
+  double* z = zv.at(inst);
+  const double* v = vv.at(inst);
+  double acc = 0.0;
+  for (int64_t i = (int64_t)kb * blockDim.x + threadIdx.x; i < 2 * n;
+       i += (int64_t)nblk * blockDim.x) {
+    const double zi = ldnt(z + i) * (i < n ? f1 : f2);
+    stnt(zi, z + i);
+    acc = fma(zi, ldnt(v + i), acc);
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) pv.at(inst)[kb] = acc;
+}
+
+__global__ void __launch_bounds__(256)
+    k_mr_start(Batch B, int* act, Vec<const double> pv, int nblk, Vec<double> mrv) {
+  __shared__ double sh[8];
+  const int inst = blockIdx.x;
+  if (inactive(B, inst)) {
+    if (threadIdx.x == 0) act[inst] = 0;
+    return;
+  }
+  const double s = sum_partials(pv.at(inst), nblk, sh);
+  if (threadIdx.x != 0) return;
+  double* mr = mrv.at(inst);
+  const double g1 = sqrt(s);
+  for (int k = 0; k < MR_COUNT; k++) mr[k] = 0.0;
+  mr[MR_GAM0] = 1.0;
+  mr[MR_GAM] = g1;
+  mr[MR_ETA] = g1;
+  mr[MR_C0] = 1.0;
+  mr[MR_C] = 1.0;
+  mr[MR_TOL] = B.coef[inst].rtol * g1;
+  mr[MR_GAM1] = g1;
+  int a = 1;
+  if (!isfinite(g1)) {
+    mr[MR_STATUS] = 2.0;
+    a = 0;
+  } else if (g1 == 0.0) {
+    mr[MR_STATUS] = 1.0;
+    a = 0;
+  }
+  act[inst] = a;
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+    k_mr_vupd(Batch B, Vec<const double> pv, Vec<const double> azv, Vec<const double> v1v,
+              Vec<const double> v0v, Vec<double> v2v, int64_t n2, Vec<double> mrv, int nblk) {
+  __shared__ double sh[kRedThreads / 64];
+  const int inst = blockIdx.x / nblk, kb = blockIdx.x % nblk;
+  if (inactive(B, inst)) return;
+  double* mr = mrv.at(inst);
+  const double gam = mr[MR_GAM], gam0 = mr[MR_GAM0];
+  const double delta = sum_partials(pv.at(inst), nblk, sh) / (gam * gam);
+  if (kb == 0 && threadIdx.x == 0) mr[MR_DELTA] = delta;
+  const double ca = 1.0 / gam, c1 = -delta / gam, c0 = -gam / gam0;
+  const double* az = azv.at(inst);
+  const double* v1 = v1v.at(inst);
+  const double* v0 = v0v.at(inst);
+  double* v2 = v2v.at(inst);
+  for (int64_t i = (int64_t)kb * blockDim.x + threadIdx.x; i < n2;
+       i += (int64_t)nblk * blockDim.x)
+    stnt(fma(c0, ldnt(v0 + i), fma(c1, ldnt(v1 + i), ca * ldnt(az + i))), v2 + i);
+}
+
+__global__ void __launch_bounds__(256)
+    k_mr_coef(Batch B, int* act, int* ran, Vec<const double> pv, int nblk, int maxit,
+              Vec<double> mrv) {
+  __shared__ double sh[8];
+  const int inst = blockIdx.x;
+  if (inactive(B, inst) || !act[inst]) {
+    if (threadIdx.x == 0) ran[inst] = 0;
+    return;
+  }
+  const double s2 = sum_partials(pv.at(inst), nblk, sh);
+  if (threadIdx.x != 0) return;
+  ran[inst] = 1;
+  double* mr = mrv.at(inst);
+  const double gnew = sqrt(s2);
+  const double gam = mr[MR_GAM], delta = mr[MR_DELTA];
+  const double s = mr[MR_S], s0 = mr[MR_S0], cc = mr[MR_C], c0 = mr[MR_C0];
+  // QR step of the Lanczos tridiagonal matrix: rotate the new column with
+  // the last two rotations, then build the rotation that removes gamma_{j+1}
+  const double a0 = cc * delta - c0 * s * gam;
+  const double a1 = sqrt(a0 * a0 + gnew * gnew);
+  const double a2 = s * delta + c0 * cc * gam;
+  const double a3 = s0 * gam;
+  const double cn = a0 / a1, sn = gnew / a1;
+  const double eta = mr[MR_ETA];
+  mr[MR_WZ] = 1.0 / (gam * a1);
+  mr[MR_W0] = -a3 / a1;
+  mr[MR_W1] = -a2 / a1;
+  mr[MR_XC] = cn * eta;
+  const double en = -sn * eta;
+  mr[MR_ETA] = en;
+  const double its = mr[MR_ITS] + 1.0;
+  mr[MR_ITS] = its;
+  mr[MR_GAM0] = gam;
+  mr[MR_GAM] = gnew;
+  mr[MR_C0] = cc;
+  mr[MR_C] = cn;
+  mr[MR_S0] = s;
+  mr[MR_S] = sn;
+  if (!isfinite(en) || !isfinite(gnew)) {
+    mr[MR_STATUS] = 2.0;
+    act[inst] = 0;
+  } else if (fabs(en) <= mr[MR_TOL] || gnew == 0.0) {
+    mr[MR_STATUS] = 1.0;
+    act[inst] = 0;
+  } else if (its >= (double)maxit) {
+    mr[MR_STATUS] = 3.0;
+    act[inst] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_mr_wx(Batch B, Vec<const double> zv, Vec<const double> w0v, Vec<const double> w1v,
+            Vec<double> w2v, Vec<double> xv, int64_t n, int swap, Vec<const double> mrv,
+            int per) {
+  const int inst = blockIdx.x / per;
+  if (inactive(B, inst)) return;
+  const double* mr = mrv.at(inst);
+  const double cz = mr[MR_WZ], c0 = mr[MR_W0], c1 = mr[MR_W1], cx = mr[MR_XC];
+  const double* z = zv.at(inst);
+  const double* w0 = w0v.at(inst);
+  const double* w1 = w1v.at(inst);
+  double* w2 = w2v.at(inst);
+  double* x = xv.at(inst);
+  for (int64_t i = (int64_t)(blockIdx.x % per) * blockDim.x + threadIdx.x; i < 2 * n;
+       i += (int64_t)per * blockDim.x) {
+    const double w = fma(c1, ldnt(w1 + i), fma(c0, ldnt(w0 + i), cz * ldnt(z + i)));
+    stnt(w, w2 + i);
+    const int64_t k = swap ? (i < n ? i + n : i - n) : i;
+    x[k] = fma(cx, w, x[k]);
+  }
+}
+
 int vec_per(int64_t n) {
   int64_t b = (n + 255) / 256;
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 4096));
@@ -556,6 +725,55 @@ hipError_t launch_axpby(const Batch& B, double a, Vec<const double> x, double b,
 hipError_t launch_fill(const Batch& B, Vec<double> x, double v, int64_t n, hipStream_t st) {
   const int per = vec_per(n);
   hipLaunchKernelGGL(k_fill, grid_of(per, B), dim3(256), 0, st, B, x, v, n, per);
+  return hipGetLastError();
+}
+
+hipError_t launch_mr_init(const Batch& B, Vec<const double> b, Vec<double> v1, Vec<double> v0,
+                          Vec<double> w0, Vec<double> w1, Vec<double> x, int64_t n,
+                          bool scale_first, hipStream_t st) {
+  const int per = vec_per(2 * n);
+  hipLaunchKernelGGL(k_mr_init, grid_of(per, B), dim3(256), 0, st, B, b, v1, v0, w0, w1, x, n,
+                     scale_first ? 1 : 0, per);
+  return hipGetLastError();
+}
+
+hipError_t launch_mr_scale_dot(const Batch& B, Vec<double> z, Vec<const double> v, int64_t n,
+                               Vec<double> partials, hipStream_t st) {
+  const int nb = red_blocks(2 * n);
+  hipLaunchKernelGGL(k_mr_scale_dot, grid_of(nb, B), dim3(kRedThreads), 0, st, B, z, v, n,
+                     partials, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_mr_start(const Batch& B, int* act, Vec<const double> partials, int64_t n2,
+                           Vec<double> mr, hipStream_t st) {
+  hipLaunchKernelGGL(k_mr_start, dim3(B.count), dim3(256), 0, st, B, act, partials,
+                     red_blocks(n2), mr);
+  return hipGetLastError();
+}
+
+hipError_t launch_mr_vupd(const Batch& B, Vec<const double> partials, Vec<const double> az,
+                          Vec<const double> v1, Vec<const double> v0, Vec<double> v2, int64_t n2,
+                          Vec<double> mr, hipStream_t st) {
+  const int nb = red_blocks(n2);
+  hipLaunchKernelGGL(k_mr_vupd, grid_of(nb, B), dim3(kRedThreads), 0, st, B, partials, az, v1, v0,
+                     v2, n2, mr, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_mr_coef(const Batch& B, int* act, int* ran, Vec<const double> partials,
+                          int64_t n2, int maxit, Vec<double> mr, hipStream_t st) {
+  hipLaunchKernelGGL(k_mr_coef, dim3(B.count), dim3(256), 0, st, B, act, ran, partials,
+                     red_blocks(n2), maxit, mr);
+  return hipGetLastError();
+}
+
+hipError_t launch_mr_wx(const Batch& B, Vec<const double> z, Vec<const double> w0,
+                        Vec<const double> w1, Vec<double> w2, Vec<double> x, int64_t n,
+                        bool swap, Vec<const double> mr, hipStream_t st) {
+  const int per = vec_per(2 * n);
+  hipLaunchKernelGGL(k_mr_wx, grid_of(per, B), dim3(256), 0, st, B, z, w0, w1, w2, x, n,
+                     swap ? 1 : 0, mr, per);
   return hipGetLastError();
 }
 

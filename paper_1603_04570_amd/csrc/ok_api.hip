@@ -156,6 +156,7 @@ int ok_default_params(ok_params* p) {
   p->mg_pre = 2;
   p->mg_post = 2;
   p->mg_cycles = 1;
+  p->linear_solver = OK_SOLVER_FGMRES;
   return OK_SUCCESS;
 }
 
@@ -247,6 +248,30 @@ int ok_fgmres(ok_ctx* c, const double* u, const double* b, double* x, int32_t* i
   return OK_SUCCESS;
 }
 
+int ok_sym_apply(ok_ctx* c, const double* u, const double* x, double* y, void* stream) {
+  if (!c) return OK_E_INVALID;
+  if (!u || !x || !y || x == y) return fail(&c->err, OK_E_INVALID, "null or aliased vectors");
+  if (!aligned8(u) || !aligned8(x) || !aligned8(y)) return fail(&c->err, OK_E_INVALID, "misaligned");
+  if (c->cls.mixed) return fail(&c->err, OK_E_INVALID, "the symmetric system is FP64 only");
+  return sym_apply_d(c->cls, nullptr, one(u), one(x), one(y), (hipStream_t)stream);
+}
+
+int ok_minres(ok_ctx* c, const double* u, const double* b, double* x, int32_t* its, void* stream) {
+  if (!c) return OK_E_INVALID;
+  if (!u || !b || !x || b == x) return fail(&c->err, OK_E_INVALID, "null or aliased vectors");
+  if (!aligned8(u) || !aligned8(b) || !aligned8(x)) return fail(&c->err, OK_E_INVALID, "misaligned");
+  ClassCtx& k = c->cls;
+  if (k.mixed) return fail(&c->err, OK_E_INVALID, "MINRES requires precision OK_FP64");
+  if (k.shape.linear_solver != OK_SOLVER_MINRES)
+    return fail(&c->err, OK_E_INVALID, "context not created for MINRES (linear_solver)");
+  k.h_part.assign(1, 1);
+  int e = minres_class(k, one(u), one(b), one(x), false, (hipStream_t)stream);
+  if (its) *its = k.out[0].fgmres_its;
+  if (e) return e;
+  if (k.out[0].status) return fail(&c->err, k.out[0].status, kStatusNames[-k.out[0].status]);
+  return OK_SUCCESS;
+}
+
 int ok_newton_step(ok_ctx* c, double* u, double* w, const double* un, const double* wn,
                    ok_newton_info* info, void* stream) {
   if (!c) return OK_E_INVALID;
@@ -269,7 +294,8 @@ int ok_newton_step(ok_ctx* c, double* u, double* w, const double* un, const doub
                                                     -1.0, k.n2(), st));
   k.h_part.assign(1, 1);
   Group grp{&k};
-  e = fgmres_group(grp, {one((const double*)u)}, {Vec<const double>{k.Bv, 0}}, {vec(k.X, 0)}, st);
+  e = newton_solve_group(grp, {one((const double*)u)}, {Vec<const double>{k.Bv, 0}},
+                         {vec(k.X, 0)}, st);
   if (e) return e;
   inf.status = k.out[0].status;
   inf.fgmres_its = k.out[0].fgmres_its;

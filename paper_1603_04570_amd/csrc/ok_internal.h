@@ -71,19 +71,21 @@ struct InstCoef {
   double alpha;               // eps sqrt(c)
   double sA, inv_sA;          // 1 + dt theta sigma and its inverse
   double dth;                 // dt theta
+  double c;                   // dt theta / (1 + dt theta sigma)
   double e2;                  // eps^2
   double dt, sigma, theta, m;
   double rtol, atol;
 };
 
 // Named per-instance scalars for stencil epilogue coefficients.
-enum CoefField { CF_ONE = 0, CF_SA = 1, CF_DTH = 2, CF_E2 = 3, CF_INV_SA = 4 };
+enum CoefField { CF_ONE = 0, CF_SA = 1, CF_DTH = 2, CF_E2 = 3, CF_INV_SA = 4, CF_C = 5 };
 __host__ __device__ inline double coef_field(const InstCoef& c, int f) {
   switch (f) {
     case CF_SA: return c.sA;
     case CF_DTH: return c.dth;
     case CF_E2: return c.e2;
     case CF_INV_SA: return c.inv_sA;
+    case CF_C: return c.c;
     default: return 1.0;
   }
 }
@@ -333,6 +335,56 @@ template <class TZ>
 hipError_t launch_lsq_update(const Batch& B, int m, Vec<const double> H, Vec<const double> g,
                              Vec<double> y, Vec<const double> kr, Vec<const TZ> Z,
                              int64_t zstride, Vec<double> x, int64_t n, hipStream_t st);
+
+// Preconditioned MINRES on the symmetric rearranged Newton system (Elman,
+// Silvester and Wathen, Alg. 4.1), per instance, vectors of length n2 = 2n
+// in the unknown order [dw; du].  The scalars of the recurrence live in
+// device memory, MR_COUNT doubles per instance (slots below); z vectors are
+// kept unnormalised (z_j = gam_j * z^_j) and the normalisation is folded
+// into the kernels that read them.
+enum MinresSlot {
+  MR_GAM0 = 0,  // gamma_{j-1}
+  MR_GAM,       // gamma_j
+  MR_ETA,       // eta (the residual norm up to sign)
+  MR_S0, MR_S, MR_C0, MR_C,  // Givens sines and cosines of the last two steps
+  MR_TOL,       // rtol * gamma_1
+  MR_DELTA,     // delta_j
+  MR_WZ, MR_W0, MR_W1,  // w_{j+1} = WZ z_j + W0 w_{j-1} + W1 w_j
+  MR_XC,        // x += XC w_{j+1}
+  MR_ITS,       // iterations done
+  MR_STATUS,    // 0 running, 1 converged, 2 non-finite, 3 iteration limit
+  MR_GAM1,      // gamma_1 (initial preconditioned residual norm)
+  MR_COUNT = 16
+};
+// Start: v1 = [s b1; b2] (s = 1/(1 + dt th sigma) if scale_first, else 1),
+// and v0, w0, w1, x = 0.
+hipError_t launch_mr_init(const Batch& B, Vec<const double> b, Vec<double> v1, Vec<double> v0,
+                          Vec<double> w0, Vec<double> w1, Vec<double> x, int64_t n,
+                          bool scale_first, hipStream_t st);
+// z = [(alpha/c) z1; (c/alpha) z2] in place, and the partials of <z, v>
+// (red_blocks(2n) per instance).
+hipError_t launch_mr_scale_dot(const Batch& B, Vec<double> z, Vec<const double> v, int64_t n,
+                               Vec<double> partials, hipStream_t st);
+// gamma_1 = sqrt(sum partials); initial scalars; act = 1 unless gamma_1 is
+// zero (converged, status 1) or not finite (status 2).  B.act: participating.
+hipError_t launch_mr_start(const Batch& B, int* act, Vec<const double> partials, int64_t n2,
+                           Vec<double> mr, hipStream_t st);
+// delta = sum(partials of <A z, z>) / gamma^2;
+// v2 = (A z)/gamma - (delta/gamma) v1 - (gamma/gamma0) v0.
+hipError_t launch_mr_vupd(const Batch& B, Vec<const double> partials, Vec<const double> az,
+                          Vec<const double> v1, Vec<const double> v0, Vec<double> v2, int64_t n2,
+                          Vec<double> mr, hipStream_t st);
+// gamma_{j+1} = sqrt(sum partials of <z2, v2>), the Givens step of the QR
+// factorisation and the stop test (act cleared on convergence, non-finite
+// values or after maxit iterations); ran = 1 for the instances that took this
+// step (act set on entry), 0 otherwise.  B.act: participating.
+hipError_t launch_mr_coef(const Batch& B, int* act, int* ran, Vec<const double> partials,
+                          int64_t n2, int maxit, Vec<double> mr, hipStream_t st);
+// w2 = WZ z + W0 w0 + W1 w1, x += XC w2; swap: x is stored with its halves
+// exchanged ([du; dw]).  B.act: the instances that took the step.
+hipError_t launch_mr_wx(const Batch& B, Vec<const double> z, Vec<const double> w0,
+                        Vec<const double> w1, Vec<double> w2, Vec<double> x, int64_t n,
+                        bool swap, Vec<const double> mr, hipStream_t st);
 
 // Residual assembly helper (FP64):
 // t1 = (u - un) + dt*sigma*(th*u + (1-th)*un - m),  t2 = dt*(th*w + (1-th)*wn)

@@ -13,6 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(PKG, "libok.so")
 
 OK_FP64, OK_MIXED = 0, 1
+OK_SOLVER_FGMRES, OK_SOLVER_MINRES = 0, 1
 OK_K_NONE, OK_K_CHEB_MASS, OK_K_MG_SMOOTH, OK_K_ELEMENT, OK_K_KRYLOV = 0, 1, 2, 3, 5
 HIST = 256
 
@@ -31,7 +32,8 @@ class Params(C.Structure):
                 ("gmres_rtol", C.c_double), ("newton_atol", C.c_double),
                 ("newton_max_it", C.c_int32), ("cheb_A_its", C.c_int32),
                 ("schur_richardson", C.c_int32), ("mg_levels", C.c_int32),
-                ("mg_pre", C.c_int32), ("mg_post", C.c_int32), ("mg_cycles", C.c_int32)]
+                ("mg_pre", C.c_int32), ("mg_post", C.c_int32), ("mg_cycles", C.c_int32),
+                ("linear_solver", C.c_int32)]
 
 
 class NewtonInfo(C.Structure):
@@ -110,6 +112,8 @@ def load():
     lib.ok_residual_noalloc.argtypes = [P(Params), vp, vp, vp, vp, vp, P(d), vp]
     lib.ok_jacobian_apply.argtypes = [vp, vp, vp, vp, vp]
     lib.ok_precond_apply.argtypes = [vp, vp, vp, vp, vp]
+    lib.ok_sym_apply.argtypes = [vp, vp, vp, vp, vp]
+    lib.ok_minres.argtypes = [vp, vp, vp, vp, P(i32), vp]
     lib.ok_cheb_mass.argtypes = [vp, vp, vp, vp]
     lib.ok_mg_apply.argtypes = [vp, vp, vp, i32, vp]
     lib.ok_fgmres.argtypes = [vp, vp, vp, vp, P(i32), vp]
@@ -274,6 +278,21 @@ class Problem:
         self._check(self.lib.ok_mg_apply(self.ctx, _ptr(b), _ptr(x), cycles,
                                          _stream(self.stream)), "ok_mg_apply")
         return x
+
+    def sym_apply(self, u, x, y=None):
+        """ok_sym_apply: the symmetric rearranged operator on x = [dw; du]."""
+        y = self.field(2) if y is None else y
+        self._check(self.lib.ok_sym_apply(self.ctx, _ptr(u), _ptr(x), _ptr(y),
+                                          _stream(self.stream)), "ok_sym_apply")
+        return y
+
+    def minres(self, u, b, x=None):
+        """ok_minres: preconditioned MINRES on the symmetric rearranged system."""
+        x = self.field(2) if x is None else x
+        its = C.c_int32()
+        st = self.lib.ok_minres(self.ctx, _ptr(u), _ptr(b), _ptr(x), C.byref(its),
+                                _stream(self.stream))
+        return x, its.value, st
 
     def fgmres(self, u, b, x=None):
         x = self.field(2) if x is None else x

@@ -66,6 +66,7 @@ def test_non_power_of_two_meshes_accepted(lib):
                                          ("precision", 7), ("gmres_restart", 0),
                                          ("gmres_restart", 65), ("cheb_A_its", 0),
                                          ("mg_pre", 0), ("mg_levels", 9),
+                                         ("linear_solver", 2), ("linear_solver", -1),
                                          # 130 -> 65 elements: 66 coarse nodes per direction
                                          ("n", 130)])
 def test_invalid_params_rejected(lib, field, value):
@@ -77,6 +78,23 @@ def test_invalid_params_rejected(lib, field, value):
     assert lib.ok_assemble_mesh(C.byref(p), C.c_void_p(256), C.c_size_t(1 << 40), None,
                                 C.byref(ctx)) == -1
     assert not ctx.value
+
+
+def test_minres_params(lib):
+    """MINRES is an FP64 path; its class keeps at least nine work vectors."""
+    from paper_1603_04570_amd import ok
+    b = C.c_size_t()
+    pm = ok.default_params(linear_solver=ok.OK_SOLVER_MINRES, precision=ok.OK_MIXED)
+    assert lib.ok_workspace_bytes(C.byref(pm), C.byref(b)) == -1
+    p = ok.default_params(dim=2, n=64, linear_solver=ok.OK_SOLVER_MINRES)
+    assert ok.workspace_bytes(p) > 0
+    # gmres_restart below 8: the MINRES class still holds its nine vectors
+    f4 = ok.workspace_bytes(ok.default_params(dim=2, n=64, gmres_restart=4))
+    m4 = ok.workspace_bytes(ok.default_params(dim=2, n=64, gmres_restart=4,
+                                              linear_solver=ok.OK_SOLVER_MINRES))
+    assert m4 - f4 >= 4 * 2 * 65 * 65 * 8 - 256  # four more vectors of 2n, up to alignment
+    assert lib.ok_sym_apply(None, None, None, None, None) == -1
+    assert lib.ok_minres(None, None, None, None, None, None) == -1
 
 
 def test_workspace_errors(lib):
