@@ -10,7 +10,9 @@ mesh (16,974,593 nodes, 33,949,186 DOFs), eps=0.01, sigma=1000, m=0.1,
 theta=1, dt=2e-5, u0 = m + 0.05*U(-1,1) seeded (seed 2), w0 = 0.  `value` is
 the FP64 path's throughput; the mixed-precision form (FP32 preconditioner,
 FP64 FGMRES, residual, Jacobian and M_E(u)) is timed beside it on the same
-input, with its error against the FP64 path after every step.  Both are
+input, with its error against the FP64 path after every step, and so is
+Newton with preconditioned MINRES on the symmetric rearrangement of the
+Newton system (FP64; --linear-solver fgmres leaves it out).  All are
 timed with no profiling events in the timed region; kernel-class rooflines
 come from a profiled rerun of the same timesteps.  --config 3d128 (4.29M
 DOFs) and 2d64 are the smaller cases of the same recipe.
@@ -60,16 +62,18 @@ KERNELS = {
                          "3 two-field vectors per projection (w and v_i read, w written), "
                          "i = 0..j",
                ("paper_1603_04570_amd/csrc/k_krylov.hip", "paper_1603_04570_amd/csrc/ok_internal.h")),
-    K_CHEB_MASS: ("cheb_pair", "Chebyshev-Jacobi iterations on M, two per launch (k_cheb2t/k_cheb2); "
-                               "algorithmic bytes: x, r, d read and written once per launch "
-                               "(6 words/node)",
+    K_CHEB_MASS: ("cheb_pair", "Chebyshev-Jacobi iterations on M, two per launch (the autotuned "
+                               "one of k_strip2/k_cheb2t/k_cheb2); algorithmic bytes: x, r, d "
+                               "read and written once per launch (6 words/node)",
                   ("paper_1603_04570_amd/csrc/k_stencil_impl.h",
+                   "paper_1603_04570_amd/csrc/k_strip2.h",
                    "paper_1603_04570_amd/csrc/ok_internal.h")),
     K_MG_SMOOTH: ("vcycle_smoother", "finest-level V-cycle smoothing passes (fused pre-smoothing + "
-                                     "residual and fused post-smoothing, k_mg2t/k_mg2, or the "
-                                     "one-iteration kernels); algorithmic bytes: 3 words/node "
-                                     "per fused pass",
+                                     "residual and fused post-smoothing, the autotuned one of "
+                                     "k_strip2/k_mg2t/k_mg2, or the one-iteration kernels); "
+                                     "algorithmic bytes: 3 words/node per fused pass",
                   ("paper_1603_04570_amd/csrc/k_stencil_impl.h",
+                   "paper_1603_04570_amd/csrc/k_strip2.h",
                    "paper_1603_04570_amd/csrc/ok_internal.h")),
 }
 
@@ -282,23 +286,34 @@ def bench_paper(args, torch, ok):
     u.copy_(u0d)
     w.copy_(w0d)
     torch.cuda.synchronize()
+    # chunks of at most 100 timesteps: each chunk's stats hold every Newton
+    # iteration's FGMRES count (the per-call history is bounded)
+    its, newton, step_ms = [], [], []
     t0 = time.perf_counter()
-    st = P.timestep(u, w, args.steps)
+    done = 0
+    while done < args.steps:
+        k = min(100, args.steps - done)
+        st = P.timestep(u, w, k)
+        its += st.its()
+        newton += st.per_step()
+        step_ms += st.ms()
+        done += k
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     nd = dofs(3, n)
-    its = st.its()
     out = _base_line(nd * args.steps / el, args.steps, args.warmup, el * 1e3 / args.steps,
                      "f64" if args.precision != "mixed" else "f64+f32",
                      {"workload": f"paper: Sec. 4 experiment on Q1, 3D N={n} ({nd} DOFs), m=0.4, "
                                   "eps=0.02, sigma=100, theta=1/2, dt=eps^2, cosine u0, w0 from "
                                   "(okb), 2 Richardson iterations of S~^-1, 5 V-cycles",
                       "dofs": nd, "global_batch": 1, "parallelism": "none (1 GPU)"})
-    step_ms = np.array(st.ms())
+    step_ms = np.array(step_ms)
     out.update({"latency_ms": {"p50": float(np.percentile(step_ms, 50)),
                                "p99": float(np.percentile(step_ms, 99))},
-                "newton_its": st.per_step(), "fgmres_its": its,
+                "horizon": f"{args.steps} timesteps = {args.steps * 4e-4:g} time units",
+                "newton_its": newton, "fgmres_its": its,
                 "fgmres_per_newton": round(float(np.mean(its)), 2),
+                "fgmres_per_newton_max": int(max(its)),
                 "paper_reference_its": 8.0, "autotuned_shapes": tuned, "roofline": None})
     return out
 
@@ -426,17 +441,35 @@ def bench_serve(args, torch, ok):
     return out
 
 
-def _single_params(ok, cfg, precision):
+def _single_params(ok, cfg, precision, solver=0):
     return ok.default_params(dim=cfg["dim"], n=cfg["n"], eps=cfg["eps"], sigma=cfg["sigma"],
-                             m=cfg["m"], dt=cfg["dt"], theta=cfg["theta"], precision=precision)
+                             m=cfg["m"], dt=cfg["dt"], theta=cfg["theta"], precision=precision,
+                             linear_solver=solver)
 
 
-def _timed_run(args, torch, ok, cfg, prec, u0d, w0d):
+def _side_by_side(torch, Pa, Pb, u0d, w0d, steps):
+    """Both problems stepped from the same initial state: relative 2-norm
+    difference of each field after each step, Pa against Pb."""
+    ua, wa, ub, wb = u0d.clone(), w0d.clone(), u0d.clone(), w0d.clone()
+    per_step = []
+    for k in range(steps):
+        Pa.timestep(ua, wa, 1)
+        Pb.timestep(ub, wb, 1)
+        per_step.append({"step": k + 1,
+                         "u": float(torch.linalg.vector_norm(ua - ub) /
+                                    torch.linalg.vector_norm(ub)),
+                         "w": float(torch.linalg.vector_norm(wa - wb) /
+                                    torch.linalg.vector_norm(wb))})
+    return {"per_step": per_step, "max_u": max(p["u"] for p in per_step),
+            "max_w": max(p["w"] for p in per_step)}
+
+
+def _timed_run(args, torch, ok, cfg, prec, u0d, w0d, solver=0):
     """One problem of the configuration in precision `prec`: autotuned,
     --warmup untimed timesteps from the initial state, then --steps timesteps
     from the same initial state timed between two device synchronisations
     (no profiling events in the timed region)."""
-    P = ok.Problem(_single_params(ok, cfg, prec), device=u0d.device)
+    P = ok.Problem(_single_params(ok, cfg, prec, solver), device=u0d.device)
     tuned = 0 if args.no_autotune else P.autotune()
     if args.graphs:
         P.use_graphs(True)
@@ -550,22 +583,30 @@ def bench_single(args, torch, ok, cfg):
             "roofline_kernels": mx["prof"]}
         # the mixed and the FP64 path stepped side by side from the same
         # initial state: relative error of each field after each step
-        Pm, Pf = mx["P"], head["P"]
-        um, wm, uf, wf = u0d.clone(), w0d.clone(), u0d.clone(), w0d.clone()
-        per_step = []
-        for k in range(args.steps):
-            Pm.timestep(um, wm, 1)
-            Pf.timestep(uf, wf, 1)
-            per_step.append({"step": k + 1,
-                             "u": float(torch.linalg.vector_norm(um - uf) /
-                                        torch.linalg.vector_norm(uf)),
-                             "w": float(torch.linalg.vector_norm(wm - wf) /
-                                        torch.linalg.vector_norm(wf))})
-        out["mixed"]["error_vs_fp64"] = {
-            "error": "relative 2-norm of each field after each step, against the FP64 path "
-                     "from the same initial state (both Newton-converged to the same tolerance)",
-            "per_step": per_step,
-            "max_u": max(p["u"] for p in per_step), "max_w": max(p["w"] for p in per_step)}
+        err = _side_by_side(torch, mx["P"], head["P"], u0d, w0d, args.steps)
+        err["error"] = ("relative 2-norm of each field after each step, against the FP64 path "
+                        "from the same initial state (both Newton-converged to the same "
+                        "tolerance)")
+        out["mixed"]["error_vs_fp64"] = err
+    if args.linear_solver == "both" and precs[0] == "fp64":
+        # Newton's linear solve by preconditioned MINRES on the symmetric
+        # rearrangement (FP64), timed the same way beside the FGMRES headline
+        Pm, mst, mel, _ = _timed_run(args, torch, ok, cfg, ok.OK_FP64, u0d, w0d,
+                                     ok.OK_SOLVER_MINRES)
+        print(f"{args.config} fp64 minres: {nd * args.steps / mel / 1e6:.1f}M DOFs/s, "
+              f"{mel * 1e3 / args.steps:.2f} ms/step", file=sys.stderr, flush=True)
+        ms_step = np.array(mst.ms())
+        err = _side_by_side(torch, Pm, head["P"], u0d, w0d, args.steps)
+        err["error"] = ("relative 2-norm of each field after each step, against the FGMRES "
+                        "path from the same initial state")
+        out["minres"] = {
+            "value": nd * args.steps / mel, "unit": "DOFs/s", "dtype": "f64",
+            "ms_per_step": mel * 1e3 / args.steps, "vs_fgmres": el / mel,
+            "latency_ms": {"p50": float(np.percentile(ms_step, 50)),
+                           "p99": float(np.percentile(ms_step, 99)), "samples": len(ms_step)},
+            "newton_its": mst.per_step(), "minres_its": mst.its(),
+            "error_vs_fgmres": err}
+        del Pm
     for r in runs.values():
         del r["P"]
     if not args.no_cpu_baseline:
@@ -595,6 +636,9 @@ def main():
                     help="run every Chebyshev iteration (on M and in the smoothers) in a pass of its own")
     ap.add_argument("--issue-ahead", action="store_true",
                     help="issue each FGMRES iteration before the previous one's stop test is read")
+    ap.add_argument("--linear-solver", choices=["both", "fgmres"], default="both",
+                    help="single-problem configs: also time Newton with MINRES on the symmetric "
+                         "system beside the FGMRES value (both, the default) or not (fgmres)")
     ap.add_argument("--gram-schmidt", choices=["icwy", "mgs"], default="icwy",
                     help="Arnoldi orthogonalisation: icwy (default; two passes, modified "
                          "Gram-Schmidt in inverse compact WY form) or mgs (one pass per "

@@ -12,7 +12,8 @@
 // evaluates its element by sum factorisation (2^d corners -> 3^d Gauss points
 // -> integrand -> 2^d corner contributions).  Contributions are summed into
 // nodes deterministically: along x with cross-lane shuffles, along y through
-// LDS (wavefront w reads w-1), along z with a register carry.
+// LDS (wavefront w reads w-1), along z with a carry that each lane keeps in
+// its own LDS slots (one per element slot along x).
 #include "ok_internal.h"
 
 #include <algorithm>
@@ -51,71 +52,63 @@ __device__ __forceinline__ void proj3(const double* t, double& o0, double& o1) {
   o1 = kPc * t[0] + m + kPa * t[2];
 }
 
+// Linear interpolant of (v0, v1) at Gauss point q (as lerp3 computes it).
+__device__ __forceinline__ double lerp_at(double v0, double v1, int q) {
+  return q == 0 ? v0 + kG0 * (v1 - v0) : q == 1 ? 0.5 * (v0 + v1) : v1 - kG0 * (v1 - v0);
+}
+// Weight of Gauss point q in the projection to end 0 / end 1 (proj3).
+__device__ __forceinline__ double pw0(int q) { return q == 0 ? kPa : q == 1 ? kPb : kPc; }
+__device__ __forceinline__ double pw1(int q) { return q == 0 ? kPc : q == 1 ? kPb : kPa; }
+
 // One 3D element: corners v[az][ay][ax] of u and x; returns corner
-// contributions E[az][ay][ax] without the h^3 factor.
+// contributions E[az][ay][ax] without the h^3 factor.  Sum factorisation
+// ordered to keep few values live: the four x-edges are interpolated to
+// their Gauss points once, then for each Gauss row qy the y- and
+// z-interpolants, the integrand and its z-projection, accumulated straight
+// into the y-projection; the x-projection comes last.
 template <int MODE>
 __device__ __forceinline__ void element3(const double (&u)[2][2][2], const double (&x)[2][2][2],
                                          double (&E)[2][2][2]) {
-  double uq[3][3][3], xq[3][3][3];
-  {
-    double a[2][2][3], b[2][3][3];
-    for (int az = 0; az < 2; az++)
-      for (int ay = 0; ay < 2; ay++) lerp3(u[az][ay][0], u[az][ay][1], a[az][ay]);
-    for (int az = 0; az < 2; az++)
-      for (int qx = 0; qx < 3; qx++) {
-        double t[3];
-        lerp3(a[az][0][qx], a[az][1][qx], t);
-        for (int qy = 0; qy < 3; qy++) b[az][qy][qx] = t[qy];
-      }
-    for (int qy = 0; qy < 3; qy++)
-      for (int qx = 0; qx < 3; qx++) {
-        double t[3];
-        lerp3(b[0][qy][qx], b[1][qy][qx], t);
-        for (int qz = 0; qz < 3; qz++) uq[qz][qy][qx] = t[qz];
-      }
-  }
-  if (MODE == 0) {
-    double a[2][2][3], b[2][3][3];
-    for (int az = 0; az < 2; az++)
-      for (int ay = 0; ay < 2; ay++) lerp3(x[az][ay][0], x[az][ay][1], a[az][ay]);
-    for (int az = 0; az < 2; az++)
-      for (int qx = 0; qx < 3; qx++) {
-        double t[3];
-        lerp3(a[az][0][qx], a[az][1][qx], t);
-        for (int qy = 0; qy < 3; qy++) b[az][qy][qx] = t[qy];
-      }
-    for (int qy = 0; qy < 3; qy++)
-      for (int qx = 0; qx < 3; qx++) {
-        double t[3];
-        lerp3(b[0][qy][qx], b[1][qy][qx], t);
-        for (int qz = 0; qz < 3; qz++) xq[qz][qy][qx] = t[qz];
-      }
-  }
-  // integrand (the Gauss weights are folded into proj3)
-  for (int qz = 0; qz < 3; qz++)
-    for (int qy = 0; qy < 3; qy++)
-      for (int qx = 0; qx < 3; qx++) {
-        double v = uq[qz][qy][qx];
-        if (MODE == 0)
-          uq[qz][qy][qx] = (v * v) * xq[qz][qy][qx];
-        else
-          uq[qz][qy][qx] = (v * v) * v - v;
-      }
-  // project back: z, then y, then x
-  double b[2][3][3];
-  for (int qy = 0; qy < 3; qy++)
-    for (int qx = 0; qx < 3; qx++) {
-      double t[3] = {uq[0][qy][qx], uq[1][qy][qx], uq[2][qy][qx]};
-      proj3(t, b[0][qy][qx], b[1][qy][qx]);
+  double ue[2][2][3], xe[2][2][3];  // [az][ay][qx]
+  for (int az = 0; az < 2; az++)
+    for (int ay = 0; ay < 2; ay++) {
+      lerp3(u[az][ay][0], u[az][ay][1], ue[az][ay]);
+      if (MODE == 0) lerp3(x[az][ay][0], x[az][ay][1], xe[az][ay]);
     }
-  for (int az = 0; az < 2; az++) {
-    double a[2][3];
+  double acc[2][2][3];  // [az][ay][qx]: z- and y-projected integrand
+  for (int az = 0; az < 2; az++)
+    for (int ay = 0; ay < 2; ay++)
+      for (int qx = 0; qx < 3; qx++) acc[az][ay][qx] = 0.0;
+#pragma unroll
+  for (int qy = 0; qy < 3; qy++) {
+    const double wy0 = pw0(qy), wy1 = pw1(qy);
+#pragma unroll
     for (int qx = 0; qx < 3; qx++) {
-      double t[3] = {b[az][0][qx], b[az][1][qx], b[az][2][qx]};
-      proj3(t, a[0][qx], a[1][qx]);
+      const double u0 = lerp_at(ue[0][0][qx], ue[0][1][qx], qy);
+      const double u1 = lerp_at(ue[1][0][qx], ue[1][1][qx], qy);
+      double f[3];
+      if (MODE == 0) {
+        const double x0 = lerp_at(xe[0][0][qx], xe[0][1][qx], qy);
+        const double x1 = lerp_at(xe[1][0][qx], xe[1][1][qx], qy);
+        double uq[3], xq[3];
+        lerp3(u0, u1, uq);
+        lerp3(x0, x1, xq);
+        for (int qz = 0; qz < 3; qz++) f[qz] = (uq[qz] * uq[qz]) * xq[qz];
+      } else {
+        double uq[3];
+        lerp3(u0, u1, uq);
+        for (int qz = 0; qz < 3; qz++) f[qz] = (uq[qz] * uq[qz]) * uq[qz] - uq[qz];
+      }
+      double fb, ft;
+      proj3(f, fb, ft);
+      acc[0][0][qx] += wy0 * fb;
+      acc[0][1][qx] += wy1 * fb;
+      acc[1][0][qx] += wy0 * ft;
+      acc[1][1][qx] += wy1 * ft;
     }
-    for (int ay = 0; ay < 2; ay++) proj3(a[ay], E[az][ay][0], E[az][ay][1]);
   }
+  for (int az = 0; az < 2; az++)
+    for (int ay = 0; ay < 2; ay++) proj3(acc[az][ay], E[az][ay][0], E[az][ay][1]);
 }
 
 template <int MODE>
@@ -162,31 +155,46 @@ struct EShape {
   int zc, nzc;   // most planes per block, z-chunks (planes split evenly)
 };
 
-EShape element_shape(const Grid& g) {
+// Blocks of one launch that are resident at once: two blocks of 8 wavefronts
+// per CU (at most 128 VGPRs per lane) on 256 CUs.
+constexpr int64_t kResidentBlocks = 512;
+
+// z-chunks: a block's time grows with its element layers (zc + 1, one halo
+// layer), the launch's with the rounds of resident blocks; the count of
+// chunks minimises rounds * (zc + 1).
+EShape element_shape(const Grid& g, int count) {
   EShape s;
   s.epl = (g.N + 63) / 64;
   s.rowtiles = (g.nn + kRows - 1) / kRows;
-  if (g.dim == 2) {
-    s.zc = 1;
-    s.nzc = 1;
-  } else {
-    int64_t zc = ((int64_t)g.nn * s.rowtiles + 599) / 600;
-    zc = std::max<int64_t>(4, std::min<int64_t>(zc, 32));
-    zc = std::min<int64_t>(zc, g.nn);
-    s.nzc = (int)((g.nn + zc - 1) / zc);
-    s.zc = (g.nn + s.nzc - 1) / s.nzc;
+  s.zc = 1;
+  s.nzc = 1;
+  if (g.dim == 3) {
+    int64_t best = -1;
+    for (int nzc = 1; nzc <= std::min(g.nn, 128); nzc++) {
+      const int zc = (g.nn + nzc - 1) / nzc;  // planes of the largest chunk
+      const int64_t blocks = (int64_t)s.rowtiles * nzc * std::max(count, 1);
+      const int64_t cost = ((blocks + kResidentBlocks - 1) / kResidentBlocks) * (zc + 1);
+      if (best < 0 || cost < best) {
+        best = cost;
+        s.nzc = nzc;
+        s.zc = zc;
+      }
+    }
   }
   return s;
 }
 
-// EPLT > 0: elements per lane fixed at compile time (3D, keeps the z carry in
-// registers); EPLT == 0: taken from the shape (2D, no carry).
-template <int DIM, int MODE, int EPLT, class TX, class TO>
-__global__ void __launch_bounds__(64 * kWaves)
+// Elements per lane along x (epl) from the shape; the element-slot loop is
+// not unrolled, so the live registers are those of one element and two
+// blocks of 8 wavefronts fit on a CU.
+constexpr int kMaxEpl = 8;
+template <int DIM, int MODE, class TX, class TO>
+__global__ void __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4, 8)))
     k_element(Vec<const double> uv, Vec<const TX> xv, Vec<const double> addv, Vec<TO> outv,
               Grid g, EShape sh, Batch B, double alpha, double beta) {
   constexpr int NZ = (DIM == 3) ? 2 : 1;  // corner layers per element
   __shared__ double xch[2][kWaves][NZ][64];
+  __shared__ double carry[(DIM == 3) ? kWaves : 1][kMaxEpl + 1][64];  // lane-private
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -214,10 +222,9 @@ __global__ void __launch_bounds__(64 * kWaves)
     z0 = (int)(((int64_t)zch * nn) / sh.nzc);
     z1 = (int)(((int64_t)(zch + 1) * nn) / sh.nzc);
   }
-  const int epl = (EPLT > 0) ? EPLT : sh.epl;
-  double carry[EPLT + 1];
-#pragma unroll
-  for (int c = 0; c <= EPLT; c++) carry[c] = 0.0;
+  const int epl = sh.epl;
+  if constexpr (DIM == 3)
+    for (int c = 0; c <= epl; c++) carry[w][c][lane] = 0.0;
 
   const int lz0 = (DIM == 3) ? z0 - 1 : 0;
   const int lz1 = (DIM == 3) ? z1 - 1 : 0;
@@ -227,7 +234,7 @@ __global__ void __launch_bounds__(64 * kWaves)
     double prevR[2][NZ];  // lane-63 right contributions of the previous slot
     for (int a = 0; a < 2; a++)
       for (int cz = 0; cz < NZ; cz++) prevR[a][cz] = 0.0;
-#pragma unroll
+#pragma unroll 1
     for (int c = 0; c <= epl; c++) {
       const int i = lane + 64 * c;
       double L[2][NZ], R[2][NZ];  // [ay][cz]: left (ax=0) and right (ax=1) corner parts
@@ -290,7 +297,7 @@ __global__ void __launch_bounds__(64 * kWaves)
         double tot[NZ];
         for (int cz = 0; cz < NZ; cz++) tot[cz] = X[0][cz] + xch[buf][w - 1][cz][lane];
         const bool node_ok = (i <= N);
-        if (DIM == 2) {
+        if constexpr (DIM == 2) {
           if (node_ok) {
             int64_t idx = (int64_t)ey * nn + i;
             double v = sc * tot[0];
@@ -300,11 +307,11 @@ __global__ void __launch_bounds__(64 * kWaves)
         } else {
           if (ez >= z0 && node_ok) {
             int64_t idx = (int64_t)ez * plane + (int64_t)ey * nn + i;
-            double v = sc * ((EPLT > 0 ? carry[c] : 0.0) + tot[0]);
+            double v = sc * (carry[w][c][lane] + tot[0]);
             if (add) v += beta * add[idx];
             out[idx] = (TO)v;
           }
-          if (EPLT > 0) carry[c] = tot[NZ - 1];
+          carry[w][c][lane] = tot[NZ - 1];
         }
       }
       buf ^= 1;
@@ -318,25 +325,18 @@ template <class TX, class TO>
 hipError_t launch_element(const Grid& g, const Batch& B, int mode, Vec<const double> u,
                           Vec<const TX> x, Vec<const double> add, double alpha, double beta,
                           Vec<TO> out, hipStream_t st) {
-  EShape sh = element_shape(g);
+  EShape sh = element_shape(g, B.count);
   int64_t blocks = (int64_t)sh.rowtiles * sh.nzc * B.count;
   if (blocks > 0x7fffffff || B.count < 1) return hipErrorInvalidValue;
   dim3 grid((unsigned)blocks), block(64 * kWaves);
-#define OKD_EL(D, M, E)                                                                     \
-  hipLaunchKernelGGL((k_element<D, M, E, TX, TO>), grid, block, 0, st, u, x, add, out, g, sh, \
-                     B, alpha, beta)
+#define OKD_EL(D, M)                                                                        \
+  hipLaunchKernelGGL((k_element<D, M, TX, TO>), grid, block, 0, st, u, x, add, out, g, sh, B, \
+                     alpha, beta)
+  if (g.dim == 3 && sh.epl > kMaxEpl) return hipErrorInvalidValue;
   if (g.dim == 2) {
-    if (mode == 0) OKD_EL(2, 0, 0); else OKD_EL(2, 1, 0);
+    if (mode == 0) OKD_EL(2, 0); else OKD_EL(2, 1);
   } else {
-    int e = sh.epl;
-    if (e > 8) return hipErrorInvalidValue;
-    if (mode == 0) {
-      if (e == 1) OKD_EL(3, 0, 1); else if (e == 2) OKD_EL(3, 0, 2);
-      else if (e <= 4) { sh.epl = 4; OKD_EL(3, 0, 4); } else { sh.epl = 8; OKD_EL(3, 0, 8); }
-    } else {
-      if (e == 1) OKD_EL(3, 1, 1); else if (e == 2) OKD_EL(3, 1, 2);
-      else if (e <= 4) { sh.epl = 4; OKD_EL(3, 1, 4); } else { sh.epl = 8; OKD_EL(3, 1, 8); }
-    }
+    if (mode == 0) OKD_EL(3, 0); else OKD_EL(3, 1);
   }
 #undef OKD_EL
   return hipGetLastError();
