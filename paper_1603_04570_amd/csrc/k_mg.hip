@@ -16,6 +16,8 @@
 // Hence (M + alpha K)^-1 = V (Lambda Gamma)^-1 V^T; V is symmetric.
 #include "ok_internal.h"
 
+#include <algorithm>
+
 namespace okd {
 
 namespace {
@@ -122,6 +124,94 @@ __global__ void __launch_bounds__(256)
   bcv.at(inst)[q] = (T)s;
 }
 
+// 3D restriction streamed along z: a block owns a tile of kRsTI x kRsTJ
+// coarse nodes (x, y) and a chunk of coarse planes; each fine plane of its
+// footprint (2 kRsTJ + 1 rows of 2 ti + 1 nodes, zero outside the grid) is
+// read once, staged in LDS (double-buffered, one barrier per plane), combined
+// along x and y with the weights (1/2, 1, 1/2), and accumulated along z in a
+// register: fine plane 2K adds to coarse plane K with weight 1, plane 2K + 1
+// with weight 1/2 to K and to K + 1.  The next plane's loads are issued
+// before the current plane is combined.
+constexpr int kRsTI = 64, kRsTJ = 4;
+constexpr int kRsFC = 2 * kRsTI + 1, kRsFR = 2 * kRsTJ + 1;
+constexpr int kRsLoads = (kRsFC * kRsFR + 255) / 256;
+
+template <class T>
+__global__ void __launch_bounds__(256)
+    k_restrict_zs(Vec<const T> rv, Vec<T> bcv, Grid f, Grid c, Batch B, int tx, int ty, int ti,
+                  int kc, int nzc) {
+  __shared__ double F[2][kRsFR][kRsFC];
+  const int per = tx * ty * nzc;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int inst = lb / per;
+  if (B.act && !B.act[inst]) return;
+  int rem = lb - inst * per;
+  const int bx = rem % tx;
+  rem /= tx;
+  const int by = rem % ty, bz = rem / ty;
+  const int I0 = bx * ti, J0 = by * kRsTJ;
+  const int K0 = bz * kc, K1 = min(K0 + kc, c.nn);
+  const int z0 = max(2 * K0 - 1, 0), z1 = min(2 * K1 - 1, f.N);
+  const T* __restrict__ r = rv.at(inst);
+  T* __restrict__ bc = bcv.at(inst);
+  // this thread's staging slots: fine (row, col) of the footprint, its
+  // offset in a fine plane (-1 outside the grid) and its LDS word
+  const int ncol = 2 * ti + 1, nel = kRsFR * ncol;
+  int off[kRsLoads], lw[kRsLoads];
+#pragma unroll
+  for (int u = 0; u < kRsLoads; u++) {
+    const int e = threadIdx.x + 256 * u;
+    off[u] = -1;
+    lw[u] = -1;
+    if (e < nel) {
+      const int row = e / ncol, col = e - row * ncol;
+      lw[u] = row * kRsFC + col;
+      const int fy = 2 * J0 - 1 + row, fx = 2 * I0 - 1 + col;
+      if (fy >= 0 && fy <= f.N && fx >= 0 && fx <= f.N) off[u] = fy * f.nn + fx;
+    }
+  }
+  // output node of this thread
+  const int i = threadIdx.x % kRsTI, j = threadIdx.x / kRsTI;
+  const bool out_ok = i < ti && I0 + i < c.nn && J0 + j < c.nn;
+  const int64_t oq = (int64_t)(J0 + j) * c.nn + (I0 + i);
+  double pf[kRsLoads];
+#pragma unroll
+  for (int u = 0; u < kRsLoads; u++)
+    pf[u] = off[u] >= 0 ? ld(r + (int64_t)z0 * f.plane + off[u]) : 0.0;
+  double acc = 0.0;
+  int buf = 0;
+  for (int zf = z0; zf <= z1; zf++) {
+#pragma unroll
+    for (int u = 0; u < kRsLoads; u++)
+      if (lw[u] >= 0) (&F[buf][0][0])[lw[u]] = pf[u];
+    if (zf < z1) {
+#pragma unroll
+      for (int u = 0; u < kRsLoads; u++)
+        pf[u] = off[u] >= 0 ? ld(r + (int64_t)(zf + 1) * f.plane + off[u]) : 0.0;
+    }
+    __syncthreads();
+    double p = 0.0;
+    if (out_ok) {
+#pragma unroll
+      for (int dy = 0; dy < 3; dy++) {
+        const double* row = &F[buf][2 * j + dy][2 * i];
+        const double t = 0.5 * row[0] + row[1] + 0.5 * row[2];
+        p += (dy == 1 ? 1.0 : 0.5) * t;
+      }
+    }
+    if ((zf & 1) == 0) {
+      acc += p;
+      if (zf == f.N && out_ok) bc[(int64_t)(zf >> 1) * c.plane + oq] = (T)acc;
+    } else {
+      const int K = zf >> 1;
+      acc += 0.5 * p;
+      if (K >= K0 && out_ok) bc[(int64_t)K * c.plane + oq] = (T)acc;
+      acc = 0.5 * p;
+    }
+    buf ^= 1;
+  }
+}
+
 // Prolongation works on one coarse row (J, K) and a segment of at most
 // kProlongW coarse nodes along x per block: the four coarse rows that the
 // segment's fine nodes interpolate from are staged in LDS with coalesced
@@ -148,6 +238,33 @@ __global__ void __launch_bounds__(256)
   const int I0 = (int)((int64_t)seg * c.nn / nseg), I1 = (int)((int64_t)(seg + 1) * c.nn / nseg);
   const T* __restrict__ ec = ecv.at(inst);
   T* __restrict__ x = xv.at(inst);
+  // fine nodes (2I0 .. min(2 I1, nn_f) - 1) x rows 2J + a x planes 2K + b:
+  // thread t owns columns t and t + 256 of every fine row of the block, and
+  // issues all its loads of x before the first sum (enough bytes in flight
+  // to stream at HBM rate), before the coarse rows are staged
+  const int nfx = min(2 * I1, f.nn) - 2 * I0;
+  constexpr int kCols = 2 * kProlongW / 256;  // columns per thread
+  constexpr int kRowsP = 2 * NZ;              // fine rows per block
+  T xo[kRowsP][kCols];
+  int64_t qo[kRowsP][kCols];
+#pragma unroll
+  for (int rr = 0; rr < kRowsP; rr++) {
+    const int a = rr & 1, b = rr >> 1;  // fine row 2J + a, plane 2K + b
+    const int fj = 2 * J + a, fk = 2 * K + b;
+    const bool row_ok = fj <= f.N && (DIM == 2 || fk <= f.N);
+#pragma unroll
+    for (int v = 0; v < kCols; v++) {
+      const int ix = threadIdx.x + 256 * v;
+      qo[rr][v] = -1;
+      if (row_ok && ix < nfx) {
+        const int fi = 2 * I0 + ix;
+        const int64_t q =
+            (DIM == 3) ? ((int64_t)fk * f.nn + fj) * f.nn + fi : (int64_t)fj * f.nn + fi;
+        qo[rr][v] = q;
+        xo[rr][v] = x[q];
+      }
+    }
+  }
   // coarse rows J, J+1 of planes K, K+1 (clamped to the grid; a clamped row
   // only feeds fine rows that do not exist)
   for (int t = threadIdx.x; t < NZ * 2 * LW; t += blockDim.x) {
@@ -157,32 +274,33 @@ __global__ void __launch_bounds__(256)
     cr[dz][dy][o] = ld(ec + ((int64_t)Kc * c.plane + (int64_t)Jc * c.nn + Ic));
   }
   __syncthreads();
-  // fine nodes (2I0 .. min(2 I1, nn_f) - 1) x rows 2J + a x planes 2K + b
-  const int nfx = min(2 * I1, f.nn) - 2 * I0;
-  const int nrow = 2 * NZ;
-  for (int e = threadIdx.x; e < nrow * nfx; e += blockDim.x) {
-    const int rr = e / nfx, ix = e - rr * nfx;
-    const int a = rr & 1, b = rr >> 1;  // fine row 2J + a, plane 2K + b
-    const int fj = 2 * J + a, fk = 2 * K + b, fi = 2 * I0 + ix;
-    if (fj > f.N || (DIM == 3 && fk > f.N)) continue;
-    const int li0 = (fi >> 1) - I0, li1 = ((fi + 1) >> 1) - I0;
-    const bool two_i = (fi & 1) != 0, two_j = a != 0, two_k = b != 0;
+#pragma unroll
+  for (int rr = 0; rr < kRowsP; rr++) {
+    const int a = rr & 1, b = rr >> 1;
+    const bool two_j = a != 0, two_k = b != 0;
     const double wk = two_k ? 0.5 : 1.0;
     const double wj = wk * (two_j ? 0.5 : 1.0);
-    const double wi = two_i ? 0.5 : 1.0;
-    double s = 0.0;
 #pragma unroll
-    for (int za = 0; za < NZ; za++) {
-      if (za && !two_k) break;
+    for (int v = 0; v < kCols; v++) {
+      if (qo[rr][v] < 0) continue;
+      const int ix = threadIdx.x + 256 * v;
+      const int fi = 2 * I0 + ix;
+      const int li0 = (fi >> 1) - I0, li1 = ((fi + 1) >> 1) - I0;
+      const bool two_i = (fi & 1) != 0;
+      const double wi = two_i ? 0.5 : 1.0;
+      double s = 0.0;
 #pragma unroll
-      for (int yb = 0; yb < 2; yb++) {
-        if (yb && !two_j) break;
-        s += wj * wi * cr[za][yb][li0];
-        if (two_i) s += wj * wi * cr[za][yb][li1];
+      for (int za = 0; za < NZ; za++) {
+        if (za && !two_k) break;
+#pragma unroll
+        for (int yb = 0; yb < 2; yb++) {
+          if (yb && !two_j) break;
+          s += wj * wi * cr[za][yb][li0];
+          if (two_i) s += wj * wi * cr[za][yb][li1];
+        }
       }
+      x[qo[rr][v]] = (T)(ld(&xo[rr][v]) + s);
     }
-    const int64_t q = (DIM == 3) ? ((int64_t)fk * f.nn + fj) * f.nn + fi : (int64_t)fj * f.nn + fi;
-    x[q] = (T)(ld(x + q) + s);
   }
 }
 
@@ -331,6 +449,23 @@ __global__ void __launch_bounds__(256)
 template <class T>
 hipError_t launch_restrict(const Grid& fine, const Grid& coarse, const Batch& B, Vec<const T> r,
                            Vec<T> bc, hipStream_t st) {
+  if (fine.N != 2 * coarse.N) return hipErrorInvalidValue;
+  if (fine.dim == 3 && coarse.nn >= 100) {
+    // streamed along z; chunks of coarse planes so that the launch holds
+    // about 1500 or more blocks
+    const int tx = (coarse.nn + kRsTI - 1) / kRsTI;
+    const int ti = (coarse.nn + tx - 1) / tx;
+    const int ty = (coarse.nn + kRsTJ - 1) / kRsTJ;
+    const int64_t tiles = (int64_t)tx * ty * B.count;
+    int nzc = (int)std::min<int64_t>(coarse.nn, std::max<int64_t>(1, (1536 + tiles - 1) / tiles));
+    const int kc = (coarse.nn + nzc - 1) / nzc;
+    nzc = (coarse.nn + kc - 1) / kc;
+    const int64_t nblk = tiles * nzc;
+    if (nblk > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_restrict_zs<T>), dim3((unsigned)nblk), dim3(256), 0, st, r, bc, fine,
+                       coarse, B, tx, ty, ti, kc, nzc);
+    return hipGetLastError();
+  }
   const int per = (int)((coarse.nodes + 255) / 256);
   dim3 grid((unsigned)((int64_t)per * B.count)), block(256);
   if (fine.dim == 2)
