@@ -908,7 +908,8 @@ __global__ void __launch_bounds__(NT)
     const int q1 = pz - 1;  // stage-1 output plane
     const int o = pz - 2;   // stage-2 output plane
     const int buf = pz & 1;
-    __syncthreads();
+    // no barrier before staging: every read of LA in the previous trip
+    // precedes that trip's barrier before stage 2
     if (insideA) {
 #pragma unroll
       for (int k = 0; k < FA; k++) {
@@ -1148,7 +1149,8 @@ __global__ void __launch_bounds__(NT)
     const int q1 = pz - 1;  // stage-1 output plane
     const int o = pz - 2;   // stage-2 output plane
     const int buf = pz & 1;
-    __syncthreads();
+    // no barrier before staging: every read of LA in the previous trip
+    // precedes that trip's barrier before stage 2
     if (insideA) {
 #pragma unroll
       for (int k = 0; k < P1; k++) {
@@ -1410,7 +1412,8 @@ __global__ void __launch_bounds__(NT)
     const int q1 = pz - 1;  // stage-1 output plane
     const int o = pz - 2;   // stage-2 output plane
     const int buf = pz & 1;
-    __syncthreads();
+    // no barrier before staging: every read of LA in the previous trip
+    // precedes that trip's barrier before stage 2
     if (insideA) {
 #pragma unroll
       for (int k = 0; k < FA; k++) {
@@ -1979,7 +1982,8 @@ __global__ void __launch_bounds__(NT)
     const int q1 = pz - 1;  // stage-1 output plane
     const int o = pz - 2;   // stage-2 output plane
     const int buf = pz & 1;
-    __syncthreads();
+    // no barrier before staging: every read of LA in the previous trip
+    // precedes that trip's barrier before stage 2
     if (insideA) {
 #pragma unroll
       for (int k = 0; k < P1; k++) {

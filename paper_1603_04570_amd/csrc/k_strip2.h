@@ -80,8 +80,8 @@ __global__ void __launch_bounds__(BX * BY / P)
                                                                               : o2v.at(inst);
   T* __restrict__ o3 = (MODE == kStripCheb && !LAST2) ? o3v.at(inst) : nullptr;
 
-  // zero the stage-1 buffer once (its ring is never written; the barrier at
-  // the top of the first trip orders this before any stage-1 write)
+  // zero the stage-1 buffer once (its ring is never written; the barrier
+  // after the first trip's staging orders this before any stage-1 write)
   for (int t = tid; t < EA; t += NT) LB[t] = 0.0;
 
   // input staging: slot t = tid + NT k holds window node (t % WA - 1, t / WA - 1)
@@ -205,7 +205,8 @@ __global__ void __launch_bounds__(BX * BY / P)
     const bool insideA = (pz >= 0 && pz <= N);
     const int q1 = pz - 1;  // stage-1 plane
     const int o = pz - 2;   // stage-2 (output) plane
-    __syncthreads();
+    // no barrier before staging: every read of LA in the previous trip
+    // precedes that trip's barrier before stage 2, and stage 2 reads only LB
     if (insideA) {
       const double fz = (SC1 && (pz == 0 || pz == N)) ? 2.0 : 1.0;
 #pragma unroll
