@@ -615,6 +615,30 @@ def bench_single(args, torch, ok, cfg):
     return out
 
 
+def kernel_probe(args, torch, ok, cfg):
+    """The preconditioner's kernels alone, in the shapes the autotuner picks:
+    --kernel-probe V-cycles of S^ and Chebyshev applications on M on a seeded
+    right-hand side of the configuration's finest grid (not a benchmark line:
+    a workload for hardware-counter runs of those kernels)."""
+    from paper_1603_04570_amd.inputs import uniform01
+    prec = ok.OK_MIXED if args.precision == "mixed" else ok.OK_FP64
+    P = ok.Problem(_single_params(ok, cfg, prec))
+    tuned = P.autotune()
+    nodes = (cfg["n"] + 1) ** cfg["dim"]
+    r = torch.from_numpy(uniform01(5, nodes) - 0.5).cuda()
+    x = torch.empty_like(r)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.kernel_probe):
+        P.mg_apply(r, x)
+    for _ in range(args.kernel_probe):
+        P.cheb_mass(r, x)
+    torch.cuda.synchronize()
+    return {"kernel_probe": args.config, "precision": "mixed" if prec else "fp64",
+            "applications": args.kernel_probe, "autotuned_shapes": tuned,
+            "seconds": time.perf_counter() - t0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -643,6 +667,10 @@ def main():
                     help="Arnoldi orthogonalisation: icwy (default; two passes, modified "
                          "Gram-Schmidt in inverse compact WY form) or mgs (one pass per "
                          "projection)")
+    ap.add_argument("--kernel-probe", type=int, default=0, metavar="K",
+                    help="single-problem configs: instead of timesteps, autotune and run K "
+                         "V-cycles (ok_mg_apply) and K Chebyshev applications on M "
+                         "(ok_cheb_mass) on the finest grid, for hardware-counter runs")
     ap.add_argument("--trace-ranges", action="store_true",
                     help="ROCTX ranges per timestep, Newton and FGMRES iteration "
                          "(for rocprofv3 --marker-trace)")
@@ -687,6 +715,9 @@ def main():
         print(json.dumps(bench_serve(args, torch, ok)), flush=True)
         return
     cfg = dict(CONFIGS[args.config])
+    if args.kernel_probe > 0:
+        print(json.dumps(kernel_probe(args, torch, ok, cfg)), flush=True)
+        return
     print(json.dumps(bench_single(args, torch, ok, cfg)), flush=True)
 
 

@@ -22,6 +22,13 @@
         two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs, each scaled by
         what the same counter reads for a plain copy kernel of BYTES bytes read
         and BYTES bytes written (the copy runs of ``bench.py --calibrate-copy``).
+
+    python -m paper_1603_04570_amd.profsum counters --csv A.csv [--csv B.csv ...] \
+        --kernel SUBSTRING [--kernel SUBSTRING ...] [--grid G]
+        mean value per dispatch of every counter in the ``--pmc`` runs A, B, ...
+        for each kernel whose name contains a SUBSTRING, over its dispatches of
+        grid size G (default: its most dispatched one), with instructions per wavefront and the
+        shares of wave cycles that the SQ_* cycle counters give
 """
 from __future__ import annotations
 
@@ -130,12 +137,58 @@ def traffic(fetch, write, copy_fetch, copy_write, copy_bytes, kernel, main_grid=
             "traffic_bytes_per_dispatch": fb + wb}
 
 
+def counters(paths, kernels, grid_size=None) -> str:
+    by = {}
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"]
+            if not any(k in name for k in kernels):
+                continue
+            by.setdefault(name, []).append((int(r["Grid_Size"]), r["Counter_Name"],
+                                            float(r["Counter_Value"])))
+    if not by:
+        raise SystemExit(f"no dispatch of a kernel containing {kernels!r}")
+    out = []
+    for name, rows in sorted(by.items()):
+        sizes = [g for g, _, _ in rows]
+        grid = grid_size if grid_size else max(set(sizes), key=sizes.count)
+        if grid not in sizes:
+            continue
+        vals = {}
+        for g, c, v in rows:
+            if g == grid:
+                vals.setdefault(c, []).append(v)
+        d = {c: statistics.mean(v) for c, v in vals.items()}
+        out.append(f"kernel: {short_name(name)}")
+        out.append(f"  grid {grid}, dispatches per counter {min(len(v) for v in vals.values())}")
+        for c in sorted(d):
+            out.append(f"  {c}: {d[c]:.0f}")
+        w = d.get("SQ_WAVES")
+        if w:
+            per = [f"{d[c] / w:.0f} {c[9:]}" for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU",
+                                                         "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
+                                                         "SQ_INSTS_VMEM_WR") if c in d]
+            out.append("  per wavefront: " + ", ".join(per))
+        wc = d.get("SQ_WAVE_CYCLES")
+        if wc:
+            sh = [f"{c[3:].lower()} {100 * d[c] / wc:.0f}%" for c in
+                  ("SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_SCA",
+                   "SQ_ACTIVE_INST_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_ANY") if c in d]
+            if sh:
+                out.append("  of wave cycles: " + ", ".join(sh))
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("stats")
     a.add_argument("csv")
     a.add_argument("top", nargs="?", type=int, default=25)
+    e = sub.add_parser("counters")
+    e.add_argument("--csv", action="append", required=True)
+    e.add_argument("--kernel", action="append", required=True)
+    e.add_argument("--grid", type=int, default=0)
     c = sub.add_parser("bygrid")
     c.add_argument("csv")
     c.add_argument("top", nargs="?", type=int, default=40)
@@ -155,6 +208,8 @@ def main():
         print(bygrid(args.csv, args.top))
     elif args.cmd == "ranges":
         print(ranges(args.csv))
+    elif args.cmd == "counters":
+        print(counters(args.csv, args.kernel, args.grid))
     else:
         r = traffic(args.fetch, args.write, args.copy_fetch, args.copy_write, args.copy_bytes,
                     args.kernel, args.main_grid, args.exclude)

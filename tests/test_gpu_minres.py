@@ -139,3 +139,61 @@ def test_minres_rejects_fgmres_context():
     u = dev(np.zeros(17 * 17))
     _, _, st = P.minres(u, dev(np.ones(2 * 17 * 17)))
     assert st == -1
+
+
+def test_sym_apply_rows_at_full_size():
+    """3D 256^3: rows of A_sym at sampled nodes (and the grid's corners) equal
+    the oracle's matrix-free Jacobian rows of eq. (newton) rearranged: row 1
+    of A_sym [a; b] is row 1 of J [b; a] divided by 1 + dt th sigma, row 2 is
+    row 2 of J [b; a]."""
+    from oracle.okref import local_jacobian, make_params
+    from paper_1603_04570_amd import ok
+    from paper_1603_04570_amd.inputs import CONFIGS, sample_nodes
+    cfg = CONFIGS["3d256"]
+    dim, n = cfg["dim"], cfg["n"]
+    say("full-size A_sym rows", dim, n)
+    P = ok.Problem(ok.default_params(dim=dim, n=n, eps=cfg["eps"], sigma=cfg["sigma"],
+                                     m=cfg["m"], dt=cfg["dt"], theta=cfg["theta"],
+                                     linear_solver=MINRES))
+    nodes = (n + 1) ** dim
+    u0, _ = noise_state(dim, n, cfg["m"], cfg["seed"])
+    x = uniform01(92, 2 * nodes) - 0.5
+    y = host(P.sym_apply(dev(u0), dev(x)))
+    idx = sample_nodes(nodes, 4096, seed=80)
+    idx = np.unique(np.concatenate([idx, [0, n, nodes - 1, (n + 1) ** 2 - 1]]))
+    prm = make_params(dim, n, cfg["eps"], cfg["sigma"], cfg["m"], cfg["dt"], cfg["theta"])
+    j1, j2 = local_jacobian(prm, u0, np.concatenate([x[nodes:], x[:nodes]]), idx)
+    sA = 1.0 + cfg["dt"] * cfg["theta"] * cfg["sigma"]
+    ref = np.concatenate([j1 / sA, j2])
+    got = np.concatenate([y[idx], y[nodes + idx]])
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_minres_timestep_at_full_size():
+    """3D 256^3, one timestep with MINRES: the oracle's residual rows at
+    sampled nodes of the new state are below the Newton tolerance, and it
+    agrees with the FGMRES timestep to the Newton tolerance's reach."""
+    from oracle.okref import local_residual, make_params
+    from paper_1603_04570_amd import ok
+    from paper_1603_04570_amd.inputs import CONFIGS, sample_nodes
+    cfg = CONFIGS["3d256"]
+    dim, n = cfg["dim"], cfg["n"]
+    say("full-size MINRES timestep", dim, n)
+    kw = dict(dim=dim, n=n, eps=cfg["eps"], sigma=cfg["sigma"], m=cfg["m"], dt=cfg["dt"],
+              theta=cfg["theta"])
+    u0, w0 = noise_state(dim, n, cfg["m"], cfg["seed"])
+    Pm = ok.Problem(ok.default_params(**kw, linear_solver=MINRES))
+    u, w = dev(u0), dev(w0)
+    st = Pm.timestep(u, w, 1)
+    assert st.status == 0
+    say("  its", st.its())
+    uh, wh = host(u), host(w)
+    del Pm
+    idx = sample_nodes(uh.size, 4096, seed=81)
+    prm = make_params(dim, n, cfg["eps"], cfg["sigma"], cfg["m"], cfg["dt"], cfg["theta"])
+    f1, f2 = local_residual(prm, uh, wh, u0, None, idx)
+    assert max(np.abs(f1).max(), np.abs(f2).max()) <= 1e-10
+    Pf = ok.Problem(ok.default_params(**kw))
+    uf, wf = dev(u0), dev(w0)
+    assert Pf.timestep(uf, wf, 1).status == 0
+    assert relnorm(uh, host(uf)) < 1e-8 and relnorm(wh, host(wf)) < 1e-8
