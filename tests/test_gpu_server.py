@@ -183,3 +183,49 @@ def test_stop_without_drain_accounts_every_request():
     assert all(r["status"] in (0, -7) for r in res)
     assert sorted(r["ticket"] for r in res) == list(range(10))
     S.close()
+
+
+def test_served_minres_simulations():
+    """Simulations whose Newton steps use MINRES on the symmetric system (FP64)
+    served beside FGMRES ones: separate classes, each final state equal bit for
+    bit to its solo run and to the oracle run with the same linear solver
+    (1e-10 relative, same iteration counts)."""
+    from oracle.okref import Oracle
+    from paper_1603_04570_amd import ok
+    specs = [sweep_instance(i, sizes=(32,)) for i in range(2)]
+    specs += [sweep_instance(2, sizes=(64,)),
+              dict(dim=3, n=16, eps=0.02, sigma=100.0, m=0.1, theta=1.0, dt=2e-4, seed=9)]
+    solvers = [0, 1, 1, 1]
+    plist = [ok.default_params(dim=s["dim"], n=s["n"], eps=s["eps"], sigma=s["sigma"], m=s["m"],
+                               dt=s["dt"], theta=s["theta"], linear_solver=ls)
+             for s, ls in zip(specs, solvers)]
+    S = start_server(specs, plist, 8 << 30, max_slots_per_pool=4)
+    t, sim = poisson_arrivals(300.0, 12, len(specs), seed=78)
+    S.start()
+    for k in range(len(t)):
+        S.submit(int(sim[k]), 1, float(t[k]) + S.now())
+    S.stop(drain=True)
+    res = S.poll(4096)
+    assert len(res) == len(t) and all(r["status"] == 0 for r in res), res
+    total = np.zeros(len(specs), dtype=int)
+    its = np.zeros(len(specs), dtype=int)
+    for r in res:
+        total[r["sim"]] += 1
+        its[r["sim"]] += r["fgmres_its"]
+    for i, s in enumerate(specs):
+        if total[i] == 0:
+            continue
+        us, ws = S.get_state(i)
+        us, ws = us.cpu().numpy(), ws.cpu().numpy()
+        uo, wo = solo_state(plist[i], s, int(total[i]))
+        assert np.array_equal(us, uo) and np.array_equal(ws, wo), (i, s)
+        u0, w0 = noise_state(s["dim"], s["n"], s["m"], s["seed"])
+        o = Oracle(s["dim"], s["n"], s["eps"], s["sigma"], s["m"], s["dt"], s["theta"],
+                   linear_solver=solvers[i])
+        ur, wr, info, st = o.timestep(u0, w0, int(total[i]))
+        assert st == 0
+        print(f"sim {i} solver {solvers[i]}: {total[i]} steps, its {its[i]} oracle "
+              f"{info.fgmres_its_total}, u {rel(us, ur):.1e} w {rel(ws, wr):.1e}", flush=True)
+        assert rel(us, ur) <= 1e-10 and rel(ws, wr) <= 1e-10, i
+        assert its[i] == info.fgmres_its_total, (i, its[i], info.fgmres_its_total)
+    S.close()
