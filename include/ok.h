@@ -316,7 +316,8 @@ int ok_set_option(int32_t option, int32_t value);
  *     nodes, the tile (about items*threads nodes) chosen by the library;
  *     CHEB2_STRIP, MG_PRE_STRIP, MG_POST_STRIP (3D only): items selects the
  *     window (1: 32x32 nodes, strips of 4; 2: 32x16, strips of 2; 3: 64x16,
- *     strips of 4), threads must be 256.  items = 0 removes the entry
+ *     strips of 4; 4: 32x24, strips of 3; 5: 64x12, strips of 3), threads
+ *     must be 256.  items = 0 removes the entry
  *     (built-in default shape; threads and zchunks are then ignored);
  *   zchunks: the n+1 planes of the streaming axis are split evenly into
  *     1..n+1 ranges, one block per (plane chunk, range).

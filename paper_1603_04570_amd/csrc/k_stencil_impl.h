@@ -1802,6 +1802,8 @@ hipError_t launch_strip(const Grid& g, const Batch& B, int key, int lev, int kk,
     case 1: return launch_strip_cfg<1, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, st);
     case 2: return launch_strip_cfg<2, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, st);
     case 3: return launch_strip_cfg<3, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, st);
+    case 4: return launch_strip_cfg<4, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, st);
+    case 5: return launch_strip_cfg<5, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -38,13 +38,21 @@ struct StripCfg {
   int bx, by, p, nt;
 };
 __host__ __device__ constexpr StripCfg strip_cfg(int id) {
-  return id == 1 ? StripCfg{32, 32, 4, 256}
-                 : (id == 2 ? StripCfg{32, 16, 2, 256} : StripCfg{64, 16, 4, 256});
+  return id == 1   ? StripCfg{32, 32, 4, 256}
+         : id == 2 ? StripCfg{32, 16, 2, 256}
+         : id == 3 ? StripCfg{64, 16, 4, 256}
+         : id == 4 ? StripCfg{32, 24, 3, 256}
+                   : StripCfg{64, 12, 3, 256};
 }
-constexpr int kStripCfgs = 3;
+constexpr int kStripCfgs = 5;
+// Strips of 3 nodes are compiled for three wavefronts per SIMD (at most 168
+// VGPRs; the stiffness variants then spill a few values), the others for the
+// compiler's own choice (two wavefronts per SIMD at 4 nodes per thread).
+constexpr int strip_min_waves(int p) { return p == 3 ? 3 : 1; }
 
 template <int BX, int BY, int P, class T, int MODE, bool LAST2>
 __global__ void __launch_bounds__(BX * BY / P)
+    __attribute__((amdgpu_waves_per_eu(strip_min_waves(P), 8)))
     k_strip2(Grid g, StencilShape sh, int ntx, Batch B, int lev, int kk, int osc,
              Vec<const T> av, Vec<const T> pv, Vec<T> xv, Vec<T> o2v, Vec<T> o3v) {
   constexpr int NT = BX * BY / P;

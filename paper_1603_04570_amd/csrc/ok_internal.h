@@ -145,7 +145,7 @@ constexpr int kFusedStripKey = 23, kMgPreStripKey = 24, kMgPostStripKey = 25;
 // windows per plane of grid g.
 int strip_threads(int cfg);
 int64_t strip_windows(const Grid& g, int cfg);
-constexpr int kStripConfigs = 3;
+constexpr int kStripConfigs = 5;
 // In-plane tile of that kernel: tx x ty nodes, ntx tiles per row of tiles.
 struct TileGeom {
   int tx, ty, ntx, nty;

@@ -137,13 +137,15 @@ def test_launch_shape_arguments(lib):
     assert f(3, 0, 1, 0, 4, 256, 5) == E       # n
     assert f(3, 64, 12, 0, 4, 256, 5) == E     # kernel
     assert f(3, 64, 0, 0, 2, 256, 5) == E
-    # strips (9, 10, 11): 3D, window configuration 1..3, 256 threads
+    # strips (9, 10, 11): 3D, window configuration 1..5, 256 threads
     assert f(3, 64, 9, 0, 1, 256, 5) == 0 and f(3, 64, 10, 1, 2, 256, 9) == 0
     assert f(3, 64, 11, 0, 3, 256, 65) == 0
+    assert f(3, 64, 9, 0, 4, 256, 5) == 0 and f(3, 64, 10, 0, 5, 256, 5) == 0
+    assert f(3, 64, 9, 0, 0, 0, 0) == 0 and f(3, 64, 10, 0, 0, 0, 0) == 0
     assert f(3, 64, 9, 0, 0, 0, 0) == 0 and f(3, 64, 10, 1, 0, 0, 0) == 0
     assert f(3, 64, 11, 0, 0, 0, 0) == 0
     assert f(2, 64, 9, 0, 1, 256, 5) == E      # strips: 3D only
-    assert f(3, 64, 9, 0, 4, 256, 5) == E      # configurations 1..3
+    assert f(3, 64, 9, 0, 6, 256, 5) == E      # configurations 1..5
     assert f(3, 64, 10, 0, 1, 512, 5) == E     # 256 threads
     assert f(3, 64, 6, 0, 2, 512, 5) == 0      # fused pair on in-plane tiles
     assert f(3, 64, 7, 0, 1, 256, 9) == 0 and f(3, 64, 8, 1, 2, 512, 3) == 0  # smoothers

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-STRIP_CFGS = (1, 2, 3)  # window configurations of the strip kernels (32x32/4, 32x16/2, 64x16/4)
+STRIP_CFGS = (1, 2, 3, 4, 5)  # window configurations of the strip kernels (32x32/4, 32x16/2, 64x16/4, 32x24/3, 64x12/3)
 
 
 def cheb_mass(P, r, nodes):

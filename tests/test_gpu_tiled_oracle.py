@@ -88,7 +88,7 @@ def test_tiled_kernels_timestep_matches_oracle(precision, items, threads):
     compare(got, oracle_run(), precision)
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3])
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_strip_kernels_timestep_matches_oracle(precision, cfg):
     """The same with the fused pairs and smoothers on overlapping windows with

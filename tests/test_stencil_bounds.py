@@ -260,7 +260,8 @@ def test_tiled_fused_kernel_indices(items, NT):
 
 
 # ---------------------------------------------------------------- k_strip2
-STRIP_CFGS = {1: (32, 32, 4, 256), 2: (32, 16, 2, 256), 3: (64, 16, 4, 256)}
+STRIP_CFGS = {1: (32, 32, 4, 256), 2: (32, 16, 2, 256), 3: (64, 16, 4, 256), 4: (32, 24, 3, 256),
+              5: (64, 12, 3, 256)}
 
 
 def emulate_strip(N, cfg):
@@ -301,7 +302,7 @@ def emulate_strip(N, cfg):
     return ntx * nty
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3])
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5])
 def test_strip_fused_kernel_indices(cfg):
     for N in GRIDS_3D:
         nn = N + 1
