@@ -58,7 +58,8 @@ enum ok_status {
   OK_E_INVALID = -1,       /* bad d, N, parameter range, null/misaligned pointer */
   OK_E_WORKSPACE = -2,     /* workspace null, misaligned or smaller than required */
   OK_E_HIP = -3,           /* a HIP runtime call or kernel launch failed */
-  OK_E_GMRES_MAXIT = -4,   /* FGMRES hit gmres_max_restarts without converging */
+  OK_E_GMRES_MAXIT = -4,   /* FGMRES hit gmres_max_restarts without converging
+                              (MINRES: its iteration limit)                    */
   OK_E_NEWTON_MAXIT = -5,  /* Newton hit newton_max_it without converging */
   OK_E_NONFINITE = -6,     /* NaN/Inf in ||F|| or in the Krylov recurrence */
   OK_E_REJECTED = -7       /* serving: request refused (queue full) or dropped at a stop */
@@ -115,10 +116,12 @@ typedef struct {
 
 typedef struct {
   int32_t status;          /* result of this Newton iteration's linear solve    */
-  int32_t fgmres_its;      /* FGMRES iterations (all cycles)                     */
-  int32_t restarts;        /* FGMRES restarts taken                              */
+  int32_t fgmres_its;      /* FGMRES iterations (all cycles); MINRES iterations
+                              for OK_SOLVER_MINRES                               */
+  int32_t restarts;        /* FGMRES restarts taken (0 for MINRES)               */
   double fnorm;            /* ||F(u,w)||_2 before the update                     */
-  double lin_res;          /* final FGMRES residual estimate / ||F||             */
+  double lin_res;          /* final FGMRES residual estimate / ||F||; MINRES:
+                              preconditioned residual norm / its initial value */
 } ok_newton_info;
 
 #define OK_HIST 256
@@ -128,7 +131,8 @@ typedef struct {
   int32_t newton_its;                  /* total over all steps                   */
   int32_t fgmres_its_total;
   int32_t newton_per_step[OK_HIST];    /* Newton iterations of each step         */
-  int32_t fgmres_its[OK_HIST];         /* FGMRES iterations of each Newton iter  */
+  int32_t fgmres_its[OK_HIST];         /* linear-solver iterations of each Newton
+                                          iteration (FGMRES, or MINRES)          */
   double fnorm[OK_HIST];               /* ||F|| at each residual evaluation      */
   int32_t fnorm_count;
   double step_ms[OK_HIST];             /* wall time of each step (HIP events)    */
