@@ -642,8 +642,8 @@ def kernel_probe(args, torch, ok, cfg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="3d256",
                     help="3d256 (default), 3d128, 2d64, sweep64, serve, robustness, paper")
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default=None,
@@ -658,6 +658,9 @@ def main():
                     help="run only a plain copy kernel of known size (for counter scaling)")
     ap.add_argument("--no-fuse", action="store_true",
                     help="run every Chebyshev iteration (on M and in the smoothers) in a pass of its own")
+    ap.add_argument("--no-fold-prolong", action="store_true",
+                    help="add the multigrid coarse-grid correction in a pass of its own instead "
+                         "of inside the strip post-smoother")
     ap.add_argument("--issue-ahead", action="store_true",
                     help="issue each FGMRES iteration before the previous one's stop test is read")
     ap.add_argument("--linear-solver", choices=["both", "fgmres"], default="both",
@@ -696,6 +699,8 @@ def main():
     if args.no_fuse:
         ok.set_option(ok.OK_OPT_FUSE_CHEB, 0)
         ok.set_option(ok.OK_OPT_FUSE_MG, 0)
+    if args.no_fuse or args.no_fold_prolong:
+        ok.set_option(ok.OK_OPT_FUSE_PROLONG, 0)
     if args.issue_ahead:
         ok.set_option(ok.OK_OPT_ISSUE_AHEAD, 1)
     if args.trace_ranges:

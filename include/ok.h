@@ -295,10 +295,16 @@ int ok_initial_w(ok_ctx *ctx, const double *d_u, double *d_w, void *stream);
  *   subtracts the projections; basis vectors are kept unnormalised with a
  *   scale.  1: modified Gram-Schmidt one projection per pass (each fused
  *   with the next dot product), normalised basis vectors.  Both compute the
- *   same Arnoldi relation; results agree to rounding. */
+ *   same Arnoldi relation; results agree to rounding.
+ *   OK_OPT_FUSE_PROLONG: 1 (default) adds the interpolated coarse-grid
+ *   correction while the post-smoother stages its input, on 3D levels that
+ *   run the strip post-smoother (OK_SHAPE_MG_POST_STRIP set by ok_autotune
+ *   or ok_set_launch_shape) with the fused V(2,2) smoothers in FP64; 0 adds
+ *   it in a pass of its own first.  Single-precision smoothers (OK_MIXED)
+ *   always use the separate pass. */
 enum ok_option {
   OK_OPT_FUSE_CHEB = 1, OK_OPT_FUSE_MG = 2, OK_OPT_ISSUE_AHEAD = 3, OK_OPT_TRACE_RANGES = 4,
-  OK_OPT_GRAM_SCHMIDT = 5
+  OK_OPT_GRAM_SCHMIDT = 5, OK_OPT_FUSE_PROLONG = 6
 };
 int ok_set_option(int32_t option, int32_t value);
 

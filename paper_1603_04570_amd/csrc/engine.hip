@@ -388,6 +388,12 @@ int mg_vcycle(ClassCtx& c, const int* fl, int l, Vec<const P> b, Vec<P> x, bool 
     OKE(c, launch_restrict<P>(g, gc, B, cst(r), bc, st));
     int e = mg_vcycle<P>(c, fl, l + 1, cst(bc), xc, true, st);
     if (e) return e;
+    if (prolong_fusion_enabled() && mg_post_prolong_ok<P>(g, gc)) {
+      // the correction interpolated while db is staged: db is not rewritten
+      ProfScope ps(c, cls, (3.0 + 0.125) * c.psz * nl * c.B, st);
+      OKE(c, launch_mg_post2_prolong<P>(g, gc, B, l, b, cst(db), cst(xc), x, st));
+      return OK_SUCCESS;
+    }
     OKE(c, launch_prolong_add<P>(g, gc, B, cst(xc), db, st));
     ProfScope ps(c, cls, 3.0 * c.psz * nl * c.B, st);
     OKE(c, launch_mg_post2<P>(g, B, l, b, cst(db), x, st));

@@ -1702,11 +1702,16 @@ hipError_t launch_cheb2_ex(const Grid& g, const Batch& B, const StencilShape& sh
 namespace {
 int g_fuse_cheb = 1;
 int g_fuse_mg = 1;
+int g_fuse_prolong = 1;
 }  // namespace
 
 void mg_fusion_set(int enable) { g_fuse_mg = enable ? 1 : 0; }
 
 bool mg_fusion_enabled() { return g_fuse_mg != 0; }
+
+void prolong_fusion_set(int enable) { g_fuse_prolong = enable ? 1 : 0; }
+
+bool prolong_fusion_enabled() { return g_fuse_prolong != 0; }
 
 bool mg2_shape_valid(const Grid& g, int key, int word) {
   const int H = (g.dim == 3) ? g.nn + 1 : 1;
@@ -1778,34 +1783,40 @@ namespace {
 template <int CFG, class T, int MODE, bool LAST2>
 hipError_t launch_strip_cfg(const Grid& g, const Batch& B, const StencilShape& sh0, int lev,
                             int kk, int osc, Vec<const T> a, Vec<const T> p, Vec<T> x,
-                            Vec<T> o2, Vec<T> o3, hipStream_t st) {
+                            Vec<T> o2, Vec<T> o3, Vec<const T> ec, hipStream_t st) {
   constexpr StripCfg C = strip_cfg(CFG);
   if (g.dim != 3) return hipErrorInvalidValue;
   const int ntx = (g.nn + C.bx - 3) / (C.bx - 2), nty = (g.nn + C.by - 3) / (C.by - 2);
   StencilShape sh = sh0;
   sh.nchunks = ntx * nty;
   sh.blocks = sh.nchunks * sh.nzc;
-  const size_t lds = (size_t)2 * (C.bx + 2) * (C.by + 2) * sizeof(double);
+  const int ce = (C.bx / 2 + 3) * (C.by / 2 + 3);  // coarse nodes under a window
+  const size_t lds = ((size_t)2 * (C.bx + 2) * (C.by + 2) +
+                      (MODE == kStripPostProlong ? 2 * (size_t)ce : 0)) * sizeof(double);
   const int64_t nblk = (int64_t)sh.blocks * B.count;
   if (nblk > 0x7fffffff || lds > 65536) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_strip2<C.bx, C.by, C.p, T, MODE, LAST2>), dim3((unsigned)nblk),
-                     dim3(C.nt), lds, st, g, sh, ntx, B, lev, kk, osc, a, p, x, o2, o3);
+                     dim3(C.nt), lds, st, g, sh, ntx, B, lev, kk, osc, a, p, x, o2, o3, ec);
   return hipGetLastError();
 }
 
 template <class T, int MODE, bool LAST2>
 hipError_t launch_strip(const Grid& g, const Batch& B, int key, int lev, int kk, int osc,
                         Vec<const T> a, Vec<const T> p, Vec<T> x, Vec<T> o2, Vec<T> o3,
-                        hipStream_t st) {
+                        hipStream_t st, Vec<const T> ec = Vec<const T>{nullptr, 0}) {
   const StencilShape sh = stencil_shape(g, key, (int)sizeof(T));
+#define OKD_STRIP(CFG)                                                                      \
+  case CFG:                                                                                 \
+    return launch_strip_cfg<CFG, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, ec, st)
   switch (sh.items) {
-    case 1: return launch_strip_cfg<1, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, st);
-    case 2: return launch_strip_cfg<2, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, st);
-    case 3: return launch_strip_cfg<3, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, st);
-    case 4: return launch_strip_cfg<4, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, st);
-    case 5: return launch_strip_cfg<5, T, MODE, LAST2>(g, B, sh, lev, kk, osc, a, p, x, o2, o3, st);
+    OKD_STRIP(1);
+    OKD_STRIP(2);
+    OKD_STRIP(3);
+    OKD_STRIP(4);
+    OKD_STRIP(5);
     default: return hipErrorInvalidValue;
   }
+#undef OKD_STRIP
 }
 }  // namespace
 
@@ -2214,6 +2225,28 @@ hipError_t launch_mg_post2(const Grid& g, const Batch& B, int lev, Vec<const T> 
   return launch_mg2<T, false>(g, B, lev, x, b, xout, Vec<T>{nullptr, 0}, st);
 }
 
+// FP64 only: with single-precision vectors the folded kernel measured no
+// faster than the separate prolongation pass at 256^3, so it is not built.
+template <class T>
+bool mg_post_prolong_ok(const Grid& g, const Grid& gc) {
+  return sizeof(T) == 8 && g.dim == 3 && g.N == 2 * gc.N &&
+         stencil_tuned(g, kMgPostStripKey, (int)sizeof(T));
+}
+
+template <class T>
+hipError_t launch_mg_post2_prolong(const Grid& g, const Grid& gc, const Batch& B, int lev,
+                                   Vec<const T> b, Vec<const T> x, Vec<const T> ec, Vec<T> xout,
+                                   hipStream_t st) {
+  if (lev < 0 || lev >= kMaxLevels || B.count < 1 || xout.null() || (const T*)xout.p == x.p ||
+      ec.null() || !mg_post_prolong_ok<T>(g, gc))
+    return hipErrorInvalidValue;
+  if constexpr (sizeof(T) == 8)
+    return launch_strip<T, kStripPostProlong, false>(g, B, kMgPostStripKey, lev, 0, CF_ONE, x,
+                                                     b, xout, Vec<T>{nullptr, 0},
+                                                     Vec<T>{nullptr, 0}, st, ec);
+  return hipErrorInvalidValue;
+}
+
 template <class T>
 hipError_t launch_cheb_start(const Grid& g, const Batch& B, int lev, Vec<const T> b,
                              Vec<const T> x, Vec<T> r, Vec<T> d, hipStream_t st) {
@@ -2301,7 +2334,11 @@ template hipError_t launch_couple<float>(const Grid&, const Batch&, Vec<const fl
   template hipError_t launch_mg_pre2<T>(const Grid&, const Batch&, int, Vec<const T>, Vec<T>,  \
                                         Vec<T>, hipStream_t);                                  \
   template hipError_t launch_mg_post2<T>(const Grid&, const Batch&, int, Vec<const T>,         \
-                                         Vec<const T>, Vec<T>, hipStream_t);
+                                         Vec<const T>, Vec<T>, hipStream_t);                   \
+  template bool mg_post_prolong_ok<T>(const Grid&, const Grid&);                               \
+  template hipError_t launch_mg_post2_prolong<T>(const Grid&, const Grid&, const Batch&, int,   \
+                                                 Vec<const T>, Vec<const T>, Vec<const T>,     \
+                                                 Vec<T>, hipStream_t);
 #if OKD_STENCIL_PART == 0
 OKD_CHEB_TB(double, double)
 OKD_CHEB_T(double)

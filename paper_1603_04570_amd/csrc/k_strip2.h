@@ -28,10 +28,12 @@
 // Modes: kStripCheb (two middle Chebyshev iterations k, k+1 on M, as
 // k_cheb2t), kStripPre (pre-smoothing from x = 0 plus the residual, as
 // k_mg2t<PRE>), kStripPost (post-smoothing from a given x, as
-// k_mg2t<POST>).
+// k_mg2t<POST>), kStripPostProlong (post-smoothing from x + P e with the
+// coarse-grid correction e interpolated while x is staged: the bits of
+// k_prolong_add followed by kStripPost, without the pass over x between).
 #pragma once
 
-constexpr int kStripCheb = 0, kStripPre = 1, kStripPost = 2;
+constexpr int kStripCheb = 0, kStripPre = 1, kStripPost = 2, kStripPostProlong = 3;
 
 // Window configurations, selected by the `items` field of a shape-table entry.
 struct StripCfg {
@@ -48,22 +50,31 @@ constexpr int kStripCfgs = 5;
 // Strips of 3 nodes are compiled for three wavefronts per SIMD (at most 168
 // VGPRs; the stiffness variants then spill a few values), the others for the
 // compiler's own choice (two wavefronts per SIMD at 4 nodes per thread).
-constexpr int strip_min_waves(int p) { return p == 3 ? 3 : 1; }
+constexpr int strip_min_waves(int p, int mode) {
+  return p == 3 ? 3 : (mode == kStripPostProlong ? 2 : 1);
+}
 
 template <int BX, int BY, int P, class T, int MODE, bool LAST2>
 __global__ void __launch_bounds__(BX * BY / P)
-    __attribute__((amdgpu_waves_per_eu(strip_min_waves(P), 8)))
+    __attribute__((amdgpu_waves_per_eu(strip_min_waves(P, MODE), 8)))
     k_strip2(Grid g, StencilShape sh, int ntx, Batch B, int lev, int kk, int osc,
-             Vec<const T> av, Vec<const T> pv, Vec<T> xv, Vec<T> o2v, Vec<T> o3v) {
+             Vec<const T> av, Vec<const T> pv, Vec<T> xv, Vec<T> o2v, Vec<T> o3v,
+             Vec<const T> ecv) {
   constexpr int NT = BX * BY / P;
   constexpr int WA = BX + 2;                        // LDS row pitch (window + ring)
   constexpr int EA = WA * (BY + 2);                 // LDS words per plane buffer
   constexpr int KA = (EA + NT - 1) / NT;            // staging slots per thread
   constexpr bool MASS = (MODE == kStripCheb);       // operator M only
   constexpr bool SC1 = (MODE == kStripPre);         // stage 1 on the W^-1-scaled input
+  constexpr bool PROL = (MODE == kStripPostProlong);
+  // prolongation: the coarse nodes under the window (CW x CH per coarse
+  // plane, two coarse planes in LDS) and the coarse staging slots per thread
+  constexpr int CW = BX / 2 + 3, CH = BY / 2 + 3, CE = CW * CH;
+  constexpr int KC = PROL ? (CE + NT - 1) / NT : 0;
   extern __shared__ double lds_raw[];
   double* LA = lds_raw;
   double* LB = lds_raw + EA;
+  double* LC = lds_raw + 2 * EA;  // PROL: coarse planes K (even K) and K (odd K)
   const int tid = threadIdx.x;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = lb / sh.blocks;
@@ -84,8 +95,9 @@ __global__ void __launch_bounds__(BX * BY / P)
   const T* __restrict__ a = av.at(inst);
   const T* __restrict__ pw = (MODE == kStripPre) ? nullptr : pv.at(inst);
   T* __restrict__ xo = xv.at(inst);
-  T* __restrict__ o2 = (MODE == kStripPost || (MODE == kStripCheb && LAST2)) ? nullptr
-                                                                              : o2v.at(inst);
+  T* __restrict__ o2 = (MODE == kStripPost || PROL || (MODE == kStripCheb && LAST2))
+                           ? nullptr
+                           : o2v.at(inst);
   T* __restrict__ o3 = (MODE == kStripCheb && !LAST2) ? o3v.at(inst) : nullptr;
 
   // zero the stage-1 buffer once (its ring is never written; the barrier
@@ -107,6 +119,72 @@ __global__ void __launch_bounds__(BX * BY / P)
     oa[k] = min(max(gy, 0), N) * nn + min(max(gx, 0), N);
     fsl[k] = (double)(1 << ((gx == 0 || gx == N) + (gy == 0 || gy == N)));
   }
+  // prolongation of the staged nodes (the coarse grid has N/2 elements):
+  // coarse window origin; a fine node at an even index copies its coarse
+  // node, at an odd one averages two
+  const int Nc = N >> 1, nnc = Nc + 1;
+  const int CI0 = (X0 - 1) >> 1, CJ0 = (Y0 - 1) >> 1;
+  const T* __restrict__ ec = PROL ? ecv.at(inst) : nullptr;
+  auto stage_coarse = [&](int kc, T (&cv)[KC > 0 ? KC : 1]) {  // load coarse plane kc
+#pragma unroll
+    for (int k2 = 0; k2 < KC; k2++) {
+      const int j = tid + NT * k2;
+      const int gj = min(max(CJ0 + j / CW, 0), Nc), gi = min(max(CI0 + j % CW, 0), Nc);
+      cv[k2] = ec[((int64_t)kc * nnc + gj) * nnc + gi];
+    }
+  };
+  auto commit_coarse = [&](int kc, const T (&cv)[KC > 0 ? KC : 1]) {
+#pragma unroll
+    for (int k2 = 0; k2 < KC; k2++) {
+      const int j = tid + NT * k2;
+      if (j < CE) LC[(kc & 1) * CE + j] = to_d(cv[k2]);
+    }
+  };
+  // each slot's coarse offset and odd-index bits, 16 bits per slot: offset
+  // in bits 0-8, odd x in bit 9, odd y in bit 10
+  static_assert(!PROL || CE <= 512, "coarse window offsets take 9 bits");
+  constexpr int KW = (KA + 1) / 2;
+  unsigned pinfo[PROL ? KW : 1] = {};
+  if constexpr (PROL) {
+#pragma unroll
+    for (int k = 0; k < KA; k++) {
+      const int t = tid + NT * k;
+      const int gy = Y0 - 1 + t / WA, gx = X0 - 1 + t % WA;
+      const unsigned cl = (unsigned)(((gy >> 1) - CJ0) * CW + ((gx >> 1) - CI0));
+      const unsigned v = (t < EA) ? (cl | (unsigned)(gx & 1) << 9 | (unsigned)(gy & 1) << 10) : 0u;
+      pinfo[k >> 1] |= v << (16 * (k & 1));
+    }
+  }
+  // P e at staging slot k of fine plane pz, summed in the order of
+  // k_prolong_add (coarse plane, then row, then the one or two columns).
+  // Every weight product is the exact power of two 2^-(number of odd
+  // indices); the terms an even index does not have are added with weight 0
+  // (reading a neighbour inside the staged window: finite, so each adds a
+  // zero), which keeps the lanes of a wavefront on one path.
+  auto prolong = [&](int k, int pz, const unsigned (&pi)[PROL ? KW : 1]) {
+    const unsigned inf = (pi[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+    const int cl = (int)(inf & 511u);
+    const bool two_i = inf & 512u, two_j = inf & 1024u;
+    const int K = pz >> 1;
+    const bool two_k = pz & 1;
+    const int hi = (1023 - (int)two_k - (int)two_i - (int)two_j) << 20;
+    const double w = __hiloint2double(hi, 0);
+    const double wi = __hiloint2double(two_i ? hi : 0, 0);
+    const double wj = __hiloint2double(two_j ? hi : 0, 0);
+    const double wij = __hiloint2double((two_i && two_j) ? hi : 0, 0);
+    double sum = 0.0;
+#pragma unroll
+    for (int za = 0; za < 2; za++) {
+      if (za && !two_k) break;
+      const double* cr = LC + ((K + za) & 1) * CE + cl;
+      sum += w * cr[0];
+      sum += wi * cr[1];
+      sum += wj * cr[CW];
+      sum += wij * cr[CW + 1];
+    }
+    return sum;
+  };
+
   // the thread's strip
   const int cx = tid % BX, cy0 = (tid / BX) * P;
   const int gx = X0 + cx, ic = min(max(gx, 0), N);
@@ -209,23 +287,54 @@ __global__ void __launch_bounds__(BX * BY / P)
   };
   issue_a(max(z0 - 2, 0));
   issue_p(max(z0 - 1, 0), max(z0, 0));
+  T cpre[KC > 0 ? KC : 1];
+  if constexpr (PROL) {
+    // the coarse planes under the first staged plane (the barrier after the
+    // first trip's staging is not enough: that staging reads them)
+    const int K0 = max(z0 - 2, 0) >> 1;
+    stage_coarse(K0, cpre);
+    commit_coarse(K0, cpre);
+    stage_coarse(min(K0 + 1, Nc), cpre);
+    commit_coarse(K0 + 1, cpre);
+    __syncthreads();
+  }
   for (int pz = z0 - 2; pz <= z1 + 1; pz++) {
     const bool insideA = (pz >= 0 && pz <= N);
     const int q1 = pz - 1;  // stage-1 plane
     const int o = pz - 2;   // stage-2 (output) plane
     // no barrier before staging: every read of LA in the previous trip
     // precedes that trip's barrier before stage 2, and stage 2 reads only LB
+    // PROL: coarse plane pz/2 + 1 is first read by trip pz + 1; loaded now,
+    // stored after this trip's barrier (its buffer was last read by trip
+    // pz - 1), visible after the barrier before stage 2
+    const bool cstage = PROL && insideA && !(pz & 1) && (pz >> 1) + 1 <= Nc;
+    if (cstage) stage_coarse((pz >> 1) + 1, cpre);
     if (insideA) {
       const double fz = (SC1 && (pz == 0 || pz == N)) ? 2.0 : 1.0;
+      // the packed slot words made opaque per trip: unpacked here, not held
+      // unpacked in registers across the plane loop
+      unsigned pi[PROL ? KW : 1];
+#pragma unroll
+      for (int q = 0; q < (PROL ? KW : 1); q++) {
+        pi[q] = pinfo[q];
+        if constexpr (PROL) asm volatile("" : "+v"(pi[q]));
+      }
 #pragma unroll
       for (int k = 0; k < KA; k++) {
         const int t = tid + NT * k;
-        double v = ((va >> k) & 1u) ? to_d(pre_a[k]) : 0.0;
+        double v = 0.0;
+        if ((va >> k) & 1u) {
+          if constexpr (PROL)
+            v = to_d((T)(to_d(pre_a[k]) + prolong(k, pz, pi)));
+          else
+            v = to_d(pre_a[k]);
+        }
         if (SC1) v = v * fsl[k] * fz;
         if (t < EA) LA[t] = v;
       }
     }
     __syncthreads();
+    if (cstage) commit_coarse((pz >> 1) + 1, cpre);
     T pq[P], xq[P];  // stage-1 pointwise input of plane q1, stage-2 x of plane o
 #pragma unroll
     for (int p = 0; p < P; p++) {

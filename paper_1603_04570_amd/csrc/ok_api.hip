@@ -350,6 +350,9 @@ int ok_set_option(int32_t option, int32_t value) {
     case OK_OPT_GRAM_SCHMIDT:
       ortho_set(value);
       return OK_SUCCESS;
+    case OK_OPT_FUSE_PROLONG:
+      prolong_fusion_set(value);
+      return OK_SUCCESS;
     default:
       return OK_E_INVALID;
   }

@@ -201,6 +201,9 @@ bool cheb_fusion_on(const Grid& g, int word);
 // coarse-grid correction, each in one pass with its neighbour).
 void mg_fusion_set(int enable);
 bool mg_fusion_enabled();
+// Prolongation folded into the strip post-smoother (default on).
+void prolong_fusion_set(int enable);
+bool prolong_fusion_enabled();
 bool mg2_shape_valid(const Grid& g, int key, int word);
 bool mg_fusion_on(const Grid& g, int word);
 template <class T>
@@ -209,6 +212,17 @@ hipError_t launch_mg_pre2(const Grid& g, const Batch& B, int lev, Vec<const T> b
 template <class T>
 hipError_t launch_mg_post2(const Grid& g, const Batch& B, int lev, Vec<const T> b,
                            Vec<const T> x, Vec<T> xout, hipStream_t st);
+// Post-smoothing from x + P ec (the coarse-grid correction ec on grid gc
+// interpolated while x is staged): bitwise launch_prolong_add(gc -> g, ec,
+// x) followed by launch_mg_post2 from the sum, without writing the sum.
+// Available (mg_post_prolong_ok) for FP64 vectors where the strip
+// post-smoother is selected.
+template <class T>
+bool mg_post_prolong_ok(const Grid& g, const Grid& gc);
+template <class T>
+hipError_t launch_mg_post2_prolong(const Grid& g, const Grid& gc, const Batch& B, int lev,
+                                   Vec<const T> b, Vec<const T> x, Vec<const T> ec, Vec<T> xout,
+                                   hipStream_t st);
 // Launch shapes that have instantiated kernels (items per thread, threads).
 bool stencil_shape_ok(int dim, int nf, int items, int threads);
 bool cheb2_shape_ok(int dim, int items, int threads);

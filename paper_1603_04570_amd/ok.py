@@ -435,6 +435,7 @@ OK_OPT_FUSE_MG = 2
 OK_OPT_ISSUE_AHEAD = 3
 OK_OPT_TRACE_RANGES = 4
 OK_OPT_GRAM_SCHMIDT = 5
+OK_OPT_FUSE_PROLONG = 6
 
 
 def set_option(option: int, value: int):

@@ -199,8 +199,9 @@ def test_mg_smoother_tile_shapes_bitwise(precision, n):
 def test_mg_smoother_strip_shapes_bitwise(precision, n):
     """The fused multigrid smoothers on overlapping windows with a column strip
     per thread (3D), pinned on the two finest levels of a 64^3 timestep and of
-    the N = 100 mesh for every window configuration and several z-splits:
-    results equal the one-iteration kernels bit for bit."""
+    the N = 100 mesh for every window configuration and several z-splits, with
+    the prolongation folded into the post-smoother (the default in FP64) and in
+    a pass of its own: results equal the one-iteration kernels bit for bit."""
     from paper_1603_04570_amd import ok
     dim = 3
     p = ok.default_params(dim=dim, n=n, eps=0.02, sigma=100.0, m=0.1, dt=2e-4,
@@ -222,8 +223,10 @@ def test_mg_smoother_strip_shapes_bitwise(precision, n):
     kinds = (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST, ok.OK_SHAPE_MG_PRE_STRIP,
              ok.OK_SHAPE_MG_POST_STRIP)
     try:
-        for cfg, zch in [(1, 1), (2, 5), (3, 3), (1, 65), (2, 2), (3, 101)]:
-            print("mg strip shape", precision, n, cfg, zch, flush=True)
+        for cfg, zch, fold in [(1, 1, 1), (2, 5, 1), (3, 3, 1), (1, 65, 1), (2, 2, 1),
+                               (3, 101, 1), (4, 7, 1), (5, 2, 1), (1, 5, 0), (4, 3, 0)]:
+            print("mg strip shape", precision, n, cfg, zch, fold, flush=True)
+            ok.set_option(ok.OK_OPT_FUSE_PROLONG, fold)
             for lev_n in (n, n // 2):
                 # a row-run entry switches the fused smoothers on; the strip entry selects strips
                 for kern in (ok.OK_SHAPE_MG_PRE, ok.OK_SHAPE_MG_POST):
@@ -234,8 +237,9 @@ def test_mg_smoother_strip_shapes_bitwise(precision, n):
             got = once()
             assert got[2] == ref[2]
             assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), \
-                (cfg, zch)
+                (cfg, zch, fold)
     finally:
+        ok.set_option(ok.OK_OPT_FUSE_PROLONG, 1)
         for lev_n in (n, n // 2):
             for kern in kinds:
                 ok.set_launch_shape(dim, lev_n, kern, precision, 0)

@@ -317,3 +317,73 @@ def test_strip_fused_kernel_indices(cfg):
                                                     for pz in range(z0 - 2, z1 + 2)])
                 check_planes(N, [max(z0, 0)] + [min(max(pz - 1, 0), N)
                                                 for pz in range(z0 - 2, z1 + 2)])
+
+
+def emulate_strip_prolong(N, cfg):
+    """Coarse staging of the post-smoother with the prolongation folded in
+    (N = 2 Nc): every coarse value a staged fine node reads lies inside the
+    CW x CH window held in LDS and is the coarse node that the interpolation
+    of that fine node names."""
+    BX, BY, P, NT = STRIP_CFGS[cfg]
+    Nc = N // 2
+    nn = N + 1
+    WA, EA = BX + 2, (BX + 2) * (BY + 2)
+    KA = (EA + NT - 1) // NT
+    CW, CH = BX // 2 + 3, BY // 2 + 3
+    CE = CW * CH
+    assert (2 * EA + 2 * CE) * 8 <= 65536
+    ntx, nty = (nn + BX - 3) // (BX - 2), (nn + BY - 3) // (BY - 2)
+    tid = np.arange(NT)
+    for tile in range(ntx * nty):
+        X0, Y0 = (tile % ntx) * (BX - 2) - 1, (tile // ntx) * (BY - 2) - 1
+        CI0, CJ0 = (X0 - 1) >> 1, (Y0 - 1) >> 1
+        for k in range(KA):
+            t = tid + NT * k
+            gy, gx = Y0 - 1 + t // WA, X0 - 1 + t % WA
+            va = (t < EA) & (gy >= 0) & (gy <= N) & (gx >= 0) & (gx <= N)
+            cl = ((gy >> 1) - CJ0) * CW + ((gx >> 1) - CI0)
+            for yb in (0, 1):
+                for di in (0, 1):
+                    use = va & ((yb == 0) | (gy & 1 == 1)) & ((di == 0) | (gx & 1 == 1))
+                    j = cl[use] + yb * CW + di
+                    assert j.size == 0 or (j.min() >= 0 and j.max() < CE)
+                    cj, ci = CJ0 + j // CW, CI0 + j % CW
+                    assert np.array_equal(cj, (gy[use] >> 1) + yb)
+                    assert np.array_equal(ci, (gx[use] >> 1) + di)
+                    assert j.size == 0 or (min(cj.min(), ci.min()) >= 0 and
+                                           max(cj.max(), ci.max()) <= Nc)
+
+
+def prolong_plane_schedule(N, z0, z1):
+    """The two LDS coarse-plane buffers over a z-chunk's trips: each trip's
+    staging finds coarse plane pz>>1 (and pz>>1 + 1 for odd pz) in place, and
+    a plane is overwritten only after the last trip that reads it."""
+    Nc = N // 2
+    buf = [None, None]
+    K0 = max(z0 - 2, 0) >> 1
+    buf[K0 & 1] = K0
+    buf[(K0 + 1) & 1] = K0 + 1 if K0 + 1 <= Nc else None
+    for pz in range(z0 - 2, z1 + 2):
+        if 0 <= pz <= N:
+            K = pz >> 1
+            assert buf[K & 1] == K, (N, z0, z1, pz)
+            if pz & 1:
+                assert buf[(K + 1) & 1] == K + 1, (N, z0, z1, pz)
+            if not (pz & 1) and K + 1 <= Nc:
+                # committed after this trip's first barrier: the buffer's
+                # previous plane K - 1 was last read by trip pz - 1
+                buf[(K + 1) & 1] = K + 1
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5])
+def test_strip_prolong_indices(cfg):
+    for N in GRIDS_3D:
+        if N % 2:
+            continue
+        nn = N + 1
+        emulate_strip_prolong(N, cfg)
+        BX, BY, _, _ = STRIP_CFGS[cfg]
+        nw = ((nn + BX - 3) // (BX - 2)) * ((nn + BY - 3) // (BY - 2))
+        for nzc in z_candidates(nn, nw):
+            for z0, z1 in zranges(nn, nzc):
+                prolong_plane_schedule(N, z0, z1)
