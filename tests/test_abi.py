@@ -170,3 +170,19 @@ def test_launch_shape_arguments(lib):
     assert f(3, 64, 5, 0, 4, 256, 9) == E
     assert f(3, 64, 1, 0, 4, 256, 0) == E      # zchunks
     assert f(3, 64, 1, 0, 4, 256, 66) == E
+
+
+def test_set_option(lib):
+    """ok_set_option edits process-wide host flags: every declared option is
+    accepted (and restored to its default here), unknown ones are rejected."""
+    from paper_1603_04570_amd import ok
+    defaults = {ok.OK_OPT_FUSE_CHEB: 1, ok.OK_OPT_FUSE_MG: 1, ok.OK_OPT_ISSUE_AHEAD: 0,
+                ok.OK_OPT_TRACE_RANGES: 0, ok.OK_OPT_GRAM_SCHMIDT: 0, ok.OK_OPT_FUSE_PROLONG: 1}
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    declared = {int(v) for v in re.findall(r"\bOK_OPT_[A-Z_]+\s*=\s*(\d+)", text)}
+    assert declared == set(defaults)
+    for opt, dflt in defaults.items():
+        assert lib.ok_set_option(opt, 1 - dflt) == 0
+        assert lib.ok_set_option(opt, dflt) == 0
+    for bad in (0, 7, -1, 1000):
+        assert lib.ok_set_option(bad, 1) == -1
