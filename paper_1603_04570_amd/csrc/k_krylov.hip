@@ -43,9 +43,17 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // Sum of nblk partials, same order in every block.
+// Blocks of at least 256 threads: each thread's (at most four) partials are
+// loaded together, from clamped indices, before they are added in order.
 __device__ __forceinline__ double sum_partials(const double* p, int nblk, double* sh) {
+  constexpr int kPer = kMaxRedBlocks / 256;
+  double t[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; u++) t[u] = p[min((int)threadIdx.x + (int)blockDim.x * u, nblk - 1)];
   double v = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += blockDim.x) v += p[i];
+#pragma unroll
+  for (int u = 0; u < kPer; u++)
+    if ((int)threadIdx.x + (int)blockDim.x * u < nblk) v += t[u];
   return block_sum(v, sh);
 }
 
@@ -117,42 +125,59 @@ __global__ void k_givens(Batch B, int* act, int j, int m, Vec<double> Hv, Vec<do
                          Vec<double> snv, Vec<double> gv, Vec<const double> pnv, int nblk,
                          Vec<double> krv, Vec<double> scv) {
   __shared__ double sh[8];
+  __shared__ double cst[64], snt[64], ct[65];  // rotations so far and the new column, staged
   const int inst = blockIdx.x;
   if (inactive(B, inst)) return;
-  double s = sum_partials(pnv.at(inst), nblk, sh);
-  if (threadIdx.x != 0) return;
   double* col = Hv.at(inst) + (int64_t)j * (m + 1);
   double* cs = csv.at(inst);
   double* sn = snv.at(inst);
-  double* g = gv.at(inst);
-  double* kr = krv.at(inst);
-  double hn = sqrt(s);
-  col[j + 1] = hn;
-  for (int i = 0; i < j; i++) {
-    double t = cs[i] * col[i] + sn[i] * col[i + 1];
-    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-    col[i] = t;
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+    ct[i] = col[i];
+    if (i < j) {
+      cst[i] = cs[i];
+      snt[i] = sn[i];
+    }
   }
-  double den = hypot(col[j], col[j + 1]);
-  cs[j] = col[j] / den;
-  sn[j] = col[j + 1] / den;
-  col[j] = den;
-  col[j + 1] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  const double res = fabs(g[j + 1]);
-  kr[3] = res;
-  kr[4] = hn;
-  kr[5] = 1.0 / hn;
-  kr[6] = (double)(j + 1);
-  if (!scv.null()) scv.at(inst)[j + 1] = kr[5];  // v_{j+1} = w / h_{j+1,j}, kept unscaled
-  if (!isfinite(hn) || !isfinite(res)) {
-    kr[7] = 2.0;
-    act[inst] = 0;
-  } else if (res <= kr[1] || hn == 0.0) {
-    kr[7] = 1.0;
-    act[inst] = 0;
+  double s = sum_partials(pnv.at(inst), nblk, sh);  // its barrier also publishes the staging
+  if (threadIdx.x == 0) {
+    double* g = gv.at(inst);
+    double* kr = krv.at(inst);
+    double hn = sqrt(s);
+    // the earlier rotations applied to the new column: entry i+1 is untouched
+    // until rotation i, so the chain carries one running value
+    double cur = ct[0];
+    for (int i = 0; i < j; i++) {
+      const double nxt = ct[i + 1];
+      const double t = cst[i] * cur + snt[i] * nxt;
+      cur = -snt[i] * cur + cst[i] * nxt;
+      ct[i] = t;
+    }
+    const double cj = cur, cj1 = hn;
+    double den = hypot(cj, cj1);
+    const double csj = cj / den, snj = cj1 / den;
+    cs[j] = csj;
+    sn[j] = snj;
+    ct[j] = den;
+    ct[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -snj * gj;
+    g[j] = csj * gj;
+    const double res = fabs(-snj * gj);
+    kr[3] = res;
+    kr[4] = hn;
+    kr[5] = 1.0 / hn;
+    kr[6] = (double)(j + 1);
+    if (!scv.null()) scv.at(inst)[j + 1] = kr[5];  // v_{j+1} = w / h_{j+1,j}, kept unscaled
+    if (!isfinite(hn) || !isfinite(res)) {
+      kr[7] = 2.0;
+      act[inst] = 0;
+    } else if (res <= kr[1] || hn == 0.0) {
+      kr[7] = 1.0;
+      act[inst] = 0;
+    }
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) col[i] = ct[i];
 }
 
 __global__ void __launch_bounds__(256)
@@ -270,33 +295,68 @@ __global__ void __launch_bounds__(512)
     k_proj_coef(Batch B, int j, int m, Vec<const double> pdv, int nblk, Vec<const double> scv,
                 Vec<double> Lv, Vec<double> Hv, Vec<double> hcv) {
   __shared__ double sums[2 * 64];
-  __shared__ double hh[64];
+  __shared__ double scs[64];
+  __shared__ double Ls[64][65];  // rows 0 .. j-1 of L, staged (padded: no bank conflicts)
   const int inst = blockIdx.x;
   if (inactive(B, inst)) return;
   const double* pd = pdv.at(inst);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int nq = 2 * (j + 1);
-  for (int q = wave; q < nq; q += nw) {
-    double s = 0.0;
-    for (int k = lane; k < nblk; k += 64) s += pd[(int64_t)q * nblk + k];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) sums[q] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
   const double* sc = scv.at(inst);
   double* L = Lv.at(inst);  // row-major (m+1) x (m+1): L[i*(m+1)+k] = <v_i, v_k>, k < i
-  double* H = Hv.at(inst);  // column j of the Hessenberg matrix
-  double* hc = hcv.at(inst);
   const int ld = m + 1;
-  const double sj = sc[j];
-  for (int i = 0; i < j; i++) L[(int64_t)j * ld + i] = sums[2 * i + 1] * sc[i] * sj;
-  for (int i = 0; i <= j; i++) {
-    double h = sums[2 * i] * sc[i];
-    for (int k = 0; k < i; k++) h = fma(-L[(int64_t)i * ld + k], hh[k], h);
-    hh[i] = h;
-    H[i] = h;
-    hc[i] = h * sc[i];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int nq = 2 * (j + 1);
+  // each lane sums partials lane, lane + 64, ... of a row in that order; the
+  // loads of two rows (clamped, unconditional) are all issued before the sums
+  constexpr int kPer = kMaxRedBlocks / 64;
+  for (int q0 = wave; q0 < nq; q0 += 2 * nw) {
+    double v[2][kPer];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const int q = min(q0 + r * nw, nq - 1);
+#pragma unroll
+      for (int u = 0; u < kPer; u++)
+        v[r][u] = pd[(int64_t)q * nblk + min(lane + 64 * u, nblk - 1)];
+    }
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < kPer; u++)
+        if (lane + 64 * u < nblk) s += v[r][u];
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+      const int q = q0 + r * nw;
+      if (lane == 0 && q < nq) sums[q] = s;
+    }
+  }
+  // the rows of L from earlier steps and the scales, all loads in flight at once
+  for (int t = threadIdx.x; t < j * j; t += blockDim.x) {
+    const int i = t / j, k = t - i * j;
+    if (k < i) Ls[i][k] = L[(int64_t)i * ld + k];
+  }
+  if ((int)threadIdx.x <= j) scs[threadIdx.x] = sc[threadIdx.x];
+  __syncthreads();
+  if (wave != 0) return;
+  // wavefront 0: lane i owns row i.  New row j of L, then forward
+  // substitution h_i = <w, v_i> sc_i - sum_{k<i} L_ik h_k with k ascending
+  // (each lane's sum in the order of a row-by-row solve): after step k, lane
+  // k's value is final and is broadcast to the lanes below it.
+  const double sj = scs[j];
+  const bool own = lane <= j;
+  if (lane < j) {
+    const double ljl = sums[2 * lane + 1] * scs[lane] * sj;
+    L[(int64_t)j * ld + lane] = ljl;
+  }
+  double h = own ? sums[2 * lane] * scs[min(lane, j)] : 0.0;
+  for (int k = 0; k < j; k++) {
+    const double hk = __shfl(h, k);
+    if (lane > k && own) {
+      const double lik = (lane == j) ? sums[2 * k + 1] * scs[k] * sj : Ls[lane][k];
+      h = fma(-lik, hk, h);
+    }
+  }
+  if (own) {
+    Hv.at(inst)[lane] = h;
+    hcv.at(inst)[lane] = h * scs[lane];
   }
 }
 
@@ -339,18 +399,29 @@ __global__ void __launch_bounds__(kRedThreads)
 // Back substitution with the triangular H (column-major, leading dim m+1).
 __global__ void k_lsq(Batch B, int m, Vec<const double> Hv, Vec<const double> gv, Vec<double> yv,
                       Vec<const double> krv) {
+  __shared__ double Hs[64][65];  // upper triangle, Hs[l][i] = H_il (padded: no bank conflicts)
+  __shared__ double gs[64], ys[64];
   const int inst = blockIdx.x;
-  if (inactive(B, inst) || threadIdx.x != 0) return;
+  if (inactive(B, inst)) return;
   const double* H = Hv.at(inst);
   const double* g = gv.at(inst);
   double* y = yv.at(inst);
   const int k = (int)krv.at(inst)[6];
   const int ldh = m + 1;
-  for (int i = k - 1; i >= 0; i--) {
-    double s = g[i];
-    for (int l = i + 1; l < k; l++) s -= H[(int64_t)l * ldh + i] * y[l];
-    y[i] = s / H[(int64_t)i * ldh + i];
+  // stage the triangle (all loads in flight at once), then solve from LDS
+  for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
+    const int l = t / k, i = t - l * k;
+    if (i <= l) Hs[l][i] = H[(int64_t)l * ldh + i];
   }
+  for (int i = threadIdx.x; i < k; i += blockDim.x) gs[i] = g[i];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; i--) {
+    double s = gs[i];
+    for (int l = i + 1; l < k; l++) s -= Hs[l][i] * ys[l];
+    ys[i] = s / Hs[i][i];
+  }
+  for (int i = 0; i < k; i++) y[i] = ys[i];
 }
 
 template <class TZ>
