@@ -464,13 +464,53 @@ def _side_by_side(torch, Pa, Pb, u0d, w0d, steps):
             "max_w": max(p["w"] for p in per_step)}
 
 
+def _tune(args, ok, P, cfg):
+    """Autotunes problem P, or pins the launch shapes a --save-shapes run wrote
+    (--load-shapes: counter runs under a profiler then use the shapes the
+    untraced run picked, not those of their own slowed autotuner).  With
+    --save-shapes, the table's entries for the configuration's grids are
+    merged into that file.  Returns the number of entries set."""
+    if args.load_shapes:
+        with open(args.load_shapes) as f:
+            entries = json.load(f)
+        for e in entries:
+            ok.set_launch_shape(e["dim"], e["n"], e["kernel"], e["precision"], e["items"],
+                                e["threads"], e["zchunks"])
+        tuned = len(entries)
+    else:
+        tuned = 0 if args.no_autotune else P.autotune()
+    if args.save_shapes:
+        table = {}
+        if os.path.exists(args.save_shapes):
+            with open(args.save_shapes) as f:
+                for e in json.load(f):
+                    table[(e["dim"], e["n"], e["kernel"], e["precision"])] = e
+        n = cfg["n"]
+        while n >= 1:
+            for kernel in range(ok.OK_SHAPE_STENCIL, ok.OK_SHAPE_MG_POST_STRIP + 1):
+                for prec in (ok.OK_FP64, ok.OK_MIXED):
+                    items, threads, zchunks = ok.get_launch_shape(cfg["dim"], n, kernel, prec)
+                    key = (cfg["dim"], n, kernel, prec)
+                    if items:
+                        table[key] = {"dim": cfg["dim"], "n": n, "kernel": kernel,
+                                      "precision": prec, "items": items, "threads": threads,
+                                      "zchunks": zchunks}
+            if n % 2:
+                break
+            n //= 2
+        with open(args.save_shapes, "w") as f:
+            json.dump(sorted(table.values(), key=lambda e: (e["n"], e["kernel"], e["precision"])),
+                      f, indent=0)
+    return tuned
+
+
 def _timed_run(args, torch, ok, cfg, prec, u0d, w0d, solver=0):
     """One problem of the configuration in precision `prec`: autotuned,
     --warmup untimed timesteps from the initial state, then --steps timesteps
     from the same initial state timed between two device synchronisations
     (no profiling events in the timed region)."""
     P = ok.Problem(_single_params(ok, cfg, prec, solver), device=u0d.device)
-    tuned = 0 if args.no_autotune else P.autotune()
+    tuned = _tune(args, ok, P, cfg)
     if args.graphs:
         P.use_graphs(True)
     u, w = u0d.clone(), w0d.clone()
@@ -623,7 +663,7 @@ def kernel_probe(args, torch, ok, cfg):
     from paper_1603_04570_amd.inputs import uniform01
     prec = ok.OK_MIXED if args.precision == "mixed" else ok.OK_FP64
     P = ok.Problem(_single_params(ok, cfg, prec))
-    tuned = P.autotune()
+    tuned = _tune(args, ok, P, cfg)
     nodes = (cfg["n"] + 1) ** cfg["dim"]
     r = torch.from_numpy(uniform01(5, nodes) - 0.5).cuda()
     x = torch.empty_like(r)
@@ -654,6 +694,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--save-shapes", metavar="FILE",
+                    help="single-problem configs: write the autotuned launch shapes of the "
+                         "configuration's grids to FILE (JSON; merged with what it holds)")
+    ap.add_argument("--load-shapes", metavar="FILE",
+                    help="single-problem configs: pin the launch shapes of FILE instead of "
+                         "autotuning")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain copy kernel of known size (for counter scaling)")
     ap.add_argument("--no-fuse", action="store_true",

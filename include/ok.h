@@ -351,6 +351,14 @@ enum ok_shape_kernel {
 };
 int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precision, int32_t items,
                         int32_t threads, int32_t zchunks);
+/* The table entry ok_set_launch_shape or ok_autotune last wrote for (dim, n,
+ * kernel, precision): *items, *threads, *zchunks as ok_set_launch_shape takes
+ * them, all three 0 when the grid uses the built-in default.  Host-side only
+ * (no device access); lets a caller save the autotuned shapes and pin them
+ * in another process.  OK_E_INVALID for an argument out of range or a null
+ * output pointer. */
+int ok_get_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precision, int32_t *items,
+                        int32_t *threads, int32_t *zchunks);
 
 /* Launch mode of the FGMRES iterations.  enable != 0: the context gets a HIP
  * stream of its own (default priority) and captures each Arnoldi iteration j

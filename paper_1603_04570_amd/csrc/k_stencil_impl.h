@@ -63,6 +63,15 @@ void stencil_tune_set(int dim, int nn, int nf, int word, int items, int nzc, int
     g_tune[std::make_tuple(dim, nn, nf, word)] = std::make_tuple(items, nzc, threads);
 }
 
+void stencil_tune_get(int dim, int nn, int nf, int word, int* items, int* nzc, int* threads) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(std::make_tuple(dim, nn, nf, word));
+  const bool set = it != g_tune.end();
+  *items = set ? std::get<0>(it->second) : 0;
+  *nzc = set ? std::get<1>(it->second) : 0;
+  *threads = set ? std::get<2>(it->second) : 0;
+}
+
 static StencilShape shape_with(const Grid& g, int items, int nzc, int threads = kThreads) {
   StencilShape s;
   const int64_t plane = (g.dim == 3) ? g.plane : (int64_t)g.nn;

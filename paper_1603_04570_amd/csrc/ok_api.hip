@@ -358,25 +358,46 @@ int ok_set_option(int32_t option, int32_t value) {
   }
 }
 
+namespace {
+// Table key of an ok_shape_kernel value, or -1.
+int shape_key(int32_t kernel) {
+  switch (kernel) {
+    case OK_SHAPE_STENCIL: return 1;
+    case OK_SHAPE_STENCIL2: return 2;
+    case OK_SHAPE_CHEB2: return kFusedKey;
+    case OK_SHAPE_MG_PRE: return kMgPreKey;
+    case OK_SHAPE_MG_POST: return kMgPostKey;
+    case OK_SHAPE_CHEB2_TILE: return kFusedTileKey;
+    case OK_SHAPE_MG_PRE_TILE: return kMgPreTileKey;
+    case OK_SHAPE_MG_POST_TILE: return kMgPostTileKey;
+    case OK_SHAPE_CHEB2_STRIP: return kFusedStripKey;
+    case OK_SHAPE_MG_PRE_STRIP: return kMgPreStripKey;
+    case OK_SHAPE_MG_POST_STRIP: return kMgPostStripKey;
+    default: return -1;
+  }
+}
+}  // namespace
+
+int ok_get_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precision, int32_t* items,
+                        int32_t* threads, int32_t* zchunks) {
+  if ((dim != 2 && dim != 3) || n < 1 || n > (1 << 20)) return OK_E_INVALID;
+  if (precision != OK_FP64 && precision != OK_MIXED) return OK_E_INVALID;
+  const int nf = shape_key(kernel);
+  if (nf < 0 || !items || !threads || !zchunks) return OK_E_INVALID;
+  int it = 0, nz = 0, th = 0;
+  stencil_tune_get(dim, n + 1, nf, precision == OK_MIXED ? 4 : 8, &it, &nz, &th);
+  *items = it;
+  *threads = th;
+  *zchunks = nz;
+  return OK_SUCCESS;
+}
+
 int ok_set_launch_shape(int32_t dim, int32_t n, int32_t kernel, int32_t precision, int32_t items,
                         int32_t threads, int32_t zchunks) {
   if ((dim != 2 && dim != 3) || n < 1 || n > (1 << 20)) return OK_E_INVALID;
   if (precision != OK_FP64 && precision != OK_MIXED) return OK_E_INVALID;
-  int nf;
-  switch (kernel) {
-    case OK_SHAPE_STENCIL: nf = 1; break;
-    case OK_SHAPE_STENCIL2: nf = 2; break;
-    case OK_SHAPE_CHEB2: nf = kFusedKey; break;
-    case OK_SHAPE_MG_PRE: nf = kMgPreKey; break;
-    case OK_SHAPE_MG_POST: nf = kMgPostKey; break;
-    case OK_SHAPE_CHEB2_TILE: nf = kFusedTileKey; break;
-    case OK_SHAPE_MG_PRE_TILE: nf = kMgPreTileKey; break;
-    case OK_SHAPE_MG_POST_TILE: nf = kMgPostTileKey; break;
-    case OK_SHAPE_CHEB2_STRIP: nf = kFusedStripKey; break;
-    case OK_SHAPE_MG_PRE_STRIP: nf = kMgPreStripKey; break;
-    case OK_SHAPE_MG_POST_STRIP: nf = kMgPostStripKey; break;
-    default: return OK_E_INVALID;
-  }
+  const int nf = shape_key(kernel);
+  if (nf < 0) return OK_E_INVALID;
   const int word = precision == OK_MIXED ? 4 : 8;
   if (items == 0) {
     stencil_tune_set(dim, n + 1, nf, word, 0, 0);

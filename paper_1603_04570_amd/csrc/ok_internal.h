@@ -158,6 +158,8 @@ bool cheb2_tile_geom(const Grid& g, int threads, int items, TileGeom& tg);
 // fused Chebyshev kernel as slower than single steps on that grid; items == 0 removes
 // the entry (back to the heuristic).  Results do not depend on the shape.
 void stencil_tune_set(int dim, int nn, int nf, int word, int items, int nzc, int threads = 256);
+// The entry of (dim, nn, nf, word); items = nzc = threads = 0 when none is set.
+void stencil_tune_get(int dim, int nn, int nf, int word, int* items, int* nzc, int* threads);
 
 // Reduction blocks per instance for vectors of length n (a fixed function of
 // n, so solo and batched runs sum in the same order).

@@ -136,6 +136,7 @@ def load():
     lib.ok_use_graphs.argtypes = [vp, i32]
     lib.ok_set_option.argtypes = [i32, i32]
     lib.ok_set_launch_shape.argtypes = [i32] * 7
+    lib.ok_get_launch_shape.argtypes = [i32] * 4 + [C.POINTER(i32)] * 3
     lib.ok_initial_w.argtypes = [vp, vp, vp, vp]
     lib.ok_batch_use_graphs.argtypes = [vp, i32]
     lib.ok_server_default_config.argtypes = [P(ServerConfig)]
@@ -458,6 +459,17 @@ def set_launch_shape(dim: int, n: int, kernel: int, precision: int, items: int,
     st = load().ok_set_launch_shape(dim, n, kernel, precision, items, threads, zchunks)
     if st:
         raise OkError(st, "ok_set_launch_shape")
+
+
+def get_launch_shape(dim: int, n: int, kernel: int, precision: int):
+    """ok_get_launch_shape: (items, threads, zchunks) of the table entry, all 0
+    when the grid uses the built-in default."""
+    it, th, zc = C.c_int32(), C.c_int32(), C.c_int32()
+    st = load().ok_get_launch_shape(dim, n, kernel, precision, C.byref(it), C.byref(th),
+                                    C.byref(zc))
+    if st:
+        raise OkError(st, "ok_get_launch_shape")
+    return it.value, th.value, zc.value
 
 
 def server_config(**kw) -> ServerConfig:

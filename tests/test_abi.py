@@ -186,3 +186,30 @@ def test_set_option(lib):
         assert lib.ok_set_option(opt, dflt) == 0
     for bad in (0, 7, -1, 1000):
         assert lib.ok_set_option(bad, 1) == -1
+
+
+def test_get_launch_shape_round_trip(lib):
+    """ok_get_launch_shape reads back what ok_set_launch_shape wrote (host
+    table only), and reports 0s for a grid with no entry."""
+    from paper_1603_04570_amd import ok
+    cases = [(3, 64, ok.OK_SHAPE_MG_POST_STRIP, ok.OK_FP64, 4, 256, 9),
+             (3, 96, ok.OK_SHAPE_CHEB2_TILE, ok.OK_MIXED, 2, 512, 97),
+             (2, 64, ok.OK_SHAPE_STENCIL, ok.OK_FP64, 8, 256, 5)]
+    try:
+        for dim, n, kern, prec, items, threads, zch in cases:
+            assert ok.get_launch_shape(dim, n, kern, prec) == (0, 0, 0)
+            ok.set_launch_shape(dim, n, kern, prec, items, threads, zch)
+            assert ok.get_launch_shape(dim, n, kern, prec) == (items, threads, zch)
+            other = ok.OK_MIXED if prec == ok.OK_FP64 else ok.OK_FP64
+            assert ok.get_launch_shape(dim, n, kern, other) == (0, 0, 0)
+    finally:
+        for dim, n, kern, prec, *_ in cases:
+            ok.set_launch_shape(dim, n, kern, prec, 0)
+    for dim, n, kern, prec, *_ in cases:
+        assert ok.get_launch_shape(dim, n, kern, prec) == (0, 0, 0)
+    i = C.c_int32()
+    E = -1
+    assert lib.ok_get_launch_shape(4, 64, 1, 0, C.byref(i), C.byref(i), C.byref(i)) == E
+    assert lib.ok_get_launch_shape(3, 64, 12, 0, C.byref(i), C.byref(i), C.byref(i)) == E
+    assert lib.ok_get_launch_shape(3, 64, 1, 2, C.byref(i), C.byref(i), C.byref(i)) == E
+    assert lib.ok_get_launch_shape(3, 64, 1, 0, None, C.byref(i), C.byref(i)) == E
