@@ -160,3 +160,46 @@ def test_batch_tiled_kernels_equal_solo(precision):
     finally:
         for kern, lev_n, _, _, _ in pins:
             ok.set_launch_shape(3, lev_n, kern, precision, 0)
+
+
+@pytest.mark.parametrize("precision,cfg", [(0, 1), (0, 4), (1, 2)])
+def test_batch_strip_kernels_equal_solo(precision, cfg):
+    """3D instances of one class with the strip kernels pinned on the two
+    finest levels (the fused Chebyshev pair, pre-smoothing, and in FP64
+    post-smoothing with the coarse-grid correction interpolated in the same
+    pass): every instance equals its solo run with the built-in kernels, bit
+    for bit, with different stopping iterations per instance."""
+    from paper_1603_04570_amd import ok
+    specs = [dict(dim=3, n=32, eps=e, sigma=s, m=m, theta=1.0, dt=d, seed=80 + i)
+             for i, (e, s, m, d) in enumerate([(0.02, 100.0, 0.1, 2e-4), (0.03, 30.0, -0.2, 4e-4),
+                                                (0.025, 300.0, 0.0, 3e-4)])]
+    plist = [params_for(s, precision) for s in specs]
+    ref = []
+    for p, s in zip(plist, specs):  # solo, no pinned shapes
+        u0, w0 = noise_state(3, 32, s["m"], s["seed"])
+        u, w = torch.from_numpy(u0).cuda(), torch.from_numpy(w0).cuda()
+        st = ok.Problem(p).timestep(u, w, 2)
+        ref.append((u.cpu().numpy(), w.cpu().numpy(), st.its()))
+    pins = [(ok.OK_SHAPE_CHEB2_STRIP, 32, cfg, 256, 3)]
+    for lev_n in (32, 16):
+        pins += [(ok.OK_SHAPE_MG_PRE, lev_n, 1, 256, 1), (ok.OK_SHAPE_MG_POST, lev_n, 1, 256, 1),
+                 (ok.OK_SHAPE_MG_PRE_STRIP, lev_n, cfg, 256, 2),
+                 (ok.OK_SHAPE_MG_POST_STRIP, lev_n, cfg, 256, 5)]
+    try:
+        for kern, lev_n, items, threads, zch in pins:
+            ok.set_launch_shape(3, lev_n, kern, precision, items, threads, zch)
+        print("batch strips", precision, cfg, flush=True)
+        B = ok.Batch(plist)
+        for i, s in enumerate(specs):
+            u0, w0 = noise_state(3, 32, s["m"], s["seed"])
+            B.set_state(i, torch.from_numpy(u0).cuda(), torch.from_numpy(w0).cuda())
+        bst = B.timestep(2)
+        for i in range(len(specs)):
+            ub, wb = B.get_state(i)
+            assert bst[i].its() == ref[i][2], i
+            assert np.array_equal(ub.cpu().numpy(), ref[i][0]), i
+            assert np.array_equal(wb.cpu().numpy(), ref[i][1]), i
+        assert len({tuple(r[2]) for r in ref}) > 1
+    finally:
+        for kern, lev_n, _, _, _ in pins:
+            ok.set_launch_shape(3, lev_n, kern, precision, 0)
