@@ -33,12 +33,16 @@ constexpr double kW1 = 8.0 / 18.0;
 __device__ __forceinline__ double ld(const double* p) { return *p; }
 __device__ __forceinline__ double ld(const float* p) { return (double)*p; }
 
-// Values at the 3 Gauss points of the linear interpolant of (v0, v1).
+// Positions of the 3 Gauss points on [0,1].
+constexpr double kGq[3] = {kG0, 0.5, 1.0 - kG0};
+
+// Values at the 3 Gauss points of the linear interpolant of (v0, v1): one
+// difference and one fused multiply-add per point.
 __device__ __forceinline__ void lerp3(double v0, double v1, double* o) {
-  double d = v1 - v0;
-  o[0] = v0 + kG0 * d;
-  o[1] = 0.5 * (v0 + v1);
-  o[2] = v1 - kG0 * d;
+  const double d = v1 - v0;
+  o[0] = fma(kGq[0], d, v0);
+  o[1] = fma(kGq[1], d, v0);
+  o[2] = fma(kGq[2], d, v0);
 }
 
 // Transpose of lerp3 with the Gauss weights folded in: contributions of the
@@ -52,9 +56,10 @@ __device__ __forceinline__ void proj3(const double* t, double& o0, double& o1) {
   o1 = kPc * t[0] + m + kPa * t[2];
 }
 
-// Linear interpolant of (v0, v1) at Gauss point q (as lerp3 computes it).
-__device__ __forceinline__ double lerp_at(double v0, double v1, int q) {
-  return q == 0 ? v0 + kG0 * (v1 - v0) : q == 1 ? 0.5 * (v0 + v1) : v1 - kG0 * (v1 - v0);
+// Linear interpolant at Gauss point q from v0 and d = v1 - v0 (as lerp3
+// computes it).
+__device__ __forceinline__ double lerp_at(double v0, double d, int q) {
+  return fma(kGq[q], d, v0);
 }
 // Weight of Gauss point q in the projection to end 0 / end 1 (proj3).
 __device__ __forceinline__ double pw0(int q) { return q == 0 ? kPa : q == 1 ? kPb : kPc; }
@@ -75,6 +80,13 @@ __device__ __forceinline__ void element3(const double (&u)[2][2][2], const doubl
       lerp3(u[az][ay][0], u[az][ay][1], ue[az][ay]);
       if (MODE == 0) lerp3(x[az][ay][0], x[az][ay][1], xe[az][ay]);
     }
+  // y-differences of the x-edge interpolants, shared by the three Gauss rows
+  double ud[2][3], xd[2][3];  // [az][qx]
+  for (int az = 0; az < 2; az++)
+    for (int qx = 0; qx < 3; qx++) {
+      ud[az][qx] = ue[az][1][qx] - ue[az][0][qx];
+      xd[az][qx] = (MODE == 0) ? xe[az][1][qx] - xe[az][0][qx] : 0.0;
+    }
   double acc[2][2][3];  // [az][ay][qx]: z- and y-projected integrand
   for (int az = 0; az < 2; az++)
     for (int ay = 0; ay < 2; ay++)
@@ -84,12 +96,12 @@ __device__ __forceinline__ void element3(const double (&u)[2][2][2], const doubl
     const double wy0 = pw0(qy), wy1 = pw1(qy);
 #pragma unroll
     for (int qx = 0; qx < 3; qx++) {
-      const double u0 = lerp_at(ue[0][0][qx], ue[0][1][qx], qy);
-      const double u1 = lerp_at(ue[1][0][qx], ue[1][1][qx], qy);
+      const double u0 = lerp_at(ue[0][0][qx], ud[0][qx], qy);
+      const double u1 = lerp_at(ue[1][0][qx], ud[1][qx], qy);
       double f[3];
       if (MODE == 0) {
-        const double x0 = lerp_at(xe[0][0][qx], xe[0][1][qx], qy);
-        const double x1 = lerp_at(xe[1][0][qx], xe[1][1][qx], qy);
+        const double x0 = lerp_at(xe[0][0][qx], xd[0][qx], qy);
+        const double x1 = lerp_at(xe[1][0][qx], xd[1][qx], qy);
         double uq[3], xq[3];
         lerp3(u0, u1, uq);
         lerp3(x0, x1, xq);
