@@ -64,6 +64,8 @@ struct ClassCtx {
   int B = 0;          // instances
   int dim = 0, L = 0, m = 0;
   int nv = 0;         // vectors of 2n per instance in V (FGMRES basis or MINRES work)
+  int64_t vs = 0;     // entries between consecutive vectors of V and of Z: 2n rounded up
+                      // to 64, so every vector starts 256-byte aligned
   bool mixed = false;
   size_t psz = 8;  // bytes per preconditioner word
   int64_t n = 0;   // finest nodes per instance

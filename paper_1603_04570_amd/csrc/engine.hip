@@ -187,8 +187,9 @@ void carve(ClassCtx& c, char* base, bool with_state, size_t* total) {
   c.part = cv.take<int>(B);
   c.incyc = cv.take<int>(B);
   c.aux = cv.take<int>(B);
-  c.V = cv.take<double>((size_t)B * c.nv * n2);
-  c.Z = cv.take<char>((size_t)B * m * n2 * ps);
+  c.vs = (n2 + 63) & ~(int64_t)63;
+  c.V = cv.take<double>((size_t)B * c.nv * c.vs);
+  c.Z = cv.take<char>((size_t)B * m * c.vs * ps);
   c.X = cv.take<double>((size_t)B * n2);
   c.Bv = cv.take<double>((size_t)B * n2);
   c.T1 = cv.take<double>((size_t)B * n2);
@@ -250,8 +251,8 @@ void setup_shape(ClassCtx& c, const ok_params& shape, int B) {
 // ---------------------------------------------------------------------------
 // Strides of the SoA arrays.
 // ---------------------------------------------------------------------------
-inline int64_t sV(const ClassCtx& c) { return (int64_t)c.nv * c.n2(); }
-inline int64_t sZ(const ClassCtx& c) { return (int64_t)c.m * c.n2(); }
+inline int64_t sV(const ClassCtx& c) { return (int64_t)c.nv * c.vs; }
+inline int64_t sZ(const ClassCtx& c) { return (int64_t)c.m * c.vs; }
 inline int64_t sH(const ClassCtx& c) { return (int64_t)(c.m + 1) * c.m; }
 inline int64_t sM(const ClassCtx& c) { return (int64_t)c.m + 1; }
 inline int64_t sL(const ClassCtx& c) { return (int64_t)(c.m + 1) * (c.m + 1); }
@@ -550,9 +551,9 @@ template <class P>
 int fgmres_iteration(ClassCtx& c, int j, Vec<const double> u, hipStream_t st) {
   const int64_t n2 = c.n2();
   const Batch B = c.batch(c.act);
-  Vec<double> Vj = Vec<double>{c.V + (int64_t)j * n2, sV(c)};
-  Vec<double> W = Vec<double>{c.V + (int64_t)(j + 1) * n2, sV(c)};
-  Vec<P> Zj = Vec<P>{(P*)c.Z + (int64_t)j * n2, sZ(c)};
+  Vec<double> Vj = Vec<double>{c.V + (int64_t)j * c.vs, sV(c)};
+  Vec<double> W = Vec<double>{c.V + (int64_t)(j + 1) * c.vs, sV(c)};
+  Vec<P> Zj = Vec<P>{(P*)c.Z + (int64_t)j * c.vs, sZ(c)};
   const bool proj = (g_ortho == 0);
   int e = precond<P>(c, c.act, u, cst(Vj), Zj, st,
                      proj ? Vec<const double>{c.sc + j, sM(c)} : Vec<const double>{nullptr, 0});
@@ -565,7 +566,7 @@ int fgmres_iteration(ClassCtx& c, int j, Vec<const double> u, hipStream_t st) {
       // modified Gram-Schmidt's algorithmic bytes (w and v_i read, w written
       // per projection i = 0..j); the two passes move 2j+5 vectors
       ProfScope ps(c, OK_K_KRYLOV, 24.0 * (j + 1) * n2 * c.B, st, j / kProjGroup + 3);
-      OKE(c, launch_proj(B, W, Vec<const double>{c.V, sV(c)}, n2, j, c.m, n2, vec(c.pd, sPd(c)),
+      OKE(c, launch_proj(B, W, Vec<const double>{c.V, sV(c)}, c.vs, j, c.m, n2, vec(c.pd, sPd(c)),
                          Vec<const double>{c.sc, sM(c)}, vec(c.Lm, sL(c)),
                          Vec<double>{c.H + (int64_t)j * (c.m + 1), sH(c)}, vec(c.hcf, sM(c)),
                          pin, st));
@@ -583,8 +584,8 @@ int fgmres_iteration(ClassCtx& c, int j, Vec<const double> u, hipStream_t st) {
     ProfScope ps(c, OK_K_KRYLOV, 24.0 * (j + 1) * n2 * c.B, st, j + 2);
     OKE(c, launch_dot_partial(B, cst(W), Vec<const double>{c.V, sV(c)}, n2, pin, st));
     for (int i = 0; i <= j; i++) {
-      Vec<const double> vi{c.V + (int64_t)i * n2, sV(c)};
-      Vec<const double> vn{(i < j) ? c.V + (int64_t)(i + 1) * n2 : nullptr, sV(c)};
+      Vec<const double> vi{c.V + (int64_t)i * c.vs, sV(c)};
+      Vec<const double> vn{(i < j) ? c.V + (int64_t)(i + 1) * c.vs : nullptr, sV(c)};
       OKE(c, launch_mgs_step(B, W, vi, vn, n2, cst(pin), pout,
                              Vec<double>{c.H + (int64_t)j * (c.m + 1) + i, sH(c)}, st));
       std::swap(pin, pout);
@@ -638,7 +639,7 @@ int lsq_update(ClassCtx& c, Vec<double> x, hipStream_t st) {
   OKE(c, launch_lsq_update<P>(B, c.m, Vec<const double>{c.H, sH(c)},
                               Vec<const double>{c.g, sM(c)}, vec(c.y, sM(c)),
                               Vec<const double>{c.kr, 8}, Vec<const P>{(const P*)c.Z, sZ(c)},
-                              c.n2(), x, c.n2(), st));
+                              c.vs, x, c.n2(), st));
   return OK_SUCCESS;
 }
 
@@ -1184,7 +1185,7 @@ int minres_class(ClassCtx& c, Vec<const double> u, Vec<const double> b, Vec<doub
   // work vectors in V: v_{j-1}, v_j, v_{j+1}; z_j, z_{j+1}; A z_j; w_{j-1}, w_j, w_{j+1}
   int v0 = 0, v1 = 1, v2 = 2, z1 = 3, z2 = 4, w0 = 6, w1 = 7, w2 = 8;
   const int az = 5;
-  auto slot = [&](int k) { return Vec<double>{c.V + (int64_t)k * n2, sV(c)}; };
+  auto slot = [&](int k) { return Vec<double>{c.V + (int64_t)k * c.vs, sV(c)}; };
   const Batch P = c.batch(c.part), A = c.batch(c.act), R = c.batch(c.incyc);
   Vec<double> mr = vec(c.mr, (int64_t)MR_COUNT);
   Vec<double> pa = vec(c.pA, (int64_t)kMaxRedBlocks), pb = vec(c.pB, (int64_t)kMaxRedBlocks);
