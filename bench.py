@@ -61,20 +61,25 @@ KERNELS = {
     K_KRYLOV: ("krylov", "Gram-Schmidt chain of one Arnoldi step of FGMRES; algorithmic bytes: "
                          "3 two-field vectors per projection (w and v_i read, w written), "
                          "i = 0..j",
-               ("paper_1603_04570_amd/csrc/k_krylov.hip", "paper_1603_04570_amd/csrc/ok_internal.h")),
+               ("paper_1603_04570_amd/csrc/k_krylov.hip", "paper_1603_04570_amd/csrc/ok_internal.h",
+                "paper_1603_04570_amd/csrc/engine.hip")),
     K_CHEB_MASS: ("cheb_pair", "Chebyshev-Jacobi iterations on M, two per launch (the autotuned "
                                "one of k_strip2/k_cheb2t/k_cheb2); algorithmic bytes: x, r, d "
                                "read and written once per launch (6 words/node)",
                   ("paper_1603_04570_amd/csrc/k_stencil_impl.h",
                    "paper_1603_04570_amd/csrc/k_strip2.h",
-                   "paper_1603_04570_amd/csrc/ok_internal.h")),
+                   "paper_1603_04570_amd/csrc/ok_internal.h",
+                   "paper_1603_04570_amd/csrc/engine.hip")),
     K_MG_SMOOTH: ("vcycle_smoother", "finest-level V-cycle smoothing passes (fused pre-smoothing + "
-                                     "residual and fused post-smoothing, the autotuned one of "
-                                     "k_strip2/k_mg2t/k_mg2, or the one-iteration kernels); "
-                                     "algorithmic bytes: 3 words/node per fused pass",
+                                     "residual and fused post-smoothing, in FP64 strips with the "
+                                     "coarse-grid correction interpolated in the same pass; the "
+                                     "autotuned one of k_strip2/k_mg2t/k_mg2, or the one-iteration "
+                                     "kernels); algorithmic bytes: 3 words/node per fused pass, "
+                                     "plus the coarse correction (2^-d words/node) when folded",
                   ("paper_1603_04570_amd/csrc/k_stencil_impl.h",
                    "paper_1603_04570_amd/csrc/k_strip2.h",
-                   "paper_1603_04570_amd/csrc/ok_internal.h")),
+                   "paper_1603_04570_amd/csrc/ok_internal.h",
+                   "paper_1603_04570_amd/csrc/engine.hip")),
 }
 
 
