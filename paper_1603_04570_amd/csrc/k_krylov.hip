@@ -240,7 +240,9 @@ __global__ void k_cycle_init(Batch B, int m, Vec<double> gv, Vec<const double> n
 
 // Partials of a_i = <W, V_i> and c_i = <V_j, V_i> for i = i0 .. i0+NV-1:
 // pd[(2i) * nblk + kb] and pd[(2i+1) * nblk + kb].  Element order as k_dot.
-template <int NV>
+// JIN: V_j is the group's last vector (i0 + NV - 1 == j), so its loaded
+// values serve as V_j and it is not streamed a second time.
+template <int NV, bool JIN>
 __global__ void __launch_bounds__(kRedThreads)
     k_proj_dots(Batch B, Vec<const double> wv, Vec<const double> Vv, int64_t vstride, int i0,
                 int j, int64_t n, Vec<double> pdv, int nblk) {
@@ -258,12 +260,15 @@ __global__ void __launch_bounds__(kRedThreads)
   for (int q = 0; q < NV; q++) a[q] = c[q] = 0.0;
   for (int64_t e = (int64_t)kb * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)nblk * blockDim.x) {
-    const double x = ldnt(w + e), y = ldnt(vj + e);
+    const double x = ldnt(w + e);
+    double v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; q++) v[q] = ldnt(vi[q] + e);
+    const double y = JIN ? v[NV - 1] : ldnt(vj + e);
 #pragma unroll
     for (int q = 0; q < NV; q++) {
-      const double v = ldnt(vi[q] + e);
-      a[q] = fma(x, v, a[q]);
-      c[q] = fma(y, v, c[q]);
+      a[q] = fma(x, v[q], a[q]);
+      c[q] = fma(y, v[q], c[q]);
     }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -717,8 +722,12 @@ namespace {
 template <int NV>
 void launch_dots_nv(const Batch& B, Vec<const double> w, Vec<const double> V, int64_t vstride,
                     int i0, int j, int64_t n, Vec<double> pd, int nb, hipStream_t st) {
-  hipLaunchKernelGGL((k_proj_dots<NV>), dim3((unsigned)((int64_t)nb * B.count)),
-                     dim3(kRedThreads), 0, st, B, w, V, vstride, i0, j, n, pd, nb);
+  if (i0 + NV - 1 == j)
+    hipLaunchKernelGGL((k_proj_dots<NV, true>), dim3((unsigned)((int64_t)nb * B.count)),
+                       dim3(kRedThreads), 0, st, B, w, V, vstride, i0, j, n, pd, nb);
+  else
+    hipLaunchKernelGGL((k_proj_dots<NV, false>), dim3((unsigned)((int64_t)nb * B.count)),
+                       dim3(kRedThreads), 0, st, B, w, V, vstride, i0, j, n, pd, nb);
 }
 using DotsFn = void (*)(const Batch&, Vec<const double>, Vec<const double>, int64_t, int, int,
                         int64_t, Vec<double>, int, hipStream_t);
