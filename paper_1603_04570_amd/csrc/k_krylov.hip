@@ -441,10 +441,22 @@ __global__ void __launch_bounds__(256)
   __syncthreads();
   const TZ* Z = Zv.at(inst);
   double* x = xv.at(inst);
+  // the directions are streamed once (nontemporal), four loads in flight
+  // per trip; the sum runs over j in order
+  auto ldz = [](const TZ* p) { return (double)__builtin_nontemporal_load(p); };
   for (int64_t i = (int64_t)(blockIdx.x % per) * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)per * blockDim.x) {
     double s = x[i];
-    for (int j = 0; j < k; j++) s += ys[j] * ld(Z + j * zstride + i);
+    int j = 0;
+    for (; j + 4 <= k; j += 4) {
+      const double z0 = ldz(Z + j * zstride + i), z1 = ldz(Z + (j + 1) * zstride + i);
+      const double z2 = ldz(Z + (j + 2) * zstride + i), z3 = ldz(Z + (j + 3) * zstride + i);
+      s += ys[j] * z0;
+      s += ys[j + 1] * z1;
+      s += ys[j + 2] * z2;
+      s += ys[j + 3] * z3;
+    }
+    for (; j < k; j++) s += ys[j] * ldz(Z + j * zstride + i);
     x[i] = s;
   }
 }
