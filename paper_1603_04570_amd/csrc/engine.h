@@ -48,6 +48,15 @@ struct ClassExec {
   ~ClassExec();
 };
 
+// A second stream of a MINRES class with its fork and join events: the two
+// V-cycles of the block-diagonal preconditioner run concurrently (owned;
+// default priority; released with the class).
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  ~SideStream();
+};
+
 // Pinned two-slot host copy of the activity flags with an event per slot:
 // the FGMRES driver reads the flags that iteration j-1 left while iteration j
 // already runs (owned; released with the class).
@@ -90,6 +99,7 @@ struct ClassCtx {
   void* cr2 = nullptr;  // second Chebyshev residual (fused iterations ping-pong r)
   void* rich = nullptr;  // Richardson on S (schur_richardson > 1): 4 vectors of n
   void* mg[kMaxLevels][5]{};  // x, b, r, d, d' per level
+  void* mg2[kMaxLevels][5]{};  // a second set (MINRES classes): its two V-cycles run at once
   // ---- host mirrors ----
   std::vector<int> h_act, h_part, h_aux;
   std::vector<int> h_hasF;  // Bv holds F of the current iterate (Newton ticks)
@@ -101,6 +111,7 @@ struct ClassCtx {
   std::unique_ptr<ClassExec> ex;  // null: iterations are launched one kernel at a time on
                                   // the caller's stream
   std::unique_ptr<FlagPipe> fp;   // created by the first FGMRES solve
+  std::unique_ptr<SideStream> side;  // created by the first MINRES solve
 
   int64_t n2() const { return 2 * n; }
   Batch batch(const int* flags) const { return Batch{B, coef, flags}; }

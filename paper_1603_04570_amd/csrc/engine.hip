@@ -25,6 +25,12 @@ ClassExec::~ClassExec() {
   if (xs) (void)hipStreamDestroy(xs);
 }
 
+SideStream::~SideStream() {
+  if (fork) (void)hipEventDestroy(fork);
+  if (join) (void)hipEventDestroy(join);
+  if (s) (void)hipStreamDestroy(s);
+}
+
 FlagPipe::~FlagPipe() {
   for (hipEvent_t e : ev)
     if (e) (void)hipEventDestroy(e);
@@ -208,10 +214,14 @@ void carve(ClassCtx& c, char* base, bool with_state, size_t* total) {
   c.yv = cv.take<char>((size_t)B * n * ps);
   c.tv = cv.take<char>((size_t)B * n * ps);
   c.sv = cv.take<char>((size_t)B * n * ps);
+  const bool two_sets = c.shape.linear_solver == OK_SOLVER_MINRES;
   for (int l = 0; l < c.L; l++) {
     const int64_t nl = c.lev[l].nodes;
-    for (int k = 0; k < 5; k++)
+    for (int k = 0; k < 5; k++) {
       c.mg[l][k] = (l == 0 && k < 2) ? nullptr : cv.take<char>((size_t)B * nl * ps);
+      c.mg2[l][k] = (two_sets && !(l == 0 && k < 2)) ? cv.take<char>((size_t)B * nl * ps)
+                                                      : nullptr;
+    }
   }
   c.pA = cv.take<double>((size_t)B * kMaxRedBlocks);
   c.pB = cv.take<double>((size_t)B * kMaxRedBlocks);
@@ -363,21 +373,23 @@ int cheb_from(ClassCtx& c, const int* fl, int cls, const Grid& g, int lev, int K
 // ---------------------------------------------------------------------------
 // Multigrid V-cycle for S^ = M + alpha K (Sec. 2 after eq. (schurinv)).
 // ---------------------------------------------------------------------------
+// set: which work buffers (c.mg, or c.mg2 for a second concurrent cycle).
 template <class P>
 int mg_vcycle(ClassCtx& c, const int* fl, int l, Vec<const P> b, Vec<P> x, bool zero_start,
-              hipStream_t st) {
+              hipStream_t st, int set = 0) {
   const Grid& g = c.lev[l];
   const Batch B = c.batch(fl);
+  void* const(*mgw)[5] = set ? c.mg2 : c.mg;
   if (l == c.L - 1) {
-    OKE(c, launch_coarse_solve<P>(g, B, b, x, pvec<P>(c.mg[l][2], g.nodes),
-                                  pvec<P>(c.mg[l][3], g.nodes), st));
+    OKE(c, launch_coarse_solve<P>(g, B, b, x, pvec<P>(mgw[l][2], g.nodes),
+                                  pvec<P>(mgw[l][3], g.nodes), st));
     return OK_SUCCESS;
   }
   const int64_t nl = g.nodes;
-  Vec<P> r = pvec<P>(c.mg[l][2], nl), da = pvec<P>(c.mg[l][3], nl), db = pvec<P>(c.mg[l][4], nl);
+  Vec<P> r = pvec<P>(mgw[l][2], nl), da = pvec<P>(mgw[l][3], nl), db = pvec<P>(mgw[l][4], nl);
   const int cls = (l == 0) ? OK_K_MG_SMOOTH : OK_K_NONE;
   const Grid& gc = c.lev[l + 1];
-  Vec<P> xc = pvec<P>(c.mg[l + 1][0], gc.nodes), bc = pvec<P>(c.mg[l + 1][1], gc.nodes);
+  Vec<P> xc = pvec<P>(mgw[l + 1][0], gc.nodes), bc = pvec<P>(mgw[l + 1][1], gc.nodes);
   if (zero_start && c.shape.mg_pre == 2 && c.shape.mg_post == 2 &&
       mg_fusion_on(g, (int)sizeof(P))) {
     // pre-smoothing and residual in one pass (smoothed x kept in db), the
@@ -387,7 +399,7 @@ int mg_vcycle(ClassCtx& c, const int* fl, int l, Vec<const P> b, Vec<P> x, bool 
       OKE(c, launch_mg_pre2<P>(g, B, l, b, db, r, st));
     }
     OKE(c, launch_restrict<P>(g, gc, B, cst(r), bc, st));
-    int e = mg_vcycle<P>(c, fl, l + 1, cst(bc), xc, true, st);
+    int e = mg_vcycle<P>(c, fl, l + 1, cst(bc), xc, true, st, set);
     if (e) return e;
     if (prolong_fusion_enabled() && mg_post_prolong_ok<P>(g, gc)) {
       // the correction interpolated while db is staged: db is not rewritten
@@ -409,16 +421,17 @@ int mg_vcycle(ClassCtx& c, const int* fl, int l, Vec<const P> b, Vec<P> x, bool 
     OKE(c, launch_resid<P>(g, B, l, b, cst(x), r, st));
   }
   OKE(c, launch_restrict<P>(g, gc, B, cst(r), bc, st));
-  e = mg_vcycle<P>(c, fl, l + 1, cst(bc), xc, true, st);
+  e = mg_vcycle<P>(c, fl, l + 1, cst(bc), xc, true, st, set);
   if (e) return e;
   OKE(c, launch_prolong_add<P>(g, gc, B, cst(xc), x, st));
   return cheb_from<P>(c, fl, cls, g, l, c.shape.mg_post, b, x, r, da, db, st);
 }
 
 template <class P>
-int mg_apply(ClassCtx& c, const int* fl, Vec<const P> b, Vec<P> x, int cycles, hipStream_t st) {
+int mg_apply(ClassCtx& c, const int* fl, Vec<const P> b, Vec<P> x, int cycles, hipStream_t st,
+             int set = 0) {
   for (int k = 0; k < cycles; k++) {
-    int e = mg_vcycle<P>(c, fl, 0, b, x, k == 0, st);
+    int e = mg_vcycle<P>(c, fl, 0, b, x, k == 0, st, set);
     if (e) return e;
   }
   return OK_SUCCESS;
@@ -1152,12 +1165,27 @@ namespace {
 
 // z = diag((alpha/c) S^^-1, (c/alpha) S^^-1) v (each block one multigrid
 // application of S^), with the partials of <z, v> in c.pA.
+// The two V-cycles share no buffer (the second uses the class's second set of
+// multigrid work vectors) and run at once: the second half's on the class's
+// side stream, forked from and joined back into st.
 int sym_precond(ClassCtx& c, const int* fl, Vec<const double> v, Vec<double> z, hipStream_t st) {
   const int64_t n = c.n;
-  int e = mg_apply<double>(c, fl, v, z, c.shape.mg_cycles, st);
+  if (!c.side) {
+    auto sd = std::make_unique<SideStream>();
+    OKE(c, hipStreamCreateWithFlags(&sd->s, hipStreamNonBlocking));
+    OKE(c, hipEventCreateWithFlags(&sd->fork, hipEventDisableTiming));
+    OKE(c, hipEventCreateWithFlags(&sd->join, hipEventDisableTiming));
+    c.side = std::move(sd);
+  }
+  SideStream* sd = c.side.get();
+  OKE(c, hipEventRecord(sd->fork, st));
+  OKE(c, hipStreamWaitEvent(sd->s, sd->fork, 0));
+  int e = mg_apply<double>(c, fl, off(v, n), off(z, n), c.shape.mg_cycles, sd->s, 1);
   if (e) return e;
-  e = mg_apply<double>(c, fl, off(v, n), off(z, n), c.shape.mg_cycles, st);
+  e = mg_apply<double>(c, fl, v, z, c.shape.mg_cycles, st, 0);
   if (e) return e;
+  OKE(c, hipEventRecord(sd->join, sd->s));
+  OKE(c, hipStreamWaitEvent(st, sd->join, 0));
   OKE(c, launch_mr_scale_dot(c.batch(fl), z, v, n, vec(c.pA, (int64_t)kMaxRedBlocks), st));
   return OK_SUCCESS;
 }
