@@ -193,7 +193,10 @@ int ok_jacobian_apply(ok_ctx *ctx, const double *d_u, const double *d_x, double 
  * the iterations).  ok_minres synchronises; it returns OK_E_GMRES_MAXIT when
  * the iteration limit is reached first (x then holds the last iterate).
  * Both require precision OK_FP64; ok_minres also needs a context created with
- * linear_solver = OK_SOLVER_MINRES (its work vectors), else OK_E_INVALID. */
+ * linear_solver = OK_SOLVER_MINRES (its work vectors, and a second set of
+ * multigrid work vectors: the two V-cycles of the block preconditioner run
+ * concurrently, the second on a stream the context creates and owns, joined
+ * back into `stream` before the next step), else OK_E_INVALID. */
 int ok_sym_apply(ok_ctx *ctx, const double *d_u, const double *d_x, double *d_y, void *stream);
 int ok_minres(ok_ctx *ctx, const double *d_u, const double *d_b, double *d_x, int32_t *its,
               void *stream);
