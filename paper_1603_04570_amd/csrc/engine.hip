@@ -1239,8 +1239,8 @@ int minres_class(ClassCtx& c, Vec<const double> u, Vec<const double> b, Vec<doub
     e = sym_precond(c, c.act, cst(slot(v2)), slot(z2), st);
     if (e) return e;
     OKE(c, launch_mr_coef(P, c.act, c.incyc, cst(pa), n2, maxit, mr, st));
-    OKE(c, launch_mr_wx(R, cst(slot(z1)), cst(slot(w0)), cst(slot(w1)), slot(w2), x, n, newton,
-                        cst(mr), st));
+    OKE(c, launch_mr_wx(R, c.act, cst(slot(z1)), cst(slot(w0)), cst(slot(w1)), slot(w2), x, n,
+                        newton, cst(mr), st));
     int t = v0;
     v0 = v1, v1 = v2, v2 = t;
     std::swap(z1, z2);

@@ -641,6 +641,7 @@ __global__ void __launch_bounds__(256)
   mr[MR_WZ] = 1.0 / (gam * a1);
   mr[MR_W0] = -a3 / a1;
   mr[MR_W1] = -a2 / a1;
+  mr[MR_XCP] = mr[MR_XC];
   mr[MR_XC] = cn * eta;
   const double en = -sn * eta;
   mr[MR_ETA] = en;
@@ -665,13 +666,20 @@ __global__ void __launch_bounds__(256)
 }
 
 __global__ void __launch_bounds__(256)
-    k_mr_wx(Batch B, Vec<const double> zv, Vec<const double> w0v, Vec<const double> w1v,
-            Vec<double> w2v, Vec<double> xv, int64_t n, int swap, Vec<const double> mrv,
-            int per) {
+    k_mr_wx(Batch B, const int* act, Vec<const double> zv, Vec<const double> w0v,
+            Vec<const double> w1v, Vec<double> w2v, Vec<double> xv, int64_t n, int swap,
+            Vec<const double> mrv, int per) {
   const int inst = blockIdx.x / per;
   if (inactive(B, inst)) return;
   const double* mr = mrv.at(inst);
   const double cz = mr[MR_WZ], c0 = mr[MR_W0], c1 = mr[MR_W1], cx = mr[MR_XC];
+  const double cxp = mr[MR_XCP];
+  // x is updated in every second iteration with both directions (w_j, the
+  // previous one, is read here anyway), and in the last one: the same fused
+  // multiply-adds in the same order as one update per iteration, with one
+  // pass over x per two iterations
+  const int t = (int)mr[MR_ITS];  // iterations done, this one included
+  const int mode = (t % 2 == 0) ? 2 : (act[inst] ? 0 : 1);
   const double* z = zv.at(inst);
   const double* w0 = w0v.at(inst);
   const double* w1 = w1v.at(inst);
@@ -679,10 +687,12 @@ __global__ void __launch_bounds__(256)
   double* x = xv.at(inst);
   for (int64_t i = (int64_t)(blockIdx.x % per) * blockDim.x + threadIdx.x; i < 2 * n;
        i += (int64_t)per * blockDim.x) {
-    const double w = fma(c1, ldnt(w1 + i), fma(c0, ldnt(w0 + i), cz * ldnt(z + i)));
+    const double wp = ldnt(w1 + i);
+    const double w = fma(c1, wp, fma(c0, ldnt(w0 + i), cz * ldnt(z + i)));
     stnt(w, w2 + i);
+    if (mode == 0) continue;
     const int64_t k = swap ? (i < n ? i + n : i - n) : i;
-    x[k] = fma(cx, w, x[k]);
+    x[k] = (mode == 2) ? fma(cx, w, fma(cxp, wp, x[k])) : fma(cx, w, x[k]);
   }
 }
 
@@ -860,11 +870,12 @@ hipError_t launch_mr_coef(const Batch& B, int* act, int* ran, Vec<const double> 
   return hipGetLastError();
 }
 
-hipError_t launch_mr_wx(const Batch& B, Vec<const double> z, Vec<const double> w0,
-                        Vec<const double> w1, Vec<double> w2, Vec<double> x, int64_t n,
-                        bool swap, Vec<const double> mr, hipStream_t st) {
+hipError_t launch_mr_wx(const Batch& B, const int* act, Vec<const double> z,
+                        Vec<const double> w0, Vec<const double> w1, Vec<double> w2,
+                        Vec<double> x, int64_t n, bool swap, Vec<const double> mr,
+                        hipStream_t st) {
   const int per = vec_per(2 * n);
-  hipLaunchKernelGGL(k_mr_wx, grid_of(per, B), dim3(256), 0, st, B, z, w0, w1, w2, x, n,
+  hipLaunchKernelGGL(k_mr_wx, grid_of(per, B), dim3(256), 0, st, B, act, z, w0, w1, w2, x, n,
                      swap ? 1 : 0, mr, per);
   return hipGetLastError();
 }

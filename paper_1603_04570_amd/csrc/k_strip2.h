@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(BX * BY / P)
   extern __shared__ double lds_raw[];
   double* LA = lds_raw;
   double* LB = lds_raw + EA;
-  double* LC = lds_raw + 2 * EA;  // PROL: coarse planes K (even K) and K (odd K)
+  double* LC = lds_raw + 2 * EA;  // PROL: two coarse planes, plane K in buffer K & 1
   const int tid = threadIdx.x;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int inst = lb / sh.blocks;

@@ -370,7 +370,8 @@ enum MinresSlot {
   MR_ITS,       // iterations done
   MR_STATUS,    // 0 running, 1 converged, 2 non-finite, 3 iteration limit
   MR_GAM1,      // gamma_1 (initial preconditioned residual norm)
-  MR_COUNT = 16
+  MR_XCP,       // XC of the previous iteration (its x update is deferred to this one)
+  MR_COUNT = 17
 };
 // Start: v1 = [s b1; b2] (s = 1/(1 + dt th sigma) if scale_first, else 1),
 // and v0, w0, w1, x = 0.
@@ -396,11 +397,14 @@ hipError_t launch_mr_vupd(const Batch& B, Vec<const double> partials, Vec<const 
 // step (act set on entry), 0 otherwise.  B.act: participating.
 hipError_t launch_mr_coef(const Batch& B, int* act, int* ran, Vec<const double> partials,
                           int64_t n2, int maxit, Vec<double> mr, hipStream_t st);
-// w2 = WZ z + W0 w0 + W1 w1, x += XC w2; swap: x is stored with its halves
+// w2 = WZ z + W0 w0 + W1 w1, and x += XCP w1 + XC w2 after an even number
+// of iterations, x += XC w2 in an odd-numbered last one (act cleared), else
+// x is left for the next iteration; swap: x is stored with its halves
 // exchanged ([du; dw]).  B.act: the instances that took the step.
-hipError_t launch_mr_wx(const Batch& B, Vec<const double> z, Vec<const double> w0,
-                        Vec<const double> w1, Vec<double> w2, Vec<double> x, int64_t n,
-                        bool swap, Vec<const double> mr, hipStream_t st);
+hipError_t launch_mr_wx(const Batch& B, const int* act, Vec<const double> z,
+                        Vec<const double> w0, Vec<const double> w1, Vec<double> w2,
+                        Vec<double> x, int64_t n, bool swap, Vec<const double> mr,
+                        hipStream_t st);
 
 // Residual assembly helper (FP64):
 // t1 = (u - un) + dt*sigma*(th*u + (1-th)*un - m),  t2 = dt*(th*w + (1-th)*wn)
