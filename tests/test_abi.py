@@ -1,6 +1,7 @@
 """CPU checks of the C ABI: the library loads, exports every entry point the
 header declares, and rejects bad arguments before touching the GPU."""
 import ctypes as C
+import json
 import os
 import re
 import subprocess
@@ -213,3 +214,41 @@ def test_get_launch_shape_round_trip(lib):
     assert lib.ok_get_launch_shape(3, 64, 12, 0, C.byref(i), C.byref(i), C.byref(i)) == E
     assert lib.ok_get_launch_shape(3, 64, 1, 2, C.byref(i), C.byref(i), C.byref(i)) == E
     assert lib.ok_get_launch_shape(3, 64, 1, 0, None, C.byref(i), C.byref(i)) == E
+
+
+def test_bench_launch_shapes_save_and_load(lib, tmp_path):
+    """bench.py --save-shapes writes the table entries of the configuration's
+    grids (every level of the hierarchy, both precisions) and --load-shapes
+    pins them instead of autotuning (host-side table only)."""
+    import argparse
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1603_04570_amd import ok
+    path = str(tmp_path / "shapes.json")
+    pins = [(64, ok.OK_SHAPE_MG_POST_STRIP, ok.OK_FP64, 4, 256, 9),
+            (32, ok.OK_SHAPE_CHEB2_TILE, ok.OK_MIXED, 2, 512, 5),
+            (16, ok.OK_SHAPE_STENCIL, ok.OK_FP64, 2, 256, 3)]
+
+    class FakeProblem:
+        def autotune(self):
+            for n, kern, prec, items, threads, zch in pins:
+                ok.set_launch_shape(3, n, kern, prec, items, threads, zch)
+            return len(pins)
+
+    cfg = {"dim": 3, "n": 64}
+    try:
+        args = argparse.Namespace(load_shapes=None, save_shapes=path, no_autotune=False)
+        assert bench._tune(args, ok, FakeProblem(), cfg) == len(pins)
+        saved = json.load(open(path))
+        assert {(e["n"], e["kernel"], e["precision"], e["items"], e["threads"], e["zchunks"])
+                for e in saved} == set(pins)
+        for n, kern, prec, *_ in pins:
+            ok.set_launch_shape(3, n, kern, prec, 0)
+        args = argparse.Namespace(load_shapes=path, save_shapes=None, no_autotune=False)
+        assert bench._tune(args, ok, None, cfg) == len(pins)
+        for n, kern, prec, items, threads, zch in pins:
+            assert ok.get_launch_shape(3, n, kern, prec) == (items, threads, zch)
+    finally:
+        for n, kern, prec, *_ in pins:
+            ok.set_launch_shape(3, n, kern, prec, 0)
