@@ -71,17 +71,21 @@ def test_minres(dim, n, cfg):
     assert relnorm(host(x), x_o) < 1e-10
 
 
-def test_minres_iteration_limit():
+@pytest.mark.parametrize("restart,restarts", [(4, 1), (3, 2), (1, 0)])
+def test_minres_iteration_limit(restart, restarts):
     """A limit below the iterations needed: status OK_E_GMRES_MAXIT after
     exactly gmres_restart * (gmres_max_restarts + 1) iterations, and the
-    iterate equals the oracle's at that point."""
+    iterate equals the oracle's at that point (an even and two odd limits:
+    the device adds the directions to x two iterations at a time, and in an
+    odd-numbered last iteration alone)."""
     dim, n = 2, 32
-    o, P = make(dim, n, CFG2, gmres_restart=4, gmres_max_restarts=1)
+    limit = restart * (restarts + 1)
+    o, P = make(dim, n, CFG2, gmres_restart=restart, gmres_max_restarts=restarts)
     u, _ = noise_state(dim, n, 0.1, 1)
     b = uniform01(74, 2 * o.nodes) - 0.5
     x_o, its_o, st_o = o.minres(u, b)
     x, its, st = P.minres(dev(u), dev(b))
-    assert st == st_o == -4 and its == its_o == 8
+    assert st == st_o == -4 and its == its_o == limit
     assert relnorm(host(x), x_o) < 1e-10
 
 
