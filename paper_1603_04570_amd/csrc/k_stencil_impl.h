@@ -610,6 +610,29 @@ struct EpiAxpy {
   }
 };
 
+// out = add + a*(M s): EpiAxpy without the stiffness term (the streaming
+// kernel then forms no K partials)
+template <class TA, class TO>
+struct EpiMassAxpy {
+  static constexpr bool kMass = true;
+  using In = In1<TA>;
+  struct K {
+    double a;
+  };
+  Vec<const TA> add;
+  double ca;
+  int fa;
+  Vec<TO> out;
+  __device__ K prep(const InstCoef& C, int) const { return K{ca * coef_field(C, fa)}; }
+  __device__ In load(int inst, int64_t i) const {
+    return In{add.null() ? (TA)0 : add.at(inst)[i]};
+  }
+  __device__ void store(int inst, int64_t i, int, const double* ms, const double*,
+                        const double*, const In& in, const K& k) const {
+    out.at(inst)[i] = (TO)fma(k.a, ms[0], to_d(in.a));
+  }
+};
+
 // Two stenciled fields s0, s1 and up to two outputs:
 //   out_o = add_o + c[o][0] M s0 + c[o][1] K s0 + c[o][2] M s1 + c[o][3] K s1
 template <class TO>
@@ -1560,6 +1583,10 @@ __global__ void __launch_bounds__(256)
 template <class TS, class TA, class TO>
 hipError_t launch_stencil_axpy(const Grid& g, const Batch& B, Vec<const TS> s, Vec<const TA> add,
                                double ca, int fa, double cb, int fb, Vec<TO> out, hipStream_t st) {
+  if (cb == 0.0) {  // a mass action: no stiffness partials
+    EpiMassAxpy<TA, TO> e{add, ca, fa, out};
+    return run_stencil<false>(g, B, s, e, st);
+  }
   EpiAxpy<TA, TO> e{add, ca, cb, fa, fb, out};
   return run_stencil<false>(g, B, s, e, st);
 }
